@@ -1,0 +1,174 @@
+"""ctypes wrapper around the FP64 CPU oracle (``bmg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use this module; the GPU library never does.  It shares no
+code with the GPU path.
+
+Arrays are numpy float64, row-major ``[ny][nx]`` over the vertex grid including
+the boundary ring, matching the plane format of the library's C interface.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bmg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        L.oracle_setup.restype = ctypes.c_void_p
+        L.oracle_setup.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)]
+        L.oracle_free.argtypes = [ctypes.c_void_p]
+        L.oracle_num_levels.argtypes = [ctypes.c_void_p]
+        L.oracle_num_levels.restype = ctypes.c_int
+        L.oracle_level_size.argtypes = [ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.oracle_get_stencil.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.oracle_get_interp.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.oracle_solve.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_double, ctypes.c_int, _D]
+        L.oracle_solve.restype = ctypes.c_int
+        L.oracle_smooth.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, ctypes.c_int]
+        L.oracle_residual.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _D]
+        L.oracle_restrict.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D]
+        L.oracle_interp_correct.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _D, ctypes.c_int]
+        L.oracle_coarse_solve.argtypes = [ctypes.c_void_p, _D, _D]
+        L.oracle_vcycle.argtypes = [ctypes.c_void_p, _D, _D]
+        L.oracle_fv5.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+        L.oracle_grad_logD.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def fv5(cellD):
+    """5-point finite-volume planes (C, W, S) from per-cell diffusivity [(ny-1),(nx-1)]."""
+    cellD = np.ascontiguousarray(cellD, dtype=np.float64)
+    ny, nx = cellD.shape[0] + 1, cellD.shape[1] + 1
+    out = np.zeros((3, ny, nx))
+    lib().oracle_fv5(nx, ny, _p(cellD), _p(out[0]), _p(out[1]), _p(out[2]))
+    return out
+
+
+def grad_logD(cellD, u, lam):
+    cellD = np.ascontiguousarray(cellD, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    ny, nx = u.shape
+    g = np.zeros((ny - 1, nx - 1))
+    lib().oracle_grad_logD(nx, ny, _p(cellD), _p(u), _p(lam), _p(g))
+    return g
+
+
+class Hierarchy:
+    """Oracle multigrid hierarchy built from the finest stencil planes.
+
+    planes: [3 or 5][ny][nx] = {C, W, S[, SW, SE]} with positive connections.
+    Level 0 is the coarsest, level L-1 the finest.
+    """
+
+    def __init__(self, planes, coarsest_n=3, nu1=2, nu2=1, rescorr=1):
+        planes = np.ascontiguousarray(planes, dtype=np.float64)
+        npt = {3: 5, 5: 9}[planes.shape[0]]
+        self.ny, self.nx = planes.shape[1:]
+        st = ctypes.c_int(0)
+        self._h = lib().oracle_setup(self.nx, self.ny, npt, _p(planes), coarsest_n, nu1, nu2,
+                                     rescorr, ctypes.byref(st))
+        self.status = st.value
+        if not self._h:
+            raise ValueError("oracle_setup rejected the arguments (status %d)" % st.value)
+        self.L = lib().oracle_num_levels(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().oracle_free(self._h)
+            self._h = None
+
+    def size(self, l):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        lib().oracle_level_size(self._h, l, ctypes.byref(a), ctypes.byref(b))
+        return b.value, a.value  # (ny, nx)
+
+    def stencil(self, l):
+        """[ny][nx][3][3] matrix entries A(p, p + (dx, dy)) at [.., dy+1, dx+1]."""
+        ny, nx = self.size(l)
+        out = np.zeros((ny, nx, 9))
+        lib().oracle_get_stencil(self._h, l, _p(out))
+        return out.reshape(ny, nx, 3, 3)
+
+    def interp(self, l):
+        """[ny][nx][2][2] interpolation rows of level l onto corners of level l-1,
+        weight on coarse vertex ((i>>1)+a, (j>>1)+b) at [.., b, a]."""
+        ny, nx = self.size(l)
+        out = np.zeros((ny, nx, 4))
+        lib().oracle_get_interp(self._h, l, _p(out))
+        return out.reshape(ny, nx, 2, 2)
+
+    def solve(self, b, u0=None, tol=1e-10, max_cycles=500):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64, order="C")
+        hist = np.zeros(max_cycles)
+        n = lib().oracle_solve(self._h, _p(b), _p(u), tol, max_cycles, _p(hist))
+        return u, hist[:n]
+
+    def vcycle(self, b, u):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        u = np.array(u, dtype=np.float64, order="C")
+        lib().oracle_vcycle(self._h, _p(b), _p(u))
+        return u
+
+    def smooth(self, l, b, x, sweeps=1):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x, dtype=np.float64, order="C")
+        lib().oracle_smooth(self._h, l, _p(b), _p(x), sweeps)
+        return x
+
+    def residual(self, l, b, x):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        r = np.zeros_like(b)
+        lib().oracle_residual(self._h, l, _p(b), _p(x), _p(r))
+        return r
+
+    def restrict(self, l, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        bc = np.zeros(self.size(l - 1))
+        lib().oracle_restrict(self._h, l, _p(r), _p(bc))
+        return bc
+
+    def interp_correct(self, l, x, r, xc, rescorr=1):
+        x = np.array(x, dtype=np.float64, order="C")
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        xc = np.ascontiguousarray(xc, dtype=np.float64)
+        lib().oracle_interp_correct(self._h, l, _p(x), _p(r), _p(xc), rescorr)
+        return x
+
+    def coarse_solve(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b)
+        lib().oracle_coarse_solve(self._h, _p(b), _p(x))
+        return x

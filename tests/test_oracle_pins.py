@@ -1,0 +1,422 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics, independent of the oracle's own code: closed forms, library
+routines on explicitly assembled matrices, invariants and brute force.
+
+Paper sections cited: section 2 (operator-induced interpolation, Galerkin
+coarse operator, Algorithm 1 V-cycle), section 3 (interpolation with the r/C
+term, Cholesky coarse solve), section 5 (5-point finite-volume discretisation
+of -div(D grad u) = f with zero Dirichlet data).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import oracle as O
+from paper_1803_02481_amd import inputs
+from tests import helpers as H
+
+
+def rand_planes(n, seed, contrast=4.0):
+    """FV5 planes from random per-cell D with log10 D ~ U[-contrast/2, contrast/2]."""
+    rng = np.random.default_rng(seed)
+    D = 10.0 ** rng.uniform(-contrast / 2, contrast / 2, size=(n - 1, n - 1))
+    return O.fv5(D), D
+
+
+# --------------------------------------------------------------------------
+# Section 5: 5-point finite-volume discretisation
+# --------------------------------------------------------------------------
+def test_fv5_constant_D_is_standard_laplacian():
+    planes = O.fv5(np.ones((8, 8)))
+    C, W, S = planes
+    assert np.all(C[1:-1, 1:-1] == 4.0)
+    assert np.all(W[1:-1, 1:] == 1.0) and np.all(S[1:, 1:-1] == 1.0)
+    A = H.matrix_from_planes(planes).toarray()
+    assert np.allclose(A, A.T)
+
+
+def test_fv5_interface_is_mean_of_cut_cells():
+    # two cells stacked: an x-edge on the interface row takes the mean
+    D = np.ones((4, 4))
+    D[2:, :] = 9.0
+    C, W, S = O.fv5(D)
+    assert W[2, 2] == 5.0 and W[1, 2] == 1.0 and W[3, 2] == 9.0
+    assert S[2, 2] == 1.0 and S[3, 2] == 9.0
+
+
+def _manufactured_error(n, smoothD):
+    h = 1.0 / (n - 1)
+    x = np.linspace(0, 1, n)
+    X, Y = np.meshgrid(x, x)
+    u = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    if smoothD:
+        xc = (np.arange(n - 1) + 0.5) * h
+        XC, YC = np.meshgrid(xc, xc)
+        D = 1.0 + 0.5 * np.sin(2 * np.pi * XC) * np.sin(2 * np.pi * YC)
+        Dv = 1.0 + 0.5 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+        Dx = np.pi * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+        Dy = np.pi * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+        f = (2 * np.pi ** 2 * Dv * u
+             - np.pi * (Dx * np.cos(np.pi * X) * np.sin(np.pi * Y)
+                        + Dy * np.sin(np.pi * X) * np.cos(np.pi * Y)))
+    else:
+        D = np.ones((n - 1, n - 1))
+        f = 2 * np.pi ** 2 * u
+    b = f * h * h
+    b[0, :] = b[-1, :] = b[:, 0] = b[:, -1] = 0.0
+    hier = O.Hierarchy(O.fv5(D))
+    uh, hist = hier.solve(b, tol=1e-11, max_cycles=100)
+    assert hist[-1] <= 1e-11
+    return np.abs(uh - u).max()
+
+
+@pytest.mark.parametrize("smoothD", [False, True])
+def test_manufactured_solution_second_order(smoothD):
+    errs = [_manufactured_error(n, smoothD) for n in (65, 129, 257)]
+    ratios = [errs[k] / errs[k + 1] for k in range(2)]
+    for r in ratios:
+        assert abs(r - 4.0) < 0.1, (errs, ratios)
+
+
+# --------------------------------------------------------------------------
+# Section 2: operator-induced interpolation
+# --------------------------------------------------------------------------
+def test_interp_constant_D_is_bilinear_on_every_level():
+    hier = O.Hierarchy(O.fv5(np.ones((64, 64))))
+    for l in range(hier.L - 1, 0, -1):
+        P = hier.interp(l)
+        ny, nx = P.shape[:2]
+        # interior vertices whose coarse corners are all interior
+        for j in range(2, ny - 2):
+            for i in range(2, nx - 2):
+                w = P[j, i]
+                if i % 2 == 0 and j % 2 == 0:
+                    exp = [[1, 0], [0, 0]]
+                elif i % 2 == 1 and j % 2 == 0:
+                    exp = [[0.5, 0.5], [0, 0]]
+                elif i % 2 == 0 and j % 2 == 1:
+                    exp = [[0.5, 0], [0.5, 0]]
+                else:
+                    exp = [[0.25, 0.25], [0.25, 0.25]]
+                assert np.array_equal(w, np.array(exp)), (l, i, j, w)
+
+
+def test_interp_finest_constant_D_is_bilinear_at_the_boundary():
+    # next to a Dirichlet side the weight goes linearly to the zero boundary value
+    hier = O.Hierarchy(O.fv5(np.ones((16, 16))))
+    P = hier.interp(hier.L - 1)
+    assert np.array_equal(P[2, 1], [[0, 0.5], [0, 0]])        # x-line next to x=0
+    assert np.array_equal(P[1, 1], [[0, 0], [0, 0.25]])       # cell centre in the corner
+    assert np.array_equal(P[1, 4], [[0, 0], [0.5, 0]])        # y-line next to y=0
+
+
+def test_interp_one_dimensional_coefficient_is_flux_weighted():
+    # D varies with x only: continuity of the normal flux through an x-line
+    # fine vertex gives w_W = D_W / (D_W + D_E) with D_W, D_E the adjacent cells
+    n = 33
+    rng = np.random.default_rng(7)
+    dcol = 10.0 ** rng.uniform(-2, 2, size=n - 1)
+    D = np.tile(dcol, (n - 1, 1))
+    hier = O.Hierarchy(O.fv5(D))
+    P = hier.interp(hier.L - 1)
+    for j in range(2, n - 2, 2):
+        for i in range(3, n - 3, 2):
+            wW = dcol[i - 1] / (dcol[i - 1] + dcol[i])
+            wE = dcol[i] / (dcol[i - 1] + dcol[i])
+            assert P[j, i, 0, 0] == pytest.approx(wW, rel=1e-14)
+            assert P[j, i, 0, 1] == pytest.approx(wE, rel=1e-14)
+
+
+def test_interp_reproduces_constants_away_from_the_boundary():
+    planes, _ = rand_planes(65, seed=11)
+    hier = O.Hierarchy(planes)
+    for l in range(hier.L - 1, 0, -1):
+        P = hier.interp(l)
+        ny, nx = P.shape[:2]
+        s = P.sum(axis=(2, 3))
+        # rows of A have zero sum at (level-dependent) distance >= 2 from the
+        # boundary; weights of vertices whose neighbours all have zero row sum
+        # sum to one
+        if ny < 12:
+            continue
+        core = s[4:ny - 4, 4:nx - 4]
+        assert np.abs(core - 1.0).max() < 1e-12, l
+
+
+# --------------------------------------------------------------------------
+# Section 2: Galerkin coarse operator
+# --------------------------------------------------------------------------
+def test_galerkin_matches_explicit_sparse_triple_product():
+    for n, seed in ((17, 1), (33, 2), (65, 3)):
+        planes, _ = rand_planes(n, seed)
+        hier = O.Hierarchy(planes)
+        for l in range(hier.L - 1, 0, -1):
+            Af = H.matrix_from_stencil(hier.stencil(l))
+            P = H.interp_matrix(hier.interp(l), hier.size(l - 1))
+            Ac_ref = (P.T @ Af @ P).toarray()
+            Ac = H.matrix_from_stencil(hier.stencil(l - 1)).toarray()
+            scale = np.abs(Ac_ref).max()
+            assert np.abs(Ac - Ac_ref).max() <= 1e-14 * scale, (n, l)
+
+
+def test_galerkin_9pt_input_matches_sparse_triple_product():
+    # a 9-point fine operator (itself a Galerkin operator) as the finest input
+    planes, _ = rand_planes(33, seed=5)
+    h0 = O.Hierarchy(planes)
+    st = h0.stencil(h0.L - 2)   # 17x17 9-point
+    ny, nx = st.shape[:2]
+    p9 = np.zeros((5, ny, nx))
+    p9[0] = st[:, :, 1, 1]
+    p9[1, :, 1:] = -st[:, 1:, 1, 0]      # W(i,j) = -A(p, p-(1,0))
+    p9[2, 1:, :] = -st[1:, :, 0, 1]      # S
+    p9[3, 1:, 1:] = -st[1:, 1:, 0, 0]    # SW
+    p9[4, 1:, :-1] = -st[1:, :-1, 0, 2]  # SE(i,j) = -A(p, p+(1,-1))
+    hier = O.Hierarchy(p9)
+    A_in = H.matrix_from_planes(p9).toarray()
+    # the plane format mirrors one half, so it equals the (rounding-level
+    # unsymmetric) source operator only to rounding
+    assert np.abs(A_in - H.matrix_from_stencil(st).toarray()).max() <= 1e-13 * np.abs(A_in).max()
+    for l in range(hier.L - 1, 0, -1):
+        Af = H.matrix_from_stencil(hier.stencil(l))
+        P = H.interp_matrix(hier.interp(l), hier.size(l - 1))
+        Ac_ref = (P.T @ Af @ P).toarray()
+        Ac = H.matrix_from_stencil(hier.stencil(l - 1)).toarray()
+        assert np.abs(Ac - Ac_ref).max() <= 1e-14 * np.abs(Ac_ref).max()
+
+
+def test_galerkin_constant_D_closed_form_bitwise():
+    # Interior coarse stencil after k Galerkin coarsenings of the 5-point
+    # Laplacian with bilinear interpolation: corner -(1-4^-k)/3,
+    # edge -(1+2*4^-k)/3, centre (4/3)(2+4^-k); all dyadic for k=1..4
+    hier = O.Hierarchy(O.fv5(np.ones((256, 256))))   # 257 -> 129 -> 65 -> 33 -> 17
+    for k in range(1, 5):
+        st = hier.stencil(hier.L - 1 - k)
+        ny, nx = st.shape[:2]
+        q = 4.0 ** (-k)
+        exp = np.array([[-(1 - q) / 3, -(1 + 2 * q) / 3, -(1 - q) / 3],
+                        [-(1 + 2 * q) / 3, (4.0 / 3.0) * (2 + q), -(1 + 2 * q) / 3],
+                        [-(1 - q) / 3, -(1 + 2 * q) / 3, -(1 - q) / 3]])
+        # the printed values are exact in binary for k=1..4
+        known = {1: (-1 / 4, -1 / 2, 3.0), 2: (-5 / 16, -3 / 8, 11 / 4),
+                 3: (-21 / 64, -11 / 32, 43 / 16), 4: (-85 / 256, -43 / 128, 171 / 64)}[k]
+        assert (exp[0, 0], exp[0, 1], exp[1, 1]) == pytest.approx(known, abs=0)
+        exact = np.array([[known[0], known[1], known[0]],
+                          [known[1], known[2], known[1]],
+                          [known[0], known[1], known[0]]])
+        for j in range(2, ny - 2):
+            for i in range(2, nx - 2):
+                assert np.array_equal(st[j, i], exact), (k, i, j, st[j, i])
+
+
+def test_galerkin_symmetry_and_row_sums():
+    planes, _ = rand_planes(65, seed=21, contrast=4.0)
+    hier = O.Hierarchy(planes)
+    for l in range(hier.L - 2, 0, -1):
+        A = H.matrix_from_stencil(hier.stencil(l))
+        d = abs(A - A.T).max()
+        assert d <= 1e-13 * abs(A).max(), l
+        st = hier.stencil(l)
+        ny, nx = st.shape[:2]
+        rs = st.sum(axis=(2, 3))
+        C = st[:, :, 1, 1]
+        if ny >= 8:
+            core = np.abs(rs[3:ny - 3, 3:nx - 3]) / C[3:ny - 3, 3:nx - 3]
+            assert core.max() <= 1e-13, l
+        # first interior ring carries the Dirichlet excess
+        assert (rs[1, 1:-1] > 1e-6 * C[1, 1:-1]).all()
+        assert (rs[1:-1, 1] > 1e-6 * C[1:-1, 1]).all()
+
+
+def test_galerkin_pattern_is_nine_point():
+    # the oracle aborts if a coarse coupling leaves the 3x3 pattern; reaching
+    # here on a 9-point input means none did
+    planes, _ = rand_planes(33, seed=9)
+    hier = O.Hierarchy(planes)
+    assert hier.L == 5
+
+
+# --------------------------------------------------------------------------
+# Section 2 / Algorithm 1: smoother, transfers, coarse solve, V-cycle
+# --------------------------------------------------------------------------
+def test_four_colour_gs_is_gauss_seidel_in_colour_order():
+    n = 17
+    planes, _ = rand_planes(n, seed=4)
+    hier = O.Hierarchy(planes)
+    rng = np.random.default_rng(0)
+    for l in (hier.L - 1, hier.L - 2):
+        st = hier.stencil(l)
+        ny, nx = st.shape[:2]
+        A = H.matrix_from_stencil(st)
+        b = np.zeros((ny, nx)); b[1:-1, 1:-1] = rng.standard_normal((ny - 2, nx - 2))
+        x = np.zeros((ny, nx)); x[1:-1, 1:-1] = rng.standard_normal((ny - 2, nx - 2))
+        got = hier.smooth(l, b, x, sweeps=1)
+        # permute unknowns by colour (stable inside a colour), then one
+        # lexicographic Gauss-Seidel step: (D + L) x_new = b - U x_old
+        jj, ii = np.meshgrid(np.arange(1, ny - 1), np.arange(1, nx - 1), indexing="ij")
+        colour = (ii % 2 + 2 * (jj % 2)).ravel()
+        perm = np.argsort(colour, kind="stable")
+        Ap = A[perm][:, perm].tocsr()
+        Lw = sp.tril(Ap, 0).tocsr()
+        U = sp.triu(Ap, 1).tocsr()
+        bp = H.to_interior(b)[perm]
+        xp = H.to_interior(x)[perm]
+        xn = spla.spsolve_triangular(Lw, bp - U @ xp, lower=True)
+        ref = np.empty_like(xn); ref[perm] = xn
+        assert np.abs(H.to_interior(got) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_restriction_is_transpose_of_interpolation():
+    planes, _ = rand_planes(33, seed=6)
+    hier = O.Hierarchy(planes)
+    rng = np.random.default_rng(1)
+    for l in range(hier.L - 1, 0, -1):
+        ny, nx = hier.size(l)
+        cny, cnx = hier.size(l - 1)
+        r = np.zeros((ny, nx)); r[1:-1, 1:-1] = rng.standard_normal((ny - 2, nx - 2))
+        v = np.zeros((cny, cnx)); v[1:-1, 1:-1] = rng.standard_normal((cny - 2, cnx - 2))
+        Rr = hier.restrict(l, r)
+        Pv = hier.interp_correct(l, np.zeros((ny, nx)), np.zeros((ny, nx)), v, rescorr=0)
+        lhs, rhs = float((Rr * v).sum()), float((r * Pv).sum())
+        assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1)
+        # and both equal the sparse matrix action
+        P = H.interp_matrix(hier.interp(l), (cny, cnx))
+        assert np.allclose(H.to_interior(Pv), P @ H.to_interior(v), rtol=0, atol=1e-14)
+        assert np.allclose(H.to_interior(Rr), P.T @ H.to_interior(r), rtol=0, atol=1e-13)
+
+
+def test_residual_correction_term_at_fine_only_vertices():
+    planes, _ = rand_planes(17, seed=8)
+    hier = O.Hierarchy(planes)
+    l = hier.L - 1
+    ny, nx = hier.size(l)
+    rng = np.random.default_rng(3)
+    r = np.zeros((ny, nx)); r[1:-1, 1:-1] = rng.standard_normal((ny - 2, nx - 2))
+    xc = np.zeros(hier.size(l - 1))
+    x0 = np.zeros((ny, nx))
+    got = hier.interp_correct(l, x0, r, xc, rescorr=1)
+    C = planes[0]
+    exp = np.where((np.arange(nx)[None, :] % 2 == 0) & (np.arange(ny)[:, None] % 2 == 0), 0.0, r / np.where(C == 0, 1, C))
+    exp[0, :] = exp[-1, :] = exp[:, 0] = exp[:, -1] = 0
+    assert np.allclose(got, exp, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("coarsest", [5, 9])
+def test_coarse_solve_is_dense_solve(coarsest):
+    planes, _ = rand_planes(33, seed=12)
+    hier = O.Hierarchy(planes, coarsest_n=coarsest)
+    st = hier.stencil(0)
+    ny, nx = st.shape[:2]
+    assert (ny, nx) == (coarsest, coarsest)
+    A = H.matrix_from_stencil(st).toarray()
+    rng = np.random.default_rng(5)
+    b = np.zeros((ny, nx)); b[1:-1, 1:-1] = rng.standard_normal((ny - 2, nx - 2))
+    x = hier.coarse_solve(b)
+    ref = np.linalg.solve(A, H.to_interior(b))
+    assert np.allclose(H.to_interior(x), ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,contrast,rescorr", [(9, 0.0, 1), (17, 4.0, 1), (33, 4.0, 1), (33, 4.0, 0)])
+def test_vcycle_solution_equals_dense_direct_solve(n, contrast, rescorr):
+    planes, _ = rand_planes(n, seed=n, contrast=contrast)
+    hier = O.Hierarchy(planes, rescorr=rescorr)
+    b = inputs.load_uniform(n, n, seed=2)
+    u, hist = hier.solve(b, tol=1e-12, max_cycles=200)
+    A = H.matrix_from_planes(planes).toarray()
+    ref = np.linalg.solve(A, H.to_interior(b))
+    rel = np.linalg.norm(A @ H.to_interior(u) - H.to_interior(b)) / np.linalg.norm(H.to_interior(b))
+    assert rel <= 1e-12 * 1.01
+    assert hist[-1] == pytest.approx(rel, rel=1e-6, abs=1e-15)
+    cond = np.linalg.cond(A)
+    assert np.abs(H.to_interior(u) - ref).max() <= 10 * cond * 1e-12 * np.abs(ref).max()
+
+
+def test_vcycle_constant_D_rate_is_h_independent():
+    rates = []
+    for n in (33, 65, 129):
+        hier = O.Hierarchy(O.fv5(np.ones((n - 1, n - 1))))
+        b = inputs.load_uniform(n, n, seed=0)
+        _, hist = hier.solve(b, tol=1e-10)
+        rates.append((hist[-1] / hist[0]) ** (1.0 / max(1, len(hist) - 1)))
+        assert len(hist) <= 9
+    assert max(rates) <= 0.05, rates
+
+
+def test_vcycle_lognormal_rate():
+    n = 129
+    hier = O.Hierarchy(O.fv5(inputs.cells_lognormal(n, n, 1.0, seed=1000)))
+    b = inputs.load_uniform(n, n, seed=2000)
+    _, hist = hier.solve(b, tol=1e-10)
+    rate = (hist[-1] / hist[0]) ** (1.0 / (len(hist) - 1))
+    assert rate <= 0.15, rate
+
+
+def test_setup_rejects_bad_sizes():
+    with pytest.raises(ValueError):
+        O.Hierarchy(np.zeros((3, 8, 9)))
+
+
+def test_nonsquare_grid_solution():
+    ny, nx = 17, 65
+    D = inputs.cells_lognormal(nx, ny, 1.0, seed=4)
+    planes = O.fv5(D)
+    hier = O.Hierarchy(planes)
+    assert hier.size(0) == (3, 9)
+    b = inputs.load_uniform(nx, ny, seed=1)
+    u, hist = hier.solve(b, tol=1e-11)
+    A = H.matrix_from_planes(planes).toarray()
+    ref = np.linalg.solve(A, H.to_interior(b))
+    assert np.abs(H.to_interior(u) - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------
+# Adjoint: dL/dtheta for L = 0.5 ||u(theta) - u_obs||^2, D = exp(theta)
+# --------------------------------------------------------------------------
+def _dense_solve_theta(theta, b):
+    planes = O.fv5(np.exp(theta))
+    A = H.matrix_from_planes(planes).toarray()
+    ny, nx = b.shape
+    return H.from_interior(np.linalg.solve(A, H.to_interior(b)), ny, nx), A
+
+
+def test_grad_logD_matches_central_differences():
+    n = 9
+    rng = np.random.default_rng(17)
+    theta = rng.standard_normal((n - 1, n - 1))
+    b = inputs.load_uniform(n, n, seed=3)
+    u_obs = _dense_solve_theta(rng.standard_normal((n - 1, n - 1)), b)[0]
+    u, A = _dense_solve_theta(theta, b)
+    lam = H.from_interior(np.linalg.solve(A, H.to_interior(u - u_obs)), n, n)
+    g = O.grad_logD(np.exp(theta), u, lam)
+    eps = 1e-6
+    fd = np.zeros_like(theta)
+    for cj in range(n - 1):
+        for ci in range(n - 1):
+            tp = theta.copy(); tp[cj, ci] += eps
+            tm = theta.copy(); tm[cj, ci] -= eps
+            up = _dense_solve_theta(tp, b)[0]
+            um = _dense_solve_theta(tm, b)[0]
+            fd[cj, ci] = (0.5 * ((up - u_obs) ** 2).sum() - 0.5 * ((um - u_obs) ** 2).sum()) / (2 * eps)
+    assert np.abs(g - fd).max() <= 1e-6 * np.abs(g).max()
+
+
+def test_grad_logD_matches_brute_force_matrix_derivative():
+    # -lam^T (dA/dtheta_c) u with dA/dtheta_c from differentiating the dense
+    # assembled matrix entry by entry (complex step, exact to rounding)
+    n = 7
+    rng = np.random.default_rng(23)
+    theta = rng.standard_normal((n - 1, n - 1))
+    u = H.from_interior(rng.standard_normal((n - 2) ** 2), n, n)
+    lam = H.from_interior(rng.standard_normal((n - 2) ** 2), n, n)
+    g = O.grad_logD(np.exp(theta), u, lam)
+    for cj in range(n - 1):
+        for ci in range(n - 1):
+            # A is linear in D: dA/dtheta_c = D_c * (A(D + e_c) - A(D)) for unit bump
+            D = np.exp(theta)
+            Dp = D.copy(); Dp[cj, ci] += 1.0
+            dA = (H.matrix_from_planes(O.fv5(Dp)) - H.matrix_from_planes(O.fv5(D))).toarray() * D[cj, ci]
+            ref = -H.to_interior(lam) @ dA @ H.to_interior(u)
+            assert g[cj, ci] == pytest.approx(ref, rel=1e-12, abs=1e-14)
