@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark: solves/s to relative residual 1e-10 on the 4097 x 4097 vertex
+heterogeneous diffusion problem (-div(D grad u) = f, zero Dirichlet data,
+5-point finite volumes, D piecewise constant on 16 x 16-cell blocks with
+log10 D ~ U[-2, 2]), V(2,1) cycles, FP64; plus FP32 V-cycles inside FP64
+iterative refinement on the same operator and on a two-phase checkerboard.
+
+A step is one complete solve from u = 0 to ||b - A u|| / ||b|| <= 1e-10 with
+the hierarchy already built and the inputs resident in HBM (the paper times
+the solve phase; setup is reported separately).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TOL = 1e-10
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stream_source_sha():
+    with open(os.path.join(ROOT, "paper_1803_02481_amd", "csrc", "bmg_stream.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("source_sha") != stream_source_sha() or t.get("kernel") != kernel:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def time_solves(hier, b, steps, warmup, torch):
+    u = torch.zeros_like(b)
+    info = None
+    for _ in range(warmup):
+        u.zero_()
+        u, info = hier.solve(b, u, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u.zero_()
+        u, info = hier.solve(b, u, tol=TOL)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return el, u, info
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4097)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles timed for the baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--collapse-level", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1803_02481_amd import hipbmg as HB
+    from paper_1803_02481_amd import inputs
+
+    dev = "cuda:0"
+    n = args.n
+    log("bench: building inputs n=%d" % n)
+    D = torch.from_numpy(inputs.cells_log10_blocks(n, n, 16, -2.0, 2.0, seed=1)).to(dev)
+    b = torch.from_numpy(inputs.load_uniform(n, n, seed=2)).to(dev)
+    coeffs = HB.fv5_from_cells(D)
+    torch.cuda.synchronize()
+
+    log("bench: FP64 setup")
+    hier = HB.Hierarchy(coeffs, collapse_level=args.collapse_level)
+    _, info0 = hier.solve(b, tol=TOL)          # also a warm-up
+    hier.profile(True)
+    log("bench: FP64 timed solves (%d)" % args.steps)
+    el, u64, info = time_solves(hier, b, args.steps, args.warmup, torch)
+    hier.profile(False)
+    prof = hier.profile_read(0)
+    ms_per_step = 1e3 * el / args.steps
+    value = args.steps / el
+    cycles = info.cycles
+    # dominant kernel: largest summed time over the timed solves
+    kname, (kms, kn, kbytes) = max(prof.items(), key=lambda kv: kv[1][0])
+    kavg_s = kms / kn / 1e3
+    achieved = kbytes / kavg_s / 1e9
+    traffic = measured_traffic(kname)
+    kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1],
+                   "GBps": v[2] / (v[0] / v[1] / 1e3) / 1e9} for k, v in prof.items()}
+    log("bench: FP64 %.3f solves/s, %d cycles, %.3f ms/solve, dominant %s %.1f GB/s"
+        % (value, cycles, ms_per_step, kname, achieved))
+
+    extra = {}
+    if not args.no_mixed:
+        log("bench: mixed precision on the same operator")
+        hm = HB.Hierarchy(coeffs, precision=HB.MIXED, collapse_level=args.collapse_level)
+        hm.solve(b, tol=TOL)
+        el_m, um, infom = time_solves(hm, b, args.steps, args.warmup, torch)
+        err = float((um - u64).abs().max() / u64.abs().max())
+        extra["mixed_blocks"] = {"solves_per_s": args.steps / el_m, "ms_per_solve": 1e3 * el_m / args.steps,
+                                 "fp32_cycles": infom.cycles, "refinement_steps": infom.outer_steps,
+                                 "relres": infom.relres, "max_rel_diff_vs_fp64": err}
+        log("bench: mixed %.3f solves/s (%d FP32 cycles, %d steps)"
+            % (args.steps / el_m, infom.cycles, infom.outer_steps))
+        del hm
+        # the two-phase checkerboard operator, FP64 and mixed
+        Dc = torch.from_numpy(inputs.cells_two_phase_blocks(n, n, 64, (1.0, 1e-3), seed=3)).to(dev)
+        bc = torch.from_numpy(inputs.load_uniform(n, n, seed=4)).to(dev)
+        cc = HB.fv5_from_cells(Dc)
+        res = {}
+        for name, prec in (("fp64", HB.FP64), ("mixed", HB.MIXED)):
+            hc = HB.Hierarchy(cc, precision=prec, collapse_level=args.collapse_level)
+            hc.solve(bc, tol=TOL)
+            el_c, uc, infoc = time_solves(hc, bc, args.steps, args.warmup, torch)
+            res[name] = {"solves_per_s": args.steps / el_c, "ms_per_solve": 1e3 * el_c / args.steps,
+                         "cycles": infoc.cycles, "refinement_steps": infoc.outer_steps,
+                         "relres": infoc.relres}
+            res[name + "_u"] = uc
+            del hc
+            log("bench: checkerboard %s %.3f solves/s" % (name, args.steps / el_c))
+        res["max_rel_diff_mixed_vs_fp64"] = float((res["mixed_u"] - res["fp64_u"]).abs().max()
+                                                  / res["fp64_u"].abs().max())
+        del res["mixed_u"], res["fp64_u"]
+        extra["checkerboard"] = res
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        log("bench: CPU oracle baseline (%d cycles)" % args.cpu_cycles)
+        planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, -2.0, 2.0, seed=1))
+        bh = inputs.load_uniform(n, n, seed=2)
+        oh = O.Hierarchy(planes)
+        uh = np.zeros_like(bh)
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_cycles):
+            uh = oh.vcycle(bh, uh)
+        t_cycle = (time.perf_counter() - t0) / args.cpu_cycles
+        cpu = {"value": 1.0 / (t_cycle * cycles), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "%d FP64 V(2,1)-cycles of the single-threaded oracle on the same %dx%d problem "
+                         "(%.2f s/cycle), scaled by the %d cycles the solve takes"
+                         % (args.cpu_cycles, n, n, t_cycle, cycles)}
+
+    out = {
+        "metric": "solves/s to rel. residual 1e-10, 4097^2 2D diffusion: FP64 vs FP32+refinement",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random-block diffusivity, uniform random load)",
+        "config": {"workload": "%dx%d vertex 2D diffusion, D on 16x16-cell blocks log10 D~U[-2,2], "
+                               "V(2,1) to rel. residual 1e-10, FP64" % (n, n),
+                   "n": n, "cycles": cycles, "levels": info.levels,
+                   "collapse_level": info.collapse_level, "setup_ms": info0.setup_ms,
+                   "relres": info.relres},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
+                     "avg_launch_us": kavg_s * 1e6},
+        "kernels_fp64_finest": kernels,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * hipbmg.h -- C interface of hipbmg, a structured variational multigrid solver
+ * for 2D heterogeneous diffusion on AMD MI355X (gfx950).
+ *
+ * Method: Reisner, Olson, Moulton, "Scaling Structured Multigrid to 500K+
+ * Cores through Coarse-Grid Redistribution" (arXiv 1803.02481):
+ *   - section 2: operator-induced interpolation, Galerkin coarse operators
+ *     A_{l-1} = P_l^T A_l P_l on a fixed 9-point pattern, standard coarsening
+ *     by two, four-colour Gauss-Seidel relaxation, the V-cycle of Algorithm 1;
+ *   - section 3: the interpolate-and-correct step u += P u_c + r/C, the
+ *     Cholesky coarse-grid solve factored at setup, and the alpha-beta-gamma
+ *     performance model (equations for T_smooth, T_residual, T_restrict,
+ *     T_interp, T_agglomerate, T_cgsolve, summed as T_V-cycle);
+ *   - sections 2.2 and 4: coarse-grid redistribution chosen by that model.  On
+ *     one GPU the redistribution becomes the choice of the level l* below which
+ *     grid-wide kernel launches stop and all coarser levels run inside one
+ *     persistent workgroup.
+ *
+ * Conventions shared by every entry point:
+ *   - Grids are vertex grids of nx x ny points including the boundary ring;
+ *     nx and ny are odd and >= 3.  Unknowns are the interior vertices; the
+ *     boundary carries the homogeneous Dirichlet value 0.
+ *   - Every array argument is a DEVICE pointer (hipMalloc / torch CUDA tensor
+ *     memory) unless the name ends in _host.  Arrays are row-major, x fastest,
+ *     contiguous: a vertex field is [ny][nx]; a cell field is [ny-1][nx-1]
+ *     with cell (i,j) = [x_i, x_i+1] x [y_j, y_j+1]; a stencil is a stack of
+ *     planes [nplanes][ny][nx].
+ *   - Stencil planes: 5-point {C, W, S}; 9-point {C, W, S, SW, SE}.  C is the
+ *     diagonal entry, the others are positive connection values: the matrix
+ *     entry between p=(i,j) and its west neighbour is -W(i,j), east -W(i+1,j),
+ *     south -S(i,j), north -S(i,j+1), south-west -SW(i,j), north-east
+ *     -SW(i+1,j+1), south-east -SE(i,j), north-west -SE(i-1,j+1).  Values that
+ *     couple to boundary vertices may be present; they multiply u = 0.
+ *   - stream is a hipStream_t (NULL = the null stream).  All device work of a
+ *     call is ordered on it.  Calls that return convergence information
+ *     synchronise the stream before returning.
+ *   - Every call returns a hipbmg_status and never throws; hipbmg_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - The caller owns every array it passes.  A handle owns all device memory
+ *     of its hierarchy (allocated with hipMalloc at setup, freed by
+ *     hipbmg_destroy).  A handle serves one stream at a time; calls on one
+ *     handle must not overlap.
+ */
+#ifndef HIPBMG_H
+#define HIPBMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hipbmg_hier *hipbmg_handle;
+
+typedef enum {
+    HIPBMG_OK = 0,
+    HIPBMG_EINVAL = 1,   /* bad size, null pointer, bad parameter          */
+    HIPBMG_ENOMEM = 2,   /* device allocation failed                       */
+    HIPBMG_EHIP = 3,     /* a HIP runtime call failed                      */
+    HIPBMG_ENOTSPD = 4,  /* coarsest operator not positive definite        */
+    HIPBMG_ENOCONV = 5,  /* max_cycles reached before tol; u = last iterate */
+    HIPBMG_ENAN = 6      /* residual norm is not finite                    */
+} hipbmg_status;
+
+typedef enum { HIPBMG_FP64 = 0, HIPBMG_MIXED = 1 } hipbmg_precision;
+
+#define HIPBMG_MAX_LEVELS 24
+#define HIPBMG_MAX_HIST 1024
+
+typedef struct {
+    int nu1;                 /* pre-relaxations per level (Algorithm 1), default 2          */
+    int nu2;                 /* post-relaxations per level, default 1                       */
+    int coarsest_n;          /* coarsen while both sides exceed this, default 3             */
+    int collapse_level;      /* -1: chosen by the performance model; k >= 0: levels 0..k    */
+                             /* run in one persistent workgroup (0 = coarsest solve only)   */
+    int residual_correction; /* 1: add r/C at fine-only vertices after interpolation (sec 3) */
+    int max_cycles;          /* FP64: V-cycles; mixed: total inner cycles cap, default 500  */
+    int precision;           /* hipbmg_precision, default HIPBMG_FP64                       */
+    int inner_max_cycles;    /* mixed: FP32 cycles per refinement step, default 12          */
+    double inner_tol;        /* mixed: inner relative residual target, default 1e-5         */
+    int use_graph;           /* 1: replay the V-cycle as a captured hipGraph, default 1     */
+} hipbmg_params;
+
+typedef struct {
+    int cycles;              /* V-cycles run (mixed: FP32 inner cycles, all steps)          */
+    int outer_steps;         /* mixed: refinement steps; FP64: equals cycles                */
+    double relres;           /* final ||b - A u||_2 / ||b||_2, FP64, interior vertices      */
+    int levels;              /* number of levels L                                          */
+    int collapse_level;      /* l* in use                                                   */
+    double model_us[HIPBMG_MAX_LEVELS]; /* model time of one cycle for each l*, microseconds */
+    double setup_ms;         /* wall time of hipbmg_setup                                   */
+    double solve_ms;         /* wall time of the solve call                                 */
+    double relres_hist[HIPBMG_MAX_HIST]; /* relres after each cycle (mixed: each step)     */
+} hipbmg_info;
+
+/* Fill *p with the defaults above. */
+void hipbmg_default_params(hipbmg_params *p);
+
+/* Build the multigrid hierarchy for the operator given by `coeffs`
+ * ([3][ny][nx] if npt == 5, [5][ny][nx] if npt == 9; see the plane convention
+ * above).  On the GPU: operator-induced interpolation weights and the Galerkin
+ * product for every level (section 2), the Cholesky factor of the coarsest
+ * operator (section 3, coarse-solve cost), and the collapse level l* from the
+ * performance model (sections 3 and 4) unless params->collapse_level >= 0.
+ * coeffs is copied and may be freed after return.  params may be NULL for the
+ * defaults.  Returns HIPBMG_ENOTSPD if the coarsest factorisation fails. */
+hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coeffs,
+                           const hipbmg_params *params, void *stream, hipbmg_handle *out);
+
+/* Solve A u = b by V(nu1,nu2)-cycles (Algorithm 1) until
+ * ||b - A u||_2 / ||b||_2 <= tol over interior vertices, or max_cycles.
+ * b: [ny][nx] right-hand side (boundary entries ignored).  u: [ny][nx], the
+ * initial guess on entry (boundary entries ignored), the iterate on return
+ * (boundary entries set to 0).  precision HIPBMG_MIXED runs FP32 V-cycles as
+ * the inner solver of FP64 iterative refinement; the outer residual, the norms
+ * and the coarsest solve stay FP64.  info may be NULL.  If ||b|| = 0 then u = 0.
+ * Returns HIPBMG_ENOCONV if tol was not reached (u holds the last iterate). */
+hipbmg_status hipbmg_solve(hipbmg_handle h, const double *b, double *u, double tol, void *stream,
+                           hipbmg_info *info);
+
+/* Release every device buffer of the handle. NULL is accepted. */
+hipbmg_status hipbmg_destroy(hipbmg_handle h);
+
+/* Number of levels and the size of level l (0 = coarsest). */
+hipbmg_status hipbmg_level_size(hipbmg_handle h, int l, int *nx_host, int *ny_host);
+
+/* Copy level l's stencil planes {C, W, S, SW, SE} into out ([5][ny][nx],
+ * device).  The finest level is stored as given (SW = SE = 0 for npt 5). */
+hipbmg_status hipbmg_get_stencil(hipbmg_handle h, int l, double *out, void *stream);
+
+/* Copy the interpolation weights from level l-1 to level l (l >= 1) into out
+ * ([8][cny][cnx], device, coarse size).  For coarse vertex (I,J) the planes
+ * hold the weights of the fine vertices of the coarse cell [I,I+1]x[J,J+1]:
+ *   0: (2I+1,2J)   on (I,J)      1: (2I+1,2J)   on (I+1,J)
+ *   2: (2I,2J+1)   on (I,J)      3: (2I,2J+1)   on (I,J+1)
+ *   4: (2I+1,2J+1) on (I,J)      5: (2I+1,2J+1) on (I+1,J)
+ *   6: (2I+1,2J+1) on (I,J+1)    7: (2I+1,2J+1) on (I+1,J+1)
+ * Weights on boundary coarse vertices and rows of boundary fine vertices are 0. */
+hipbmg_status hipbmg_get_interp(hipbmg_handle h, int l, double *out, void *stream);
+
+/* Single solve-phase operations on level l, in the plain [ny][nx] layout,
+ * exposed for checking the fused kernels one by one (they overwrite level l's
+ * internal right-hand side and iterate buffers; a later hipbmg_solve is not
+ * affected):
+ *   op_smooth: `sweeps` four-colour Gauss-Seidel relaxations of A_l x = b,
+ *     x updated in place (section 2).
+ *   op_smooth_restrict (l >= 1): one relaxation, then the residual r = b - A_l x,
+ *     q = r / C at vertices that are not coarse points (q = 0 elsewhere), and
+ *     bc = P_l^T r ([cny][cnx]) (Algorithm 1, residual and restriction).
+ *   op_interp_smooth (l >= 1): x += P_l xc (plus q at vertices that are not
+ *     coarse points if rescorr), then one relaxation (Algorithm 1, interpolate
+ *     and correct; section 3, the r/C term); if sumsq_host is not NULL it
+ *     receives ||b - A_l x||^2 after the relaxation. */
+hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *b, double *x, int sweeps,
+                               void *stream);
+hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
+                                        double *q, double *bc, void *stream);
+hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
+                                      const double *q, const double *xc, int rescorr,
+                                      double *sumsq_host, void *stream);
+
+/* Vertex-centred 5-point finite-volume stencil of -div(D grad u) (section 5):
+ * the face between vertices p and q takes the mean of the two cells it cuts,
+ * C is the sum of the four connections.  cell: [ny-1][nx-1] holding D, or
+ * theta = ln D if is_log.  coeffs_out: [3][ny][nx] planes {C, W, S}. */
+hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cell, int is_log,
+                                    double *coeffs_out, void *stream);
+
+/* Gradient of a scalar loss with respect to theta = ln D per cell, given the
+ * solution u and the adjoint lam = A^{-1} dL/du:
+ *   g_c = -(D_c/2) * sum over the four edges (p,q) of cell c of
+ *         (lam_p - lam_q)(u_p - u_q)          (boundary values 0).
+ * theta: [ny-1][nx-1]; u, lam: [ny][nx]; grad_out: [ny-1][nx-1]. */
+hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double *u,
+                               const double *lam, double *grad_out, void *stream);
+
+/* Live timing of the finest-level relaxation kernels, the per-component
+ * timers of the paper's experiments (section 5) for one GPU.  While enabled,
+ * every solve records HIP events around each finest-level streaming kernel on
+ * the solve stream.  enable = 0 stops and keeps the totals; enable = 1 clears
+ * them.  profile_read returns, for one precision (0 FP64, 1 FP32 inner) and
+ * one kernel index (0 relax, 1 relax from zero, 2 relax + residual +
+ * restriction, 3 the same from zero, 4 interpolate + relax, 5 the same + norm,
+ * 6 relax + norm), the summed duration, the number of launches and the
+ * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
+hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);
+hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,
+                                  double *total_ms_host, long long *launches_host,
+                                  double *bytes_per_launch_host);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *hipbmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPBMG_H */

@@ -1,0 +1,302 @@
+// bmg_collapse.hip -- the coarse levels collapsed into one persistent workgroup,
+// plus deterministic norm reductions.
+//
+// The paper (sections 2.2 and 4) stops spreading coarse levels over all
+// processors once their halo exchanges cost more than their work, and gathers
+// them onto fewer processors chosen by its performance model.  On one GPU the
+// corresponding cost is the kernel boundary: a grid-wide launch per
+// relaxation / transfer costs microseconds even when a level holds a few
+// hundred points.  Levels 0..l* therefore run here, inside ONE workgroup of
+// 1024 threads, with a workgroup barrier where the paper's algorithm has a halo
+// exchange (after every colour of Gauss-Seidel, after the residual, the
+// restriction and the interpolation).  All level data stays in global memory
+// (it is small and L2 resident).  The coarsest level is solved with the
+// Cholesky factor computed at setup (section 3, coarse-solve cost), in FP64.
+#include "bmg_internal.h"
+
+namespace hbmg {
+
+constexpr int CWG = 1024;   // threads of the collapse workgroup
+
+// Residual (b - A x)_p at interior vertex p and the diagonal used by the
+// relaxation (9-point form; the SW/SE planes of a 5-point level are zero).
+// FP64 levels: standard form with C.  FP32 levels: edge form, the C plane
+// holding the excess E = C - sum(connections).
+template <typename T> struct EdgeForm { enum { value = 0 }; };
+template <> struct EdgeForm<float> { enum { value = 1 }; };
+
+template <typename T>
+__device__ __forceinline__ T point_res(const LevelDev<T> &L, const T *__restrict__ x, size_t p, T &diag)
+{
+    const size_t P = L.pitch;
+    const T cw = L.W[p], ce = L.W[p + 1], cs = L.S[p], cn = L.S[p + P];
+    const T csw = L.SW[p], cne = L.SW[p + P + 1], cse = L.SE[p], cnw = L.SE[p + P - 1];
+    const T xp = x[p];
+    if (!EdgeForm<T>::value) {
+        const T s = L.b[p] + cw * x[p - 1] + ce * x[p + 1] + cs * x[p - P] + cn * x[p + P] +
+                    csw * x[p - P - 1] + cne * x[p + P + 1] + cse * x[p - P + 1] + cnw * x[p + P - 1];
+        diag = L.C[p];
+        return s - L.C[p] * xp;
+    } else {
+        const T s = L.b[p] + cw * (x[p - 1] - xp) + ce * (x[p + 1] - xp) + cs * (x[p - P] - xp) +
+                    cn * (x[p + P] - xp) + csw * (x[p - P - 1] - xp) + cne * (x[p + P + 1] - xp) +
+                    cse * (x[p - P + 1] - xp) + cnw * (x[p + P - 1] - xp);
+        diag = cw + ce + cs + cn + L.C[p] + csw + cne + cse + cnw;
+        return s - L.C[p] * xp;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T point_diag(const LevelDev<T> &L, size_t p)
+{
+    if (!EdgeForm<T>::value) return L.C[p];
+    const size_t P = L.pitch;
+    return L.W[p] + L.W[p + 1] + L.S[p] + L.S[p + P] + L.C[p] + L.SW[p] + L.SW[p + P + 1] + L.SE[p] +
+           L.SE[p + P - 1];
+}
+
+__device__ __forceinline__ int count_par(int lo, int hi) { return hi >= lo ? (hi - lo) / 2 + 1 : 0; }
+
+// one colour of Gauss-Seidel: colour k has (i mod 2, j mod 2) = (k & 1, k >> 1)
+template <typename T>
+__device__ void gs_colour(const LevelDev<T> &L, T *__restrict__ x, int k)
+{
+    const int i0 = (k & 1) ? 1 : 2, j0 = (k >> 1) ? 1 : 2;
+    const int ni = count_par(i0, L.nx - 2), nj = count_par(j0, L.ny - 2);
+    for (int idx = threadIdx.x; idx < ni * nj; idx += CWG) {
+        const int i = i0 + 2 * (idx % ni), j = j0 + 2 * (idx / ni);
+        const size_t p = (size_t)j * L.pitch + i;
+        T d;
+        const T r = point_res(L, x, p, d);
+        x[p] += r / d;
+    }
+}
+
+template <typename T>
+__device__ void zero_interior(const LevelDev<T> &L, T *__restrict__ x)
+{
+    const int ni = L.nx - 2, n = ni * (L.ny - 2);
+    for (int idx = threadIdx.x; idx < n; idx += CWG)
+        x[(size_t)(1 + idx / ni) * L.pitch + 1 + idx % ni] = T(0);
+}
+
+template <typename T>
+__device__ double residual(const LevelDev<T> &L, const T *__restrict__ x, T *__restrict__ r)
+{
+    const int ni = L.nx - 2, n = ni * (L.ny - 2);
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const size_t p = (size_t)(1 + idx / ni) * L.pitch + 1 + idx % ni;
+        T d;
+        const T v = point_res(L, x, p, d);
+        r[p] = v;
+        acc += (double)v * v;
+    }
+    return acc;
+}
+
+// b_c = P^T r on the interior coarse vertices
+template <typename T>
+__device__ void restrict_pt(const LevelDev<T> &F, const T *__restrict__ r, const LevelDev<T> &Cl)
+{
+    const int ni = Cl.nx - 2, n = ni * (Cl.ny - 2);
+    const size_t cp = F.cplane;
+    const T *w = F.wt;
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int I = 1 + idx % ni, J = 1 + idx / ni;
+        const size_t c = (size_t)J * Cl.pitch + I;
+        const size_t P = F.pitch;
+        const size_t f = (size_t)(2 * J) * P + 2 * I;
+        const size_t cW = c - 1, cS = c - Cl.pitch, cSW = c - Cl.pitch - 1;
+        T v = r[f] + w[WXL * cp + c] * r[f + 1] + w[WXR * cp + cW] * r[f - 1] +
+              w[WYB * cp + c] * r[f + P] + w[WYT * cp + cS] * r[f - P] +
+              w[WCSW * cp + c] * r[f + P + 1] + w[WCSE * cp + cW] * r[f + P - 1] +
+              w[WCNW * cp + cS] * r[f - P + 1] + w[WCNE * cp + cSW] * r[f - P - 1];
+        Cl.b[c] = v;
+    }
+}
+
+// x += P x_c (+ r/C at fine-only vertices)
+template <typename T>
+__device__ void interp_correct(const LevelDev<T> &F, T *__restrict__ x, const T *__restrict__ r,
+                               const LevelDev<T> &Cl, const T *__restrict__ xc, int rescorr)
+{
+    const int ni = F.nx - 2, n = ni * (F.ny - 2);
+    const size_t cp = F.cplane;
+    const T *w = F.wt;
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int i = 1 + idx % ni, j = 1 + idx / ni;
+        const size_t p = (size_t)j * F.pitch + i;
+        const size_t c = (size_t)(j >> 1) * Cl.pitch + (i >> 1);
+        const size_t CP = Cl.pitch;
+        T v;
+        if (!(i & 1) && !(j & 1)) {
+            v = xc[c];
+        } else {
+            if ((i & 1) && !(j & 1))
+                v = w[WXL * cp + c] * xc[c] + w[WXR * cp + c] * xc[c + 1];
+            else if (!(i & 1) && (j & 1))
+                v = w[WYB * cp + c] * xc[c] + w[WYT * cp + c] * xc[c + CP];
+            else
+                v = w[WCSW * cp + c] * xc[c] + w[WCSE * cp + c] * xc[c + 1] +
+                    w[WCNW * cp + c] * xc[c + CP] + w[WCNE * cp + c] * xc[c + CP + 1];
+            if (rescorr) v += r[p] / point_diag(F, p);
+        }
+        x[p] += v;
+    }
+}
+
+// deterministic workgroup sum (fixed pairing)
+__device__ double block_sum(double v, double *sh)
+{
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < CWG / 64; ++k) s += sh[k];
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
+{
+    __shared__ double sh[CWG / 64];
+    const LevelDev<T> *lv = a.levels;
+    // down: relax, residual, restrict
+    for (int l = a.top; l >= 1; --l) {
+        const LevelDev<T> L = lv[l];
+        const int xb = l == a.top ? a.xb_top : 1;
+        T *x = L.x[xb], *r = L.x[1 - xb];
+        if (l < a.top || a.zero_top) {
+            zero_interior(L, x);
+            __syncthreads();
+        }
+        for (int s = 0; s < a.nu1; ++s)
+            for (int k = 0; k < 4; ++k) {
+                gs_colour(L, x, k);
+                __syncthreads();
+            }
+        residual(L, x, r);
+        __syncthreads();
+        restrict_pt(L, r, lv[l - 1]);
+        __syncthreads();
+    }
+    // coarsest: Cholesky solve in FP64 (column-oriented substitutions)
+    {
+        const LevelDev<T> L0 = lv[0];
+        T *x0 = L0.x[a.top == 0 ? a.xb_top : 1];
+        const int nc = a.nc;
+        double *y = a.work;
+        const int ni = L0.nx - 2, n = ni * (L0.ny - 2);
+        for (int idx = threadIdx.x; idx < n; idx += CWG) {
+            const int i = 1 + idx % ni, j = 1 + idx / ni;
+            const int k = a.cidx[j * L0.nx + i];
+            y[k] = (double)L0.b[(size_t)j * L0.pitch + i];
+        }
+        __syncthreads();
+        for (int k = 0; k < nc; ++k) {            // L y = b
+            const double yk = y[k] / a.chol[(size_t)k * nc + k];
+            for (int m = k + 1 + threadIdx.x; m < nc; m += CWG) y[m] -= a.chol[(size_t)m * nc + k] * yk;
+            __syncthreads();
+            if (threadIdx.x == 0) y[k] = yk;
+            __syncthreads();
+        }
+        for (int k = nc - 1; k >= 0; --k) {       // L^T x = y
+            const double xk = y[k] / a.chol[(size_t)k * nc + k];
+            for (int m = threadIdx.x; m < k; m += CWG) y[m] -= a.chol[(size_t)k * nc + m] * xk;
+            __syncthreads();
+            if (threadIdx.x == 0) y[k] = xk;
+            __syncthreads();
+        }
+        for (int idx = threadIdx.x; idx < n; idx += CWG) {
+            const int i = 1 + idx % ni, j = 1 + idx / ni;
+            x0[(size_t)j * L0.pitch + i] = (T)y[a.cidx[j * L0.nx + i]];
+        }
+        __syncthreads();
+    }
+    // up: interpolate and correct, relax
+    for (int l = 1; l <= a.top; ++l) {
+        const LevelDev<T> L = lv[l];
+        const int xb = l == a.top ? a.xb_top : 1;
+        T *x = L.x[xb], *r = L.x[1 - xb];
+        interp_correct(L, x, r, lv[l - 1], lv[l - 1].x[1], a.rescorr);
+        __syncthreads();
+        for (int s = 0; s < a.nu2; ++s)
+            for (int k = 0; k < 4; ++k) {
+                gs_colour(L, x, k);
+                __syncthreads();
+            }
+    }
+    if (a.want_norm) {
+        const LevelDev<T> L = lv[a.top];
+        double v = residual(L, L.x[a.xb_top], L.x[1 - a.xb_top]);
+        v = block_sum(v, sh);
+        if (threadIdx.x == 0) a.partials[0] = v;
+    }
+}
+
+template <typename T>
+hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_collapse<T>), dim3(1), dim3(CWG), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_collapse<double>(const CollapseArgs<double> &, hipStream_t);
+template hipError_t launch_collapse<float>(const CollapseArgs<float> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Norm helpers: per-block partial sums of squares over interior vertices, then
+// one workgroup adds the partials in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ v, int nx, int ny,
+                                               int pitch, double *__restrict__ partials)
+{
+    __shared__ double sh[4];
+    const int ni = nx - 2;
+    const long long n = (long long)ni * (ny - 2);
+    double acc = 0.0;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * 256) {
+        const double a = v[(size_t)(1 + idx / ni) * pitch + 1 + idx % ni];
+        acc += a * a;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+hipError_t launch_sumsq(const double *v, int nx, int ny, int pitch, double *partials, int nparts,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumsq, dim3(nparts), dim3(256), 0, s, v, nx, ny, pitch, partials);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int n,
+                                                  const double *__restrict__ denom,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) acc += partials[k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = denom ? sqrt(sh[0]) / denom[0] : sqrt(sh[0]);
+}
+
+hipError_t launch_finalize_norm(const double *partials, int n, const double *denom, double *out,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, n, denom, out);
+    return hipGetLastError();
+}
+
+}  // namespace hbmg

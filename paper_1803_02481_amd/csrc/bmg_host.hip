@@ -1,0 +1,901 @@
+// bmg_host.hip -- host runtime of hipbmg: hierarchy construction, the V-cycle
+// launch plan, the collapse-level performance model, the FP64 and mixed
+// precision solve drivers, and the C interface declared in include/hipbmg.h.
+#include "hipbmg.h"
+#include "bmg_internal.h"
+#include "bmg_misc.h"
+#include "bmg_model.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace hbmg;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static hipbmg_status fail(hipbmg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(HIPBMG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
+    } while (0)
+
+#define STCHK(call)                                                                         \
+    do {                                                                                    \
+        hipbmg_status s_ = (call);                                                          \
+        if (s_ != HIPBMG_OK) return s_;                                                     \
+    } while (0)
+
+extern "C" const char *hipbmg_last_error(void) { return g_err.c_str(); }
+
+extern "C" void hipbmg_default_params(hipbmg_params *p)
+{
+    if (!p) return;
+    p->nu1 = 2;
+    p->nu2 = 1;
+    p->coarsest_n = 3;
+    p->collapse_level = -1;
+    p->residual_correction = 1;
+    p->max_cycles = 500;
+    p->precision = HIPBMG_FP64;
+    p->inner_max_cycles = 12;
+    p->inner_tol = 1e-5;
+    p->use_graph = 1;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+struct hipbmg_hier {
+    int L = 0, nx = 0, ny = 0, npt = 5;
+    hipbmg_params prm{};
+    std::vector<LevelDev<double>> lv;
+    std::vector<LevelDev<float>> lv32;
+    LevelDev<double> *d_lv = nullptr;
+    LevelDev<float> *d_lv32 = nullptr;
+    std::vector<void *> allocs;
+    double *d_chol = nullptr;
+    int *d_cidx = nullptr;
+    double *d_work = nullptr;
+    int nc = 0;
+    double *d_partials = nullptr;
+    size_t n_partials = 0;
+    double *d_scal = nullptr;   // [0] ||b||, [1] relres, [2] ||r|| (mixed outer), [3] inner relres
+    double *h_scal = nullptr;   // pinned mirror
+    int lstar = 0;
+    double model_us[HIPBMG_MAX_LEVELS] = {};
+    double setup_ms = 0.0;
+    std::vector<int> rb;        // row-block steps per level for the streaming kernels
+    // live timing of the finest-level streaming kernels (HIP events on the solve stream)
+    int prof_on = 0;
+    int prof_n = 0;                       // event pairs recorded in the current cycle
+    int prof_var[64];
+    int prof_prec[64];
+    hipEvent_t ev0[64] = {}, ev1[64] = {};
+    double prof_ms[2][SV_COUNT] = {};
+    long long prof_cnt[2][SV_COUNT] = {};
+    ~hipbmg_hier()
+    {
+        for (int k = 0; k < 64; ++k) {
+            if (ev0[k]) (void)hipEventDestroy(ev0[k]);
+            if (ev1[k]) (void)hipEventDestroy(ev1[k]);
+        }
+        for (void *p : allocs) (void)hipFree(p);
+        if (h_scal) (void)hipHostFree(h_scal);
+    }
+};
+
+template <typename T> struct PrecIdx { enum { v = 0 }; };
+template <> struct PrecIdx<float> { enum { v = 1 }; };
+
+// collect the event pairs of the last cycle (the stream has been synchronised)
+static void prof_collect(hipbmg_hier *h)
+{
+    for (int k = 0; k < h->prof_n; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev0[k], h->ev1[k]) == hipSuccess) {
+            h->prof_ms[h->prof_prec[k]][h->prof_var[k]] += ms;
+            h->prof_cnt[h->prof_prec[k]][h->prof_var[k]] += 1;
+        }
+    }
+    h->prof_n = 0;
+}
+
+static int pitch_for(int nx) { return (nx + 63) / 64 * 64; }   // >= nx+1 for odd nx
+
+template <typename T>
+static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, n * sizeof(T) + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HIPBMG_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+    }
+    h->allocs.push_back(q);
+    HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 256, s));
+    *p = static_cast<T *>(q);
+    return HIPBMG_OK;
+}
+
+template <typename T>
+static hipbmg_status alloc_levels(hipbmg_hier *h, std::vector<LevelDev<T>> &lv,
+                                  const std::vector<int> &sx, const std::vector<int> &sy,
+                                  hipStream_t s)
+{
+    const int L = (int)sx.size();
+    lv.assign(L, LevelDev<T>{});
+    for (int l = 0; l < L; ++l) {
+        LevelDev<T> &d = lv[l];
+        d.nx = sx[l];
+        d.ny = sy[l];
+        d.pitch = pitch_for(d.nx);
+        d.npt = (l == L - 1) ? h->npt : 9;
+        d.plane = (size_t)d.ny * d.pitch;
+        T *blk = nullptr;
+        STCHK(dalloc(h, &blk, d.plane * 9, s));
+        d.C = blk;
+        d.W = blk + d.plane;
+        d.S = blk + 2 * d.plane;
+        d.SW = blk + 3 * d.plane;
+        d.SE = blk + 4 * d.plane;
+        d.x[0] = blk + 5 * d.plane;
+        d.x[1] = blk + 6 * d.plane;
+        d.b = blk + 7 * d.plane;
+        d.q = blk + 8 * d.plane;
+        d.wt = nullptr;
+        if (l >= 1) {
+            d.cpitch = pitch_for(sx[l - 1]);
+            d.cplane = (size_t)sy[l - 1] * d.cpitch;
+            STCHK(dalloc(h, &d.wt, d.cplane * 8, s));
+        }
+    }
+    return HIPBMG_OK;
+}
+
+// dense Cholesky of the coarsest operator (interior unknowns), on the host
+static hipbmg_status factor_coarsest(hipbmg_hier *h, hipStream_t s)
+{
+    const LevelDev<double> &c = h->lv[0];
+    const int nx = c.nx, ny = c.ny;
+    std::vector<double> pl(5 * c.plane);
+    HIPCHK(hipMemcpyAsync(pl.data(), c.C, 5 * c.plane * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    auto at = [&](int k, int i, int j) { return pl[k * c.plane + (size_t)j * c.pitch + i]; };
+    std::vector<int> cidx((size_t)nx * ny, -1);
+    int n = 0;
+    for (int j = 1; j <= ny - 2; ++j)
+        for (int i = 1; i <= nx - 2; ++i) cidx[(size_t)j * nx + i] = n++;
+    std::vector<double> M((size_t)n * n, 0.0);
+    auto put = [&](int i, int j, int di, int dj, double v) {
+        int a = cidx[(size_t)j * nx + i];
+        int ii = i + di, jj = j + dj;
+        if (ii < 1 || ii > nx - 2 || jj < 1 || jj > ny - 2) return;
+        M[(size_t)a * n + cidx[(size_t)jj * nx + ii]] = v;
+    };
+    for (int j = 1; j <= ny - 2; ++j)
+        for (int i = 1; i <= nx - 2; ++i) {
+            put(i, j, 0, 0, at(0, i, j));
+            put(i, j, -1, 0, -at(1, i, j));
+            put(i, j, 1, 0, -at(1, i + 1, j));
+            put(i, j, 0, -1, -at(2, i, j));
+            put(i, j, 0, 1, -at(2, i, j + 1));
+            put(i, j, -1, -1, -at(3, i, j));
+            put(i, j, 1, 1, -at(3, i + 1, j + 1));
+            put(i, j, 1, -1, -at(4, i, j));
+            put(i, j, -1, 1, -at(4, i - 1, j + 1));
+        }
+    for (int k = 0; k < n; ++k) {
+        double d = M[(size_t)k * n + k];
+        for (int m = 0; m < k; ++m) d -= M[(size_t)k * n + m] * M[(size_t)k * n + m];
+        if (!(d > 0.0)) return fail(HIPBMG_ENOTSPD, "coarsest operator not positive definite (pivot %d)", k);
+        d = std::sqrt(d);
+        M[(size_t)k * n + k] = d;
+        for (int r = k + 1; r < n; ++r) {
+            double v = M[(size_t)r * n + k];
+            for (int m = 0; m < k; ++m) v -= M[(size_t)r * n + m] * M[(size_t)k * n + m];
+            M[(size_t)r * n + k] = v / d;
+        }
+        for (int r = 0; r < k; ++r) M[(size_t)r * n + k] = 0.0;
+    }
+    h->nc = n;
+    STCHK(dalloc(h, &h->d_chol, (size_t)n * n, s));
+    STCHK(dalloc(h, &h->d_cidx, (size_t)nx * ny, s));
+    STCHK(dalloc(h, &h->d_work, (size_t)n + 1, s));
+    HIPCHK(hipMemcpyAsync(h->d_chol, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->d_cidx, cidx.data(), cidx.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+// row-block length of the streaming kernels: long blocks amortise the
+// prologue, short blocks give small levels enough waves
+static int pick_rb(int nx, int ny, int npt)
+{
+    int nst, nbl, nt, g;
+    for (int rb : {32, 16, 8, 4}) {
+        stream_geometry(nx, ny, npt, SV_SWEEP_RQ, rb, &nst, &nbl, &nt, &g);
+        if (nt >= 1024) return rb;
+    }
+    return 4;
+}
+
+static double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coeffs,
+                                      const hipbmg_params *params, void *stream,
+                                      hipbmg_handle *out)
+{
+    const double t0 = now_ms();
+    if (!out) return fail(HIPBMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!coeffs) return fail(HIPBMG_EINVAL, "coeffs is NULL");
+    if (nx < 3 || ny < 3 || !(nx & 1) || !(ny & 1))
+        return fail(HIPBMG_EINVAL, "grid %d x %d: sizes must be odd and >= 3", nx, ny);
+    if (npt != 5 && npt != 9) return fail(HIPBMG_EINVAL, "npt must be 5 or 9 (got %d)", npt);
+    hipbmg_params prm;
+    hipbmg_default_params(&prm);
+    if (params) prm = *params;
+    if (prm.nu1 < 1 || prm.nu2 < 1 || prm.nu1 > 16 || prm.nu2 > 16)
+        return fail(HIPBMG_EINVAL, "nu1 and nu2 must be in [1, 16]");
+    if (prm.coarsest_n < 3) return fail(HIPBMG_EINVAL, "coarsest_n must be >= 3");
+    if (prm.max_cycles < 1) return fail(HIPBMG_EINVAL, "max_cycles must be >= 1");
+    if (prm.precision != HIPBMG_FP64 && prm.precision != HIPBMG_MIXED)
+        return fail(HIPBMG_EINVAL, "unknown precision %d", prm.precision);
+    if (prm.precision == HIPBMG_MIXED && (prm.inner_max_cycles < 1 || !(prm.inner_tol > 0.0)))
+        return fail(HIPBMG_EINVAL, "mixed precision needs inner_max_cycles >= 1 and inner_tol > 0");
+    if ((long long)nx * ny > (1LL << 31)) return fail(HIPBMG_EINVAL, "grid too large");
+    hipStream_t s = (hipStream_t)stream;
+
+    std::vector<int> sx{nx}, sy{ny};
+    while (sx.back() > prm.coarsest_n && sy.back() > prm.coarsest_n && (int)sx.size() < HIPBMG_MAX_LEVELS) {
+        sx.push_back((sx.back() + 1) / 2);
+        sy.push_back((sy.back() + 1) / 2);
+    }
+    std::reverse(sx.begin(), sx.end());
+    std::reverse(sy.begin(), sy.end());
+    const int L = (int)sx.size();
+    if (prm.collapse_level >= L)
+        return fail(HIPBMG_EINVAL, "collapse_level %d >= number of levels %d", prm.collapse_level, L);
+    if ((long long)(sx[0] - 2) * (sy[0] - 2) > 4096)
+        return fail(HIPBMG_EINVAL, "coarsest level %d x %d too large for the dense solve", sx[0], sy[0]);
+
+    hipbmg_hier *h = new hipbmg_hier();
+    h->L = L;
+    h->nx = nx;
+    h->ny = ny;
+    h->npt = npt;
+    h->prm = prm;
+    auto bail = [&](hipbmg_status st) {
+        delete h;
+        return st;
+    };
+    hipbmg_status st = alloc_levels(h, h->lv, sx, sy, s);
+    if (st != HIPBMG_OK) return bail(st);
+    // finest operator, as given
+    LevelDev<double> &F = h->lv[L - 1];
+    const int nplanes = npt == 5 ? 3 : 5;
+    for (int k = 0; k < nplanes; ++k) {
+        if (hipMemcpy2DAsync(F.C + k * F.plane, F.pitch * sizeof(double),
+                             coeffs + (size_t)k * nx * ny, nx * sizeof(double), nx * sizeof(double),
+                             ny, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return bail(fail(HIPBMG_EHIP, "copy of the stencil planes failed (device pointer?)"));
+    }
+    // coarse operators: interpolation weights and Galerkin products
+    for (int l = L - 1; l >= 1; --l) {
+        const LevelDev<double> &f = h->lv[l], &c = h->lv[l - 1];
+        if (launch_interp_weights(f, c.nx, c.ny, f.wt, f.cpitch, f.cplane, s) != hipSuccess ||
+            launch_rap(f, c, s) != hipSuccess)
+            return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
+                             hipGetErrorString(hipGetLastError())));
+    }
+    if (hipMalloc(&h->d_lv, L * sizeof(LevelDev<double>)) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "hipMalloc failed"));
+    h->allocs.push_back(h->d_lv);
+    if (hipMemcpyAsync(h->d_lv, h->lv.data(), L * sizeof(LevelDev<double>), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return bail(fail(HIPBMG_EHIP, "hipMemcpyAsync failed"));
+    st = factor_coarsest(h, s);
+    if (st != HIPBMG_OK) return bail(st);
+
+    // FP32 edge-form copy of every level for mixed precision
+    if (prm.precision == HIPBMG_MIXED) {
+        st = alloc_levels(h, h->lv32, sx, sy, s);
+        if (st != HIPBMG_OK) return bail(st);
+        for (int l = 0; l < L; ++l) {
+            int cnx = l ? sx[l - 1] : 0, cny = l ? sy[l - 1] : 0;
+            if (launch_demote_level(h->lv[l], h->lv32[l], cnx, cny, s) != hipSuccess)
+                return bail(fail(HIPBMG_EHIP, "demote launch failed"));
+        }
+        if (hipMalloc(&h->d_lv32, L * sizeof(LevelDev<float>)) != hipSuccess)
+            return bail(fail(HIPBMG_ENOMEM, "hipMalloc failed"));
+        h->allocs.push_back(h->d_lv32);
+        if (hipMemcpyAsync(h->d_lv32, h->lv32.data(), L * sizeof(LevelDev<float>),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return bail(fail(HIPBMG_EHIP, "hipMemcpyAsync failed"));
+    }
+
+    // streaming geometry and reduction scratch
+    h->rb.resize(L);
+    size_t np = 4096;
+    for (int l = 0; l < L; ++l) {
+        h->rb[l] = pick_rb(sx[l], sy[l], h->lv[l].npt);
+        int nst, nbl, nt, g;
+        stream_geometry(sx[l], sy[l], h->lv[l].npt, SV_INTERP_NORM, h->rb[l], &nst, &nbl, &nt, &g);
+        np = std::max(np, (size_t)nt);
+        stream_geometry(sx[l], sy[l], h->lv[l].npt, SV_SWEEP_NORM, h->rb[l], &nst, &nbl, &nt, &g);
+        np = std::max(np, (size_t)nt);
+    }
+    np = std::max(np, (size_t)((nx + 255) / 256) * ny);   // refinement residual partials
+    h->n_partials = np;
+    st = dalloc(h, &h->d_partials, np, s);
+    if (st != HIPBMG_OK) return bail(st);
+    st = dalloc(h, &h->d_scal, 8, s);
+    if (st != HIPBMG_OK) return bail(st);
+    if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+
+    // collapse level from the performance model (sections 3 and 4)
+    ModelLevel ml[HIPBMG_MAX_LEVELS];
+    for (int l = 0; l < L; ++l) {
+        ml[l].nx = sx[l];
+        ml[l].ny = sy[l];
+        ml[l].npt = h->lv[l].npt;
+        ml[l].rb = h->rb[l];
+    }
+    const ModelParams &mp = model_params();
+    int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc,
+                            prm.precision == HIPBMG_MIXED ? 4 : 8, mp, h->model_us);
+    h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
+    if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
+                                                             hipGetErrorString(hipGetLastError())));
+    h->setup_ms = now_ms() - t0;
+    *out = h;
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_destroy(hipbmg_handle h)
+{
+    if (h) {
+        (void)hipDeviceSynchronize();
+        delete h;
+    }
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_level_size(hipbmg_handle h, int l, int *nx, int *ny)
+{
+    if (!h) return fail(HIPBMG_EINVAL, "null handle");
+    if (l < 0 || l >= h->L) return fail(HIPBMG_EINVAL, "level %d out of range [0,%d)", l, h->L);
+    if (nx) *nx = h->lv[l].nx;
+    if (ny) *ny = h->lv[l].ny;
+    return HIPBMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle launch plan (Algorithm 1 with levels 0..l* collapsed)
+// ---------------------------------------------------------------------------
+template <typename T>
+static StreamArgs<T> base_args(const LevelDev<T> &A, int rb)
+{
+    StreamArgs<T> a{};
+    a.nx = A.nx;
+    a.ny = A.ny;
+    a.pitch = A.pitch;
+    a.C = A.C;
+    a.W = A.W;
+    a.S = A.S;
+    a.SW = A.SW;
+    a.SE = A.SE;
+    a.b = A.b;
+    a.rb = rb;
+    return a;
+}
+
+template <typename T>
+static hipError_t run_stream(const LevelDev<T> &A, int variant, StreamArgs<T> a, hipStream_t s,
+                             int *ntiles_out = nullptr)
+{
+    int g;
+    stream_geometry(A.nx, A.ny, A.npt, variant, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+    if (ntiles_out) *ntiles_out = a.ntiles;
+    return launch_stream<T>(A.npt, variant, a, g, s);
+}
+
+// Enqueue one V-cycle on the hierarchy `lv` whose finest iterate is in
+// x[cur] (or is zero if zero_start).  The finest post-relaxation leaves its
+// residual norm partials in d_partials (*nparts of them).  Returns the buffer
+// index holding the new finest iterate.
+template <typename T>
+static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
+                                 const LevelDev<T> *d_lv, int cur, bool zero_start, int *new_cur,
+                                 int *nparts, hipStream_t s)
+{
+    const int L = h->L, ls = h->lstar;
+    const int nu1 = h->prm.nu1, nu2 = h->prm.nu2, rc = h->prm.residual_correction;
+    int xb_after[HIPBMG_MAX_LEVELS], xres[HIPBMG_MAX_LEVELS];
+    hipError_t e = hipSuccess;
+    for (int l = L - 1; l > ls; --l) {
+        const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
+        const bool fine = l == L - 1;
+        int xb = fine ? cur : 0;
+        const bool zero = !fine || zero_start;
+        for (int k = 1; k <= nu1; ++k) {
+            const bool last = k == nu1, zx = zero && k == 1;
+            const int v = last ? (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ) : (zx ? SV_SWEEP_ZX : SV_SWEEP);
+            StreamArgs<T> a = base_args(A, h->rb[l]);
+            a.x_in = A.x[xb];
+            a.x_out = A.x[1 - xb];
+            if (last) {
+                a.q_out = A.q;
+                a.bc = Cl.b;
+                a.wt = A.wt;
+                a.cnx = Cl.nx;
+                a.cny = Cl.ny;
+                a.cpitch = Cl.pitch;
+                a.cplane = (long long)Cl.plane;
+            }
+            const int pk = (h->prof_on && fine && h->prof_n < 64) ? h->prof_n++ : -1;
+            if (pk >= 0) {
+                h->prof_var[pk] = v;
+                h->prof_prec[pk] = PrecIdx<T>::v;
+                (void)hipEventRecord(h->ev0[pk], s);
+            }
+            if ((e = run_stream(A, v, a, s)) != hipSuccess) return e;
+            if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+            xb = 1 - xb;
+        }
+        xb_after[l] = xb;
+    }
+    // levels 0..l* in one workgroup
+    {
+        CollapseArgs<T> c{};
+        c.levels = d_lv;
+        c.top = ls;
+        const bool fine = ls == L - 1;
+        c.xb_top = fine ? cur : 1;
+        c.zero_top = fine ? (zero_start ? 1 : 0) : 1;
+        c.nu1 = nu1;
+        c.nu2 = nu2;
+        c.rescorr = rc;
+        c.chol = h->d_chol;
+        c.cidx = h->d_cidx;
+        c.nc = h->nc;
+        c.work = h->d_work;
+        c.partials = h->d_partials;
+        c.want_norm = fine ? 1 : 0;
+        if ((e = launch_collapse<T>(c, s)) != hipSuccess) return e;
+        xres[ls] = c.xb_top;
+        if (fine) {
+            *new_cur = cur;
+            *nparts = 1;
+            return hipSuccess;
+        }
+    }
+    for (int l = ls + 1; l < L; ++l) {
+        const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
+        const bool fine = l == L - 1;
+        int xb = xb_after[l];
+        for (int k = 1; k <= nu2; ++k) {
+            const bool first = k == 1, last = k == nu2;
+            int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP)
+                          : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
+            StreamArgs<T> a = base_args(A, h->rb[l]);
+            a.x_in = A.x[xb];
+            a.x_out = A.x[1 - xb];
+            if (first) {
+                a.xc = Cl.x[xres[l - 1]];
+                a.wt = A.wt;
+                a.q_in = A.q;
+                a.rescorr = rc;
+                a.cnx = Cl.nx;
+                a.cny = Cl.ny;
+                a.cpitch = Cl.pitch;
+                a.cplane = (long long)Cl.plane;
+            }
+            a.partials = h->d_partials;
+            int nt = 0;
+            const int pk = (h->prof_on && fine && h->prof_n < 64) ? h->prof_n++ : -1;
+            if (pk >= 0) {
+                h->prof_var[pk] = v;
+                h->prof_prec[pk] = PrecIdx<T>::v;
+                (void)hipEventRecord(h->ev0[pk], s);
+            }
+            if ((e = run_stream(A, v, a, s, &nt)) != hipSuccess) return e;
+            if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+            if (fine && last) *nparts = nt;
+            xb = 1 - xb;
+        }
+        xres[l] = xb;
+    }
+    *new_cur = xres[L - 1];
+    return hipSuccess;
+}
+
+static hipbmg_status read_scalars(hipbmg_hier *h, int first, int n, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(h->h_scal + first, h->d_scal + first, n * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+static void fill_info_common(hipbmg_hier *h, hipbmg_info *info)
+{
+    if (!info) return;
+    info->levels = h->L;
+    info->collapse_level = h->lstar;
+    for (int l = 0; l < HIPBMG_MAX_LEVELS; ++l) info->model_us[l] = l < h->L ? h->model_us[l] : 0.0;
+    info->setup_ms = h->setup_ms;
+}
+
+static hipbmg_status solve_fp64(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
+                                int *cur_out)
+{
+    const LevelDev<double> &F = h->lv[h->L - 1];
+    int cur = 0, cycles = 0;
+    double rel = 1.0;
+    hipbmg_status st = HIPBMG_ENOCONV;
+    while (cycles < h->prm.max_cycles) {
+        int nc, np = 0;
+        hipError_t e = enqueue_vcycle<double>(h, h->lv, h->d_lv, cur, false, &nc, &np, s);
+        if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
+        cur = nc;
+        HIPCHK(launch_finalize_norm(h->d_partials, np, h->d_scal, h->d_scal + 1, s));
+        STCHK(read_scalars(h, 1, 1, s));
+        prof_collect(h);
+        rel = h->h_scal[1];
+        if (info && cycles < HIPBMG_MAX_HIST) info->relres_hist[cycles] = rel;
+        ++cycles;
+        if (!std::isfinite(rel)) {
+            st = HIPBMG_ENAN;
+            break;
+        }
+        if (rel <= tol) {
+            st = HIPBMG_OK;
+            break;
+        }
+    }
+    (void)F;
+    *cur_out = cur;
+    if (info) {
+        info->cycles = cycles;
+        info->outer_steps = cycles;
+        info->relres = rel;
+    }
+    if (st == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "residual norm is not finite after cycle %d", cycles);
+    if (st == HIPBMG_ENOCONV)
+        return fail(HIPBMG_ENOCONV, "relres %.3e > tol %.3e after %d cycles", rel, tol, cycles);
+    return HIPBMG_OK;
+}
+
+// FP32 V-cycles inside FP64 iterative refinement: the FP64 residual of the
+// FP64 iterate is demoted to the FP32 right-hand side, FP32 cycles reduce it
+// by inner_tol, and the FP32 correction is added to the FP64 iterate.
+static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
+                                 int *cur_out)
+{
+    const int L = h->L;
+    const LevelDev<double> &F = h->lv[L - 1];
+    const LevelDev<float> &F32 = h->lv32[L - 1];
+    int cycles = 0, steps = 0;
+    double rel = 1.0;
+    hipbmg_status st = HIPBMG_ENOCONV;
+    const double bnorm = h->h_scal[0];
+    for (;;) {
+        int np = 0;
+        HIPCHK(launch_ir_residual(F, F.x[0], F32.b, F32.pitch, h->d_partials, &np, s));
+        HIPCHK(launch_finalize_norm(h->d_partials, np, nullptr, h->d_scal + 2, s));
+        STCHK(read_scalars(h, 2, 1, s));
+        const double rnorm = h->h_scal[2];
+        rel = rnorm / bnorm;
+        if (info && steps < HIPBMG_MAX_HIST) info->relres_hist[steps] = rel;
+        if (!std::isfinite(rel)) {
+            st = HIPBMG_ENAN;
+            break;
+        }
+        if (rel <= tol) {
+            st = HIPBMG_OK;
+            break;
+        }
+        if (cycles >= h->prm.max_cycles) break;
+        ++steps;
+        // inner FP32 solve of A e = r from e = 0
+        h->h_scal[4] = rnorm;
+        HIPCHK(hipMemcpyAsync(h->d_scal + 4, h->h_scal + 4, sizeof(double), hipMemcpyHostToDevice, s));
+        int cur = 0;
+        bool zero = true;
+        for (int k = 0; k < h->prm.inner_max_cycles && cycles < h->prm.max_cycles; ++k) {
+            int nc, npp = 0;
+            hipError_t e = enqueue_vcycle<float>(h, h->lv32, h->d_lv32, cur, zero, &nc, &npp, s);
+            if (e != hipSuccess) return fail(HIPBMG_EHIP, "FP32 V-cycle launch failed: %s", hipGetErrorString(e));
+            cur = nc;
+            zero = false;
+            ++cycles;
+            HIPCHK(launch_finalize_norm(h->d_partials, npp, h->d_scal + 4, h->d_scal + 3, s));
+            STCHK(read_scalars(h, 3, 1, s));
+            prof_collect(h);
+            const double irel = h->h_scal[3];
+            if (!std::isfinite(irel)) break;
+            if (irel <= h->prm.inner_tol) break;
+        }
+        HIPCHK(launch_ir_update(F.x[0], F.pitch, F32.x[cur], F32.pitch, F.nx, F.ny, s));
+    }
+    *cur_out = 0;
+    if (info) {
+        info->cycles = cycles;
+        info->outer_steps = steps;
+        info->relres = rel;
+    }
+    if (st == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "residual norm is not finite");
+    if (st == HIPBMG_ENOCONV)
+        return fail(HIPBMG_ENOCONV, "relres %.3e > tol %.3e after %d FP32 cycles", rel, tol, cycles);
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_solve(hipbmg_handle h, const double *b, double *u, double tol,
+                                      void *stream, hipbmg_info *info)
+{
+    const double t0 = now_ms();
+    if (!h) return fail(HIPBMG_EINVAL, "null handle");
+    if (!b || !u) return fail(HIPBMG_EINVAL, "b and u must be device pointers");
+    if (!(tol > 0.0)) return fail(HIPBMG_EINVAL, "tol must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int L = h->L, nx = h->nx, ny = h->ny;
+    const LevelDev<double> &F = h->lv[L - 1];
+    if (info) {
+        memset(info, 0, sizeof *info);
+        fill_info_common(h, info);
+    }
+    HIPCHK(hipMemcpy2DAsync(F.b, F.pitch * sizeof(double), b, nx * sizeof(double), nx * sizeof(double),
+                            ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(F.x[0], F.pitch * sizeof(double), u, nx * sizeof(double),
+                            nx * sizeof(double), ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_zero_ring(F.x[0], nx, ny, F.pitch, s));
+    HIPCHK(launch_zero_ring(F.b, nx, ny, F.pitch, s));
+    const int nparts = 1024;
+    HIPCHK(launch_sumsq(F.b, nx, ny, F.pitch, h->d_partials, nparts, s));
+    HIPCHK(launch_finalize_norm(h->d_partials, nparts, nullptr, h->d_scal, s));
+    STCHK(read_scalars(h, 0, 1, s));
+    const double bnorm = h->h_scal[0];
+    if (!std::isfinite(bnorm)) return fail(HIPBMG_ENAN, "||b|| is not finite");
+    if (bnorm == 0.0) {
+        HIPCHK(hipMemsetAsync(u, 0, (size_t)nx * ny * sizeof(double), s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (info) info->solve_ms = now_ms() - t0;
+        return HIPBMG_OK;
+    }
+    int cur = 0;
+    hipbmg_status st = h->prm.precision == HIPBMG_MIXED ? solve_mixed(h, tol, s, info, &cur)
+                                                         : solve_fp64(h, tol, s, info, &cur);
+    if (st != HIPBMG_OK && st != HIPBMG_ENOCONV && st != HIPBMG_ENAN) return st;
+    std::string msg = g_err;
+    HIPCHK(hipMemcpy2DAsync(u, nx * sizeof(double), F.x[cur], F.pitch * sizeof(double),
+                            nx * sizeof(double), ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) info->solve_ms = now_ms() - t0;
+    g_err = msg;
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// inspection and single operations
+// ---------------------------------------------------------------------------
+extern "C" hipbmg_status hipbmg_get_stencil(hipbmg_handle h, int l, double *out, void *stream)
+{
+    if (!h || !out) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 0 || l >= h->L) return fail(HIPBMG_EINVAL, "level out of range");
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<double> &A = h->lv[l];
+    for (int k = 0; k < 5; ++k)
+        HIPCHK(hipMemcpy2DAsync(out + (size_t)k * A.nx * A.ny, A.nx * sizeof(double), A.C + k * A.plane,
+                                A.pitch * sizeof(double), A.nx * sizeof(double), A.ny,
+                                hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_get_interp(hipbmg_handle h, int l, double *out, void *stream)
+{
+    if (!h || !out) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
+    for (int k = 0; k < 8; ++k)
+        HIPCHK(hipMemcpy2DAsync(out + (size_t)k * C.nx * C.ny, C.nx * sizeof(double), A.wt + k * A.cplane,
+                                A.cpitch * sizeof(double), C.nx * sizeof(double), C.ny,
+                                hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+static hipbmg_status to_pitched(double *dst, int pitch, const double *src, int nx, int ny, hipStream_t s)
+{
+    HIPCHK(hipMemcpy2DAsync(dst, pitch * sizeof(double), src, nx * sizeof(double), nx * sizeof(double),
+                            ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_zero_ring(dst, nx, ny, pitch, s));
+    return HIPBMG_OK;
+}
+
+static hipbmg_status from_pitched(double *dst, const double *src, int pitch, int nx, int ny, hipStream_t s)
+{
+    HIPCHK(hipMemcpy2DAsync(dst, nx * sizeof(double), src, pitch * sizeof(double), nx * sizeof(double),
+                            ny, hipMemcpyDeviceToDevice, s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *b, double *x,
+                                          int sweeps, void *stream)
+{
+    if (!h || !b || !x) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 0 || l >= h->L || sweeps < 0) return fail(HIPBMG_EINVAL, "bad level or sweeps");
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<double> &A = h->lv[l];
+    STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
+    STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
+    int xb = 0;
+    for (int k = 0; k < sweeps; ++k) {
+        StreamArgs<double> a = base_args(A, h->rb[l]);
+        a.x_in = A.x[xb];
+        a.x_out = A.x[1 - xb];
+        HIPCHK(run_stream(A, SV_SWEEP, a, s));
+        xb = 1 - xb;
+    }
+    STCHK(from_pitched(x, A.x[xb], A.pitch, A.nx, A.ny, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
+                                                   double *q, double *bc, void *stream)
+{
+    if (!h || !b || !x || !q || !bc) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
+    STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
+    STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
+    HIPCHK(hipMemsetAsync(A.q, 0, A.plane * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(C.b, 0, C.plane * sizeof(double), s));
+    StreamArgs<double> a = base_args(A, h->rb[l]);
+    a.x_in = A.x[0];
+    a.x_out = A.x[1];
+    a.q_out = A.q;
+    a.bc = C.b;
+    a.wt = A.wt;
+    a.cnx = C.nx;
+    a.cny = C.ny;
+    a.cpitch = C.pitch;
+    a.cplane = (long long)C.plane;
+    HIPCHK(run_stream(A, SV_SWEEP_RQ, a, s));
+    STCHK(from_pitched(x, A.x[1], A.pitch, A.nx, A.ny, s));
+    STCHK(from_pitched(q, A.q, A.pitch, A.nx, A.ny, s));
+    STCHK(from_pitched(bc, C.b, C.pitch, C.nx, C.ny, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
+                                                 const double *q, const double *xc, int rescorr,
+                                                 double *sumsq_host, void *stream)
+{
+    if (!h || !b || !x || !q || !xc) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
+    STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
+    STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
+    STCHK(to_pitched(A.q, A.pitch, q, A.nx, A.ny, s));
+    STCHK(to_pitched(C.x[1], C.pitch, xc, C.nx, C.ny, s));
+    StreamArgs<double> a = base_args(A, h->rb[l]);
+    a.x_in = A.x[0];
+    a.x_out = A.x[1];
+    a.xc = C.x[1];
+    a.wt = A.wt;
+    a.q_in = A.q;
+    a.rescorr = rescorr;
+    a.cnx = C.nx;
+    a.cny = C.ny;
+    a.cpitch = C.pitch;
+    a.cplane = (long long)C.plane;
+    a.partials = h->d_partials;
+    int nt = 0;
+    HIPCHK(run_stream(A, sumsq_host ? SV_INTERP_NORM : SV_INTERP, a, s, &nt));
+    if (sumsq_host) {
+        HIPCHK(launch_finalize_norm(h->d_partials, nt, nullptr, h->d_scal + 5, s));
+        STCHK(read_scalars(h, 5, 1, s));
+        *sumsq_host = h->h_scal[5] * h->h_scal[5];
+    }
+    STCHK(from_pitched(x, A.x[1], A.pitch, A.nx, A.ny, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// finite-volume operator and adjoint gradient
+// ---------------------------------------------------------------------------
+extern "C" hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cell, int is_log,
+                                               double *coeffs_out, void *stream)
+{
+    if (!cell || !coeffs_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)nx * ny;
+    HIPCHK(launch_fv5(nx, ny, cell, is_log, coeffs_out, coeffs_out + n, coeffs_out + 2 * n, nx, s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double *u,
+                                          const double *lam, double *grad_out, void *stream)
+{
+    if (!theta || !u || !lam || !grad_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
+    HIPCHK(launch_grad_logD(nx, ny, theta, u, lam, grad_out, (hipStream_t)stream));
+    return HIPBMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// live kernel timing
+// ---------------------------------------------------------------------------
+extern "C" hipbmg_status hipbmg_profile(hipbmg_handle h, int enable)
+{
+    if (!h) return fail(HIPBMG_EINVAL, "null handle");
+    if (enable && !h->ev0[0])
+        for (int k = 0; k < 64; ++k) {
+            HIPCHK(hipEventCreate(&h->ev0[k]));
+            HIPCHK(hipEventCreate(&h->ev1[k]));
+        }
+    h->prof_on = enable ? 1 : 0;
+    h->prof_n = 0;
+    memset(h->prof_ms, 0, sizeof h->prof_ms);
+    memset(h->prof_cnt, 0, sizeof h->prof_cnt);
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int variant,
+                                             double *total_ms_host, long long *launches_host,
+                                             double *bytes_per_launch_host)
+{
+    if (!h) return fail(HIPBMG_EINVAL, "null handle");
+    if (precision < 0 || precision > 1 || variant < 0 || variant >= SV_COUNT)
+        return fail(HIPBMG_EINVAL, "bad precision or kernel index");
+    if (total_ms_host) *total_ms_host = h->prof_ms[precision][variant];
+    if (launches_host) *launches_host = h->prof_cnt[precision][variant];
+    if (bytes_per_launch_host) {
+        // algorithmic bytes of one launch on the finest level (every vertex of
+        // the grid, boundary ring included): the relaxation reads x, b and the
+        // stencil planes and writes x; the fused variants add their extra fields
+        const LevelDev<double> &F = h->lv[h->L - 1];
+        const double n = (double)F.nx * F.ny, w = precision ? 4.0 : 8.0;
+        const double s = F.npt == 5 ? 3.0 : 5.0;
+        double per = (s + 3.0) * w;
+        if (variant == SV_SWEEP_ZX || variant == SV_SWEEP_RQ_ZX) per -= w;
+        if (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX) per += w + 2.0 * w + 0.25 * w;
+        if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
+        *bytes_per_launch_host = per * n;
+    }
+    return HIPBMG_OK;
+}

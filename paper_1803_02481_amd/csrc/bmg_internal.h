@@ -1,0 +1,107 @@
+// bmg_internal.h -- shared declarations of the hipbmg device code and host runtime.
+//
+// Storage of one level (all planes pitched, row j starts at j*pitch, pitch even
+// and rows 256-byte aligned, padding columns hold 0):
+//   coef planes C, W, S, SW, SE   (positive connections; SW = SE = 0 for a
+//                                  5-point finest level)
+//   x0, x1                        ping-pong iterates (streaming kernels read one
+//                                 and write the other)
+//   b                             right-hand side (restricted residual below the finest)
+//   q                             r/C at fine-only vertices after pre-relaxation
+//   wt                            8 interpolation weight planes from level l-1,
+//                                 at coarse resolution (plane order as in hipbmg.h)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace hbmg {
+
+// Weight plane indices (fine vertex of coarse cell (I,J) -> coarse corner).
+enum { WXL = 0, WXR = 1, WYB = 2, WYT = 3, WCSW = 4, WCSE = 5, WCNW = 6, WCNE = 7 };
+
+template <typename T>
+struct LevelDev {
+    int nx, ny, pitch, npt;
+    size_t plane;          // elements per plane (ny * pitch)
+    T *C, *W, *S, *SW, *SE;
+    T *x[2];
+    T *b, *q;
+    T *wt;                 // weights from the next-coarser level onto this one (null on level 0)
+    int cpitch;            // pitch of the coarser level
+    size_t cplane;         // plane size of the coarser level
+};
+
+// Arguments of the streaming relaxation kernel.
+template <typename T>
+struct StreamArgs {
+    int nx, ny, pitch;
+    const T *C, *W, *S, *SW, *SE, *b;
+    const T *x_in;
+    T *x_out;
+    // interpolate-and-correct on load (up-leg)
+    const T *xc, *wt, *q_in;
+    int cnx, cny, cpitch;
+    long long cplane;
+    int rescorr;
+    // residual -> q, restriction -> bc (down-leg)
+    T *q_out, *bc;
+    // norm partial sums, one per tile
+    double *partials;
+    int nstrips, nblocks, rb, ntiles;
+};
+
+enum StreamVariant {
+    SV_SWEEP = 0,        // one relaxation
+    SV_SWEEP_ZX = 1,     // one relaxation from x = 0 (x not read)
+    SV_SWEEP_RQ = 2,     // relaxation, residual -> q, restriction -> bc
+    SV_SWEEP_RQ_ZX = 3,
+    SV_INTERP = 4,       // interpolate-and-correct on load, then relaxation
+    SV_INTERP_NORM = 5,  // ... plus residual norm partials
+    SV_SWEEP_NORM = 6,   // relaxation plus residual norm partials
+    SV_COUNT = 7
+};
+
+// Owned column pairs per strip for a variant (64 lanes minus halo lanes).
+int stream_owned_pairs(int npt, int variant);
+// Launch geometry for a level.
+void stream_geometry(int nx, int ny, int npt, int variant, int rb, int *nstrips, int *nblocks,
+                     int *ntiles, int *grid);
+template <typename T>
+hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid, hipStream_t s);
+
+// Setup kernels.
+hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,
+                      double *S, int pitch, hipStream_t s);
+hipError_t launch_grad_logD(int nx, int ny, const double *theta, const double *u,
+                            const double *lam, double *g, hipStream_t s);
+hipError_t launch_interp_weights(const LevelDev<double> &f, int cnx, int cny, double *wt,
+                                 int cpitch, size_t cplane, hipStream_t s);
+hipError_t launch_rap(const LevelDev<double> &f, const LevelDev<double> &c, hipStream_t s);
+
+// Collapsed coarse levels: one persistent workgroup runs levels top..0 of the
+// V-cycle.  The iterate of a collapsed level below `top` is x[1] and x[0] holds
+// its residual; at `top` the iterate is x[xb_top] and the residual x[1 - xb_top].
+template <typename T>
+struct CollapseArgs {
+    const LevelDev<T> *levels;   // device array, index = level
+    int top, xb_top, zero_top;   // zero_top: start level `top` from x = 0
+    int nu1, nu2, rescorr;
+    const double *chol;          // coarsest Cholesky factor (nc x nc, lower, row-major), FP64
+    const int *cidx;             // coarsest vertex (row-major [ny0][nx0]) -> unknown or -1
+    int nc;
+    double *work;                // nc doubles
+    double *partials;            // want_norm: partials[0] = ||b - A x||^2 at level top
+    int want_norm;
+};
+template <typename T>
+hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s);
+
+// Sum of squares of interior entries of a pitched field -> partials.
+hipError_t launch_sumsq(const double *v, int nx, int ny, int pitch, double *partials, int nparts,
+                        hipStream_t s);
+// out[0] = sqrt(sum(partials)) / denom_src[0] (denom_src may be null -> plain norm).
+hipError_t launch_finalize_norm(const double *partials, int n, const double *denom, double *out,
+                                hipStream_t s);
+
+}  // namespace hbmg

@@ -1,0 +1,18 @@
+// bmg_misc.h -- declarations of the element-wise solve-driver kernels.
+#pragma once
+#include "bmg_internal.h"
+
+namespace hbmg {
+
+hipError_t launch_zero_ring(double *v, int nx, int ny, int pitch, hipStream_t s);
+// FP64 level -> FP32 edge-form level (and its interpolation weights)
+hipError_t launch_demote_level(const LevelDev<double> &d, const LevelDev<float> &f, int cnx,
+                               int cny, hipStream_t s);
+// r32 = (float)(b - A u) with FP64 partial sums of squares; *nparts partials written
+hipError_t launch_ir_residual(const LevelDev<double> &d, const double *u, float *r32, int pitchf,
+                              double *partials, int *nparts, hipStream_t s);
+// u += (double) e
+hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, int nx, int ny,
+                            hipStream_t s);
+
+}  // namespace hbmg

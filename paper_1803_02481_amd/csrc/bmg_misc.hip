@@ -1,0 +1,137 @@
+// bmg_misc.hip -- small element-wise kernels of the solve driver: boundary ring
+// clearing, FP32 demotion of a level into edge form, and the FP64 outer steps
+// of mixed-precision iterative refinement.
+#include "bmg_misc.h"
+
+namespace hbmg {
+
+__global__ void k_zero_ring(double *__restrict__ v, int nx, int ny, int pitch)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nx) {
+        v[k] = 0.0;
+        v[(size_t)(ny - 1) * pitch + k] = 0.0;
+    }
+    if (k < ny) {
+        v[(size_t)k * pitch] = 0.0;
+        v[(size_t)k * pitch + nx - 1] = 0.0;
+    }
+}
+
+hipError_t launch_zero_ring(double *v, int nx, int ny, int pitch, hipStream_t s)
+{
+    const int n = nx > ny ? nx : ny;
+    hipLaunchKernelGGL(k_zero_ring, dim3((n + 255) / 256), dim3(256), 0, s, v, nx, ny, pitch);
+    return hipGetLastError();
+}
+
+// FP32 edge form of a level: connections rounded to float, and the plane that
+// holds C in FP64 holds instead the excess E = C - (sum of the connections),
+// rounded to float.  The FP32 kernels form A x as
+//   sum_q conn_pq (x_p - x_q) + E_p x_p,
+// so the zero row sums of pure-diffusion rows survive the rounding exactly.
+__global__ void k_demote_level(LevelDev<double> d, LevelDev<float> f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const size_t p = (size_t)j * d.pitch + i, P = d.pitch;
+    const size_t pf = (size_t)j * f.pitch + i;
+    f.W[pf] = (float)d.W[p];
+    f.S[pf] = (float)d.S[p];
+    f.SW[pf] = (float)d.SW[p];
+    f.SE[pf] = (float)d.SE[p];
+    float e = 0.0f;
+    if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2) {
+        double rs = d.W[p] + d.W[p + 1] + d.S[p] + d.S[p + P] + d.SW[p] + d.SW[p + P + 1] + d.SE[p] +
+                    d.SE[p + P - 1];
+        e = (float)(d.C[p] - rs);
+    }
+    f.C[pf] = e;
+}
+
+__global__ void k_demote_weights(const double *__restrict__ wd, size_t pd, int pitchd,
+                                 float *__restrict__ wf, size_t pf, int pitchf, int cnx, int cny)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y;
+    if (I >= cnx) return;
+    for (int k = 0; k < 8; ++k)
+        wf[k * pf + (size_t)J * pitchf + I] = (float)wd[k * pd + (size_t)J * pitchd + I];
+}
+
+hipError_t launch_demote_level(const LevelDev<double> &d, const LevelDev<float> &f, int cnx,
+                               int cny, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_demote_level, dim3((d.nx + 255) / 256, d.ny), dim3(256), 0, s, d, f);
+    if (d.wt)
+        hipLaunchKernelGGL(k_demote_weights, dim3((cnx + 255) / 256, cny), dim3(256), 0, s, d.wt,
+                           d.cplane, d.cpitch, f.wt, f.cplane, f.cpitch, cnx, cny);
+    return hipGetLastError();
+}
+
+// FP64 outer residual of iterative refinement: r = b - A u (FP64, standard
+// form), written demoted to FP32 as the inner right-hand side, with per-block
+// partial sums of r^2 in FP64.
+template <int NPT>
+__global__ __launch_bounds__(256) void k_ir_residual(LevelDev<double> d, const double *__restrict__ u,
+                                                     float *__restrict__ r32, int pitchf,
+                                                     double *__restrict__ partials)
+{
+    __shared__ double sh[4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    double acc = 0.0;
+    if (i < d.nx) {
+        const size_t p = (size_t)j * d.pitch + i, P = d.pitch;
+        float out = 0.0f;
+        if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2) {
+            double s = d.b[p] + d.W[p] * u[p - 1] + d.W[p + 1] * u[p + 1] + d.S[p] * u[p - P] +
+                       d.S[p + P] * u[p + P];
+            if (NPT == 9)
+                s += d.SW[p] * u[p - P - 1] + d.SW[p + P + 1] * u[p + P + 1] + d.SE[p] * u[p - P + 1] +
+                     d.SE[p + P - 1] * u[p + P - 1];
+            const double r = s - d.C[p] * u[p];
+            acc = r * r;
+            out = (float)r;
+        }
+        r32[(size_t)j * pitchf + i] = out;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+hipError_t launch_ir_residual(const LevelDev<double> &d, const double *u, float *r32, int pitchf,
+                              double *partials, int *nparts, hipStream_t s)
+{
+    dim3 g((d.nx + 255) / 256, d.ny);
+    *nparts = g.x * g.y;
+    if (d.npt == 9)
+        hipLaunchKernelGGL(k_ir_residual<9>, g, dim3(256), 0, s, d, u, r32, pitchf, partials);
+    else
+        hipLaunchKernelGGL(k_ir_residual<5>, g, dim3(256), 0, s, d, u, r32, pitchf, partials);
+    return hipGetLastError();
+}
+
+// u += (double) e on interior vertices
+__global__ void k_ir_update(double *__restrict__ u, int pitch, const float *__restrict__ e,
+                            int pitchf, int nx, int ny)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2)
+        u[(size_t)j * pitch + i] += (double)e[(size_t)j * pitchf + i];
+}
+
+hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, int nx, int ny,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ir_update, dim3((nx + 255) / 256, ny), dim3(256), 0, s, u, pitch, e,
+                       pitchf, nx, ny);
+    return hipGetLastError();
+}
+
+}  // namespace hbmg

@@ -1,0 +1,378 @@
+// bmg_stream.hip -- streaming four-colour Gauss-Seidel relaxation for gfx950.
+//
+// One relaxation (section 2: pointwise Gauss-Seidel with four colours,
+// colour k = (i mod 2) + 2 (j mod 2), colours 0,1,2,3 in turn) done in ONE pass
+// over HBM instead of four:
+//
+//   * A wave (64 lanes) owns a strip of column pairs; lane t holds the even
+//     column 2t and the odd column 2t+1.  Neighbour columns come from the
+//     adjacent lanes by cross-lane shuffles, so no LDS and no barriers.
+//   * The wave walks up the strip two rows per step.  Step j (j even) updates
+//     colours 0 and 1 on row j, then colours 2 and 3 on row j-1.  Every value
+//     a colour reads is then exactly the value the colour-by-colour sweep would
+//     read: colour 0/1 on row j see rows j+-1 before colours 2/3 touch them,
+//     and colours 2/3 on row j-1 see rows j-2 and j after colours 0/1.  After
+//     step j rows j-1 and j are final.
+//   * Strips overlap by a few halo lanes that recompute their neighbour's
+//     columns (no lane reads a value another wave writes), and each block of
+//     rows is preceded by one or two prologue steps that rebuild the state of
+//     the rows below it.  The kernel therefore reads x_in and writes x_out.
+//
+// Fused variants (one HBM pass each):
+//   - residual r = b - A x on the final rows (rows j-2, j-1 at step j), q = r/C
+//     stored at fine-only vertices, and the restriction b_c = P^T r of coarse
+//     row (j-2)/2 (Algorithm 1, restrict residual; section 3, interpolation
+//     with the r/C term);
+//   - interpolate-and-correct x += P x_c (+ q) applied to each row as it is
+//     loaded, before the relaxation (Algorithm 1, interpolate and correct);
+//   - residual norm partial sums for the convergence test.
+//
+// The tile index is remapped so that the 8 XCDs (WG i runs on XCD i mod 8)
+// each get a contiguous band of strips and share halo rows in their own L2.
+#include "bmg_internal.h"
+
+namespace hbmg {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T>
+__device__ __forceinline__ void ld2(const T *__restrict__ p, T &a, T &b)
+{
+    typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type *>(p);
+    a = v.x;
+    b = v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void st2(T *__restrict__ p, T a, T b)
+{
+    typename Vec2<T>::type v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename Vec2<T>::type *>(p) = v;
+}
+
+// value of lane-1 / lane+1 (lane 0 / lane 63 receive an unusable value; those
+// lanes are halo lanes whose results are never stored)
+template <typename T> __device__ __forceinline__ T fromL(T v) { return __shfl_up(v, 1, 64); }
+template <typename T> __device__ __forceinline__ T fromR(T v) { return __shfl_down(v, 1, 64); }
+
+template <typename T>
+struct Row {
+    T x0, x1, b0, b1, C0, C1, W0, W1, S0, S1, SW0, SW1, SE0, SE1;
+};
+
+// Residual b - (A x) at the even column of row `cu` (rows `bl` below and `ab`
+// above), and the diagonal used by the relaxation.  All lanes must call: the
+// functions shuffle.  FP64 levels hold C in the C plane (standard form); FP32
+// levels hold the excess E = C - sum(connections) there and use the edge form
+//   (A x)_p = sum_q conn_pq (x_p - x_q) + E_p x_p,   diag = sum_q conn_pq + E_p,
+// which keeps zero row sums exact after rounding to FP32.
+template <typename T> struct IsEdge { enum { value = 0 }; };
+template <> struct IsEdge<float> { enum { value = 1 }; };
+
+template <typename T, int NPT>
+__device__ __forceinline__ T res_even(const Row<T> &bl, const Row<T> &cu, const Row<T> &ab, T &diag)
+{
+    const T xw = fromL(cu.x1);
+    T xsw = T(0), xnw = T(0), cnw = T(0);
+    if (NPT == 9) {
+        xsw = fromL(bl.x1);
+        xnw = fromL(ab.x1);
+        cnw = fromL(ab.SE1);
+    }
+    const T x = cu.x0;
+    if (!IsEdge<T>::value) {
+        T s = cu.b0 + cu.W0 * xw + cu.W1 * cu.x1 + cu.S0 * bl.x0 + ab.S0 * ab.x0;
+        if (NPT == 9) s += cu.SW0 * xsw + ab.SW1 * ab.x1 + cu.SE0 * bl.x1 + cnw * xnw;
+        diag = cu.C0;
+        return s - cu.C0 * x;
+    } else {
+        T s = cu.b0 + cu.W0 * (xw - x) + cu.W1 * (cu.x1 - x) + cu.S0 * (bl.x0 - x) + ab.S0 * (ab.x0 - x);
+        T d = cu.W0 + cu.W1 + cu.S0 + ab.S0 + cu.C0;
+        if (NPT == 9) {
+            s += cu.SW0 * (xsw - x) + ab.SW1 * (ab.x1 - x) + cu.SE0 * (bl.x1 - x) + cnw * (xnw - x);
+            d += cu.SW0 + ab.SW1 + cu.SE0 + cnw;
+        }
+        diag = d;
+        return s - cu.C0 * x;
+    }
+}
+
+template <typename T, int NPT>
+__device__ __forceinline__ T res_odd(const Row<T> &bl, const Row<T> &cu, const Row<T> &ab, T &diag)
+{
+    const T xe = fromR(cu.x0), we = fromR(cu.W0);
+    T xne = T(0), xse = T(0), cne = T(0);
+    if (NPT == 9) {
+        xne = fromR(ab.x0);
+        xse = fromR(bl.x0);
+        cne = fromR(ab.SW0);
+    }
+    const T x = cu.x1;
+    if (!IsEdge<T>::value) {
+        T s = cu.b1 + cu.W1 * cu.x0 + we * xe + cu.S1 * bl.x1 + ab.S1 * ab.x1;
+        if (NPT == 9) s += cu.SW1 * bl.x0 + cne * xne + cu.SE1 * xse + ab.SE0 * ab.x0;
+        diag = cu.C1;
+        return s - cu.C1 * x;
+    } else {
+        T s = cu.b1 + cu.W1 * (cu.x0 - x) + we * (xe - x) + cu.S1 * (bl.x1 - x) + ab.S1 * (ab.x1 - x);
+        T d = cu.W1 + we + cu.S1 + ab.S1 + cu.C1;
+        if (NPT == 9) {
+            s += cu.SW1 * (bl.x0 - x) + cne * (xne - x) + cu.SE1 * (xse - x) + ab.SE0 * (ab.x0 - x);
+            d += cu.SW1 + cne + cu.SE1 + ab.SE0;
+        }
+        diag = d;
+        return s - cu.C1 * x;
+    }
+}
+
+template <int V> struct VariantFlags;
+template <> struct VariantFlags<SV_SWEEP>       { enum { ZX = 0, INTERP = 0, RES = 0, RQ = 0, NORM = 0 }; };
+template <> struct VariantFlags<SV_SWEEP_ZX>    { enum { ZX = 1, INTERP = 0, RES = 0, RQ = 0, NORM = 0 }; };
+template <> struct VariantFlags<SV_SWEEP_RQ>    { enum { ZX = 0, INTERP = 0, RES = 1, RQ = 1, NORM = 0 }; };
+template <> struct VariantFlags<SV_SWEEP_RQ_ZX> { enum { ZX = 1, INTERP = 0, RES = 1, RQ = 1, NORM = 0 }; };
+template <> struct VariantFlags<SV_INTERP>      { enum { ZX = 0, INTERP = 1, RES = 0, RQ = 0, NORM = 0 }; };
+template <> struct VariantFlags<SV_INTERP_NORM> { enum { ZX = 0, INTERP = 1, RES = 1, RQ = 0, NORM = 1 }; };
+template <> struct VariantFlags<SV_SWEEP_NORM>  { enum { ZX = 0, INTERP = 0, RES = 1, RQ = 0, NORM = 1 }; };
+
+__host__ __device__ constexpr int halo_left(int npt, int res) { return 1 + (npt == 9) + res; }
+__host__ __device__ constexpr int halo_right(int npt, int interp) { return 1 + (npt == 9) + interp; }
+
+template <typename T, int NPT, int V>
+__global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
+{
+    using F = VariantFlags<V>;
+    constexpr int HL = halo_left(NPT, F::RES);
+    constexpr int HR = halo_right(NPT, F::INTERP);
+    constexpr int OWN = 64 - HL - HR;
+
+    // XCD-aware tile order: consecutive tiles land on the same XCD
+    const int per = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;
+    const int strip = tile % a.nstrips;
+    const int blk = tile / a.nstrips;
+    const int lane = threadIdx.x;
+    const int t = strip * OWN + lane - HL;   // column pair index
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;      // pair in the allocation (o may be padding)
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = F::INTERP || F::RQ ? (t >= 0 && t < a.cnx) : false;   // coarse column t
+
+    auto load_row = [&](Row<T> &r, int j) {
+        bool rv = colv && j >= 0 && j < ny;
+        r.x0 = r.x1 = r.b0 = r.b1 = r.C0 = r.C1 = r.W0 = r.W1 = r.S0 = r.S1 = T(0);
+        r.SW0 = r.SW1 = r.SE0 = r.SE1 = T(0);
+        if (rv) {
+            const size_t off = (size_t)j * pitch + e;
+            if (!F::ZX) ld2(a.x_in + off, r.x0, r.x1);
+            ld2(a.b + off, r.b0, r.b1);
+            ld2(a.C + off, r.C0, r.C1);
+            ld2(a.W + off, r.W0, r.W1);
+            ld2(a.S + off, r.S0, r.S1);
+            if (NPT == 9) {
+                ld2(a.SW + off, r.SW0, r.SW1);
+                ld2(a.SE + off, r.SE0, r.SE1);
+            }
+        }
+        if (F::INTERP) {
+            // x += P x_c (+ r/C at fine-only vertices); coarse column t
+            const bool rin = j >= 1 && j <= ny - 2;
+            const int jc = j >> 1;
+            const T *wt = a.wt;
+            const long long cp = a.cplane;
+            if ((j & 1) == 0) {
+                T xa = T(0), wl = T(0), wr = T(0), qo = T(0), qe = T(0);
+                if (cv && rin) {
+                    const size_t co = (size_t)jc * a.cpitch + t;
+                    xa = a.xc[co];
+                    wl = wt[WXL * cp + co];
+                    wr = wt[WXR * cp + co];
+                    if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, qe, qo);
+                }
+                T xb = fromR(xa);
+                if (rin && ie) r.x0 += xa;
+                if (rin && io) r.x1 += wl * xa + wr * xb + qo;
+            } else {
+                T xa = T(0), xcu = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0), cnw = T(0),
+                  cne = T(0), qe = T(0), qo = T(0);
+                if (cv && rin) {
+                    const size_t co = (size_t)jc * a.cpitch + t;
+                    xa = a.xc[co];
+                    xcu = a.xc[co + a.cpitch];
+                    yb = wt[WYB * cp + co];
+                    yt = wt[WYT * cp + co];
+                    csw = wt[WCSW * cp + co];
+                    cse = wt[WCSE * cp + co];
+                    cnw = wt[WCNW * cp + co];
+                    cne = wt[WCNE * cp + co];
+                    if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, qe, qo);
+                }
+                T xb = fromR(xa), xd = fromR(xcu);
+                if (rin && ie) r.x0 += yb * xa + yt * xcu + qe;
+                if (rin && io) r.x1 += csw * xa + cse * xb + cnw * xcu + cne * xd + qo;
+            }
+        }
+    };
+
+    const int nsteps = (ny - 1) / 2;            // steps j = 2, 4, ..., ny-1
+    const int s0 = blk * a.rb;
+    const int s1 = min(s0 + a.rb, nsteps);
+    const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+    constexpr int PRO = F::RES ? 2 : 1;         // prologue steps
+
+    Row<T> rm3, rm2, rm1, r0, rp1;
+    T rr3e = T(0), rr3o = T(0);                 // residual of row j-3
+    T ytp = T(0), cnwp = T(0), cnep = T(0);     // weights of coarse row (j-2)/2 - 1
+    double acc = 0.0;
+
+    // state below the first prologue step: only row j-1 is read by a partial
+    // step (colours 0 and 1); rows j-2, j-3 are rotated in before any use
+    rm3 = Row<T>{};
+    rm2 = Row<T>{};
+    load_row(rm1, jfirst - 2 * PRO - 1);
+
+    for (int step = -PRO; step <= s1 - 1 - s0; ++step) {
+        const int j = jfirst + 2 * step;
+        const int mode = step < 0 ? (step == -PRO ? 0 : 1) : 2;   // 0 partial, 1 full, 2 write
+        load_row(r0, j);
+        load_row(rp1, j + 1);
+        const bool rj = j >= 1 && j <= ny - 2;
+        const bool rjm = j - 1 >= 1 && j - 1 <= ny - 2;
+        // colours 0 and 1 on row j
+        {
+            T d;
+            T r = res_even<T, NPT>(rm1, r0, rp1, d);
+            if (rj && ie) r0.x0 += r / d;
+            r = res_odd<T, NPT>(rm1, r0, rp1, d);
+            if (rj && io) r0.x1 += r / d;
+        }
+        if (mode != 0) {
+            // colours 2 and 3 on row j-1
+            T d;
+            T r = res_even<T, NPT>(rm2, rm1, r0, d);
+            if (rjm && ie) rm1.x0 += r / d;
+            r = res_odd<T, NPT>(rm2, rm1, r0, d);
+            if (rjm && io) rm1.x1 += r / d;
+
+            if (mode == 2 && own) {
+                if (rjm) st2(a.x_out + (size_t)(j - 1) * pitch + e, rm1.x0, rm1.x1);
+                if (rj) st2(a.x_out + (size_t)j * pitch + e, r0.x0, r0.x1);
+            }
+            if (F::RES) {
+                // residuals of the final rows j-2 (even) and j-1 (odd)
+                const bool rA = j - 2 >= 1 && j - 2 <= ny - 2;
+                T dae, dao, dbe, dbo;
+                T ae = res_even<T, NPT>(rm3, rm2, rm1, dae);
+                T ao = res_odd<T, NPT>(rm3, rm2, rm1, dao);
+                T be = res_even<T, NPT>(rm2, rm1, r0, dbe);
+                T bo = res_odd<T, NPT>(rm2, rm1, r0, dbo);
+                if (!(rA && ie)) ae = T(0);
+                if (!(rA && io)) ao = T(0);
+                if (!(rjm && ie)) be = T(0);
+                if (!(rjm && io)) bo = T(0);
+                if (F::NORM && mode == 2 && own)
+                    acc += (double)ae * ae + (double)ao * ao + (double)be * be + (double)bo * bo;
+                if (F::RQ) {
+                    if (mode == 2 && own) {
+                        if (rA && io) a.q_out[(size_t)(j - 2) * pitch + o] = ao / dao;
+                        if (rjm) st2(a.q_out + (size_t)(j - 1) * pitch + e,
+                                     ie ? be / dbe : T(0), io ? bo / dbo : T(0));
+                    }
+                    // restriction onto coarse row jc = (j-2)/2, coarse column t
+                    const int jc = (j - 2) >> 1;
+                    const bool jcin = j - 2 >= 2 && jc <= a.cny - 2;
+                    T xl = T(0), xr = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0),
+                      cnw = T(0), cne = T(0);
+                    if (cv && j - 2 >= 0 && jc <= a.cny - 1) {
+                        const size_t co = (size_t)jc * a.cpitch + t;
+                        const long long cp = a.cplane;
+                        xl = a.wt[WXL * cp + co];
+                        xr = a.wt[WXR * cp + co];
+                        yb = a.wt[WYB * cp + co];
+                        yt = a.wt[WYT * cp + co];
+                        csw = a.wt[WCSW * cp + co];
+                        cse = a.wt[WCSE * cp + co];
+                        cnw = a.wt[WCNW * cp + co];
+                        cne = a.wt[WCNE * cp + co];
+                    }
+                    T lxr = fromL(xr), lcse = fromL(cse), lcnep = fromL(cnep);
+                    T lao = fromL(ao), lbo = fromL(bo), lr3o = fromL(rr3o);
+                    T bcv = ae + xl * ao + lxr * lao + yb * be + ytp * rr3e + csw * bo + lcse * lbo +
+                            cnwp * rr3o + lcnep * lr3o;
+                    if (mode == 2 && own && jcin && t >= 1 && t <= a.cnx - 2)
+                        a.bc[(size_t)jc * a.cpitch + t] = bcv;
+                    ytp = yt;
+                    cnwp = cnw;
+                    cnep = cne;
+                }
+                rr3e = be;
+                rr3o = bo;
+            }
+        }
+        rm3 = rm1;
+        rm2 = r0;
+        rm1 = rp1;
+    }
+    if (F::NORM) {
+        // wave reduction in a fixed order -> one partial per tile
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) a.partials[tile] = acc;
+    }
+}
+
+int stream_owned_pairs(int npt, int variant)
+{
+    int res = (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_INTERP_NORM ||
+               variant == SV_SWEEP_NORM);
+    int interp = (variant == SV_INTERP || variant == SV_INTERP_NORM);
+    return 64 - halo_left(npt, res) - halo_right(npt, interp);
+}
+
+void stream_geometry(int nx, int ny, int npt, int variant, int rb, int *nstrips, int *nblocks,
+                     int *ntiles, int *grid)
+{
+    int own = stream_owned_pairs(npt, variant);
+    int pairs = (nx + 1) / 2;
+    int nsteps = (ny - 1) / 2;
+    *nstrips = (pairs + own - 1) / own;
+    *nblocks = (nsteps + rb - 1) / rb;
+    *ntiles = *nstrips * *nblocks;
+    *grid = (*ntiles + 7) / 8 * 8;
+}
+
+template <typename T, int NPT>
+static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStream_t s)
+{
+    dim3 g(grid), b(64);
+    switch (variant) {
+    case SV_SWEEP: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP>), g, b, 0, s, a); break;
+    case SV_SWEEP_ZX: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_ZX>), g, b, 0, s, a); break;
+    case SV_SWEEP_RQ: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_RQ>), g, b, 0, s, a); break;
+    case SV_SWEEP_RQ_ZX: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_RQ_ZX>), g, b, 0, s, a); break;
+    case SV_INTERP: hipLaunchKernelGGL((k_stream<T, NPT, SV_INTERP>), g, b, 0, s, a); break;
+    case SV_INTERP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_INTERP_NORM>), g, b, 0, s, a); break;
+    case SV_SWEEP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_NORM>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid, hipStream_t s)
+{
+    if (npt == 5) return launch_v<T, 5>(variant, a, grid, s);
+    if (npt == 9) return launch_v<T, 9>(variant, a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_stream<double>(int, int, const StreamArgs<double> &, int, hipStream_t);
+template hipError_t launch_stream<float>(int, int, const StreamArgs<float> &, int, hipStream_t);
+
+}  // namespace hbmg

@@ -1,0 +1,248 @@
+"""Thin Python binding of the hipbmg C interface (include/hipbmg.h).
+
+Argument marshalling only: every step of setup and solve runs in the HIP
+library ``libhipbmg.so`` built in-tree for gfx950.  torch supplies device
+memory (tensor data pointers) and the current stream.  Loading fails loudly if
+the library is missing; there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhipbmg.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ENAN = range(7)
+FP64, MIXED = 0, 1
+MAX_LEVELS = 24
+MAX_HIST = 1024
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("coarsest_n", ctypes.c_int),
+                ("collapse_level", ctypes.c_int), ("residual_correction", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_max_cycles", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("use_graph", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("outer_steps", ctypes.c_int), ("relres", ctypes.c_double),
+                ("levels", ctypes.c_int), ("collapse_level", ctypes.c_int),
+                ("model_us", ctypes.c_double * MAX_LEVELS), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("relres_hist", ctypes.c_double * MAX_HIST)]
+
+    def history(self):
+        n = self.outer_steps if self.outer_steps else self.cycles
+        return list(self.relres_hist[: min(n, MAX_HIST)])
+
+
+class HipBMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("hipbmg status %d: %s" % (status, msg))
+        self.status = status
+
+
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "hipbmg_default_params": (None, [ctypes.POINTER(Params)]),
+    "hipbmg_setup": (_I, [_I, _I, _I, _VP, ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
+    "hipbmg_solve": (_I, [_VP, _VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(Info)]),
+    "hipbmg_destroy": (_I, [_VP]),
+    "hipbmg_level_size": (_I, [_VP, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "hipbmg_get_stencil": (_I, [_VP, _I, _VP, _VP]),
+    "hipbmg_get_interp": (_I, [_VP, _I, _VP, _VP]),
+    "hipbmg_op_smooth": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
+    "hipbmg_op_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
+    "hipbmg_op_interp_smooth": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(ctypes.c_double), _VP]),
+    "hipbmg_fv5_from_cells": (_I, [_I, _I, _VP, _I, _VP, _VP]),
+    "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "hipbmg_profile": (_I, [_VP, _I]),
+    "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libhipbmg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhipbmg.so is not built (run python -m paper_1803_02481_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise HipBMGError(status, lib().hipbmg_last_error().decode())
+
+
+def _ptr(t, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("expected a contiguous %s tensor" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_params(**kw):
+    p = Params()
+    lib().hipbmg_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Hierarchy:
+    """Multigrid hierarchy on the GPU (hipbmg_setup / hipbmg_solve)."""
+
+    def __init__(self, coeffs, **params):
+        if coeffs.dim() != 3 or coeffs.shape[0] not in (3, 5):
+            raise ValueError("coeffs must be [3 or 5][ny][nx]")
+        self.npt = 5 if coeffs.shape[0] == 3 else 9
+        self.ny, self.nx = int(coeffs.shape[1]), int(coeffs.shape[2])
+        self.params = default_params(**params)
+        self.device = coeffs.device
+        h = ctypes.c_void_p()
+        _check(lib().hipbmg_setup(self.nx, self.ny, self.npt, _ptr(coeffs), ctypes.byref(self.params),
+                                  _stream(), ctypes.byref(h)))
+        self._h = h
+        self.L = self._levels()
+
+    def _levels(self):
+        L = 0
+        while lib().hipbmg_level_size(self._h, L, None, None) == OK:
+            L += 1
+        return L
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().hipbmg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self, l):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().hipbmg_level_size(self._h, l, ctypes.byref(a), ctypes.byref(b)))
+        return b.value, a.value   # (ny, nx)
+
+    def solve(self, b, u=None, tol=1e-10, check=True):
+        """Returns (u, info).  u is updated in place if given."""
+        if u is None:
+            u = torch.zeros_like(b)
+        info = Info()
+        st = lib().hipbmg_solve(self._h, _ptr(b), _ptr(u), tol, _stream(), ctypes.byref(info))
+        if check and st != OK:
+            _check(st)
+        info.status = st
+        return u, info
+
+    def stencil(self, l):
+        ny, nx = self.size(l)
+        out = torch.zeros((5, ny, nx), dtype=torch.float64, device=self.device)
+        _check(lib().hipbmg_get_stencil(self._h, l, _ptr(out), _stream()))
+        return out
+
+    def interp(self, l):
+        cny, cnx = self.size(l - 1)
+        out = torch.zeros((8, cny, cnx), dtype=torch.float64, device=self.device)
+        _check(lib().hipbmg_get_interp(self._h, l, _ptr(out), _stream()))
+        return out
+
+    def profile(self, enable=True):
+        _check(lib().hipbmg_profile(self._h, 1 if enable else 0))
+
+    KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
+               "interp_relax_norm", "relax_norm")
+
+    def profile_read(self, precision=0):
+        """{kernel name: (total_ms, launches, bytes_per_launch)} for launched kernels."""
+        out = {}
+        for k, name in enumerate(self.KERNELS):
+            ms, n, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+            _check(lib().hipbmg_profile_read(self._h, precision, k, ctypes.byref(ms), ctypes.byref(n),
+                                             ctypes.byref(by)))
+            if n.value:
+                out[name] = (ms.value, n.value, by.value)
+        return out
+
+    def op_smooth(self, l, b, x, sweeps=1):
+        x = x.clone()
+        _check(lib().hipbmg_op_smooth(self._h, l, _ptr(b), _ptr(x), sweeps, _stream()))
+        return x
+
+    def op_smooth_restrict(self, l, b, x):
+        x = x.clone()
+        q = torch.zeros_like(x)
+        cny, cnx = self.size(l - 1)
+        bc = torch.zeros((cny, cnx), dtype=torch.float64, device=x.device)
+        _check(lib().hipbmg_op_smooth_restrict(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(bc), _stream()))
+        return x, q, bc
+
+    def op_interp_smooth(self, l, b, x, q, xc, rescorr=1, want_norm=False):
+        x = x.clone()
+        ss = ctypes.c_double(0.0)
+        _check(lib().hipbmg_op_interp_smooth(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(xc), rescorr,
+                                             ctypes.byref(ss) if want_norm else None, _stream()))
+        return (x, ss.value) if want_norm else x
+
+
+def fv5_from_cells(cell, is_log=False):
+    """5-point finite-volume planes {C, W, S} ([3][ny][nx]) from per-cell D or ln D."""
+    ny, nx = cell.shape[0] + 1, cell.shape[1] + 1
+    out = torch.empty((3, ny, nx), dtype=torch.float64, device=cell.device)
+    _check(lib().hipbmg_fv5_from_cells(nx, ny, _ptr(cell), 1 if is_log else 0, _ptr(out), _stream()))
+    return out
+
+
+def grad_logD(theta, u, lam):
+    ny, nx = u.shape
+    g = torch.empty_like(theta)
+    _check(lib().hipbmg_grad_logD(nx, ny, _ptr(theta), _ptr(u), _ptr(lam), _ptr(g), _stream()))
+    return g
+
+
+class SolveFV(torch.autograd.Function):
+    """u = A(theta)^{-1} b with A the 5-point finite-volume operator of
+    -div(exp(theta) grad u) and zero Dirichlet data.  Backward: one adjoint
+    solve with the same hierarchy (A is symmetric) and the per-cell gradient
+    kernel."""
+
+    @staticmethod
+    def forward(ctx, theta, b, tol=1e-10, params=None):
+        coeffs = fv5_from_cells(theta.detach().contiguous(), is_log=True)
+        hier = Hierarchy(coeffs, **(params or {}))
+        u, info = hier.solve(b.detach().contiguous(), tol=tol)
+        ctx.hier = hier
+        ctx.tol = tol
+        ctx.save_for_backward(theta, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        theta, u = ctx.saved_tensors
+        lam, _ = ctx.hier.solve(grad_u.contiguous(), tol=ctx.tol)
+        g_theta = grad_logD(theta.detach().contiguous(), u, lam)
+        ctx.hier.close()
+        return g_theta, lam, None, None

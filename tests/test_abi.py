@@ -1,0 +1,53 @@
+"""CPU checks of the C boundary: the library is built, loads, and exports every
+entry point declared in include/hipbmg.h (no device calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hipbmg.h")
+LIB = os.path.join(ROOT, "paper_1803_02481_amd", "libhipbmg.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hipbmg_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("hipbmg_setup", "hipbmg_solve", "hipbmg_destroy", "hipbmg_fv5_from_cells",
+                 "hipbmg_grad_logD", "hipbmg_last_error", "hipbmg_default_params"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhipbmg.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhipbmg.so not built")
+def test_binding_signatures_cover_the_header():
+    from paper_1803_02481_amd import hipbmg
+    assert set(hipbmg._SIGS) == set(declared_functions())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhipbmg.so not built")
+def test_default_params_and_errors_without_device():
+    from paper_1803_02481_amd import hipbmg
+    p = hipbmg.default_params()
+    assert (p.nu1, p.nu2, p.coarsest_n, p.collapse_level, p.max_cycles) == (2, 1, 3, -1, 500)
+    lib = hipbmg.lib()
+    h = ctypes.c_void_p()
+    # argument validation happens before any device call
+    assert lib.hipbmg_setup(64, 65, 5, ctypes.c_void_p(8), None, None, ctypes.byref(h)) == hipbmg.EINVAL
+    assert b"odd" in lib.hipbmg_last_error()
+    assert lib.hipbmg_setup(65, 65, 7, ctypes.c_void_p(8), None, None, ctypes.byref(h)) == hipbmg.EINVAL
+    assert lib.hipbmg_setup(65, 65, 5, None, None, None, ctypes.byref(h)) == hipbmg.EINVAL
+    assert lib.hipbmg_solve(None, None, None, 1e-10, None, None) == hipbmg.EINVAL
+    assert lib.hipbmg_destroy(None) == hipbmg.OK
