@@ -70,7 +70,7 @@ typedef enum { HIPBMG_FP64 = 0, HIPBMG_MIXED = 1 } hipbmg_precision;
 typedef struct {
     int nu1;                 /* pre-relaxations per level (Algorithm 1), default 2          */
     int nu2;                 /* post-relaxations per level, default 1                       */
-    int coarsest_n;          /* coarsen while both sides exceed this, default 3             */
+    int coarsest_n;          /* coarsen while both sides are odd and exceed this, default 3 */
     int collapse_level;      /* -1: chosen by the performance model; k >= 0: levels 0..k    */
                              /* run in one persistent workgroup (0 = coarsest solve only)   */
     int residual_correction; /* 1: add r/C at fine-only vertices after interpolation (sec 3) */

@@ -300,7 +300,11 @@ void *oracle_setup(int nx, int ny, int npt, const double *planes, int coarsest_n
     int sx[MAXLEV], sy[MAXLEV], L = 1;
     sx[0] = nx;
     sy[0] = ny;
-    while (sx[L - 1] > coarsest_n && sy[L - 1] > coarsest_n && L < MAXLEV) {
+    /* standard coarsening keeps the even-indexed vertices; a level with an even
+     * number of vertices on a side has its last (boundary) vertex at an odd
+     * index, so it cannot be coarsened again and becomes the coarsest level */
+    while (sx[L - 1] > coarsest_n && sy[L - 1] > coarsest_n && (sx[L - 1] & 1) && (sy[L - 1] & 1) &&
+           L < MAXLEV) {
         sx[L] = (sx[L - 1] + 1) / 2;
         sy[L] = (sy[L - 1] + 1) / 2;
         ++L;

@@ -271,7 +271,10 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     hipStream_t s = (hipStream_t)stream;
 
     std::vector<int> sx{nx}, sy{ny};
-    while (sx.back() > prm.coarsest_n && sy.back() > prm.coarsest_n && (int)sx.size() < HIPBMG_MAX_LEVELS) {
+    // every other vertex is kept; a side with an even number of vertices ends
+    // in a boundary vertex at an odd index and cannot be coarsened again
+    while (sx.back() > prm.coarsest_n && sy.back() > prm.coarsest_n && (sx.back() & 1) &&
+           (sy.back() & 1) && (int)sx.size() < HIPBMG_MAX_LEVELS) {
         sx.push_back((sx.back() + 1) / 2);
         sy.push_back((sy.back() + 1) / 2);
     }

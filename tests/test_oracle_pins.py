@@ -420,3 +420,21 @@ def test_grad_logD_matches_brute_force_matrix_derivative():
             dA = (H.matrix_from_planes(O.fv5(Dp)) - H.matrix_from_planes(O.fv5(D))).toarray() * D[cj, ci]
             ref = -H.to_interior(lam) @ dA @ H.to_interior(u)
             assert g[cj, ci] == pytest.approx(ref, rel=1e-12, abs=1e-14)
+
+
+def test_coarsening_stops_at_an_even_side():
+    # 97 -> 49 -> 25 -> 13 -> 7 -> 4: the 4-vertex side ends in a boundary
+    # vertex at an odd index, so that level is the coarsest
+    ny, nx = 97, 129
+    planes = O.fv5(inputs.cells_lognormal(nx, ny, 1.0, seed=9))
+    hier = O.Hierarchy(planes)
+    assert [hier.size(l) for l in range(hier.L)] == [(4, 5), (7, 9), (13, 17), (25, 33), (49, 65), (97, 129)]
+    b = inputs.load_uniform(nx, ny, seed=2)
+    u, hist = hier.solve(b, tol=1e-11)
+    A = H.matrix_from_planes(planes)
+    rel = np.linalg.norm(H.to_interior(b) - A @ H.to_interior(u)) / np.linalg.norm(H.to_interior(b))
+    assert rel <= 1e-11 * 1.01
+    Af = H.matrix_from_stencil(hier.stencil(1))
+    P = H.interp_matrix(hier.interp(1), hier.size(0))
+    Ac_ref = (P.T @ Af @ P).toarray()
+    assert np.abs(H.matrix_from_stencil(hier.stencil(0)).toarray() - Ac_ref).max() <= 1e-14 * np.abs(Ac_ref).max()
