@@ -873,8 +873,10 @@ extern "C" hipbmg_status hipbmg_profile(hipbmg_handle h, int enable)
         }
     h->prof_on = enable ? 1 : 0;
     h->prof_n = 0;
-    memset(h->prof_ms, 0, sizeof h->prof_ms);
-    memset(h->prof_cnt, 0, sizeof h->prof_cnt);
+    if (enable) {
+        memset(h->prof_ms, 0, sizeof h->prof_ms);
+        memset(h->prof_cnt, 0, sizeof h->prof_cnt);
+    }
     return HIPBMG_OK;
 }
 

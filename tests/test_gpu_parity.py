@@ -163,7 +163,9 @@ def test_setup_constant_D_closed_form_on_gpu():
         assert np.all(inner[:, :, 0, 1] == edge) and np.all(inner[:, :, 1, 2] == edge)
 
 
-SMOOTH_CASES = [(65, 65, 1, 0), (257, 257, 1, 1), (249, 131, 1, 2), (129, 129, 2, 3), (131, 251, 2, 4)]
+# ragged sizes m * 2^k + 1 (m odd) span several strips and row blocks with a
+# partial last strip, and still coarsen several times
+SMOOTH_CASES = [(65, 65, 1, 0), (257, 257, 1, 1), (225, 161, 1, 2), (129, 129, 2, 3), (161, 225, 2, 4)]
 
 
 @pytest.mark.parametrize("nx,ny,level_from_top,seed", SMOOTH_CASES)
@@ -186,7 +188,7 @@ def test_relaxation_matches_oracle(nx, ny, level_from_top, seed):
             assert err <= 1e-12, (l, sweeps, err)
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(65, 65, 0), (257, 129, 1), (129, 257, 2), (251, 249, 3)])
+@pytest.mark.parametrize("nx,ny,seed", [(65, 65, 0), (257, 129, 1), (129, 257, 2), (225, 193, 3)])
 def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed):
     planes = O.fv5(rand_cells(nx, ny, seed))
     ora = O.Hierarchy(planes)
@@ -216,7 +218,7 @@ def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed):
         assert eb <= 1e-11, (l, eb)
 
 
-@pytest.mark.parametrize("nx,ny,seed,rescorr", [(65, 65, 0, 1), (257, 129, 1, 1), (131, 251, 2, 0)])
+@pytest.mark.parametrize("nx,ny,seed,rescorr", [(65, 65, 0, 1), (257, 129, 1, 1), (161, 225, 2, 0)])
 def test_fused_interp_relax_matches_oracle(nx, ny, seed, rescorr):
     planes = O.fv5(rand_cells(nx, ny, seed))
     ora = O.Hierarchy(planes)
