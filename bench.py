@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles timed for the baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--collapse-level", type=int, default=-1)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip timing each forced collapse level against the model")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -94,6 +96,9 @@ def main():
     coeffs = HB.fv5_from_cells(D)
     torch.cuda.synchronize()
 
+    log("bench: calibrating the collapse-level model")
+    calib = HB.calibrate()
+    log("bench: calibration %s" % {k: round(v, 3) for k, v in calib.items()})
     log("bench: FP64 setup")
     hier = HB.Hierarchy(coeffs, collapse_level=args.collapse_level)
     _, info0 = hier.solve(b, tol=TOL)          # also a warm-up
@@ -116,6 +121,26 @@ def main():
         % (value, cycles, ms_per_step, kname, achieved))
 
     extra = {}
+    if not args.no_sweep:
+        # every forced collapse level l*: measured time per V-cycle next to the
+        # model's prediction (the one-GPU form of the paper's path comparison)
+        sweep = []
+        model = list(info.model_us)[: info.levels]
+        for ls in range(0, info.levels):
+            if model[ls] > 20 * min(model):
+                continue
+            hs = HB.Hierarchy(coeffs, collapse_level=ls, max_cycles=6)
+            hs.solve(b, tol=1e-30, check=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf_s = hs.solve(b, tol=1e-30, check=False)
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t0) / inf_s.cycles
+            sweep.append({"collapse_level": ls, "measured_us_per_cycle": 1e6 * per,
+                          "model_us_per_cycle": model[ls]})
+            del hs
+            log("bench: l*=%d measured %.1f us/cycle, model %.1f" % (ls, 1e6 * per, model[ls]))
+        extra["collapse_sweep"] = sweep
     if not args.no_mixed:
         log("bench: mixed precision on the same operator")
         hm = HB.Hierarchy(coeffs, precision=HB.MIXED, collapse_level=args.collapse_level)
@@ -188,6 +213,7 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
                      "avg_launch_us": kavg_s * 1e6},
         "kernels_fp64_finest": kernels,
+        "model_calibration": calib,
         "cpu_baseline": cpu,
     }
     out.update(extra)

@@ -188,6 +188,20 @@ hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,
                                   double *total_ms_host, long long *launches_host,
                                   double *bytes_per_launch_host);
 
+/* Measure the machine parameters of the collapse-level performance model on
+ * the current device with micro-kernels, as the paper measures its alpha,
+ * beta and gamma (section 3, postal model; section 5, machine parameters from
+ * benchmarks): the gap between dependent kernel launches, the latency of one
+ * row-pair step of a streaming wave, streaming bandwidth with the
+ * relaxation's access mix out of HBM and out of cache, the cost of a
+ * workgroup barrier after an L2 and after an LDS access, and one workgroup's
+ * bandwidth on L2-resident data.  The values replace the process-wide model
+ * parameters used by later hipbmg_setup calls.  out_host (may be NULL)
+ * receives 8 doubles: alpha_launch_us, step_us, hbm_GBps, cache_GBps,
+ * alpha_bar_us, wg_GBps, alpha_bar_lds_us, 0.  Allocates about 1 GB of
+ * device memory for the duration of the call. */
+hipbmg_status hipbmg_calibrate(void *stream, double *out_host);
+
 /* Message for the calling thread's most recent failure ("" if none). */
 const char *hipbmg_last_error(void);
 

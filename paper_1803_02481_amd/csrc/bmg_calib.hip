@@ -1,0 +1,211 @@
+// bmg_calib.hip -- micro-kernels that measure the machine parameters of the
+// collapse-level performance model.  The paper determines gamma by timing a
+// local stencil matrix-vector product and alpha, beta with standard network
+// benchmarks (section 3, postal model and its parameter table); on one GPU the
+// corresponding quantities are measured here:
+//   alpha_launch  gap between two dependent kernels on one stream
+//   step_us       one row-pair step of a streaming relaxation wave
+//   hbm / cache   streaming bandwidth with the relaxation's access mix (five
+//                 arrays read, one written), out of HBM and out of cache
+//   alpha_bar     one workgroup barrier after a dependent L2 access (collapsed
+//                 levels in global memory) or LDS access (levels staged in LDS)
+//   wg            bandwidth one workgroup reaches on L2-resident data
+#include "hipbmg.h"
+#include "bmg_internal.h"
+#include "bmg_model.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace hbmg {
+
+__global__ void k_empty(int) {}
+
+// read five arrays, write one: the access mix of a relaxation sweep
+__global__ __launch_bounds__(256) void k_stream_mix(const double2 *__restrict__ a,
+                                                    const double2 *__restrict__ b,
+                                                    const double2 *__restrict__ c,
+                                                    const double2 *__restrict__ d,
+                                                    const double2 *__restrict__ e,
+                                                    double2 *__restrict__ o, long long n2)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long long)gridDim.x * 256) {
+        double2 va = a[i], vb = b[i], vc = c[i], vd = d[i], ve = e[i];
+        double2 r;
+        r.x = va.x + vb.x * vc.x + vd.x * ve.x;
+        r.y = va.y + vb.y * vc.y + vd.y * ve.y;
+        o[i] = r;
+    }
+}
+
+// one workgroup: `iters` rounds of a dependent access + barrier
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_barrier(double *__restrict__ g, int iters, double *out)
+{
+    __shared__ double sh[1024];
+    double *buf = LDS ? sh : g;
+    const int t = threadIdx.x;
+    buf[t] = (double)t;
+    __syncthreads();
+    double acc = 0.0;
+    for (int k = 0; k < iters; ++k) {
+        const double v = buf[(t + 1 + k) & 1023];
+        __syncthreads();
+        buf[t] = v + 1.0;
+        acc += v;
+        __syncthreads();
+    }
+    if (t == 0) out[0] = acc;
+}
+
+// one workgroup streaming an L2-resident buffer (read + write)
+__global__ __launch_bounds__(1024) void k_wg_stream(double2 *__restrict__ g, long long n2, int reps)
+{
+    for (int r = 0; r < reps; ++r)
+        for (long long i = threadIdx.x; i < n2; i += 1024) {
+            double2 v = g[i];
+            v.x += 1.0;
+            v.y -= 1.0;
+            g[i] = v;
+        }
+}
+
+template <typename F>
+static float time_ms(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, F &&launch)
+{
+    launch();   // warm-up
+    float best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(e0, s);
+        launch();
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, ms);
+    }
+    return best;
+}
+
+}  // namespace hbmg
+
+using namespace hbmg;
+
+extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
+{
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HIPBMG_EHIP;
+    ModelParams p = model_params();
+    hipbmg_status st = HIPBMG_OK;
+    const long long nbig = 1LL << 24;      // doubles per array: 134 MB, far beyond the caches
+    const long long nsmall = 1LL << 19;    // 4 MB per array: cache resident
+    double *buf = nullptr, *small = nullptr;
+    const size_t bytes = 6 * nbig * sizeof(double);
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return HIPBMG_ENOMEM;
+    }
+    if (hipMalloc(&small, 4 * 1024 * 1024) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(buf);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return HIPBMG_ENOMEM;
+    }
+    hipMemsetAsync(buf, 0, bytes, s);
+    hipMemsetAsync(small, 0, 4 * 1024 * 1024, s);
+    {
+        // dependent launch gap
+        const int n = 200;
+        float ms = time_ms(s, e0, e1, 3, [&] {
+            for (int k = 0; k < n; ++k) hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, k);
+        });
+        p.alpha_launch_us = 1e3 * ms / n;
+
+        // streaming bandwidth, relaxation access mix
+        auto mix = [&](long long n2, int grid) {
+            const double2 *a = reinterpret_cast<const double2 *>(buf);
+            const long long nd2 = nbig / 2;
+            hipLaunchKernelGGL(k_stream_mix, dim3(grid), dim3(256), 0, s, a, a + nd2, a + 2 * nd2,
+                               a + 3 * nd2, a + 4 * nd2, reinterpret_cast<double2 *>(buf) + 5 * nd2, n2);
+        };
+        ms = time_ms(s, e0, e1, 5, [&] { mix(nbig / 2, 8192); });
+        const double hbm_gbps = 6.0 * nbig * 8.0 / (ms * 1e-3) / 1e9;
+        ms = time_ms(s, e0, e1, 5, [&] { mix(nsmall / 2, 1024); });
+        const double cache_gbps = 6.0 * nsmall * 8.0 / (ms * 1e-3) / 1e9;
+        p.beta_hbm_us_per_B = 1.0 / (hbm_gbps * 1e3);
+        p.beta_cache_us_per_B = 1.0 / (cache_gbps * 1e3);
+
+        // one row-pair step of a streaming wave: one wave, 64 steps
+        {
+            const int nx = 121, ny = 2 * 64 + 1, pitch = 128;
+            const size_t plane = (size_t)ny * pitch;
+            double *lv = nullptr;
+            if (hipMalloc(&lv, 9 * plane * sizeof(double)) == hipSuccess) {
+                hipMemsetAsync(lv, 0, 9 * plane * sizeof(double), s);
+                StreamArgs<double> a{};
+                a.nx = nx;
+                a.ny = ny;
+                a.pitch = pitch;
+                a.C = lv;
+                a.W = lv + plane;
+                a.S = lv + 2 * plane;
+                a.SW = lv + 3 * plane;
+                a.SE = lv + 4 * plane;
+                a.b = lv + 7 * plane;
+                a.x_in = lv + 5 * plane;
+                a.x_out = lv + 6 * plane;
+                a.rb = 64;
+                int g;
+                stream_geometry(nx, ny, 5, SV_SWEEP, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+                ms = time_ms(s, e0, e1, 5, [&] { launch_stream<double>(5, SV_SWEEP, a, g, s); });
+                p.step_us = std::max(0.05, (1e3 * ms - p.alpha_launch_us) / (a.rb + 1));
+                hipStreamSynchronize(s);
+                hipFree(lv);
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+
+        // barriers in one workgroup
+        const int iters = 2000;
+        double *out = small + 1024 * 64;
+        ms = time_ms(s, e0, e1, 3, [&] {
+            hipLaunchKernelGGL((k_barrier<false>), dim3(1), dim3(1024), 0, s, small, iters, out);
+        });
+        p.alpha_bar_us = 1e3 * ms / (2.0 * iters);
+        ms = time_ms(s, e0, e1, 3, [&] {
+            hipLaunchKernelGGL((k_barrier<true>), dim3(1), dim3(1024), 0, s, small, iters, out);
+        });
+        p.alpha_bar_lds_us = 1e3 * ms / (2.0 * iters);
+
+        // one workgroup on L2-resident data
+        const long long n2 = (1LL << 18) / 2;   // 2 MB
+        ms = time_ms(s, e0, e1, 3, [&] {
+            hipLaunchKernelGGL(k_wg_stream, dim3(1), dim3(1024), 0, s, reinterpret_cast<double2 *>(small), n2, 4);
+        });
+        const double wg_gbps = 4.0 * 2.0 * n2 * 16.0 / (ms * 1e-3) / 1e9;
+        p.beta_wg_us_per_B = 1.0 / (wg_gbps * 1e3);
+        p.calibrated = 1;
+        model_params() = p;
+        if (out_host) {
+            out_host[0] = p.alpha_launch_us;
+            out_host[1] = p.step_us;
+            out_host[2] = hbm_gbps;
+            out_host[3] = cache_gbps;
+            out_host[4] = p.alpha_bar_us;
+            out_host[5] = wg_gbps;
+            out_host[6] = p.alpha_bar_lds_us;
+            out_host[7] = 0.0;
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) st = HIPBMG_EHIP;
+    hipFree(buf);
+    hipFree(small);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return st;
+}

@@ -95,24 +95,26 @@ __device__ double residual(const LevelDev<T> &L, const T *__restrict__ x, T *__r
     return acc;
 }
 
-// b_c = P^T r on the interior coarse vertices
+// b_c = P^T r on the interior coarse vertices.  The weights use the fine
+// view's coarse pitch and the coarse arrays the coarse view's pitch (they
+// differ when only one of the two levels is staged in LDS).
 template <typename T>
 __device__ void restrict_pt(const LevelDev<T> &F, const T *__restrict__ r, const LevelDev<T> &Cl)
 {
     const int ni = Cl.nx - 2, n = ni * (Cl.ny - 2);
-    const size_t cp = F.cplane;
+    const size_t cp = F.cplane, WP = F.cpitch;
     const T *w = F.wt;
     for (int idx = threadIdx.x; idx < n; idx += CWG) {
         const int I = 1 + idx % ni, J = 1 + idx / ni;
-        const size_t c = (size_t)J * Cl.pitch + I;
         const size_t P = F.pitch;
         const size_t f = (size_t)(2 * J) * P + 2 * I;
-        const size_t cW = c - 1, cS = c - Cl.pitch, cSW = c - Cl.pitch - 1;
+        const size_t c = (size_t)J * WP + I;
+        const size_t cW = c - 1, cS = c - WP, cSW = c - WP - 1;
         T v = r[f] + w[WXL * cp + c] * r[f + 1] + w[WXR * cp + cW] * r[f - 1] +
               w[WYB * cp + c] * r[f + P] + w[WYT * cp + cS] * r[f - P] +
               w[WCSW * cp + c] * r[f + P + 1] + w[WCSE * cp + cW] * r[f + P - 1] +
               w[WCNW * cp + cS] * r[f - P + 1] + w[WCNE * cp + cSW] * r[f - P - 1];
-        Cl.b[c] = v;
+        Cl.b[(size_t)J * Cl.pitch + I] = v;
     }
 }
 
@@ -122,24 +124,24 @@ __device__ void interp_correct(const LevelDev<T> &F, T *__restrict__ x, const T 
                                const LevelDev<T> &Cl, const T *__restrict__ xc, int rescorr)
 {
     const int ni = F.nx - 2, n = ni * (F.ny - 2);
-    const size_t cp = F.cplane;
+    const size_t cp = F.cplane, WP = F.cpitch, CP = Cl.pitch;
     const T *w = F.wt;
     for (int idx = threadIdx.x; idx < n; idx += CWG) {
         const int i = 1 + idx % ni, j = 1 + idx / ni;
         const size_t p = (size_t)j * F.pitch + i;
-        const size_t c = (size_t)(j >> 1) * Cl.pitch + (i >> 1);
-        const size_t CP = Cl.pitch;
+        const size_t c = (size_t)(j >> 1) * CP + (i >> 1);
+        const size_t cw = (size_t)(j >> 1) * WP + (i >> 1);
         T v;
         if (!(i & 1) && !(j & 1)) {
             v = xc[c];
         } else {
             if ((i & 1) && !(j & 1))
-                v = w[WXL * cp + c] * xc[c] + w[WXR * cp + c] * xc[c + 1];
+                v = w[WXL * cp + cw] * xc[c] + w[WXR * cp + cw] * xc[c + 1];
             else if (!(i & 1) && (j & 1))
-                v = w[WYB * cp + c] * xc[c] + w[WYT * cp + c] * xc[c + CP];
+                v = w[WYB * cp + cw] * xc[c] + w[WYT * cp + cw] * xc[c + CP];
             else
-                v = w[WCSW * cp + c] * xc[c] + w[WCSE * cp + c] * xc[c + 1] +
-                    w[WCNW * cp + c] * xc[c + CP] + w[WCNE * cp + c] * xc[c + CP + 1];
+                v = w[WCSW * cp + cw] * xc[c] + w[WCSE * cp + cw] * xc[c + 1] +
+                    w[WCNW * cp + cw] * xc[c + CP] + w[WCNE * cp + cw] * xc[c + CP + 1];
             if (rescorr) v += r[p] / point_diag(F, p);
         }
         x[p] += v;
@@ -160,17 +162,94 @@ __device__ double block_sum(double v, double *sh)
     return s;
 }
 
+// Bytes of LDS a level occupies when staged: C, W, S, SW, SE, iterate,
+// residual and right-hand side at compact pitch, plus the 8 weight planes
+// from the coarser level.
+template <typename T>
+size_t collapse_lds_bytes(int nx, int ny, int cnx, int cny)
+{
+    size_t n = (size_t)nx * ny, cn = (size_t)cnx * cny;
+    size_t b = (8 * n + 8 * cn) * sizeof(T);
+    return (b + 15) / 16 * 16;
+}
+template size_t collapse_lds_bytes<double>(int, int, int, int);
+template size_t collapse_lds_bytes<float>(int, int, int, int);
+
 template <typename T>
 __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sh[CWG / 64];
-    const LevelDev<T> *lv = a.levels;
+    __shared__ LevelDev<T> V[COLLAPSE_MAX_LEVELS];
+    const int top = a.top;
+    // level views: levels 0..lds_top live in LDS at compact pitch
+    if (threadIdx.x == 0) {
+        for (int l = 0; l <= top; ++l) {
+            LevelDev<T> v = a.levels[l];
+            if (l <= a.lds_top) {
+                T *base = reinterpret_cast<T *>(smem + a.lds_off[l]);
+                const size_t n = (size_t)v.nx * v.ny;
+                v.pitch = v.nx;
+                v.plane = n;
+                v.C = base;
+                v.W = base + n;
+                v.S = base + 2 * n;
+                v.SW = base + 3 * n;
+                v.SE = base + 4 * n;
+                const int xb = l == top ? a.xb_top : 1;
+                v.x[xb] = base + 5 * n;
+                v.x[1 - xb] = base + 6 * n;
+                v.b = base + 7 * n;
+                v.q = nullptr;
+                if (l >= 1) {
+                    const LevelDev<T> &c = a.levels[l - 1];
+                    v.wt = base + 8 * n;
+                    v.cpitch = c.nx;
+                    v.cplane = (size_t)c.nx * c.ny;
+                }
+            }
+            V[l] = v;
+        }
+    }
+    __syncthreads();
+    // stage the LDS levels in: operator, weights; zero iterate and residual;
+    // the top level's right-hand side (and iterate) come from global memory
+    for (int l = 0; l <= a.lds_top; ++l) {
+        const LevelDev<T> &g = a.levels[l];
+        const LevelDev<T> &v = V[l];
+        const int nx = g.nx, n = g.nx * g.ny;
+        const int xb = l == top ? a.xb_top : 1;
+        for (int idx = threadIdx.x; idx < n; idx += CWG) {
+            const size_t gp = (size_t)(idx / nx) * g.pitch + idx % nx;
+            v.C[idx] = g.C[gp];
+            v.W[idx] = g.W[gp];
+            v.S[idx] = g.S[gp];
+            v.SW[idx] = g.SW[gp];
+            v.SE[idx] = g.SE[gp];
+            v.x[1 - xb][idx] = T(0);
+            if (l == top) {
+                v.b[idx] = g.b[gp];
+                v.x[xb][idx] = a.zero_top ? T(0) : g.x[xb][gp];
+            } else {
+                v.b[idx] = T(0);
+                v.x[xb][idx] = T(0);
+            }
+        }
+        if (l >= 1) {
+            const int cnx = a.levels[l - 1].nx, cn = cnx * a.levels[l - 1].ny;
+            for (int k = 0; k < 8; ++k)
+                for (int idx = threadIdx.x; idx < cn; idx += CWG)
+                    v.wt[k * cn + idx] = g.wt[k * g.cplane + (size_t)(idx / cnx) * g.cpitch + idx % cnx];
+        }
+    }
+    __syncthreads();
+
     // down: relax, residual, restrict
-    for (int l = a.top; l >= 1; --l) {
-        const LevelDev<T> L = lv[l];
-        const int xb = l == a.top ? a.xb_top : 1;
+    for (int l = top; l >= 1; --l) {
+        const LevelDev<T> &L = V[l];
+        const int xb = l == top ? a.xb_top : 1;
         T *x = L.x[xb], *r = L.x[1 - xb];
-        if (l < a.top || a.zero_top) {
+        if (l < top || a.zero_top) {
             zero_interior(L, x);
             __syncthreads();
         }
@@ -181,13 +260,13 @@ __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
             }
         residual(L, x, r);
         __syncthreads();
-        restrict_pt(L, r, lv[l - 1]);
+        restrict_pt(L, r, V[l - 1]);
         __syncthreads();
     }
     // coarsest: Cholesky solve in FP64 (column-oriented substitutions)
     {
-        const LevelDev<T> L0 = lv[0];
-        T *x0 = L0.x[a.top == 0 ? a.xb_top : 1];
+        const LevelDev<T> &L0 = V[0];
+        T *x0 = L0.x[top == 0 ? a.xb_top : 1];
         const int nc = a.nc;
         double *y = a.work;
         const int ni = L0.nx - 2, n = ni * (L0.ny - 2);
@@ -218,11 +297,11 @@ __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
         __syncthreads();
     }
     // up: interpolate and correct, relax
-    for (int l = 1; l <= a.top; ++l) {
-        const LevelDev<T> L = lv[l];
-        const int xb = l == a.top ? a.xb_top : 1;
+    for (int l = 1; l <= top; ++l) {
+        const LevelDev<T> &L = V[l];
+        const int xb = l == top ? a.xb_top : 1;
         T *x = L.x[xb], *r = L.x[1 - xb];
-        interp_correct(L, x, r, lv[l - 1], lv[l - 1].x[1], a.rescorr);
+        interp_correct(L, x, r, V[l - 1], V[l - 1].x[1], a.rescorr);
         __syncthreads();
         for (int s = 0; s < a.nu2; ++s)
             for (int k = 0; k < 4; ++k) {
@@ -230,18 +309,35 @@ __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
                 __syncthreads();
             }
     }
+    const LevelDev<T> &Lt = V[top];
     if (a.want_norm) {
-        const LevelDev<T> L = lv[a.top];
-        double v = residual(L, L.x[a.xb_top], L.x[1 - a.xb_top]);
+        double v = residual(Lt, Lt.x[a.xb_top], Lt.x[1 - a.xb_top]);
         v = block_sum(v, sh);
         if (threadIdx.x == 0) a.partials[0] = v;
+    }
+    // the top level's iterate goes back to global memory when it was staged
+    if (top <= a.lds_top) {
+        const LevelDev<T> &g = a.levels[top];
+        const int ni = g.nx - 2, n = ni * (g.ny - 2);
+        for (int idx = threadIdx.x; idx < n; idx += CWG) {
+            const int i = 1 + idx % ni, j = 1 + idx / ni;
+            g.x[a.xb_top][(size_t)j * g.pitch + i] = Lt.x[a.xb_top][(size_t)j * Lt.pitch + i];
+        }
     }
 }
 
 template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_collapse<T>), dim3(1), dim3(CWG), 0, s, a);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_collapse<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           COLLAPSE_LDS_BUDGET);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_collapse<T>), dim3(1), dim3(CWG), a.lds_bytes, s, a);
     return hipGetLastError();
 }
 template hipError_t launch_collapse<double>(const CollapseArgs<double> &, hipStream_t);

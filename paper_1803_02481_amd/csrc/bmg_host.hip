@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -86,6 +87,7 @@ struct hipbmg_hier {
     double model_us[HIPBMG_MAX_LEVELS] = {};
     double setup_ms = 0.0;
     std::vector<int> rb;        // row-block steps per level for the streaming kernels
+    int no_lds = 0;             // HIPBMG_NO_LDS=1: keep collapsed levels in global memory
     // live timing of the finest-level streaming kernels (HIP events on the solve stream)
     int prof_on = 0;
     int prof_n = 0;                       // event pairs recorded in the current cycle
@@ -231,6 +233,10 @@ static hipbmg_status factor_coarsest(hipbmg_hier *h, hipStream_t s)
 // prologue, short blocks give small levels enough waves
 static int pick_rb(int nx, int ny, int npt)
 {
+    if (const char *e = std::getenv("HIPBMG_RB")) {   // fixed row-block length (tuning)
+        int v = std::atoi(e);
+        if (v >= 1 && v <= 4096) return v;
+    }
     int nst, nbl, nt, g;
     for (int rb : {32, 16, 8, 4}) {
         stream_geometry(nx, ny, npt, SV_SWEEP_RQ, rb, &nst, &nbl, &nt, &g);
@@ -287,6 +293,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         return fail(HIPBMG_EINVAL, "coarsest level %d x %d too large for the dense solve", sx[0], sy[0]);
 
     hipbmg_hier *h = new hipbmg_hier();
+    if (const char *e = std::getenv("HIPBMG_NO_LDS")) h->no_lds = std::atoi(e);
     h->L = L;
     h->nx = nx;
     h->ny = ny;
@@ -369,7 +376,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         ml[l].npt = h->lv[l].npt;
         ml[l].rb = h->rb[l];
     }
-    const ModelParams &mp = model_params();
+    ModelParams mp = model_params();
+    mp.lds_budget_bytes = (double)(h->no_lds ? 0 : COLLAPSE_LDS_BUDGET);
     int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc,
                             prm.precision == HIPBMG_MIXED ? 4 : 8, mp, h->model_us);
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
@@ -490,6 +498,18 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         c.work = h->d_work;
         c.partials = h->d_partials;
         c.want_norm = fine ? 1 : 0;
+        // stage as many of the collapsed levels (from the coarsest up) as fit in LDS
+        c.lds_top = -1;
+        size_t off = 0;
+        for (int l = 0; l <= ls; ++l) {
+            const size_t bytes = collapse_lds_bytes<T>(lv[l].nx, lv[l].ny, l ? lv[l - 1].nx : 0,
+                                                       l ? lv[l - 1].ny : 0);
+            if (off + bytes > (size_t)COLLAPSE_LDS_BUDGET || h->no_lds) break;
+            c.lds_off[l] = (int)off;
+            off += bytes;
+            c.lds_top = l;
+        }
+        c.lds_bytes = (int)off;
         if ((e = launch_collapse<T>(c, s)) != hipSuccess) return e;
         xres[ls] = c.xb_top;
         if (fine) {

@@ -82,6 +82,9 @@ hipError_t launch_rap(const LevelDev<double> &f, const LevelDev<double> &c, hipS
 // Collapsed coarse levels: one persistent workgroup runs levels top..0 of the
 // V-cycle.  The iterate of a collapsed level below `top` is x[1] and x[0] holds
 // its residual; at `top` the iterate is x[xb_top] and the residual x[1 - xb_top].
+// Levels 0..lds_top are staged in LDS for the whole launch.
+constexpr int COLLAPSE_MAX_LEVELS = 24;
+constexpr int COLLAPSE_LDS_BUDGET = 150 * 1024;   // dynamic LDS bytes for staged levels
 template <typename T>
 struct CollapseArgs {
     const LevelDev<T> *levels;   // device array, index = level
@@ -93,9 +96,14 @@ struct CollapseArgs {
     double *work;                // nc doubles
     double *partials;            // want_norm: partials[0] = ||b - A x||^2 at level top
     int want_norm;
+    int lds_top;                 // highest level staged in LDS (-1: none)
+    int lds_bytes;               // dynamic LDS of the launch
+    int lds_off[COLLAPSE_MAX_LEVELS];   // byte offset of each staged level
 };
 template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s);
+template <typename T>
+size_t collapse_lds_bytes(int nx, int ny, int cnx, int cny);
 
 // Sum of squares of interior entries of a pitched field -> partials.
 hipError_t launch_sumsq(const double *v, int nx, int ny, int pitch, double *partials, int nparts,

@@ -29,8 +29,11 @@ ModelParams &model_params()
         d.beta_cache_us_per_B = 1.0 / 10.0e6;  // 10 TB/s from cache-resident levels
         d.cache_bytes = 256.0e6;
         d.alpha_bar_us = 1.0;
+        d.alpha_bar_lds_us = 0.1;
         d.beta_wg_us_per_B = 1.0 / 1.0e5;      // 100 GB/s for one workgroup
         d.gamma_wg_us_per_flop = 1.0e-3;
+        d.lds_budget_bytes = 150.0 * 1024.0;
+        d.calibrated = 0;
         if (const char *env = std::getenv("HIPBMG_MODEL_PARAMS")) {
             double a, st, hb, cb, ab, wb;
             if (std::sscanf(env, "%lf,%lf,%lf,%lf,%lf,%lf", &a, &st, &hb, &cb, &ab, &wb) == 6) {
@@ -80,12 +83,16 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
     return t;
 }
 
-double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, const ModelParams &p)
+double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, bool in_lds,
+                         const ModelParams &p)
 {
     const double n = (double)lv.nx * lv.ny, s = 5.0, w = word;
     // barriers: zeroing, 4 colours per relaxation, residual, restriction, interpolation
     const double phases = 1.0 + 4.0 * (nu1 + nu2) + 3.0;
     const double bytes = n * w * ((nu1 + nu2) * (s + 3.0) + (s + 3.0) + 3.25 + 6.25);
+    if (in_lds)   // staged once per launch from global memory, then LDS speed
+        return phases * p.alpha_bar_lds_us + n * w * 10.0 * p.beta_wg_us_per_B +
+               0.25 * bytes * p.beta_wg_us_per_B;
     return phases * p.alpha_bar_us + bytes * p.beta_wg_us_per_B;
 }
 
@@ -93,13 +100,22 @@ int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word
                  const ModelParams &p, double *t_us)
 {
     // coarse solve: two triangular substitutions, 2 barriers per unknown
-    const double t_cg = (nc > 1 ? 4.0 * nc * p.alpha_bar_us : p.alpha_bar_us) +
+    const double t_cg = (nc > 1 ? 4.0 * nc * p.alpha_bar_lds_us : p.alpha_bar_lds_us) +
                         2.0 * (double)nc * nc * p.gamma_wg_us_per_flop;
+    // levels staged in LDS: from the coarsest up while their footprint fits
+    bool in_lds[64] = {};
+    double used = 0.0;
+    for (int l = 0; l < L && l < 64; ++l) {
+        const double cn = l ? (double)lv[l - 1].nx * lv[l - 1].ny : 0.0;
+        used += (8.0 * lv[l].nx * lv[l].ny + 8.0 * cn) * word;
+        if (used > p.lds_budget_bytes) break;
+        in_lds[l] = true;
+    }
     int best = 0;
     for (int ls = 0; ls < L; ++ls) {
         double t = p.alpha_launch_us + t_cg;                   // the collapsed launch
         for (int l = ls + 1; l < L; ++l) t += model_grid_level_us(lv[l], l == L - 1, nu1, nu2, word, p);
-        for (int l = 1; l <= ls; ++l) t += model_wg_level_us(lv[l], nu1, nu2, word, p);
+        for (int l = 1; l <= ls; ++l) t += model_wg_level_us(lv[l], nu1, nu2, word, in_lds[l], p);
         t += p.alpha_launch_us;                                // norm finalisation
         t_us[ls] = t;
         if (t < t_us[best]) best = ls;

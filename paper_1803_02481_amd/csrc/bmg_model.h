@@ -24,9 +24,12 @@ struct ModelParams {
     double beta_hbm_us_per_B;
     double beta_cache_us_per_B;
     double cache_bytes;
-    double alpha_bar_us;
+    double alpha_bar_us;        // barrier after a dependent L2 access (level in global memory)
+    double alpha_bar_lds_us;    // barrier after a dependent LDS access (level staged in LDS)
     double beta_wg_us_per_B;
     double gamma_wg_us_per_flop;
+    double lds_budget_bytes;    // LDS available for staged collapsed levels
+    int calibrated;             // 1 once measured on the device
 };
 
 // process-wide parameters (defaults, replaced by calibrate or the
@@ -42,6 +45,7 @@ int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word
 // the two parts of the model for one level (exposed for reporting)
 double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, int word,
                            const ModelParams &p);
-double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, const ModelParams &p);
+double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, bool in_lds,
+                         const ModelParams &p);
 
 }  // namespace hbmg

@@ -59,9 +59,12 @@ __device__ __forceinline__ void st2(T *__restrict__ p, T a, T b)
 template <typename T> __device__ __forceinline__ T fromL(T v) { return __shfl_up(v, 1, 64); }
 template <typename T> __device__ __forceinline__ T fromR(T v) { return __shfl_down(v, 1, 64); }
 
+// One row of the lane's column pair.  The c*/w*/q* fields hold the raw inputs
+// of the interpolate-and-correct step until the row is finished.
 template <typename T>
 struct Row {
     T x0, x1, b0, b1, C0, C1, W0, W1, S0, S1, SW0, SW1, SE0, SE1;
+    T ca, cu, w0, w1, w2, w3, w4, w5, q0, q1;
 };
 
 // Residual b - (A x) at the even column of row `cu` (rows `bl` below and `ab`
@@ -129,6 +132,11 @@ __device__ __forceinline__ T res_odd(const Row<T> &bl, const Row<T> &cu, const R
     }
 }
 
+// Issuing the next row pair's loads before computing the current one was
+// measured slower on gfx950 (more registers, no gain in achieved bandwidth),
+// so rows are loaded at the start of their step.
+constexpr bool kPrefetch = false;
+
 template <int V> struct VariantFlags;
 template <> struct VariantFlags<SV_SWEEP>       { enum { ZX = 0, INTERP = 0, RES = 0, RQ = 0, NORM = 0 }; };
 template <> struct VariantFlags<SV_SWEEP_ZX>    { enum { ZX = 1, INTERP = 0, RES = 0, RQ = 0, NORM = 0 }; };
@@ -165,10 +173,11 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     const bool io = o >= 1 && o <= nx - 2;
     const bool cv = F::INTERP || F::RQ ? (t >= 0 && t < a.cnx) : false;   // coarse column t
 
-    auto load_row = [&](Row<T> &r, int j) {
-        bool rv = colv && j >= 0 && j < ny;
-        r.x0 = r.x1 = r.b0 = r.b1 = r.C0 = r.C1 = r.W0 = r.W1 = r.S0 = r.S1 = T(0);
-        r.SW0 = r.SW1 = r.SE0 = r.SE1 = T(0);
+    // issue the loads of row j (no use of the loaded values: they stay in
+    // flight while the previous rows are being computed)
+    auto load_raw = [&](Row<T> &r, int j) {
+        const bool rv = colv && j >= 0 && j < ny;
+        r = Row<T>{};
         if (rv) {
             const size_t off = (size_t)j * pitch + e;
             if (!F::ZX) ld2(a.x_in + off, r.x0, r.x1);
@@ -182,41 +191,41 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
             }
         }
         if (F::INTERP) {
-            // x += P x_c (+ r/C at fine-only vertices); coarse column t
             const bool rin = j >= 1 && j <= ny - 2;
-            const int jc = j >> 1;
-            const T *wt = a.wt;
-            const long long cp = a.cplane;
+            if (cv && rin) {
+                const int jc = j >> 1;
+                const size_t co = (size_t)jc * a.cpitch + t;
+                const T *wt = a.wt;
+                const long long cp = a.cplane;
+                r.ca = a.xc[co];
+                if (j & 1) {
+                    r.cu = a.xc[co + a.cpitch];
+                    r.w0 = wt[WYB * cp + co];
+                    r.w1 = wt[WYT * cp + co];
+                    r.w2 = wt[WCSW * cp + co];
+                    r.w3 = wt[WCSE * cp + co];
+                    r.w4 = wt[WCNW * cp + co];
+                    r.w5 = wt[WCNE * cp + co];
+                } else {
+                    r.w0 = wt[WXL * cp + co];
+                    r.w1 = wt[WXR * cp + co];
+                }
+                if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, r.q0, r.q1);
+            }
+        }
+    };
+    // x += P x_c (+ r/C at fine-only vertices) on a loaded row; coarse column t
+    auto finish_row = [&](Row<T> &r, int j) {
+        if (F::INTERP) {
+            const bool rin = j >= 1 && j <= ny - 2;
             if ((j & 1) == 0) {
-                T xa = T(0), wl = T(0), wr = T(0), qo = T(0), qe = T(0);
-                if (cv && rin) {
-                    const size_t co = (size_t)jc * a.cpitch + t;
-                    xa = a.xc[co];
-                    wl = wt[WXL * cp + co];
-                    wr = wt[WXR * cp + co];
-                    if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, qe, qo);
-                }
-                T xb = fromR(xa);
-                if (rin && ie) r.x0 += xa;
-                if (rin && io) r.x1 += wl * xa + wr * xb + qo;
+                const T xb = fromR(r.ca);
+                if (rin && ie) r.x0 += r.ca;
+                if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + r.q1;
             } else {
-                T xa = T(0), xcu = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0), cnw = T(0),
-                  cne = T(0), qe = T(0), qo = T(0);
-                if (cv && rin) {
-                    const size_t co = (size_t)jc * a.cpitch + t;
-                    xa = a.xc[co];
-                    xcu = a.xc[co + a.cpitch];
-                    yb = wt[WYB * cp + co];
-                    yt = wt[WYT * cp + co];
-                    csw = wt[WCSW * cp + co];
-                    cse = wt[WCSE * cp + co];
-                    cnw = wt[WCNW * cp + co];
-                    cne = wt[WCNE * cp + co];
-                    if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, qe, qo);
-                }
-                T xb = fromR(xa), xd = fromR(xcu);
-                if (rin && ie) r.x0 += yb * xa + yt * xcu + qe;
-                if (rin && io) r.x1 += csw * xa + cse * xb + cnw * xcu + cne * xd + qo;
+                const T xb = fromR(r.ca), xd = fromR(r.cu);
+                if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + r.q0;
+                if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + r.q1;
             }
         }
     };
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
     constexpr int PRO = F::RES ? 2 : 1;         // prologue steps
 
-    Row<T> rm3, rm2, rm1, r0, rp1;
+    Row<T> rm3, rm2, rm1, r0, rp1, n0, n1;
     T rr3e = T(0), rr3o = T(0);                 // residual of row j-3
     T ytp = T(0), cnwp = T(0), cnep = T(0);     // weights of coarse row (j-2)/2 - 1
     double acc = 0.0;
@@ -236,13 +245,31 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     // step (colours 0 and 1); rows j-2, j-3 are rotated in before any use
     rm3 = Row<T>{};
     rm2 = Row<T>{};
-    load_row(rm1, jfirst - 2 * PRO - 1);
+    const int jstart = jfirst - 2 * PRO;
+    load_raw(rm1, jstart - 1);
+    finish_row(rm1, jstart - 1);
+    if (kPrefetch) {
+        load_raw(n0, jstart);
+        load_raw(n1, jstart + 1);
+    }
 
-    for (int step = -PRO; step <= s1 - 1 - s0; ++step) {
+    const int last = s1 - 1 - s0;
+    for (int step = -PRO; step <= last; ++step) {
         const int j = jfirst + 2 * step;
         const int mode = step < 0 ? (step == -PRO ? 0 : 1) : 2;   // 0 partial, 1 full, 2 write
-        load_row(r0, j);
-        load_row(rp1, j + 1);
+        if (kPrefetch) {
+            r0 = n0;
+            rp1 = n1;
+            if (step < last) {      // prefetch the next row pair
+                load_raw(n0, j + 2);
+                load_raw(n1, j + 3);
+            }
+        } else {
+            load_raw(r0, j);
+            load_raw(rp1, j + 1);
+        }
+        finish_row(r0, j);
+        finish_row(rp1, j + 1);
         const bool rj = j >= 1 && j <= ny - 2;
         const bool rjm = j - 1 >= 1 && j - 1 <= ny - 2;
         // colours 0 and 1 on row j

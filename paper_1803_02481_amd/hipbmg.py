@@ -63,6 +63,7 @@ _SIGS = {
     "hipbmg_profile": (_I, [_VP, _I]),
     "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_calibrate": (_I, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -206,6 +207,16 @@ class Hierarchy:
         _check(lib().hipbmg_op_interp_smooth(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(xc), rescorr,
                                              ctypes.byref(ss) if want_norm else None, _stream()))
         return (x, ss.value) if want_norm else x
+
+
+def calibrate():
+    """Measure the performance-model parameters on the current device; later
+    hierarchies choose their collapse level with them."""
+    out = (ctypes.c_double * 8)()
+    _check(lib().hipbmg_calibrate(_stream(), out))
+    keys = ("alpha_launch_us", "step_us", "hbm_GBps", "cache_GBps", "alpha_bar_us", "wg_GBps",
+            "alpha_bar_lds_us")
+    return {k: out[i] for i, k in enumerate(keys)}
 
 
 def fv5_from_cells(cell, is_log=False):
