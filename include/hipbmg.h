@@ -144,7 +144,8 @@ hipbmg_status hipbmg_get_interp(hipbmg_handle h, int l, double *out, void *strea
  * affected):
  *   op_smooth: `sweeps` four-colour Gauss-Seidel relaxations of A_l x = b,
  *     x updated in place (section 2).
- *   op_smooth_restrict (l >= 1): one relaxation, then the residual r = b - A_l x,
+ *   op_smooth_restrict (l >= 1): `sweeps` (1 or 2, the latter as one fused pass)
+ *     relaxations, then the residual r = b - A_l x,
  *     q = r / C at vertices that are not coarse points (q = 0 elsewhere), and
  *     bc = P_l^T r ([cny][cnx]) (Algorithm 1, residual and restriction).
  *   op_interp_smooth (l >= 1): x += P_l xc (plus q at vertices that are not
@@ -154,7 +155,7 @@ hipbmg_status hipbmg_get_interp(hipbmg_handle h, int l, double *out, void *strea
 hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *b, double *x, int sweeps,
                                void *stream);
 hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
-                                        double *q, double *bc, void *stream);
+                                        int sweeps, double *q, double *bc, void *stream);
 hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
                                       const double *q, const double *xc, int rescorr,
                                       double *sumsq_host, void *stream);
@@ -181,7 +182,8 @@ hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double
  * them.  profile_read returns, for one precision (0 FP64, 1 FP32 inner) and
  * one kernel index (0 relax, 1 relax from zero, 2 relax + residual +
  * restriction, 3 the same from zero, 4 interpolate + relax, 5 the same + norm,
- * 6 relax + norm), the summed duration, the number of launches and the
+ * 6 relax + norm, 7 two relaxations + residual + restriction in one pass,
+ * 8 the same from zero), the summed duration, the number of launches and the
  * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
 hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);
 hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,

@@ -88,6 +88,7 @@ struct hipbmg_hier {
     double setup_ms = 0.0;
     std::vector<int> rb;        // row-block steps per level for the streaming kernels
     int no_lds = 0;             // HIPBMG_NO_LDS=1: keep collapsed levels in global memory
+    int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
     // live timing of the finest-level streaming kernels (HIP events on the solve stream)
     int prof_on = 0;
     int prof_n = 0;                       // event pairs recorded in the current cycle
@@ -238,7 +239,7 @@ static int pick_rb(int nx, int ny, int npt)
         if (v >= 1 && v <= 4096) return v;
     }
     int nst, nbl, nt, g;
-    for (int rb : {32, 16, 8, 4}) {
+    for (int rb : {64, 32, 16, 8, 4}) {
         stream_geometry(nx, ny, npt, SV_SWEEP_RQ, rb, &nst, &nbl, &nt, &g);
         if (nt >= 1024) return rb;
     }
@@ -294,6 +295,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
 
     hipbmg_hier *h = new hipbmg_hier();
     if (const char *e = std::getenv("HIPBMG_NO_LDS")) h->no_lds = std::atoi(e);
+    if (const char *e = std::getenv("HIPBMG_NO_FUSE2")) h->no_fuse2 = std::atoi(e);
     h->L = L;
     h->nx = nx;
     h->ny = ny;
@@ -353,6 +355,11 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     size_t np = 4096;
     for (int l = 0; l < L; ++l) {
         h->rb[l] = pick_rb(sx[l], sy[l], h->lv[l].npt);
+        if (l == L - 1)
+            if (const char *e = std::getenv("HIPBMG_RB_FINEST")) {   // tuning override
+                const int v = std::atoi(e);
+                if (v >= 1 && v <= 4096) h->rb[l] = v;
+            }
         int nst, nbl, nt, g;
         stream_geometry(sx[l], sy[l], h->lv[l].npt, SV_INTERP_NORM, h->rb[l], &nst, &nbl, &nt, &g);
         np = std::max(np, (size_t)nt);
@@ -454,9 +461,14 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         const bool fine = l == L - 1;
         int xb = fine ? cur : 0;
         const bool zero = !fine || zero_start;
-        for (int k = 1; k <= nu1; ++k) {
-            const bool last = k == nu1, zx = zero && k == 1;
-            const int v = last ? (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ) : (zx ? SV_SWEEP_ZX : SV_SWEEP);
+        // the last two pre-relaxations run as one fused pass unless disabled
+        const int nk = (nu1 >= 2 && !h->no_fuse2) ? nu1 - 1 : nu1;
+        for (int k = 1; k <= nk; ++k) {
+            const bool last = k == nk, zx = zero && k == 1;
+            const bool two = last && nk < nu1;
+            const int v = last ? (two ? (zx ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ)
+                                      : (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ))
+                               : (zx ? SV_SWEEP_ZX : SV_SWEEP);
             StreamArgs<T> a = base_args(A, h->rb[l]);
             a.x_in = A.x[xb];
             a.x_out = A.x[1 - xb];
@@ -793,10 +805,11 @@ extern "C" hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *
 }
 
 extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
-                                                   double *q, double *bc, void *stream)
+                                                   int sweeps, double *q, double *bc, void *stream)
 {
     if (!h || !b || !x || !q || !bc) return fail(HIPBMG_EINVAL, "null argument");
     if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
+    if (sweeps != 1 && sweeps != 2) return fail(HIPBMG_EINVAL, "sweeps must be 1 or 2");
     hipStream_t s = (hipStream_t)stream;
     const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
     STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
@@ -813,7 +826,7 @@ extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const
     a.cny = C.ny;
     a.cpitch = C.pitch;
     a.cplane = (long long)C.plane;
-    HIPCHK(run_stream(A, SV_SWEEP_RQ, a, s));
+    HIPCHK(run_stream(A, sweeps == 2 ? SV_SWEEP2_RQ : SV_SWEEP_RQ, a, s));
     STCHK(from_pitched(x, A.x[1], A.pitch, A.nx, A.ny, s));
     STCHK(from_pitched(q, A.q, A.pitch, A.nx, A.ny, s));
     STCHK(from_pitched(bc, C.b, C.pitch, C.nx, C.ny, s));
@@ -918,7 +931,10 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         const double s = F.npt == 5 ? 3.0 : 5.0;
         double per = (s + 3.0) * w;
         if (variant == SV_SWEEP_ZX || variant == SV_SWEEP_RQ_ZX) per -= w;
-        if (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX) per += w + 2.0 * w + 0.25 * w;
+        if (variant == SV_SWEEP2_RQ_ZX) per -= w;
+        if (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_SWEEP2_RQ ||
+            variant == SV_SWEEP2_RQ_ZX)
+            per += w + 2.0 * w + 0.25 * w;
         if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
         *bytes_per_launch_host = per * n;
     }

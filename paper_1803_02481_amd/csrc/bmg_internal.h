@@ -59,7 +59,9 @@ enum StreamVariant {
     SV_INTERP = 4,       // interpolate-and-correct on load, then relaxation
     SV_INTERP_NORM = 5,  // ... plus residual norm partials
     SV_SWEEP_NORM = 6,   // relaxation plus residual norm partials
-    SV_COUNT = 7
+    SV_SWEEP2_RQ = 7,    // two relaxations, residual -> q, restriction -> bc
+    SV_SWEEP2_RQ_ZX = 8, // the same from x = 0
+    SV_COUNT = 9
 };
 
 // Owned column pairs per strip for a variant (64 lanes minus halo lanes).

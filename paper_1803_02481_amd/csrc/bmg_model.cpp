@@ -61,14 +61,16 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
     const double beta = level_bytes < p.cache_bytes ? p.beta_cache_us_per_B : p.beta_hbm_us_per_B;
     const int nsteps = (lv.ny - 1) / 2;
     double t = 0.0;
-    // down: nu1 relaxations, the last fused with residual, r/C and restriction
-    for (int k = 1; k <= nu1; ++k) {
+    // down: nu1 relaxations; the last two run as one pass fused with residual,
+    // r/C and restriction (the last one alone if nu1 = 1)
+    const int nk = nu1 >= 2 ? nu1 - 1 : nu1;
+    for (int k = 1; k <= nk; ++k) {
         double bytes = n * w * (s + 3.0);
         if (k == 1 && !finest) bytes -= n * w;               // iterate starts at zero
         int pro = 1;
-        if (k == nu1) {
+        if (k == nk) {
             bytes += n * w * (1.0 + 2.0 + 0.25);             // q, weights, coarse rhs
-            pro = 2;
+            pro = nk < nu1 ? 5 : 2;
         }
         const double steps = std::min(lv.rb, nsteps) + pro;
         t += p.alpha_launch_us + std::max(steps * p.step_us, bytes * beta);

@@ -149,6 +149,114 @@ template <> struct VariantFlags<SV_SWEEP_NORM>  { enum { ZX = 0, INTERP = 0, RES
 __host__ __device__ constexpr int halo_left(int npt, int res) { return 1 + (npt == 9) + res; }
 __host__ __device__ constexpr int halo_right(int npt, int interp) { return 1 + (npt == 9) + interp; }
 
+// Per-lane constants of a strip.
+struct LaneCtx {
+    int t, e, o, pitch, ny;
+    bool own, ie, io, cv;
+};
+
+// Window of one relaxation stage walking up the strip: rows j-3..j+1 around
+// step j, the residual of row j-3 and the restriction weights of the coarse
+// row below.
+template <typename T>
+struct Stage {
+    Row<T> rm3, rm2, rm1, r0, rp1;
+    T rr3e, rr3o, ytp, cnwp, cnep;
+    double acc;
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_rotate(Stage<T> &S)
+{
+    S.rm3 = S.rm1;
+    S.rm2 = S.r0;
+    S.rm1 = S.rp1;
+}
+
+// One step j of a relaxation stage whose rows j and j+1 are in S.r0, S.rp1
+// (mode 0: colours 0, 1 only; 1: full step, nothing stored; 2: full step,
+// stores if WRITE).  With RES the residual of the final rows j-2 and j-1 is
+// formed, with RQ stored as q = r/C and restricted onto coarse row (j-2)/2,
+// with NORM its squares are accumulated.
+template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM>
+__device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const LaneCtx &L,
+                                           const StreamArgs<T> &a)
+{
+    const bool rj = j >= 1 && j <= L.ny - 2;
+    const bool rjm = j - 1 >= 1 && j - 1 <= L.ny - 2;
+    // colours 0 and 1 on row j
+    {
+        T d;
+        T r = res_even<T, NPT>(S.rm1, S.r0, S.rp1, d);
+        if (rj && L.ie) S.r0.x0 += r / d;
+        r = res_odd<T, NPT>(S.rm1, S.r0, S.rp1, d);
+        if (rj && L.io) S.r0.x1 += r / d;
+    }
+    if (mode != 0) {
+        // colours 2 and 3 on row j-1
+        T d;
+        T r = res_even<T, NPT>(S.rm2, S.rm1, S.r0, d);
+        if (rjm && L.ie) S.rm1.x0 += r / d;
+        r = res_odd<T, NPT>(S.rm2, S.rm1, S.r0, d);
+        if (rjm && L.io) S.rm1.x1 += r / d;
+
+        if (WRITE && mode == 2 && L.own) {
+            if (rjm) st2(a.x_out + (size_t)(j - 1) * L.pitch + L.e, S.rm1.x0, S.rm1.x1);
+            if (rj) st2(a.x_out + (size_t)j * L.pitch + L.e, S.r0.x0, S.r0.x1);
+        }
+        if (RES) {
+            // residuals of the final rows j-2 (even) and j-1 (odd)
+            const bool rA = j - 2 >= 1 && j - 2 <= L.ny - 2;
+            T dae, dao, dbe, dbo;
+            T ae = res_even<T, NPT>(S.rm3, S.rm2, S.rm1, dae);
+            T ao = res_odd<T, NPT>(S.rm3, S.rm2, S.rm1, dao);
+            T be = res_even<T, NPT>(S.rm2, S.rm1, S.r0, dbe);
+            T bo = res_odd<T, NPT>(S.rm2, S.rm1, S.r0, dbo);
+            if (!(rA && L.ie)) ae = T(0);
+            if (!(rA && L.io)) ao = T(0);
+            if (!(rjm && L.ie)) be = T(0);
+            if (!(rjm && L.io)) bo = T(0);
+            if (NORM && WRITE && mode == 2 && L.own)
+                S.acc += (double)ae * ae + (double)ao * ao + (double)be * be + (double)bo * bo;
+            if (RQ) {
+                if (WRITE && mode == 2 && L.own) {
+                    if (rA && L.io) a.q_out[(size_t)(j - 2) * L.pitch + L.o] = ao / dao;
+                    if (rjm) st2(a.q_out + (size_t)(j - 1) * L.pitch + L.e,
+                                 L.ie ? be / dbe : T(0), L.io ? bo / dbo : T(0));
+                }
+                // restriction onto coarse row jc = (j-2)/2, coarse column L.t
+                const int jc = (j - 2) >> 1;
+                const bool jcin = j - 2 >= 2 && jc <= a.cny - 2;
+                T xl = T(0), xr = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0),
+                  cnw = T(0), cne = T(0);
+                if (L.cv && j - 2 >= 0 && jc <= a.cny - 1) {
+                    const size_t co = (size_t)jc * a.cpitch + L.t;
+                    const long long cp = a.cplane;
+                    xl = a.wt[WXL * cp + co];
+                    xr = a.wt[WXR * cp + co];
+                    yb = a.wt[WYB * cp + co];
+                    yt = a.wt[WYT * cp + co];
+                    csw = a.wt[WCSW * cp + co];
+                    cse = a.wt[WCSE * cp + co];
+                    cnw = a.wt[WCNW * cp + co];
+                    cne = a.wt[WCNE * cp + co];
+                }
+                T lxr = fromL(xr), lcse = fromL(cse), lcnep = fromL(S.cnep);
+                T lao = fromL(ao), lbo = fromL(bo), lr3o = fromL(S.rr3o);
+                T bcv = ae + xl * ao + lxr * lao + yb * be + S.ytp * S.rr3e + csw * bo + lcse * lbo +
+                        S.cnwp * S.rr3o + lcnep * lr3o;
+                if (WRITE && mode == 2 && L.own && jcin && L.t >= 1 && L.t <= a.cnx - 2)
+                    a.bc[(size_t)jc * a.cpitch + L.t] = bcv;
+                S.ytp = yt;
+                S.cnwp = cnw;
+                S.cnep = cne;
+            }
+            S.rr3e = be;
+            S.rr3o = bo;
+        }
+    }
+}
+
 template <typename T, int NPT, int V>
 __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
 {
@@ -236,15 +344,13 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
     constexpr int PRO = F::RES ? 2 : 1;         // prologue steps
 
-    Row<T> rm3, rm2, rm1, r0, rp1, n0, n1;
-    T rr3e = T(0), rr3o = T(0);                 // residual of row j-3
-    T ytp = T(0), cnwp = T(0), cnep = T(0);     // weights of coarse row (j-2)/2 - 1
-    double acc = 0.0;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+    Stage<T> S{};
+    Row<T> n0, n1;
+    Row<T> &rm1 = S.rm1, &r0 = S.r0, &rp1 = S.rp1;
 
     // state below the first prologue step: only row j-1 is read by a partial
     // step (colours 0 and 1); rows j-2, j-3 are rotated in before any use
-    rm3 = Row<T>{};
-    rm2 = Row<T>{};
     const int jstart = jfirst - 2 * PRO;
     load_raw(rm1, jstart - 1);
     finish_row(rm1, jstart - 1);
@@ -270,92 +376,92 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
         }
         finish_row(r0, j);
         finish_row(rp1, j + 1);
-        const bool rj = j >= 1 && j <= ny - 2;
-        const bool rjm = j - 1 >= 1 && j - 1 <= ny - 2;
-        // colours 0 and 1 on row j
-        {
-            T d;
-            T r = res_even<T, NPT>(rm1, r0, rp1, d);
-            if (rj && ie) r0.x0 += r / d;
-            r = res_odd<T, NPT>(rm1, r0, rp1, d);
-            if (rj && io) r0.x1 += r / d;
-        }
-        if (mode != 0) {
-            // colours 2 and 3 on row j-1
-            T d;
-            T r = res_even<T, NPT>(rm2, rm1, r0, d);
-            if (rjm && ie) rm1.x0 += r / d;
-            r = res_odd<T, NPT>(rm2, rm1, r0, d);
-            if (rjm && io) rm1.x1 += r / d;
-
-            if (mode == 2 && own) {
-                if (rjm) st2(a.x_out + (size_t)(j - 1) * pitch + e, rm1.x0, rm1.x1);
-                if (rj) st2(a.x_out + (size_t)j * pitch + e, r0.x0, r0.x1);
-            }
-            if (F::RES) {
-                // residuals of the final rows j-2 (even) and j-1 (odd)
-                const bool rA = j - 2 >= 1 && j - 2 <= ny - 2;
-                T dae, dao, dbe, dbo;
-                T ae = res_even<T, NPT>(rm3, rm2, rm1, dae);
-                T ao = res_odd<T, NPT>(rm3, rm2, rm1, dao);
-                T be = res_even<T, NPT>(rm2, rm1, r0, dbe);
-                T bo = res_odd<T, NPT>(rm2, rm1, r0, dbo);
-                if (!(rA && ie)) ae = T(0);
-                if (!(rA && io)) ao = T(0);
-                if (!(rjm && ie)) be = T(0);
-                if (!(rjm && io)) bo = T(0);
-                if (F::NORM && mode == 2 && own)
-                    acc += (double)ae * ae + (double)ao * ao + (double)be * be + (double)bo * bo;
-                if (F::RQ) {
-                    if (mode == 2 && own) {
-                        if (rA && io) a.q_out[(size_t)(j - 2) * pitch + o] = ao / dao;
-                        if (rjm) st2(a.q_out + (size_t)(j - 1) * pitch + e,
-                                     ie ? be / dbe : T(0), io ? bo / dbo : T(0));
-                    }
-                    // restriction onto coarse row jc = (j-2)/2, coarse column t
-                    const int jc = (j - 2) >> 1;
-                    const bool jcin = j - 2 >= 2 && jc <= a.cny - 2;
-                    T xl = T(0), xr = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0),
-                      cnw = T(0), cne = T(0);
-                    if (cv && j - 2 >= 0 && jc <= a.cny - 1) {
-                        const size_t co = (size_t)jc * a.cpitch + t;
-                        const long long cp = a.cplane;
-                        xl = a.wt[WXL * cp + co];
-                        xr = a.wt[WXR * cp + co];
-                        yb = a.wt[WYB * cp + co];
-                        yt = a.wt[WYT * cp + co];
-                        csw = a.wt[WCSW * cp + co];
-                        cse = a.wt[WCSE * cp + co];
-                        cnw = a.wt[WCNW * cp + co];
-                        cne = a.wt[WCNE * cp + co];
-                    }
-                    T lxr = fromL(xr), lcse = fromL(cse), lcnep = fromL(cnep);
-                    T lao = fromL(ao), lbo = fromL(bo), lr3o = fromL(rr3o);
-                    T bcv = ae + xl * ao + lxr * lao + yb * be + ytp * rr3e + csw * bo + lcse * lbo +
-                            cnwp * rr3o + lcnep * lr3o;
-                    if (mode == 2 && own && jcin && t >= 1 && t <= a.cnx - 2)
-                        a.bc[(size_t)jc * a.cpitch + t] = bcv;
-                    ytp = yt;
-                    cnwp = cnw;
-                    cnep = cne;
-                }
-                rr3e = be;
-                rr3o = bo;
-            }
-        }
-        rm3 = rm1;
-        rm2 = r0;
-        rm1 = rp1;
+        stage_step<T, NPT, true, F::RES, F::RQ, F::NORM>(S, j, mode, L, a);
+        stage_rotate(S);
     }
     if (F::NORM) {
         // wave reduction in a fixed order -> one partial per tile
+        double acc = S.acc;
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) a.partials[tile] = acc;
     }
 }
 
+// Two relaxations, then residual, r/C and restriction, in ONE pass (temporal
+// blocking of the two pre-relaxations of Algorithm 1).  Stage A (first
+// relaxation) runs one row-pair step ahead of stage B (second relaxation);
+// stage B takes A's final rows as its "old" rows, so it is exactly the
+// second colour-by-colour sweep.  A's results are correct on fewer lanes than
+// a loaded row, so the halo is the sum of both stages' halos, and each block
+// of rows starts with three A steps and two B steps of prologue.
+template <typename T, int NPT, bool ZX>
+__global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
+{
+    constexpr int HA = 1 + (NPT == 9);          // lanes of A's garbage margin per side
+    constexpr int HL = HA + halo_left(NPT, 1);
+    constexpr int HR = HA + halo_right(NPT, 0);
+    constexpr int OWN = 64 - HL - HR;
+
+    const int per = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;
+    const int strip = tile % a.nstrips;
+    const int blk = tile / a.nstrips;
+    const int lane = threadIdx.x;
+    const int t = strip * OWN + lane - HL;
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = t >= 0 && t < a.cnx;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+
+    auto load_row = [&](Row<T> &r, int j) {
+        r = Row<T>{};
+        if (colv && j >= 0 && j < ny) {
+            const size_t off = (size_t)j * pitch + e;
+            if (!ZX) ld2(a.x_in + off, r.x0, r.x1);
+            ld2(a.b + off, r.b0, r.b1);
+            ld2(a.C + off, r.C0, r.C1);
+            ld2(a.W + off, r.W0, r.W1);
+            ld2(a.S + off, r.S0, r.S1);
+            if (NPT == 9) {
+                ld2(a.SW + off, r.SW0, r.SW1);
+                ld2(a.SE + off, r.SE0, r.SE1);
+            }
+        }
+    };
+
+    const int nsteps = (ny - 1) / 2;
+    const int s0 = blk * a.rb;
+    const int s1 = min(s0 + a.rb, nsteps);
+    const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+
+    Stage<T> A{}, B{};
+    load_row(A.rm1, jfirst - 7);
+    for (int ja = jfirst - 6; ja <= jlast + 2; ja += 2) {
+        load_row(A.r0, ja);
+        load_row(A.rp1, ja + 1);
+        stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
+        const int jb = ja - 2;
+        if (jb >= jfirst - 4) {
+            if (jb == jfirst - 4) B.rm1 = A.rm3;   // A-final row jb-1
+            B.r0 = A.rm2;                           // A-final rows jb, jb+1 as B's old rows
+            B.rp1 = A.rm1;
+            const int mode = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
+            stage_step<T, NPT, true, true, true, false>(B, jb, mode, L, a);
+            stage_rotate(B);
+        }
+        stage_rotate(A);
+    }
+}
+
 int stream_owned_pairs(int npt, int variant)
 {
+    if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX)
+        return 64 - (1 + (npt == 9)) - halo_left(npt, 1) - (1 + (npt == 9)) - halo_right(npt, 0);
     int res = (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_INTERP_NORM ||
                variant == SV_SWEEP_NORM);
     int interp = (variant == SV_INTERP || variant == SV_INTERP_NORM);
@@ -386,6 +492,8 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_INTERP: hipLaunchKernelGGL((k_stream<T, NPT, SV_INTERP>), g, b, 0, s, a); break;
     case SV_INTERP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_INTERP_NORM>), g, b, 0, s, a); break;
     case SV_SWEEP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_NORM>), g, b, 0, s, a); break;
+    case SV_SWEEP2_RQ: hipLaunchKernelGGL((k_stream2<T, NPT, false>), g, b, 0, s, a); break;
+    case SV_SWEEP2_RQ_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -56,7 +56,7 @@ _SIGS = {
     "hipbmg_get_stencil": (_I, [_VP, _I, _VP, _VP]),
     "hipbmg_get_interp": (_I, [_VP, _I, _VP, _VP]),
     "hipbmg_op_smooth": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
-    "hipbmg_op_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
+    "hipbmg_op_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _I, _VP, _VP, _VP]),
     "hipbmg_op_interp_smooth": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(ctypes.c_double), _VP]),
     "hipbmg_fv5_from_cells": (_I, [_I, _I, _VP, _I, _VP, _VP]),
     "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
@@ -175,7 +175,7 @@ class Hierarchy:
         _check(lib().hipbmg_profile(self._h, 1 if enable else 0))
 
     KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
-               "interp_relax_norm", "relax_norm")
+               "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero")
 
     def profile_read(self, precision=0):
         """{kernel name: (total_ms, launches, bytes_per_launch)} for launched kernels."""
@@ -193,12 +193,13 @@ class Hierarchy:
         _check(lib().hipbmg_op_smooth(self._h, l, _ptr(b), _ptr(x), sweeps, _stream()))
         return x
 
-    def op_smooth_restrict(self, l, b, x):
+    def op_smooth_restrict(self, l, b, x, sweeps=1):
         x = x.clone()
         q = torch.zeros_like(x)
         cny, cnx = self.size(l - 1)
         bc = torch.zeros((cny, cnx), dtype=torch.float64, device=x.device)
-        _check(lib().hipbmg_op_smooth_restrict(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(bc), _stream()))
+        _check(lib().hipbmg_op_smooth_restrict(self._h, l, _ptr(b), _ptr(x), sweeps, _ptr(q), _ptr(bc),
+                                               _stream()))
         return x, q, bc
 
     def op_interp_smooth(self, l, b, x, q, xc, rescorr=1, want_norm=False):

@@ -188,8 +188,9 @@ def test_relaxation_matches_oracle(nx, ny, level_from_top, seed):
             assert err <= 1e-12, (l, sweeps, err)
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
 @pytest.mark.parametrize("nx,ny,seed", [(65, 65, 0), (257, 129, 1), (129, 257, 2), (225, 193, 3)])
-def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed):
+def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed, sweeps):
     planes = O.fv5(rand_cells(nx, ny, seed))
     ora = O.Hierarchy(planes)
     hier = HB.Hierarchy(g(planes))
@@ -202,7 +203,7 @@ def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed):
         x = rng.standard_normal((sy, sx))
         x[0] = x[-1] = 0
         x[:, 0] = x[:, -1] = 0
-        xs = step.smooth(lo, b, x, 1)
+        xs = step.smooth(lo, b, x, sweeps)
         r = step.residual(lo, b, xs)
         bc = step.restrict(lo, r)
         C = step.stencil(lo)[:, :, 1, 1]
@@ -211,7 +212,7 @@ def test_fused_relax_residual_restrict_matches_oracle(nx, ny, seed):
         fo[::2, ::2] = False
         nz = (C != 0) & fo
         q[nz] = r[nz] / C[nz]
-        gx, gq, gbc = (c(t) for t in hier.op_smooth_restrict(l, g(b), g(x)))
+        gx, gq, gbc = (c(t) for t in hier.op_smooth_restrict(l, g(b), g(x), sweeps))
         ex, eq, eb = rel(gx, xs), rel(gq, q), rel(gbc, bc)
         assert ex <= 1e-12, (l, ex)
         assert eq <= 1e-11, (l, eq)
@@ -314,8 +315,11 @@ def test_collapse_level_does_not_change_the_iteration(n):
     ref = hists[0]
     for h in hists[1:]:
         assert len(h) == len(ref)
+        # summation order differs between the streaming and the collapsed
+        # kernels: relative agreement plus an absolute rounding floor
         early = ref > 1e-6
-        assert np.all(np.abs(h[early] - ref[early]) <= 1e-9 * ref[early])
+        d = np.abs(h[early] - ref[early])
+        assert np.all(d <= 1e-9 * ref[early] + 1e-13), float(d.max())
 
 
 def test_model_choice_is_reported_and_valid():
