@@ -160,6 +160,27 @@ hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, d
                                       const double *q, const double *xc, int rescorr,
                                       double *sumsq_host, void *stream);
 
+/* Batched solves of many independent problems of different sizes (each with
+ * its own hierarchy, built as by hipbmg_setup, and its own collapse level).
+ * One launch runs the same V-cycle stage (Algorithm 1) of all problems; the
+ * collapsed levels run one workgroup per problem; converged problems are
+ * retired on the device and skipped by later launches; with use_graph one
+ * cycle is captured as a hipGraph and replayed.  precision HIPBMG_MIXED runs
+ * the FP32 V-cycles of all problems inside FP64 iterative refinement.
+ * nx, ny: host arrays [nprob]; coeffs: host array of nprob device pointers to
+ * [3 or 5][ny][nx] planes (npt 5 or 9 for every problem).  b, u: host arrays
+ * of nprob device pointers to [ny][nx]; u holds the initial guesses on entry.
+ * infos: NULL or a host array [nprob].  Returns HIPBMG_ENOCONV if any problem
+ * did not reach tol (every u holds its last iterate). */
+typedef struct hipbmg_batch *hipbmg_batch_handle;
+hipbmg_status hipbmg_setup_batched(int nprob, const int *nx_host, const int *ny_host, int npt,
+                                   const double *const *coeffs_host, const hipbmg_params *params,
+                                   void *stream, hipbmg_batch_handle *out);
+hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle h, const double *const *b_host,
+                                   double *const *u_host, double tol, void *stream,
+                                   hipbmg_info *infos_host);
+hipbmg_status hipbmg_destroy_batched(hipbmg_batch_handle h);
+
 /* Vertex-centred 5-point finite-volume stencil of -div(D grad u) (section 5):
  * the face between vertices p and q takes the mean of the two cells it cuts,
  * C is the sum of the four connections.  cell: [ny-1][nx-1] holding D, or

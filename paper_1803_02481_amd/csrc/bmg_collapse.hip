@@ -176,7 +176,7 @@ template size_t collapse_lds_bytes<double>(int, int, int, int);
 template size_t collapse_lds_bytes<float>(int, int, int, int);
 
 template <typename T>
-__global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
+__device__ __forceinline__ void collapse_body(const CollapseArgs<T> &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sh[CWG / 64];
@@ -327,16 +327,50 @@ __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
 }
 
 template <typename T>
+__global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
+{
+    collapse_body(a);
+}
+
+// one workgroup per problem of a batch; converged problems are skipped
+template <typename T>
+__global__ __launch_bounds__(CWG) void k_collapse_batched(const CollapseArgs<T> *__restrict__ args,
+                                                          const int *__restrict__ active)
+{
+    if (!active[blockIdx.x]) return;
+    collapse_body(args[blockIdx.x]);
+}
+
+template <typename T>
+hipError_t launch_collapse_batched(const CollapseArgs<T> *args, int nprob, int lds_bytes,
+                                   const int *active, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_collapse_batched<T>), dim3(nprob), dim3(CWG), lds_bytes, s, args, active);
+    return hipGetLastError();
+}
+template hipError_t launch_collapse_batched<double>(const CollapseArgs<double> *, int, int, const int *,
+                                                    hipStream_t);
+template hipError_t launch_collapse_batched<float>(const CollapseArgs<float> *, int, int, const int *,
+                                                   hipStream_t);
+
+// allow the collapse kernels the large dynamic LDS they stage levels in (called
+// at setup, outside any stream capture)
+hipError_t collapse_set_attributes()
+{
+    const void *fns[4] = {reinterpret_cast<const void *>(&k_collapse<double>),
+                          reinterpret_cast<const void *>(&k_collapse<float>),
+                          reinterpret_cast<const void *>(&k_collapse_batched<double>),
+                          reinterpret_cast<const void *>(&k_collapse_batched<float>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, COLLAPSE_LDS_BUDGET);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_collapse<T>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           COLLAPSE_LDS_BUDGET);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     hipLaunchKernelGGL((k_collapse<T>), dim3(1), dim3(CWG), a.lds_bytes, s, a);
     return hipGetLastError();
 }
@@ -392,6 +426,99 @@ hipError_t launch_finalize_norm(const double *partials, int n, const double *den
                                 hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, n, denom, out);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched norms.  Problem p's norm partials are partials[off[p] .. off[p] +
+// cnt[p]); one workgroup per problem adds them in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sumsq_batched(const double *const *__restrict__ v,
+                                                       const int4 *__restrict__ dims,
+                                                       double *__restrict__ partials, int nparts)
+{
+    __shared__ double sh[4];
+    const int p = blockIdx.y;
+    const int4 d = dims[p];   // nx, ny, pitch
+    const int ni = d.x - 2;
+    const long long n = (long long)ni * (d.y - 2);
+    const double *x = v[p];
+    double acc = 0.0;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (long long)nparts * 256) {
+        const double a = x[(size_t)(1 + idx / ni) * d.z + 1 + idx % ni];
+        acc += a * a;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[(size_t)p * nparts + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+hipError_t launch_sumsq_batched(const double *const *v, const int4 *dims, int nprob, double *partials,
+                                int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumsq_batched, dim3(nparts, nprob), dim3(256), 0, s, v, dims, partials, nparts);
+    return hipGetLastError();
+}
+
+// out[p] = sqrt(sum of p's partials) / denom[p] (denom may be null); with a
+// non-null `active`, an active problem is retired once out[p] <= tol or out[p]
+// is not finite
+__global__ __launch_bounds__(256) void k_finalize_batched(const double *__restrict__ partials,
+                                                          const int *__restrict__ off,
+                                                          const int *__restrict__ cnt,
+                                                          const double *__restrict__ denom,
+                                                          double *__restrict__ out,
+                                                          int *__restrict__ active, double tol)
+{
+    __shared__ double sh[256];
+    const int p = blockIdx.x;
+    if (active && !active[p]) return;
+    double acc = 0.0;
+    const double *src = partials + off[p];
+    for (int k = threadIdx.x; k < cnt[p]; k += 256) acc += src[k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double v = denom ? sqrt(sh[0]) / denom[p] : sqrt(sh[0]);
+        out[p] = v;
+        if (active && (!(v > tol) || !isfinite(v))) active[p] = 0;
+    }
+}
+
+hipError_t launch_finalize_batched(const double *partials, const int *off, const int *cnt,
+                                   const double *denom, double *out, int *active, double tol, int nprob,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_batched, dim3(nprob), dim3(256), 0, s, partials, off, cnt, denom, out,
+                       active, tol);
+    return hipGetLastError();
+}
+
+// number of active problems -> count[0] (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_count_active(const int *__restrict__ active, int n,
+                                                      int *__restrict__ count)
+{
+    __shared__ int sh[256];
+    int c = 0;
+    for (int k = threadIdx.x; k < n; k += 256) c += active[k] != 0;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[0] = sh[0];
+}
+
+hipError_t launch_count_active(const int *active, int n, int *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, active, n, count);
     return hipGetLastError();
 }
 

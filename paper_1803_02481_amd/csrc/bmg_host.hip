@@ -293,6 +293,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if ((long long)(sx[0] - 2) * (sy[0] - 2) > 4096)
         return fail(HIPBMG_EINVAL, "coarsest level %d x %d too large for the dense solve", sx[0], sy[0]);
 
+    if (collapse_set_attributes() != hipSuccess)
+        return fail(HIPBMG_EHIP, "cannot enable %d bytes of LDS for the collapse kernel", COLLAPSE_LDS_BUDGET);
     hipbmg_hier *h = new hipbmg_hier();
     if (const char *e = std::getenv("HIPBMG_NO_LDS")) h->no_lds = std::atoi(e);
     if (const char *e = std::getenv("HIPBMG_NO_FUSE2")) h->no_fuse2 = std::atoi(e);
@@ -938,5 +940,610 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
         *bytes_per_launch_host = per * n;
     }
+    return HIPBMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: many independent problems of different sizes.  Every
+// problem keeps its own hierarchy (and its own collapse level from the model);
+// one launch runs the same stage of the V-cycle for all problems (depth d from
+// the finest level, the kernel's position within the level), mapping each
+// workgroup to a (problem, tile) pair; the collapsed levels run one workgroup
+// per problem.  Converged problems are retired on the device and skipped by
+// every later launch.  A cycle is captured once as a hipGraph and replayed.
+// ---------------------------------------------------------------------------
+struct BLaunch {
+    int kind;            // 0 streaming stage, 1 collapse
+    int npt, variant;
+    void *d_args;        // StreamArgs<T>[nprob] or CollapseArgs<T>[nprob]
+    int2 *d_map;
+    int nmap;
+    int lds_bytes;
+};
+
+struct BPlan {
+    std::vector<BLaunch> launches;
+    int end_cur = 0;
+    bool built = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct hipbmg_batch {
+    int n = 0;
+    hipbmg_params prm{};
+    std::vector<hipbmg_hier *> hs;
+    std::vector<void *> allocs;
+    int *d_active = nullptr, *d_active2 = nullptr, *d_count = nullptr;
+    double *d_relres = nullptr, *d_bnorm = nullptr, *d_rnorm = nullptr, *d_irel = nullptr;
+    double *d_partials = nullptr, *d_bpart = nullptr;
+    int *d_poff = nullptr, *d_pcnt = nullptr, *d_boff = nullptr, *d_bcnt = nullptr;
+    int *d_roff = nullptr, *d_rcnt = nullptr;
+    double **d_bptr = nullptr, **d_xptr = nullptr;
+    int4 *d_dims = nullptr;
+    LevelDev<double> *d_fine64 = nullptr;
+    LevelDev<float> *d_fine32 = nullptr;
+    double *d_rpart = nullptr;   // refinement residual partials (segments d_roff / d_rcnt)
+    int n_partials = 0;
+    std::vector<int> h_pcnt;
+    double *h_relres = nullptr;
+    int *h_active = nullptr, *h_count = nullptr;
+    int max_nx = 0, max_ny = 0, fine_npt = 5;
+    BPlan plan64[2], plan32[2][2];
+    hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    ~hipbmg_batch()
+    {
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (ws) (void)hipStreamDestroy(ws);
+        auto drop = [](BPlan &p) {
+            if (p.exec) (void)hipGraphExecDestroy(p.exec);
+            if (p.graph) (void)hipGraphDestroy(p.graph);
+        };
+        for (auto &p : plan64) drop(p);
+        for (auto &q : plan32)
+            for (auto &p : q) drop(p);
+        for (void *p : allocs) (void)hipFree(p);
+        if (h_relres) (void)hipHostFree(h_relres);
+        if (h_active) (void)hipHostFree(h_active);
+        if (h_count) (void)hipHostFree(h_count);
+        for (hipbmg_hier *h : hs) delete h;
+    }
+};
+
+template <typename T>
+static hipbmg_status balloc(hipbmg_batch *B, T **p, size_t n, hipStream_t s)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, n * sizeof(T) + 64) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HIPBMG_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+    }
+    B->allocs.push_back(q);
+    HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 64, s));
+    *p = static_cast<T *>(q);
+    return HIPBMG_OK;
+}
+
+template <typename T>
+static const std::vector<LevelDev<T>> &levels_of(hipbmg_hier *h);
+template <>
+const std::vector<LevelDev<double>> &levels_of<double>(hipbmg_hier *h) { return h->lv; }
+template <>
+const std::vector<LevelDev<float>> &levels_of<float>(hipbmg_hier *h) { return h->lv32; }
+template <typename T>
+static const LevelDev<T> *dlevels_of(hipbmg_hier *h);
+template <>
+const LevelDev<double> *dlevels_of<double>(hipbmg_hier *h) { return h->d_lv; }
+template <>
+const LevelDev<float> *dlevels_of<float>(hipbmg_hier *h) { return h->d_lv32; }
+
+// Record the launches of one V-cycle of every problem (same order as
+// enqueue_vcycle) and group them into batched stages.
+template <typename T>
+static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan &plan, hipStream_t s)
+{
+    const int n = B->n;
+    const int nu1 = B->prm.nu1, nu2 = B->prm.nu2, rc = B->prm.residual_correction;
+    struct Rec {
+        int p, npt, variant;
+        StreamArgs<T> a;
+    };
+    // key: phase (0 down, 2 up), depth, k
+    std::vector<std::vector<std::vector<Rec>>> down, up;
+    std::vector<CollapseArgs<T>> cargs(n);
+    int lds_max = 0, end_cur = -1;
+    int off = 0;
+    std::vector<int> poff(n), pcnt(n);
+    for (int p = 0; p < n; ++p) {
+        hipbmg_hier *h = B->hs[p];
+        const std::vector<LevelDev<T>> &lv = levels_of<T>(h);
+        const int L = h->L, ls = h->lstar;
+        int xb_after[HIPBMG_MAX_LEVELS], xres[HIPBMG_MAX_LEVELS];
+        for (int l = L - 1; l > ls; --l) {
+            const int d = L - 1 - l;
+            const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
+            const bool fine = l == L - 1;
+            int xb = fine ? cur : 0;
+            const bool zero = !fine || zero_start;
+            const int nk = (nu1 >= 2 && !h->no_fuse2) ? nu1 - 1 : nu1;
+            for (int k = 1; k <= nk; ++k) {
+                const bool last = k == nk, zx = zero && k == 1, two = last && nk < nu1;
+                const int v = last ? (two ? (zx ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ) : (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ))
+                                   : (zx ? SV_SWEEP_ZX : SV_SWEEP);
+                StreamArgs<T> a = base_args(A, h->rb[l]);
+                a.x_in = A.x[xb];
+                a.x_out = A.x[1 - xb];
+                if (last) {
+                    a.q_out = A.q;
+                    a.bc = Cl.b;
+                    a.wt = A.wt;
+                    a.cnx = Cl.nx;
+                    a.cny = Cl.ny;
+                    a.cpitch = Cl.pitch;
+                    a.cplane = (long long)Cl.plane;
+                }
+                int g;
+                stream_geometry(A.nx, A.ny, A.npt, v, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+                if ((int)down.size() <= d) down.resize(d + 1);
+                if ((int)down[d].size() < k) down[d].resize(k);
+                down[d][k - 1].push_back({p, A.npt, v, a});
+                xb = 1 - xb;
+            }
+            xb_after[l] = xb;
+        }
+        CollapseArgs<T> c{};
+        c.levels = dlevels_of<T>(h);
+        c.top = ls;
+        const bool cfine = ls == L - 1;
+        c.xb_top = cfine ? cur : 1;
+        c.zero_top = cfine ? (zero_start ? 1 : 0) : 1;
+        c.nu1 = nu1;
+        c.nu2 = nu2;
+        c.rescorr = rc;
+        c.chol = h->d_chol;
+        c.cidx = h->d_cidx;
+        c.nc = h->nc;
+        c.work = h->d_work;
+        c.want_norm = cfine ? 1 : 0;
+        c.lds_top = -1;
+        size_t lo = 0;
+        for (int l = 0; l <= ls; ++l) {
+            const size_t bytes = collapse_lds_bytes<T>(lv[l].nx, lv[l].ny, l ? lv[l - 1].nx : 0, l ? lv[l - 1].ny : 0);
+            if (lo + bytes > (size_t)COLLAPSE_LDS_BUDGET || h->no_lds) break;
+            c.lds_off[l] = (int)lo;
+            lo += bytes;
+            c.lds_top = l;
+        }
+        c.lds_bytes = (int)lo;
+        lds_max = std::max(lds_max, (int)lo);
+        xres[ls] = c.xb_top;
+        int pc = 1;
+        for (int l = ls + 1; l < L; ++l) {
+            const int d = L - 1 - l;
+            const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
+            const bool fine = l == L - 1;
+            int xb = xb_after[l];
+            for (int k = 1; k <= nu2; ++k) {
+                const bool first = k == 1, last = k == nu2;
+                const int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP) : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
+                StreamArgs<T> a = base_args(A, h->rb[l]);
+                a.x_in = A.x[xb];
+                a.x_out = A.x[1 - xb];
+                if (first) {
+                    a.xc = Cl.x[xres[l - 1]];
+                    a.wt = A.wt;
+                    a.q_in = A.q;
+                    a.rescorr = rc;
+                    a.cnx = Cl.nx;
+                    a.cny = Cl.ny;
+                    a.cpitch = Cl.pitch;
+                    a.cplane = (long long)Cl.plane;
+                }
+                int g;
+                stream_geometry(A.nx, A.ny, A.npt, v, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+                if (fine && last) pc = a.ntiles;
+                if ((int)up.size() <= d) up.resize(d + 1);
+                if ((int)up[d].size() < k) up[d].resize(k);
+                up[d][k - 1].push_back({p, A.npt, v, a});
+                xb = 1 - xb;
+            }
+            xres[l] = xb;
+        }
+        const int ec = xres[L - 1];
+        if (end_cur >= 0 && ec != end_cur) return fail(HIPBMG_EINVAL, "batched plan: buffer parity differs between problems");
+        end_cur = ec;
+        poff[p] = off;
+        pcnt[p] = pc;
+        off += pc;
+        cargs[p] = c;
+    }
+    // partial-sum segments of the finest norm: the same geometry (hence the
+    // same segments) for every plan of the batch, so one buffer serves all
+    if (!B->d_partials) {
+        STCHK(balloc(B, &B->d_partials, (size_t)off + 1, s));
+        STCHK(balloc(B, &B->d_poff, n, s));
+        STCHK(balloc(B, &B->d_pcnt, n, s));
+        HIPCHK(hipMemcpyAsync(B->d_poff, poff.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(B->d_pcnt, pcnt.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+        B->n_partials = off;
+        B->h_pcnt = pcnt;
+    } else if (off != B->n_partials || pcnt != B->h_pcnt) {
+        return fail(HIPBMG_EINVAL, "batched plan: norm segments differ between plans");
+    }
+    double *parts = B->d_partials;
+    for (auto &dd : up)
+        for (auto &kk : dd)
+            for (Rec &r : kk) r.a.partials = parts + poff[r.p];
+    for (int p = 0; p < n; ++p) cargs[p].partials = parts + poff[p];
+    // materialise the stages
+    auto add_stage = [&](std::vector<Rec> &recs) -> hipbmg_status {
+        if (recs.empty()) return HIPBMG_OK;
+        std::vector<StreamArgs<T>> args(n);
+        std::vector<int2> map;
+        for (Rec &r : recs) {
+            if (r.variant != recs[0].variant || r.npt != recs[0].npt)
+                return fail(HIPBMG_EINVAL, "batched plan: mixed kernels in one stage");
+            args[r.p] = r.a;
+            for (int tl = 0; tl < r.a.ntiles; ++tl) map.push_back(make_int2(r.p, tl));
+        }
+        BLaunch bl{};
+        bl.kind = 0;
+        bl.npt = recs[0].npt;
+        bl.variant = recs[0].variant;
+        StreamArgs<T> *da = nullptr;
+        int2 *dm = nullptr;
+        STCHK(balloc(B, &da, n, s));
+        STCHK(balloc(B, &dm, map.size(), s));
+        HIPCHK(hipMemcpyAsync(da, args.data(), n * sizeof(StreamArgs<T>), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        bl.d_args = da;
+        bl.d_map = dm;
+        bl.nmap = (int)map.size();
+        plan.launches.push_back(bl);
+        return HIPBMG_OK;
+    };
+    for (size_t d = 0; d < down.size(); ++d)
+        for (auto &kk : down[d]) STCHK(add_stage(kk));
+    {
+        BLaunch bl{};
+        bl.kind = 1;
+        CollapseArgs<T> *dc = nullptr;
+        STCHK(balloc(B, &dc, n, s));
+        HIPCHK(hipMemcpyAsync(dc, cargs.data(), n * sizeof(CollapseArgs<T>), hipMemcpyHostToDevice, s));
+        bl.d_args = dc;
+        bl.lds_bytes = lds_max;
+        plan.launches.push_back(bl);
+    }
+    for (int d = (int)up.size() - 1; d >= 0; --d)
+        for (auto &kk : up[d]) STCHK(add_stage(kk));
+    HIPCHK(hipStreamSynchronize(s));
+    plan.end_cur = end_cur;
+    plan.built = true;
+    return HIPBMG_OK;
+}
+
+template <typename T>
+static hipError_t run_plan_launches(hipbmg_batch *B, BPlan &plan, const int *active, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (BLaunch &bl : plan.launches) {
+        if (bl.kind == 0)
+            e = launch_stream_batched<T>(bl.npt, bl.variant, static_cast<const StreamArgs<T> *>(bl.d_args),
+                                         bl.d_map, bl.nmap, active, s);
+        else
+            e = launch_collapse_batched<T>(static_cast<const CollapseArgs<T> *>(bl.d_args), B->n,
+                                           bl.lds_bytes, active, s);
+        if (e != hipSuccess) return e;
+    }
+    return e;
+}
+
+// one V-cycle of all active problems plus their residual norms and
+// retirement; replayed from a captured graph when use_graph is set
+template <typename T>
+static hipbmg_status batch_cycle(hipbmg_batch *B, BPlan &plan, int *active, const double *denom, double *out,
+                                 double tol, hipStream_t s)
+{
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = run_plan_launches<T>(B, plan, active, s);
+        if (e != hipSuccess) return e;
+        e = launch_finalize_batched(B->d_partials, B->d_poff, B->d_pcnt, denom, out, active, tol, B->n, s);
+        if (e != hipSuccess) return e;
+        return launch_count_active(active, B->n, B->d_count, s);
+    };
+    if (!B->prm.use_graph) {
+        HIPCHK(enqueue());
+        return HIPBMG_OK;
+    }
+    // one graph per (plan, active buffer, denominator, output) combination:
+    // the plans are only ever used with one combination each
+    if (!plan.exec) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue();
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(HIPBMG_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        plan.graph = g;
+        HIPCHK(hipGraphInstantiate(&plan.exec, g, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(plan.exec, s));
+    return HIPBMG_OK;
+}
+
+static hipbmg_status batch_read(hipbmg_batch *B, const double *d_vals, const int *d_act, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(B->h_relres, d_vals, B->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(B->h_active, d_act, B->n * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const int *ny, int npt,
+                                              const double *const *coeffs, const hipbmg_params *params,
+                                              void *stream, hipbmg_batch_handle *out)
+{
+    if (!out) return fail(HIPBMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nprob < 1 || !nx || !ny || !coeffs) return fail(HIPBMG_EINVAL, "bad batch arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipbmg_params prm;
+    hipbmg_default_params(&prm);
+    if (params) prm = *params;
+    hipbmg_batch *B = new hipbmg_batch();
+    B->n = nprob;
+    B->prm = prm;
+    auto bail = [&](hipbmg_status st) {
+        std::string m = g_err;
+        delete B;
+        g_err = m;
+        return st;
+    };
+    for (int p = 0; p < nprob; ++p) {
+        hipbmg_handle h = nullptr;
+        hipbmg_status st = hipbmg_setup(nx[p], ny[p], npt, coeffs[p], &prm, stream, &h);
+        if (st != HIPBMG_OK) {
+            std::string m = g_err;
+            (void)fail(st, "problem %d: %s", p, m.c_str());
+            return bail(st);
+        }
+        B->hs.push_back(h);
+        B->max_nx = std::max(B->max_nx, nx[p]);
+        B->max_ny = std::max(B->max_ny, ny[p]);
+    }
+    B->fine_npt = npt;
+    hipbmg_status st = HIPBMG_OK;
+    auto chk = [&](hipbmg_status x) {
+        if (st == HIPBMG_OK) st = x;
+    };
+    chk(balloc(B, &B->d_active, nprob, s));
+    chk(balloc(B, &B->d_active2, nprob, s));
+    chk(balloc(B, &B->d_count, 1, s));
+    chk(balloc(B, &B->d_relres, nprob, s));
+    chk(balloc(B, &B->d_bnorm, nprob, s));
+    chk(balloc(B, &B->d_rnorm, nprob, s));
+    chk(balloc(B, &B->d_irel, nprob, s));
+    chk(balloc(B, &B->d_bpart, (size_t)nprob * 64, s));
+    chk(balloc(B, &B->d_boff, nprob, s));
+    chk(balloc(B, &B->d_bcnt, nprob, s));
+    chk(balloc(B, &B->d_roff, nprob, s));
+    chk(balloc(B, &B->d_rcnt, nprob, s));
+    chk(balloc(B, &B->d_bptr, nprob, s));
+    chk(balloc(B, &B->d_xptr, nprob, s));
+    chk(balloc(B, &B->d_dims, nprob, s));
+    chk(balloc(B, &B->d_fine64, nprob, s));
+    if (prm.precision == HIPBMG_MIXED) chk(balloc(B, &B->d_fine32, nprob, s));
+    if (st != HIPBMG_OK) return bail(st);
+    std::vector<int> boff(nprob), bcnt(nprob, 64), roff(nprob), rcnt(nprob);
+    std::vector<double *> bptr(nprob), xptr(nprob);
+    std::vector<int4> dims(nprob);
+    std::vector<LevelDev<double>> f64(nprob);
+    std::vector<LevelDev<float>> f32(nprob);
+    size_t roffs = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const LevelDev<double> &F = B->hs[p]->lv[B->hs[p]->L - 1];
+        boff[p] = 64 * p;
+        bptr[p] = F.b;
+        xptr[p] = F.x[0];
+        dims[p] = make_int4(F.nx, F.ny, F.pitch, 0);
+        f64[p] = F;
+        if (prm.precision == HIPBMG_MIXED) f32[p] = B->hs[p]->lv32[B->hs[p]->L - 1];
+        roff[p] = (int)roffs;
+        rcnt[p] = ((F.nx + 255) / 256) * F.ny;
+        roffs += rcnt[p];
+    }
+    if (balloc(B, &B->d_rpart, roffs + 1, s) != HIPBMG_OK) return bail(HIPBMG_ENOMEM);
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (st == HIPBMG_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            st = fail(HIPBMG_EHIP, "batch table upload failed");
+    };
+    up(B->d_boff, boff.data(), nprob * sizeof(int));
+    up(B->d_bcnt, bcnt.data(), nprob * sizeof(int));
+    up(B->d_roff, roff.data(), nprob * sizeof(int));
+    up(B->d_rcnt, rcnt.data(), nprob * sizeof(int));
+    up(B->d_bptr, bptr.data(), nprob * sizeof(double *));
+    up(B->d_xptr, xptr.data(), nprob * sizeof(double *));
+    up(B->d_dims, dims.data(), nprob * sizeof(int4));
+    up(B->d_fine64, f64.data(), nprob * sizeof(LevelDev<double>));
+    if (prm.precision == HIPBMG_MIXED) up(B->d_fine32, f32.data(), nprob * sizeof(LevelDev<float>));
+    if (st != HIPBMG_OK) return bail(st);
+    if (hipHostMalloc(&B->h_relres, nprob * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&B->h_active, nprob * sizeof(int)) != hipSuccess ||
+        hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+    // plans: FP64 from buffer 0 (and from 1 if a cycle changes the parity);
+    // FP32 inner cycles from zero, then from where the previous cycle ended
+    st = build_plan<double>(B, 0, false, B->plan64[0], s);
+    if (st == HIPBMG_OK && B->plan64[0].end_cur != 0) st = build_plan<double>(B, 1, false, B->plan64[1], s);
+    if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) {
+        st = build_plan<float>(B, 0, true, B->plan32[1][0], s);
+        const int c1 = B->plan32[1][0].end_cur;
+        if (st == HIPBMG_OK) st = build_plan<float>(B, c1, false, B->plan32[0][c1], s);
+        const int c2 = B->plan32[0][c1].end_cur;
+        if (st == HIPBMG_OK && c2 != c1) st = build_plan<float>(B, c2, false, B->plan32[0][c2], s);
+    }
+    if (st != HIPBMG_OK) return bail(st);
+    if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "batch setup failed"));
+    if (hipStreamCreateWithFlags(&B->ws, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(HIPBMG_EHIP, "stream creation failed"));
+    *out = B;
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_destroy_batched(hipbmg_batch_handle B)
+{
+    if (B) {
+        (void)hipDeviceSynchronize();
+        delete B;
+    }
+    return HIPBMG_OK;
+}
+
+// ||b|| per problem; the finest level's b and x[0] are loaded beforehand
+static hipbmg_status batch_bnorm(hipbmg_batch *B, hipStream_t s)
+{
+    HIPCHK(launch_sumsq_batched(B->d_bptr, B->d_dims, B->n, B->d_bpart, 64, s));
+    HIPCHK(launch_finalize_batched(B->d_bpart, B->d_boff, B->d_bcnt, nullptr, B->d_bnorm, nullptr, 0.0, B->n, s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const double *const *b, double *const *u,
+                                              double tol, void *stream, hipbmg_info *infos)
+{
+    const double t0 = now_ms();
+    if (!B) return fail(HIPBMG_EINVAL, "null handle");
+    if (!b || !u) return fail(HIPBMG_EINVAL, "b and u must be arrays of device pointers");
+    if (!(tol > 0.0)) return fail(HIPBMG_EINVAL, "tol must be > 0");
+    // the batch works on its own stream, ordered after the caller's stream's
+    // earlier work and before its later work
+    hipStream_t s_user = (hipStream_t)stream;
+    hipStream_t s = B->ws;
+    HIPCHK(hipEventRecord(B->ev_in, s_user));
+    HIPCHK(hipStreamWaitEvent(s, B->ev_in, 0));
+    const int n = B->n;
+    for (int p = 0; p < n; ++p) {
+        hipbmg_hier *h = B->hs[p];
+        const LevelDev<double> &F = h->lv[h->L - 1];
+        if (!b[p] || !u[p]) return fail(HIPBMG_EINVAL, "problem %d: null pointer", p);
+        HIPCHK(hipMemcpy2DAsync(F.b, F.pitch * sizeof(double), b[p], F.nx * sizeof(double), F.nx * sizeof(double),
+                                F.ny, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpy2DAsync(F.x[0], F.pitch * sizeof(double), u[p], F.nx * sizeof(double),
+                                F.nx * sizeof(double), F.ny, hipMemcpyDeviceToDevice, s));
+        if (infos) {
+            memset(&infos[p], 0, sizeof(hipbmg_info));
+            fill_info_common(h, &infos[p]);
+        }
+    }
+    const int maxn = std::max(B->max_nx, B->max_ny);
+    HIPCHK(launch_zero_ring_batched(B->d_bptr, B->d_dims, maxn, n, s));
+    HIPCHK(launch_zero_ring_batched(B->d_xptr, B->d_dims, maxn, n, s));
+    STCHK(batch_bnorm(B, s));
+    HIPCHK(hipMemcpyAsync(B->h_relres, B->d_bnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> bnorm(B->h_relres, B->h_relres + n);
+    std::vector<int> act(n), cycles(n, 0), steps(n, 0), done_cur(n, 0);
+    std::vector<double> rel(n, 0.0);
+    int nbad = 0;
+    for (int p = 0; p < n; ++p) {
+        act[p] = bnorm[p] > 0.0 && std::isfinite(bnorm[p]);
+        if (!std::isfinite(bnorm[p])) ++nbad;
+    }
+    HIPCHK(hipMemcpyAsync(B->d_active, act.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    hipbmg_status result = HIPBMG_OK;
+    int cur = 0;
+    if (B->prm.precision != HIPBMG_MIXED) {
+        for (int c = 0; c < B->prm.max_cycles; ++c) {
+            BPlan &plan = B->plan64[cur];
+            STCHK(batch_cycle<double>(B, plan, B->d_active, B->d_bnorm, B->d_relres, tol, s));
+            STCHK(batch_read(B, B->d_relres, B->d_active, s));
+            for (int p = 0; p < n; ++p)
+                if (act[p]) {
+                    rel[p] = B->h_relres[p];
+                    if (infos && cycles[p] < HIPBMG_MAX_HIST) infos[p].relres_hist[cycles[p]] = rel[p];
+                    ++cycles[p];
+                    if (!B->h_active[p]) {
+                        act[p] = 0;
+                        done_cur[p] = plan.end_cur;
+                    }
+                }
+            cur = plan.end_cur;
+            if (B->h_count[0] == 0) break;
+        }
+        for (int p = 0; p < n; ++p)
+            if (act[p]) done_cur[p] = cur;
+        for (int p = 0; p < n; ++p) steps[p] = cycles[p];
+    } else {
+        // FP64 iterative refinement around batched FP32 V-cycles
+        int total = 0;
+        while (true) {
+            HIPCHK(launch_ir_residual_batched(B->d_fine64, B->d_fine32, B->d_active, B->d_rpart, B->d_roff,
+                                              B->fine_npt, B->max_nx, B->max_ny, n, s));
+            HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, nullptr, B->d_rnorm, B->d_active,
+                                           -1.0, n, s));
+            HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, B->d_bnorm, B->d_relres, B->d_active,
+                                           tol, n, s));
+            HIPCHK(launch_count_active(B->d_active, n, B->d_count, s));
+            STCHK(batch_read(B, B->d_relres, B->d_active, s));
+            for (int p = 0; p < n; ++p)
+                if (act[p]) {
+                    rel[p] = B->h_relres[p];
+                    if (infos && steps[p] < HIPBMG_MAX_HIST) infos[p].relres_hist[steps[p]] = rel[p];
+                    if (!B->h_active[p]) act[p] = 0;
+                    else ++steps[p];
+                }
+            if (B->h_count[0] == 0 || total >= B->prm.max_cycles) break;
+            // inner FP32 solves of A e = r for the active problems
+            HIPCHK(hipMemcpyAsync(B->d_active2, B->d_active, n * sizeof(int), hipMemcpyDeviceToDevice, s));
+            int icur = 0;
+            for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
+                BPlan &plan = k == 0 ? B->plan32[1][0] : B->plan32[0][icur];
+                STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->prm.inner_tol, s));
+                icur = plan.end_cur;
+                ++total;
+                HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                for (int p = 0; p < n; ++p)
+                    if (act[p]) ++cycles[p];
+                if (B->h_count[0] == 0) break;
+            }
+            if (icur != 0) return fail(HIPBMG_EINVAL, "batched refinement expects the correction in buffer 0");
+            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_active, B->max_nx, B->max_ny, n, s));
+        }
+        for (int p = 0; p < n; ++p) done_cur[p] = 0;
+    }
+    for (int p = 0; p < n; ++p) {
+        hipbmg_hier *h = B->hs[p];
+        const LevelDev<double> &F = h->lv[h->L - 1];
+        if (bnorm[p] == 0.0) {
+            HIPCHK(hipMemsetAsync(u[p], 0, (size_t)F.nx * F.ny * sizeof(double), s));
+        } else {
+            HIPCHK(hipMemcpy2DAsync(u[p], F.nx * sizeof(double), F.x[done_cur[p]], F.pitch * sizeof(double),
+                                    F.nx * sizeof(double), F.ny, hipMemcpyDeviceToDevice, s));
+        }
+        const bool ok = bnorm[p] == 0.0 || rel[p] <= tol;
+        if (!std::isfinite(rel[p]) || !std::isfinite(bnorm[p])) result = HIPBMG_ENAN;
+        else if (!ok && result == HIPBMG_OK) result = HIPBMG_ENOCONV;
+        if (infos) {
+            infos[p].cycles = cycles[p];
+            infos[p].outer_steps = steps[p];
+            infos[p].relres = rel[p];
+        }
+    }
+    HIPCHK(hipEventRecord(B->ev_out, s));
+    HIPCHK(hipStreamWaitEvent(s_user, B->ev_out, 0));
+    HIPCHK(hipStreamSynchronize(s));
+    const double ms = now_ms() - t0;
+    if (infos)
+        for (int p = 0; p < n; ++p) infos[p].solve_ms = ms;
+    if (result == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "a residual norm is not finite");
+    if (result == HIPBMG_ENOCONV) return fail(HIPBMG_ENOCONV, "some problems did not reach tol");
+    (void)nbad;
     return HIPBMG_OK;
 }

@@ -71,6 +71,10 @@ void stream_geometry(int nx, int ny, int npt, int variant, int rb, int *nstrips,
                      int *ntiles, int *grid);
 template <typename T>
 hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid, hipStream_t s);
+// one launch over many problems: map[w] = (problem, tile), args[problem]
+template <typename T>
+hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
+                                 int nmap, const int *active, hipStream_t s);
 
 // Setup kernels.
 hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,
@@ -106,6 +110,18 @@ template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s);
 template <typename T>
 size_t collapse_lds_bytes(int nx, int ny, int cnx, int cny);
+hipError_t collapse_set_attributes();
+template <typename T>
+hipError_t launch_collapse_batched(const CollapseArgs<T> *args, int nprob, int lds_bytes,
+                                   const int *active, hipStream_t s);
+
+// batched norm helpers (see bmg_collapse.hip)
+hipError_t launch_sumsq_batched(const double *const *v, const int4 *dims, int nprob, double *partials,
+                                int nparts, hipStream_t s);
+hipError_t launch_finalize_batched(const double *partials, const int *off, const int *cnt,
+                                   const double *denom, double *out, int *active, double tol, int nprob,
+                                   hipStream_t s);
+hipError_t launch_count_active(const int *active, int n, int *count, hipStream_t s);
 
 // Sum of squares of interior entries of a pitched field -> partials.
 hipError_t launch_sumsq(const double *v, int nx, int ny, int pitch, double *partials, int nparts,

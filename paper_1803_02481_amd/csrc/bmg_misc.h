@@ -15,4 +15,14 @@ hipError_t launch_ir_residual(const LevelDev<double> &d, const double *u, float 
 hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, int nx, int ny,
                             hipStream_t s);
 
+// batched forms (blockIdx.z = problem; inactive problems skipped).  The FP64
+// iterate is x[0] of the finest level, the FP32 correction x[0] of the FP32
+// finest level; partials of problem p start at poff[p]
+hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
+                                      const int *active, double *partials, const int *poff, int npt,
+                                      int max_nx, int max_ny, int nprob, hipStream_t s);
+hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const int *active,
+                                    int max_nx, int max_ny, int nprob, hipStream_t s);
+hipError_t launch_zero_ring_batched(double *const *v, const int4 *dims, int maxn, int nprob, hipStream_t s);
+
 }  // namespace hbmg

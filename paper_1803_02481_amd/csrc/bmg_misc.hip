@@ -134,4 +134,101 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// batched forms of the refinement steps: blockIdx.z = problem; problems whose
+// flag is 0 are skipped
+// ---------------------------------------------------------------------------
+template <int NPT>
+__global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<double> *__restrict__ d,
+                                                             const LevelDev<float> *__restrict__ f,
+                                                             const int *__restrict__ active,
+                                                             double *__restrict__ partials,
+                                                             const int *__restrict__ poff)
+{
+    __shared__ double sh[4];
+    const int p = blockIdx.z;
+    if (!active[p]) return;
+    const LevelDev<double> &D = d[p];
+    if (D.npt != NPT) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (j >= D.ny || (int)(blockIdx.x * 256) >= D.nx) return;   // whole block outside: uniform
+    const double *u = D.x[0];
+    double acc = 0.0;
+    if (i < D.nx) {
+        const size_t q = (size_t)j * D.pitch + i, P = D.pitch;
+        float out = 0.0f;
+        if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2) {
+            double s = D.b[q] + D.W[q] * u[q - 1] + D.W[q + 1] * u[q + 1] + D.S[q] * u[q - P] +
+                       D.S[q + P] * u[q + P];
+            if (NPT == 9)
+                s += D.SW[q] * u[q - P - 1] + D.SW[q + P + 1] * u[q + P + 1] + D.SE[q] * u[q - P + 1] +
+                     D.SE[q + P - 1] * u[q + P - 1];
+            const double r = s - D.C[q] * u[q];
+            acc = r * r;
+            out = (float)r;
+        }
+        f[p].b[(size_t)j * f[p].pitch + i] = out;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[poff[p] + blockIdx.y * ((D.nx + 255) / 256) + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
+                                      const int *active, double *partials, const int *poff, int npt,
+                                      int max_nx, int max_ny, int nprob, hipStream_t s)
+{
+    dim3 g((max_nx + 255) / 256, max_ny, nprob);
+    if (npt == 9)
+        hipLaunchKernelGGL(k_ir_residual_batched<9>, g, dim3(256), 0, s, d, f, active, partials, poff);
+    else
+        hipLaunchKernelGGL(k_ir_residual_batched<5>, g, dim3(256), 0, s, d, f, active, partials, poff);
+    return hipGetLastError();
+}
+
+__global__ void k_ir_update_batched(const LevelDev<double> *__restrict__ d, const LevelDev<float> *__restrict__ f,
+                                    const int *__restrict__ active)
+{
+    const int p = blockIdx.z;
+    if (!active[p]) return;
+    const LevelDev<double> &D = d[p];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2)
+        D.x[0][(size_t)j * D.pitch + i] += (double)f[p].x[0][(size_t)j * f[p].pitch + i];
+}
+
+hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const int *active,
+                                    int max_nx, int max_ny, int nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ir_update_batched, dim3((max_nx + 255) / 256, max_ny, nprob), dim3(256), 0, s, d, f,
+                       active);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_ring_batched(double *const *__restrict__ v, const int4 *__restrict__ dims)
+{
+    const int p = blockIdx.y;
+    const int4 dd = dims[p];
+    double *x = v[p];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < dd.x) {
+        x[k] = 0.0;
+        x[(size_t)(dd.y - 1) * dd.z + k] = 0.0;
+    }
+    if (k < dd.y) {
+        x[(size_t)k * dd.z] = 0.0;
+        x[(size_t)k * dd.z + dd.x - 1] = 0.0;
+    }
+}
+
+hipError_t launch_zero_ring_batched(double *const *v, const int4 *dims, int maxn, int nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_ring_batched, dim3((maxn + 255) / 256, nprob), dim3(256), 0, s, v, dims);
+    return hipGetLastError();
+}
+
 }  // namespace hbmg

@@ -258,17 +258,13 @@ __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const L
 }
 
 template <typename T, int NPT, int V>
-__global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
+__device__ __forceinline__ void stream_tile(const StreamArgs<T> &a, const int tile)
 {
     using F = VariantFlags<V>;
     constexpr int HL = halo_left(NPT, F::RES);
     constexpr int HR = halo_right(NPT, F::INTERP);
     constexpr int OWN = 64 - HL - HR;
 
-    // XCD-aware tile order: consecutive tiles land on the same XCD
-    const int per = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= a.ntiles) return;
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
     const int lane = threadIdx.x;
@@ -395,16 +391,13 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
 // a loaded row, so the halo is the sum of both stages' halos, and each block
 // of rows starts with three A steps and two B steps of prologue.
 template <typename T, int NPT, bool ZX>
-__global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
+__device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int HA = 1 + (NPT == 9);          // lanes of A's garbage margin per side
     constexpr int HL = HA + halo_left(NPT, 1);
     constexpr int HR = HA + halo_right(NPT, 0);
     constexpr int OWN = 64 - HL - HR;
 
-    const int per = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= a.ntiles) return;
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
     const int lane = threadIdx.x;
@@ -458,6 +451,50 @@ __global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
     }
 }
 
+// XCD-aware tile order: WG i runs on XCD i mod 8, so consecutive tiles (the
+// neighbouring strips of a row band) are given to the same XCD
+__device__ __forceinline__ int xcd_tile()
+{
+    const int per = gridDim.x >> 3;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+template <typename T, int NPT, int V>
+__global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
+{
+    const int tile = xcd_tile();
+    if (tile >= a.ntiles) return;
+    stream_tile<T, NPT, V>(a, tile);
+}
+
+template <typename T, int NPT, bool ZX>
+__global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
+{
+    const int tile = xcd_tile();
+    if (tile >= a.ntiles) return;
+    stream2_tile<T, NPT, ZX>(a, tile);
+}
+
+// Batched form: one launch covers the same stage of many problems.  map[w] =
+// (problem, tile) of workgroup w; problems whose flag in `active` is 0 are
+// skipped (converged).
+template <typename T, int NPT, int V>
+__global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__restrict__ args,
+                                                       const int2 *__restrict__ map, int nmap,
+                                                       const int *__restrict__ active)
+{
+    if ((int)blockIdx.x >= nmap) return;
+    const int2 m = map[blockIdx.x];
+    if (!active[m.x]) return;
+    const StreamArgs<T> a = args[m.x];
+    if (V == SV_SWEEP2_RQ)
+        stream2_tile<T, NPT, false>(a, m.y);
+    else if (V == SV_SWEEP2_RQ_ZX)
+        stream2_tile<T, NPT, true>(a, m.y);
+    else
+        stream_tile<T, NPT, (V >= SV_SWEEP2_RQ ? SV_SWEEP : V)>(a, m.y);
+}
+
 int stream_owned_pairs(int npt, int variant)
 {
     if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX)
@@ -506,6 +543,43 @@ hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid,
     if (npt == 9) return launch_v<T, 9>(variant, a, grid, s);
     return hipErrorInvalidValue;
 }
+
+template <typename T, int NPT>
+static hipError_t launch_vb(int variant, const StreamArgs<T> *args, const int2 *map, int nmap,
+                            const int *active, hipStream_t s)
+{
+    dim3 g(nmap), b(64);
+    switch (variant) {
+#define HB_CASE(V)                                                                                 \
+    case V: hipLaunchKernelGGL((k_stream_batched<T, NPT, V>), g, b, 0, s, args, map, nmap, active); break;
+    HB_CASE(SV_SWEEP)
+    HB_CASE(SV_SWEEP_ZX)
+    HB_CASE(SV_SWEEP_RQ)
+    HB_CASE(SV_SWEEP_RQ_ZX)
+    HB_CASE(SV_INTERP)
+    HB_CASE(SV_INTERP_NORM)
+    HB_CASE(SV_SWEEP_NORM)
+    HB_CASE(SV_SWEEP2_RQ)
+    HB_CASE(SV_SWEEP2_RQ_ZX)
+#undef HB_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
+                                 int nmap, const int *active, hipStream_t s)
+{
+    if (nmap <= 0) return hipSuccess;
+    if (npt == 5) return launch_vb<T, 5>(variant, args, map, nmap, active, s);
+    if (npt == 9) return launch_vb<T, 9>(variant, args, map, nmap, active, s);
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_stream_batched<double>(int, int, const StreamArgs<double> *, const int2 *,
+                                                  int, const int *, hipStream_t);
+template hipError_t launch_stream_batched<float>(int, int, const StreamArgs<float> *, const int2 *, int,
+                                                 const int *, hipStream_t);
 
 template hipError_t launch_stream<double>(int, int, const StreamArgs<double> &, int, hipStream_t);
 template hipError_t launch_stream<float>(int, int, const StreamArgs<float> &, int, hipStream_t);

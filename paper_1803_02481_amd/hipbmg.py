@@ -64,6 +64,11 @@ _SIGS = {
     "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
     "hipbmg_calibrate": (_I, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_setup_batched": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, ctypes.POINTER(_VP),
+                                  ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
+    "hipbmg_solve_batched": (_I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_double, _VP,
+                                  ctypes.POINTER(Info)]),
+    "hipbmg_destroy_batched": (_I, [_VP]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -208,6 +213,51 @@ class Hierarchy:
         _check(lib().hipbmg_op_interp_smooth(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(xc), rescorr,
                                              ctypes.byref(ss) if want_norm else None, _stream()))
         return (x, ss.value) if want_norm else x
+
+
+class BatchHierarchy:
+    """Many independent problems of different sizes solved together
+    (hipbmg_setup_batched / hipbmg_solve_batched)."""
+
+    def __init__(self, coeffs_list, **params):
+        n = len(coeffs_list)
+        if n == 0:
+            raise ValueError("empty batch")
+        npt = 5 if coeffs_list[0].shape[0] == 3 else 9
+        self.shapes = [(int(c.shape[1]), int(c.shape[2])) for c in coeffs_list]
+        nx = (_I * n)(*[s[1] for s in self.shapes])
+        ny = (_I * n)(*[s[0] for s in self.shapes])
+        ptrs = (_VP * n)(*[_ptr(c).value for c in coeffs_list])
+        self.params = default_params(**params)
+        h = ctypes.c_void_p()
+        _check(lib().hipbmg_setup_batched(n, nx, ny, npt, ptrs, ctypes.byref(self.params), _stream(),
+                                          ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().hipbmg_destroy_batched(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b_list, u_list=None, tol=1e-10, check=True):
+        if u_list is None:
+            u_list = [torch.zeros_like(b) for b in b_list]
+        n = self.n
+        bp = (_VP * n)(*[_ptr(b).value for b in b_list])
+        up = (_VP * n)(*[_ptr(u).value for u in u_list])
+        infos = (Info * n)()
+        st = lib().hipbmg_solve_batched(self._h, bp, up, tol, _stream(), infos)
+        if check and st != OK:
+            _check(st)
+        self.status = st
+        return u_list, list(infos)
 
 
 def calibrate():

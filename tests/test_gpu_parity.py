@@ -461,3 +461,53 @@ def test_deterministic_and_resumable():
     u33, _ = h3.solve(b, u3.clone(), tol=1e-30, check=False)
     u6, _ = h6.solve(b, tol=1e-30, check=False)
     assert torch.equal(u33, u6)
+
+
+def batch_case(sizes, seed0=0):
+    planes, bs = [], []
+    for k, (nx, ny) in enumerate(sizes):
+        planes.append(O.fv5(inputs.cells_lognormal(nx, ny, 1.0, seed=1000 + seed0 + k)))
+        bs.append(inputs.load_uniform(nx, ny, seed=2000 + seed0 + k))
+    return planes, bs
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batched_fp64_equals_single_problem_solves(use_graph):
+    sizes = [(65, 65), (129, 129), (33, 33), (97, 65), (129, 129), (65, 129)]
+    planes, bs = batch_case(sizes)
+    bh = HB.BatchHierarchy([g(p) for p in planes], use_graph=use_graph)
+    us, infos = bh.solve([g(b) for b in bs], tol=1e-10)
+    for k in range(len(sizes)):
+        single = HB.Hierarchy(g(planes[k]))
+        u1, info1 = single.solve(g(bs[k]), tol=1e-10)
+        assert infos[k].cycles == info1.cycles, (k, infos[k].cycles, info1.cycles)
+        assert torch.equal(us[k], u1), k
+        rr = oracle_relres(planes[k], bs[k], c(us[k]))
+        assert rr <= 1.2e-10, (k, rr)
+
+
+def test_batched_mixed_precision_reaches_fp64_residual():
+    sizes = [(129, 129), (65, 65), (257, 257), (33, 33)]
+    planes, bs = batch_case(sizes, seed0=50)
+    bh = HB.BatchHierarchy([g(p) for p in planes], precision=HB.MIXED)
+    us, infos = bh.solve([g(b) for b in bs], tol=1e-10)
+    for k in range(len(sizes)):
+        rr = oracle_relres(planes[k], bs[k], c(us[k]))
+        assert rr <= 1.2e-10, (k, rr)
+        assert infos[k].outer_steps >= 1
+        single = HB.Hierarchy(g(planes[k]), precision=HB.MIXED)
+        u1, info1 = single.solve(g(bs[k]), tol=1e-10)
+        assert infos[k].outer_steps == info1.outer_steps, k
+        assert rel(c(us[k]), c(u1)) <= 1e-9, k
+
+
+def test_batched_zero_rhs_and_retirement():
+    sizes = [(65, 65), (33, 33), (65, 65)]
+    planes, bs = batch_case(sizes, seed0=80)
+    bs[1] = np.zeros_like(bs[1])
+    bh = HB.BatchHierarchy([g(p) for p in planes])
+    u0 = [torch.randn((s[1], s[0]), dtype=torch.float64, device=DEV) for s in sizes]
+    us, infos = bh.solve([g(b) for b in bs], [x.clone() for x in u0], tol=1e-10)
+    assert torch.count_nonzero(us[1]) == 0 and infos[1].cycles == 0
+    for k in (0, 2):
+        assert oracle_relres(planes[k], bs[k], c(us[k])) <= 1.2e-10
