@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles timed for the baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--collapse-level", type=int, default=-1)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip timing each forced collapse level against the model")
     args = ap.parse_args()
@@ -172,6 +174,47 @@ def main():
                                                   / res["fp64_u"].abs().max())
         del res["mixed_u"], res["fp64_u"]
         extra["checkerboard"] = res
+
+    if not args.no_batch:
+        # many independent problems of different sizes in one batched solve:
+        # sizes from {129, 257, 513, 1025}^2, per-cell lognormal D (sigma 1),
+        # FP32 V-cycles inside FP64 refinement, one cycle replayed as a graph
+        log("bench: batched workload (%d problems)" % args.batch)
+        sizes = inputs.batch_sizes(args.batch, seed=5)
+        cs, bs = [], []
+        for i, m in enumerate(sizes):
+            Di = torch.from_numpy(inputs.cells_lognormal(m, m, 1.0, seed=1000 + i)).to(dev)
+            cs.append(HB.fv5_from_cells(Di))
+            bs.append(torch.from_numpy(inputs.load_uniform(m, m, seed=2000 + i)).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bh = HB.BatchHierarchy(cs, precision=HB.MIXED)
+        t_setup = time.perf_counter() - t0
+        us = [torch.zeros_like(x) for x in bs]
+        bh.solve(bs, us, tol=TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for x in us:
+                x.zero_()
+            us, infos_b = bh.solve(bs, us, tol=TOL)
+        torch.cuda.synchronize()
+        el_b = time.perf_counter() - t0
+        npts = sum(m * m for m in sizes)
+        extra["batched"] = {
+            "workload": "%d problems, n from {129,257,513,1025} (seed 5), lognormal D sigma=1, "
+                        "FP32 V(2,1) inside FP64 refinement to rel. residual 1e-10" % args.batch,
+            "problems_per_s": args.steps * args.batch / el_b,
+            "ms_per_batch": 1e3 * el_b / args.steps,
+            "points": npts,
+            "setup_s": t_setup,
+            "max_relres": max(i.relres for i in infos_b),
+            "fp32_cycles_max": max(i.cycles for i in infos_b),
+            "refinement_steps_max": max(i.outer_steps for i in infos_b),
+        }
+        log("bench: batched %.1f problems/s (%.2f ms per batch)" % (args.steps * args.batch / el_b,
+                                                                   1e3 * el_b / args.steps))
+        del bh, cs, bs, us
 
     cpu = None
     if not args.no_cpu:
