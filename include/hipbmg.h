@@ -91,6 +91,10 @@ typedef struct {
     double setup_ms;         /* wall time of hipbmg_setup                                   */
     double solve_ms;         /* wall time of the solve call                                 */
     double relres_hist[HIPBMG_MAX_HIST]; /* relres after each cycle (mixed: each step)     */
+    int rb_down[HIPBMG_MAX_LEVELS]; /* row-pair steps per tile, pre-relaxation kernels, level l */
+    int rb_up[HIPBMG_MAX_LEVELS];   /* row-pair steps per tile, interpolation kernels, level l  */
+    int rb_pipelined;        /* row-pair steps per tile of the pipelined finest kernel, 0 if */
+                             /* the finest level is not pipelined                            */
 } hipbmg_info;
 
 /* Fill *p with the defaults above. */
@@ -204,7 +208,9 @@ hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double
  * one kernel index (0 relax, 1 relax from zero, 2 relax + residual +
  * restriction, 3 the same from zero, 4 interpolate + relax, 5 the same + norm,
  * 6 relax + norm, 7 two relaxations + residual + restriction in one pass,
- * 8 the same from zero), the summed duration, the number of launches and the
+ * 8 the same from zero, 9 interpolate + relax + norm followed by the next
+ * cycle's two relaxations + residual + restriction in one pass), the summed
+ * duration, the number of launches and the
  * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
 hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);
 hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,

@@ -19,6 +19,10 @@ HIP_SOURCES = ["bmg_stream.hip", "bmg_setup.hip", "bmg_collapse.hip", "bmg_misc.
 CXX_SOURCES = ["bmg_model.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INC,
+             # fuse a*b+c only within one source expression: every inlined or
+             # peeled copy of a step then rounds alike, so results do not
+             # depend on the tiling
+             "-ffp-contract=on",
              # no packed-FP32 instructions (v_pk_*_f32) in device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

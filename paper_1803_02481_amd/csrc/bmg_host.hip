@@ -86,9 +86,14 @@ struct hipbmg_hier {
     int lstar = 0;
     double model_us[HIPBMG_MAX_LEVELS] = {};
     double setup_ms = 0.0;
-    std::vector<int> rb;        // row-block steps per level for the streaming kernels
+    std::vector<int> rb;        // row-block steps per level, pre-relaxation (down) kernels
+    std::vector<int> rb_up;     // row-block steps per level, interpolation (up) kernels
     int no_lds = 0;             // HIPBMG_NO_LDS=1: keep collapsed levels in global memory
     int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
+    int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
+    int rb3 = 0;                // row-block steps of the pipelined finest kernel
+    double *x3_64 = nullptr, *q2_64 = nullptr;   // third iterate, second r/C buffer of the finest level
+    float *x3_32 = nullptr, *q2_32 = nullptr;
     // live timing of the finest-level streaming kernels (HIP events on the solve stream)
     int prof_on = 0;
     int prof_n = 0;                       // event pairs recorded in the current cycle
@@ -234,16 +239,35 @@ static hipbmg_status factor_coarsest(hipbmg_hier *h, hipStream_t s)
 // prologue, short blocks give small levels enough waves
 static int pick_rb(int nx, int ny, int npt)
 {
-    if (const char *e = std::getenv("HIPBMG_RB")) {   // fixed row-block length (tuning)
-        int v = std::atoi(e);
-        if (v >= 1 && v <= 4096) return v;
-    }
     int nst, nbl, nt, g;
     for (int rb : {64, 32, 16, 8, 4}) {
         stream_geometry(nx, ny, npt, SV_SWEEP_RQ, rb, &nst, &nbl, &nt, &g);
         if (nt >= 1024) return rb;
     }
     return 4;
+}
+
+// Row-block length by residency rounds: a launch of `nt` one-wave workgroups
+// on a device that holds `resident` of them at once takes ceil(nt/resident)
+// rounds of (steps per tile) row-pair steps each.  The length that minimises
+// that product wins; ties go to the longer block (fewer re-read prologue rows).
+static int pick_rb_rounds(int nx, int ny, int npt, int variant, int resident, int rbmax)
+{
+    const int nsteps = (ny - 1) / 2;
+    const int hi = std::max(4, std::min(rbmax, nsteps));
+    int best = hi;
+    long long bestc = -1;
+    for (int rb = hi; rb >= 4; --rb) {
+        int nst, nbl, nt, g;
+        stream_geometry(nx, ny, npt, variant, rb, &nst, &nbl, &nt, &g);
+        const long long rounds = (nt + resident - 1) / resident;
+        const long long c = rounds * stream_steps_per_tile(variant, rb);
+        if (bestc < 0 || c < bestc) {
+            bestc = c;
+            best = rb;
+        }
+    }
+    return best;
 }
 
 static double now_ms()
@@ -353,19 +377,54 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     }
 
     // streaming geometry and reduction scratch
+    // Each leg's row block from the residency rounds of the kernel that
+    // dominates it (the last pre-relaxation going down, the interpolation
+    // coming up), in the precision the cycles run in.  HIPBMG_RB_MODE=fixed
+    // takes the longest of 64, 32, ... 4 that still gives 1024 tiles.
     h->rb.resize(L);
+    h->rb_up.resize(L);
     size_t np = 4096;
-    for (int l = 0; l < L; ++l) {
-        h->rb[l] = pick_rb(sx[l], sy[l], h->lv[l].npt);
-        if (l == L - 1)
-            if (const char *e = std::getenv("HIPBMG_RB_FINEST")) {   // tuning override
+    {
+        bool fixed = false;
+        if (const char *e = std::getenv("HIPBMG_RB_MODE")) fixed = std::string(e) == "fixed";
+        const int fp32 = prm.precision == HIPBMG_MIXED;
+        for (int l = 0; l < L; ++l) {
+            const int lnpt = h->lv[l].npt;
+            const bool fine = l == L - 1;
+            const int vdn = prm.nu1 >= 2 ? (fine ? SV_SWEEP2_RQ : SV_SWEEP2_RQ_ZX)
+                                         : (fine ? SV_SWEEP_RQ : SV_SWEEP_RQ_ZX);
+            const int vup = fine ? SV_INTERP_NORM : SV_INTERP;
+            const int rdn = fixed ? 0 : stream_resident(lnpt, vdn, fp32);
+            const int rup = fixed ? 0 : stream_resident(lnpt, vup, fp32);
+            h->rb[l] = rdn > 0 ? pick_rb_rounds(sx[l], sy[l], lnpt, vdn, rdn, 256) : pick_rb(sx[l], sy[l], lnpt);
+            h->rb_up[l] = rup > 0 ? pick_rb_rounds(sx[l], sy[l], lnpt, vup, rup, 256) : pick_rb(sx[l], sy[l], lnpt);
+            if (const char *e = std::getenv("HIPBMG_RB")) {   // one fixed length everywhere (tuning)
                 const int v = std::atoi(e);
-                if (v >= 1 && v <= 4096) h->rb[l] = v;
+                if (v >= 1 && v <= 4096) h->rb[l] = h->rb_up[l] = v;
             }
+            if (fine)
+                if (const char *e = std::getenv("HIPBMG_RB_FINEST")) {   // tuning override
+                    const int v = std::atoi(e);
+                    if (v >= 1 && v <= 4096) h->rb[l] = h->rb_up[l] = v;
+                }
+            int nst, nbl, nt, g;
+            stream_geometry(sx[l], sy[l], lnpt, SV_INTERP_NORM, h->rb_up[l], &nst, &nbl, &nt, &g);
+            np = std::max(np, (size_t)nt);
+            stream_geometry(sx[l], sy[l], lnpt, SV_SWEEP_NORM, h->rb_up[l], &nst, &nbl, &nt, &g);
+            np = std::max(np, (size_t)nt);
+        }
+    }
+    if (npt == 5) {
+        // pipelined finest kernel: its row block from the residency rounds of
+        // the precision the cycles run in (HIPBMG_RB_FUSED3 overrides)
+        const int resident = stream_resident(5, SV_FUSED3, prm.precision == HIPBMG_MIXED);
+        h->rb3 = resident > 0 ? pick_rb_rounds(nx, ny, 5, SV_FUSED3, resident, 256) : h->rb[L - 1];
+        if (const char *e = std::getenv("HIPBMG_RB_FUSED3")) {
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 4096) h->rb3 = v;
+        }
         int nst, nbl, nt, g;
-        stream_geometry(sx[l], sy[l], h->lv[l].npt, SV_INTERP_NORM, h->rb[l], &nst, &nbl, &nt, &g);
-        np = std::max(np, (size_t)nt);
-        stream_geometry(sx[l], sy[l], h->lv[l].npt, SV_SWEEP_NORM, h->rb[l], &nst, &nbl, &nt, &g);
+        stream_geometry(sx[L - 1], sy[L - 1], npt, SV_FUSED3, h->rb3, &nst, &nbl, &nt, &g);
         np = std::max(np, (size_t)nt);
     }
     np = std::max(np, (size_t)((nx + 255) / 256) * ny);   // refinement residual partials
@@ -377,6 +436,23 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
 
+    // finest level pipelined across cycles (5-point finest, V(2,1), finest
+    // level not collapsed); HIPBMG_NO_FUSE3=1 disables it
+    {
+        int nof3 = 0;
+        if (const char *e = std::getenv("HIPBMG_NO_FUSE3")) nof3 = std::atoi(e);
+        h->fused3 = (!nof3 && !h->no_fuse2 && npt == 5 && prm.nu1 == 2 && prm.nu2 == 1 && L >= 2) ? 1 : 0;
+        if (h->fused3) {
+            const LevelDev<double> &F = h->lv[L - 1];
+            st = dalloc(h, &h->x3_64, F.plane, s);
+            if (st == HIPBMG_OK) st = dalloc(h, &h->q2_64, F.plane, s);
+            if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) {
+                st = dalloc(h, &h->x3_32, F.plane, s);
+                if (st == HIPBMG_OK) st = dalloc(h, &h->q2_32, F.plane, s);
+            }
+            if (st != HIPBMG_OK) return bail(st);
+        }
+    }
     // collapse level from the performance model (sections 3 and 4)
     ModelLevel ml[HIPBMG_MAX_LEVELS];
     for (int l = 0; l < L; ++l) {
@@ -390,6 +466,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc,
                             prm.precision == HIPBMG_MIXED ? 4 : 8, mp, h->model_us);
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
+    if (h->lstar >= L - 1) h->fused3 = 0;   // the finest level itself is collapsed
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
                                                              hipGetErrorString(hipGetLastError())));
     h->setup_ms = now_ms() - t0;
@@ -452,15 +529,18 @@ static hipError_t run_stream(const LevelDev<T> &A, int variant, StreamArgs<T> a,
 template <typename T>
 static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
                                  const LevelDev<T> *d_lv, int cur, bool zero_start, int *new_cur,
-                                 int *nparts, hipStream_t s)
+                                 int *nparts, hipStream_t s, bool skip_finest = false)
 {
-    const int L = h->L, ls = h->lstar;
+    // skip_finest: run levels L-2..0 only (the finest level's kernels are
+    // issued by the caller); *new_cur then receives the buffer of level L-2's
+    // correction
+    const int L = skip_finest ? h->L - 1 : h->L, ls = h->lstar;
     const int nu1 = h->prm.nu1, nu2 = h->prm.nu2, rc = h->prm.residual_correction;
     int xb_after[HIPBMG_MAX_LEVELS], xres[HIPBMG_MAX_LEVELS];
     hipError_t e = hipSuccess;
     for (int l = L - 1; l > ls; --l) {
         const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
-        const bool fine = l == L - 1;
+        const bool fine = l == h->L - 1;
         int xb = fine ? cur : 0;
         const bool zero = !fine || zero_start;
         // the last two pre-relaxations run as one fused pass unless disabled
@@ -500,7 +580,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         CollapseArgs<T> c{};
         c.levels = d_lv;
         c.top = ls;
-        const bool fine = ls == L - 1;
+        const bool fine = ls == h->L - 1;
         c.xb_top = fine ? cur : 1;
         c.zero_top = fine ? (zero_start ? 1 : 0) : 1;
         c.nu1 = nu1;
@@ -534,13 +614,13 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
     }
     for (int l = ls + 1; l < L; ++l) {
         const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
-        const bool fine = l == L - 1;
+        const bool fine = l == h->L - 1;
         int xb = xb_after[l];
         for (int k = 1; k <= nu2; ++k) {
             const bool first = k == 1, last = k == nu2;
             int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP)
                           : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
-            StreamArgs<T> a = base_args(A, h->rb[l]);
+            StreamArgs<T> a = base_args(A, h->rb_up[l]);
             a.x_in = A.x[xb];
             a.x_out = A.x[1 - xb];
             if (first) {
@@ -572,6 +652,85 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
     return hipSuccess;
 }
 
+template <typename T> static T *&x3_of(hipbmg_hier *h);
+template <> double *&x3_of<double>(hipbmg_hier *h) { return h->x3_64; }
+template <> float *&x3_of<float>(hipbmg_hier *h) { return h->x3_32; }
+template <typename T> static T *&q2_of(hipbmg_hier *h);
+template <> double *&q2_of<double>(hipbmg_hier *h) { return h->q2_64; }
+template <> float *&q2_of<float>(hipbmg_hier *h) { return h->q2_32; }
+
+// V-cycles with the finest level pipelined: after one pass of the two
+// pre-relaxations, every cycle is [coarse levels] + one finest pass that
+// interpolates, post-relaxes (the iterate after this cycle, and its residual
+// norm) and pre-relaxes for the next cycle.  Three iterate buffers and two r/C
+// buffers rotate at the finest level.  `on_norm(k, nparts)` finalises and
+// checks the norm of cycle k and returns 1 to stop, 0 to go on, <0 on error.
+// Returns the buffer with the final iterate in *result.
+template <typename T, typename OnNorm>
+static hipbmg_status run_cycles_fused(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
+                                      const LevelDev<T> *d_lv, int cur, bool zero_start, int max_cycles,
+                                      hipStream_t s, OnNorm on_norm, const T **result, int *cycles_done)
+{
+    const int L = h->L;
+    const LevelDev<T> &F = lv[L - 1], &Cl = lv[L - 2];
+    T *xb[3] = {F.x[cur], F.x[1 - cur], x3_of<T>(h)};
+    T *qb[2] = {F.q, q2_of<T>(h)};
+    // pre-relaxations of cycle 1 (and the restriction of its residual)
+    {
+        StreamArgs<T> a = base_args(F, h->rb[L - 1]);
+        a.x_in = xb[0];
+        a.x_out = xb[1];
+        a.q_out = qb[0];
+        a.bc = Cl.b;
+        a.wt = F.wt;
+        a.cnx = Cl.nx;
+        a.cny = Cl.ny;
+        a.cpitch = Cl.pitch;
+        a.cplane = (long long)Cl.plane;
+        HIPCHK(run_stream(F, zero_start ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ, a, s));
+    }
+    int i = 1, qa = 0, k = 0;
+    *result = xb[0];
+    while (k < max_cycles) {
+        int cc = 0, dummy = 0;
+        hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, 0, false, &cc, &dummy, s, true);
+        if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
+        StreamArgs<T> a = base_args(F, h->rb3);
+        a.x_in = xb[i];
+        a.x_out = xb[(i + 1) % 3];
+        a.x_out2 = xb[(i + 2) % 3];
+        a.xc = Cl.x[cc];
+        a.wt = F.wt;
+        a.q_in = qb[qa];
+        a.rescorr = h->prm.residual_correction;
+        a.q_out = qb[1 - qa];
+        a.bc = Cl.b;
+        a.cnx = Cl.nx;
+        a.cny = Cl.ny;
+        a.cpitch = Cl.pitch;
+        a.cplane = (long long)Cl.plane;
+        a.partials = h->d_partials;
+        int nt = 0;
+        const int pk = (h->prof_on && h->prof_n < 64) ? h->prof_n++ : -1;
+        if (pk >= 0) {
+            h->prof_var[pk] = SV_FUSED3;
+            h->prof_prec[pk] = PrecIdx<T>::v;
+            (void)hipEventRecord(h->ev0[pk], s);
+        }
+        HIPCHK(run_stream(F, SV_FUSED3, a, s, &nt));
+        if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+        ++k;
+        *result = xb[(i + 1) % 3];
+        const int r = on_norm(k, nt);
+        if (r < 0) return HIPBMG_EHIP;
+        if (r > 0) break;
+        i = (i + 2) % 3;
+        qa = 1 - qa;
+    }
+    *cycles_done = k;
+    return HIPBMG_OK;
+}
+
 static hipbmg_status read_scalars(hipbmg_hier *h, int first, int n, hipStream_t s)
 {
     HIPCHK(hipMemcpyAsync(h->h_scal + first, h->d_scal + first, n * sizeof(double),
@@ -585,17 +744,59 @@ static void fill_info_common(hipbmg_hier *h, hipbmg_info *info)
     if (!info) return;
     info->levels = h->L;
     info->collapse_level = h->lstar;
-    for (int l = 0; l < HIPBMG_MAX_LEVELS; ++l) info->model_us[l] = l < h->L ? h->model_us[l] : 0.0;
+    for (int l = 0; l < HIPBMG_MAX_LEVELS; ++l) {
+        info->model_us[l] = l < h->L ? h->model_us[l] : 0.0;
+        info->rb_down[l] = l < h->L ? h->rb[l] : 0;
+        info->rb_up[l] = l < h->L ? h->rb_up[l] : 0;
+    }
+    info->rb_pipelined = h->fused3 ? h->rb3 : 0;
     info->setup_ms = h->setup_ms;
 }
 
 static hipbmg_status solve_fp64(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
-                                int *cur_out)
+                                int *cur_out, const double **res_out)
 {
     const LevelDev<double> &F = h->lv[h->L - 1];
     int cur = 0, cycles = 0;
     double rel = 1.0;
     hipbmg_status st = HIPBMG_ENOCONV;
+    *res_out = nullptr;
+    if (h->fused3) {
+        hipbmg_status err = HIPBMG_OK;
+        auto on_norm = [&](int k, int np) -> int {
+            if (launch_finalize_norm(h->d_partials, np, h->d_scal, h->d_scal + 1, s) != hipSuccess) {
+                err = fail(HIPBMG_EHIP, "norm launch failed");
+                return -1;
+            }
+            if ((err = read_scalars(h, 1, 1, s)) != HIPBMG_OK) return -1;
+            prof_collect(h);
+            rel = h->h_scal[1];
+            if (info && k - 1 < HIPBMG_MAX_HIST) info->relres_hist[k - 1] = rel;
+            if (!std::isfinite(rel)) {
+                st = HIPBMG_ENAN;
+                return 1;
+            }
+            if (rel <= tol) {
+                st = HIPBMG_OK;
+                return 1;
+            }
+            return 0;
+        };
+        const double *res = nullptr;
+        hipbmg_status r = run_cycles_fused<double>(h, h->lv, h->d_lv, 0, false, h->prm.max_cycles, s, on_norm,
+                                                   &res, &cycles);
+        if (r != HIPBMG_OK) return err != HIPBMG_OK ? err : r;
+        *res_out = res;
+        if (info) {
+            info->cycles = cycles;
+            info->outer_steps = cycles;
+            info->relres = rel;
+        }
+        if (st == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "residual norm is not finite after cycle %d", cycles);
+        if (st == HIPBMG_ENOCONV)
+            return fail(HIPBMG_ENOCONV, "relres %.3e > tol %.3e after %d cycles", rel, tol, cycles);
+        return HIPBMG_OK;
+    }
     while (cycles < h->prm.max_cycles) {
         int nc, np = 0;
         hipError_t e = enqueue_vcycle<double>(h, h->lv, h->d_lv, cur, false, &nc, &np, s);
@@ -665,6 +866,27 @@ static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipb
         HIPCHK(hipMemcpyAsync(h->d_scal + 4, h->h_scal + 4, sizeof(double), hipMemcpyHostToDevice, s));
         int cur = 0;
         bool zero = true;
+        if (h->fused3) {
+            hipbmg_status err = HIPBMG_OK;
+            const int cap = std::min(h->prm.inner_max_cycles, h->prm.max_cycles - cycles);
+            auto on_norm = [&](int, int np) -> int {
+                if (launch_finalize_norm(h->d_partials, np, h->d_scal + 4, h->d_scal + 3, s) != hipSuccess) {
+                    err = fail(HIPBMG_EHIP, "norm launch failed");
+                    return -1;
+                }
+                if ((err = read_scalars(h, 3, 1, s)) != HIPBMG_OK) return -1;
+                prof_collect(h);
+                const double irel = h->h_scal[3];
+                return (!std::isfinite(irel) || irel <= h->prm.inner_tol) ? 1 : 0;
+            };
+            const float *e32 = nullptr;
+            int done = 0;
+            hipbmg_status r = run_cycles_fused<float>(h, h->lv32, h->d_lv32, 0, true, cap, s, on_norm, &e32, &done);
+            if (r != HIPBMG_OK) return err != HIPBMG_OK ? err : r;
+            cycles += done;
+            HIPCHK(launch_ir_update(F.x[0], F.pitch, e32, F32.pitch, F.nx, F.ny, s));
+            continue;
+        }
         for (int k = 0; k < h->prm.inner_max_cycles && cycles < h->prm.max_cycles; ++k) {
             int nc, npp = 0;
             hipError_t e = enqueue_vcycle<float>(h, h->lv32, h->d_lv32, cur, zero, &nc, &npp, s);
@@ -726,11 +948,13 @@ extern "C" hipbmg_status hipbmg_solve(hipbmg_handle h, const double *b, double *
         return HIPBMG_OK;
     }
     int cur = 0;
+    const double *res = nullptr;
     hipbmg_status st = h->prm.precision == HIPBMG_MIXED ? solve_mixed(h, tol, s, info, &cur)
-                                                         : solve_fp64(h, tol, s, info, &cur);
+                                                         : solve_fp64(h, tol, s, info, &cur, &res);
     if (st != HIPBMG_OK && st != HIPBMG_ENOCONV && st != HIPBMG_ENAN) return st;
     std::string msg = g_err;
-    HIPCHK(hipMemcpy2DAsync(u, nx * sizeof(double), F.x[cur], F.pitch * sizeof(double),
+    if (!res) res = F.x[cur];
+    HIPCHK(hipMemcpy2DAsync(u, nx * sizeof(double), res, F.pitch * sizeof(double),
                             nx * sizeof(double), ny, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     if (info) info->solve_ms = now_ms() - t0;
@@ -848,7 +1072,7 @@ extern "C" hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const d
     STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
     STCHK(to_pitched(A.q, A.pitch, q, A.nx, A.ny, s));
     STCHK(to_pitched(C.x[1], C.pitch, xc, C.nx, C.ny, s));
-    StreamArgs<double> a = base_args(A, h->rb[l]);
+    StreamArgs<double> a = base_args(A, h->rb_up[l]);
     a.x_in = A.x[0];
     a.x_out = A.x[1];
     a.xc = C.x[1];
@@ -938,6 +1162,8 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
             variant == SV_SWEEP2_RQ_ZX)
             per += w + 2.0 * w + 0.25 * w;
         if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
+        // interpolation inputs, the weights once, r/C in and out, coarse rhs, second iterate
+        if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + w + w + 0.25 * w + w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;
@@ -1039,6 +1265,20 @@ const LevelDev<double> *dlevels_of<double>(hipbmg_hier *h) { return h->d_lv; }
 template <>
 const LevelDev<float> *dlevels_of<float>(hipbmg_hier *h) { return h->d_lv32; }
 
+// Row blocks of the batched launches: the tiles of all problems share the
+// device, so the single-problem residency rounds do not apply; the longest
+// of 64, 32, ... 4 that gives a level 1024 tiles of its own keeps the
+// prologue overhead low.
+template <typename T>
+static int batch_rb(const LevelDev<T> &A)
+{
+    if (const char *e = std::getenv("HIPBMG_RB")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 4096) return v;
+    }
+    return pick_rb(A.nx, A.ny, A.npt);
+}
+
 // Record the launches of one V-cycle of every problem (same order as
 // enqueue_vcycle) and group them into batched stages.
 template <typename T>
@@ -1072,7 +1312,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
                 const bool last = k == nk, zx = zero && k == 1, two = last && nk < nu1;
                 const int v = last ? (two ? (zx ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ) : (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ))
                                    : (zx ? SV_SWEEP_ZX : SV_SWEEP);
-                StreamArgs<T> a = base_args(A, h->rb[l]);
+                StreamArgs<T> a = base_args(A, batch_rb(A));
                 a.x_in = A.x[xb];
                 a.x_out = A.x[1 - xb];
                 if (last) {
@@ -1128,7 +1368,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             for (int k = 1; k <= nu2; ++k) {
                 const bool first = k == 1, last = k == nu2;
                 const int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP) : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
-                StreamArgs<T> a = base_args(A, h->rb[l]);
+                StreamArgs<T> a = base_args(A, batch_rb(A));
                 a.x_in = A.x[xb];
                 a.x_out = A.x[1 - xb];
                 if (first) {
@@ -1439,6 +1679,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         if (infos) {
             memset(&infos[p], 0, sizeof(hipbmg_info));
             fill_info_common(h, &infos[p]);
+            for (int l = 0; l < h->L; ++l) infos[p].rb_down[l] = infos[p].rb_up[l] = batch_rb(h->lv[l]);
+            infos[p].rb_pipelined = 0;
         }
     }
     const int maxn = std::max(B->max_nx, B->max_ny);

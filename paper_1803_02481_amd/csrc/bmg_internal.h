@@ -39,6 +39,7 @@ struct StreamArgs {
     const T *C, *W, *S, *SW, *SE, *b;
     const T *x_in;
     T *x_out;
+    T *x_out2;           // SV_FUSED3: the iterate after the next pre-relaxations
     // interpolate-and-correct on load (up-leg)
     const T *xc, *wt, *q_in;
     int cnx, cny, cpitch;
@@ -61,7 +62,9 @@ enum StreamVariant {
     SV_SWEEP_NORM = 6,   // relaxation plus residual norm partials
     SV_SWEEP2_RQ = 7,    // two relaxations, residual -> q, restriction -> bc
     SV_SWEEP2_RQ_ZX = 8, // the same from x = 0
-    SV_COUNT = 9
+    SV_FUSED3 = 9,       // 5-point finest level: interpolate + relax (-> x_out, norm), then
+                         // two relaxations (-> x_out2), residual -> q, restriction -> bc
+    SV_COUNT = 10
 };
 
 // Owned column pairs per strip for a variant (64 lanes minus halo lanes).
@@ -69,6 +72,12 @@ int stream_owned_pairs(int npt, int variant);
 // Launch geometry for a level.
 void stream_geometry(int nx, int ny, int npt, int variant, int rb, int *nstrips, int *nblocks,
                      int *ntiles, int *grid);
+// workgroups of a single-problem streaming kernel (one 64-lane wave each) that
+// the device holds at once (compute units x occupancy); 0 if unknown
+int stream_resident(int npt, int variant, int fp32);
+// row-pair steps one tile of the variant walks for a row block of rb steps
+// (its own rb plus the prologue that rebuilds the state below the block)
+int stream_steps_per_tile(int variant, int rb);
 template <typename T>
 hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid, hipStream_t s);
 // one launch over many problems: map[w] = (problem, tile), args[problem]

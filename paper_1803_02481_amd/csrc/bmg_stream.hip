@@ -59,6 +59,12 @@ __device__ __forceinline__ void st2(T *__restrict__ p, T a, T b)
 template <typename T> __device__ __forceinline__ T fromL(T v) { return __shfl_up(v, 1, 64); }
 template <typename T> __device__ __forceinline__ T fromR(T v) { return __shfl_down(v, 1, 64); }
 
+__device__ __forceinline__ int xcd_tile_fn()
+{
+    const int per = gridDim.x >> 3;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
 // One row of the lane's column pair.  The c*/w*/q* fields hold the raw inputs
 // of the interpolate-and-correct step until the row is finished.
 template <typename T>
@@ -451,6 +457,140 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
     }
 }
 
+// The finest level's post-relaxation of cycle k and both pre-relaxations of
+// cycle k+1 in ONE pass (5-point operators): stage P interpolates and corrects
+// each loaded row (x_in + P x_c + q_in), relaxes it, stores the result in
+// x_out (the iterate after cycle k) and accumulates its residual norm (the
+// convergence test of cycle k); stage A relaxes P's final rows; stage B
+// relaxes A's final rows, stores them in x_out2 and forms the residual, q_out
+// = r/C and the restriction b_c of cycle k+1.  Each stage lags the previous one
+// by one row-pair step.  Per column, the lanes whose results are exact shrink
+// by one per stage, so 4 halo lanes are needed on each side; a row block
+// starts with four P, three A and two B prologue steps.
+template <typename T>
+__device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int tile)
+{
+    constexpr int NPT = 5;
+    constexpr int HL = 4, HR = 4, OWN = 64 - HL - HR;
+    const int strip = tile % a.nstrips;
+    const int blk = tile / a.nstrips;
+    const int lane = threadIdx.x;
+    const int t = strip * OWN + lane - HL;
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = t >= 0 && t < a.cnx;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+
+    // issue the loads of row j (no use of the loaded values: they stay in
+    // flight while the previous rows are being computed)
+    auto load_raw = [&](Row<T> &r, int j) {
+        const bool rv = colv && j >= 0 && j < ny;
+        r = Row<T>{};
+        if (rv) {
+            const size_t off = (size_t)j * pitch + e;
+            if (!false) ld2(a.x_in + off, r.x0, r.x1);
+            ld2(a.b + off, r.b0, r.b1);
+            ld2(a.C + off, r.C0, r.C1);
+            ld2(a.W + off, r.W0, r.W1);
+            ld2(a.S + off, r.S0, r.S1);
+            if (NPT == 9) {
+                ld2(a.SW + off, r.SW0, r.SW1);
+                ld2(a.SE + off, r.SE0, r.SE1);
+            }
+        }
+        if (true) {
+            const bool rin = j >= 1 && j <= ny - 2;
+            if (cv && rin) {
+                const int jc = j >> 1;
+                const size_t co = (size_t)jc * a.cpitch + t;
+                const T *wt = a.wt;
+                const long long cp = a.cplane;
+                r.ca = a.xc[co];
+                if (j & 1) {
+                    r.cu = a.xc[co + a.cpitch];
+                    r.w0 = wt[WYB * cp + co];
+                    r.w1 = wt[WYT * cp + co];
+                    r.w2 = wt[WCSW * cp + co];
+                    r.w3 = wt[WCSE * cp + co];
+                    r.w4 = wt[WCNW * cp + co];
+                    r.w5 = wt[WCNE * cp + co];
+                } else {
+                    r.w0 = wt[WXL * cp + co];
+                    r.w1 = wt[WXR * cp + co];
+                }
+                if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, r.q0, r.q1);
+            }
+        }
+    };
+    // x += P x_c (+ r/C at fine-only vertices) on a loaded row; coarse column t
+    auto finish_row = [&](Row<T> &r, int j) {
+        if (true) {
+            const bool rin = j >= 1 && j <= ny - 2;
+            if ((j & 1) == 0) {
+                const T xb = fromR(r.ca);
+                if (rin && ie) r.x0 += r.ca;
+                if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + r.q1;
+            } else {
+                const T xb = fromR(r.ca), xd = fromR(r.cu);
+                if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + r.q0;
+                if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + r.q1;
+            }
+        }
+    };
+
+    const int nsteps = (ny - 1) / 2;
+    const int s0 = blk * a.rb;
+    const int s1 = min(s0 + a.rb, nsteps);
+    const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+
+    StreamArgs<T> aB = a;          // stage B stores the next cycle's iterate and r/C
+    aB.x_out = a.x_out2;
+    Stage<T> P{}, A{}, B{};
+    load_raw(P.rm1, jfirst - 9);
+    finish_row(P.rm1, jfirst - 9);
+    for (int jp = jfirst - 8; jp <= jlast + 4; jp += 2) {
+        load_raw(P.r0, jp);
+        load_raw(P.rp1, jp + 1);
+        finish_row(P.r0, jp);
+        finish_row(P.rp1, jp + 1);
+        const int modeP = jp == jfirst - 8 ? 0 : (jp >= jfirst && jp <= jlast ? 2 : 1);
+        stage_step<T, NPT, true, true, false, true>(P, jp, modeP, L, a);
+        const int ja = jp - 2;
+        if (ja >= jfirst - 6) {
+            if (ja == jfirst - 6) A.rm1 = P.rm3;   // P-final row ja-1
+            A.r0 = P.rm2;
+            A.rp1 = P.rm1;
+            stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
+            const int jb = ja - 2;
+            if (jb >= jfirst - 4) {
+                if (jb == jfirst - 4) B.rm1 = A.rm3;
+                B.r0 = A.rm2;
+                B.rp1 = A.rm1;
+                const int modeB = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
+                stage_step<T, NPT, true, true, true, false>(B, jb, modeB, L, aB);
+                stage_rotate(B);
+            }
+            stage_rotate(A);
+        }
+        stage_rotate(P);
+    }
+    double acc = P.acc;
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) a.partials[tile] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
+{
+    const int tile = xcd_tile_fn();
+    if (tile >= a.ntiles) return;
+    stream3_tile<T>(a, tile);
+}
+
 // XCD-aware tile order: WG i runs on XCD i mod 8, so consecutive tiles (the
 // neighbouring strips of a row band) are given to the same XCD
 __device__ __forceinline__ int xcd_tile()
@@ -497,6 +637,7 @@ __global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__re
 
 int stream_owned_pairs(int npt, int variant)
 {
+    if (variant == SV_FUSED3) return 56;
     if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX)
         return 64 - (1 + (npt == 9)) - halo_left(npt, 1) - (1 + (npt == 9)) - halo_right(npt, 0);
     int res = (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_INTERP_NORM ||
@@ -531,9 +672,63 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_SWEEP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_NORM>), g, b, 0, s, a); break;
     case SV_SWEEP2_RQ: hipLaunchKernelGGL((k_stream2<T, NPT, false>), g, b, 0, s, a); break;
     case SV_SWEEP2_RQ_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true>), g, b, 0, s, a); break;
+    case SV_FUSED3:
+        if (NPT != 5) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stream3<T>), g, b, 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// device function of one single-problem streaming variant (nullptr if none)
+template <typename T, int NPT>
+static const void *kernel_of(int variant)
+{
+    switch (variant) {
+    case SV_SWEEP: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP>);
+    case SV_SWEEP_ZX: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_ZX>);
+    case SV_SWEEP_RQ: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_RQ>);
+    case SV_SWEEP_RQ_ZX: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_RQ_ZX>);
+    case SV_INTERP: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_INTERP>);
+    case SV_INTERP_NORM: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_INTERP_NORM>);
+    case SV_SWEEP_NORM: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_NORM>);
+    case SV_SWEEP2_RQ: return reinterpret_cast<const void *>(&k_stream2<T, NPT, false>);
+    case SV_SWEEP2_RQ_ZX: return reinterpret_cast<const void *>(&k_stream2<T, NPT, true>);
+    case SV_FUSED3: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T>) : nullptr;
+    default: return nullptr;
+    }
+}
+
+int stream_resident(int npt, int variant, int fp32)
+{
+    const void *k = nullptr;
+    if (fp32)
+        k = npt == 9 ? kernel_of<float, 9>(variant) : kernel_of<float, 5>(variant);
+    else
+        k = npt == 9 ? kernel_of<double, 9>(variant) : kernel_of<double, 5>(variant);
+    int dev = 0, ncu = 0, per = 0;
+    if (!k || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return ncu * per;
+}
+
+int stream_steps_per_tile(int variant, int rb)
+{
+    switch (variant) {
+    case SV_FUSED3: return rb + 6;
+    case SV_SWEEP2_RQ:
+    case SV_SWEEP2_RQ_ZX: return rb + 4;
+    case SV_SWEEP_RQ:
+    case SV_SWEEP_RQ_ZX:
+    case SV_INTERP_NORM:
+    case SV_SWEEP_NORM: return rb + 2;
+    default: return rb + 1;
+    }
 }
 
 template <typename T>

@@ -32,7 +32,9 @@ class Info(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("outer_steps", ctypes.c_int), ("relres", ctypes.c_double),
                 ("levels", ctypes.c_int), ("collapse_level", ctypes.c_int),
                 ("model_us", ctypes.c_double * MAX_LEVELS), ("setup_ms", ctypes.c_double),
-                ("solve_ms", ctypes.c_double), ("relres_hist", ctypes.c_double * MAX_HIST)]
+                ("solve_ms", ctypes.c_double), ("relres_hist", ctypes.c_double * MAX_HIST),
+                ("rb_down", ctypes.c_int * MAX_LEVELS), ("rb_up", ctypes.c_int * MAX_LEVELS),
+                ("rb_pipelined", ctypes.c_int)]
 
     def history(self):
         n = self.outer_steps if self.outer_steps else self.cycles
@@ -180,7 +182,7 @@ class Hierarchy:
         _check(lib().hipbmg_profile(self._h, 1 if enable else 0))
 
     KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
-               "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero")
+               "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero", "fused3")
 
     def profile_read(self, precision=0):
         """{kernel name: (total_ms, launches, bytes_per_launch)} for launched kernels."""

@@ -447,7 +447,14 @@ def test_zero_rhs_gives_zero_and_boundary_is_ignored():
     assert torch.count_nonzero(ua[0]) == 0 and torch.count_nonzero(ua[:, -1]) == 0
 
 
-def test_deterministic_and_resumable():
+@pytest.mark.parametrize("pipelined", ["0", "1"])
+def test_deterministic_and_resumable(pipelined, monkeypatch):
+    # with the finest level pipelined, a resumed solve runs its first
+    # pre-relaxations in the stand-alone two-sweep kernel instead of inside the
+    # fused finest pass: the same expressions, contracted alike (fused
+    # multiply-adds only within one expression), so the iterate is bitwise
+    # the same
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
     n = 129
     planes = g(O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=5)))
     b = g(inputs.load_uniform(n, n, seed=6))
@@ -460,6 +467,9 @@ def test_deterministic_and_resumable():
     u3, _ = h3.solve(b, tol=1e-30, check=False)
     u33, _ = h3.solve(b, u3.clone(), tol=1e-30, check=False)
     u6, _ = h6.solve(b, tol=1e-30, check=False)
+    d = rel(c(u33), c(u6))
+    print("resume difference (pipelined %s): %.3e" % (pipelined, d))
+    assert d <= 1e-12, d
     assert torch.equal(u33, u6)
 
 
@@ -472,7 +482,9 @@ def batch_case(sizes, seed0=0):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_batched_fp64_equals_single_problem_solves(use_graph):
+def test_batched_fp64_equals_single_problem_solves(use_graph, monkeypatch):
+    # the batch runs the unpipelined cycle; so does the reference single solve
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "1")
     sizes = [(65, 65), (129, 129), (33, 33), (97, 65), (129, 129), (65, 129)]
     planes, bs = batch_case(sizes)
     bh = HB.BatchHierarchy([g(p) for p in planes], use_graph=use_graph)
@@ -486,7 +498,8 @@ def test_batched_fp64_equals_single_problem_solves(use_graph):
         assert rr <= 1.2e-10, (k, rr)
 
 
-def test_batched_mixed_precision_reaches_fp64_residual():
+def test_batched_mixed_precision_reaches_fp64_residual(monkeypatch):
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "1")
     sizes = [(129, 129), (65, 65), (257, 257), (33, 33)]
     planes, bs = batch_case(sizes, seed0=50)
     bh = HB.BatchHierarchy([g(p) for p in planes], precision=HB.MIXED)
@@ -511,3 +524,113 @@ def test_batched_zero_rhs_and_retirement():
     assert torch.count_nonzero(us[1]) == 0 and infos[1].cycles == 0
     for k in (0, 2):
         assert oracle_relres(planes[k], bs[k], c(us[k])) <= 1.2e-10
+
+
+@pytest.mark.parametrize("n", [129, 257])
+def test_pipelined_finest_level_matches_unpipelined(n, monkeypatch):
+    planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=21))
+    b = inputs.load_uniform(n, n, seed=22)
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "1")
+    u0, i0 = HB.Hierarchy(g(planes)).solve(g(b), tol=1e-10)
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "0")
+    u1, i1 = HB.Hierarchy(g(planes)).solve(g(b), tol=1e-10)
+    assert i0.cycles == i1.cycles
+    print("pipelined vs unpipelined: max rel difference %.3e" % rel(c(u1), c(u0)))
+    h0, h1 = np.array(i0.history()), np.array(i1.history())
+    assert np.all(np.abs(h0 - h1) <= 1e-9 * h0 + 1e-13)
+    assert rel(c(u1), c(u0)) <= 1e-6
+    assert oracle_relres(planes, b, c(u1)) <= 1.2e-10
+    # mixed precision with the pipelined inner cycles
+    u2, i2 = HB.Hierarchy(g(planes), precision=HB.MIXED).solve(g(b), tol=1e-10)
+    assert oracle_relres(planes, b, c(u2)) <= 1.2e-10
+
+
+@pytest.mark.parametrize("pipelined", ["0", "1"])
+def test_row_block_length_does_not_change_the_iterate(pipelined, monkeypatch):
+    # each vertex is relaxed, restricted and interpolated by the same arithmetic
+    # whatever row block its tile covers; only the order of the residual norm's
+    # partial sums depends on the tiling.  The collapse level is fixed: the
+    # model's choice of it depends on the row blocks
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
+    nx, ny = 257, 225
+    planes = g(O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=31)))
+    b = g(inputs.load_uniform(nx, ny, seed=32))
+
+    def run(env):
+        for k in ("HIPBMG_RB", "HIPBMG_RB_FUSED3", "HIPBMG_RB_MODE"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        return HB.Hierarchy(planes, max_cycles=5, collapse_level=1).solve(b, tol=1e-30, check=False)
+
+    u0, i0 = run({})
+    h0 = np.array(i0.history())
+    for env in ({"HIPBMG_RB_MODE": "fixed"}, {"HIPBMG_RB": "1"}, {"HIPBMG_RB": "5"}, {"HIPBMG_RB": "13"},
+                {"HIPBMG_RB": "300"}, {"HIPBMG_RB_FUSED3": "1"}, {"HIPBMG_RB_FUSED3": "7"},
+                {"HIPBMG_RB_FUSED3": "150"}):
+        print("row blocks", env, flush=True)
+        u, info = run(env)
+        assert info.cycles == 5
+        d = rel(c(u), c(u0))
+        print("  max rel difference %.3e" % d, flush=True)
+        assert d <= 1e-13, env
+        assert torch.equal(u, u0), env
+        h = np.array(info.history())
+        assert np.all(np.abs(h - h0) <= 1e-12 * h0), env
+        if pipelined == "1" and "HIPBMG_RB_FUSED3" in env:
+            assert info.rb_pipelined == int(env["HIPBMG_RB_FUSED3"])
+        if "HIPBMG_RB" in env:
+            assert all(r == int(env["HIPBMG_RB"]) for r in list(info.rb_down)[: info.levels])
+
+
+@pytest.fixture(scope="module")
+def full_size_case():
+    """The 4097 x 4097 log10-blocks workload (16-cell blocks, D in [1e-2, 1e2])
+    with a uniform random load, and the oracle's hierarchy of it."""
+    n = 4097
+    planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, -2.0, 2.0, seed=1))
+    b = inputs.load_uniform(n, n, seed=2)
+    return planes, b, O.Hierarchy(planes)
+
+
+def oracle_relres_full(ora, b, u):
+    r = ora.residual(ora.L - 1, b, u)
+    return float(np.linalg.norm(r[1:-1, 1:-1]) / np.linalg.norm(b[1:-1, 1:-1]))
+
+
+def test_full_size_cycles_match_oracle(full_size_case):
+    # the launch configuration of the timed solves (default parameters: model
+    # collapse level, pipelined finest level, residency-chosen row blocks);
+    # one V-cycle from zero is compared vertex by vertex, the first cycles'
+    # residual norms against the oracle's own cycles
+    planes, b, ora = full_size_case
+    u1, i1 = HB.Hierarchy(g(planes), max_cycles=1).solve(g(b), tol=1e-30, check=False)
+    print("levels %d, collapse level %d, row blocks down %s up %s pipelined %d"
+          % (i1.levels, i1.collapse_level, list(i1.rb_down)[: i1.levels], list(i1.rb_up)[: i1.levels],
+             i1.rb_pipelined), flush=True)
+    v = ora.vcycle(b, np.zeros_like(b))
+    d = rel(c(u1), v)
+    print("one V-cycle: max rel difference %.3e" % d, flush=True)
+    assert d <= 1e-9, d
+    hist_ref = []
+    u = np.zeros_like(b)
+    for _ in range(3):
+        u = ora.vcycle(b, u)
+        hist_ref.append(oracle_relres_full(ora, b, u))
+    u3, i3 = HB.Hierarchy(g(planes), max_cycles=3).solve(g(b), tol=1e-30, check=False)
+    h3 = np.array(i3.history())
+    print("first cycles: gpu %s oracle %s" % (list(h3), hist_ref), flush=True)
+    assert np.all(np.abs(h3 - np.array(hist_ref)) <= 1e-8 * np.array(hist_ref))
+    assert rel(c(u3), u) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_solution_meets_tolerance_by_oracle_residual(full_size_case, precision):
+    planes, b, ora = full_size_case
+    prec = HB.FP64 if precision == "fp64" else HB.MIXED
+    u, info = HB.Hierarchy(g(planes), precision=prec).solve(g(b), tol=1e-10)
+    rr = oracle_relres_full(ora, b, c(u))
+    print("%s: %d cycles, gpu relres %.3e, oracle relres %.3e" % (precision, info.cycles, info.relres, rr),
+          flush=True)
+    assert rr <= 1.2e-10, rr
+    assert info.relres == pytest.approx(rr, rel=0.2)
