@@ -218,17 +218,27 @@ hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,
                                   double *bytes_per_launch_host);
 
 /* Measure the machine parameters of the collapse-level performance model on
- * the current device with micro-kernels, as the paper measures its alpha,
- * beta and gamma (section 3, postal model; section 5, machine parameters from
- * benchmarks): the gap between dependent kernel launches, the latency of one
- * row-pair step of a streaming wave, streaming bandwidth with the
- * relaxation's access mix out of HBM and out of cache, the cost of a
- * workgroup barrier after an L2 and after an LDS access, and one workgroup's
- * bandwidth on L2-resident data.  The values replace the process-wide model
- * parameters used by later hipbmg_setup calls.  out_host (may be NULL)
- * receives 8 doubles: alpha_launch_us, step_us, hbm_GBps, cache_GBps,
- * alpha_bar_us, wg_GBps, alpha_bar_lds_us, 0.  Allocates about 1 GB of
- * device memory for the duration of the call. */
+ * the current device, as the paper measures its alpha, beta and gamma
+ * (section 3, postal model; section 5, machine parameters from benchmarks):
+ * the gap between dependent kernel launches and the streaming bandwidth of the
+ * relaxation's access mix out of HBM and out of cache, with micro-kernels;
+ * then, on a synthetic 257 x 257 hierarchy built and destroyed inside the
+ * call, the solver's own kernels: the row-pair step latency of the down and up
+ * streaming kernels, and per collapsed level the cost of a barrier phase and
+ * the workgroup's inverse bandwidth, fitted separately for levels staged in
+ * LDS and levels left in global memory, in FP64 and FP32.  The values replace
+ * the process-wide model parameters used by later hipbmg_setup calls.
+ * out_host (may be NULL) receives 24 doubles:
+ *   [0] alpha_launch_us  [1] hbm_GBps  [2] cache_GBps
+ *   [3] step_dn_us FP64  [4] step_up_us FP64  [5] step_dn_us FP32  [6] step_up_us FP32
+ *   [7] t_base_us FP64 (collapsed launch holding only the coarsest level)  [8] t_base_us FP32
+ *   [9] alpha_bar_us FP64 LDS  [10] alpha_bar_us FP64 global
+ *   [11] alpha_bar_us FP32 LDS  [12] alpha_bar_us FP32 global
+ *   [13] wg_GBps FP64 LDS  [14] wg_GBps FP64 global  [15] wg_GBps FP32 LDS  [16] wg_GBps FP32 global
+ *   [17] bare LDS barrier us  [18] bare barrier after an L2 access us
+ *   [19] one workgroup's L2 bandwidth GBps  [20] step of a plain relaxation sweep us
+ *   [21..23] 0.
+ * Allocates about 1 GB of device memory for the duration of the call. */
 hipbmg_status hipbmg_calibrate(void *stream, double *out_host);
 
 /* Message for the calling thread's most recent failure ("" if none). */

@@ -1,15 +1,16 @@
-// bmg_calib.hip -- micro-kernels that measure the machine parameters of the
-// collapse-level performance model.  The paper determines gamma by timing a
-// local stencil matrix-vector product and alpha, beta with standard network
-// benchmarks (section 3, postal model and its parameter table); on one GPU the
+// bmg_calib.hip -- measurement of the machine parameters of the collapse-level
+// performance model.  The paper determines gamma by timing a local stencil
+// matrix-vector product and alpha, beta with standard network benchmarks
+// (section 3, postal model and its parameter table); on one GPU the
 // corresponding quantities are measured here:
 //   alpha_launch  gap between two dependent kernels on one stream
-//   step_us       one row-pair step of a streaming relaxation wave
 //   hbm / cache   streaming bandwidth with the relaxation's access mix (five
 //                 arrays read, one written), out of HBM and out of cache
-//   alpha_bar     one workgroup barrier after a dependent L2 access (collapsed
-//                 levels in global memory) or LDS access (levels staged in LDS)
-//   wg            bandwidth one workgroup reaches on L2-resident data
+// and, by timing the solver's own kernels on a synthetic hierarchy
+// (calibrate_on_kernels), the step latencies of the streaming kernels and the
+// barrier-phase and bandwidth terms of collapsed levels.  Micro-kernels for a
+// bare barrier and one workgroup's L2 bandwidth are timed as well, for
+// comparison with the fitted values.
 #include "hipbmg.h"
 #include "bmg_internal.h"
 #include "bmg_model.h"
@@ -139,7 +140,8 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
         p.beta_hbm_us_per_B = 1.0 / (hbm_gbps * 1e3);
         p.beta_cache_us_per_B = 1.0 / (cache_gbps * 1e3);
 
-        // one row-pair step of a streaming wave: one wave, 64 steps
+        // one row-pair step of a plain streaming sweep: one wave, 64 steps
+        double sweep_step_us = 0.0;
         {
             const int nx = 121, ny = 2 * 64 + 1, pitch = 128;
             const size_t plane = (size_t)ny * pitch;
@@ -162,7 +164,7 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
                 int g;
                 stream_geometry(nx, ny, 5, SV_SWEEP, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
                 ms = time_ms(s, e0, e1, 5, [&] { launch_stream<double>(5, SV_SWEEP, a, g, s); });
-                p.step_us = std::max(0.05, (1e3 * ms - p.alpha_launch_us) / (a.rb + 1));
+                sweep_step_us = std::max(0.05, (1e3 * ms - p.alpha_launch_us) / (a.rb + 1));
                 hipStreamSynchronize(s);
                 hipFree(lv);
             } else {
@@ -176,11 +178,11 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
         ms = time_ms(s, e0, e1, 3, [&] {
             hipLaunchKernelGGL((k_barrier<false>), dim3(1), dim3(1024), 0, s, small, iters, out);
         });
-        p.alpha_bar_us = 1e3 * ms / (2.0 * iters);
+        const double bar_glb_us = 1e3 * ms / (2.0 * iters);
         ms = time_ms(s, e0, e1, 3, [&] {
             hipLaunchKernelGGL((k_barrier<true>), dim3(1), dim3(1024), 0, s, small, iters, out);
         });
-        p.alpha_bar_lds_us = 1e3 * ms / (2.0 * iters);
+        const double bar_lds_us = 1e3 * ms / (2.0 * iters);
 
         // one workgroup on L2-resident data
         const long long n2 = (1LL << 18) / 2;   // 2 MB
@@ -188,23 +190,38 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
             hipLaunchKernelGGL(k_wg_stream, dim3(1), dim3(1024), 0, s, reinterpret_cast<double2 *>(small), n2, 4);
         });
         const double wg_gbps = 4.0 * 2.0 * n2 * 16.0 / (ms * 1e-3) / 1e9;
-        p.beta_wg_us_per_B = 1.0 / (wg_gbps * 1e3);
-        p.calibrated = 1;
-        model_params() = p;
+        if (hipStreamSynchronize(s) != hipSuccess) st = HIPBMG_EHIP;
+        hipFree(buf);
+        hipFree(small);
+        buf = small = nullptr;
+        // the step latencies and collapsed-level terms from the solver's own kernels
+        if (st == HIPBMG_OK) st = calibrate_on_kernels(stream, p);
+        if (st == HIPBMG_OK) {
+            p.calibrated = 1;
+            model_params() = p;
+        }
         if (out_host) {
+            for (int k = 0; k < 24; ++k) out_host[k] = 0.0;
             out_host[0] = p.alpha_launch_us;
-            out_host[1] = p.step_us;
-            out_host[2] = hbm_gbps;
-            out_host[3] = cache_gbps;
-            out_host[4] = p.alpha_bar_us;
-            out_host[5] = wg_gbps;
-            out_host[6] = p.alpha_bar_lds_us;
-            out_host[7] = 0.0;
+            out_host[1] = hbm_gbps;
+            out_host[2] = cache_gbps;
+            for (int q = 0; q < 2; ++q) {
+                out_host[3 + 2 * q] = p.step_dn_us[q];
+                out_host[4 + 2 * q] = p.step_up_us[q];
+                out_host[7 + q] = p.t_base_us[q];
+                out_host[9 + 2 * q] = p.alpha_bar_us[q][0];
+                out_host[10 + 2 * q] = p.alpha_bar_us[q][1];
+                out_host[13 + 2 * q] = p.beta_wg_us_per_B[q][0] > 0 ? 1e-3 / p.beta_wg_us_per_B[q][0] : 0.0;
+                out_host[14 + 2 * q] = p.beta_wg_us_per_B[q][1] > 0 ? 1e-3 / p.beta_wg_us_per_B[q][1] : 0.0;
+            }
+            out_host[17] = bar_lds_us;
+            out_host[18] = bar_glb_us;
+            out_host[19] = wg_gbps;
+            out_host[20] = sweep_step_us;
         }
     }
-    if (hipStreamSynchronize(s) != hipSuccess) st = HIPBMG_EHIP;
-    hipFree(buf);
-    hipFree(small);
+    if (buf) hipFree(buf);
+    if (small) hipFree(small);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return st;

@@ -329,6 +329,7 @@ __device__ __forceinline__ void collapse_body(const CollapseArgs<T> &a)
 template <typename T>
 __global__ __launch_bounds__(CWG) void k_collapse(CollapseArgs<T> a)
 {
+    if (a.active && *a.active == 0) return;
     collapse_body(a);
 }
 
@@ -426,6 +427,65 @@ hipError_t launch_finalize_norm(const double *partials, int n, const double *den
                                 hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, n, denom, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_finalize_check(const double *__restrict__ partials, int n,
+                                                        const double *__restrict__ denom, double tol, int k,
+                                                        double *__restrict__ hist, int hist_cap, double *last,
+                                                        int *flags, double *slot)
+{
+    __shared__ double sh[256];
+    if (flags[0] == 0) return;   // an earlier cycle met the test
+    double acc = 0.0;
+    for (int m = threadIdx.x; m < n; m += 256) acc += partials[m];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rel = sqrt(sh[0]) / denom[0];
+        if (k - 1 < hist_cap) hist[k - 1] = rel;
+        last[0] = rel;
+        int run = 1;
+        if (!isfinite(rel)) {
+            run = 0;
+            flags[1] = k;
+            flags[2] = 2;
+        } else if (rel <= tol) {
+            run = 0;
+            flags[1] = k;
+            flags[2] = 1;
+        }
+        flags[0] = run;
+        volatile double *v = slot;
+        v[0] = rel;
+        v[1] = (double)run;
+        v[2] = (double)flags[1];
+        v[3] = (double)k;
+        __threadfence_system();
+    }
+}
+
+hipError_t launch_finalize_check(const double *partials, int n, const double *denom, double tol, int k,
+                                 double *hist, int hist_cap, double *last, int *flags, double *slot,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_check, dim3(1), dim3(256), 0, s, partials, n, denom, tol, k, hist, hist_cap,
+                       last, flags, slot);
+    return hipGetLastError();
+}
+
+__global__ void k_flags_reset(int *flags)
+{
+    if (threadIdx.x < 4) flags[threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+}
+
+hipError_t launch_flags_reset(int *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flags_reset, dim3(1), dim3(64), 0, s, flags);
     return hipGetLastError();
 }
 

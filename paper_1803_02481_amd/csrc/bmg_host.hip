@@ -67,6 +67,9 @@ extern "C" void hipbmg_default_params(hipbmg_params *p)
 // ---------------------------------------------------------------------------
 // hierarchy
 // ---------------------------------------------------------------------------
+constexpr int RING = 8;          // host-mapped convergence-test slots
+constexpr int PROF_RING = 256;   // profiling event pairs in flight
+
 struct hipbmg_hier {
     int L = 0, nx = 0, ny = 0, npt = 5;
     hipbmg_params prm{};
@@ -94,39 +97,78 @@ struct hipbmg_hier {
     int rb3 = 0;                // row-block steps of the pipelined finest kernel
     double *x3_64 = nullptr, *q2_64 = nullptr;   // third iterate, second r/C buffer of the finest level
     float *x3_32 = nullptr, *q2_32 = nullptr;
-    // live timing of the finest-level streaming kernels (HIP events on the solve stream)
+    // device-side stopping: run flag, residual history, and a ring of
+    // host-mapped slots through which the host sees each cycle's test
+    int *d_flags = nullptr;               // [0] run, [1] stopping cycle, [2] reason
+    int h_flags[4] = {};
+    double *d_hist = nullptr;             // relres after each cycle of the current solve
+    double *ring_host = nullptr, *ring_dev = nullptr;   // RING x {relres, run, stop, k}
+    hipEvent_t ring_ev[RING] = {};
+    int ahead = 2;                        // cycles enqueued beyond the last test seen
+    // live timing of the finest-level streaming kernels (HIP events on the
+    // solve stream), kept in a ring and collected in order once complete
     int prof_on = 0;
-    int prof_n = 0;                       // event pairs recorded in the current cycle
-    int prof_var[64];
-    int prof_prec[64];
-    hipEvent_t ev0[64] = {}, ev1[64] = {};
+    long long prof_head = 0, prof_tail = 0;
+    int prof_cycle = 0;                   // cycle being enqueued
+    int prof_var[PROF_RING];
+    int prof_prec[PROF_RING];
+    int prof_cyc[PROF_RING];
+    hipEvent_t ev0[PROF_RING] = {}, ev1[PROF_RING] = {};
     double prof_ms[2][SV_COUNT] = {};
     long long prof_cnt[2][SV_COUNT] = {};
     ~hipbmg_hier()
     {
-        for (int k = 0; k < 64; ++k) {
+        for (int k = 0; k < PROF_RING; ++k) {
             if (ev0[k]) (void)hipEventDestroy(ev0[k]);
             if (ev1[k]) (void)hipEventDestroy(ev1[k]);
         }
+        for (int k = 0; k < RING; ++k)
+            if (ring_ev[k]) (void)hipEventDestroy(ring_ev[k]);
         for (void *p : allocs) (void)hipFree(p);
         if (h_scal) (void)hipHostFree(h_scal);
+        if (ring_host) (void)hipHostFree(ring_host);
     }
 };
 
 template <typename T> struct PrecIdx { enum { v = 0 }; };
 template <> struct PrecIdx<float> { enum { v = 1 }; };
 
-// collect the event pairs of the last cycle (the stream has been synchronised)
-static void prof_collect(hipbmg_hier *h)
+// Record the start of a profiled finest-level launch; returns its ring slot or -1.
+static int prof_begin(hipbmg_hier *h, int variant, int prec, hipStream_t s)
 {
-    for (int k = 0; k < h->prof_n; ++k) {
+    if (!h->prof_on || h->prof_tail - h->prof_head >= PROF_RING) return -1;
+    const int k = (int)(h->prof_tail++ % PROF_RING);
+    h->prof_var[k] = variant;
+    h->prof_prec[k] = prec;
+    h->prof_cyc[k] = h->prof_cycle;
+    (void)hipEventRecord(h->ev0[k], s);
+    return k;
+}
+
+static void prof_end(hipbmg_hier *h, int k, hipStream_t s)
+{
+    if (k >= 0) (void)hipEventRecord(h->ev1[k], s);
+}
+
+// Collect recorded pairs in order: all of them if `wait`, else those already
+// complete.  Pairs of cycles after `last_cycle` (cycles the device skipped
+// once the convergence test was met) are dropped.
+static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30)
+{
+    while (h->prof_head < h->prof_tail) {
+        const int k = (int)(h->prof_head % PROF_RING);
+        if (!wait && hipEventQuery(h->ev1[k]) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h->ev0[k], h->ev1[k]) == hipSuccess) {
+        if (h->prof_cyc[k] <= last_cycle && hipEventElapsedTime(&ms, h->ev0[k], h->ev1[k]) == hipSuccess) {
             h->prof_ms[h->prof_prec[k]][h->prof_var[k]] += ms;
             h->prof_cnt[h->prof_prec[k]][h->prof_var[k]] += 1;
         }
+        (void)hipGetLastError();
+        ++h->prof_head;
     }
-    h->prof_n = 0;
 }
 
 static int pitch_for(int nx) { return (nx + 63) / 64 * 64; }   // >= nx+1 for odd nx
@@ -251,13 +293,71 @@ static int pick_rb(int nx, int ny, int npt)
 // on a device that holds `resident` of them at once takes ceil(nt/resident)
 // rounds of (steps per tile) row-pair steps each.  The length that minimises
 // that product wins; ties go to the longer block (fewer re-read prologue rows).
+// the kernel that dominates a level's down leg (its last pre-relaxation, fused
+// with residual and restriction) and its up leg (the interpolating relaxation)
+static int variant_down(const hipbmg_params &prm, bool fine)
+{
+    return prm.nu1 >= 2 ? (fine ? SV_SWEEP2_RQ : SV_SWEEP2_RQ_ZX) : (fine ? SV_SWEEP_RQ : SV_SWEEP_RQ_ZX);
+}
+static int variant_up(bool fine) { return fine ? SV_INTERP_NORM : SV_INTERP; }
+
+// The model's view of level l: launch geometry of its down and up kernels and
+// whether it is staged in LDS when collapsed (levels fill the LDS budget from
+// the coarsest up, as the collapse launch stages them).
+static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
+{
+    const int L = h->L;
+    size_t used = 0;
+    bool fits = !h->no_lds;
+    for (int l = 0; l < L; ++l) {
+        const LevelDev<double> &A = h->lv[l];
+        const bool fine = l == L - 1;
+        const int nsteps = (A.ny - 1) / 2;
+        ml[l].nx = A.nx;
+        ml[l].ny = A.ny;
+        ml[l].npt = A.npt;
+        const int v[2] = {variant_down(h->prm, fine), variant_up(fine)};
+        const int rb[2] = {h->rb[l], h->rb_up[l]};
+        int steps[2], rounds[2];
+        for (int k = 0; k < 2; ++k) {
+            int nst, nbl, nt, g;
+            stream_geometry(A.nx, A.ny, A.npt, v[k], rb[k], &nst, &nbl, &nt, &g);
+            const int res = stream_resident(A.npt, v[k], fp32);
+            steps[k] = stream_steps_per_tile(v[k], std::min(rb[k], nsteps));
+            rounds[k] = res > 0 ? (nt + res - 1) / res : 1;
+        }
+        ml[l].steps_dn = steps[0];
+        ml[l].rounds_dn = rounds[0];
+        ml[l].steps_up = steps[1];
+        ml[l].rounds_up = rounds[1];
+        const int cnx = l ? h->lv[l - 1].nx : 0, cny = l ? h->lv[l - 1].ny : 0;
+        const size_t bytes = fp32 ? collapse_lds_bytes<float>(A.nx, A.ny, cnx, cny)
+                                  : collapse_lds_bytes<double>(A.nx, A.ny, cnx, cny);
+        fits = fits && used + bytes <= (size_t)COLLAPSE_LDS_BUDGET;
+        if (fits) used += bytes;
+        ml[l].in_lds = fits ? 1 : 0;
+    }
+}
+
+// shortest row block the residency choice may take (HIPBMG_RB_MIN overrides):
+// on levels too small to fill the device a wave's time is its sequential
+// steps, so one-step blocks (each with its own prologue) are the fastest
+static int rb_floor()
+{
+    if (const char *e = std::getenv("HIPBMG_RB_MIN")) {
+        const int k = std::atoi(e);
+        if (k >= 1 && k <= 64) return k;
+    }
+    return 1;
+}
+
 static int pick_rb_rounds(int nx, int ny, int npt, int variant, int resident, int rbmax)
 {
-    const int nsteps = (ny - 1) / 2;
-    const int hi = std::max(4, std::min(rbmax, nsteps));
+    const int nsteps = (ny - 1) / 2, lo = rb_floor();
+    const int hi = std::max(lo, std::min(rbmax, nsteps));
     int best = hi;
     long long bestc = -1;
-    for (int rb = hi; rb >= 4; --rb) {
+    for (int rb = hi; rb >= lo; --rb) {
         int nst, nbl, nt, g;
         stream_geometry(nx, ny, npt, variant, rb, &nst, &nbl, &nt, &g);
         const long long rounds = (nt + resident - 1) / resident;
@@ -391,9 +491,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         for (int l = 0; l < L; ++l) {
             const int lnpt = h->lv[l].npt;
             const bool fine = l == L - 1;
-            const int vdn = prm.nu1 >= 2 ? (fine ? SV_SWEEP2_RQ : SV_SWEEP2_RQ_ZX)
-                                         : (fine ? SV_SWEEP_RQ : SV_SWEEP_RQ_ZX);
-            const int vup = fine ? SV_INTERP_NORM : SV_INTERP;
+            const int vdn = variant_down(prm, fine), vup = variant_up(fine);
             const int rdn = fixed ? 0 : stream_resident(lnpt, vdn, fp32);
             const int rup = fixed ? 0 : stream_resident(lnpt, vup, fp32);
             h->rb[l] = rdn > 0 ? pick_rb_rounds(sx[l], sy[l], lnpt, vdn, rdn, 256) : pick_rb(sx[l], sy[l], lnpt);
@@ -435,6 +533,22 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if (st != HIPBMG_OK) return bail(st);
     if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+    // device-side stopping: run flag, residual history, host-mapped test slots
+    st = dalloc(h, &h->d_flags, 4, s);
+    if (st == HIPBMG_OK) st = dalloc(h, &h->d_hist, HIPBMG_MAX_HIST, s);
+    if (st != HIPBMG_OK) return bail(st);
+    if (hipHostMalloc(&h->ring_host, RING * 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&h->ring_dev, h->ring_host, 0) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "host-mapped allocation failed"));
+    for (int k = 0; k < RING * 4; ++k) h->ring_host[k] = 0.0;
+    for (int k = 0; k < RING; ++k)
+        if (hipEventCreateWithFlags(&h->ring_ev[k], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HIPBMG_EHIP, "event creation failed"));
+    if (const char *e = std::getenv("HIPBMG_AHEAD")) {   // cycles enqueued ahead of the last test seen
+        const int v = std::atoi(e);
+        if (v >= 0 && v < RING) h->ahead = v;
+    }
 
     // finest level pipelined across cycles (5-point finest, V(2,1), finest
     // level not collapsed); HIPBMG_NO_FUSE3=1 disables it
@@ -455,16 +569,9 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     }
     // collapse level from the performance model (sections 3 and 4)
     ModelLevel ml[HIPBMG_MAX_LEVELS];
-    for (int l = 0; l < L; ++l) {
-        ml[l].nx = sx[l];
-        ml[l].ny = sy[l];
-        ml[l].npt = h->lv[l].npt;
-        ml[l].rb = h->rb[l];
-    }
-    ModelParams mp = model_params();
-    mp.lds_budget_bytes = (double)(h->no_lds ? 0 : COLLAPSE_LDS_BUDGET);
-    int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc,
-                            prm.precision == HIPBMG_MIXED ? 4 : 8, mp, h->model_us);
+    model_levels(h, prm.precision == HIPBMG_MIXED, ml);
+    int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc, prm.precision == HIPBMG_MIXED ? 4 : 8,
+                            model_params(), h->model_us);
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
     if (h->lstar >= L - 1) h->fused3 = 0;   // the finest level itself is collapsed
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
@@ -522,6 +629,39 @@ static hipError_t run_stream(const LevelDev<T> &A, int variant, StreamArgs<T> a,
     return launch_stream<T>(A.npt, variant, a, g, s);
 }
 
+// Launch arguments of the collapsed levels 0..top: levels from the coarsest up
+// are staged in LDS while they fit (lds_in_budget gives the same test).
+template <typename T>
+static CollapseArgs<T> collapse_args(const hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
+                                     const LevelDev<T> *d_lv, int top, int xb_top, int zero_top, int want_norm)
+{
+    CollapseArgs<T> c{};
+    c.levels = d_lv;
+    c.top = top;
+    c.xb_top = xb_top;
+    c.zero_top = zero_top;
+    c.nu1 = h->prm.nu1;
+    c.nu2 = h->prm.nu2;
+    c.rescorr = h->prm.residual_correction;
+    c.chol = h->d_chol;
+    c.cidx = h->d_cidx;
+    c.nc = h->nc;
+    c.work = h->d_work;
+    c.partials = h->d_partials;
+    c.want_norm = want_norm;
+    c.lds_top = -1;
+    size_t off = 0;
+    for (int l = 0; l <= top; ++l) {
+        const size_t bytes = collapse_lds_bytes<T>(lv[l].nx, lv[l].ny, l ? lv[l - 1].nx : 0, l ? lv[l - 1].ny : 0);
+        if (off + bytes > (size_t)COLLAPSE_LDS_BUDGET || h->no_lds) break;
+        c.lds_off[l] = (int)off;
+        off += bytes;
+        c.lds_top = l;
+    }
+    c.lds_bytes = (int)off;
+    return c;
+}
+
 // Enqueue one V-cycle on the hierarchy `lv` whose finest iterate is in
 // x[cur] (or is zero if zero_start).  The finest post-relaxation leaves its
 // residual norm partials in d_partials (*nparts of them).  Returns the buffer
@@ -529,7 +669,8 @@ static hipError_t run_stream(const LevelDev<T> &A, int variant, StreamArgs<T> a,
 template <typename T>
 static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
                                  const LevelDev<T> *d_lv, int cur, bool zero_start, int *new_cur,
-                                 int *nparts, hipStream_t s, bool skip_finest = false)
+                                 int *nparts, hipStream_t s, bool skip_finest = false,
+                                 const int *active = nullptr)
 {
     // skip_finest: run levels L-2..0 only (the finest level's kernels are
     // issued by the caller); *new_cur then receives the buffer of level L-2's
@@ -563,47 +704,20 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
                 a.cpitch = Cl.pitch;
                 a.cplane = (long long)Cl.plane;
             }
-            const int pk = (h->prof_on && fine && h->prof_n < 64) ? h->prof_n++ : -1;
-            if (pk >= 0) {
-                h->prof_var[pk] = v;
-                h->prof_prec[pk] = PrecIdx<T>::v;
-                (void)hipEventRecord(h->ev0[pk], s);
-            }
+            const int pk = fine ? prof_begin(h, v, PrecIdx<T>::v, s) : -1;
+            a.active = active;
             if ((e = run_stream(A, v, a, s)) != hipSuccess) return e;
-            if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+            prof_end(h, pk, s);
             xb = 1 - xb;
         }
         xb_after[l] = xb;
     }
     // levels 0..l* in one workgroup
     {
-        CollapseArgs<T> c{};
-        c.levels = d_lv;
-        c.top = ls;
         const bool fine = ls == h->L - 1;
-        c.xb_top = fine ? cur : 1;
-        c.zero_top = fine ? (zero_start ? 1 : 0) : 1;
-        c.nu1 = nu1;
-        c.nu2 = nu2;
-        c.rescorr = rc;
-        c.chol = h->d_chol;
-        c.cidx = h->d_cidx;
-        c.nc = h->nc;
-        c.work = h->d_work;
-        c.partials = h->d_partials;
-        c.want_norm = fine ? 1 : 0;
-        // stage as many of the collapsed levels (from the coarsest up) as fit in LDS
-        c.lds_top = -1;
-        size_t off = 0;
-        for (int l = 0; l <= ls; ++l) {
-            const size_t bytes = collapse_lds_bytes<T>(lv[l].nx, lv[l].ny, l ? lv[l - 1].nx : 0,
-                                                       l ? lv[l - 1].ny : 0);
-            if (off + bytes > (size_t)COLLAPSE_LDS_BUDGET || h->no_lds) break;
-            c.lds_off[l] = (int)off;
-            off += bytes;
-            c.lds_top = l;
-        }
-        c.lds_bytes = (int)off;
+        CollapseArgs<T> c = collapse_args<T>(h, lv, d_lv, ls, fine ? cur : 1, fine ? (zero_start ? 1 : 0) : 1,
+                                             fine ? 1 : 0);
+        c.active = active;
         if ((e = launch_collapse<T>(c, s)) != hipSuccess) return e;
         xres[ls] = c.xb_top;
         if (fine) {
@@ -635,14 +749,10 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             }
             a.partials = h->d_partials;
             int nt = 0;
-            const int pk = (h->prof_on && fine && h->prof_n < 64) ? h->prof_n++ : -1;
-            if (pk >= 0) {
-                h->prof_var[pk] = v;
-                h->prof_prec[pk] = PrecIdx<T>::v;
-                (void)hipEventRecord(h->ev0[pk], s);
-            }
+            const int pk = fine ? prof_begin(h, v, PrecIdx<T>::v, s) : -1;
+            a.active = active;
             if ((e = run_stream(A, v, a, s, &nt)) != hipSuccess) return e;
-            if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+            prof_end(h, pk, s);
             if (fine && last) *nparts = nt;
             xb = 1 - xb;
         }
@@ -659,24 +769,33 @@ template <typename T> static T *&q2_of(hipbmg_hier *h);
 template <> double *&q2_of<double>(hipbmg_hier *h) { return h->q2_64; }
 template <> float *&q2_of<float>(hipbmg_hier *h) { return h->q2_32; }
 
-// V-cycles with the finest level pipelined: after one pass of the two
-// pre-relaxations, every cycle is [coarse levels] + one finest pass that
-// interpolates, post-relaxes (the iterate after this cycle, and its residual
-// norm) and pre-relaxes for the next cycle.  Three iterate buffers and two r/C
-// buffers rotate at the finest level.  `on_norm(k, nparts)` finalises and
-// checks the norm of cycle k and returns 1 to stop, 0 to go on, <0 on error.
-// Returns the buffer with the final iterate in *result.
-template <typename T, typename OnNorm>
-static hipbmg_status run_cycles_fused(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
-                                      const LevelDev<T> *d_lv, int cur, bool zero_start, int max_cycles,
-                                      hipStream_t s, OnNorm on_norm, const T **result, int *cycles_done)
+// Run up to max_cycles V-cycles on the hierarchy lv (FP64 levels, or the FP32
+// levels of a mixed solve) from its finest iterate x[0] (or from zero), with
+// the convergence test ||r|| / denom[0] <= tol after every cycle taken on the
+// device.  The host enqueues up to `ahead` cycles beyond the last test it has
+// seen; once a test is met the device clears the run flag and every launch of
+// later cycles returns at once, so the iterate stays the one of the stopping
+// cycle.  With the finest level pipelined, cycle k's post-relaxation, norm and
+// cycle k+1's pre-relaxations and restriction are one pass over three
+// iterate buffers.  On return *result is the finest buffer holding the
+// iterate after the last cycle run, *cycles_done their number, and the
+// residual history of the run is in d_hist.
+template <typename T>
+static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv, const LevelDev<T> *d_lv,
+                                bool zero_start, int max_cycles, double tol, const double *d_denom,
+                                hipStream_t s, const T **result, int *cycles_done)
 {
     const int L = h->L;
-    const LevelDev<T> &F = lv[L - 1], &Cl = lv[L - 2];
-    T *xb[3] = {F.x[cur], F.x[1 - cur], x3_of<T>(h)};
-    T *qb[2] = {F.q, q2_of<T>(h)};
-    // pre-relaxations of cycle 1 (and the restriction of its residual)
-    {
+    const LevelDev<T> &F = lv[L - 1];
+    const int *act = h->d_flags;
+    const bool pipe = h->fused3 != 0;
+    T *xb[3] = {F.x[0], F.x[1], pipe ? x3_of<T>(h) : nullptr};
+    T *qb[2] = {F.q, pipe ? q2_of<T>(h) : nullptr};
+    std::vector<const T *> res_after((size_t)max_cycles + 1, F.x[0]);
+    HIPCHK(launch_flags_reset(h->d_flags, s));
+    if (pipe) {
+        // pre-relaxations of cycle 1 and the restriction of its residual
+        const LevelDev<T> &Cl = lv[L - 2];
         StreamArgs<T> a = base_args(F, h->rb[L - 1]);
         a.x_in = xb[0];
         a.x_out = xb[1];
@@ -689,45 +808,64 @@ static hipbmg_status run_cycles_fused(hipbmg_hier *h, const std::vector<LevelDev
         a.cplane = (long long)Cl.plane;
         HIPCHK(run_stream(F, zero_start ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ, a, s));
     }
-    int i = 1, qa = 0, k = 0;
-    *result = xb[0];
-    while (k < max_cycles) {
-        int cc = 0, dummy = 0;
-        hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, 0, false, &cc, &dummy, s, true);
-        if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
-        StreamArgs<T> a = base_args(F, h->rb3);
-        a.x_in = xb[i];
-        a.x_out = xb[(i + 1) % 3];
-        a.x_out2 = xb[(i + 2) % 3];
-        a.xc = Cl.x[cc];
-        a.wt = F.wt;
-        a.q_in = qb[qa];
-        a.rescorr = h->prm.residual_correction;
-        a.q_out = qb[1 - qa];
-        a.bc = Cl.b;
-        a.cnx = Cl.nx;
-        a.cny = Cl.ny;
-        a.cpitch = Cl.pitch;
-        a.cplane = (long long)Cl.plane;
-        a.partials = h->d_partials;
-        int nt = 0;
-        const int pk = (h->prof_on && h->prof_n < 64) ? h->prof_n++ : -1;
-        if (pk >= 0) {
-            h->prof_var[pk] = SV_FUSED3;
-            h->prof_prec[pk] = PrecIdx<T>::v;
-            (void)hipEventRecord(h->ev0[pk], s);
-        }
-        HIPCHK(run_stream(F, SV_FUSED3, a, s, &nt));
-        if (pk >= 0) (void)hipEventRecord(h->ev1[pk], s);
+    int k = 0, seen = 0, i = 1, qa = 0, cur = 0;
+    bool stopped = false;
+    while (k < max_cycles && !stopped) {
         ++k;
-        *result = xb[(i + 1) % 3];
-        const int r = on_norm(k, nt);
-        if (r < 0) return HIPBMG_EHIP;
-        if (r > 0) break;
-        i = (i + 2) % 3;
-        qa = 1 - qa;
+        h->prof_cycle = k;
+        int np = 0;
+        if (pipe) {
+            const LevelDev<T> &Cl = lv[L - 2];
+            int cc = 0, dummy = 0;
+            hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, 0, false, &cc, &dummy, s, true, act);
+            if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
+            StreamArgs<T> a = base_args(F, h->rb3);
+            a.x_in = xb[i];
+            a.x_out = xb[(i + 1) % 3];
+            a.x_out2 = xb[(i + 2) % 3];
+            a.xc = Cl.x[cc];
+            a.wt = F.wt;
+            a.q_in = qb[qa];
+            a.rescorr = h->prm.residual_correction;
+            a.q_out = qb[1 - qa];
+            a.bc = Cl.b;
+            a.cnx = Cl.nx;
+            a.cny = Cl.ny;
+            a.cpitch = Cl.pitch;
+            a.cplane = (long long)Cl.plane;
+            a.partials = h->d_partials;
+            a.active = act;
+            const int pk = prof_begin(h, SV_FUSED3, PrecIdx<T>::v, s);
+            HIPCHK(run_stream(F, SV_FUSED3, a, s, &np));
+            prof_end(h, pk, s);
+            res_after[k] = xb[(i + 1) % 3];
+            i = (i + 2) % 3;
+            qa = 1 - qa;
+        } else {
+            int nc = 0;
+            hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, cur, zero_start && k == 1, &nc, &np, s, false, act);
+            if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
+            cur = nc;
+            res_after[k] = F.x[cur];
+        }
+        HIPCHK(launch_finalize_check(h->d_partials, np, d_denom, tol, k, h->d_hist, HIPBMG_MAX_HIST, h->d_scal + 1,
+                                     h->d_flags, h->ring_dev + 4 * (k % RING), s));
+        HIPCHK(hipEventRecord(h->ring_ev[k % RING], s));
+        // the tests of earlier cycles, `ahead` cycles behind the newest
+        while (seen < k - h->ahead && !stopped) {
+            ++seen;
+            HIPCHK(hipEventSynchronize(h->ring_ev[seen % RING]));
+            prof_collect(h, false);
+            const volatile double *slot = h->ring_host + 4 * (seen % RING);
+            if (slot[1] == 0.0) stopped = true;
+        }
     }
-    *cycles_done = k;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(h->h_flags, h->d_flags, 4 * sizeof(int), hipMemcpyDeviceToHost));
+    const int kdone = h->h_flags[0] ? k : h->h_flags[1];
+    prof_collect(h, true, kdone);
+    *cycles_done = kdone;
+    *result = res_after[kdone];
     return HIPBMG_OK;
 }
 
@@ -754,87 +892,32 @@ static void fill_info_common(hipbmg_hier *h, hipbmg_info *info)
 }
 
 static hipbmg_status solve_fp64(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
-                                int *cur_out, const double **res_out)
+                                const double **res_out)
 {
-    const LevelDev<double> &F = h->lv[h->L - 1];
-    int cur = 0, cycles = 0;
-    double rel = 1.0;
-    hipbmg_status st = HIPBMG_ENOCONV;
-    *res_out = nullptr;
-    if (h->fused3) {
-        hipbmg_status err = HIPBMG_OK;
-        auto on_norm = [&](int k, int np) -> int {
-            if (launch_finalize_norm(h->d_partials, np, h->d_scal, h->d_scal + 1, s) != hipSuccess) {
-                err = fail(HIPBMG_EHIP, "norm launch failed");
-                return -1;
-            }
-            if ((err = read_scalars(h, 1, 1, s)) != HIPBMG_OK) return -1;
-            prof_collect(h);
-            rel = h->h_scal[1];
-            if (info && k - 1 < HIPBMG_MAX_HIST) info->relres_hist[k - 1] = rel;
-            if (!std::isfinite(rel)) {
-                st = HIPBMG_ENAN;
-                return 1;
-            }
-            if (rel <= tol) {
-                st = HIPBMG_OK;
-                return 1;
-            }
-            return 0;
-        };
-        const double *res = nullptr;
-        hipbmg_status r = run_cycles_fused<double>(h, h->lv, h->d_lv, 0, false, h->prm.max_cycles, s, on_norm,
-                                                   &res, &cycles);
-        if (r != HIPBMG_OK) return err != HIPBMG_OK ? err : r;
-        *res_out = res;
-        if (info) {
-            info->cycles = cycles;
-            info->outer_steps = cycles;
-            info->relres = rel;
-        }
-        if (st == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "residual norm is not finite after cycle %d", cycles);
-        if (st == HIPBMG_ENOCONV)
-            return fail(HIPBMG_ENOCONV, "relres %.3e > tol %.3e after %d cycles", rel, tol, cycles);
-        return HIPBMG_OK;
-    }
-    while (cycles < h->prm.max_cycles) {
-        int nc, np = 0;
-        hipError_t e = enqueue_vcycle<double>(h, h->lv, h->d_lv, cur, false, &nc, &np, s);
-        if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
-        cur = nc;
-        HIPCHK(launch_finalize_norm(h->d_partials, np, h->d_scal, h->d_scal + 1, s));
-        STCHK(read_scalars(h, 1, 1, s));
-        prof_collect(h);
-        rel = h->h_scal[1];
-        if (info && cycles < HIPBMG_MAX_HIST) info->relres_hist[cycles] = rel;
-        ++cycles;
-        if (!std::isfinite(rel)) {
-            st = HIPBMG_ENAN;
-            break;
-        }
-        if (rel <= tol) {
-            st = HIPBMG_OK;
-            break;
-        }
-    }
-    (void)F;
-    *cur_out = cur;
+    int cycles = 0;
+    STCHK(run_cycles<double>(h, h->lv, h->d_lv, false, h->prm.max_cycles, tol, h->d_scal, s, res_out, &cycles));
+    std::vector<double> hist(std::min(cycles, HIPBMG_MAX_HIST));
+    if (!hist.empty())
+        HIPCHK(hipMemcpy(hist.data(), h->d_hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost));
+    STCHK(read_scalars(h, 1, 1, s));
+    const double rel = cycles > 0 ? h->h_scal[1] : 1.0;
     if (info) {
         info->cycles = cycles;
         info->outer_steps = cycles;
         info->relres = rel;
+        for (size_t m = 0; m < hist.size(); ++m) info->relres_hist[m] = hist[m];
     }
-    if (st == HIPBMG_ENAN) return fail(HIPBMG_ENAN, "residual norm is not finite after cycle %d", cycles);
-    if (st == HIPBMG_ENOCONV)
+    if (h->h_flags[0] == 0 && h->h_flags[2] == 2)
+        return fail(HIPBMG_ENAN, "residual norm is not finite after cycle %d", cycles);
+    if (h->h_flags[0] != 0)
         return fail(HIPBMG_ENOCONV, "relres %.3e > tol %.3e after %d cycles", rel, tol, cycles);
     return HIPBMG_OK;
 }
 
-// FP32 V-cycles inside FP64 iterative refinement: the FP64 residual of the
-// FP64 iterate is demoted to the FP32 right-hand side, FP32 cycles reduce it
-// by inner_tol, and the FP32 correction is added to the FP64 iterate.
-static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
-                                 int *cur_out)
+// FP64 iterative refinement: the outer residual r = b - A u in FP64 (demoted
+// into the FP32 right-hand side), inner FP32 V-cycles on A e = r from e = 0 to
+// a relative residual of inner_tol, u += e.
+static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info)
 {
     const int L = h->L;
     const LevelDev<double> &F = h->lv[L - 1];
@@ -861,49 +944,15 @@ static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipb
         }
         if (cycles >= h->prm.max_cycles) break;
         ++steps;
-        // inner FP32 solve of A e = r from e = 0
-        h->h_scal[4] = rnorm;
-        HIPCHK(hipMemcpyAsync(h->d_scal + 4, h->h_scal + 4, sizeof(double), hipMemcpyHostToDevice, s));
-        int cur = 0;
-        bool zero = true;
-        if (h->fused3) {
-            hipbmg_status err = HIPBMG_OK;
-            const int cap = std::min(h->prm.inner_max_cycles, h->prm.max_cycles - cycles);
-            auto on_norm = [&](int, int np) -> int {
-                if (launch_finalize_norm(h->d_partials, np, h->d_scal + 4, h->d_scal + 3, s) != hipSuccess) {
-                    err = fail(HIPBMG_EHIP, "norm launch failed");
-                    return -1;
-                }
-                if ((err = read_scalars(h, 3, 1, s)) != HIPBMG_OK) return -1;
-                prof_collect(h);
-                const double irel = h->h_scal[3];
-                return (!std::isfinite(irel) || irel <= h->prm.inner_tol) ? 1 : 0;
-            };
-            const float *e32 = nullptr;
-            int done = 0;
-            hipbmg_status r = run_cycles_fused<float>(h, h->lv32, h->d_lv32, 0, true, cap, s, on_norm, &e32, &done);
-            if (r != HIPBMG_OK) return err != HIPBMG_OK ? err : r;
-            cycles += done;
-            HIPCHK(launch_ir_update(F.x[0], F.pitch, e32, F32.pitch, F.nx, F.ny, s));
-            continue;
-        }
-        for (int k = 0; k < h->prm.inner_max_cycles && cycles < h->prm.max_cycles; ++k) {
-            int nc, npp = 0;
-            hipError_t e = enqueue_vcycle<float>(h, h->lv32, h->d_lv32, cur, zero, &nc, &npp, s);
-            if (e != hipSuccess) return fail(HIPBMG_EHIP, "FP32 V-cycle launch failed: %s", hipGetErrorString(e));
-            cur = nc;
-            zero = false;
-            ++cycles;
-            HIPCHK(launch_finalize_norm(h->d_partials, npp, h->d_scal + 4, h->d_scal + 3, s));
-            STCHK(read_scalars(h, 3, 1, s));
-            prof_collect(h);
-            const double irel = h->h_scal[3];
-            if (!std::isfinite(irel)) break;
-            if (irel <= h->prm.inner_tol) break;
-        }
-        HIPCHK(launch_ir_update(F.x[0], F.pitch, F32.x[cur], F32.pitch, F.nx, F.ny, s));
+        // inner FP32 solve of A e = r from e = 0, relative to ||r|| (on the device)
+        const int cap = std::min(h->prm.inner_max_cycles, h->prm.max_cycles - cycles);
+        const float *e32 = nullptr;
+        int done = 0;
+        STCHK(run_cycles<float>(h, h->lv32, h->d_lv32, true, cap, h->prm.inner_tol, h->d_scal + 2, s, &e32,
+                                &done));
+        cycles += done;
+        HIPCHK(launch_ir_update(F.x[0], F.pitch, e32, F32.pitch, F.nx, F.ny, s));
     }
-    *cur_out = 0;
     if (info) {
         info->cycles = cycles;
         info->outer_steps = steps;
@@ -947,13 +996,11 @@ extern "C" hipbmg_status hipbmg_solve(hipbmg_handle h, const double *b, double *
         if (info) info->solve_ms = now_ms() - t0;
         return HIPBMG_OK;
     }
-    int cur = 0;
-    const double *res = nullptr;
-    hipbmg_status st = h->prm.precision == HIPBMG_MIXED ? solve_mixed(h, tol, s, info, &cur)
-                                                         : solve_fp64(h, tol, s, info, &cur, &res);
+    const double *res = F.x[0];
+    hipbmg_status st = h->prm.precision == HIPBMG_MIXED ? solve_mixed(h, tol, s, info)
+                                                         : solve_fp64(h, tol, s, info, &res);
     if (st != HIPBMG_OK && st != HIPBMG_ENOCONV && st != HIPBMG_ENAN) return st;
     std::string msg = g_err;
-    if (!res) res = F.x[cur];
     HIPCHK(hipMemcpy2DAsync(u, nx * sizeof(double), res, F.pitch * sizeof(double),
                             nx * sizeof(double), ny, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1126,12 +1173,12 @@ extern "C" hipbmg_status hipbmg_profile(hipbmg_handle h, int enable)
 {
     if (!h) return fail(HIPBMG_EINVAL, "null handle");
     if (enable && !h->ev0[0])
-        for (int k = 0; k < 64; ++k) {
+        for (int k = 0; k < PROF_RING; ++k) {
             HIPCHK(hipEventCreate(&h->ev0[k]));
             HIPCHK(hipEventCreate(&h->ev1[k]));
         }
+    prof_collect(h, true);   // pairs still pending belong to the previous setting
     h->prof_on = enable ? 1 : 0;
-    h->prof_n = 0;
     if (enable) {
         memset(h->prof_ms, 0, sizeof h->prof_ms);
         memset(h->prof_cnt, 0, sizeof h->prof_cnt);
@@ -1167,6 +1214,202 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Calibration of the model on the kernels themselves.  A synthetic hierarchy
+// (D = 1 on 257 x 257 vertices, FP64 and FP32 levels) is built; the collapse
+// launch is timed with every level as its top, and the down and up kernels of
+// every level are timed back to back.  The collapsed-level terms (alpha_bar,
+// beta_wg, separately for levels staged in LDS and levels left in global
+// memory) are fitted to the per-level increments of the collapse time, the
+// step latencies to the grid kernels on levels too small to be
+// bandwidth-bound.  This is the single-GPU form of measuring the model's
+// parameters with benchmarks of the operations the solver performs.
+// ---------------------------------------------------------------------------
+template <typename F>
+static double time_launches_us(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, int per, F &&launch)
+{
+    for (int k = 0; k < per; ++k) launch();   // warm-up
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, s);
+        for (int k = 0; k < per; ++k) launch();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, 1e3 * (double)ms / per);
+    }
+    return best;
+}
+
+// least squares y = a + b x over the samples, with a, b >= 0 (a, b unchanged
+// if there is no sample)
+static void fit_nonneg(const std::vector<double> &x, const std::vector<double> &y, double *a, double *b)
+{
+    const size_t n = x.size();
+    if (n == 0) return;
+    double mx = 0.0, my = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        mx += x[i];
+        my += y[i];
+    }
+    mx /= (double)n;
+    my /= (double)n;
+    double sxy = 0.0, sxx = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        sxy += (x[i] - mx) * (y[i] - my);
+        sxx += (x[i] - mx) * (x[i] - mx);
+    }
+    double bb = (n > 1 && sxx > 0.0) ? sxy / sxx : 0.0, aa = my - bb * mx;
+    if (bb < 0.0) {
+        bb = 0.0;
+        aa = my;
+    }
+    if (aa < 0.0) {   // through the origin
+        double s0 = 0.0, s1 = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            s0 += x[i] * y[i];
+            s1 += x[i] * x[i];
+        }
+        aa = 0.0;
+        bb = s1 > 0.0 ? std::max(0.0, s0 / s1) : 0.0;
+    }
+    *a = aa;
+    *b = bb;
+}
+
+static double median(std::vector<double> v)
+{
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+template <typename T>
+static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv, const LevelDev<T> *d_lv,
+                                      hipStream_t s, hipEvent_t e0, hipEvent_t e1, ModelParams &p)
+{
+    const int L = h->L, nu1 = h->prm.nu1, nu2 = h->prm.nu2, word = (int)sizeof(T);
+    const int q = word == 4 ? 1 : 0;
+    ModelLevel ml[HIPBMG_MAX_LEVELS];
+    model_levels(h, q, ml);
+    // collapse launch with each level as its top
+    std::vector<double> tc(L);
+    for (int top = 0; top < L; ++top) {
+        const CollapseArgs<T> c = collapse_args<T>(h, lv, d_lv, top, 1, 1, 0);
+        tc[top] = time_launches_us(s, e0, e1, 3, 2, [&] { (void)launch_collapse<T>(c, s); });
+    }
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    p.t_base_us[q] = std::max(0.0, tc[0] - p.alpha_launch_us);
+    std::vector<double> xs[2], ys[2];
+    for (int l = 1; l < L; ++l) {
+        const int g = ml[l].in_lds ? 0 : 1;
+        xs[g].push_back(model_wg_bytes(lv[l].nx, lv[l].ny, nu1, nu2, word));
+        ys[g].push_back(tc[l] - tc[l - 1]);
+    }
+    const double P = model_wg_phases(nu1, nu2);
+    for (int g = 0; g < 2; ++g) {
+        double a = P * p.alpha_bar_us[q][g], b = p.beta_wg_us_per_B[q][g];
+        fit_nonneg(xs[g], ys[g], &a, &b);
+        p.alpha_bar_us[q][g] = a / P;
+        p.beta_wg_us_per_B[q][g] = b;
+    }
+    // grid kernels of every level below the finest (zero-start pre-relaxation
+    // fused with residual and restriction; interpolating relaxation)
+    std::vector<double> sdn, sup;
+    const int vdn = nu1 >= 2 ? SV_SWEEP2_RQ_ZX : SV_SWEEP_RQ_ZX;
+    for (int l = 1; l < L; ++l) {
+        const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
+        const int nsteps = (A.ny - 1) / 2;
+        StreamArgs<T> a = base_args(A, h->rb[l]);
+        a.x_in = A.x[0];
+        a.x_out = A.x[1];
+        a.q_out = A.q;
+        a.bc = Cl.b;
+        a.wt = A.wt;
+        a.cnx = Cl.nx;
+        a.cny = Cl.ny;
+        a.cpitch = Cl.pitch;
+        a.cplane = (long long)Cl.plane;
+        const double tdn = time_launches_us(s, e0, e1, 3, 8, [&] { (void)run_stream(A, vdn, a, s); });
+        StreamArgs<T> u = base_args(A, h->rb_up[l]);
+        u.x_in = A.x[1];
+        u.x_out = A.x[0];
+        u.xc = Cl.x[1];
+        u.wt = A.wt;
+        u.q_in = A.q;
+        u.rescorr = h->prm.residual_correction;
+        u.cnx = Cl.nx;
+        u.cny = Cl.ny;
+        u.cpitch = Cl.pitch;
+        u.cplane = (long long)Cl.plane;
+        const double tup = time_launches_us(s, e0, e1, 3, 8, [&] { (void)run_stream(A, SV_INTERP, u, s); });
+        // one residency round and a working set whose bytes take well under the
+        // measured time at the cache bandwidth: the waves' step latency bounds it
+        const double nbytes = (double)A.nx * A.ny * word * 12.0;
+        int nst, nbl, nt, gg;
+        stream_geometry(A.nx, A.ny, A.npt, vdn, h->rb[l], &nst, &nbl, &nt, &gg);
+        const int rdn = stream_resident(A.npt, vdn, q);
+        if (rdn > 0 && nt <= rdn && nbytes * p.beta_cache_us_per_B < 0.3 * (tdn - p.alpha_launch_us))
+            sdn.push_back((tdn - p.alpha_launch_us) / stream_steps_per_tile(vdn, std::min(h->rb[l], nsteps)));
+        stream_geometry(A.nx, A.ny, A.npt, SV_INTERP, h->rb_up[l], &nst, &nbl, &nt, &gg);
+        const int rup = stream_resident(A.npt, SV_INTERP, q);
+        if (rup > 0 && nt <= rup && nbytes * p.beta_cache_us_per_B < 0.3 * (tup - p.alpha_launch_us))
+            sup.push_back((tup - p.alpha_launch_us) / stream_steps_per_tile(SV_INTERP, std::min(h->rb_up[l], nsteps)));
+    }
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    if (!sdn.empty()) p.step_dn_us[q] = std::max(0.05, median(sdn));
+    if (!sup.empty()) p.step_up_us[q] = std::max(0.05, median(sup));
+    return hipStreamSynchronize(s);
+}
+
+hipbmg_status hbmg::calibrate_on_kernels(void *stream, ModelParams &p)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int n = 257;
+    const size_t ncell = (size_t)(n - 1) * (n - 1);
+    std::vector<double> ones(ncell, 1.0);
+    double *cells = nullptr, *planes = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipbmg_handle h = nullptr;
+    hipbmg_status st = HIPBMG_OK;
+    auto cleanup = [&] {
+        if (h) hipbmg_destroy(h);
+        if (cells) (void)hipFree(cells);
+        if (planes) (void)hipFree(planes);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&cells, ncell * sizeof(double)) != hipSuccess ||
+        hipMalloc(&planes, 3 * (size_t)n * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(HIPBMG_ENOMEM, "calibration: device allocation failed");
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipMemcpyAsync(cells, ones.data(), ncell * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+        cleanup();
+        return fail(HIPBMG_EHIP, "calibration: event or copy failed");
+    }
+    if ((st = hipbmg_fv5_from_cells(n, n, cells, 0, planes, s)) != HIPBMG_OK) {
+        cleanup();
+        return st;
+    }
+    hipbmg_params prm;
+    hipbmg_default_params(&prm);
+    prm.precision = HIPBMG_MIXED;
+    prm.collapse_level = 0;
+    if ((st = hipbmg_setup(n, n, 5, planes, &prm, stream, &h)) != HIPBMG_OK) {
+        cleanup();
+        return st;
+    }
+    hipError_t e = calibrate_precision<double>(h, h->lv, h->d_lv, s, e0, e1, p);
+    if (e == hipSuccess) e = calibrate_precision<float>(h, h->lv32, h->d_lv32, s, e0, e1, p);
+    if (e != hipSuccess) st = fail(HIPBMG_EHIP, "calibration launches failed: %s", hipGetErrorString(e));
+    cleanup();
+    return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -1333,31 +1576,10 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             }
             xb_after[l] = xb;
         }
-        CollapseArgs<T> c{};
-        c.levels = dlevels_of<T>(h);
-        c.top = ls;
         const bool cfine = ls == L - 1;
-        c.xb_top = cfine ? cur : 1;
-        c.zero_top = cfine ? (zero_start ? 1 : 0) : 1;
-        c.nu1 = nu1;
-        c.nu2 = nu2;
-        c.rescorr = rc;
-        c.chol = h->d_chol;
-        c.cidx = h->d_cidx;
-        c.nc = h->nc;
-        c.work = h->d_work;
-        c.want_norm = cfine ? 1 : 0;
-        c.lds_top = -1;
-        size_t lo = 0;
-        for (int l = 0; l <= ls; ++l) {
-            const size_t bytes = collapse_lds_bytes<T>(lv[l].nx, lv[l].ny, l ? lv[l - 1].nx : 0, l ? lv[l - 1].ny : 0);
-            if (lo + bytes > (size_t)COLLAPSE_LDS_BUDGET || h->no_lds) break;
-            c.lds_off[l] = (int)lo;
-            lo += bytes;
-            c.lds_top = l;
-        }
-        c.lds_bytes = (int)lo;
-        lds_max = std::max(lds_max, (int)lo);
+        CollapseArgs<T> c = collapse_args<T>(h, lv, dlevels_of<T>(h), ls, cfine ? cur : 1,
+                                             cfine ? (zero_start ? 1 : 0) : 1, cfine ? 1 : 0);
+        lds_max = std::max(lds_max, c.lds_bytes);
         xres[ls] = c.xb_top;
         int pc = 1;
         for (int l = ls + 1; l < L; ++l) {

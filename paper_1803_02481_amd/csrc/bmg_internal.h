@@ -50,6 +50,9 @@ struct StreamArgs {
     // norm partial sums, one per tile
     double *partials;
     int nstrips, nblocks, rb, ntiles;
+    // the solve's run flag (null: always run); a launch whose flag reads 0
+    // returns at once (the convergence test of an earlier cycle was met)
+    const int *active;
 };
 
 enum StreamVariant {
@@ -114,6 +117,7 @@ struct CollapseArgs {
     int lds_top;                 // highest level staged in LDS (-1: none)
     int lds_bytes;               // dynamic LDS of the launch
     int lds_off[COLLAPSE_MAX_LEVELS];   // byte offset of each staged level
+    const int *active;                  // run flag as in StreamArgs (null: always run)
 };
 template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s);
@@ -138,5 +142,17 @@ hipError_t launch_sumsq(const double *v, int nx, int ny, int pitch, double *part
 // out[0] = sqrt(sum(partials)) / denom_src[0] (denom_src may be null -> plain norm).
 hipError_t launch_finalize_norm(const double *partials, int n, const double *denom, double *out,
                                 hipStream_t s);
+// Convergence test after cycle k of a solve: ||r|| / denom[0] from the norm
+// partials (the same fixed-order reduction as launch_finalize_norm) goes to
+// last[0], to hist[k-1] (if k <= hist_cap) and, with the flag state, to the four doubles
+// at slot {relres, run flag, stopping cycle, k} (host-mapped memory read by
+// the host a few cycles later).  When relres <= tol, or is not finite, the run
+// flag flags[0] is cleared and flags[1] = k, flags[2] = 1 (met) or 2 (not
+// finite).  Nothing is written once the flag is clear.
+hipError_t launch_finalize_check(const double *partials, int n, const double *denom, double tol, int k,
+                                 double *hist, int hist_cap, double *last, int *flags, double *slot,
+                                 hipStream_t s);
+// flags[0] = 1 (run), flags[1] = flags[2] = 0: the start of a solve
+hipError_t launch_flags_reset(int *flags, hipStream_t s);
 
 }  // namespace hbmg

@@ -3,39 +3,63 @@
 // the redistribution choice of section 4).
 #pragma once
 
+#include "hipbmg.h"
+
 namespace hbmg {
 
+// One level as the model sees it.  The host fills in the launch geometry the
+// streaming kernels will use: row-pair steps one wave walks and the number of
+// residency rounds of the launch, for the down (pre-relaxation) and up
+// (interpolation) kernels; in_lds says whether the level is staged in LDS when
+// it is collapsed.
 struct ModelLevel {
-    int nx, ny, npt, rb;
+    int nx, ny, npt;
+    int steps_dn, rounds_dn;
+    int steps_up, rounds_up;
+    int in_lds;
 };
 
 // Machine parameters.  Paper -> GPU correspondence:
-//   alpha (message latency)  -> alpha_launch: one dependent kernel boundary for
-//                               grid-wide levels; alpha_bar: one workgroup barrier
-//                               plus an L2 round trip inside the collapsed workgroup
-//   beta (inverse bandwidth) -> beta_hbm / beta_cache (grid-wide, by working set)
-//                               and beta_wg (one workgroup)
-//   gamma (per flop)         -> gamma_wg (single-thread FP64 work of the coarse solve)
-// plus step_us, the latency of one row-pair step of a streaming wave, which
-// bounds a grid-wide kernel on a level too small to fill the GPU.
+//   alpha (message latency)  -> alpha_launch: one dependent kernel boundary on a
+//                               grid-wide level; alpha_bar: one barrier phase of
+//                               the collapsed workgroup (level in LDS or in
+//                               global memory)
+//   beta (inverse bandwidth) -> beta_hbm / beta_cache for grid-wide levels (by
+//                               working set), beta_wg for the collapsed workgroup
+//   gamma (per flop)         -> gamma_wg, single-thread FP64 work of the coarse solve
+// plus step_dn / step_up, the latency of one row-pair step of a streaming wave
+// (pre-relaxation and interpolation kernels), which bounds a grid-wide kernel
+// on a level too small to fill the GPU, and t_base, the collapsed launch
+// holding only the coarsest level.  Per-precision entries are indexed
+// [0] FP64, [1] FP32; alpha_bar and beta_wg also by [0] LDS, [1] global.
 struct ModelParams {
     double alpha_launch_us;
-    double step_us;
     double beta_hbm_us_per_B;
     double beta_cache_us_per_B;
     double cache_bytes;
-    double alpha_bar_us;        // barrier after a dependent L2 access (level in global memory)
-    double alpha_bar_lds_us;    // barrier after a dependent LDS access (level staged in LDS)
-    double beta_wg_us_per_B;
+    double step_dn_us[2];
+    double step_up_us[2];
+    double t_base_us[2];
+    double alpha_bar_us[2][2];
+    double beta_wg_us_per_B[2][2];
     double gamma_wg_us_per_flop;
     double lds_budget_bytes;    // LDS available for staged collapsed levels
     int calibrated;             // 1 once measured on the device
 };
 
-// process-wide parameters (defaults, replaced by calibrate or the
-// HIPBMG_MODEL_PARAMS environment variable: "alpha_launch_us,step_us,
-// hbm_GBps,cache_GBps,alpha_bar_us,wg_GBps")
+// process-wide parameters: defaults until hipbmg_calibrate replaces them
 ModelParams &model_params();
+
+// Fit the step latencies and the collapsed-level terms of p by timing the
+// solver's own kernels on a synthetic hierarchy (alpha_launch and the
+// bandwidths must already be measured).  stream is a hipStream_t.
+hipbmg_status calibrate_on_kernels(void *stream, ModelParams &p);
+
+// barrier phases and algorithmic bytes of one visit of a collapsed level per
+// V(nu1,nu2)-cycle (zeroing, 4 colours per relaxation, residual, restriction,
+// interpolation; 9-point operator, word bytes per value)
+double model_wg_phases(int nu1, int nu2);
+double model_wg_bytes(int nx, int ny, int nu1, int nu2, int word);
 
 // Predicted time (microseconds) of one V(nu1,nu2)-cycle for every collapse
 // level l* in [0, L-1] into t_us[l*]; returns the argmin.  word = bytes per value.
@@ -45,7 +69,6 @@ int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word
 // the two parts of the model for one level (exposed for reporting)
 double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, int word,
                            const ModelParams &p);
-double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, bool in_lds,
-                         const ModelParams &p);
+double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, const ModelParams &p);
 
 }  // namespace hbmg

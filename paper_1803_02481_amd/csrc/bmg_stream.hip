@@ -586,6 +586,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
 template <typename T>
 __global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
 {
+    if (a.active && *a.active == 0) return;
     const int tile = xcd_tile_fn();
     if (tile >= a.ntiles) return;
     stream3_tile<T>(a, tile);
@@ -602,6 +603,7 @@ __device__ __forceinline__ int xcd_tile()
 template <typename T, int NPT, int V>
 __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
 {
+    if (a.active && *a.active == 0) return;
     const int tile = xcd_tile();
     if (tile >= a.ntiles) return;
     stream_tile<T, NPT, V>(a, tile);
@@ -610,6 +612,7 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
 template <typename T, int NPT, bool ZX>
 __global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
 {
+    if (a.active && *a.active == 0) return;
     const int tile = xcd_tile();
     if (tile >= a.ntiles) return;
     stream2_tile<T, NPT, ZX>(a, tile);

@@ -265,11 +265,18 @@ class BatchHierarchy:
 def calibrate():
     """Measure the performance-model parameters on the current device; later
     hierarchies choose their collapse level with them."""
-    out = (ctypes.c_double * 8)()
+    out = (ctypes.c_double * 24)()
     _check(lib().hipbmg_calibrate(_stream(), out))
-    keys = ("alpha_launch_us", "step_us", "hbm_GBps", "cache_GBps", "alpha_bar_us", "wg_GBps",
-            "alpha_bar_lds_us")
-    return {k: out[i] for i, k in enumerate(keys)}
+    return {k: out[i] for i, k in enumerate(CALIBRATION_KEYS)}
+
+
+CALIBRATION_KEYS = ("alpha_launch_us", "hbm_GBps", "cache_GBps",
+                    "step_dn_us_fp64", "step_up_us_fp64", "step_dn_us_fp32", "step_up_us_fp32",
+                    "t_base_us_fp64", "t_base_us_fp32",
+                    "alpha_bar_us_fp64_lds", "alpha_bar_us_fp64_global",
+                    "alpha_bar_us_fp32_lds", "alpha_bar_us_fp32_global",
+                    "wg_GBps_fp64_lds", "wg_GBps_fp64_global", "wg_GBps_fp32_lds", "wg_GBps_fp32_global",
+                    "bare_barrier_lds_us", "bare_barrier_l2_us", "bare_wg_l2_GBps", "plain_sweep_step_us")
 
 
 def fv5_from_cells(cell, is_log=False):

@@ -4,7 +4,7 @@ V-cycles on the 4097^2 random-block problem.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT_F -o run -- python3 perf_probe.py
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT_W -o run -- python3 perf_probe.py
-    python3 perf_probe.py --summarize OUT_F OUT_W --kernel relax2_restrict
+    python3 perf_probe.py --summarize OUT_F OUT_W --kernel fused3
 
 The summary step turns the two counter files into HBM bytes per launch of the
 finest-level kernels, each counter scaled by what it reads for the copy
@@ -24,12 +24,14 @@ FINEST = {
     "relax_restrict": "void hbmg::k_stream<double, 5, 2>(hbmg::StreamArgs<double>)",
     "interp_relax_norm": "void hbmg::k_stream<double, 5, 5>(hbmg::StreamArgs<double>)",
     "relax2_restrict": "void hbmg::k_stream2<double, 5, false>(hbmg::StreamArgs<double>)",
+    "fused3": "void hbmg::k_stream3<double>(hbmg::StreamArgs<double>)",
 }
 # algorithmic bytes per vertex (FP64, 5-point): relaxation reads x, b, C, W, S
 # and writes x; fused variants add q, the 8 weights at quarter resolution, and
-# the coarse right-hand side or coarse x
+# the coarse right-hand side or coarse x; the pipelined finest pass adds to the
+# interpolating relaxation the second iterate, r/C out and the coarse rhs
 ALGO_B_PER_VERTEX = {"relax": 48.0, "relax_restrict": 74.0, "interp_relax_norm": 74.0,
-                     "relax2_restrict": 74.0}
+                     "relax2_restrict": 74.0, "fused3": 92.0}
 
 
 def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
@@ -99,7 +101,7 @@ def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--kernel", default="relax2_restrict")
+    ap.add_argument("--kernel", default="fused3")
     ap.add_argument("--n", type=int, default=4097)
     ap.add_argument("--cycles", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)

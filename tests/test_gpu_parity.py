@@ -634,3 +634,37 @@ def test_full_size_solution_meets_tolerance_by_oracle_residual(full_size_case, p
           flush=True)
     assert rr <= 1.2e-10, rr
     assert info.relres == pytest.approx(rr, rel=0.2)
+
+
+@pytest.mark.parametrize("pipelined", ["0", "1"])
+def test_cycles_enqueued_ahead_do_not_change_the_solve(pipelined, monkeypatch):
+    # the host enqueues cycles before it has seen the previous convergence
+    # tests; the device stops at the first cycle that meets the test and every
+    # later launch returns at once, so the result is that of reading the test
+    # after every cycle
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
+    n = 257
+    planes = g(O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=41)))
+    b = g(inputs.load_uniform(n, n, seed=42))
+    ref = {}
+    for prec in (HB.FP64, HB.MIXED):
+        for ahead in ("0", "1", "2", "7"):
+            monkeypatch.setenv("HIPBMG_AHEAD", ahead)
+            u, info = HB.Hierarchy(planes, precision=prec).solve(b, tol=1e-10)
+            got = (info.cycles, info.outer_steps, info.history(), info.relres)
+            print("precision %d ahead %s: %d cycles, relres %.3e" % (prec, ahead, info.cycles, info.relres),
+                  flush=True)
+            if prec not in ref:
+                ref[prec] = (u, got)
+                continue
+            u0, got0 = ref[prec]
+            assert got == got0, (ahead, got, got0)
+            assert torch.equal(u, u0), ahead
+    # a cap that ends exactly at the converging cycle, and one short of it
+    monkeypatch.setenv("HIPBMG_AHEAD", "2")
+    _, (c, _, _, _) = ref[HB.FP64]
+    u1, i1 = HB.Hierarchy(planes, max_cycles=c).solve(b, tol=1e-10)
+    assert i1.cycles == c and torch.equal(u1, ref[HB.FP64][0])
+    with pytest.raises(HB.HipBMGError) as ei:
+        HB.Hierarchy(planes, max_cycles=c - 1).solve(b, tol=1e-10)
+    assert ei.value.status == HB.ENOCONV
