@@ -143,6 +143,12 @@ def main():
             del hs
             log("bench: l*=%d measured %.1f us/cycle, model %.1f" % (ls, 1e6 * per, model[ls]))
         extra["collapse_sweep"] = sweep
+        best = min(sweep, key=lambda r: r["measured_us_per_cycle"])
+        chosen = [r for r in sweep if r["collapse_level"] == info.collapse_level]
+        if chosen:
+            extra["collapse_choice"] = {
+                "model": info.collapse_level, "measured_best": best["collapse_level"],
+                "model_choice_over_best": chosen[0]["measured_us_per_cycle"] / best["measured_us_per_cycle"]}
     if not args.no_mixed:
         log("bench: mixed precision on the same operator")
         hm = HB.Hierarchy(coeffs, precision=HB.MIXED, collapse_level=args.collapse_level)
@@ -250,7 +256,10 @@ def main():
                                "V(2,1) to rel. residual 1e-10, FP64" % (n, n),
                    "n": n, "cycles": cycles, "levels": info.levels,
                    "collapse_level": info.collapse_level, "setup_ms": info0.setup_ms,
-                   "relres": info.relres},
+                   "relres": info.relres,
+                   "row_blocks": {"down": list(info.rb_down)[: info.levels],
+                                  "up": list(info.rb_up)[: info.levels],
+                                  "pipelined_finest": info.rb_pipelined}},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,

@@ -9,14 +9,84 @@
 // hundred points.  Levels 0..l* therefore run here, inside ONE workgroup of
 // 1024 threads, with a workgroup barrier where the paper's algorithm has a halo
 // exchange (after every colour of Gauss-Seidel, after the residual, the
-// restriction and the interpolation).  All level data stays in global memory
-// (it is small and L2 resident).  The coarsest level is solved with the
-// Cholesky factor computed at setup (section 3, coarse-solve cost), in FP64.
+// restriction and the interpolation).  Levels from the coarsest up are staged
+// in LDS while they fit; the rest are addressed in global memory (L2
+// resident).  The coarsest level is solved with the Cholesky factor computed
+// at setup (section 3, coarse-solve cost), in FP64.
 #include "bmg_internal.h"
 
 namespace hbmg {
 
 constexpr int CWG = 1024;   // threads of the collapse workgroup
+
+// A collapsed level as the workgroup addresses it: operator planes, iterate x,
+// residual scratch r, right-hand side b, and the interpolation weights from
+// the next-coarser level.  A level staged in LDS is laid out at compact pitch
+// (planes C, W, S, SW, SE, x, r, b, then 8 weight planes at the coarse
+// level's size) and its view is built from the workgroup's LDS array where it
+// is used, so every access compiles to an LDS instruction; a level in global
+// memory uses its own arrays.  Views live in registers.
+template <typename T>
+struct CV {
+    int nx, ny, pitch;
+    const T *C, *W, *S, *SW, *SE;
+    T *x, *r, *b;
+    const T *wt;
+    int cpitch, cplane;   // pitch and plane size of the weight planes
+};
+
+template <typename T, bool LDS>
+__device__ __forceinline__ CV<T> cview(const CollapseArgs<T> &a, int l, int xb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LevelDev<T> &g = a.levels[l];
+    CV<T> v;
+    v.nx = g.nx;
+    v.ny = g.ny;
+    if (LDS) {
+        const int n = g.nx * g.ny;
+        T *base = reinterpret_cast<T *>(smem + a.lds_off[l]);
+        v.pitch = g.nx;
+        v.C = base;
+        v.W = base + n;
+        v.S = base + 2 * n;
+        v.SW = base + 3 * n;
+        v.SE = base + 4 * n;
+        v.x = base + 5 * n;
+        v.r = base + 6 * n;
+        v.b = base + 7 * n;
+        v.wt = base + 8 * n;
+        if (l >= 1) {
+            v.cpitch = a.levels[l - 1].nx;
+            v.cplane = a.levels[l - 1].nx * a.levels[l - 1].ny;
+        } else {
+            v.cpitch = v.cplane = 0;
+        }
+    } else {
+        v.pitch = g.pitch;
+        v.C = g.C;
+        v.W = g.W;
+        v.S = g.S;
+        v.SW = g.SW;
+        v.SE = g.SE;
+        v.x = g.x[xb];
+        v.r = g.x[1 - xb];
+        v.b = g.b;
+        v.wt = g.wt;
+        v.cpitch = g.cpitch;
+        v.cplane = (int)g.cplane;
+    }
+    return v;
+}
+
+// idx / n for 0 <= idx < 2^24 from a float reciprocal, corrected to exact
+__device__ __forceinline__ int quot(int idx, int n, float rn)
+{
+    int q = (int)((float)idx * rn);
+    if (q * n > idx) --q;
+    else if ((q + 1) * n <= idx) ++q;
+    return q;
+}
 
 // Residual (b - A x)_p at interior vertex p and the diagonal used by the
 // relaxation (9-point form; the SW/SE planes of a 5-point level are zero).
@@ -26,9 +96,9 @@ template <typename T> struct EdgeForm { enum { value = 0 }; };
 template <> struct EdgeForm<float> { enum { value = 1 }; };
 
 template <typename T>
-__device__ __forceinline__ T point_res(const LevelDev<T> &L, const T *__restrict__ x, size_t p, T &diag)
+__device__ __forceinline__ T point_res(const CV<T> &L, const T *x, int p, T &diag)
 {
-    const size_t P = L.pitch;
+    const int P = L.pitch;
     const T cw = L.W[p], ce = L.W[p + 1], cs = L.S[p], cn = L.S[p + P];
     const T csw = L.SW[p], cne = L.SW[p + P + 1], cse = L.SE[p], cnw = L.SE[p + P - 1];
     const T xp = x[p];
@@ -47,10 +117,10 @@ __device__ __forceinline__ T point_res(const LevelDev<T> &L, const T *__restrict
 }
 
 template <typename T>
-__device__ __forceinline__ T point_diag(const LevelDev<T> &L, size_t p)
+__device__ __forceinline__ T point_diag(const CV<T> &L, int p)
 {
     if (!EdgeForm<T>::value) return L.C[p];
-    const size_t P = L.pitch;
+    const int P = L.pitch;
     return L.W[p] + L.W[p + 1] + L.S[p] + L.S[p + P] + L.C[p] + L.SW[p] + L.SW[p + P + 1] + L.SE[p] +
            L.SE[p + P - 1];
 }
@@ -59,78 +129,86 @@ __device__ __forceinline__ int count_par(int lo, int hi) { return hi >= lo ? (hi
 
 // one colour of Gauss-Seidel: colour k has (i mod 2, j mod 2) = (k & 1, k >> 1)
 template <typename T>
-__device__ void gs_colour(const LevelDev<T> &L, T *__restrict__ x, int k)
+__device__ __forceinline__ void gs_colour(const CV<T> &L, int k)
 {
     const int i0 = (k & 1) ? 1 : 2, j0 = (k >> 1) ? 1 : 2;
     const int ni = count_par(i0, L.nx - 2), nj = count_par(j0, L.ny - 2);
+    const float rni = 1.0f / (float)ni;
     for (int idx = threadIdx.x; idx < ni * nj; idx += CWG) {
-        const int i = i0 + 2 * (idx % ni), j = j0 + 2 * (idx / ni);
-        const size_t p = (size_t)j * L.pitch + i;
+        const int jj = quot(idx, ni, rni);
+        const int i = i0 + 2 * (idx - jj * ni), j = j0 + 2 * jj;
+        const int p = j * L.pitch + i;
         T d;
-        const T r = point_res(L, x, p, d);
-        x[p] += r / d;
+        const T r = point_res(L, L.x, p, d);
+        L.x[p] += r / d;
     }
 }
 
 template <typename T>
-__device__ void zero_interior(const LevelDev<T> &L, T *__restrict__ x)
+__device__ __forceinline__ void zero_interior(const CV<T> &L)
 {
     const int ni = L.nx - 2, n = ni * (L.ny - 2);
-    for (int idx = threadIdx.x; idx < n; idx += CWG)
-        x[(size_t)(1 + idx / ni) * L.pitch + 1 + idx % ni] = T(0);
+    const float rni = 1.0f / (float)ni;
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int jj = quot(idx, ni, rni);
+        L.x[(1 + jj) * L.pitch + 1 + idx - jj * ni] = T(0);
+    }
 }
 
+// r = b - A x on the interior; returns this thread's share of ||r||^2
 template <typename T>
-__device__ double residual(const LevelDev<T> &L, const T *__restrict__ x, T *__restrict__ r)
+__device__ __forceinline__ double residual(const CV<T> &L)
 {
     const int ni = L.nx - 2, n = ni * (L.ny - 2);
+    const float rni = 1.0f / (float)ni;
     double acc = 0.0;
     for (int idx = threadIdx.x; idx < n; idx += CWG) {
-        const size_t p = (size_t)(1 + idx / ni) * L.pitch + 1 + idx % ni;
+        const int jj = quot(idx, ni, rni);
+        const int p = (1 + jj) * L.pitch + 1 + idx - jj * ni;
         T d;
-        const T v = point_res(L, x, p, d);
-        r[p] = v;
+        const T v = point_res(L, L.x, p, d);
+        L.r[p] = v;
         acc += (double)v * v;
     }
     return acc;
 }
 
-// b_c = P^T r on the interior coarse vertices.  The weights use the fine
-// view's coarse pitch and the coarse arrays the coarse view's pitch (they
-// differ when only one of the two levels is staged in LDS).
+// b_c = P^T r on the interior coarse vertices (weights in F's weight planes)
 template <typename T>
-__device__ void restrict_pt(const LevelDev<T> &F, const T *__restrict__ r, const LevelDev<T> &Cl)
+__device__ __forceinline__ void restrict_pt(const CV<T> &F, const CV<T> &Cl)
 {
     const int ni = Cl.nx - 2, n = ni * (Cl.ny - 2);
-    const size_t cp = F.cplane, WP = F.cpitch;
-    const T *w = F.wt;
+    const float rni = 1.0f / (float)ni;
+    const int cp = F.cplane, WP = F.cpitch, P = F.pitch;
+    const T *w = F.wt, *r = F.r;
     for (int idx = threadIdx.x; idx < n; idx += CWG) {
-        const int I = 1 + idx % ni, J = 1 + idx / ni;
-        const size_t P = F.pitch;
-        const size_t f = (size_t)(2 * J) * P + 2 * I;
-        const size_t c = (size_t)J * WP + I;
-        const size_t cW = c - 1, cS = c - WP, cSW = c - WP - 1;
+        const int jj = quot(idx, ni, rni);
+        const int I = 1 + idx - jj * ni, J = 1 + jj;
+        const int f = 2 * J * P + 2 * I;
+        const int c = J * WP + I;
+        const int cW = c - 1, cS = c - WP, cSW = c - WP - 1;
         T v = r[f] + w[WXL * cp + c] * r[f + 1] + w[WXR * cp + cW] * r[f - 1] +
               w[WYB * cp + c] * r[f + P] + w[WYT * cp + cS] * r[f - P] +
               w[WCSW * cp + c] * r[f + P + 1] + w[WCSE * cp + cW] * r[f + P - 1] +
               w[WCNW * cp + cS] * r[f - P + 1] + w[WCNE * cp + cSW] * r[f - P - 1];
-        Cl.b[(size_t)J * Cl.pitch + I] = v;
+        Cl.b[J * Cl.pitch + I] = v;
     }
 }
 
-// x += P x_c (+ r/C at fine-only vertices)
+// x += P x_c (+ r/C at fine-only vertices); x_c is the coarse view's iterate
 template <typename T>
-__device__ void interp_correct(const LevelDev<T> &F, T *__restrict__ x, const T *__restrict__ r,
-                               const LevelDev<T> &Cl, const T *__restrict__ xc, int rescorr)
+__device__ __forceinline__ void interp_correct(const CV<T> &F, const CV<T> &Cl, int rescorr)
 {
     const int ni = F.nx - 2, n = ni * (F.ny - 2);
-    const size_t cp = F.cplane, WP = F.cpitch, CP = Cl.pitch;
-    const T *w = F.wt;
+    const float rni = 1.0f / (float)ni;
+    const int cp = F.cplane, WP = F.cpitch, CP = Cl.pitch;
+    const T *w = F.wt, *xc = Cl.x;
     for (int idx = threadIdx.x; idx < n; idx += CWG) {
-        const int i = 1 + idx % ni, j = 1 + idx / ni;
-        const size_t p = (size_t)j * F.pitch + i;
-        const size_t c = (size_t)(j >> 1) * CP + (i >> 1);
-        const size_t cw = (size_t)(j >> 1) * WP + (i >> 1);
+        const int jj = quot(idx, ni, rni);
+        const int i = 1 + idx - jj * ni, j = 1 + jj;
+        const int p = j * F.pitch + i;
+        const int c = (j >> 1) * CP + (i >> 1);
+        const int cw = (j >> 1) * WP + (i >> 1);
         T v;
         if (!(i & 1) && !(j & 1)) {
             v = xc[c];
@@ -142,9 +220,9 @@ __device__ void interp_correct(const LevelDev<T> &F, T *__restrict__ x, const T 
             else
                 v = w[WCSW * cp + cw] * xc[c] + w[WCSE * cp + cw] * xc[c + 1] +
                     w[WCNW * cp + cw] * xc[c + CP] + w[WCNE * cp + cw] * xc[c + CP + 1];
-            if (rescorr) v += r[p] / point_diag(F, p);
+            if (rescorr) v += F.r[p] / point_diag(F, p);
         }
-        x[p] += v;
+        F.x[p] += v;
     }
 }
 
@@ -175,154 +253,166 @@ size_t collapse_lds_bytes(int nx, int ny, int cnx, int cny)
 template size_t collapse_lds_bytes<double>(int, int, int, int);
 template size_t collapse_lds_bytes<float>(int, int, int, int);
 
+// Down leg on level l (fine view in LDS if FL, its coarse level if CL):
+// relaxations, residual, restriction onto level l-1.
+template <typename T, bool FL, bool CL>
+__device__ void level_down(const CollapseArgs<T> &a, int l)
+{
+    const int xb = l == a.top ? a.xb_top : 1;
+    const CV<T> F = cview<T, FL>(a, l, xb), Cl = cview<T, CL>(a, l - 1, 1);
+    if (l < a.top || a.zero_top) {
+        zero_interior(F);
+        __syncthreads();
+    }
+    for (int s = 0; s < a.nu1; ++s)
+        for (int k = 0; k < 4; ++k) {
+            gs_colour(F, k);
+            __syncthreads();
+        }
+    residual(F);
+    __syncthreads();
+    restrict_pt(F, Cl);
+    __syncthreads();
+}
+
+// Up leg on level l: interpolate and correct from level l-1, relax.
+template <typename T, bool FL, bool CL>
+__device__ void level_up(const CollapseArgs<T> &a, int l)
+{
+    const int xb = l == a.top ? a.xb_top : 1;
+    const CV<T> F = cview<T, FL>(a, l, xb), Cl = cview<T, CL>(a, l - 1, 1);
+    interp_correct(F, Cl, a.rescorr);
+    __syncthreads();
+    for (int s = 0; s < a.nu2; ++s)
+        for (int k = 0; k < 4; ++k) {
+            gs_colour(F, k);
+            __syncthreads();
+        }
+}
+
+// coarsest level: Cholesky solve in FP64 (column-oriented substitutions)
+template <typename T, bool LDS>
+__device__ void coarse_solve(const CollapseArgs<T> &a)
+{
+    const CV<T> L0 = cview<T, LDS>(a, 0, a.top == 0 ? a.xb_top : 1);
+    const int nc = a.nc;
+    double *y = a.work;
+    const int ni = L0.nx - 2, n = ni * (L0.ny - 2);
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int i = 1 + idx % ni, j = 1 + idx / ni;
+        const int k = a.cidx[j * L0.nx + i];
+        y[k] = (double)L0.b[j * L0.pitch + i];
+    }
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {            // L y = b
+        const double yk = y[k] / a.chol[(size_t)k * nc + k];
+        for (int m = k + 1 + threadIdx.x; m < nc; m += CWG) y[m] -= a.chol[(size_t)m * nc + k] * yk;
+        __syncthreads();
+        if (threadIdx.x == 0) y[k] = yk;
+        __syncthreads();
+    }
+    for (int k = nc - 1; k >= 0; --k) {       // L^T x = y
+        const double xk = y[k] / a.chol[(size_t)k * nc + k];
+        for (int m = threadIdx.x; m < k; m += CWG) y[m] -= a.chol[(size_t)k * nc + m] * xk;
+        __syncthreads();
+        if (threadIdx.x == 0) y[k] = xk;
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int i = 1 + idx % ni, j = 1 + idx / ni;
+        L0.x[j * L0.pitch + i] = (T)y[a.cidx[j * L0.nx + i]];
+    }
+    __syncthreads();
+}
+
+// stage level l into LDS: operator and weights; iterate and residual zero;
+// the top level's right-hand side (and iterate) from global memory
+template <typename T>
+__device__ void stage_in(const CollapseArgs<T> &a, int l)
+{
+    const LevelDev<T> &g = a.levels[l];
+    const CV<T> v = cview<T, true>(a, l, 1);
+    const int nx = g.nx, n = g.nx * g.ny, top = a.top;
+    const T *xg = g.x[l == top ? a.xb_top : 1];
+    const float rnx = 1.0f / (float)nx;
+    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+        const int jj = quot(idx, nx, rnx);
+        const size_t gp = (size_t)jj * g.pitch + (idx - jj * nx);
+        const_cast<T *>(v.C)[idx] = g.C[gp];
+        const_cast<T *>(v.W)[idx] = g.W[gp];
+        const_cast<T *>(v.S)[idx] = g.S[gp];
+        const_cast<T *>(v.SW)[idx] = g.SW[gp];
+        const_cast<T *>(v.SE)[idx] = g.SE[gp];
+        v.r[idx] = T(0);
+        if (l == top) {
+            v.b[idx] = g.b[gp];
+            v.x[idx] = a.zero_top ? T(0) : xg[gp];
+        } else {
+            v.b[idx] = T(0);
+            v.x[idx] = T(0);
+        }
+    }
+    if (l >= 1) {
+        const LevelDev<T> &c = a.levels[l - 1];
+        const int cnx = c.nx, cn = c.nx * c.ny;
+        const float rcnx = 1.0f / (float)cnx;
+        T *wt = const_cast<T *>(v.wt);
+        for (int k = 0; k < 8; ++k)
+            for (int idx = threadIdx.x; idx < cn; idx += CWG) {
+                const int jj = quot(idx, cnx, rcnx);
+                wt[k * cn + idx] = g.wt[k * g.cplane + (size_t)jj * g.cpitch + (idx - jj * cnx)];
+            }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void collapse_body(const CollapseArgs<T> &a)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sh[CWG / 64];
-    __shared__ LevelDev<T> V[COLLAPSE_MAX_LEVELS];
     const int top = a.top;
-    // level views: levels 0..lds_top live in LDS at compact pitch
-    if (threadIdx.x == 0) {
-        for (int l = 0; l <= top; ++l) {
-            LevelDev<T> v = a.levels[l];
-            if (l <= a.lds_top) {
-                T *base = reinterpret_cast<T *>(smem + a.lds_off[l]);
-                const size_t n = (size_t)v.nx * v.ny;
-                v.pitch = v.nx;
-                v.plane = n;
-                v.C = base;
-                v.W = base + n;
-                v.S = base + 2 * n;
-                v.SW = base + 3 * n;
-                v.SE = base + 4 * n;
-                const int xb = l == top ? a.xb_top : 1;
-                v.x[xb] = base + 5 * n;
-                v.x[1 - xb] = base + 6 * n;
-                v.b = base + 7 * n;
-                v.q = nullptr;
-                if (l >= 1) {
-                    const LevelDev<T> &c = a.levels[l - 1];
-                    v.wt = base + 8 * n;
-                    v.cpitch = c.nx;
-                    v.cplane = (size_t)c.nx * c.ny;
-                }
-            }
-            V[l] = v;
-        }
-    }
+    for (int l = 0; l <= a.lds_top; ++l) stage_in(a, l);
     __syncthreads();
-    // stage the LDS levels in: operator, weights; zero iterate and residual;
-    // the top level's right-hand side (and iterate) come from global memory
-    for (int l = 0; l <= a.lds_top; ++l) {
-        const LevelDev<T> &g = a.levels[l];
-        const LevelDev<T> &v = V[l];
-        const int nx = g.nx, n = g.nx * g.ny;
-        const int xb = l == top ? a.xb_top : 1;
-        for (int idx = threadIdx.x; idx < n; idx += CWG) {
-            const size_t gp = (size_t)(idx / nx) * g.pitch + idx % nx;
-            v.C[idx] = g.C[gp];
-            v.W[idx] = g.W[gp];
-            v.S[idx] = g.S[gp];
-            v.SW[idx] = g.SW[gp];
-            v.SE[idx] = g.SE[gp];
-            v.x[1 - xb][idx] = T(0);
-            if (l == top) {
-                v.b[idx] = g.b[gp];
-                v.x[xb][idx] = a.zero_top ? T(0) : g.x[xb][gp];
-            } else {
-                v.b[idx] = T(0);
-                v.x[xb][idx] = T(0);
-            }
-        }
-        if (l >= 1) {
-            const int cnx = a.levels[l - 1].nx, cn = cnx * a.levels[l - 1].ny;
-            for (int k = 0; k < 8; ++k)
-                for (int idx = threadIdx.x; idx < cn; idx += CWG)
-                    v.wt[k * cn + idx] = g.wt[k * g.cplane + (size_t)(idx / cnx) * g.cpitch + idx % cnx];
-        }
-    }
-    __syncthreads();
-
-    // down: relax, residual, restrict
+    // down: relax, residual, restrict (levels fill LDS from the coarsest up,
+    // so a staged level's coarser neighbour is staged too)
     for (int l = top; l >= 1; --l) {
-        const LevelDev<T> &L = V[l];
-        const int xb = l == top ? a.xb_top : 1;
-        T *x = L.x[xb], *r = L.x[1 - xb];
-        if (l < top || a.zero_top) {
-            zero_interior(L, x);
-            __syncthreads();
-        }
-        for (int s = 0; s < a.nu1; ++s)
-            for (int k = 0; k < 4; ++k) {
-                gs_colour(L, x, k);
-                __syncthreads();
-            }
-        residual(L, x, r);
-        __syncthreads();
-        restrict_pt(L, r, V[l - 1]);
-        __syncthreads();
+        if (l <= a.lds_top)
+            level_down<T, true, true>(a, l);
+        else if (l - 1 <= a.lds_top)
+            level_down<T, false, true>(a, l);
+        else
+            level_down<T, false, false>(a, l);
     }
-    // coarsest: Cholesky solve in FP64 (column-oriented substitutions)
-    {
-        const LevelDev<T> &L0 = V[0];
-        T *x0 = L0.x[top == 0 ? a.xb_top : 1];
-        const int nc = a.nc;
-        double *y = a.work;
-        const int ni = L0.nx - 2, n = ni * (L0.ny - 2);
-        for (int idx = threadIdx.x; idx < n; idx += CWG) {
-            const int i = 1 + idx % ni, j = 1 + idx / ni;
-            const int k = a.cidx[j * L0.nx + i];
-            y[k] = (double)L0.b[(size_t)j * L0.pitch + i];
-        }
-        __syncthreads();
-        for (int k = 0; k < nc; ++k) {            // L y = b
-            const double yk = y[k] / a.chol[(size_t)k * nc + k];
-            for (int m = k + 1 + threadIdx.x; m < nc; m += CWG) y[m] -= a.chol[(size_t)m * nc + k] * yk;
-            __syncthreads();
-            if (threadIdx.x == 0) y[k] = yk;
-            __syncthreads();
-        }
-        for (int k = nc - 1; k >= 0; --k) {       // L^T x = y
-            const double xk = y[k] / a.chol[(size_t)k * nc + k];
-            for (int m = threadIdx.x; m < k; m += CWG) y[m] -= a.chol[(size_t)k * nc + m] * xk;
-            __syncthreads();
-            if (threadIdx.x == 0) y[k] = xk;
-            __syncthreads();
-        }
-        for (int idx = threadIdx.x; idx < n; idx += CWG) {
-            const int i = 1 + idx % ni, j = 1 + idx / ni;
-            x0[(size_t)j * L0.pitch + i] = (T)y[a.cidx[j * L0.nx + i]];
-        }
-        __syncthreads();
-    }
+    if (a.lds_top >= 0)
+        coarse_solve<T, true>(a);
+    else
+        coarse_solve<T, false>(a);
     // up: interpolate and correct, relax
     for (int l = 1; l <= top; ++l) {
-        const LevelDev<T> &L = V[l];
-        const int xb = l == top ? a.xb_top : 1;
-        T *x = L.x[xb], *r = L.x[1 - xb];
-        interp_correct(L, x, r, V[l - 1], V[l - 1].x[1], a.rescorr);
-        __syncthreads();
-        for (int s = 0; s < a.nu2; ++s)
-            for (int k = 0; k < 4; ++k) {
-                gs_colour(L, x, k);
-                __syncthreads();
-            }
+        if (l <= a.lds_top)
+            level_up<T, true, true>(a, l);
+        else if (l - 1 <= a.lds_top)
+            level_up<T, false, true>(a, l);
+        else
+            level_up<T, false, false>(a, l);
     }
-    const LevelDev<T> &Lt = V[top];
-    if (a.want_norm) {
-        double v = residual(Lt, Lt.x[a.xb_top], Lt.x[1 - a.xb_top]);
-        v = block_sum(v, sh);
-        if (threadIdx.x == 0) a.partials[0] = v;
-    }
-    // the top level's iterate goes back to global memory when it was staged
     if (top <= a.lds_top) {
+        const CV<T> Lt = cview<T, true>(a, top, a.xb_top);
+        if (a.want_norm) {
+            const double v = block_sum(residual(Lt), sh);
+            if (threadIdx.x == 0) a.partials[0] = v;
+        }
+        // the top level's iterate goes back to global memory
         const LevelDev<T> &g = a.levels[top];
         const int ni = g.nx - 2, n = ni * (g.ny - 2);
+        T *xg = g.x[a.xb_top];
         for (int idx = threadIdx.x; idx < n; idx += CWG) {
             const int i = 1 + idx % ni, j = 1 + idx / ni;
-            g.x[a.xb_top][(size_t)j * g.pitch + i] = Lt.x[a.xb_top][(size_t)j * Lt.pitch + i];
+            xg[(size_t)j * g.pitch + i] = Lt.x[j * Lt.pitch + i];
         }
+    } else if (a.want_norm) {
+        const CV<T> Lt = cview<T, false>(a, top, a.xb_top);
+        const double v = block_sum(residual(Lt), sh);
+        if (threadIdx.x == 0) a.partials[0] = v;
     }
 }
 

@@ -572,6 +572,19 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     model_levels(h, prm.precision == HIPBMG_MIXED, ml);
     int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc, prm.precision == HIPBMG_MIXED ? 4 : 8,
                             model_params(), h->model_us);
+    // the collapse workgroup indexes a level's planes with 32-bit integers
+    int lcap = -1;
+    for (int l = 0; l < L; ++l) {
+        if (h->lv[l].plane > (size_t)(1 << 30) || 8 * h->lv[l].cplane > (size_t)(1 << 30)) break;
+        lcap = l;
+    }
+    if (prm.collapse_level > lcap)
+        return bail(fail(HIPBMG_EINVAL, "collapse_level %d: level too large for one workgroup", prm.collapse_level));
+    if (best > lcap) {
+        best = 0;
+        for (int l = 1; l <= lcap; ++l)
+            if (h->model_us[l] < h->model_us[best]) best = l;
+    }
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
     if (h->lstar >= L - 1) h->fused3 = 0;   // the finest level itself is collapsed
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
