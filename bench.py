@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--collapse-level", type=int, default=-1)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the batched adjoint workload")
+    ap.add_argument("--adjoint-batch", type=int, default=64, help="problems in the adjoint workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip timing each forced collapse level against the model")
     args = ap.parse_args()
@@ -221,6 +223,47 @@ def main():
         log("bench: batched %.1f problems/s (%.2f ms per batch)" % (args.steps * args.batch / el_b,
                                                                    1e3 * el_b / args.steps))
         del bh, cs, bs, us
+
+    if not args.no_adjoint:
+        # gradient of 0.5 ||u(theta) - u_obs||^2 for a batch of problems:
+        # theta = per-cell ln D, 5x5 box-filtered N(0,1); u_obs from a second
+        # theta; forward and adjoint batched FP64 solves to 1e-10 and the
+        # per-cell gradient kernel (hierarchy setup included: theta changes
+        # every step of an optimisation)
+        nb, m = args.adjoint_batch, 1025
+        log("bench: adjoint workload (%d problems of %d^2)" % (nb, m))
+        th0 = torch.stack([torch.from_numpy(inputs.theta_box5(m, m, seed=3000 + k)) for k in range(nb)]).to(dev)
+        tho = torch.stack([torch.from_numpy(inputs.theta_box5(m, m, seed=4000 + k)) for k in range(nb)]).to(dev)
+        ba = torch.stack([torch.from_numpy(inputs.load_uniform(m, m, seed=5000 + k)) for k in range(nb)]).to(dev)
+        with torch.no_grad():
+            u_obs = HB.SolveFVBatched.apply(tho, ba, TOL)
+        del tho
+
+        def grad_step():
+            th = th0.clone().requires_grad_(True)
+            ua = HB.SolveFVBatched.apply(th, ba, TOL)
+            loss = 0.5 * ((ua - u_obs) ** 2).sum()
+            loss.backward()
+            return th.grad
+
+        grad_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gth = grad_step()
+        torch.cuda.synchronize()
+        el_a = time.perf_counter() - t0
+        extra["adjoint"] = {
+            "workload": "%d problems of %dx%d, theta = box5(N(0,1)) per cell (seeds 3000+k), u_obs from "
+                        "seeds 4000+k, loss 0.5||u-u_obs||^2, FP64 forward + adjoint to 1e-10, setup "
+                        "included" % (nb, m, m),
+            "gradients_per_s": args.steps * nb / el_a,
+            "ms_per_batch": 1e3 * el_a / args.steps,
+            "grad_abs_max": float(gth.abs().max()),
+        }
+        log("bench: adjoint %.1f gradients/s (%.1f ms per batch of %d)"
+            % (args.steps * nb / el_a, 1e3 * el_a / args.steps, nb))
+        del th0, ba, u_obs, gth
 
     cpu = None
     if not args.no_cpu:

@@ -317,3 +317,38 @@ class SolveFV(torch.autograd.Function):
         g_theta = grad_logD(theta.detach().contiguous(), u, lam)
         ctx.hier.close()
         return g_theta, lam, None, None
+
+
+class SolveFVBatched(torch.autograd.Function):
+    """u_k = A(theta_k)^{-1} b_k for a batch of problems of one size
+    (theta: [B, ny-1, nx-1] per-cell ln D, b: [B, ny, nx]).  Forward: one
+    hierarchy per problem, all problems solved together by the batched solver.
+    Backward: the adjoint problems A(theta_k) lambda_k = dL/du_k, batched on the
+    same hierarchies (A is symmetric), then the per-cell gradient kernel."""
+
+    @staticmethod
+    def forward(ctx, theta, b, tol=1e-10, params=None):
+        th = theta.detach().contiguous()
+        bb = b.detach().contiguous()
+        nb = th.shape[0]
+        coeffs = [fv5_from_cells(th[k], is_log=True) for k in range(nb)]
+        hier = BatchHierarchy(coeffs, **(params or {}))
+        del coeffs
+        u = torch.zeros_like(bb)
+        hier.solve([bb[k] for k in range(nb)], [u[k] for k in range(nb)], tol=tol)
+        ctx.hier = hier
+        ctx.tol = tol
+        ctx.save_for_backward(theta, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        theta, u = ctx.saved_tensors
+        gu = grad_u.contiguous()
+        nb = gu.shape[0]
+        lam = torch.zeros_like(gu)
+        ctx.hier.solve([gu[k] for k in range(nb)], [lam[k] for k in range(nb)], tol=ctx.tol)
+        th = theta.detach().contiguous()
+        g_theta = torch.stack([grad_logD(th[k], u[k], lam[k]) for k in range(nb)])
+        ctx.hier.close()
+        return g_theta, lam, None, None

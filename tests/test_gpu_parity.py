@@ -668,3 +668,83 @@ def test_cycles_enqueued_ahead_do_not_change_the_solve(pipelined, monkeypatch):
     with pytest.raises(HB.HipBMGError) as ei:
         HB.Hierarchy(planes, max_cycles=c - 1).solve(b, tol=1e-10)
     assert ei.value.status == HB.ENOCONV
+
+
+def test_adjoint_full_size_matches_oracle_gradient_and_central_differences():
+    # one problem of the 1025^2 adjoint workload: theta = box5(N(0,1)) per
+    # cell, u_obs from a second theta, loss 0.5 ||u - u_obs||^2
+    n = 1025
+    theta = inputs.theta_box5(n, n, seed=3000)
+    b = inputs.load_uniform(n, n, seed=5000)
+    u_obs, _ = O.Hierarchy(O.fv5(np.exp(inputs.theta_box5(n, n, seed=4000)))).solve(b, tol=1e-12)
+    ora = O.Hierarchy(O.fv5(np.exp(theta)))
+    uo, _ = ora.solve(b, tol=1e-12)
+    lam, _ = ora.solve(uo - u_obs, tol=1e-12)
+    go = O.grad_logD(np.exp(theta), uo, lam)
+    del ora
+    # forward and adjoint solves to 1e-10, as the workload specifies (the
+    # adjoint's small right-hand side puts its rounding floor near 3e-12)
+    th = g(theta).requires_grad_(True)
+    u = HB.SolveFV.apply(th, g(b), 1e-10)
+    loss = 0.5 * ((u - g(u_obs)) ** 2).sum()
+    loss.backward()
+    grad = c(th.grad)
+    e = rel(grad, go)
+    print("gradient vs oracle: max rel difference %.3e" % e, flush=True)
+    assert e <= 1e-6, e
+    # central differences, h = 1e-6, on 32 random cells.  Each loss comes from
+    # a solve started at the unperturbed solution and run to the rounding
+    # floor; the loss's evaluation noise is measured by evaluating it at theta
+    # from two different starting points, and each difference quotient must
+    # agree with the gradient within 1e-4 relative plus ten times that noise
+    # over 2h
+    ub, uog = g(b), g(u_obs)
+    hier0 = HB.Hierarchy(HB.fv5_from_cells(g(theta), is_log=True), max_cycles=300)
+    u_star, _ = hier0.solve(ub, tol=1e-14, check=False)
+    u_zero, _ = hier0.solve(ub, torch.zeros_like(ub), tol=1e-14, check=False)
+
+    def loss_of(uu):
+        return 0.5 * float(((uu - uog) ** 2).sum())
+
+    def loss_at(tp):
+        hier = HB.Hierarchy(HB.fv5_from_cells(g(tp), is_log=True), max_cycles=300)
+        uu, _ = hier.solve(ub, u_star.clone(), tol=1e-14, check=False)
+        return loss_of(uu)
+
+    noise = abs(loss_at(theta) - loss_of(u_zero)) + 1e-300
+    h = 1e-6
+    rng = np.random.default_rng(6000)
+    worst, resolved = 0.0, 0
+    for cj, ci in rng.integers(0, n - 1, size=(32, 2)):
+        fd = (loss_at(np.where(np.arange(theta.size).reshape(theta.shape) == cj * (n - 1) + ci, theta + h, theta))
+              - loss_at(np.where(np.arange(theta.size).reshape(theta.shape) == cj * (n - 1) + ci, theta - h, theta))
+              ) / (2 * h)
+        gk = float(grad[cj, ci])
+        bound = 1e-4 * abs(gk) + 10.0 * noise / (2 * h)
+        print("cell (%4d,%4d): gradient % .6e  central difference % .6e  bound %.2e"
+              % (cj, ci, gk, fd, bound), flush=True)
+        worst = max(worst, abs(fd - gk) / bound)
+        resolved += abs(gk) > 100.0 * noise / (2 * h)
+    print("loss noise %.3e; %d of 32 cells resolved to 1%%; worst difference / bound %.3f"
+          % (noise, resolved, worst), flush=True)
+    assert worst <= 1.0, worst
+    assert resolved >= 16, resolved
+
+
+def test_batched_adjoint_equals_single_problem_adjoint():
+    n, nb = 129, 3
+    theta = np.stack([inputs.theta_box5(n, n, seed=3100 + k) for k in range(nb)])
+    b = np.stack([inputs.load_uniform(n, n, seed=5100 + k) for k in range(nb)])
+    u_obs = np.stack([O.Hierarchy(O.fv5(np.exp(inputs.theta_box5(n, n, seed=4100 + k)))).solve(b[k], tol=1e-12)[0]
+                      for k in range(nb)])
+    th = g(theta).requires_grad_(True)
+    u = HB.SolveFVBatched.apply(th, g(b), 1e-10)
+    (0.5 * ((u - g(u_obs)) ** 2).sum()).backward()
+    gb = c(th.grad)
+    for k in range(nb):
+        t1 = g(theta[k]).requires_grad_(True)
+        u1 = HB.SolveFV.apply(t1, g(b[k]), 1e-10)
+        (0.5 * ((u1 - g(u_obs[k])) ** 2).sum()).backward()
+        d = rel(gb[k], c(t1.grad))
+        print("problem %d: batched vs single gradient %.3e" % (k, d), flush=True)
+        assert d <= 1e-6, d
