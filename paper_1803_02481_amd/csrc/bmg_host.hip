@@ -7,6 +7,7 @@
 #include "bmg_model.h"
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -1449,7 +1450,16 @@ struct BPlan {
     bool built = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<void *> allocs;   // device tables of the launches
 };
+
+static void drop_plan(BPlan &p)
+{
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    for (void *q : p.allocs) (void)hipFree(q);
+    p = BPlan{};
+}
 
 struct hipbmg_batch {
     int n = 0;
@@ -1472,6 +1482,8 @@ struct hipbmg_batch {
     int *h_active = nullptr, *h_count = nullptr;
     int max_nx = 0, max_ny = 0, fine_npt = 5;
     BPlan plan64[2], plan32[2][2];
+    int rb_cap = 0;                           // row blocks of the batched launches (0: per-level rule)
+    std::vector<void *> seg_allocs;           // norm segment tables (rebuilt with the plans)
     hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     ~hipbmg_batch()
@@ -1479,13 +1491,10 @@ struct hipbmg_batch {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (ws) (void)hipStreamDestroy(ws);
-        auto drop = [](BPlan &p) {
-            if (p.exec) (void)hipGraphExecDestroy(p.exec);
-            if (p.graph) (void)hipGraphDestroy(p.graph);
-        };
-        for (auto &p : plan64) drop(p);
+        for (auto &p : plan64) drop_plan(p);
         for (auto &q : plan32)
-            for (auto &p : q) drop(p);
+            for (auto &p : q) drop_plan(p);
+        for (void *p : seg_allocs) (void)hipFree(p);
         for (void *p : allocs) (void)hipFree(p);
         if (h_relres) (void)hipHostFree(h_relres);
         if (h_active) (void)hipHostFree(h_active);
@@ -1495,17 +1504,23 @@ struct hipbmg_batch {
 };
 
 template <typename T>
-static hipbmg_status balloc(hipbmg_batch *B, T **p, size_t n, hipStream_t s)
+static hipbmg_status balloc_to(std::vector<void *> &owner, T **p, size_t n, hipStream_t s)
 {
     void *q = nullptr;
     if (hipMalloc(&q, n * sizeof(T) + 64) != hipSuccess) {
         (void)hipGetLastError();
         return fail(HIPBMG_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
     }
-    B->allocs.push_back(q);
+    owner.push_back(q);
     HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 64, s));
     *p = static_cast<T *>(q);
     return HIPBMG_OK;
+}
+
+template <typename T>
+static hipbmg_status balloc(hipbmg_batch *B, T **p, size_t n, hipStream_t s)
+{
+    return balloc_to(B->allocs, p, n, s);
 }
 
 template <typename T>
@@ -1526,12 +1541,13 @@ const LevelDev<float> *dlevels_of<float>(hipbmg_hier *h) { return h->d_lv32; }
 // of 64, 32, ... 4 that gives a level 1024 tiles of its own keeps the
 // prologue overhead low.
 template <typename T>
-static int batch_rb(const LevelDev<T> &A)
+static int batch_rb(const hipbmg_batch *B, const LevelDev<T> &A)
 {
     if (const char *e = std::getenv("HIPBMG_RB")) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 4096) return v;
     }
+    if (B->rb_cap > 0) return std::max(1, std::min(B->rb_cap, (A.ny - 1) / 2));
     return pick_rb(A.nx, A.ny, A.npt);
 }
 
@@ -1568,7 +1584,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
                 const bool last = k == nk, zx = zero && k == 1, two = last && nk < nu1;
                 const int v = last ? (two ? (zx ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ) : (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ))
                                    : (zx ? SV_SWEEP_ZX : SV_SWEEP);
-                StreamArgs<T> a = base_args(A, batch_rb(A));
+                StreamArgs<T> a = base_args(A, batch_rb(B, A));
                 a.x_in = A.x[xb];
                 a.x_out = A.x[1 - xb];
                 if (last) {
@@ -1603,7 +1619,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             for (int k = 1; k <= nu2; ++k) {
                 const bool first = k == 1, last = k == nu2;
                 const int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP) : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
-                StreamArgs<T> a = base_args(A, batch_rb(A));
+                StreamArgs<T> a = base_args(A, batch_rb(B, A));
                 a.x_in = A.x[xb];
                 a.x_out = A.x[1 - xb];
                 if (first) {
@@ -1637,9 +1653,9 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
     // partial-sum segments of the finest norm: the same geometry (hence the
     // same segments) for every plan of the batch, so one buffer serves all
     if (!B->d_partials) {
-        STCHK(balloc(B, &B->d_partials, (size_t)off + 1, s));
-        STCHK(balloc(B, &B->d_poff, n, s));
-        STCHK(balloc(B, &B->d_pcnt, n, s));
+        STCHK(balloc_to(B->seg_allocs, &B->d_partials, (size_t)off + 1, s));
+        STCHK(balloc_to(B->seg_allocs, &B->d_poff, n, s));
+        STCHK(balloc_to(B->seg_allocs, &B->d_pcnt, n, s));
         HIPCHK(hipMemcpyAsync(B->d_poff, poff.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(B->d_pcnt, pcnt.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
         B->n_partials = off;
@@ -1669,8 +1685,8 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
         bl.variant = recs[0].variant;
         StreamArgs<T> *da = nullptr;
         int2 *dm = nullptr;
-        STCHK(balloc(B, &da, n, s));
-        STCHK(balloc(B, &dm, map.size(), s));
+        STCHK(balloc_to(plan.allocs, &da, n, s));
+        STCHK(balloc_to(plan.allocs, &dm, map.size(), s));
         HIPCHK(hipMemcpyAsync(da, args.data(), n * sizeof(StreamArgs<T>), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice, s));
         bl.d_args = da;
@@ -1685,7 +1701,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
         BLaunch bl{};
         bl.kind = 1;
         CollapseArgs<T> *dc = nullptr;
-        STCHK(balloc(B, &dc, n, s));
+        STCHK(balloc_to(plan.allocs, &dc, n, s));
         HIPCHK(hipMemcpyAsync(dc, cargs.data(), n * sizeof(CollapseArgs<T>), hipMemcpyHostToDevice, s));
         bl.d_args = dc;
         bl.lds_bytes = lds_max;
@@ -1757,6 +1773,117 @@ static hipbmg_status batch_read(hipbmg_batch *B, const double *d_vals, const int
     HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return HIPBMG_OK;
+}
+
+// (Re)build every plan of the batch for its current row blocks: FP64 cycles
+// from buffer 0 (and from 1 if a cycle changes the parity); FP32 inner cycles
+// from zero, then from where the previous cycle ended.
+static hipbmg_status build_plans(hipbmg_batch *B, hipStream_t s)
+{
+    HIPCHK(hipStreamSynchronize(s));
+    for (auto &p : B->plan64) drop_plan(p);
+    for (auto &q : B->plan32)
+        for (auto &p : q) drop_plan(p);
+    for (void *q : B->seg_allocs) (void)hipFree(q);
+    B->seg_allocs.clear();
+    B->d_partials = nullptr;
+    B->d_poff = B->d_pcnt = nullptr;
+    B->n_partials = 0;
+    B->h_pcnt.clear();
+    hipbmg_status st = build_plan<double>(B, 0, false, B->plan64[0], s);
+    if (st == HIPBMG_OK && B->plan64[0].end_cur != 0) st = build_plan<double>(B, 1, false, B->plan64[1], s);
+    if (st == HIPBMG_OK && B->prm.precision == HIPBMG_MIXED) {
+        st = build_plan<float>(B, 0, true, B->plan32[1][0], s);
+        const int c1 = B->plan32[1][0].end_cur;
+        if (st == HIPBMG_OK) st = build_plan<float>(B, c1, false, B->plan32[0][c1], s);
+        const int c2 = B->plan32[0][c1].end_cur;
+        if (st == HIPBMG_OK && c2 != c1) st = build_plan<float>(B, c2, false, B->plan32[0][c2], s);
+    }
+    return st;
+}
+
+template <typename T>
+static double time_plan_us(hipbmg_batch *B, BPlan &plan, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    (void)run_plan_launches<T>(B, plan, B->d_active, s);   // warm-up
+    double best = 1e30;
+    for (int r = 0; r < 3; ++r) {
+        (void)hipEventRecord(e0, s);
+        (void)run_plan_launches<T>(B, plan, B->d_active, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, 1e3 * (double)ms);
+    }
+    return best;
+}
+
+// Autotuner of the batched tile shape.  A tile is one wave's strip of column
+// pairs times a block of rb row-pair steps; in a batched launch the tiles of
+// every problem share the device, so the best rb is not the single-problem
+// one.  Each candidate cap on rb (and the single-problem rule) is built into
+// plans and one steady-state V-cycle of the batch is timed (every problem
+// active, on the zero data of a fresh hierarchy); the fastest is kept.  The
+// choice is remembered per batch signature (sizes, stencil, precision,
+// cycle) for the life of the process.  HIPBMG_BATCH_TUNE=0 keeps the
+// single-problem rule.
+static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
+{
+    static std::map<std::string, int> cache;
+    std::vector<std::pair<int, int>> sz;
+    for (hipbmg_hier *h : B->hs) sz.push_back({h->nx, h->ny});
+    std::sort(sz.begin(), sz.end());
+    std::string key = std::to_string(B->fine_npt) + "/" + std::to_string(B->prm.precision) + "/" +
+                      std::to_string(B->prm.nu1) + "," + std::to_string(B->prm.nu2) + ":";
+    for (auto &q : sz) key += std::to_string(q.first) + "x" + std::to_string(q.second) + ";";
+    bool tune = true;
+    if (const char *e = std::getenv("HIPBMG_BATCH_TUNE")) tune = std::atoi(e) != 0;
+    if (!tune) {
+        B->rb_cap = 0;
+        return build_plans(B, s);
+    }
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        B->rb_cap = it->second;
+        return build_plans(B, s);
+    }
+    std::vector<int> ones(B->n, 1);
+    HIPCHK(hipMemcpyAsync(B->d_active, ones.data(), B->n * sizeof(int), hipMemcpyHostToDevice, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(HIPBMG_EHIP, "event creation failed");
+    }
+    const bool mixed = B->prm.precision == HIPBMG_MIXED;
+    int best = 0;
+    double tbest = 1e30;
+    hipbmg_status st = HIPBMG_OK;
+    for (int cap : {0, 1, 2, 4, 8, 16, 32, 64}) {
+        B->rb_cap = cap;
+        if ((st = build_plans(B, s)) != HIPBMG_OK) break;
+        double us;
+        if (mixed) {
+            const int c1 = B->plan32[1][0].end_cur;
+            us = time_plan_us<float>(B, B->plan32[0][c1], s, e0, e1);
+        } else {
+            us = time_plan_us<double>(B, B->plan64[0], s, e0, e1);
+        }
+        if (std::getenv("HIPBMG_VERBOSE"))
+            std::fprintf(stderr, "hipbmg: batch of %d, row-block cap %d: %.1f us per cycle\n", B->n, cap, us);
+        if (us < tbest) {
+            tbest = us;
+            best = cap;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HIPBMG_OK) return st;
+    HIPCHK(hipMemsetAsync(B->d_active, 0, B->n * sizeof(int), s));
+    cache[key] = best;
+    B->rb_cap = best;
+    return build_plans(B, s);
 }
 
 extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const int *ny, int npt,
@@ -1851,17 +1978,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         hipHostMalloc(&B->h_active, nprob * sizeof(int)) != hipSuccess ||
         hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
-    // plans: FP64 from buffer 0 (and from 1 if a cycle changes the parity);
-    // FP32 inner cycles from zero, then from where the previous cycle ended
-    st = build_plan<double>(B, 0, false, B->plan64[0], s);
-    if (st == HIPBMG_OK && B->plan64[0].end_cur != 0) st = build_plan<double>(B, 1, false, B->plan64[1], s);
-    if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) {
-        st = build_plan<float>(B, 0, true, B->plan32[1][0], s);
-        const int c1 = B->plan32[1][0].end_cur;
-        if (st == HIPBMG_OK) st = build_plan<float>(B, c1, false, B->plan32[0][c1], s);
-        const int c2 = B->plan32[0][c1].end_cur;
-        if (st == HIPBMG_OK && c2 != c1) st = build_plan<float>(B, c2, false, B->plan32[0][c2], s);
-    }
+    st = tune_batch(B, s);
     if (st != HIPBMG_OK) return bail(st);
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "batch setup failed"));
     if (hipStreamCreateWithFlags(&B->ws, hipStreamNonBlocking) != hipSuccess ||
@@ -1914,7 +2031,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         if (infos) {
             memset(&infos[p], 0, sizeof(hipbmg_info));
             fill_info_common(h, &infos[p]);
-            for (int l = 0; l < h->L; ++l) infos[p].rb_down[l] = infos[p].rb_up[l] = batch_rb(h->lv[l]);
+            for (int l = 0; l < h->L; ++l) infos[p].rb_down[l] = infos[p].rb_up[l] = batch_rb(B, h->lv[l]);
             infos[p].rb_pipelined = 0;
         }
     }
