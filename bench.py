@@ -125,6 +125,31 @@ def main():
         % (value, cycles, ms_per_step, kname, achieved))
 
     extra = {}
+    # per-level table: one more solve with every level's kernels timed, next
+    # to the model's terms for the same levels
+    hier.profile(True, levels=True)
+    _, info_l = hier.solve(b, tol=TOL)
+    hier.profile(False)
+    lv_ms = hier.profile_levels(0)
+    mod = hier.model_levels()
+    ls_ = info_l.collapse_level
+    table = []
+    for l in range(info_l.levels):
+        ny_l, nx_l = hier.size(l)
+        row = {"level": l, "n": nx_l}
+        if l > ls_:
+            row.update(mode="grid", measured_us_per_cycle=1e3 * (lv_ms[l][0] + lv_ms[l][1]) / info_l.cycles,
+                       model_us_per_cycle=mod["grid_us"][l])
+        elif l == ls_:
+            row.update(mode="collapse launch (levels 0..%d)" % ls_,
+                       measured_us_per_cycle=1e3 * lv_ms[l][2] / info_l.cycles,
+                       model_us_per_cycle=mod["base_us"] + sum(mod["collapsed_us"][1: ls_ + 1]))
+        else:
+            continue
+        table.append(row)
+    extra["levels_fp64"] = table
+    log("bench: per-level " + ", ".join("%d:%.0f/%.0f" % (r["n"], r["measured_us_per_cycle"], r["model_us_per_cycle"])
+                                        for r in table))
     if not args.no_sweep:
         # every forced collapse level l*: measured time per V-cycle next to the
         # model's prediction (the one-GPU form of the paper's path comparison)
@@ -133,16 +158,22 @@ def main():
         for ls in range(0, info.levels):
             if model[ls] > 20 * min(model):
                 continue
-            hs = HB.Hierarchy(coeffs, collapse_level=ls, max_cycles=6)
-            hs.solve(b, tol=1e-30, check=False)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, inf_s = hs.solve(b, tol=1e-30, check=False)
-            torch.cuda.synchronize()
-            per = (time.perf_counter() - t0) / inf_s.cycles
+            # per cycle from a 12-cycle and a 6-cycle solve: the difference
+            # leaves out what every solve pays once (first pre-relaxations,
+            # ||b||, copies)
+            tk = {}
+            for kc in (6, 12):
+                hs = HB.Hierarchy(coeffs, collapse_level=ls, max_cycles=kc)
+                hs.solve(b, tol=1e-30, check=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                hs.solve(b, tol=1e-30, check=False)
+                torch.cuda.synchronize()
+                tk[kc] = time.perf_counter() - t0
+                del hs
+            per = (tk[12] - tk[6]) / 6.0
             sweep.append({"collapse_level": ls, "measured_us_per_cycle": 1e6 * per,
                           "model_us_per_cycle": model[ls]})
-            del hs
             log("bench: l*=%d measured %.1f us/cycle, model %.1f" % (ls, 1e6 * per, model[ls]))
         extra["collapse_sweep"] = sweep
         best = min(sweep, key=lambda r: r["measured_us_per_cycle"])

@@ -200,11 +200,13 @@ hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cell, int is_l
 hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double *u,
                                const double *lam, double *grad_out, void *stream);
 
-/* Live timing of the finest-level relaxation kernels, the per-component
- * timers of the paper's experiments (section 5) for one GPU.  While enabled,
- * every solve records HIP events around each finest-level streaming kernel on
- * the solve stream.  enable = 0 stops and keeps the totals; enable = 1 clears
- * them.  profile_read returns, for one precision (0 FP64, 1 FP32 inner) and
+/* Live timing of the relaxation kernels, the per-component timers of the
+ * paper's experiments (section 5) for one GPU.  While enabled, every solve
+ * records HIP events on the solve stream around each finest-level streaming
+ * kernel (enable = 1), or around every streaming kernel of every level and
+ * the collapse launch (enable = 2; more events, so slightly slower solves).
+ * enable = 0 stops and keeps the totals; enable = 1 or 2 clears them.
+ * profile_read returns, for one precision (0 FP64, 1 FP32 inner) and
  * one kernel index (0 relax, 1 relax from zero, 2 relax + residual +
  * restriction, 3 the same from zero, 4 interpolate + relax, 5 the same + norm,
  * 6 relax + norm, 7 two relaxations + residual + restriction in one pass,
@@ -217,18 +219,36 @@ hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,
                                   double *total_ms_host, long long *launches_host,
                                   double *bytes_per_launch_host);
 
+/* Per-level totals recorded with enable = 2, for one precision: for level l,
+ * ms_host[3l] the down leg (pre-relaxations, residual, restriction),
+ * ms_host[3l+1] the up leg (interpolation and post-relaxations), ms_host[3l+2]
+ * the collapse launch whose top level is l; n_host the matching launch
+ * counts.  Both arrays hold 3 * HIPBMG_MAX_LEVELS entries (n_host may be
+ * NULL).  For the pipelined finest level the single pass is counted in its
+ * up leg. */
+hipbmg_status hipbmg_profile_levels(hipbmg_handle h, int precision, double *ms_host, long long *n_host);
+
+/* The performance model's terms for this hierarchy, in microseconds per
+ * V-cycle (section 3 model; parameters as at setup): grid_us_host[l] the
+ * level's grid-wide kernels, wg_us_host[l] the level inside the collapse
+ * workgroup, base_us_host[0] the collapse launch holding only the coarsest
+ * level (launch gap and coarse solve included).  Arrays of HIPBMG_MAX_LEVELS
+ * entries; entries past the number of levels are 0. */
+hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double *wg_us_host,
+                                  double *base_us_host);
+
 /* Measure the machine parameters of the collapse-level performance model on
  * the current device, as the paper measures its alpha, beta and gamma
  * (section 3, postal model; section 5, machine parameters from benchmarks):
  * the gap between dependent kernel launches and the streaming bandwidth of the
  * relaxation's access mix out of HBM and out of cache, with micro-kernels;
  * then, on a synthetic 257 x 257 hierarchy built and destroyed inside the
- * call, the solver's own kernels: the row-pair step latency of the down and up
- * streaming kernels, and per collapsed level the cost of a barrier phase and
+ * call, the solver's own kernels: the row-pair step latency and fixed cost of the
+ * down and up streaming kernels, and per collapsed level the cost of a barrier phase and
  * the workgroup's inverse bandwidth, fitted separately for levels staged in
  * LDS and levels left in global memory, in FP64 and FP32.  The values replace
  * the process-wide model parameters used by later hipbmg_setup calls.
- * out_host (may be NULL) receives 24 doubles:
+ * out_host (may be NULL) receives 32 doubles:
  *   [0] alpha_launch_us  [1] hbm_GBps  [2] cache_GBps
  *   [3] step_dn_us FP64  [4] step_up_us FP64  [5] step_dn_us FP32  [6] step_up_us FP32
  *   [7] t_base_us FP64 (collapsed launch holding only the coarsest level)  [8] t_base_us FP32
@@ -237,7 +257,11 @@ hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int kernel,
  *   [13] wg_GBps FP64 LDS  [14] wg_GBps FP64 global  [15] wg_GBps FP32 LDS  [16] wg_GBps FP32 global
  *   [17] bare LDS barrier us  [18] bare barrier after an L2 access us
  *   [19] one workgroup's L2 bandwidth GBps  [20] step of a plain relaxation sweep us
- *   [21..23] 0.
+ *   [21] t0_dn_us FP64  [22] t0_up_us FP64  [23] t0_dn_us FP32  [24] t0_up_us FP32 (fixed cost of
+ *        a down / up streaming kernel after the previous kernel)
+ *   [25..31] 0.
+ * Every timing of the solver's kernels is taken cold (after a 512 MB write
+ * has evicted the caches), as the kernels run inside a solve.
  * Allocates about 1 GB of device memory for the duration of the call. */
 hipbmg_status hipbmg_calibrate(void *stream, double *out_host);
 

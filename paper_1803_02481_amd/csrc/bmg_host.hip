@@ -114,9 +114,16 @@ struct hipbmg_hier {
     int prof_var[PROF_RING];
     int prof_prec[PROF_RING];
     int prof_cyc[PROF_RING];
+    int prof_slot[PROF_RING];             // 3 * level + leg (0 down, 1 up, 2 collapse)
+    bool prof_fine[PROF_RING];            // a finest-level streaming kernel
     hipEvent_t ev0[PROF_RING] = {}, ev1[PROF_RING] = {};
     double prof_ms[2][SV_COUNT] = {};
     long long prof_cnt[2][SV_COUNT] = {};
+    double lvl_ms[2][3 * HIPBMG_MAX_LEVELS] = {};
+    long long lvl_cnt[2][3 * HIPBMG_MAX_LEVELS] = {};
+    // the model's inputs at setup (per-level terms are reported from them)
+    ModelLevel ml[HIPBMG_MAX_LEVELS] = {};
+    ModelParams mp{};
     ~hipbmg_hier()
     {
         for (int k = 0; k < PROF_RING; ++k) {
@@ -134,14 +141,18 @@ struct hipbmg_hier {
 template <typename T> struct PrecIdx { enum { v = 0 }; };
 template <> struct PrecIdx<float> { enum { v = 1 }; };
 
-// Record the start of a profiled finest-level launch; returns its ring slot or -1.
-static int prof_begin(hipbmg_hier *h, int variant, int prec, hipStream_t s)
+// Record the start of a profiled launch of level `level`, leg 0 (down), 1
+// (up) or 2 (collapse, variant -1); returns its ring slot or -1.  Mode 1
+// records finest-level streaming kernels only, mode 2 everything.
+static int prof_begin(hipbmg_hier *h, int variant, int prec, int level, int leg, bool fine, hipStream_t s)
 {
-    if (!h->prof_on || h->prof_tail - h->prof_head >= PROF_RING) return -1;
+    if (!h->prof_on || (h->prof_on == 1 && !fine) || h->prof_tail - h->prof_head >= PROF_RING) return -1;
     const int k = (int)(h->prof_tail++ % PROF_RING);
     h->prof_var[k] = variant;
     h->prof_prec[k] = prec;
     h->prof_cyc[k] = h->prof_cycle;
+    h->prof_slot[k] = 3 * level + leg;
+    h->prof_fine[k] = fine;
     (void)hipEventRecord(h->ev0[k], s);
     return k;
 }
@@ -152,20 +163,28 @@ static void prof_end(hipbmg_hier *h, int k, hipStream_t s)
 }
 
 // Collect recorded pairs in order: all of them if `wait`, else those already
-// complete.  Pairs of cycles after `last_cycle` (cycles the device skipped
-// once the convergence test was met) are dropped.
-static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30)
+// complete.  With `final`, pairs of cycles after `last_cycle` (cycles the
+// device skipped once the convergence test was met) are dropped; without it,
+// collection stops at the first pair of a cycle after `last_cycle`, whose
+// fate is not known yet.
+static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30, bool final = true)
 {
     while (h->prof_head < h->prof_tail) {
         const int k = (int)(h->prof_head % PROF_RING);
+        if (!final && h->prof_cyc[k] > last_cycle) break;
         if (!wait && hipEventQuery(h->ev1[k]) != hipSuccess) {
             (void)hipGetLastError();
             break;
         }
         float ms = 0.f;
         if (h->prof_cyc[k] <= last_cycle && hipEventElapsedTime(&ms, h->ev0[k], h->ev1[k]) == hipSuccess) {
-            h->prof_ms[h->prof_prec[k]][h->prof_var[k]] += ms;
-            h->prof_cnt[h->prof_prec[k]][h->prof_var[k]] += 1;
+            const int q = h->prof_prec[k];
+            if (h->prof_fine[k] && h->prof_var[k] >= 0) {
+                h->prof_ms[q][h->prof_var[k]] += ms;
+                h->prof_cnt[q][h->prof_var[k]] += 1;
+            }
+            h->lvl_ms[q][h->prof_slot[k]] += ms;
+            h->lvl_cnt[q][h->prof_slot[k]] += 1;
         }
         (void)hipGetLastError();
         ++h->prof_head;
@@ -310,6 +329,18 @@ static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
     const int L = h->L;
     size_t used = 0;
     bool fits = !h->no_lds;
+    // cache residency: a level's down leg follows the previous cycle's finest
+    // pass, so its data is in HBM unless the whole hierarchy fits in the
+    // last-level cache; its up leg follows the coarser levels only, so its
+    // data is cached if it and every coarser level fit
+    const double word = fp32 ? 4.0 : 8.0, cache = h->mp.cache_bytes > 0 ? h->mp.cache_bytes : model_params().cache_bytes;
+    std::vector<double> below(L + 1, 0.0);   // footprint of levels 0..l-1
+    for (int l = 0; l < L; ++l) {
+        const LevelDev<double> &A = h->lv[l];
+        const double planes_l = (A.npt == 5 ? 3.0 : 5.0) + 4.0 + (l ? 2.0 : 0.0);
+        below[l + 1] = below[l] + (double)A.nx * A.ny * word * planes_l;
+    }
+    const bool all_fit = below[L] < cache;
     for (int l = 0; l < L; ++l) {
         const LevelDev<double> &A = h->lv[l];
         const bool fine = l == L - 1;
@@ -317,20 +348,24 @@ static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
         ml[l].nx = A.nx;
         ml[l].ny = A.ny;
         ml[l].npt = A.npt;
-        const int v[2] = {variant_down(h->prm, fine), variant_up(fine)};
-        const int rb[2] = {h->rb[l], h->rb_up[l]};
-        int steps[2], rounds[2];
-        for (int k = 0; k < 2; ++k) {
+        // steps per wave, residency rounds, and loaded bytes per algorithmic
+        // byte (64 loaded lanes per owned strip; steps walked per owned step)
+        auto describe = [&](int variant, int rb, ModelKernel &k) {
             int nst, nbl, nt, g;
-            stream_geometry(A.nx, A.ny, A.npt, v[k], rb[k], &nst, &nbl, &nt, &g);
-            const int res = stream_resident(A.npt, v[k], fp32);
-            steps[k] = stream_steps_per_tile(v[k], std::min(rb[k], nsteps));
-            rounds[k] = res > 0 ? (nt + res - 1) / res : 1;
-        }
-        ml[l].steps_dn = steps[0];
-        ml[l].rounds_dn = rounds[0];
-        ml[l].steps_up = steps[1];
-        ml[l].rounds_up = rounds[1];
+            stream_geometry(A.nx, A.ny, A.npt, variant, rb, &nst, &nbl, &nt, &g);
+            const int res = stream_resident(A.npt, variant, fp32);
+            const int rbe = std::max(1, std::min(rb, nsteps));
+            k.steps = stream_steps_per_tile(variant, rbe);
+            k.rounds = res > 0 ? (nt + res - 1) / res : 1;
+            k.reread = 64.0 / stream_owned_pairs(A.npt, variant) * (double)k.steps / rbe;
+        };
+        ml[l].dn_cold = all_fit ? 0 : 1;
+        ml[l].up_cold = below[l + 1] < cache ? 0 : 1;
+        describe(variant_down(h->prm, fine), h->rb[l], ml[l].dn);
+        describe(variant_up(fine), h->rb_up[l], ml[l].up);
+        ml[l].pipelined = fine && h->fused3 ? 1 : 0;
+        if (ml[l].pipelined) describe(SV_FUSED3, h->rb3, ml[l].pipe);
+        else ml[l].pipe = ModelKernel{0, 0, 1.0};
         const int cnx = l ? h->lv[l - 1].nx : 0, cny = l ? h->lv[l - 1].ny : 0;
         const size_t bytes = fp32 ? collapse_lds_bytes<float>(A.nx, A.ny, cnx, cny)
                                   : collapse_lds_bytes<double>(A.nx, A.ny, cnx, cny);
@@ -569,10 +604,11 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         }
     }
     // collapse level from the performance model (sections 3 and 4)
-    ModelLevel ml[HIPBMG_MAX_LEVELS];
+    ModelLevel *ml = h->ml;
     model_levels(h, prm.precision == HIPBMG_MIXED, ml);
-    int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc, prm.precision == HIPBMG_MIXED ? 4 : 8,
-                            model_params(), h->model_us);
+    h->mp = model_params();
+    int best = model_choose(ml, L, prm.nu1, prm.nu2, h->nc, prm.precision == HIPBMG_MIXED ? 4 : 8, h->mp,
+                            h->model_us);
     // the collapse workgroup indexes a level's planes with 32-bit integers
     int lcap = -1;
     for (int l = 0; l < L; ++l) {
@@ -718,7 +754,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
                 a.cpitch = Cl.pitch;
                 a.cplane = (long long)Cl.plane;
             }
-            const int pk = fine ? prof_begin(h, v, PrecIdx<T>::v, s) : -1;
+            const int pk = prof_begin(h, v, PrecIdx<T>::v, l, 0, fine, s);
             a.active = active;
             if ((e = run_stream(A, v, a, s)) != hipSuccess) return e;
             prof_end(h, pk, s);
@@ -732,7 +768,9 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         CollapseArgs<T> c = collapse_args<T>(h, lv, d_lv, ls, fine ? cur : 1, fine ? (zero_start ? 1 : 0) : 1,
                                              fine ? 1 : 0);
         c.active = active;
+        const int pk = prof_begin(h, -1, PrecIdx<T>::v, ls, 2, false, s);
         if ((e = launch_collapse<T>(c, s)) != hipSuccess) return e;
+        prof_end(h, pk, s);
         xres[ls] = c.xb_top;
         if (fine) {
             *new_cur = cur;
@@ -763,7 +801,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             }
             a.partials = h->d_partials;
             int nt = 0;
-            const int pk = fine ? prof_begin(h, v, PrecIdx<T>::v, s) : -1;
+            const int pk = prof_begin(h, v, PrecIdx<T>::v, l, 1, fine, s);
             a.active = active;
             if ((e = run_stream(A, v, a, s, &nt)) != hipSuccess) return e;
             prof_end(h, pk, s);
@@ -849,7 +887,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             a.cplane = (long long)Cl.plane;
             a.partials = h->d_partials;
             a.active = act;
-            const int pk = prof_begin(h, SV_FUSED3, PrecIdx<T>::v, s);
+            const int pk = prof_begin(h, SV_FUSED3, PrecIdx<T>::v, L - 1, 1, true, s);
             HIPCHK(run_stream(F, SV_FUSED3, a, s, &np));
             prof_end(h, pk, s);
             res_after[k] = xb[(i + 1) % 3];
@@ -869,7 +907,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
         while (seen < k - h->ahead && !stopped) {
             ++seen;
             HIPCHK(hipEventSynchronize(h->ring_ev[seen % RING]));
-            prof_collect(h, false);
+            prof_collect(h, false, seen, false);
             const volatile double *slot = h->ring_host + 4 * (seen % RING);
             if (slot[1] == 0.0) stopped = true;
         }
@@ -1191,11 +1229,14 @@ extern "C" hipbmg_status hipbmg_profile(hipbmg_handle h, int enable)
             HIPCHK(hipEventCreate(&h->ev0[k]));
             HIPCHK(hipEventCreate(&h->ev1[k]));
         }
+    if (enable < 0 || enable > 2) return fail(HIPBMG_EINVAL, "enable must be 0, 1 or 2");
     prof_collect(h, true);   // pairs still pending belong to the previous setting
-    h->prof_on = enable ? 1 : 0;
+    h->prof_on = enable;
     if (enable) {
         memset(h->prof_ms, 0, sizeof h->prof_ms);
         memset(h->prof_cnt, 0, sizeof h->prof_cnt);
+        memset(h->lvl_ms, 0, sizeof h->lvl_ms);
+        memset(h->lvl_cnt, 0, sizeof h->lvl_cnt);
     }
     return HIPBMG_OK;
 }
@@ -1230,6 +1271,31 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
     return HIPBMG_OK;
 }
 
+extern "C" hipbmg_status hipbmg_profile_levels(hipbmg_handle h, int precision, double *ms_host, long long *n_host)
+{
+    if (!h || !ms_host) return fail(HIPBMG_EINVAL, "null argument");
+    if (precision < 0 || precision > 1) return fail(HIPBMG_EINVAL, "bad precision");
+    for (int k = 0; k < 3 * HIPBMG_MAX_LEVELS; ++k) {
+        ms_host[k] = h->lvl_ms[precision][k];
+        if (n_host) n_host[k] = h->lvl_cnt[precision][k];
+    }
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double *wg_us_host,
+                                             double *base_us_host)
+{
+    if (!h || !grid_us_host || !wg_us_host || !base_us_host) return fail(HIPBMG_EINVAL, "null argument");
+    const int word = h->prm.precision == HIPBMG_MIXED ? 4 : 8;
+    for (int l = 0; l < HIPBMG_MAX_LEVELS; ++l) {
+        grid_us_host[l] = l < h->L ? model_grid_level_us(h->ml[l], l == h->L - 1, h->prm.nu1, h->prm.nu2, word, h->mp)
+                                   : 0.0;
+        wg_us_host[l] = (l >= 1 && l < h->L) ? model_wg_level_us(h->ml[l], h->prm.nu1, h->prm.nu2, word, h->mp) : 0.0;
+    }
+    base_us_host[0] = model_base_us(h->nc, word, h->mp);
+    return HIPBMG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Calibration of the model on the kernels themselves.  A synthetic hierarchy
 // (D = 1 on 257 x 257 vertices, FP64 and FP32 levels) is built; the collapse
@@ -1241,23 +1307,6 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
 // bandwidth-bound.  This is the single-GPU form of measuring the model's
 // parameters with benchmarks of the operations the solver performs.
 // ---------------------------------------------------------------------------
-template <typename F>
-static double time_launches_us(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, int per, F &&launch)
-{
-    for (int k = 0; k < per; ++k) launch();   // warm-up
-    double best = 1e30;
-    for (int r = 0; r < reps; ++r) {
-        (void)hipEventRecord(e0, s);
-        for (int k = 0; k < per; ++k) launch();
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        best = std::min(best, 1e3 * (double)ms / per);
-    }
-    return best;
-}
-
 // least squares y = a + b x over the samples, with a, b >= 0 (a, b unchanged
 // if there is no sample)
 static void fit_nonneg(const std::vector<double> &x, const std::vector<double> &y, double *a, double *b)
@@ -1301,10 +1350,37 @@ static double median(std::vector<double> v)
     return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
 }
 
+// One launch timed as it runs inside a solve: after a large write has pushed
+// everything else out of the caches, bracketed by events on the stream (the
+// launch gap after the previous kernel is included).  Minimum over reps.
+struct ColdTimer {
+    hipStream_t s;
+    hipEvent_t e0, e1;
+    void *flush;
+    size_t flush_bytes;
+    template <typename F>
+    double us(int reps, F &&launch)
+    {
+        double best = 1e30;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipMemsetAsync(flush, r & 0xff, flush_bytes, s);
+            (void)hipEventRecord(e0, s);
+            launch();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, 1e3 * (double)ms);
+        }
+        return best;
+    }
+};
+
 template <typename T>
 static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev<T>> &lv, const LevelDev<T> *d_lv,
-                                      hipStream_t s, hipEvent_t e0, hipEvent_t e1, ModelParams &p)
+                                      ColdTimer &ct, ModelParams &p)
 {
+    hipStream_t s = ct.s;
     const int L = h->L, nu1 = h->prm.nu1, nu2 = h->prm.nu2, word = (int)sizeof(T);
     const int q = word == 4 ? 1 : 0;
     ModelLevel ml[HIPBMG_MAX_LEVELS];
@@ -1313,7 +1389,7 @@ static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev
     std::vector<double> tc(L);
     for (int top = 0; top < L; ++top) {
         const CollapseArgs<T> c = collapse_args<T>(h, lv, d_lv, top, 1, 1, 0);
-        tc[top] = time_launches_us(s, e0, e1, 3, 2, [&] { (void)launch_collapse<T>(c, s); });
+        tc[top] = ct.us(3, [&] { (void)launch_collapse<T>(c, s); });
     }
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     p.t_base_us[q] = std::max(0.0, tc[0] - p.alpha_launch_us);
@@ -1331,51 +1407,64 @@ static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev
         p.beta_wg_us_per_B[q][g] = b;
     }
     // grid kernels of every level below the finest (zero-start pre-relaxation
-    // fused with residual and restriction; interpolating relaxation)
-    std::vector<double> sdn, sup;
+    // fused with residual and restriction; interpolating relaxation), each at
+    // two row-block lengths: on a level whose waves all fit in one residency
+    // round and whose bytes take a small part of the time, the difference
+    // gives the step latency and the rest the kernel's fixed cost
+    std::vector<double> sdn, sup, fdn, fup;
     const int vdn = nu1 >= 2 ? SV_SWEEP2_RQ_ZX : SV_SWEEP_RQ_ZX;
     for (int l = 1; l < L; ++l) {
         const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
         const int nsteps = (A.ny - 1) / 2;
-        StreamArgs<T> a = base_args(A, h->rb[l]);
-        a.x_in = A.x[0];
-        a.x_out = A.x[1];
-        a.q_out = A.q;
-        a.bc = Cl.b;
-        a.wt = A.wt;
-        a.cnx = Cl.nx;
-        a.cny = Cl.ny;
-        a.cpitch = Cl.pitch;
-        a.cplane = (long long)Cl.plane;
-        const double tdn = time_launches_us(s, e0, e1, 3, 8, [&] { (void)run_stream(A, vdn, a, s); });
-        StreamArgs<T> u = base_args(A, h->rb_up[l]);
-        u.x_in = A.x[1];
-        u.x_out = A.x[0];
-        u.xc = Cl.x[1];
-        u.wt = A.wt;
-        u.q_in = A.q;
-        u.rescorr = h->prm.residual_correction;
-        u.cnx = Cl.nx;
-        u.cny = Cl.ny;
-        u.cpitch = Cl.pitch;
-        u.cplane = (long long)Cl.plane;
-        const double tup = time_launches_us(s, e0, e1, 3, 8, [&] { (void)run_stream(A, SV_INTERP, u, s); });
-        // one residency round and a working set whose bytes take well under the
-        // measured time at the cache bandwidth: the waves' step latency bounds it
+        if (nsteps < 4) continue;
         const double nbytes = (double)A.nx * A.ny * word * 12.0;
-        int nst, nbl, nt, gg;
-        stream_geometry(A.nx, A.ny, A.npt, vdn, h->rb[l], &nst, &nbl, &nt, &gg);
-        const int rdn = stream_resident(A.npt, vdn, q);
-        if (rdn > 0 && nt <= rdn && nbytes * p.beta_cache_us_per_B < 0.3 * (tdn - p.alpha_launch_us))
-            sdn.push_back((tdn - p.alpha_launch_us) / stream_steps_per_tile(vdn, std::min(h->rb[l], nsteps)));
-        stream_geometry(A.nx, A.ny, A.npt, SV_INTERP, h->rb_up[l], &nst, &nbl, &nt, &gg);
-        const int rup = stream_resident(A.npt, SV_INTERP, q);
-        if (rup > 0 && nt <= rup && nbytes * p.beta_cache_us_per_B < 0.3 * (tup - p.alpha_launch_us))
-            sup.push_back((tup - p.alpha_launch_us) / stream_steps_per_tile(SV_INTERP, std::min(h->rb_up[l], nsteps)));
+        for (int leg = 0; leg < 2; ++leg) {
+            const int v = leg == 0 ? vdn : SV_INTERP;
+            StreamArgs<T> a = base_args(A, 1);
+            if (leg == 0) {
+                a.x_in = A.x[0];
+                a.x_out = A.x[1];
+                a.q_out = A.q;
+                a.bc = Cl.b;
+            } else {
+                a.x_in = A.x[1];
+                a.x_out = A.x[0];
+                a.xc = Cl.x[1];
+                a.q_in = A.q;
+                a.rescorr = h->prm.residual_correction;
+            }
+            a.wt = A.wt;
+            a.cnx = Cl.nx;
+            a.cny = Cl.ny;
+            a.cpitch = Cl.pitch;
+            a.cplane = (long long)Cl.plane;
+            const int rbs[2] = {1, 4};
+            double tt[2];
+            bool ok = true;
+            for (int m = 0; m < 2; ++m) {
+                a.rb = rbs[m];
+                tt[m] = ct.us(3, [&] { (void)run_stream(A, v, a, s); });
+                int nst, nbl, nt, gg;
+                stream_geometry(A.nx, A.ny, A.npt, v, rbs[m], &nst, &nbl, &nt, &gg);
+                const int res = stream_resident(A.npt, v, q);
+                ok = ok && res > 0 && nt <= res && nbytes * p.beta_cache_us_per_B < 0.3 * tt[m];
+            }
+            if (!ok) continue;
+            const int s0 = stream_steps_per_tile(v, 1), s1 = stream_steps_per_tile(v, 4);
+            const double step = std::max(0.05, (tt[1] - tt[0]) / (s1 - s0));
+            (leg == 0 ? sdn : sup).push_back(step);
+            (leg == 0 ? fdn : fup).push_back(std::max(0.0, tt[0] - s0 * step));
+        }
     }
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    if (!sdn.empty()) p.step_dn_us[q] = std::max(0.05, median(sdn));
-    if (!sup.empty()) p.step_up_us[q] = std::max(0.05, median(sup));
+    if (!sdn.empty()) {
+        p.step_dn_us[q] = median(sdn);
+        p.t0_dn_us[q] = median(fdn);
+    }
+    if (!sup.empty()) {
+        p.step_up_us[q] = median(sup);
+        p.t0_up_us[q] = median(fup);
+    }
     return hipStreamSynchronize(s);
 }
 
@@ -1419,9 +1508,19 @@ hipbmg_status hbmg::calibrate_on_kernels(void *stream, ModelParams &p)
         cleanup();
         return st;
     }
-    hipError_t e = calibrate_precision<double>(h, h->lv, h->d_lv, s, e0, e1, p);
-    if (e == hipSuccess) e = calibrate_precision<float>(h, h->lv32, h->d_lv32, s, e0, e1, p);
+    void *flush = nullptr;
+    const size_t flush_bytes = (size_t)512 << 20;   // beyond L2 and the 256 MB last-level cache
+    if (hipMalloc(&flush, flush_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(HIPBMG_ENOMEM, "calibration: device allocation failed");
+    }
+    ColdTimer ct{s, e0, e1, flush, flush_bytes};
+    hipError_t e = calibrate_precision<double>(h, h->lv, h->d_lv, ct, p);
+    if (e == hipSuccess) e = calibrate_precision<float>(h, h->lv32, h->d_lv32, ct, p);
     if (e != hipSuccess) st = fail(HIPBMG_EHIP, "calibration launches failed: %s", hipGetErrorString(e));
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(flush);
     cleanup();
     return st;
 }

@@ -27,8 +27,10 @@ ModelParams &model_params()
         d.beta_cache_us_per_B = 1.0 / 10.0e6;  // 10 TB/s from cache-resident levels
         d.cache_bytes = 256.0e6;
         for (int q = 0; q < 2; ++q) {
-            d.step_dn_us[q] = 2.4;
-            d.step_up_us[q] = 1.8;
+            d.step_dn_us[q] = 1.4;
+            d.step_up_us[q] = 1.2;
+            d.t0_dn_us[q] = 5.0;
+            d.t0_up_us[q] = 4.0;
             d.t_base_us[q] = 10.0;
             d.alpha_bar_us[q][0] = 0.15;
             d.alpha_bar_us[q][1] = 1.5;
@@ -46,31 +48,44 @@ ModelParams &model_params()
 // planes read by a relaxation: b, x and the stencil (3 planes 5-point, 5 planes 9-point)
 static double planes(int npt) { return npt == 5 ? 3.0 : 5.0; }
 
+// one streaming kernel: the longer of its waves' sequential steps (after its
+// fixed cost) and the bytes it loads at the level's bandwidth (after a launch gap)
+static double kernel_us(const ModelKernel &k, double step_us, double t0_us, double bytes, double beta,
+                        const ModelParams &p)
+{
+    const double lat = t0_us + (double)k.rounds * k.steps * step_us;
+    return std::max(lat, p.alpha_launch_us + bytes * k.reread * beta);
+}
+
 double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, int word,
                            const ModelParams &p)
 {
     const int q = word == 4 ? 1 : 0;
     const double n = (double)lv.nx * lv.ny, s = planes(lv.npt), w = word;
-    const double level_bytes = n * w * (s + 4.0) + n * w * 2.0 / 4.0 * 8.0 / 4.0;
-    const double beta = level_bytes < p.cache_bytes ? p.beta_cache_us_per_B : p.beta_hbm_us_per_B;
+    const double bdn = lv.dn_cold ? p.beta_hbm_us_per_B : p.beta_cache_us_per_B;
+    const double bup = lv.up_cold ? p.beta_hbm_us_per_B : p.beta_cache_us_per_B;
+    if (finest && lv.pipelined) {
+        // one pass per cycle: interpolate + relax + norm of this cycle, two
+        // relaxations + residual + r/C + restriction of the next; its waves
+        // do the work of a down and an up step per row pair
+        const double bytes = n * w * (s + 3.0 + 0.25 + 2.0 + 1.0 + 1.0 + 0.25 + 1.0);
+        return kernel_us(lv.pipe, p.step_dn_us[q] + p.step_up_us[q], p.t0_dn_us[q], bytes, bdn, p);
+    }
     double t = 0.0;
     // down: nu1 relaxations; the last two run as one pass fused with residual,
-    // r/C and restriction (the last one alone if nu1 = 1); a kernel takes the
-    // longer of its waves' sequential steps and its bytes at the level's bandwidth
+    // r/C and restriction (the last one alone if nu1 = 1)
     const int nk = nu1 >= 2 ? nu1 - 1 : nu1;
     for (int k = 1; k <= nk; ++k) {
-        double bytes = n * w * (s + 3.0) * (k == nk && nk < nu1 ? 2.0 : 1.0);
+        double bytes = n * w * (s + 3.0);                    // one pass, however many sweeps it fuses
         if (k == 1 && !finest) bytes -= n * w;               // iterate starts at zero
         if (k == nk) bytes += n * w * (1.0 + 2.0 + 0.25);    // q, weights, coarse rhs
-        const double lat = (double)lv.rounds_dn * lv.steps_dn * p.step_dn_us[q];
-        t += p.alpha_launch_us + std::max(lat, bytes * beta);
+        t += kernel_us(lv.dn, p.step_dn_us[q], p.t0_dn_us[q], bytes, bdn, p);
     }
     // up: interpolation fused with the first post-relaxation
     for (int k = 1; k <= nu2; ++k) {
         double bytes = n * w * (s + 3.0);
         if (k == 1) bytes += n * w * (0.25 + 2.0 + 1.0);     // coarse x, weights, q
-        const double lat = (double)lv.rounds_up * lv.steps_up * p.step_up_us[q];
-        t += p.alpha_launch_us + std::max(lat, bytes * beta);
+        t += kernel_us(lv.up, p.step_up_us[q], p.t0_up_us[q], bytes, bup, p);
     }
     return t;
 }
@@ -92,17 +107,23 @@ double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, const
            model_wg_bytes(lv.nx, lv.ny, nu1, nu2, word) * p.beta_wg_us_per_B[q][g];
 }
 
-int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word,
-                 const ModelParams &p, double *t_us)
+double model_base_us(int nc, int word, const ModelParams &p)
 {
     const int q = word == 4 ? 1 : 0;
     // coarse solve beyond the one-unknown base: two triangular substitutions,
     // 2 barriers per unknown, nc^2 multiply-adds each
     const double t_cg = (nc > 1 ? 4.0 * (nc - 1) * p.alpha_bar_us[q][0] : 0.0) +
                         2.0 * (double)nc * nc * p.gamma_wg_us_per_flop;
+    return p.alpha_launch_us + p.t_base_us[q] + t_cg;
+}
+
+int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word,
+                 const ModelParams &p, double *t_us)
+{
+    const double base = model_base_us(nc, word, p);
     int best = 0;
     for (int ls = 0; ls < L; ++ls) {
-        double t = p.alpha_launch_us + p.t_base_us[q] + t_cg;   // the collapsed launch
+        double t = base;                                         // the collapsed launch
         for (int l = ls + 1; l < L; ++l) t += model_grid_level_us(lv[l], l == L - 1, nu1, nu2, word, p);
         for (int l = 1; l <= ls; ++l) t += model_wg_level_us(lv[l], nu1, nu2, word, p);
         t += p.alpha_launch_us;                                  // norm finalisation

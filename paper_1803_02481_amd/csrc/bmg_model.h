@@ -7,16 +7,28 @@
 
 namespace hbmg {
 
+// One streaming kernel as the model sees it: the row-pair steps one wave
+// walks, the residency rounds of the launch, and the bytes it loads per
+// algorithmic byte (halo lanes shared with neighbouring strips and prologue
+// rows shared with the block below are loaded twice).
+struct ModelKernel {
+    int steps, rounds;
+    double reread;
+};
+
 // One level as the model sees it.  The host fills in the launch geometry the
-// streaming kernels will use: row-pair steps one wave walks and the number of
-// residency rounds of the launch, for the down (pre-relaxation) and up
-// (interpolation) kernels; in_lds says whether the level is staged in LDS when
-// it is collapsed.
+// streaming kernels will use: the down (pre-relaxation) and up
+// (interpolation) kernels, and for a pipelined finest level the single pass
+// that replaces both; in_lds says whether the level is staged in LDS when it
+// is collapsed.
 struct ModelLevel {
     int nx, ny, npt;
-    int steps_dn, rounds_dn;
-    int steps_up, rounds_up;
+    ModelKernel dn, up, pipe;
+    int pipelined;
     int in_lds;
+    // where a leg finds the level's data: 1 in HBM (evicted since its last
+    // use), 0 in the last-level cache
+    int dn_cold, up_cold;
 };
 
 // Machine parameters.  Paper -> GPU correspondence:
@@ -28,10 +40,12 @@ struct ModelLevel {
 //                               working set), beta_wg for the collapsed workgroup
 //   gamma (per flop)         -> gamma_wg, single-thread FP64 work of the coarse solve
 // plus step_dn / step_up, the latency of one row-pair step of a streaming wave
-// (pre-relaxation and interpolation kernels), which bounds a grid-wide kernel
-// on a level too small to fill the GPU, and t_base, the collapsed launch
-// holding only the coarsest level.  Per-precision entries are indexed
-// [0] FP64, [1] FP32; alpha_bar and beta_wg also by [0] LDS, [1] global.
+// (pre-relaxation and interpolation kernels), and t0_dn / t0_up, a kernel's
+// fixed cost after the previous one (launch gap, wave start, first loads),
+// which bound a grid-wide kernel on a level too small to fill the GPU; and
+// t_base, the collapsed launch holding only the coarsest level.
+// Per-precision entries are indexed [0] FP64, [1] FP32; alpha_bar and beta_wg
+// also by [0] LDS, [1] global.
 struct ModelParams {
     double alpha_launch_us;
     double beta_hbm_us_per_B;
@@ -39,6 +53,8 @@ struct ModelParams {
     double cache_bytes;
     double step_dn_us[2];
     double step_up_us[2];
+    double t0_dn_us[2];
+    double t0_up_us[2];
     double t_base_us[2];
     double alpha_bar_us[2][2];
     double beta_wg_us_per_B[2][2];
@@ -65,6 +81,10 @@ double model_wg_bytes(int nx, int ny, int nu1, int nu2, int word);
 // level l* in [0, L-1] into t_us[l*]; returns the argmin.  word = bytes per value.
 int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word,
                  const ModelParams &p, double *t_us);
+
+// the collapsed launch holding only the coarsest level (nc unknowns):
+// launch gap, base cost and coarse solve
+double model_base_us(int nc, int word, const ModelParams &p);
 
 // the two parts of the model for one level (exposed for reporting)
 double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, int word,

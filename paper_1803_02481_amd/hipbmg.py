@@ -65,6 +65,9 @@ _SIGS = {
     "hipbmg_profile": (_I, [_VP, _I]),
     "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_profile_levels": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "hipbmg_model_levels": (_I, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]),
     "hipbmg_calibrate": (_I, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "hipbmg_setup_batched": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, ctypes.POINTER(_VP),
                                   ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
@@ -178,8 +181,27 @@ class Hierarchy:
         _check(lib().hipbmg_get_interp(self._h, l, _ptr(out), _stream()))
         return out
 
-    def profile(self, enable=True):
-        _check(lib().hipbmg_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True, levels=False):
+        """Record finest-level kernel times (levels=True: every level's legs
+        and the collapse launch too)."""
+        _check(lib().hipbmg_profile(self._h, (2 if levels else 1) if enable else 0))
+
+    def profile_levels(self, precision=0):
+        """[(down_ms, up_ms, collapse_ms, launches down/up/collapse)] per level."""
+        ms = (ctypes.c_double * (3 * MAX_LEVELS))()
+        n = (ctypes.c_longlong * (3 * MAX_LEVELS))()
+        _check(lib().hipbmg_profile_levels(self._h, precision, ms, n))
+        return [(ms[3 * l], ms[3 * l + 1], ms[3 * l + 2], n[3 * l], n[3 * l + 1], n[3 * l + 2])
+                for l in range(self.L)]
+
+    def model_levels(self):
+        """The model's terms (us per V-cycle): grid-wide kernels and collapsed
+        form of every level, and the collapsed launch holding the coarsest."""
+        grid = (ctypes.c_double * MAX_LEVELS)()
+        wg = (ctypes.c_double * MAX_LEVELS)()
+        base = (ctypes.c_double * 1)()
+        _check(lib().hipbmg_model_levels(self._h, grid, wg, base))
+        return {"grid_us": list(grid)[: self.L], "collapsed_us": list(wg)[: self.L], "base_us": base[0]}
 
     KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
                "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero", "fused3")
@@ -265,7 +287,7 @@ class BatchHierarchy:
 def calibrate():
     """Measure the performance-model parameters on the current device; later
     hierarchies choose their collapse level with them."""
-    out = (ctypes.c_double * 24)()
+    out = (ctypes.c_double * 32)()
     _check(lib().hipbmg_calibrate(_stream(), out))
     return {k: out[i] for i, k in enumerate(CALIBRATION_KEYS)}
 
@@ -276,7 +298,8 @@ CALIBRATION_KEYS = ("alpha_launch_us", "hbm_GBps", "cache_GBps",
                     "alpha_bar_us_fp64_lds", "alpha_bar_us_fp64_global",
                     "alpha_bar_us_fp32_lds", "alpha_bar_us_fp32_global",
                     "wg_GBps_fp64_lds", "wg_GBps_fp64_global", "wg_GBps_fp32_lds", "wg_GBps_fp32_global",
-                    "bare_barrier_lds_us", "bare_barrier_l2_us", "bare_wg_l2_GBps", "plain_sweep_step_us")
+                    "bare_barrier_lds_us", "bare_barrier_l2_us", "bare_wg_l2_GBps", "plain_sweep_step_us",
+                    "t0_dn_us_fp64", "t0_up_us_fp64", "t0_dn_us_fp32", "t0_up_us_fp32")
 
 
 def fv5_from_cells(cell, is_log=False):

@@ -748,3 +748,39 @@ def test_batched_adjoint_equals_single_problem_adjoint():
         d = rel(gb[k], c(t1.grad))
         print("problem %d: batched vs single gradient %.3e" % (k, d), flush=True)
         assert d <= 1e-6, d
+
+
+@pytest.mark.parametrize("pipelined", ["0", "1"])
+def test_per_level_profile_and_model_terms(pipelined, monkeypatch):
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
+    n = 257
+    planes = g(O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=51)))
+    b = g(inputs.load_uniform(n, n, seed=52))
+    hier = HB.Hierarchy(planes, collapse_level=2)
+    hier.profile(True, levels=True)
+    _, info = hier.solve(b, tol=1e-10)
+    hier.profile(False)
+    lv = hier.profile_levels(0)
+    k, L, ls = info.cycles, info.levels, info.collapse_level
+    assert ls == 2
+    for l in range(L):
+        down_ms, up_ms, coll_ms, nd, nu, nc = lv[l]
+        if l > ls:
+            fine_pipelined = pipelined == "1" and l == L - 1
+            # V(2,1): one fused two-sweep down kernel, one interpolating up
+            # kernel per cycle (the pipelined finest pass counts as up)
+            assert nd == (0 if fine_pipelined else k), (l, nd, k)
+            assert nu == k and up_ms > 0.0, (l, nu, k)
+            assert nc == 0
+        else:
+            assert nd == 0 and nu == 0
+            assert nc == (k if l == ls else 0)
+    m = hier.model_levels()
+    assert m["base_us"] > 0.0
+    assert all(v > 0.0 for v in m["grid_us"])
+    assert m["collapsed_us"][0] == 0.0 and all(v > 0.0 for v in m["collapsed_us"][1:])
+    # the finest-level stats of profile mode 1 are untouched by mode 2's extra records
+    hier.profile(True)
+    hier.solve(b, tol=1e-10)
+    hier.profile(False)
+    assert sum(v[1] for v in hier.profile_read(0).values()) == (k if pipelined == "1" else 2 * k)
