@@ -541,6 +541,13 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
                     const int v = std::atoi(e);
                     if (v >= 1 && v <= 4096) h->rb[l] = h->rb_up[l] = v;
                 }
+            if (const char *e = std::getenv("HIPBMG_RB_AT")) {   // tuning override "nx:down:up"
+                int anx = 0, adn = 0, aup = 0;
+                if (std::sscanf(e, "%d:%d:%d", &anx, &adn, &aup) == 3 && anx == sx[l]) {
+                    if (adn >= 1 && adn <= 4096) h->rb[l] = adn;
+                    if (aup >= 1 && aup <= 4096) h->rb_up[l] = aup;
+                }
+            }
             int nst, nbl, nt, g;
             stream_geometry(sx[l], sy[l], lnpt, SV_INTERP_NORM, h->rb_up[l], &nst, &nbl, &nt, &g);
             np = std::max(np, (size_t)nt);

@@ -184,7 +184,7 @@ __device__ __forceinline__ void stage_rotate(Stage<T> &S)
 // stores if WRITE).  With RES the residual of the final rows j-2 and j-1 is
 // formed, with RQ stored as q = r/C and restricted onto coarse row (j-2)/2,
 // with NORM its squares are accumulated.
-template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM>
+template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM, bool WROW = false>
 __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const LaneCtx &L,
                                            const StreamArgs<T> &a)
 {
@@ -235,7 +235,18 @@ __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const L
                 const bool jcin = j - 2 >= 2 && jc <= a.cny - 2;
                 T xl = T(0), xr = T(0), yb = T(0), yt = T(0), csw = T(0), cse = T(0),
                   cnw = T(0), cne = T(0);
-                if (L.cv && j - 2 >= 0 && jc <= a.cny - 1) {
+                if (WROW) {
+                    // the weights came in with rows j-2 (x-line pair) and j-1
+                    // (the other six) when an earlier stage interpolated them
+                    xl = S.rm2.w0;
+                    xr = S.rm2.w1;
+                    yb = S.rm1.w0;
+                    yt = S.rm1.w1;
+                    csw = S.rm1.w2;
+                    cse = S.rm1.w3;
+                    cnw = S.rm1.w4;
+                    cne = S.rm1.w5;
+                } else if (L.cv && j - 2 >= 0 && jc <= a.cny - 1) {
                     const size_t co = (size_t)jc * a.cpitch + L.t;
                     const long long cp = a.cplane;
                     xl = a.wt[WXL * cp + co];
@@ -571,7 +582,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
                 B.r0 = A.rm2;
                 B.rp1 = A.rm1;
                 const int modeB = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
-                stage_step<T, NPT, true, true, true, false>(B, jb, modeB, L, aB);
+                stage_step<T, NPT, true, true, true, false, true>(B, jb, modeB, L, aB);
                 stage_rotate(B);
             }
             stage_rotate(A);
