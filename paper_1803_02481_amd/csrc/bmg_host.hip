@@ -851,6 +851,10 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
     T *xb[3] = {F.x[0], F.x[1], pipe ? x3_of<T>(h) : nullptr};
     T *qb[2] = {F.q, pipe ? q2_of<T>(h) : nullptr};
     std::vector<const T *> res_after((size_t)max_cycles + 1, F.x[0]);
+    // pipelined: the inputs of each cycle's finest pass (iterate buffer,
+    // r/C buffer, coarse correction), to rebuild the stopping cycle's iterate
+    std::vector<int> in_i((size_t)max_cycles + 1, 0), in_qa((size_t)max_cycles + 1, 0);
+    std::vector<const T *> in_xc((size_t)max_cycles + 1, nullptr);
     HIPCHK(launch_flags_reset(h->d_flags, s));
     if (pipe) {
         // pre-relaxations of cycle 1 and the restriction of its residual
@@ -898,6 +902,9 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             HIPCHK(run_stream(F, SV_FUSED3, a, s, &np));
             prof_end(h, pk, s);
             res_after[k] = xb[(i + 1) % 3];
+            in_i[k] = i;
+            in_qa[k] = qa;
+            in_xc[k] = Cl.x[cc];
             i = (i + 2) % 3;
             qa = 1 - qa;
         } else {
@@ -923,6 +930,25 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
     HIPCHK(hipMemcpy(h->h_flags, h->d_flags, 4 * sizeof(int), hipMemcpyDeviceToHost));
     const int kdone = h->h_flags[0] ? k : h->h_flags[1];
     prof_collect(h, true, kdone);
+    if (pipe && kdone > 0) {
+        // the pipelined pass does not store the iterate after its cycle; the
+        // stopping cycle's is rebuilt by the same interpolation and relaxation
+        // from that pass's inputs, which later (skipped) cycles left untouched
+        const LevelDev<T> &Cl = lv[L - 2];
+        const int ik = in_i[kdone];
+        StreamArgs<T> a = base_args(F, h->rb_up[L - 1]);
+        a.x_in = xb[ik];
+        a.x_out = xb[(ik + 1) % 3];
+        a.xc = in_xc[kdone];
+        a.wt = F.wt;
+        a.q_in = qb[in_qa[kdone]];
+        a.rescorr = h->prm.residual_correction;
+        a.cnx = Cl.nx;
+        a.cny = Cl.ny;
+        a.cpitch = Cl.pitch;
+        a.cplane = (long long)Cl.plane;
+        HIPCHK(run_stream(F, SV_INTERP, a, s));
+    }
     *cycles_done = kdone;
     *result = res_after[kdone];
     return HIPBMG_OK;
@@ -1271,8 +1297,10 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
             variant == SV_SWEEP2_RQ_ZX)
             per += w + 2.0 * w + 0.25 * w;
         if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
-        // interpolation inputs, the weights once, r/C in and out, coarse rhs, second iterate
-        if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + w + w + 0.25 * w + w;
+        // interpolation inputs, the weights once, r/C in and out, coarse rhs (the
+        // relaxation's x write is the next cycle's iterate; the post-relaxed
+        // iterate itself is not stored)
+        if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + w + w + 0.25 * w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;

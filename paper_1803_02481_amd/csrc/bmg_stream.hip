@@ -184,7 +184,7 @@ __device__ __forceinline__ void stage_rotate(Stage<T> &S)
 // stores if WRITE).  With RES the residual of the final rows j-2 and j-1 is
 // formed, with RQ stored as q = r/C and restricted onto coarse row (j-2)/2,
 // with NORM its squares are accumulated.
-template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM, bool WROW = false>
+template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM, bool WROW = false, bool STOREX = true>
 __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const LaneCtx &L,
                                            const StreamArgs<T> &a)
 {
@@ -206,7 +206,7 @@ __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const L
         r = res_odd<T, NPT>(S.rm2, S.rm1, S.r0, d);
         if (rjm && L.io) S.rm1.x1 += r / d;
 
-        if (WRITE && mode == 2 && L.own) {
+        if (WRITE && STOREX && mode == 2 && L.own) {
             if (rjm) st2(a.x_out + (size_t)(j - 1) * L.pitch + L.e, S.rm1.x0, S.rm1.x1);
             if (rj) st2(a.x_out + (size_t)j * L.pitch + L.e, S.r0.x0, S.r0.x1);
         }
@@ -470,11 +470,12 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 
 // The finest level's post-relaxation of cycle k and both pre-relaxations of
 // cycle k+1 in ONE pass (5-point operators): stage P interpolates and corrects
-// each loaded row (x_in + P x_c + q_in), relaxes it, stores the result in
-// x_out (the iterate after cycle k) and accumulates its residual norm (the
-// convergence test of cycle k); stage A relaxes P's final rows; stage B
-// relaxes A's final rows, stores them in x_out2 and forms the residual, q_out
-// = r/C and the restriction b_c of cycle k+1.  Each stage lags the previous one
+// each loaded row (x_in + P x_c + q_in), relaxes it and accumulates its
+// residual norm (the convergence test of cycle k) -- the iterate after cycle
+// k itself is not stored (the solve rebuilds the stopping cycle's with one
+// interpolating relaxation from the same inputs); stage A relaxes P's final
+// rows; stage B relaxes A's final rows, stores them in x_out2 and forms the
+// residual, q_out = r/C and the restriction b_c of cycle k+1.  Each stage lags the previous one
 // by one row-pair step.  Per column, the lanes whose results are exact shrink
 // by one per stage, so 4 halo lanes are needed on each side; a row block
 // starts with four P, three A and two B prologue steps.
@@ -569,7 +570,9 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         finish_row(P.r0, jp);
         finish_row(P.rp1, jp + 1);
         const int modeP = jp == jfirst - 8 ? 0 : (jp >= jfirst && jp <= jlast ? 2 : 1);
-        stage_step<T, NPT, true, true, false, true>(P, jp, modeP, L, a);
+        // the iterate after cycle k is not stored: only the stopping cycle's
+        // is needed, and it is rebuilt from this pass's inputs afterwards
+        stage_step<T, NPT, true, true, false, true, false, false>(P, jp, modeP, L, a);
         const int ja = jp - 2;
         if (ja >= jfirst - 6) {
             if (ja == jfirst - 6) A.rm1 = P.rm3;   // P-final row ja-1
