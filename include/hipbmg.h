@@ -211,7 +211,9 @@ hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double
  * restriction, 3 the same from zero, 4 interpolate + relax, 5 the same + norm,
  * 6 relax + norm, 7 two relaxations + residual + restriction in one pass,
  * 8 the same from zero, 9 interpolate + relax + norm followed by the next
- * cycle's two relaxations + residual + restriction in one pass), the summed
+ * cycle's two relaxations + residual + restriction in one pass, 10 its
+ * interpolate + relax stage alone, which rebuilds the stopping cycle's
+ * iterate), the summed
  * duration, the number of launches and the
  * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
 hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);

@@ -96,8 +96,8 @@ struct hipbmg_hier {
     int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
     int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
     int rb3 = 0;                // row-block steps of the pipelined finest kernel
-    double *x3_64 = nullptr, *q2_64 = nullptr;   // third iterate, second r/C buffer of the finest level
-    float *x3_32 = nullptr, *q2_32 = nullptr;
+    double *x3_64 = nullptr;    // third iterate buffer of the pipelined finest level
+    float *x3_32 = nullptr;
     // device-side stopping: run flag, residual history, and a ring of
     // host-mapped slots through which the host sees each cycle's test
     int *d_flags = nullptr;               // [0] run, [1] stopping cycle, [2] reason
@@ -602,11 +602,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         if (h->fused3) {
             const LevelDev<double> &F = h->lv[L - 1];
             st = dalloc(h, &h->x3_64, F.plane, s);
-            if (st == HIPBMG_OK) st = dalloc(h, &h->q2_64, F.plane, s);
-            if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) {
-                st = dalloc(h, &h->x3_32, F.plane, s);
-                if (st == HIPBMG_OK) st = dalloc(h, &h->q2_32, F.plane, s);
-            }
+            if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) st = dalloc(h, &h->x3_32, F.plane, s);
             if (st != HIPBMG_OK) return bail(st);
         }
     }
@@ -824,9 +820,6 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
 template <typename T> static T *&x3_of(hipbmg_hier *h);
 template <> double *&x3_of<double>(hipbmg_hier *h) { return h->x3_64; }
 template <> float *&x3_of<float>(hipbmg_hier *h) { return h->x3_32; }
-template <typename T> static T *&q2_of(hipbmg_hier *h);
-template <> double *&q2_of<double>(hipbmg_hier *h) { return h->q2_64; }
-template <> float *&q2_of<float>(hipbmg_hier *h) { return h->q2_32; }
 
 // Run up to max_cycles V-cycles on the hierarchy lv (FP64 levels, or the FP32
 // levels of a mixed solve) from its finest iterate x[0] (or from zero), with
@@ -849,11 +842,11 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
     const int *act = h->d_flags;
     const bool pipe = h->fused3 != 0;
     T *xb[3] = {F.x[0], F.x[1], pipe ? x3_of<T>(h) : nullptr};
-    T *qb[2] = {F.q, pipe ? q2_of<T>(h) : nullptr};
+
     std::vector<const T *> res_after((size_t)max_cycles + 1, F.x[0]);
     // pipelined: the inputs of each cycle's finest pass (iterate buffer,
-    // r/C buffer, coarse correction), to rebuild the stopping cycle's iterate
-    std::vector<int> in_i((size_t)max_cycles + 1, 0), in_qa((size_t)max_cycles + 1, 0);
+    // coarse correction), to rebuild the stopping cycle's iterate
+    std::vector<int> in_i((size_t)max_cycles + 1, 0);
     std::vector<const T *> in_xc((size_t)max_cycles + 1, nullptr);
     HIPCHK(launch_flags_reset(h->d_flags, s));
     if (pipe) {
@@ -862,7 +855,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
         StreamArgs<T> a = base_args(F, h->rb[L - 1]);
         a.x_in = xb[0];
         a.x_out = xb[1];
-        a.q_out = qb[0];
+        a.q_out = F.q;
         a.bc = Cl.b;
         a.wt = F.wt;
         a.cnx = Cl.nx;
@@ -871,7 +864,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
         a.cplane = (long long)Cl.plane;
         HIPCHK(run_stream(F, zero_start ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ, a, s));
     }
-    int k = 0, seen = 0, i = 1, qa = 0, cur = 0;
+    int k = 0, seen = 0, i = 1, cur = 0;
     bool stopped = false;
     while (k < max_cycles && !stopped) {
         ++k;
@@ -888,9 +881,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             a.x_out2 = xb[(i + 2) % 3];
             a.xc = Cl.x[cc];
             a.wt = F.wt;
-            a.q_in = qb[qa];
             a.rescorr = h->prm.residual_correction;
-            a.q_out = qb[1 - qa];
             a.bc = Cl.b;
             a.cnx = Cl.nx;
             a.cny = Cl.ny;
@@ -903,10 +894,8 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             prof_end(h, pk, s);
             res_after[k] = xb[(i + 1) % 3];
             in_i[k] = i;
-            in_qa[k] = qa;
             in_xc[k] = Cl.x[cc];
             i = (i + 2) % 3;
-            qa = 1 - qa;
         } else {
             int nc = 0;
             hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, cur, zero_start && k == 1, &nc, &np, s, false, act);
@@ -932,22 +921,22 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
     prof_collect(h, true, kdone);
     if (pipe && kdone > 0) {
         // the pipelined pass does not store the iterate after its cycle; the
-        // stopping cycle's is rebuilt by the same interpolation and relaxation
-        // from that pass's inputs, which later (skipped) cycles left untouched
+        // stopping cycle's is rebuilt by the pass's own interpolation and
+        // relaxation stage from that pass's inputs, which later (skipped)
+        // cycles left untouched
         const LevelDev<T> &Cl = lv[L - 2];
         const int ik = in_i[kdone];
-        StreamArgs<T> a = base_args(F, h->rb_up[L - 1]);
+        StreamArgs<T> a = base_args(F, h->rb3);
         a.x_in = xb[ik];
         a.x_out = xb[(ik + 1) % 3];
         a.xc = in_xc[kdone];
         a.wt = F.wt;
-        a.q_in = qb[in_qa[kdone]];
         a.rescorr = h->prm.residual_correction;
         a.cnx = Cl.nx;
         a.cny = Cl.ny;
         a.cpitch = Cl.pitch;
         a.cplane = (long long)Cl.plane;
-        HIPCHK(run_stream(F, SV_INTERP, a, s));
+        HIPCHK(run_stream(F, SV_FUSED3_P, a, s));
     }
     *cycles_done = kdone;
     *result = res_after[kdone];
@@ -1297,10 +1286,11 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
             variant == SV_SWEEP2_RQ_ZX)
             per += w + 2.0 * w + 0.25 * w;
         if (variant == SV_INTERP || variant == SV_INTERP_NORM) per += 0.25 * w + 2.0 * w + w;
-        // interpolation inputs, the weights once, r/C in and out, coarse rhs (the
+        // interpolation inputs and the weights once, coarse rhs (the
         // relaxation's x write is the next cycle's iterate; the post-relaxed
-        // iterate itself is not stored)
-        if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + w + w + 0.25 * w;
+        // iterate and r/C are not stored, r/C is formed from the loaded rows)
+        if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + 0.25 * w;
+        if (variant == SV_FUSED3_P) per += 0.25 * w + 2.0 * w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;

@@ -65,9 +65,11 @@ enum StreamVariant {
     SV_SWEEP_NORM = 6,   // relaxation plus residual norm partials
     SV_SWEEP2_RQ = 7,    // two relaxations, residual -> q, restriction -> bc
     SV_SWEEP2_RQ_ZX = 8, // the same from x = 0
-    SV_FUSED3 = 9,       // 5-point finest level: interpolate + relax (-> x_out, norm), then
-                         // two relaxations (-> x_out2), residual -> q, restriction -> bc
-    SV_COUNT = 10
+    SV_FUSED3 = 9,       // 5-point finest level: interpolate (r/C formed from the loaded
+                         // iterate) + relax (norm), then two relaxations (-> x_out2),
+                         // residual, restriction -> bc
+    SV_FUSED3_P = 10,    // the interpolate + relax stage of SV_FUSED3 alone (-> x_out)
+    SV_COUNT = 11
 };
 
 // Owned column pairs per strip for a variant (64 lanes minus halo lanes).

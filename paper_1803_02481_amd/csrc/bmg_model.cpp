@@ -66,10 +66,9 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
     const double bup = lv.up_cold ? p.beta_hbm_us_per_B : p.beta_cache_us_per_B;
     if (finest && lv.pipelined) {
         // one pass per cycle: interpolate + relax + norm of this cycle, two
-        // relaxations + residual + r/C + restriction of the next (84 B per
-        // vertex in FP64); its waves do the work of a down and an up step per
-        // row pair
-        const double bytes = n * w * (s + 3.0 + 0.25 + 2.0 + 1.0 + 1.0 + 0.25);
+        // relaxations + residual + restriction of the next (68 B per vertex in
+        // FP64); its waves do the work of a down and an up step per row pair
+        const double bytes = n * w * (s + 3.0 + 0.25 + 2.0 + 0.25);
         return kernel_us(lv.pipe, p.step_dn_us[q] + p.step_up_us[q], p.t0_dn_us[q], bytes, bdn, p);
     }
     double t = 0.0;

@@ -184,7 +184,8 @@ __device__ __forceinline__ void stage_rotate(Stage<T> &S)
 // stores if WRITE).  With RES the residual of the final rows j-2 and j-1 is
 // formed, with RQ stored as q = r/C and restricted onto coarse row (j-2)/2,
 // with NORM its squares are accumulated.
-template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM, bool WROW = false, bool STOREX = true>
+template <typename T, int NPT, bool WRITE, bool RES, bool RQ, bool NORM, bool WROW = false, bool STOREX = true,
+          bool STOREQ = true>
 __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const LaneCtx &L,
                                            const StreamArgs<T> &a)
 {
@@ -225,7 +226,7 @@ __device__ __forceinline__ void stage_step(Stage<T> &S, int j, int mode, const L
             if (NORM && WRITE && mode == 2 && L.own)
                 S.acc += (double)ae * ae + (double)ao * ao + (double)be * be + (double)bo * bo;
             if (RQ) {
-                if (WRITE && mode == 2 && L.own) {
+                if (WRITE && STOREQ && mode == 2 && L.own) {
                     if (rA && L.io) a.q_out[(size_t)(j - 2) * L.pitch + L.o] = ao / dao;
                     if (rjm) st2(a.q_out + (size_t)(j - 1) * L.pitch + L.e,
                                  L.ie ? be / dbe : T(0), L.io ? bo / dbo : T(0));
@@ -469,21 +470,25 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 }
 
 // The finest level's post-relaxation of cycle k and both pre-relaxations of
-// cycle k+1 in ONE pass (5-point operators): stage P interpolates and corrects
-// each loaded row (x_in + P x_c + q_in), relaxes it and accumulates its
-// residual norm (the convergence test of cycle k) -- the iterate after cycle
-// k itself is not stored (the solve rebuilds the stopping cycle's with one
-// interpolating relaxation from the same inputs); stage A relaxes P's final
-// rows; stage B relaxes A's final rows, stores them in x_out2 and forms the
-// residual, q_out = r/C and the restriction b_c of cycle k+1.  Each stage lags the previous one
-// by one row-pair step.  Per column, the lanes whose results are exact shrink
-// by one per stage, so 4 halo lanes are needed on each side; a row block
-// starts with four P, three A and two B prologue steps.
-template <typename T>
+// cycle k+1 in ONE pass (5-point operators).  Stage P interpolates and
+// corrects each loaded row (x_in + P x_c + r/C, the r/C of the loaded
+// iterate computed here from the raw rows around it -- the same residual the
+// previous pass's stage B formed before storing that iterate), relaxes it and
+// accumulates its residual norm (the convergence test of cycle k); the
+// iterate after cycle k itself is not stored (the solve rebuilds the stopping
+// cycle's with this kernel's P stage alone, PONLY).  Stage A relaxes P's
+// final rows; stage B relaxes A's final rows, stores them in x_out2 and forms
+// the residual and the restriction b_c of cycle k+1.  Each stage lags the
+// previous one by one row-pair step; rows are loaded one row ahead of stage
+// P, because the r/C of an odd row needs the raw row above it.  Per column,
+// the lanes whose results are exact shrink by one for P's r/C and by one per
+// stage, so 5 halo lanes are needed on each side; a row block starts with
+// four P, three A and two B prologue steps.
+template <typename T, bool PONLY>
 __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int NPT = 5;
-    constexpr int HL = 4, HR = 4, OWN = 64 - HL - HR;
+    constexpr int HL = 5, HR = 5, OWN = 64 - HL - HR;
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
     const int lane = threadIdx.x;
@@ -504,72 +509,97 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         r = Row<T>{};
         if (rv) {
             const size_t off = (size_t)j * pitch + e;
-            if (!false) ld2(a.x_in + off, r.x0, r.x1);
+            ld2(a.x_in + off, r.x0, r.x1);
             ld2(a.b + off, r.b0, r.b1);
             ld2(a.C + off, r.C0, r.C1);
             ld2(a.W + off, r.W0, r.W1);
             ld2(a.S + off, r.S0, r.S1);
-            if (NPT == 9) {
-                ld2(a.SW + off, r.SW0, r.SW1);
-                ld2(a.SE + off, r.SE0, r.SE1);
-            }
         }
-        if (true) {
-            const bool rin = j >= 1 && j <= ny - 2;
-            if (cv && rin) {
-                const int jc = j >> 1;
-                const size_t co = (size_t)jc * a.cpitch + t;
-                const T *wt = a.wt;
-                const long long cp = a.cplane;
-                r.ca = a.xc[co];
-                if (j & 1) {
-                    r.cu = a.xc[co + a.cpitch];
-                    r.w0 = wt[WYB * cp + co];
-                    r.w1 = wt[WYT * cp + co];
-                    r.w2 = wt[WCSW * cp + co];
-                    r.w3 = wt[WCSE * cp + co];
-                    r.w4 = wt[WCNW * cp + co];
-                    r.w5 = wt[WCNE * cp + co];
-                } else {
-                    r.w0 = wt[WXL * cp + co];
-                    r.w1 = wt[WXR * cp + co];
-                }
-                if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, r.q0, r.q1);
+        const bool rin = j >= 1 && j <= ny - 2;
+        if (cv && rin) {
+            const int jc = j >> 1;
+            const size_t co = (size_t)jc * a.cpitch + t;
+            const T *wt = a.wt;
+            const long long cp = a.cplane;
+            r.ca = a.xc[co];
+            if (j & 1) {
+                r.cu = a.xc[co + a.cpitch];
+                r.w0 = wt[WYB * cp + co];
+                r.w1 = wt[WYT * cp + co];
+                r.w2 = wt[WCSW * cp + co];
+                r.w3 = wt[WCSE * cp + co];
+                r.w4 = wt[WCNW * cp + co];
+                r.w5 = wt[WCNE * cp + co];
+            } else {
+                r.w0 = wt[WXL * cp + co];
+                r.w1 = wt[WXR * cp + co];
             }
         }
     };
     // x += P x_c (+ r/C at fine-only vertices) on a loaded row; coarse column t
-    auto finish_row = [&](Row<T> &r, int j) {
-        if (true) {
-            const bool rin = j >= 1 && j <= ny - 2;
-            if ((j & 1) == 0) {
-                const T xb = fromR(r.ca);
-                if (rin && ie) r.x0 += r.ca;
-                if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + r.q1;
-            } else {
-                const T xb = fromR(r.ca), xd = fromR(r.cu);
-                if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + r.q0;
-                if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + r.q1;
-            }
+    auto finish_row = [&](Row<T> &r, int j, T q0, T q1) {
+        const bool rin = j >= 1 && j <= ny - 2;
+        if ((j & 1) == 0) {
+            const T xb = fromR(r.ca);
+            if (rin && ie) r.x0 += r.ca;
+            if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + q1;
+        } else {
+            const T xb = fromR(r.ca), xd = fromR(r.cu);
+            if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + q0;
+            if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + q1;
         }
+    };
+    // r/C of the raw iterate: odd column of an even row cu, and both columns
+    // of an odd row cu (bl, ab: the raw rows below and above)
+    const bool rc = a.rescorr != 0;
+    auto rc_odd = [&](const Row<T> &bl, const Row<T> &cu, const Row<T> &ab) {
+        T d;
+        const T r = res_odd<T, NPT>(bl, cu, ab, d);
+        return rc ? r / d : T(0);
+    };
+    auto rc_even = [&](const Row<T> &bl, const Row<T> &cu, const Row<T> &ab) {
+        T d;
+        const T r = res_even<T, NPT>(bl, cu, ab, d);
+        return rc ? r / d : T(0);
     };
 
     const int nsteps = (ny - 1) / 2;
     const int s0 = blk * a.rb;
     const int s1 = min(s0 + a.rb, nsteps);
     const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+    // P alone (the rebuild) needs one prologue step; with A and B, four
+    const int jp0 = PONLY ? jfirst - 2 : jfirst - 8, jpend = PONLY ? jlast : jlast + 4;
 
-    StreamArgs<T> aB = a;          // stage B stores the next cycle's iterate and r/C
+    StreamArgs<T> aB = a;          // stage B stores the next cycle's iterate
     aB.x_out = a.x_out2;
     Stage<T> P{}, A{}, B{};
-    load_raw(P.rm1, jfirst - 9);
-    finish_row(P.rm1, jfirst - 9);
-    for (int jp = jfirst - 8; jp <= jlast + 4; jp += 2) {
-        load_raw(P.r0, jp);
-        load_raw(P.rp1, jp + 1);
-        finish_row(P.r0, jp);
-        finish_row(P.rp1, jp + 1);
-        const int modeP = jp == jfirst - 8 ? 0 : (jp >= jfirst && jp <= jlast ? 2 : 1);
+    Row<T> Rm1, Rn;                // raw rows jp-1 and jp
+    {
+        Row<T> Ra;
+        load_raw(Ra, jp0 - 2);
+        load_raw(Rm1, jp0 - 1);
+        load_raw(Rn, jp0);
+        P.rm1 = Rm1;
+        finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
+    }
+    for (int jp = jp0; jp <= jpend; jp += 2) {
+        Row<T> R1, R2;
+        load_raw(R1, jp + 1);
+        load_raw(R2, jp + 2);
+        const T q1_even_row = rc_odd(Rm1, Rn, R1);
+        const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
+        P.r0 = Rn;
+        P.rp1 = R1;
+        finish_row(P.r0, jp, T(0), q1_even_row);
+        finish_row(P.rp1, jp + 1, q0_odd_row, q1_odd_row);
+        Rm1 = R1;
+        Rn = R2;
+        const int modeP = jp == jp0 ? 0 : (jp >= jfirst && jp <= jlast ? 2 : 1);
+        if (PONLY) {
+            stage_step<T, NPT, true, false, false, false>(P, jp, modeP, L, a);
+            stage_rotate(P);
+            continue;
+        }
         // the iterate after cycle k is not stored: only the stopping cycle's
         // is needed, and it is rebuilt from this pass's inputs afterwards
         stage_step<T, NPT, true, true, false, true, false, false>(P, jp, modeP, L, a);
@@ -585,25 +615,29 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
                 B.r0 = A.rm2;
                 B.rp1 = A.rm1;
                 const int modeB = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
-                stage_step<T, NPT, true, true, true, false, true>(B, jb, modeB, L, aB);
+                // weights from the rows P loaded; r/C not stored (the next
+                // pass's P forms it from the stored iterate)
+                stage_step<T, NPT, true, true, true, false, true, true, false>(B, jb, modeB, L, aB);
                 stage_rotate(B);
             }
             stage_rotate(A);
         }
         stage_rotate(P);
     }
-    double acc = P.acc;
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) a.partials[tile] = acc;
+    if (!PONLY) {
+        double acc = P.acc;
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) a.partials[tile] = acc;
+    }
 }
 
-template <typename T>
+template <typename T, bool PONLY>
 __global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile_fn();
     if (tile >= a.ntiles) return;
-    stream3_tile<T>(a, tile);
+    stream3_tile<T, PONLY>(a, tile);
 }
 
 // XCD-aware tile order: WG i runs on XCD i mod 8, so consecutive tiles (the
@@ -654,7 +688,7 @@ __global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__re
 
 int stream_owned_pairs(int npt, int variant)
 {
-    if (variant == SV_FUSED3) return 56;
+    if (variant == SV_FUSED3 || variant == SV_FUSED3_P) return 54;
     if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX)
         return 64 - (1 + (npt == 9)) - halo_left(npt, 1) - (1 + (npt == 9)) - halo_right(npt, 0);
     int res = (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_INTERP_NORM ||
@@ -691,7 +725,11 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_SWEEP2_RQ_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true>), g, b, 0, s, a); break;
     case SV_FUSED3:
         if (NPT != 5) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stream3<T>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_stream3<T, false>), g, b, 0, s, a);
+        break;
+    case SV_FUSED3_P:
+        if (NPT != 5) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stream3<T, true>), g, b, 0, s, a);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -712,7 +750,8 @@ static const void *kernel_of(int variant)
     case SV_SWEEP_NORM: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_NORM>);
     case SV_SWEEP2_RQ: return reinterpret_cast<const void *>(&k_stream2<T, NPT, false>);
     case SV_SWEEP2_RQ_ZX: return reinterpret_cast<const void *>(&k_stream2<T, NPT, true>);
-    case SV_FUSED3: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T>) : nullptr;
+    case SV_FUSED3: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, false>) : nullptr;
+    case SV_FUSED3_P: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, true>) : nullptr;
     default: return nullptr;
     }
 }
@@ -738,6 +777,7 @@ int stream_steps_per_tile(int variant, int rb)
 {
     switch (variant) {
     case SV_FUSED3: return rb + 6;
+    case SV_FUSED3_P: return rb + 1;
     case SV_SWEEP2_RQ:
     case SV_SWEEP2_RQ_ZX: return rb + 4;
     case SV_SWEEP_RQ:

@@ -204,7 +204,8 @@ class Hierarchy:
         return {"grid_us": list(grid)[: self.L], "collapsed_us": list(wg)[: self.L], "base_us": base[0]}
 
     KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
-               "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero", "fused3")
+               "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero", "fused3",
+               "fused3_rebuild")
 
     def profile_read(self, precision=0):
         """{kernel name: (total_ms, launches, bytes_per_launch)} for launched kernels."""

@@ -28,11 +28,11 @@ FINEST = {
 }
 # algorithmic bytes per vertex (FP64, 5-point): relaxation reads x, b, C, W, S
 # and writes x; fused variants add q, the 8 weights at quarter resolution, and
-# the coarse right-hand side or coarse x; the pipelined finest pass adds to the
-# interpolating relaxation r/C out and the coarse rhs, and writes the next
-# cycle's iterate instead of this cycle's
+# the coarse right-hand side or coarse x; the pipelined finest pass reads what
+# the interpolating relaxation reads except r/C (formed from the loaded rows),
+# writes the next cycle's iterate and the coarse rhs
 ALGO_B_PER_VERTEX = {"relax": 48.0, "relax_restrict": 74.0, "interp_relax_norm": 74.0,
-                     "relax2_restrict": 74.0, "fused3": 84.0}
+                     "relax2_restrict": 74.0, "fused3": 68.0}
 
 
 def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
