@@ -24,7 +24,7 @@ FINEST = {
     "relax_restrict": "void hbmg::k_stream<double, 5, 2>(hbmg::StreamArgs<double>)",
     "interp_relax_norm": "void hbmg::k_stream<double, 5, 5>(hbmg::StreamArgs<double>)",
     "relax2_restrict": "void hbmg::k_stream2<double, 5, false>(hbmg::StreamArgs<double>)",
-    "fused3": "void hbmg::k_stream3<double>(hbmg::StreamArgs<double>)",
+    "fused3": "void hbmg::k_stream3<double, false>(hbmg::StreamArgs<double>)",
 }
 # algorithmic bytes per vertex (FP64, 5-point): relaxation reads x, b, C, W, S
 # and writes x; fused variants add q, the 8 weights at quarter resolution, and
