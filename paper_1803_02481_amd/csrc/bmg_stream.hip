@@ -574,18 +574,24 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     aB.x_out = a.x_out2;
     Stage<T> P{}, A{}, B{};
     Row<T> Rm1, Rn;                // raw rows jp-1 and jp
+    Row<T> N1, N2;                 // raw rows jp+1 and jp+2, loaded one step ahead
     {
         Row<T> Ra;
         load_raw(Ra, jp0 - 2);
         load_raw(Rm1, jp0 - 1);
         load_raw(Rn, jp0);
+        load_raw(N1, jp0 + 1);
+        load_raw(N2, jp0 + 2);
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
     for (int jp = jp0; jp <= jpend; jp += 2) {
-        Row<T> R1, R2;
-        load_raw(R1, jp + 1);
-        load_raw(R2, jp + 2);
+        const Row<T> R1 = N1, R2 = N2;
+        if (jp + 2 <= jpend) {
+            // the next step's rows: in flight while this step computes
+            load_raw(N1, jp + 3);
+            load_raw(N2, jp + 4);
+        }
         const T q1_even_row = rc_odd(Rm1, Rn, R1);
         const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
         P.r0 = Rn;
