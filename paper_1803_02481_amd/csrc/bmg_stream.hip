@@ -138,10 +138,11 @@ __device__ __forceinline__ T res_odd(const Row<T> &bl, const Row<T> &cu, const R
     }
 }
 
-// Issuing the next row pair's loads before computing the current one was
-// measured slower on gfx950 (more registers, no gain in achieved bandwidth),
-// so rows are loaded at the start of their step.
-constexpr bool kPrefetch = false;
+// The next row pair's loads are issued before the current step is computed,
+// so their latency overlaps the step's arithmetic.  It costs registers (FP64
+// two-sweep kernels drop to one wave per SIMD); measured on gfx950 it is
+// neutral for FP64 and faster for the FP32 levels of mixed precision.
+constexpr bool kPrefetch = true;
 
 template <int V> struct VariantFlags;
 template <> struct VariantFlags<SV_SWEEP>       { enum { ZX = 0, INTERP = 0, RES = 0, RQ = 0, NORM = 0 }; };
@@ -452,9 +453,16 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 
     Stage<T> A{}, B{};
     load_row(A.rm1, jfirst - 7);
+    Row<T> N0, N1;                 // rows ja and ja+1, loaded one step ahead
+    load_row(N0, jfirst - 6);
+    load_row(N1, jfirst - 5);
     for (int ja = jfirst - 6; ja <= jlast + 2; ja += 2) {
-        load_row(A.r0, ja);
-        load_row(A.rp1, ja + 1);
+        A.r0 = N0;
+        A.rp1 = N1;
+        if (ja + 2 <= jlast + 2) {
+            load_row(N0, ja + 2);
+            load_row(N1, ja + 3);
+        }
         stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
         const int jb = ja - 2;
         if (jb >= jfirst - 4) {
