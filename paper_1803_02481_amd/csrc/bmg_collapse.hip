@@ -326,7 +326,10 @@ __device__ void coarse_solve(const CollapseArgs<T> &a)
 }
 
 // stage level l into LDS: operator and weights; iterate and residual zero;
-// the top level's right-hand side (and iterate) from global memory
+// the top level's right-hand side (and iterate) from global memory.  Each
+// thread issues all loads of an index (the operator at a vertex, the 8
+// weights at a coarse vertex) before storing any, so a level costs one or two
+// memory round trips, not one per plane.
 template <typename T>
 __device__ void stage_in(const CollapseArgs<T> &a, int l)
 {
@@ -334,34 +337,48 @@ __device__ void stage_in(const CollapseArgs<T> &a, int l)
     const CV<T> v = cview<T, true>(a, l, 1);
     const int nx = g.nx, n = g.nx * g.ny, top = a.top;
     const T *xg = g.x[l == top ? a.xb_top : 1];
-    const float rnx = 1.0f / (float)nx;
-    for (int idx = threadIdx.x; idx < n; idx += CWG) {
-        const int jj = quot(idx, nx, rnx);
-        const size_t gp = (size_t)jj * g.pitch + (idx - jj * nx);
-        const_cast<T *>(v.C)[idx] = g.C[gp];
-        const_cast<T *>(v.W)[idx] = g.W[gp];
-        const_cast<T *>(v.S)[idx] = g.S[gp];
-        const_cast<T *>(v.SW)[idx] = g.SW[gp];
-        const_cast<T *>(v.SE)[idx] = g.SE[gp];
-        v.r[idx] = T(0);
-        if (l == top) {
-            v.b[idx] = g.b[gp];
-            v.x[idx] = a.zero_top ? T(0) : xg[gp];
-        } else {
-            v.b[idx] = T(0);
-            v.x[idx] = T(0);
-        }
-    }
+    int cnx = 1, cn = 0;
     if (l >= 1) {
-        const LevelDev<T> &c = a.levels[l - 1];
-        const int cnx = c.nx, cn = c.nx * c.ny;
-        const float rcnx = 1.0f / (float)cnx;
-        T *wt = const_cast<T *>(v.wt);
-        for (int k = 0; k < 8; ++k)
-            for (int idx = threadIdx.x; idx < cn; idx += CWG) {
-                const int jj = quot(idx, cnx, rcnx);
-                wt[k * cn + idx] = g.wt[k * g.cplane + (size_t)jj * g.cpitch + (idx - jj * cnx)];
+        cnx = a.levels[l - 1].nx;
+        cn = cnx * a.levels[l - 1].ny;
+    }
+    const float rnx = 1.0f / (float)nx, rcnx = 1.0f / (float)cnx;
+    const int m = n > cn ? n : cn;
+    T *wt = const_cast<T *>(v.wt);
+    for (int idx = threadIdx.x; idx < m; idx += CWG) {
+        const bool op = idx < n, wq = idx < cn;
+        T c = T(0), w = T(0), s = T(0), sw = T(0), se = T(0), bb = T(0), xx = T(0);
+        T wk[8];
+        if (op) {
+            const int jj = quot(idx, nx, rnx);
+            const size_t gp = (size_t)jj * g.pitch + (idx - jj * nx);
+            c = g.C[gp];
+            w = g.W[gp];
+            s = g.S[gp];
+            sw = g.SW[gp];
+            se = g.SE[gp];
+            if (l == top) {
+                bb = g.b[gp];
+                if (!a.zero_top) xx = xg[gp];
             }
+        }
+        if (wq) {
+            const int jj = quot(idx, cnx, rcnx);
+            const size_t cg = (size_t)jj * g.cpitch + (idx - jj * cnx);
+            for (int k = 0; k < 8; ++k) wk[k] = g.wt[k * g.cplane + cg];
+        }
+        if (op) {
+            const_cast<T *>(v.C)[idx] = c;
+            const_cast<T *>(v.W)[idx] = w;
+            const_cast<T *>(v.S)[idx] = s;
+            const_cast<T *>(v.SW)[idx] = sw;
+            const_cast<T *>(v.SE)[idx] = se;
+            v.r[idx] = T(0);
+            v.b[idx] = bb;
+            v.x[idx] = xx;
+        }
+        if (wq)
+            for (int k = 0; k < 8; ++k) wt[k * cn + idx] = wk[k];
     }
 }
 
