@@ -54,10 +54,23 @@ __device__ __forceinline__ void st2(T *__restrict__ p, T a, T b)
     *reinterpret_cast<typename Vec2<T>::type *>(p) = v;
 }
 
-// value of lane-1 / lane+1 (lane 0 / lane 63 receive an unusable value; those
-// lanes are halo lanes whose results are never stored)
-template <typename T> __device__ __forceinline__ T fromL(T v) { return __shfl_up(v, 1, 64); }
-template <typename T> __device__ __forceinline__ T fromR(T v) { return __shfl_down(v, 1, 64); }
+// value of lane-1 / lane+1 by the GFX9 whole-wave DPP shifts (wave_shr:1,
+// wave_shl:1): a VALU move with no LDS round trip.  Lane 0 / lane 63 receive
+// 0; those are halo lanes whose results are never stored.
+__device__ __forceinline__ int dpp_from_lower(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_from_upper(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+template <typename T> __device__ __forceinline__ T fromL(T v);
+template <typename T> __device__ __forceinline__ T fromR(T v);
+template <> __device__ __forceinline__ float fromL(float v) { return __int_as_float(dpp_from_lower(__float_as_int(v))); }
+template <> __device__ __forceinline__ float fromR(float v) { return __int_as_float(dpp_from_upper(__float_as_int(v))); }
+template <> __device__ __forceinline__ double fromL(double v)
+{
+    return __hiloint2double(dpp_from_lower(__double2hiint(v)), dpp_from_lower(__double2loint(v)));
+}
+template <> __device__ __forceinline__ double fromR(double v)
+{
+    return __hiloint2double(dpp_from_upper(__double2hiint(v)), dpp_from_upper(__double2loint(v)));
+}
 
 __device__ __forceinline__ int xcd_tile_fn()
 {
