@@ -70,9 +70,13 @@ hipError_t launch_demote_level(const LevelDev<double> &d, const LevelDev<float> 
     return hipGetLastError();
 }
 
+// rows per workgroup of the outer residual: fewer partial sums for the
+// single-workgroup norm that follows
+constexpr int IR_ROWS = 16;
+
 // FP64 outer residual of iterative refinement: r = b - A u (FP64, standard
 // form), written demoted to FP32 as the inner right-hand side, with per-block
-// partial sums of r^2 in FP64.
+// partial sums of r^2 in FP64 (each thread adds its IR_ROWS rows in order).
 template <int NPT>
 __global__ __launch_bounds__(256) void k_ir_residual(LevelDev<double> d, const double *__restrict__ u,
                                                      float *__restrict__ r32, int pitchf,
@@ -80,22 +84,24 @@ __global__ __launch_bounds__(256) void k_ir_residual(LevelDev<double> d, const d
 {
     __shared__ double sh[4];
     const int i = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
+    const int j0 = blockIdx.y * IR_ROWS, j1 = min(j0 + IR_ROWS, d.ny);
     double acc = 0.0;
     if (i < d.nx) {
-        const size_t p = (size_t)j * d.pitch + i, P = d.pitch;
-        float out = 0.0f;
-        if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2) {
-            double s = d.b[p] + d.W[p] * u[p - 1] + d.W[p + 1] * u[p + 1] + d.S[p] * u[p - P] +
-                       d.S[p + P] * u[p + P];
-            if (NPT == 9)
-                s += d.SW[p] * u[p - P - 1] + d.SW[p + P + 1] * u[p + P + 1] + d.SE[p] * u[p - P + 1] +
-                     d.SE[p + P - 1] * u[p + P - 1];
-            const double r = s - d.C[p] * u[p];
-            acc = r * r;
-            out = (float)r;
+        for (int j = j0; j < j1; ++j) {
+            const size_t p = (size_t)j * d.pitch + i, P = d.pitch;
+            float out = 0.0f;
+            if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2) {
+                double s = d.b[p] + d.W[p] * u[p - 1] + d.W[p + 1] * u[p + 1] + d.S[p] * u[p - P] +
+                           d.S[p + P] * u[p + P];
+                if (NPT == 9)
+                    s += d.SW[p] * u[p - P - 1] + d.SW[p + P + 1] * u[p + P + 1] + d.SE[p] * u[p - P + 1] +
+                         d.SE[p + P - 1] * u[p + P - 1];
+                const double r = s - d.C[p] * u[p];
+                acc += r * r;
+                out = (float)r;
+            }
+            r32[(size_t)j * pitchf + i] = out;
         }
-        r32[(size_t)j * pitchf + i] = out;
     }
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(256) void k_ir_residual(LevelDev<double> d, const d
 hipError_t launch_ir_residual(const LevelDev<double> &d, const double *u, float *r32, int pitchf,
                               double *partials, int *nparts, hipStream_t s)
 {
-    dim3 g((d.nx + 255) / 256, d.ny);
+    dim3 g((d.nx + 255) / 256, (d.ny + IR_ROWS - 1) / IR_ROWS);
     *nparts = g.x * g.y;
     if (d.npt == 9)
         hipLaunchKernelGGL(k_ir_residual<9>, g, dim3(256), 0, s, d, u, r32, pitchf, partials);
