@@ -65,6 +65,73 @@ def time_solves(hier, b, steps, warmup, torch):
     return el, u, info
 
 
+def oracle_workloads(args, n, extra, O, np, inputs):
+    """The single-threaded FP64 oracle timed on bounded samples of the other
+    workloads (the oracle has no FP32 path: every entry is its FP64 solve)."""
+    res = {}
+    # 65^2, D = 1: the whole solve
+    m = 65
+    oh = O.Hierarchy(O.fv5(inputs.cells_constant(m, m)))
+    bm = inputs.load_uniform(m, m, seed=0)
+    t0 = time.perf_counter()
+    _, hist = oh.solve(bm, tol=TOL)
+    el = time.perf_counter() - t0
+    res["constant_65"] = {"value": 1.0 / el, "unit": "solves/s", "cores": 1,
+                          "sample": "whole FP64 solve, %d cycles" % (len(hist))}
+    # two-phase checkerboard at n^2: a few cycles, scaled by the GPU solve's
+    # FP64 cycle count
+    cb = extra.get("checkerboard", {}).get("fp64")
+    if cb:
+        oh = O.Hierarchy(O.fv5(inputs.cells_two_phase_blocks(n, n, 64, (1.0, 1e-3), seed=3)))
+        bc = inputs.load_uniform(n, n, seed=4)
+        uc = np.zeros_like(bc)
+        k = max(1, args.cpu_cycles // 2)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            uc = oh.vcycle(bc, uc)
+        tc = (time.perf_counter() - t0) / k
+        res["checkerboard_%d" % n] = {"value": 1.0 / (tc * cb["cycles"]), "unit": "solves/s", "cores": 1,
+                                      "sample": "%d FP64 cycles (%.2f s/cycle), scaled by the %d cycles of the "
+                                                "GPU FP64 solve" % (k, tc, cb["cycles"])}
+        del oh
+    # batched: the first 8 problems solved whole, scaled to the batch by vertex count
+    if "batched" in extra:
+        sizes = inputs.batch_sizes(args.batch, seed=5)
+        sample = list(range(min(8, len(sizes))))
+        t_s, pts = 0.0, 0
+        for i in sample:
+            mi = sizes[i]
+            oh = O.Hierarchy(O.fv5(inputs.cells_lognormal(mi, mi, 1.0, seed=1000 + i)))
+            bi = inputs.load_uniform(mi, mi, seed=2000 + i)
+            t0 = time.perf_counter()
+            oh.solve(bi, tol=TOL)
+            t_s += time.perf_counter() - t0
+            pts += mi * mi
+            del oh
+        t_batch = t_s * extra["batched"]["points"] / pts
+        res["batched"] = {"value": len(sizes) / t_batch, "unit": "problems/s", "cores": 1,
+                          "sample": "FP64 solves of problems 0-%d (sizes %s, %.2f s), scaled to the batch's "
+                                    "%d vertices" % (len(sample) - 1, [sizes[i] for i in sample], t_s,
+                                                     extra["batched"]["points"])}
+    # adjoint: one 1025^2 gradient (forward solve, adjoint solve, cell kernel)
+    if "adjoint" in extra:
+        m = 1025
+        theta = inputs.theta_box5(m, m, seed=3000)
+        ba = inputs.load_uniform(m, m, seed=5000)
+        u_obs, _ = O.Hierarchy(O.fv5(np.exp(inputs.theta_box5(m, m, seed=4000)))).solve(ba, tol=TOL)
+        t0 = time.perf_counter()
+        D = np.exp(theta)
+        oh = O.Hierarchy(O.fv5(D))
+        uo, _ = oh.solve(ba, tol=TOL)
+        lam, _ = oh.solve(uo - u_obs, tol=TOL)
+        O.grad_logD(D, uo, lam)
+        el = time.perf_counter() - t0
+        res["adjoint"] = {"value": 1.0 / el, "unit": "gradients/s", "cores": 1,
+                          "sample": "one %dx%d gradient: setup, FP64 forward and adjoint solves, cell kernel "
+                                    "(%.2f s)" % (m, m, el)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +379,9 @@ def main():
                "sample": "%d FP64 V(2,1)-cycles of the single-threaded oracle on the same %dx%d problem "
                          "(%.2f s/cycle), scaled by the %d cycles the solve takes"
                          % (args.cpu_cycles, n, n, t_cycle, cycles)}
+
+    if not args.no_cpu:
+        extra["cpu_oracle_workloads"] = oracle_workloads(args, n, extra, O, np, inputs)
 
     out = {
         "metric": "solves/s to rel. residual 1e-10, 4097^2 2D diffusion: FP64 vs FP32+refinement",
