@@ -79,6 +79,13 @@ typedef struct {
     int inner_max_cycles;    /* mixed: FP32 cycles per refinement step, default 12          */
     double inner_tol;        /* mixed: inner relative residual target, default 1e-5         */
     int use_graph;           /* 1: replay the V-cycle as a captured hipGraph, default 1     */
+    int cluster_wg;          /* agglomeration stages on several workgroups between the      */
+                             /* grid-wide kernels and the collapsed workgroup (section 4):  */
+                             /* -1 chosen with l* by the model's A* search (default; needs  */
+                             /* collapse_level = -1), 0 none, K = 2, 4, ..., 256 one stage   */
+                             /* of K workgroups forced (with collapse_level and cluster_top) */
+    int cluster_top;         /* forced stage: its highest level, collapse_level < cluster_top */
+                             /* <= L - 2                                                      */
 } hipbmg_params;
 
 typedef struct {
@@ -95,6 +102,14 @@ typedef struct {
     int rb_up[HIPBMG_MAX_LEVELS];   /* row-pair steps per tile, interpolation kernels, level l  */
     int rb_pipelined;        /* row-pair steps per tile of the pipelined finest kernel, 0 if */
                              /* the finest level is not pipelined                            */
+    int cluster_stages;      /* agglomeration stages in use above l* (0: grid-wide kernels   */
+                             /* down to l*, then one workgroup)                               */
+    int cluster_wg[4];       /* workgroups of each stage, decreasing                         */
+    int cluster_hi[4];       /* highest level of each stage                                  */
+    double search_us;        /* model time of one cycle along the path the search found     */
+    int search_expanded;     /* states the A* search expanded                                */
+    double path_us;          /* model time of one cycle of the configuration in use (l* and */
+                             /* stages, searched or forced)                                   */
 } hipbmg_info;
 
 /* Fill *p with the defaults above. */
@@ -250,7 +265,7 @@ hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double 
  * the workgroup's inverse bandwidth, fitted separately for levels staged in
  * LDS and levels left in global memory, in FP64 and FP32.  The values replace
  * the process-wide model parameters used by later hipbmg_setup calls.
- * out_host (may be NULL) receives 32 doubles:
+ * out_host (may be NULL) receives 64 doubles:
  *   [0] alpha_launch_us  [1] hbm_GBps  [2] cache_GBps
  *   [3] step_dn_us FP64  [4] step_up_us FP64  [5] step_dn_us FP32  [6] step_up_us FP32
  *   [7] t_base_us FP64 (collapsed launch holding only the coarsest level)  [8] t_base_us FP32
@@ -261,7 +276,11 @@ hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double 
  *   [19] one workgroup's L2 bandwidth GBps  [20] step of a plain relaxation sweep us
  *   [21] t0_dn_us FP64  [22] t0_up_us FP64  [23] t0_dn_us FP32  [24] t0_up_us FP32 (fixed cost of
  *        a down / up streaming kernel after the previous kernel)
- *   [25..31] 0.
+ *   [25..32] alpha_stage_us FP64 and [33..40] stage GBps FP64 of an agglomeration
+ *        stage of 2, 4, ..., 256 workgroups (barrier phase cost; bytes of a level
+ *        per second), [41..48] and [49..56] the same for FP32 (sizes the
+ *        device cannot hold at once keep the uncalibrated defaults)
+ *   [57..63] 0.
  * Every timing of the solver's kernels is taken cold (after a 512 MB write
  * has evicted the caches), as the kernels run inside a solve.
  * Allocates about 1 GB of device memory for the duration of the call. */

@@ -204,7 +204,7 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
             model_params() = p;
         }
         if (out_host) {
-            for (int k = 0; k < 32; ++k) out_host[k] = 0.0;
+            for (int k = 0; k < 64; ++k) out_host[k] = 0.0;
             out_host[0] = p.alpha_launch_us;
             out_host[1] = hbm_gbps;
             out_host[2] = cache_gbps;
@@ -225,6 +225,12 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
                 out_host[21 + 2 * q] = p.t0_dn_us[q];
                 out_host[22 + 2 * q] = p.t0_up_us[q];
             }
+            for (int q = 0; q < 2; ++q)
+                for (int k = 0; k < MODEL_STAGE_SIZES; ++k) {
+                    out_host[25 + 16 * q + k] = p.alpha_stage_us[q][k];
+                    out_host[33 + 16 * q + k] =
+                        p.beta_stage_us_per_B[q][k] > 0 ? 1e-3 / p.beta_stage_us_per_B[q][k] : 0.0;
+                }
         }
     }
     if (buf) hipFree(buf);

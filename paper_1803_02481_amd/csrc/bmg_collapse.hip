@@ -127,14 +127,18 @@ __device__ __forceinline__ T point_diag(const CV<T> &L, int p)
 
 __device__ __forceinline__ int count_par(int lo, int hi) { return hi >= lo ? (hi - lo) / 2 + 1 : 0; }
 
+// The point loops below are shared by the single collapse workgroup (thread
+// tid of nthr = CWG) and the multi-workgroup stage (tid over all its
+// workgroups): every point's arithmetic is the same whichever thread does it.
+
 // one colour of Gauss-Seidel: colour k has (i mod 2, j mod 2) = (k & 1, k >> 1)
 template <typename T>
-__device__ __forceinline__ void gs_colour(const CV<T> &L, int k)
+__device__ __forceinline__ void gs_colour(const CV<T> &L, int k, int tid, int nthr)
 {
     const int i0 = (k & 1) ? 1 : 2, j0 = (k >> 1) ? 1 : 2;
     const int ni = count_par(i0, L.nx - 2), nj = count_par(j0, L.ny - 2);
     const float rni = 1.0f / (float)ni;
-    for (int idx = threadIdx.x; idx < ni * nj; idx += CWG) {
+    for (int idx = tid; idx < ni * nj; idx += nthr) {
         const int jj = quot(idx, ni, rni);
         const int i = i0 + 2 * (idx - jj * ni), j = j0 + 2 * jj;
         const int p = j * L.pitch + i;
@@ -145,11 +149,11 @@ __device__ __forceinline__ void gs_colour(const CV<T> &L, int k)
 }
 
 template <typename T>
-__device__ __forceinline__ void zero_interior(const CV<T> &L)
+__device__ __forceinline__ void zero_interior(const CV<T> &L, int tid, int nthr)
 {
     const int ni = L.nx - 2, n = ni * (L.ny - 2);
     const float rni = 1.0f / (float)ni;
-    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+    for (int idx = tid; idx < n; idx += nthr) {
         const int jj = quot(idx, ni, rni);
         L.x[(1 + jj) * L.pitch + 1 + idx - jj * ni] = T(0);
     }
@@ -157,12 +161,12 @@ __device__ __forceinline__ void zero_interior(const CV<T> &L)
 
 // r = b - A x on the interior; returns this thread's share of ||r||^2
 template <typename T>
-__device__ __forceinline__ double residual(const CV<T> &L)
+__device__ __forceinline__ double residual(const CV<T> &L, int tid, int nthr)
 {
     const int ni = L.nx - 2, n = ni * (L.ny - 2);
     const float rni = 1.0f / (float)ni;
     double acc = 0.0;
-    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+    for (int idx = tid; idx < n; idx += nthr) {
         const int jj = quot(idx, ni, rni);
         const int p = (1 + jj) * L.pitch + 1 + idx - jj * ni;
         T d;
@@ -175,13 +179,13 @@ __device__ __forceinline__ double residual(const CV<T> &L)
 
 // b_c = P^T r on the interior coarse vertices (weights in F's weight planes)
 template <typename T>
-__device__ __forceinline__ void restrict_pt(const CV<T> &F, const CV<T> &Cl)
+__device__ __forceinline__ void restrict_pt(const CV<T> &F, const CV<T> &Cl, int tid, int nthr)
 {
     const int ni = Cl.nx - 2, n = ni * (Cl.ny - 2);
     const float rni = 1.0f / (float)ni;
     const int cp = F.cplane, WP = F.cpitch, P = F.pitch;
     const T *w = F.wt, *r = F.r;
-    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+    for (int idx = tid; idx < n; idx += nthr) {
         const int jj = quot(idx, ni, rni);
         const int I = 1 + idx - jj * ni, J = 1 + jj;
         const int f = 2 * J * P + 2 * I;
@@ -197,13 +201,13 @@ __device__ __forceinline__ void restrict_pt(const CV<T> &F, const CV<T> &Cl)
 
 // x += P x_c (+ r/C at fine-only vertices); x_c is the coarse view's iterate
 template <typename T>
-__device__ __forceinline__ void interp_correct(const CV<T> &F, const CV<T> &Cl, int rescorr)
+__device__ __forceinline__ void interp_correct(const CV<T> &F, const CV<T> &Cl, int rescorr, int tid, int nthr)
 {
     const int ni = F.nx - 2, n = ni * (F.ny - 2);
     const float rni = 1.0f / (float)ni;
     const int cp = F.cplane, WP = F.cpitch, CP = Cl.pitch;
     const T *w = F.wt, *xc = Cl.x;
-    for (int idx = threadIdx.x; idx < n; idx += CWG) {
+    for (int idx = tid; idx < n; idx += nthr) {
         const int jj = quot(idx, ni, rni);
         const int i = 1 + idx - jj * ni, j = 1 + jj;
         const int p = j * F.pitch + i;
@@ -260,18 +264,19 @@ __device__ void level_down(const CollapseArgs<T> &a, int l)
 {
     const int xb = l == a.top ? a.xb_top : 1;
     const CV<T> F = cview<T, FL>(a, l, xb), Cl = cview<T, CL>(a, l - 1, 1);
+    const int tid = threadIdx.x;
     if (l < a.top || a.zero_top) {
-        zero_interior(F);
+        zero_interior(F, tid, CWG);
         __syncthreads();
     }
     for (int s = 0; s < a.nu1; ++s)
         for (int k = 0; k < 4; ++k) {
-            gs_colour(F, k);
+            gs_colour(F, k, tid, CWG);
             __syncthreads();
         }
-    residual(F);
+    residual(F, tid, CWG);
     __syncthreads();
-    restrict_pt(F, Cl);
+    restrict_pt(F, Cl, tid, CWG);
     __syncthreads();
 }
 
@@ -281,11 +286,12 @@ __device__ void level_up(const CollapseArgs<T> &a, int l)
 {
     const int xb = l == a.top ? a.xb_top : 1;
     const CV<T> F = cview<T, FL>(a, l, xb), Cl = cview<T, CL>(a, l - 1, 1);
-    interp_correct(F, Cl, a.rescorr);
+    const int tid = threadIdx.x;
+    interp_correct(F, Cl, a.rescorr, tid, CWG);
     __syncthreads();
     for (int s = 0; s < a.nu2; ++s)
         for (int k = 0; k < 4; ++k) {
-            gs_colour(F, k);
+            gs_colour(F, k, tid, CWG);
             __syncthreads();
         }
 }
@@ -415,7 +421,7 @@ __device__ __forceinline__ void collapse_body(const CollapseArgs<T> &a)
     if (top <= a.lds_top) {
         const CV<T> Lt = cview<T, true>(a, top, a.xb_top);
         if (a.want_norm) {
-            const double v = block_sum(residual(Lt), sh);
+            const double v = block_sum(residual(Lt, (int)threadIdx.x, CWG), sh);
             if (threadIdx.x == 0) a.partials[0] = v;
         }
         // the top level's iterate goes back to global memory
@@ -428,7 +434,7 @@ __device__ __forceinline__ void collapse_body(const CollapseArgs<T> &a)
         }
     } else if (a.want_norm) {
         const CV<T> Lt = cview<T, false>(a, top, a.xb_top);
-        const double v = block_sum(residual(Lt), sh);
+        const double v = block_sum(residual(Lt, (int)threadIdx.x, CWG), sh);
         if (threadIdx.x == 0) a.partials[0] = v;
     }
 }
@@ -461,14 +467,137 @@ template hipError_t launch_collapse_batched<double>(const CollapseArgs<double> *
 template hipError_t launch_collapse_batched<float>(const CollapseArgs<float> *, int, int, const int *,
                                                    hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Agglomeration stages on several workgroups of one launch.
+// ---------------------------------------------------------------------------
+
+// Longest wait at one grid barrier, in polls (each a device-scope load and a
+// short sleep: well over a second); past it the workgroup sets *err and stops
+// waiting, and every later barrier of the launch returns at once, so a launch
+// whose workgroups were not all resident still ends.
+constexpr unsigned kBarrierPollLimit = 1u << 21;
+
+// Barrier among the first K workgroups of the launch.  bar[0] counts
+// arrivals, bar[1] is the generation.  The device-scope fences write this
+// workgroup's stores back from its XCD's L2 before arriving and invalidate
+// stale lines after leaving (the XCDs' L2s are not coherent with each other).
+__device__ void grid_bar(unsigned *bar, unsigned K, int *err)
+{
+    __syncthreads();
+    if (threadIdx.x == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __threadfence();
+        const unsigned g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (arrived == K) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bar + 1, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            for (unsigned polls = 0;
+                 __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g; ++polls) {
+                if (polls >= kBarrierPollLimit ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// down leg of level l on a stage of K workgroups (thread tid of nthr)
+template <typename T>
+__device__ void cluster_down(const ClusterArgs<T> &a, int l, int tid, int nthr, unsigned *bar, int K)
+{
+    const CollapseArgs<T> &c = a.col;
+    const CV<T> F = cview<T, false>(c, l, l == a.hi[0] ? a.xb_top : 1), Cl = cview<T, false>(c, l - 1, 1);
+    zero_interior(F, tid, nthr);
+    grid_bar(bar, K, a.err);
+    for (int s = 0; s < c.nu1; ++s)
+        for (int k = 0; k < 4; ++k) {
+            gs_colour(F, k, tid, nthr);
+            grid_bar(bar, K, a.err);
+        }
+    residual(F, tid, nthr);
+    grid_bar(bar, K, a.err);
+    restrict_pt(F, Cl, tid, nthr);
+    grid_bar(bar, K, a.err);
+}
+
+// up leg of level l on a stage of K workgroups
+template <typename T>
+__device__ void cluster_up(const ClusterArgs<T> &a, int l, int tid, int nthr, unsigned *bar, int K)
+{
+    const CollapseArgs<T> &c = a.col;
+    const CV<T> F = cview<T, false>(c, l, l == a.hi[0] ? a.xb_top : 1), Cl = cview<T, false>(c, l - 1, 1);
+    interp_correct(F, Cl, c.rescorr, tid, nthr);
+    grid_bar(bar, K, a.err);
+    for (int s = 0; s < c.nu2; ++s)
+        for (int k = 0; k < 4; ++k) {
+            gs_colour(F, k, tid, nthr);
+            grid_bar(bar, K, a.err);
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(CWG) void k_cluster(ClusterArgs<T> a)
+{
+    if (a.active && *a.active == 0) return;
+    const int wg = blockIdx.x;
+    int s = 0;
+    // down legs; a workgroup beyond a stage's count leaves the descent there
+    for (; s < a.nstage && wg < a.wg[s]; ++s) {
+        const int K = a.wg[s];
+        for (int l = a.hi[s]; l > a.hi[s + 1]; --l)
+            cluster_down(a, l, wg * CWG + (int)threadIdx.x, K * CWG, a.bar + 2 * s, K);
+    }
+    // workgroup 0, the only one in every stage, collapses the rest
+    if (s == a.nstage && wg == 0) collapse_body(a.col);
+    // up legs: each stage first waits for the coarser ones
+    for (int t = a.nstage - 1; t >= 0; --t) {
+        if (wg >= a.wg[t]) continue;
+        const int K = a.wg[t];
+        grid_bar(a.bar + 2 * t, K, a.err);
+        for (int l = a.hi[t + 1] + 1; l <= a.hi[t]; ++l)
+            cluster_up(a, l, wg * CWG + (int)threadIdx.x, K * CWG, a.bar + 2 * t, K);
+    }
+}
+
+template <typename T>
+hipError_t launch_cluster(const ClusterArgs<T> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cluster<T>), dim3(a.wg[0]), dim3(CWG), a.col.lds_bytes, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_cluster<double>(const ClusterArgs<double> &, hipStream_t);
+template hipError_t launch_cluster<float>(const ClusterArgs<float> &, hipStream_t);
+
+template <typename T>
+int cluster_max_resident(int lds_bytes)
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cluster<T>), CWG,
+                                                     (size_t)lds_bytes) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+template int cluster_max_resident<double>(int);
+template int cluster_max_resident<float>(int);
+
 // allow the collapse kernels the large dynamic LDS they stage levels in (called
 // at setup, outside any stream capture)
 hipError_t collapse_set_attributes()
 {
-    const void *fns[4] = {reinterpret_cast<const void *>(&k_collapse<double>),
+    const void *fns[6] = {reinterpret_cast<const void *>(&k_collapse<double>),
                           reinterpret_cast<const void *>(&k_collapse<float>),
                           reinterpret_cast<const void *>(&k_collapse_batched<double>),
-                          reinterpret_cast<const void *>(&k_collapse_batched<float>)};
+                          reinterpret_cast<const void *>(&k_collapse_batched<float>),
+                          reinterpret_cast<const void *>(&k_cluster<double>),
+                          reinterpret_cast<const void *>(&k_cluster<float>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, COLLAPSE_LDS_BUDGET);
         if (e != hipSuccess) return e;

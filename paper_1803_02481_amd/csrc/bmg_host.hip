@@ -63,6 +63,8 @@ extern "C" void hipbmg_default_params(hipbmg_params *p)
     p->inner_max_cycles = 12;
     p->inner_tol = 1e-5;
     p->use_graph = 1;
+    p->cluster_wg = -1;
+    p->cluster_top = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -88,6 +90,14 @@ struct hipbmg_hier {
     double *d_scal = nullptr;   // [0] ||b||, [1] relres, [2] ||r|| (mixed outer), [3] inner relres
     double *h_scal = nullptr;   // pinned mirror
     int lstar = 0;
+    // agglomeration stages between the grid-wide kernels and the collapse
+    int cl_nstage = 0;
+    int cl_wg[CLUSTER_MAX_STAGES] = {}, cl_hi[CLUSTER_MAX_STAGES] = {};
+    unsigned *d_bar = nullptr;   // grid barriers of the stages
+    int *d_err = nullptr;        // a stage barrier gave up waiting
+    double search_us = 0.0;
+    int search_expanded = 0;
+    double path_us = 0.0;        // model time of one cycle of the configuration in use
     double model_us[HIPBMG_MAX_LEVELS] = {};
     double setup_ms = 0.0;
     std::vector<int> rb;        // row-block steps per level, pre-relaxation (down) kernels
@@ -626,6 +636,70 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             if (h->model_us[l] < h->model_us[best]) best = l;
     }
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
+    // agglomeration stages: the redistribution search of section 4 over
+    // (level, workgroups), or one forced stage
+    {
+        const int word = prm.precision == HIPBMG_MIXED ? 4 : 8;
+        const int res = prm.precision == HIPBMG_MIXED ? cluster_max_resident<float>(COLLAPSE_LDS_BUDGET)
+                                                      : cluster_max_resident<double>(COLLAPSE_LDS_BUDGET);
+        const int max_wg = std::min(256, res);
+        const ModelPath path = model_search(ml, L, prm.nu1, prm.nu2, h->nc, word, h->mp, max_wg, lcap);
+        h->search_us = path.t_us;
+        h->search_expanded = path.expanded;
+        if (prm.cluster_wg >= 2) {
+            const int K = prm.cluster_wg, top = prm.cluster_top;
+            if (K > 256 || (K & (K - 1)) != 0)
+                return bail(fail(HIPBMG_EINVAL, "cluster_wg %d: must be a power of two from 2 to 256", K));
+            if (K > max_wg)
+                return bail(fail(HIPBMG_EINVAL, "cluster_wg %d: only %d workgroups fit on the device", K, max_wg));
+            if (prm.collapse_level < 0 || top <= prm.collapse_level || top > L - 2 || top > lcap)
+                return bail(fail(HIPBMG_EINVAL, "cluster_top %d: needs collapse_level < cluster_top <= %d", top,
+                                 std::min(L - 2, lcap)));
+            h->cl_nstage = 1;
+            h->cl_wg[0] = K;
+            h->cl_hi[0] = top;
+        } else if (prm.cluster_wg == -1 && prm.collapse_level < 0 && std::isfinite(path.t_us)) {
+            h->lstar = path.lstar;
+            h->cl_nstage = std::min(path.nstage, CLUSTER_MAX_STAGES);
+            for (int k = 0; k < h->cl_nstage; ++k) {
+                h->cl_wg[k] = path.wg[k];
+                h->cl_hi[k] = path.hi[k];
+            }
+        } else if (prm.cluster_wg != 0 && prm.cluster_wg != -1) {
+            return bail(fail(HIPBMG_EINVAL, "cluster_wg %d: must be -1, 0 or a power of two from 2 to 256",
+                             prm.cluster_wg));
+        }
+        // HIPBMG_STAGES="K1:top1,K2:top2,..." forces several stages above a
+        // forced collapse level (decreasing workgroups and levels)
+        if (const char *e = std::getenv("HIPBMG_STAGES")) {
+            if (prm.collapse_level < 0 || prm.cluster_wg != -1)
+                return bail(fail(HIPBMG_EINVAL, "HIPBMG_STAGES needs collapse_level >= 0 and cluster_wg = -1"));
+            int n = 0, wg[CLUSTER_MAX_STAGES], hi[CLUSTER_MAX_STAGES];
+            const char *c = e;
+            while (*c && n < CLUSTER_MAX_STAGES) {
+                int K = 0, top = 0, used = 0;
+                if (std::sscanf(c, "%d:%d%n", &K, &top, &used) != 2) break;
+                const bool ok = K >= 2 && K <= max_wg && (K & (K - 1)) == 0 && top <= std::min(L - 2, lcap) &&
+                                top > prm.collapse_level && (n == 0 || (K < wg[n - 1] && top < hi[n - 1]));
+                if (!ok) return bail(fail(HIPBMG_EINVAL, "HIPBMG_STAGES: bad stage %d:%d", K, top));
+                wg[n] = K;
+                hi[n] = top;
+                ++n;
+                c += used;
+                if (*c == ',') ++c;
+            }
+            h->cl_nstage = n;
+            for (int k = 0; k < n; ++k) {
+                h->cl_wg[k] = wg[k];
+                h->cl_hi[k] = hi[k];
+            }
+        }
+        h->path_us = model_path_us(ml, L, prm.nu1, prm.nu2, h->nc, word, h->mp, h->lstar, h->cl_nstage, h->cl_wg,
+                                   h->cl_hi);
+        st = dalloc(h, &h->d_bar, 2 * CLUSTER_MAX_STAGES, s);
+        if (st == HIPBMG_OK) st = dalloc(h, &h->d_err, 1, s);
+        if (st != HIPBMG_OK) return bail(st);
+    }
     if (h->lstar >= L - 1) h->fused3 = 0;   // the finest level itself is collapsed
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
                                                              hipGetErrorString(hipGetLastError())));
@@ -715,6 +789,29 @@ static CollapseArgs<T> collapse_args(const hipbmg_hier *h, const std::vector<Lev
     return c;
 }
 
+// Agglomeration stages above collapse level lstar: stage k on wg[k]
+// workgroups from level hi[k] down; workgroup 0 collapses levels 0..lstar
+// (from zero, no norm); the highest stage level's iterate ends in x[1].
+template <typename T>
+static ClusterArgs<T> cluster_args(const hipbmg_hier *h, const std::vector<LevelDev<T>> &lv,
+                                   const LevelDev<T> *d_lv, int lstar, int nstage, const int *wg, const int *hi,
+                                   const int *active)
+{
+    ClusterArgs<T> a{};
+    a.col = collapse_args<T>(h, lv, d_lv, lstar, 1, 1, 0);
+    a.nstage = nstage;
+    for (int k = 0; k < nstage; ++k) {
+        a.wg[k] = wg[k];
+        a.hi[k] = hi[k];
+    }
+    a.hi[nstage] = lstar;
+    a.xb_top = 1;
+    a.bar = h->d_bar;
+    a.err = h->d_err;
+    a.active = active;
+    return a;
+}
+
 // Enqueue one V-cycle on the hierarchy `lv` whose finest iterate is in
 // x[cur] (or is zero if zero_start).  The finest post-relaxation leaves its
 // residual norm partials in d_partials (*nparts of them).  Returns the buffer
@@ -730,9 +827,11 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
     // correction
     const int L = skip_finest ? h->L - 1 : h->L, ls = h->lstar;
     const int nu1 = h->prm.nu1, nu2 = h->prm.nu2, rc = h->prm.residual_correction;
+    // highest level below the grid-wide kernels: the first stage's, or l*
+    const int gtop = h->cl_nstage > 0 ? h->cl_hi[0] : ls;
     int xb_after[HIPBMG_MAX_LEVELS], xres[HIPBMG_MAX_LEVELS];
     hipError_t e = hipSuccess;
-    for (int l = L - 1; l > ls; --l) {
+    for (int l = L - 1; l > gtop; --l) {
         const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
         const bool fine = l == h->L - 1;
         int xb = fine ? cur : 0;
@@ -765,8 +864,15 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         }
         xb_after[l] = xb;
     }
-    // levels 0..l* in one workgroup
-    {
+    if (h->cl_nstage > 0) {
+        // levels 0..gtop in one launch: the stages, then the collapse
+        const ClusterArgs<T> c = cluster_args<T>(h, lv, d_lv, ls, h->cl_nstage, h->cl_wg, h->cl_hi, active);
+        const int pk = prof_begin(h, -1, PrecIdx<T>::v, gtop, 2, false, s);
+        if ((e = launch_cluster<T>(c, s)) != hipSuccess) return e;
+        prof_end(h, pk, s);
+        xres[gtop] = c.xb_top;
+    } else {
+        // levels 0..l* in one workgroup
         const bool fine = ls == h->L - 1;
         CollapseArgs<T> c = collapse_args<T>(h, lv, d_lv, ls, fine ? cur : 1, fine ? (zero_start ? 1 : 0) : 1,
                                              fine ? 1 : 0);
@@ -781,7 +887,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             return hipSuccess;
         }
     }
-    for (int l = ls + 1; l < L; ++l) {
+    for (int l = gtop + 1; l < L; ++l) {
         const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
         const bool fine = l == h->L - 1;
         int xb = xb_after[l];
@@ -963,6 +1069,29 @@ static void fill_info_common(hipbmg_hier *h, hipbmg_info *info)
     }
     info->rb_pipelined = h->fused3 ? h->rb3 : 0;
     info->setup_ms = h->setup_ms;
+    info->cluster_stages = h->cl_nstage;
+    for (int k = 0; k < 4; ++k) {
+        info->cluster_wg[k] = k < h->cl_nstage ? h->cl_wg[k] : 0;
+        info->cluster_hi[k] = k < h->cl_nstage ? h->cl_hi[k] : 0;
+    }
+    info->search_us = h->search_us;
+    info->search_expanded = h->search_expanded;
+    info->path_us = h->path_us;
+}
+
+// A stage barrier that gave up waiting (its workgroups were not all resident)
+// leaves a flag: report it, and reset the barriers for the next solve.
+static hipbmg_status check_stage_barriers(hipbmg_hier *h, hipStream_t s)
+{
+    if (h->cl_nstage == 0) return HIPBMG_OK;
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!err) return HIPBMG_OK;
+    HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(h->d_bar, 0, 2 * CLUSTER_MAX_STAGES * sizeof(unsigned), s));
+    HIPCHK(hipStreamSynchronize(s));
+    return fail(HIPBMG_EHIP, "an agglomeration-stage barrier gave up waiting (workgroups not all resident)");
 }
 
 static hipbmg_status solve_fp64(hipbmg_hier *h, double tol, hipStream_t s, hipbmg_info *info,
@@ -1074,6 +1203,7 @@ extern "C" hipbmg_status hipbmg_solve(hipbmg_handle h, const double *b, double *
     hipbmg_status st = h->prm.precision == HIPBMG_MIXED ? solve_mixed(h, tol, s, info)
                                                          : solve_fp64(h, tol, s, info, &res);
     if (st != HIPBMG_OK && st != HIPBMG_ENOCONV && st != HIPBMG_ENAN) return st;
+    STCHK(check_stage_barriers(h, s));
     std::string msg = g_err;
     HIPCHK(hipMemcpy2DAsync(u, nx * sizeof(double), res, F.pitch * sizeof(double),
                             nx * sizeof(double), ny, hipMemcpyDeviceToDevice, s));
@@ -1431,6 +1561,37 @@ static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev
         p.alpha_bar_us[q][g] = a / P;
         p.beta_wg_us_per_B[q][g] = b;
     }
+    // agglomeration stages: one launch of K workgroups running levels
+    // 2..top, with levels 0..1 collapsed on workgroup 0, for every top (top = 1:
+    // the stage runs no level); the increments are the levels' costs on K
+    // workgroups, fitted to phases x alpha_stage + bytes x beta_stage
+    {
+        const int max_wg = std::min(256, cluster_max_resident<T>(COLLAPSE_LDS_BUDGET));
+        for (int k = 0; k < MODEL_STAGE_SIZES && L >= 4; ++k) {
+            const int K = 2 << k;
+            if (K > max_wg) break;
+            std::vector<double> bx, by;
+            double prev = 0.0;
+            for (int top = 1; top <= L - 2; ++top) {
+                const int wg[1] = {K}, hi[1] = {top};
+                const ClusterArgs<T> a = cluster_args<T>(h, lv, d_lv, 1, 1, wg, hi, nullptr);
+                const double t = ct.us(3, [&] { (void)launch_cluster<T>(a, s); });
+                if (top >= 2) {
+                    bx.push_back(model_wg_bytes(lv[top].nx, lv[top].ny, nu1, nu2, word));
+                    by.push_back(t - prev);
+                }
+                prev = t;
+            }
+            double a = P * p.alpha_stage_us[q][k], b = p.beta_stage_us_per_B[q][k];
+            fit_nonneg(bx, by, &a, &b);
+            p.alpha_stage_us[q][k] = a / P;
+            p.beta_stage_us_per_B[q][k] = b;
+        }
+        int err = 0;
+        if (hipMemcpy(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || err)
+            return hipErrorLaunchFailure;
+        p.stages_calibrated = 1;
+    }
     // grid kernels of every level below the finest (zero-start pre-relaxation
     // fused with residual and restriction; interpolating relaxation), each at
     // two row-block lengths: on a level whose waves all fit in one residency
@@ -1529,6 +1690,7 @@ hipbmg_status hbmg::calibrate_on_kernels(void *stream, ModelParams &p)
     hipbmg_default_params(&prm);
     prm.precision = HIPBMG_MIXED;
     prm.collapse_level = 0;
+    prm.cluster_wg = 0;
     if ((st = hipbmg_setup(n, n, 5, planes, &prm, stream, &h)) != HIPBMG_OK) {
         cleanup();
         return st;
@@ -2021,6 +2183,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     hipbmg_params prm;
     hipbmg_default_params(&prm);
     if (params) prm = *params;
+    prm.cluster_wg = 0;   // a batch collapses each problem at its own l*, no stages
     hipbmg_batch *B = new hipbmg_batch();
     B->n = nprob;
     B->prm = prm;

@@ -123,6 +123,32 @@ struct CollapseArgs {
 };
 template <typename T>
 hipError_t launch_collapse(const CollapseArgs<T> &a, hipStream_t s);
+
+// Agglomeration stages between the grid-wide kernels and the collapsed
+// workgroup (section 4: the coarse grid moves onto fewer and fewer
+// processors).  One launch of wg[0] workgroups: stage s runs levels
+// hi[s] down to hi[s+1]+1 on its first wg[s] workgroups, with a grid barrier
+// where the single workgroup has a workgroup barrier; workgroup 0 then runs
+// the collapse of levels 0..col.top (= hi[nstage]); the up legs follow in
+// reverse order.  The stages' workgroup counts decrease.
+constexpr int CLUSTER_MAX_STAGES = 4;
+template <typename T>
+struct ClusterArgs {
+    CollapseArgs<T> col;                 // levels 0..col.top on workgroup 0 (from zero, no norm)
+    int nstage;
+    int wg[CLUSTER_MAX_STAGES];
+    int hi[CLUSTER_MAX_STAGES + 1];
+    int xb_top;                          // iterate buffer of level hi[0] (its residual: the other)
+    unsigned *bar;                       // per stage: arrival count, generation
+    int *err;                            // set when a barrier wait gives up
+    const int *active;                   // run flag as in StreamArgs
+};
+template <typename T>
+hipError_t launch_cluster(const ClusterArgs<T> &a, hipStream_t s);
+// workgroups of the cluster kernel that fit on the device at once with
+// `lds_bytes` of dynamic LDS each (0 on error)
+template <typename T>
+int cluster_max_resident(int lds_bytes);
 template <typename T>
 size_t collapse_lds_bytes(int nx, int ny, int cnx, int cny);
 hipError_t collapse_set_attributes();

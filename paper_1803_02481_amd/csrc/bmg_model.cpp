@@ -14,6 +14,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
+#include <queue>
+#include <vector>
 
 namespace hbmg {
 
@@ -39,6 +42,13 @@ ModelParams &model_params()
         }
         d.gamma_wg_us_per_flop = 1.0e-3;
         d.lds_budget_bytes = 150.0 * 1024.0;
+        // until measured, stages cost far more than either alternative
+        for (int q = 0; q < 2; ++q)
+            for (int k = 0; k < MODEL_STAGE_SIZES; ++k) {
+                d.alpha_stage_us[q][k] = 50.0;
+                d.beta_stage_us_per_B[q][k] = 1.0 / 1.0e4;
+            }
+        d.stages_calibrated = 0;
         d.calibrated = 0;
         return d;
     }();
@@ -131,6 +141,221 @@ int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word
         if (t < t_us[best]) best = ls;
     }
     return best;
+}
+
+static const double kInf = std::numeric_limits<double>::infinity();
+constexpr int kSingle = MODEL_MODES - 1;
+constexpr int kMaxStages = 4;
+
+int model_mode_wg(int m)
+{
+    if (m <= 0) return 0;
+    if (m >= kSingle) return 1;
+    return 256 >> (m - 1);
+}
+
+// stage parameters of mode m: index k with 2^(k+1) workgroups
+static int stage_index(int m) { return MODEL_STAGE_SIZES - m; }
+
+double model_level_cost(const ModelLevel *lv, int L, int l, int m, int nu1, int nu2, int word,
+                        const ModelParams &p, int max_wg, int lcap)
+{
+    if (l < 1 || l >= L) return kInf;   // level 0 is the coarse solve, inside the hand-off
+    if (m == 0) return model_grid_level_us(lv[l], l == L - 1, nu1, nu2, word, p);
+    if (l > lcap) return kInf;
+    if (m == kSingle) return model_wg_level_us(lv[l], nu1, nu2, word, p);
+    if (l >= L - 1 || model_mode_wg(m) > max_wg) return kInf;
+    const int q = word == 4 ? 1 : 0, k = stage_index(m);
+    return model_wg_phases(nu1, nu2) * p.alpha_stage_us[q][k] +
+           model_wg_bytes(lv[l].nx, lv[l].ny, nu1, nu2, word) * p.beta_stage_us_per_B[q][k];
+}
+
+// agglomeration at level l from mode m onto mode m2: the launch that starts
+// the several-workgroup part (its coarsest-level part inside it), or the
+// collapse launch
+static double handoff_us(int l, int L, int m, int m2, int nc, int word, const ModelParams &p, int max_wg,
+                         int lcap)
+{
+    if (m2 <= m || l > lcap) return kInf;
+    if (m2 == kSingle) return m == 0 ? model_base_us(nc, word, p) : model_base_us(nc, word, p) - p.alpha_launch_us;
+    if (l >= L - 1 || model_mode_wg(m2) > max_wg) return kInf;
+    return m == 0 ? p.alpha_launch_us : 0.0;
+}
+
+namespace {
+struct SearchCtx {
+    const ModelLevel *lv;
+    int L, nu1, nu2, nc, word, max_wg, lcap;
+    const ModelParams *p;
+    double level(int l, int m) const { return model_level_cost(lv, L, l, m, nu1, nu2, word, *p, max_wg, lcap); }
+    double handoff(int l, int m, int m2) const { return handoff_us(l, L, m, m2, nc, word, *p, max_wg, lcap); }
+    int id(int l, int m, int n) const { return (l * MODEL_MODES + m) * (kMaxStages + 1) + n; }
+};
+
+// a path as the list of (level, mode) states it passes, start to goal
+ModelPath path_from_states(const SearchCtx &c, const std::vector<std::pair<int, int>> &st, double g, int expanded)
+{
+    ModelPath r{};
+    r.t_us = g + c.p->alpha_launch_us;   // norm finalisation after the cycle
+    r.expanded = expanded;
+    r.lstar = 0;
+    // levels run in each mode: a move (l, m) -> (l-1, m) runs level l in m
+    int cur_m = -1;
+    for (size_t i = 1; i < st.size(); ++i) {
+        const int l0 = st[i - 1].first, m0 = st[i - 1].second, l1 = st[i].first;
+        if (l1 == l0 - 1 && m0 > 0 && m0 < kSingle) {
+            if (m0 != cur_m) {
+                if (r.nstage < 4) {
+                    r.wg[r.nstage] = model_mode_wg(m0);
+                    r.hi[r.nstage] = l0;
+                    ++r.nstage;
+                }
+                cur_m = m0;
+            }
+        }
+        if (st[i].second == kSingle && m0 != kSingle) r.lstar = l0;
+    }
+    return r;
+}
+}  // namespace
+
+ModelPath model_search(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word, const ModelParams &p,
+                       int max_wg, int lcap)
+{
+    const SearchCtx c{lv, L, nu1, nu2, nc, word, max_wg, lcap, &p};
+    // heuristic: cheapest cost of each level left over the modes still
+    // reachable, plus the cheapest hand-off into one workgroup
+    std::vector<double> hs((size_t)L * MODEL_MODES, 0.0);
+    const double base = model_base_us(nc, word, p);
+    for (int m = 0; m < MODEL_MODES; ++m) {
+        double acc = m == kSingle ? 0.0 : (m == 0 ? base : base - p.alpha_launch_us);
+        hs[m] = acc;
+        for (int l = 1; l < L; ++l) {
+            double mn = kInf;
+            for (int m2 = m; m2 < MODEL_MODES; ++m2) mn = std::min(mn, c.level(l, m2));
+            if (std::isfinite(mn)) acc += mn;
+            hs[(size_t)l * MODEL_MODES + m] = acc;
+        }
+    }
+    const int nstates = L * MODEL_MODES * (kMaxStages + 1);
+    std::vector<double> g(nstates, kInf);
+    std::vector<int> parent(nstates, -1);
+    std::vector<char> closed(nstates, 0);
+    struct Node {
+        double f;
+        int id, l, m, n;
+        bool operator<(const Node &o) const { return f > o.f || (f == o.f && id > o.id); }
+    };
+    std::priority_queue<Node> open;
+    const int s0 = c.id(L - 1, 0, 0);
+    g[s0] = 0.0;
+    open.push({hs[(size_t)(L - 1) * MODEL_MODES], s0, L - 1, 0, 0});
+    int expanded = 0, goal = -1;
+    auto relax = [&](int from, int l, int m, int n, double cost) {
+        if (!std::isfinite(cost)) return;
+        const int to = c.id(l, m, n);
+        const double gn = g[from] + cost;
+        if (gn < g[to] && !closed[to]) {
+            g[to] = gn;
+            parent[to] = from;
+            open.push({gn + hs[(size_t)l * MODEL_MODES + m], to, l, m, n});
+        }
+    };
+    while (!open.empty()) {
+        const Node nd = open.top();
+        open.pop();
+        if (closed[nd.id]) continue;
+        closed[nd.id] = 1;
+        ++expanded;
+        if (nd.l == 0 && nd.m == kSingle) {
+            goal = nd.id;
+            break;
+        }
+        if (nd.l >= 1) relax(nd.id, nd.l - 1, nd.m, nd.n, c.level(nd.l, nd.m));
+        for (int m2 = nd.m + 1; m2 < MODEL_MODES; ++m2) {
+            const int n2 = nd.n + (m2 != kSingle ? 1 : 0);
+            if (n2 > kMaxStages) continue;
+            relax(nd.id, nd.l, m2, n2, c.handoff(nd.l, nd.m, m2));
+        }
+    }
+    ModelPath r{};
+    if (goal < 0) {
+        r.t_us = kInf;
+        r.expanded = expanded;
+        return r;
+    }
+    std::vector<std::pair<int, int>> st;
+    for (int v = goal; v >= 0; v = parent[v]) {
+        const int n = v % (kMaxStages + 1), lm = v / (kMaxStages + 1);
+        (void)n;
+        st.push_back({lm / MODEL_MODES, lm % MODEL_MODES});
+    }
+    std::reverse(st.begin(), st.end());
+    return path_from_states(c, st, g[goal], expanded);
+}
+
+ModelPath model_search_exhaustive(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word,
+                                  const ModelParams &p, int max_wg, int lcap)
+{
+    const SearchCtx c{lv, L, nu1, nu2, nc, word, max_wg, lcap, &p};
+    double best = kInf;
+    std::vector<std::pair<int, int>> cur, best_st;
+    int visited = 0;
+    // depth-first over every path from (L-1, 0) to (0, one workgroup)
+    struct Rec {
+        const SearchCtx &c;
+        double &best;
+        std::vector<std::pair<int, int>> &cur, &best_st;
+        int &visited;
+        void go(int l, int m, int n, double g)
+        {
+            ++visited;
+            cur.push_back({l, m});
+            if (l == 0 && m == kSingle) {
+                if (g < best) {
+                    best = g;
+                    best_st = cur;
+                }
+            } else {
+                const double cl = l >= 1 ? c.level(l, m) : kInf;
+                if (std::isfinite(cl)) go(l - 1, m, n, g + cl);
+                for (int m2 = m + 1; m2 < MODEL_MODES; ++m2) {
+                    const int n2 = n + (m2 != kSingle ? 1 : 0);
+                    const double h = c.handoff(l, m, m2);
+                    if (n2 <= kMaxStages && std::isfinite(h)) go(l, m2, n2, g + h);
+                }
+            }
+            cur.pop_back();
+        }
+    } rec{c, best, cur, best_st, visited};
+    rec.go(L - 1, 0, 0, 0.0);
+    if (!std::isfinite(best)) {
+        ModelPath r{};
+        r.t_us = kInf;
+        r.expanded = visited;
+        return r;
+    }
+    return path_from_states(c, best_st, best, visited);
+}
+
+double model_path_us(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word, const ModelParams &p,
+                     int lstar, int nstage, const int *wg, const int *hi)
+{
+    const SearchCtx c{lv, L, nu1, nu2, nc, word, 256, L - 1, &p};
+    const int top = nstage > 0 ? hi[0] : lstar;
+    double t = 0.0;
+    for (int l = L - 1; l > top; --l) t += c.level(l, 0);
+    for (int s = 0; s < nstage; ++s) {
+        const int lo = s + 1 < nstage ? hi[s + 1] : lstar;
+        int m = 1;
+        while (m < kSingle && model_mode_wg(m) != wg[s]) ++m;
+        for (int l = hi[s]; l > lo; --l) t += c.level(l, m);
+    }
+    for (int l = lstar; l >= 1; --l) t += c.level(l, kSingle);
+    // the collapse launch, or the stages' launch with the collapse inside it
+    // (its launch gap, then the collapse without one): the same total
+    t += model_base_us(nc, word, p);
+    return t + p.alpha_launch_us;
 }
 
 }  // namespace hbmg

@@ -45,7 +45,10 @@ struct ModelLevel {
 // which bound a grid-wide kernel on a level too small to fill the GPU; and
 // t_base, the collapsed launch holding only the coarsest level.
 // Per-precision entries are indexed [0] FP64, [1] FP32; alpha_bar and beta_wg
-// also by [0] LDS, [1] global.
+// also by [0] LDS, [1] global.  An agglomeration stage of 2^(k+1) workgroups
+// (k < MODEL_STAGE_SIZES) costs alpha_stage per barrier phase plus bytes x
+// beta_stage per level.
+constexpr int MODEL_STAGE_SIZES = 8;   // 2, 4, ..., 256 workgroups
 struct ModelParams {
     double alpha_launch_us;
     double beta_hbm_us_per_B;
@@ -60,6 +63,9 @@ struct ModelParams {
     double beta_wg_us_per_B[2][2];
     double gamma_wg_us_per_flop;
     double lds_budget_bytes;    // LDS available for staged collapsed levels
+    double alpha_stage_us[2][MODEL_STAGE_SIZES];
+    double beta_stage_us_per_B[2][MODEL_STAGE_SIZES];
+    int stages_calibrated;      // 1 once the stage terms are measured
     int calibrated;             // 1 once measured on the device
 };
 
@@ -85,6 +91,39 @@ int model_choose(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word
 // the collapsed launch holding only the coarsest level (nc unknowns):
 // launch gap, base cost and coarse solve
 double model_base_us(int nc, int word, const ModelParams &p);
+
+// The redistribution search of section 4 on one GPU.  A state is (level l,
+// processors m): m = 0 all processors (grid-wide kernels), m = 1..8 a stage
+// of 256, 128, ..., 2 workgroups (the factor-2 enumeration), m = 9 one
+// workgroup.  From (l, m) the solve either runs level l there and moves to
+// (l-1, m), or agglomerates onto fewer processors, (l, m') with m' > m.  The
+// start is (L-1, 0), the goal (0, 9): level 0 is the coarse solve.  g is the
+// model time so far; the heuristic h is the sum over the levels left of
+// their cheapest cost on the processors still reachable, plus the cheapest
+// hand-off to one workgroup, which never overestimates.
+constexpr int MODEL_MODES = MODEL_STAGE_SIZES + 2;
+struct ModelPath {
+    int lstar;        // levels 0..lstar in one workgroup
+    int nstage;       // stages on several workgroups, above it
+    int wg[4], hi[4]; // workgroups and highest level of each stage, decreasing
+    double t_us;      // model time of one cycle along the path
+    int expanded;     // states expanded by the search
+};
+// workgroups of mode m (0 for all processors)
+int model_mode_wg(int m);
+// cost of level l in mode m (infinite where not allowed); max_wg: largest
+// stage that fits on the device; lcap: highest level one workgroup (or a
+// stage) can address
+double model_level_cost(const ModelLevel *lv, int L, int l, int m, int nu1, int nu2, int word,
+                        const ModelParams &p, int max_wg, int lcap);
+ModelPath model_search(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word, const ModelParams &p,
+                       int max_wg, int lcap);
+// every path enumerated (the cost A* avoids), for checking the search
+ModelPath model_search_exhaustive(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word,
+                                  const ModelParams &p, int max_wg, int lcap);
+// model time of one cycle with the given stages above collapse level lstar
+double model_path_us(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int word, const ModelParams &p,
+                     int lstar, int nstage, const int *wg, const int *hi);
 
 // the two parts of the model for one level (exposed for reporting)
 double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, int word,

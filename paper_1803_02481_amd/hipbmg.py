@@ -25,7 +25,7 @@ class Params(ctypes.Structure):
                 ("collapse_level", ctypes.c_int), ("residual_correction", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_max_cycles", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("cluster_wg", ctypes.c_int), ("cluster_top", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -34,7 +34,10 @@ class Info(ctypes.Structure):
                 ("model_us", ctypes.c_double * MAX_LEVELS), ("setup_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("relres_hist", ctypes.c_double * MAX_HIST),
                 ("rb_down", ctypes.c_int * MAX_LEVELS), ("rb_up", ctypes.c_int * MAX_LEVELS),
-                ("rb_pipelined", ctypes.c_int)]
+                ("rb_pipelined", ctypes.c_int), ("cluster_stages", ctypes.c_int),
+                ("cluster_wg", ctypes.c_int * 4), ("cluster_hi", ctypes.c_int * 4),
+                ("search_us", ctypes.c_double), ("search_expanded", ctypes.c_int),
+                ("path_us", ctypes.c_double)]
 
     def history(self):
         n = self.outer_steps if self.outer_steps else self.cycles
@@ -288,7 +291,7 @@ class BatchHierarchy:
 def calibrate():
     """Measure the performance-model parameters on the current device; later
     hierarchies choose their collapse level with them."""
-    out = (ctypes.c_double * 32)()
+    out = (ctypes.c_double * 64)()
     _check(lib().hipbmg_calibrate(_stream(), out))
     return {k: out[i] for i, k in enumerate(CALIBRATION_KEYS)}
 
@@ -300,7 +303,9 @@ CALIBRATION_KEYS = ("alpha_launch_us", "hbm_GBps", "cache_GBps",
                     "alpha_bar_us_fp32_lds", "alpha_bar_us_fp32_global",
                     "wg_GBps_fp64_lds", "wg_GBps_fp64_global", "wg_GBps_fp32_lds", "wg_GBps_fp32_global",
                     "bare_barrier_lds_us", "bare_barrier_l2_us", "bare_wg_l2_GBps", "plain_sweep_step_us",
-                    "t0_dn_us_fp64", "t0_up_us_fp64", "t0_dn_us_fp32", "t0_up_us_fp32")
+                    "t0_dn_us_fp64", "t0_up_us_fp64", "t0_dn_us_fp32", "t0_up_us_fp32") + tuple(
+    "%s_%dwg_%s" % (what, 2 << k, prec) for prec in ("fp64", "fp32") for what in ("alpha_stage_us", "stage_GBps")
+    for k in range(8))
 
 
 def fv5_from_cells(cell, is_log=False):
