@@ -65,6 +65,28 @@ def time_solves(hier, b, steps, warmup, torch):
     return el, u, info
 
 
+def per_cycle(HB, torch, coeffs, b, reps=3, **prm):
+    """Seconds per V-cycle of a configuration: a 12-cycle solve minus a
+    6-cycle solve (what every solve pays once drops out), median of `reps`
+    such differences; and the model's time for the configuration (us)."""
+    hs = {kc: HB.Hierarchy(coeffs, max_cycles=kc, **prm) for kc in (6, 12)}
+    for h in hs.values():
+        h.solve(b, tol=1e-30, check=False)
+    diffs, model = [], 0.0
+    for _ in range(reps):
+        tk = {}
+        for kc, h in hs.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = h.solve(b, tol=1e-30, check=False)
+            torch.cuda.synchronize()
+            tk[kc] = time.perf_counter() - t0
+            model = info.path_us
+        diffs.append((tk[12] - tk[6]) / 6.0)
+    del hs
+    return sorted(diffs)[len(diffs) // 2], model
+
+
 def oracle_workloads(args, n, extra, O, np, inputs):
     """The single-threaded FP64 oracle timed on bounded samples of the other
     workloads (the oracle has no FP32 path: every entry is its FP64 solve)."""
@@ -228,21 +250,26 @@ def main():
             # per cycle from a 12-cycle and a 6-cycle solve: the difference
             # leaves out what every solve pays once (first pre-relaxations,
             # ||b||, copies)
-            tk = {}
-            for kc in (6, 12):
-                hs = HB.Hierarchy(coeffs, collapse_level=ls, max_cycles=kc)
-                hs.solve(b, tol=1e-30, check=False)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                hs.solve(b, tol=1e-30, check=False)
-                torch.cuda.synchronize()
-                tk[kc] = time.perf_counter() - t0
-                del hs
-            per = (tk[12] - tk[6]) / 6.0
+            per, _ = per_cycle(HB, torch, coeffs, b, collapse_level=ls)
             sweep.append({"collapse_level": ls, "measured_us_per_cycle": 1e6 * per,
                           "model_us_per_cycle": model[ls]})
             log("bench: l*=%d measured %.1f us/cycle, model %.1f" % (ls, 1e6 * per, model[ls]))
         extra["collapse_sweep"] = sweep
+        # forced agglomeration stages above the model's l*: one stage of K
+        # workgroups on the next one or two levels, measured against the
+        # model's time for that configuration (the search's alternatives)
+        ssweep = []
+        ls0 = info.collapse_level
+        for top in (ls0 + 1, ls0 + 2):
+            if top > info.levels - 2:
+                continue
+            for wg in (2, 16, 256):
+                per, pus = per_cycle(HB, torch, coeffs, b, collapse_level=ls0, cluster_wg=wg, cluster_top=top)
+                ssweep.append({"collapse_level": ls0, "stage_workgroups": wg, "stage_top": top,
+                               "measured_us_per_cycle": 1e6 * per, "model_us_per_cycle": pus})
+                log("bench: stage of %d workgroups on levels %d..%d above l*=%d: measured %.1f us/cycle, model %.1f"
+                    % (wg, top, ls0 + 1, ls0, 1e6 * per, pus))
+        extra["stage_sweep"] = ssweep
         best = min(sweep, key=lambda r: r["measured_us_per_cycle"])
         chosen = [r for r in sweep if r["collapse_level"] == info.collapse_level]
         if chosen:
@@ -410,6 +437,10 @@ def main():
                      "avg_launch_us": kavg_s * 1e6},
         "kernels_fp64_finest": kernels,
         "model_calibration": calib,
+        "redistribution_search": {"collapse_level": info.collapse_level, "stages": info.cluster_stages,
+                                  "stage_workgroups": list(info.cluster_wg)[: info.cluster_stages],
+                                  "stage_top_levels": list(info.cluster_hi)[: info.cluster_stages],
+                                  "model_us_per_cycle": info.search_us, "states_expanded": info.search_expanded},
         "cpu_baseline": cpu,
     }
     out.update(extra)

@@ -120,7 +120,10 @@ void hipbmg_default_params(hipbmg_params *p);
  * above).  On the GPU: operator-induced interpolation weights and the Galerkin
  * product for every level (section 2), the Cholesky factor of the coarsest
  * operator (section 3, coarse-solve cost), and the collapse level l* from the
- * performance model (sections 3 and 4) unless params->collapse_level >= 0.
+ * performance model (sections 3 and 4) unless params->collapse_level >= 0.  With
+ * cluster_wg = -1 (the default) and collapse_level = -1, l* and any
+ * agglomeration stages above it come from the model's A* search over
+ * (level, workgroups) states (section 4); info reports the path.
  * coeffs is copied and may be freed after return.  params may be NULL for the
  * defaults.  Returns HIPBMG_ENOTSPD if the coarsest factorisation fails. */
 hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coeffs,
