@@ -116,6 +116,22 @@ def oracle_workloads(args, n, extra, O, np, inputs):
                                       "sample": "%d FP64 cycles (%.2f s/cycle), scaled by the %d cycles of the "
                                                 "GPU FP64 solve" % (k, tc, cb["cycles"])}
         del oh
+    # the paper's workload: a few cycles at full size, scaled to its 10
+    if "paper_workload" in extra:
+        px, py = 16385, 1025
+        Dxp, Dyp = inputs.cells_compensating(px, py)
+        hx, hy = inputs.spacings(px, py)
+        oh = O.Hierarchy(O.fv5_aniso(Dxp, Dyp, hx, hy))
+        bp = inputs.load_uniform(px, py, seed=12)
+        up = np.zeros_like(bp)
+        k = max(1, args.cpu_cycles // 2)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            up = oh.vcycle(bp, up)
+        tc = (time.perf_counter() - t0) / k
+        res["paper_workload"] = {"value": 1e3 * 10 * tc, "unit": "ms per 10 cycles", "cores": 1,
+                                 "sample": "%d FP64 cycles (%.2f s/cycle), scaled to 10" % (k, tc)}
+        del oh
     # batched: the first 8 problems solved whole, scaled to the batch by vertex count
     if "batched" in extra:
         sizes = inputs.batch_sizes(args.batch, seed=5)
@@ -164,6 +180,7 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles timed for the baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--collapse-level", type=int, default=-1)
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batched adjoint workload")
@@ -307,6 +324,39 @@ def main():
                                                   / res["fp64_u"].abs().max())
         del res["mixed_u"], res["fp64_u"]
         extra["checkerboard"] = res
+
+    if not args.no_paper:
+        # the paper's own workload (section 5): the unit square on a stretched
+        # 16385 x 1025 vertex grid (16:1, a 2:1 processor grid of 8:1 local
+        # problems, as one GPU's share), D = diag(1/r, r) with r = hy/hx = 16,
+        # f ~ U[-1,1], and a fixed 10 V(2,1)-cycles from zero, as its runs time
+        px, py = 16385, 1025
+        log("bench: paper workload %dx%d, 10 V(2,1)-cycles" % (px, py))
+        Dxp, Dyp = inputs.cells_compensating(px, py)
+        hx, hy = inputs.spacings(px, py)
+        cp = HB.fv5_aniso(torch.from_numpy(Dxp).to(dev), torch.from_numpy(Dyp).to(dev), hx, hy)
+        bp = torch.from_numpy(inputs.load_uniform(px, py, seed=12)).to(dev)
+        hp = HB.Hierarchy(cp, max_cycles=10)
+        up, ip = hp.solve(bp, tol=1e-30, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            up, ip = hp.solve(bp, tol=1e-30, check=False)
+        torch.cuda.synchronize()
+        el_p = (time.perf_counter() - t0) / args.steps
+        hist = ip.history()
+        extra["paper_workload"] = {
+            "workload": "%dx%d vertices on the unit square (hx/hy = 1/16), D = diag(1/16, 16) per cell, f ~ "
+                        "U[-1,1] (seed 12), 10 V(2,1)-cycles from zero, FP64" % (px, py),
+            "ms_per_10_cycles": 1e3 * el_p,
+            "us_per_cycle": 1e6 * el_p / 10,
+            "relres_after_10": hist[-1],
+            "rate_per_cycle": (hist[-1] / hist[0]) ** (1.0 / 9),
+            "levels": ip.levels, "collapse_level": ip.collapse_level, "stages": ip.cluster_stages,
+        }
+        log("bench: paper workload %.2f ms per 10 cycles, relres %.2e, rate %.3f"
+            % (1e3 * el_p, hist[-1], extra["paper_workload"]["rate_per_cycle"]))
+        del hp, cp, bp, up
 
     if not args.no_batch:
         # many independent problems of different sizes in one batched solve:

@@ -210,6 +210,16 @@ hipbmg_status hipbmg_destroy_batched(hipbmg_batch_handle h);
 hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cell, int is_log,
                                     double *coeffs_out, void *stream);
 
+/* The same stencil for a diagonal diffusion tensor D = diag(Dx, Dy) per cell
+ * on a grid of spacings hx, hy (section 5: the stretched grids with
+ * compensating anisotropy D = diag(1/r, r)).  The dual face of an x-edge has
+ * length hy across a distance hx and takes (hy/hx) times the mean Dx of the two
+ * cells it cuts; a y-edge takes (hx/hy) times the mean Dy.  dx_cell, dy_cell:
+ * [ny-1][nx-1] device arrays; coeffs_out: [3][ny][nx] planes {C, W, S}.
+ * EINVAL for null pointers, nx or ny < 3, or a spacing that is not positive. */
+hipbmg_status hipbmg_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx,
+                               double hy, double *coeffs_out, void *stream);
+
 /* Gradient of a scalar loss with respect to theta = ln D per cell, given the
  * solution u and the adjoint lam = A^{-1} dL/du:
  *   g_c = -(D_c/2) * sum over the four edges (p,q) of cell c of

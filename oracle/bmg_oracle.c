@@ -108,6 +108,41 @@ void oracle_fv5(int nx, int ny, const double *cellD, double *C, double *W, doubl
         }
 }
 
+/* Section 5, the paper's own workload: a diagonal diffusion tensor
+ * D = diag(Dx, Dy) per cell on a grid of spacings hx, hy.  The flux through
+ * the dual face of an x-edge is the integral of Dx du/dx over the face: the
+ * face has length hy, half of it in each of the two cells it cuts, and
+ * du/dx = (u_q - u_p) / hx, so the connection is
+ *   (hy/2 * Dx(cell below) + hy/2 * Dx(cell above)) / hx;
+ * a y-edge likewise with Dy, hx and hy exchanged.  C is the sum of the four
+ * connections of the vertex. */
+void oracle_fv5_aniso(int nx, int ny, const double *Dx, const double *Dy, double hx, double hy, double *C,
+                      double *W, double *S)
+{
+    size_t n = (size_t)nx * ny;
+    memset(C, 0, n * sizeof(double));
+    memset(W, 0, n * sizeof(double));
+    memset(S, 0, n * sizeof(double));
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            /* x-edge (i-1,j)-(i,j): face x = x_{i-1/2}, cells (i-1,j-1) and (i-1,j) */
+            if (i >= 1 && j >= 1 && j <= ny - 2) {
+                double flux = 0.5 * hy * cellv(Dx, nx, ny, i - 1, j - 1) + 0.5 * hy * cellv(Dx, nx, ny, i - 1, j);
+                W[(size_t)j * nx + i] = flux / hx;
+            }
+            /* y-edge (i,j-1)-(i,j): face y = y_{j-1/2}, cells (i-1,j-1) and (i,j-1) */
+            if (j >= 1 && i >= 1 && i <= nx - 2) {
+                double flux = 0.5 * hx * cellv(Dy, nx, ny, i - 1, j - 1) + 0.5 * hx * cellv(Dy, nx, ny, i, j - 1);
+                S[(size_t)j * nx + i] = flux / hy;
+            }
+        }
+    for (int j = 1; j <= ny - 2; ++j)
+        for (int i = 1; i <= nx - 2; ++i) {
+            size_t p = (size_t)j * nx + i;
+            C[p] = W[p] + W[p + 1] + S[p] + S[p + nx];
+        }
+}
+
 /* ---------------------------------------------------------------------------
  * Hierarchy construction.
  * ------------------------------------------------------------------------- */

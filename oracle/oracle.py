@@ -57,6 +57,8 @@ def lib():
         L.oracle_vcycle.argtypes = [ctypes.c_void_p, _D, _D]
         L.oracle_fv5.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.oracle_grad_logD.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+        L.oracle_fv5_aniso.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
+                                       _D, _D, _D]
     return _lib
 
 
@@ -71,6 +73,17 @@ def fv5(cellD):
     ny, nx = cellD.shape[0] + 1, cellD.shape[1] + 1
     out = np.zeros((3, ny, nx))
     lib().oracle_fv5(nx, ny, _p(cellD), _p(out[0]), _p(out[1]), _p(out[2]))
+    return out
+
+
+def fv5_aniso(Dx, Dy, hx, hy):
+    """5-point finite-volume planes (C, W, S) for D = diag(Dx, Dy) per cell
+    [(ny-1),(nx-1)] on a grid of spacings hx, hy (section 5)."""
+    Dx = np.ascontiguousarray(Dx, dtype=np.float64)
+    Dy = np.ascontiguousarray(Dy, dtype=np.float64)
+    ny, nx = Dx.shape[0] + 1, Dx.shape[1] + 1
+    out = np.zeros((3, ny, nx))
+    lib().oracle_fv5_aniso(nx, ny, _p(Dx), _p(Dy), float(hx), float(hy), _p(out[0]), _p(out[1]), _p(out[2]))
     return out
 
 

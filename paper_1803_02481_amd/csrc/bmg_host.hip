@@ -1361,6 +1361,20 @@ extern "C" hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cel
     return HIPBMG_OK;
 }
 
+extern "C" hipbmg_status hipbmg_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx,
+                                          double hy, double *coeffs_out, void *stream)
+{
+    if (!dx_cell || !dy_cell || !coeffs_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
+    if (!(hx > 0.0) || !(hy > 0.0) || !std::isfinite(hx) || !std::isfinite(hy))
+        return fail(HIPBMG_EINVAL, "spacings must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)nx * ny;
+    HIPCHK(launch_fv5_aniso(nx, ny, dx_cell, dy_cell, hx, hy, coeffs_out, coeffs_out + n, coeffs_out + 2 * n, nx,
+                            s));
+    return HIPBMG_OK;
+}
+
 extern "C" hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double *u,
                                           const double *lam, double *grad_out, void *stream)
 {

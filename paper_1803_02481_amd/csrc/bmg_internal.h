@@ -93,6 +93,8 @@ hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args
 // Setup kernels.
 hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,
                       double *S, int pitch, hipStream_t s);
+hipError_t launch_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx, double hy,
+                            double *C, double *W, double *S, int pitch, hipStream_t s);
 hipError_t launch_grad_logD(int nx, int ny, const double *theta, const double *u,
                             const double *lam, double *g, hipStream_t s);
 hipError_t launch_interp_weights(const LevelDev<double> &f, int cnx, int cny, double *wt,

@@ -19,9 +19,14 @@ __device__ __forceinline__ double cell_at(const double *cell, int nx, int ny, in
     return is_log ? exp(v) : v;
 }
 
-__global__ void k_fv5(int nx, int ny, const double *__restrict__ cell, int is_log,
-                      double *__restrict__ C, double *__restrict__ W, double *__restrict__ S,
-                      int pitch)
+// Diagonal tensor D = diag(Dx, Dy) per cell on a grid of spacings hx, hy
+// (section 5, the stretched grids with compensating anisotropy): the dual face
+// of an x-edge has length hy across a distance hx, so it takes sx = hy/hx times
+// the mean Dx of the two cells it cuts; a y-edge takes sy = hx/hy times the
+// mean Dy.  The isotropic form passes the same cells twice and sx = sy = 1.
+__global__ void k_fv5(int nx, int ny, const double *__restrict__ cx, const double *__restrict__ cy, int is_log,
+                      double sx, double sy, double *__restrict__ C, double *__restrict__ W,
+                      double *__restrict__ S, int pitch)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
@@ -30,16 +35,16 @@ __global__ void k_fv5(int nx, int ny, const double *__restrict__ cell, int is_lo
     // W(i,j): edge (i-1,j)-(i,j), cells (i-1,j-1) and (i-1,j)
     double w = 0.0, s = 0.0;
     if (i >= 1 && j >= 1 && j <= ny - 2)
-        w = 0.5 * (cell_at(cell, nx, ny, i - 1, j - 1, is_log) + cell_at(cell, nx, ny, i - 1, j, is_log));
+        w = sx * (0.5 * (cell_at(cx, nx, ny, i - 1, j - 1, is_log) + cell_at(cx, nx, ny, i - 1, j, is_log)));
     // S(i,j): edge (i,j-1)-(i,j), cells (i-1,j-1) and (i,j-1)
     if (j >= 1 && i >= 1 && i <= nx - 2)
-        s = 0.5 * (cell_at(cell, nx, ny, i - 1, j - 1, is_log) + cell_at(cell, nx, ny, i, j - 1, is_log));
+        s = sy * (0.5 * (cell_at(cy, nx, ny, i - 1, j - 1, is_log) + cell_at(cy, nx, ny, i, j - 1, is_log)));
     W[p] = w;
     S[p] = s;
     double c = 0.0;
     if (i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2) {
-        double we = 0.5 * (cell_at(cell, nx, ny, i, j - 1, is_log) + cell_at(cell, nx, ny, i, j, is_log));
-        double sn = 0.5 * (cell_at(cell, nx, ny, i - 1, j, is_log) + cell_at(cell, nx, ny, i, j, is_log));
+        double we = sx * (0.5 * (cell_at(cx, nx, ny, i, j - 1, is_log) + cell_at(cx, nx, ny, i, j, is_log)));
+        double sn = sy * (0.5 * (cell_at(cy, nx, ny, i - 1, j, is_log) + cell_at(cy, nx, ny, i, j, is_log)));
         c = w + we + s + sn;
     }
     C[p] = c;
@@ -49,7 +54,15 @@ hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C,
                       double *S, int pitch, hipStream_t s)
 {
     dim3 b(256), g((nx + 255) / 256, ny);
-    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, cell, is_log, C, W, S, pitch);
+    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, cell, cell, is_log, 1.0, 1.0, C, W, S, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx, double hy,
+                            double *C, double *W, double *S, int pitch, hipStream_t s)
+{
+    dim3 b(256), g((nx + 255) / 256, ny);
+    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, dx_cell, dy_cell, 0, hy / hx, hx / hy, C, W, S, pitch);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ _SIGS = {
     "hipbmg_op_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _I, _VP, _VP, _VP]),
     "hipbmg_op_interp_smooth": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(ctypes.c_double), _VP]),
     "hipbmg_fv5_from_cells": (_I, [_I, _I, _VP, _I, _VP, _VP]),
+    "hipbmg_fv5_aniso": (_I, [_I, _I, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
     "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
     "hipbmg_profile": (_I, [_VP, _I]),
     "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
@@ -313,6 +314,18 @@ def fv5_from_cells(cell, is_log=False):
     ny, nx = cell.shape[0] + 1, cell.shape[1] + 1
     out = torch.empty((3, ny, nx), dtype=torch.float64, device=cell.device)
     _check(lib().hipbmg_fv5_from_cells(nx, ny, _ptr(cell), 1 if is_log else 0, _ptr(out), _stream()))
+    return out
+
+
+def fv5_aniso(dx_cell, dy_cell, hx, hy):
+    """5-point finite-volume planes {C, W, S} for D = diag(Dx, Dy) per cell on a
+    grid of spacings hx, hy (the stretched grids of section 5)."""
+    ny, nx = dx_cell.shape[0] + 1, dx_cell.shape[1] + 1
+    if tuple(dy_cell.shape) != tuple(dx_cell.shape):
+        raise ValueError("dx_cell and dy_cell must have the same shape")
+    out = torch.empty((3, ny, nx), dtype=torch.float64, device=dx_cell.device)
+    _check(lib().hipbmg_fv5_aniso(nx, ny, _ptr(dx_cell), _ptr(dy_cell), float(hx), float(hy), _ptr(out),
+                                  _stream()))
     return out
 
 

@@ -35,6 +35,21 @@ def cells_two_phase_blocks(nx, ny, block=64, values=(1.0, 1e-3), seed=3):
     return np.ascontiguousarray(D[: ny - 1, : nx - 1])
 
 
+def cells_compensating(nx, ny, r=None):
+    """The paper's workload tensor D = diag(1/r, r) per cell (section 5), as
+    (Dx, Dy).  r defaults to the cell aspect ratio hy/hx of the unit square
+    with nx x ny vertices, which makes the discrete operator isotropic."""
+    if r is None:
+        r = (nx - 1) / (ny - 1)
+    shape = (ny - 1, nx - 1)
+    return np.full(shape, 1.0 / r), np.full(shape, float(r))
+
+
+def spacings(nx, ny):
+    """Grid spacings (hx, hy) of the unit square with nx x ny vertices."""
+    return 1.0 / (nx - 1), 1.0 / (ny - 1)
+
+
 def cells_lognormal(nx, ny, sigma=1.0, seed=1000):
     """Per-cell i.i.d. D = exp(sigma * Z), Z ~ N(0, 1)."""
     rng = np.random.default_rng(seed)

@@ -438,3 +438,65 @@ def test_coarsening_stops_at_an_even_side():
     P = H.interp_matrix(hier.interp(1), hier.size(0))
     Ac_ref = (P.T @ Af @ P).toarray()
     assert np.abs(H.matrix_from_stencil(hier.stencil(0)).toarray() - Ac_ref).max() <= 1e-14 * np.abs(Ac_ref).max()
+
+
+# --------------------------------------------------------------------------
+# Section 5, the paper's own workload: stretched grids with compensating
+# anisotropy D = diag(1/r, r)
+# --------------------------------------------------------------------------
+def test_fv5_aniso_reduces_to_the_isotropic_stencil():
+    D = inputs.cells_lognormal(33, 17, 1.0, seed=3)
+    a, b = O.fv5_aniso(D, D, 0.1, 0.1), O.fv5(D)
+    # the same sums, grouped differently: a few ulps
+    assert np.abs(a - b).max() <= 8 * np.finfo(float).eps * np.abs(b).max()
+
+
+@pytest.mark.parametrize("nx,ny", [(129, 9), (257, 17), (65, 5)])
+def test_fv5_compensating_anisotropy_gives_the_isotropic_laplacian(nx, ny):
+    # x-faces: hy * (1/r) / hx = 1 and y-faces: hx * r / hy = 1 with r = hy/hx
+    Dx, Dy = inputs.cells_compensating(nx, ny)
+    hx, hy = inputs.spacings(nx, ny)
+    C, W, S = O.fv5_aniso(Dx, Dy, hx, hy)
+    assert np.all(W[1:-1, 1:] == 1.0) and np.all(S[1:, 1:-1] == 1.0)
+    assert np.all(C[1:-1, 1:-1] == 4.0)
+    assert np.all(C[0] == 0) and np.all(C[:, 0] == 0) and np.all(W[0] == 0) and np.all(S[:, 0] == 0)
+
+
+def anisotropic_error(nx, ny, dx, dy):
+    """max error at the vertices of the discrete solution of
+    -div(diag(dx, dy) grad u) = f, u = sin(pi x) sin(pi y) on the unit square"""
+    hx, hy = inputs.spacings(nx, ny)
+    Dx, Dy = np.full((ny - 1, nx - 1), dx), np.full((ny - 1, nx - 1), dy)
+    planes = O.fv5_aniso(Dx, Dy, hx, hy)
+    x, y = np.meshgrid(np.linspace(0, 1, nx), np.linspace(0, 1, ny))
+    u = np.sin(np.pi * x) * np.sin(np.pi * y)
+    f = (dx + dy) * np.pi ** 2 * u
+    A = H.matrix_from_planes(planes)
+    uh = spla.spsolve(A.tocsc(), H.to_interior(hx * hy * f))
+    return np.abs(uh - H.to_interior(u)).max()
+
+
+def test_fv5_aniso_is_second_order_on_stretched_grids():
+    e1 = anisotropic_error(65, 17, 0.25, 4.0)
+    e2 = anisotropic_error(129, 33, 0.25, 4.0)
+    assert 3.6 <= e1 / e2 <= 4.4, (e1, e2)
+
+
+def test_paper_workload_converges_like_the_isotropic_problem():
+    # compensating anisotropy keeps pointwise four-colour smoothing optimal;
+    # the same stretched grid with isotropic D is a strongly anisotropic
+    # discrete problem on which pointwise smoothing deteriorates (section 5)
+    rates = {}
+    for name, comp in (("compensating", True), ("isotropic", False)):
+        nx, ny = 257, 17
+        hx, hy = inputs.spacings(nx, ny)
+        if comp:
+            Dx, Dy = inputs.cells_compensating(nx, ny)
+        else:
+            Dx = Dy = np.ones((ny - 1, nx - 1))
+        hier = O.Hierarchy(O.fv5_aniso(Dx, Dy, hx, hy))
+        _, hist = hier.solve(inputs.load_uniform(nx, ny, seed=0), tol=1e-10, max_cycles=60)
+        rates[name] = (hist[-1] / hist[0]) ** (1.0 / max(1, len(hist) - 1))
+    print(rates)
+    assert rates["compensating"] <= 0.05, rates
+    assert rates["isotropic"] >= 0.5, rates
