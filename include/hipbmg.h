@@ -241,7 +241,8 @@ hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double
  * 8 the same from zero, 9 interpolate + relax + norm followed by the next
  * cycle's two relaxations + residual + restriction in one pass, 10 its
  * interpolate + relax stage alone, which rebuilds the stopping cycle's
- * iterate), the summed
+ * iterate, 11 and 12 kernels 7 and 8 without storing r/C, 13 interpolate
+ * with r/C formed from the loaded rows + relax), the summed
  * duration, the number of launches and the
  * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
 hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);

@@ -102,6 +102,7 @@ struct hipbmg_hier {
     double setup_ms = 0.0;
     std::vector<int> rb;        // row-block steps per level, pre-relaxation (down) kernels
     std::vector<int> rb_up;     // row-block steps per level, interpolation (up) kernels
+    std::vector<char> rc_level; // level forms r/C in its up leg (no q plane)
     int no_lds = 0;             // HIPBMG_NO_LDS=1: keep collapsed levels in global memory
     int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
     int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
@@ -325,11 +326,24 @@ static int pick_rb(int nx, int ny, int npt)
 // that product wins; ties go to the longer block (fewer re-read prologue rows).
 // the kernel that dominates a level's down leg (its last pre-relaxation, fused
 // with residual and restriction) and its up leg (the interpolating relaxation)
-static int variant_down(const hipbmg_params &prm, bool fine)
+static int variant_down(const hipbmg_params &prm, bool fine, bool rc = false)
 {
+    if (rc) return SV_SWEEP2_R_ZX;
     return prm.nu1 >= 2 ? (fine ? SV_SWEEP2_RQ : SV_SWEEP2_RQ_ZX) : (fine ? SV_SWEEP_RQ : SV_SWEEP_RQ_ZX);
 }
-static int variant_up(bool fine) { return fine ? SV_INTERP_NORM : SV_INTERP; }
+static int variant_up(bool fine, bool rc = false) { return fine ? SV_INTERP_NORM : (rc ? SV_INTERP_RC : SV_INTERP); }
+
+// Levels whose up leg forms r/C from the rows it loads instead of reading the
+// q plane the down leg would store (16 bytes per vertex less): coarse levels
+// of at least HIPBMG_RC_MIN vertices (default 2^20, where the two legs are
+// bandwidth-bound rather than latency-bound), with the two pre-relaxations
+// fused into one pass.
+static bool rc_on_the_fly(const hipbmg_hier *h, int nx, int ny, bool fine)
+{
+    long long lim = 1LL << 20;
+    if (const char *e = std::getenv("HIPBMG_RC_MIN")) lim = std::atoll(e);
+    return !fine && h->prm.nu1 == 2 && !h->no_fuse2 && (long long)nx * ny >= lim;
+}
 
 // The model's view of level l: launch geometry of its down and up kernels and
 // whether it is staged in LDS when collapsed (levels fill the LDS budget from
@@ -371,8 +385,10 @@ static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
         };
         ml[l].dn_cold = all_fit ? 0 : 1;
         ml[l].up_cold = below[l + 1] < cache ? 0 : 1;
-        describe(variant_down(h->prm, fine), h->rb[l], ml[l].dn);
-        describe(variant_up(fine), h->rb_up[l], ml[l].up);
+        const bool rc = h->rc_level[l] != 0;
+        ml[l].rc = rc ? 1 : 0;
+        describe(variant_down(h->prm, fine, rc), h->rb[l], ml[l].dn);
+        describe(variant_up(fine, rc), h->rb_up[l], ml[l].up);
         ml[l].pipelined = fine && h->fused3 ? 1 : 0;
         if (ml[l].pipelined) describe(SV_FUSED3, h->rb3, ml[l].pipe);
         else ml[l].pipe = ModelKernel{0, 0, 1.0};
@@ -529,6 +545,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     // takes the longest of 64, 32, ... 4 that still gives 1024 tiles.
     h->rb.resize(L);
     h->rb_up.resize(L);
+    h->rc_level.assign(L, 0);
     size_t np = 4096;
     {
         bool fixed = false;
@@ -537,7 +554,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         for (int l = 0; l < L; ++l) {
             const int lnpt = h->lv[l].npt;
             const bool fine = l == L - 1;
-            const int vdn = variant_down(prm, fine), vup = variant_up(fine);
+            h->rc_level[l] = rc_on_the_fly(h, sx[l], sy[l], fine) ? 1 : 0;
+            const int vdn = variant_down(prm, fine, h->rc_level[l]), vup = variant_up(fine, h->rc_level[l]);
             const int rdn = fixed ? 0 : stream_resident(lnpt, vdn, fp32);
             const int rup = fixed ? 0 : stream_resident(lnpt, vup, fp32);
             h->rb[l] = rdn > 0 ? pick_rb_rounds(sx[l], sy[l], lnpt, vdn, rdn, 256) : pick_rb(sx[l], sy[l], lnpt);
@@ -841,7 +859,9 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         for (int k = 1; k <= nk; ++k) {
             const bool last = k == nk, zx = zero && k == 1;
             const bool two = last && nk < nu1;
-            const int v = last ? (two ? (zx ? SV_SWEEP2_RQ_ZX : SV_SWEEP2_RQ)
+            const bool rcl = h->rc_level[l] && two;
+            const int v = last ? (two ? (zx ? (rcl ? SV_SWEEP2_R_ZX : SV_SWEEP2_RQ_ZX)
+                                            : (rcl ? SV_SWEEP2_R : SV_SWEEP2_RQ))
                                       : (zx ? SV_SWEEP_RQ_ZX : SV_SWEEP_RQ))
                                : (zx ? SV_SWEEP_ZX : SV_SWEEP);
             StreamArgs<T> a = base_args(A, h->rb[l]);
@@ -893,7 +913,8 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
         int xb = xb_after[l];
         for (int k = 1; k <= nu2; ++k) {
             const bool first = k == 1, last = k == nu2;
-            int v = first ? (fine && last ? SV_INTERP_NORM : SV_INTERP)
+            // a level whose down leg stored no q forms r/C in its first up pass
+            int v = first ? (fine && last ? SV_INTERP_NORM : (h->rc_level[l] ? SV_INTERP_RC : SV_INTERP))
                           : (fine && last ? SV_SWEEP_NORM : SV_SWEEP);
             StreamArgs<T> a = base_args(A, h->rb_up[l]);
             a.x_in = A.x[xb];
@@ -1434,7 +1455,9 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         // relaxation's x write is the next cycle's iterate; the post-relaxed
         // iterate and r/C are not stored, r/C is formed from the loaded rows)
         if (variant == SV_FUSED3) per += 0.25 * w + 2.0 * w + 0.25 * w;
-        if (variant == SV_FUSED3_P) per += 0.25 * w + 2.0 * w;
+        if (variant == SV_FUSED3_P || variant == SV_INTERP_RC) per += 0.25 * w + 2.0 * w;
+        if (variant == SV_SWEEP2_R_ZX) per -= w;
+        if (variant == SV_SWEEP2_R || variant == SV_SWEEP2_R_ZX) per += 2.0 * w + 0.25 * w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;

@@ -69,7 +69,10 @@ enum StreamVariant {
                          // iterate) + relax (norm), then two relaxations (-> x_out2),
                          // residual, restriction -> bc
     SV_FUSED3_P = 10,    // the interpolate + relax stage of SV_FUSED3 alone (-> x_out)
-    SV_COUNT = 11
+    SV_SWEEP2_R = 11,    // SV_SWEEP2_RQ without storing q (the up leg forms r/C itself)
+    SV_SWEEP2_R_ZX = 12, // the same from x = 0
+    SV_INTERP_RC = 13,   // interpolate-and-correct with r/C formed from the loaded rows, relaxation
+    SV_COUNT = 14
 };
 
 // Owned column pairs per strip for a variant (64 lanes minus halo lanes).

@@ -29,6 +29,8 @@ struct ModelLevel {
     // where a leg finds the level's data: 1 in HBM (evicted since its last
     // use), 0 in the last-level cache
     int dn_cold, up_cold;
+    // the up leg forms r/C from the rows it loads (no q plane written or read)
+    int rc;
 };
 
 // Machine parameters.  Paper -> GPU correspondence:

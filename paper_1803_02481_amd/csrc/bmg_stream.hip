@@ -422,7 +422,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<T> &a, const int ti
 // second colour-by-colour sweep.  A's results are correct on fewer lanes than
 // a loaded row, so the halo is the sum of both stages' halos, and each block
 // of rows starts with three A steps and two B steps of prologue.
-template <typename T, int NPT, bool ZX>
+template <typename T, int NPT, bool ZX, bool STOREQ = true>
 __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int HA = 1 + (NPT == 9);          // lanes of A's garbage margin per side
@@ -483,7 +483,7 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
             B.r0 = A.rm2;                           // A-final rows jb, jb+1 as B's old rows
             B.rp1 = A.rm1;
             const int mode = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
-            stage_step<T, NPT, true, true, true, false>(B, jb, mode, L, a);
+            stage_step<T, NPT, true, true, true, false, false, true, STOREQ>(B, jb, mode, L, a);
             stage_rotate(B);
         }
         stage_rotate(A);
@@ -684,13 +684,143 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     stream_tile<T, NPT, V>(a, tile);
 }
 
-template <typename T, int NPT, bool ZX>
+template <typename T, int NPT, bool ZX, bool STOREQ = true>
 __global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile();
     if (tile >= a.ntiles) return;
-    stream2_tile<T, NPT, ZX>(a, tile);
+    stream2_tile<T, NPT, ZX, STOREQ>(a, tile);
+}
+
+// The up leg's first pass with the r/C term formed from the loaded rows
+// instead of read from a stored plane (section 3, interpolation with r/C):
+// the iterate this pass loads is the pre-relaxed one whose residual the down
+// leg restricted, so b - A x of the raw rows is that residual, computed by
+// the same expressions as the down leg's (bitwise the stored values).  Then
+// x += P x_c + r/C and one relaxation.  Rows are loaded two rows ahead of the
+// relaxation, because the r/C of an odd row needs the raw row above it.  The
+// r/C costs one lane of exact columns on each side.
+template <typename T, int NPT>
+__device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int tile)
+{
+    constexpr int HL = 1 + halo_left(NPT, 0), HR = 1 + halo_right(NPT, 0), OWN = 64 - HL - HR;
+    const int strip = tile % a.nstrips;
+    const int blk = tile / a.nstrips;
+    const int lane = threadIdx.x;
+    const int t = strip * OWN + lane - HL;
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = t >= 0 && t < a.cnx;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+
+    auto load_raw = [&](Row<T> &r, int j) {
+        const bool rv = colv && j >= 0 && j < ny;
+        r = Row<T>{};
+        if (rv) {
+            const size_t off = (size_t)j * pitch + e;
+            ld2(a.x_in + off, r.x0, r.x1);
+            ld2(a.b + off, r.b0, r.b1);
+            ld2(a.C + off, r.C0, r.C1);
+            ld2(a.W + off, r.W0, r.W1);
+            ld2(a.S + off, r.S0, r.S1);
+            if (NPT == 9) {
+                ld2(a.SW + off, r.SW0, r.SW1);
+                ld2(a.SE + off, r.SE0, r.SE1);
+            }
+        }
+        const bool rin = j >= 1 && j <= ny - 2;
+        if (cv && rin) {
+            const int jc = j >> 1;
+            const size_t co = (size_t)jc * a.cpitch + t;
+            const T *wt = a.wt;
+            const long long cp = a.cplane;
+            r.ca = a.xc[co];
+            if (j & 1) {
+                r.cu = a.xc[co + a.cpitch];
+                r.w0 = wt[WYB * cp + co];
+                r.w1 = wt[WYT * cp + co];
+                r.w2 = wt[WCSW * cp + co];
+                r.w3 = wt[WCSE * cp + co];
+                r.w4 = wt[WCNW * cp + co];
+                r.w5 = wt[WCNE * cp + co];
+            } else {
+                r.w0 = wt[WXL * cp + co];
+                r.w1 = wt[WXR * cp + co];
+            }
+        }
+    };
+    auto finish_row = [&](Row<T> &r, int j, T q0, T q1) {
+        const bool rin = j >= 1 && j <= ny - 2;
+        if ((j & 1) == 0) {
+            const T xb = fromR(r.ca);
+            if (rin && ie) r.x0 += r.ca;
+            if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + q1;
+        } else {
+            const T xb = fromR(r.ca), xd = fromR(r.cu);
+            if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + q0;
+            if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + q1;
+        }
+    };
+    const bool rc = a.rescorr != 0;
+    auto rc_odd = [&](const Row<T> &bl, const Row<T> &cu, const Row<T> &ab) {
+        T d;
+        const T r = res_odd<T, NPT>(bl, cu, ab, d);
+        return rc ? r / d : T(0);
+    };
+    auto rc_even = [&](const Row<T> &bl, const Row<T> &cu, const Row<T> &ab) {
+        T d;
+        const T r = res_even<T, NPT>(bl, cu, ab, d);
+        return rc ? r / d : T(0);
+    };
+
+    const int nsteps = (ny - 1) / 2;
+    const int s0 = blk * a.rb;
+    const int s1 = min(s0 + a.rb, nsteps);
+    const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+    const int jp0 = jfirst - 2;   // one prologue step
+    Stage<T> P{};
+    Row<T> Rm1, Rn, N1, N2;       // raw rows jp-1, jp; jp+1, jp+2 loaded a step ahead
+    {
+        Row<T> Ra;
+        load_raw(Ra, jp0 - 2);
+        load_raw(Rm1, jp0 - 1);
+        load_raw(Rn, jp0);
+        load_raw(N1, jp0 + 1);
+        load_raw(N2, jp0 + 2);
+        P.rm1 = Rm1;
+        finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
+    }
+    for (int jp = jp0; jp <= jlast; jp += 2) {
+        const Row<T> R1 = N1, R2 = N2;
+        if (jp + 2 <= jlast) {
+            load_raw(N1, jp + 3);
+            load_raw(N2, jp + 4);
+        }
+        const T q1_even_row = rc_odd(Rm1, Rn, R1);
+        const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
+        P.r0 = Rn;
+        P.rp1 = R1;
+        finish_row(P.r0, jp, T(0), q1_even_row);
+        finish_row(P.rp1, jp + 1, q0_odd_row, q1_odd_row);
+        Rm1 = R1;
+        Rn = R2;
+        stage_step<T, NPT, true, false, false, false>(P, jp, jp == jp0 ? 0 : 2, L, a);
+        stage_rotate(P);
+    }
+}
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(64) void k_interp_rc(StreamArgs<T> a)
+{
+    if (a.active && *a.active == 0) return;
+    const int tile = xcd_tile();
+    if (tile >= a.ntiles) return;
+    interp_rc_tile<T, NPT>(a, tile);
 }
 
 // Batched form: one launch covers the same stage of many problems.  map[w] =
@@ -716,7 +846,8 @@ __global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__re
 int stream_owned_pairs(int npt, int variant)
 {
     if (variant == SV_FUSED3 || variant == SV_FUSED3_P) return 54;
-    if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX)
+    if (variant == SV_INTERP_RC) return 64 - (1 + halo_left(npt, 0)) - (1 + halo_right(npt, 0));
+    if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX || variant == SV_SWEEP2_R || variant == SV_SWEEP2_R_ZX)
         return 64 - (1 + (npt == 9)) - halo_left(npt, 1) - (1 + (npt == 9)) - halo_right(npt, 0);
     int res = (variant == SV_SWEEP_RQ || variant == SV_SWEEP_RQ_ZX || variant == SV_INTERP_NORM ||
                variant == SV_SWEEP_NORM);
@@ -750,6 +881,9 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_SWEEP_NORM: hipLaunchKernelGGL((k_stream<T, NPT, SV_SWEEP_NORM>), g, b, 0, s, a); break;
     case SV_SWEEP2_RQ: hipLaunchKernelGGL((k_stream2<T, NPT, false>), g, b, 0, s, a); break;
     case SV_SWEEP2_RQ_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true>), g, b, 0, s, a); break;
+    case SV_SWEEP2_R: hipLaunchKernelGGL((k_stream2<T, NPT, false, false>), g, b, 0, s, a); break;
+    case SV_SWEEP2_R_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true, false>), g, b, 0, s, a); break;
+    case SV_INTERP_RC: hipLaunchKernelGGL((k_interp_rc<T, NPT>), g, b, 0, s, a); break;
     case SV_FUSED3:
         if (NPT != 5) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_stream3<T, false>), g, b, 0, s, a);
@@ -777,6 +911,9 @@ static const void *kernel_of(int variant)
     case SV_SWEEP_NORM: return reinterpret_cast<const void *>(&k_stream<T, NPT, SV_SWEEP_NORM>);
     case SV_SWEEP2_RQ: return reinterpret_cast<const void *>(&k_stream2<T, NPT, false>);
     case SV_SWEEP2_RQ_ZX: return reinterpret_cast<const void *>(&k_stream2<T, NPT, true>);
+    case SV_SWEEP2_R: return reinterpret_cast<const void *>(&k_stream2<T, NPT, false, false>);
+    case SV_SWEEP2_R_ZX: return reinterpret_cast<const void *>(&k_stream2<T, NPT, true, false>);
+    case SV_INTERP_RC: return reinterpret_cast<const void *>(&k_interp_rc<T, NPT>);
     case SV_FUSED3: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, false>) : nullptr;
     case SV_FUSED3_P: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, true>) : nullptr;
     default: return nullptr;
@@ -806,7 +943,9 @@ int stream_steps_per_tile(int variant, int rb)
     case SV_FUSED3: return rb + 6;
     case SV_FUSED3_P: return rb + 1;
     case SV_SWEEP2_RQ:
-    case SV_SWEEP2_RQ_ZX: return rb + 4;
+    case SV_SWEEP2_RQ_ZX:
+    case SV_SWEEP2_R:
+    case SV_SWEEP2_R_ZX: return rb + 4;
     case SV_SWEEP_RQ:
     case SV_SWEEP_RQ_ZX:
     case SV_INTERP_NORM:
