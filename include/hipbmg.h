@@ -242,7 +242,8 @@ hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double
  * cycle's two relaxations + residual + restriction in one pass, 10 its
  * interpolate + relax stage alone, which rebuilds the stopping cycle's
  * iterate, 11 and 12 kernels 7 and 8 without storing r/C, 13 interpolate
- * with r/C formed from the loaded rows + relax), the summed
+ * with r/C formed from the loaded rows + relax, 14 kernel 10 with the norm,
+ * the last cycle of a solve that reaches max_cycles), the summed
  * duration, the number of launches and the
  * algorithmic bytes one launch moves.  Any output pointer may be NULL. */
 hipbmg_status hipbmg_profile(hipbmg_handle h, int enable);

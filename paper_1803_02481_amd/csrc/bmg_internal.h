@@ -72,7 +72,8 @@ enum StreamVariant {
     SV_SWEEP2_R = 11,    // SV_SWEEP2_RQ without storing q (the up leg forms r/C itself)
     SV_SWEEP2_R_ZX = 12, // the same from x = 0
     SV_INTERP_RC = 13,   // interpolate-and-correct with r/C formed from the loaded rows, relaxation
-    SV_COUNT = 14
+    SV_FUSED3_PN = 14,   // SV_FUSED3_P plus the residual norm: a capped solve's last cycle
+    SV_COUNT = 15
 };
 
 // Owned column pairs per strip for a variant (64 lanes minus halo lanes).

@@ -505,7 +505,10 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 // the lanes whose results are exact shrink by one for P's r/C and by one per
 // stage, so 5 halo lanes are needed on each side; a row block starts with
 // four P, three A and two B prologue steps.
-template <typename T, bool PONLY>
+// PONLY && PNORM: stage P alone with its norm and the iterate stored, for a
+// cycle known to be the last (two prologue steps, as the norm's residual
+// reads the row below a block's first final row).
+template <typename T, bool PONLY, bool PNORM = false>
 __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int NPT = 5;
@@ -588,8 +591,8 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     const int s0 = blk * a.rb;
     const int s1 = min(s0 + a.rb, nsteps);
     const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
-    // P alone (the rebuild) needs one prologue step; with A and B, four
-    const int jp0 = PONLY ? jfirst - 2 : jfirst - 8, jpend = PONLY ? jlast : jlast + 4;
+    // P alone (the rebuild) needs one prologue step, two with its norm; with A and B, four
+    const int jp0 = PONLY ? (PNORM ? jfirst - 4 : jfirst - 2) : jfirst - 8, jpend = PONLY ? jlast : jlast + 4;
 
     StreamArgs<T> aB = a;          // stage B stores the next cycle's iterate
     aB.x_out = a.x_out2;
@@ -623,7 +626,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         Rn = R2;
         const int modeP = jp == jp0 ? 0 : (jp >= jfirst && jp <= jlast ? 2 : 1);
         if (PONLY) {
-            stage_step<T, NPT, true, false, false, false>(P, jp, modeP, L, a);
+            stage_step<T, NPT, true, PNORM, false, PNORM>(P, jp, modeP, L, a);
             stage_rotate(P);
             continue;
         }
@@ -651,20 +654,20 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         }
         stage_rotate(P);
     }
-    if (!PONLY) {
+    if (!PONLY || PNORM) {
         double acc = P.acc;
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) a.partials[tile] = acc;
     }
 }
 
-template <typename T, bool PONLY>
+template <typename T, bool PONLY, bool PNORM = false>
 __global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile_fn();
     if (tile >= a.ntiles) return;
-    stream3_tile<T, PONLY>(a, tile);
+    stream3_tile<T, PONLY, PNORM>(a, tile);
 }
 
 // XCD-aware tile order: WG i runs on XCD i mod 8, so consecutive tiles (the
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__re
 
 int stream_owned_pairs(int npt, int variant)
 {
-    if (variant == SV_FUSED3 || variant == SV_FUSED3_P) return 54;
+    if (variant == SV_FUSED3 || variant == SV_FUSED3_P || variant == SV_FUSED3_PN) return 54;
     if (variant == SV_INTERP_RC) return 64 - (1 + halo_left(npt, 0)) - (1 + halo_right(npt, 0));
     if (variant == SV_SWEEP2_RQ || variant == SV_SWEEP2_RQ_ZX || variant == SV_SWEEP2_R || variant == SV_SWEEP2_R_ZX)
         return 64 - (1 + (npt == 9)) - halo_left(npt, 1) - (1 + (npt == 9)) - halo_right(npt, 0);
@@ -892,6 +895,10 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
         if (NPT != 5) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_stream3<T, true>), g, b, 0, s, a);
         break;
+    case SV_FUSED3_PN:
+        if (NPT != 5) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stream3<T, true, true>), g, b, 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -916,6 +923,7 @@ static const void *kernel_of(int variant)
     case SV_INTERP_RC: return reinterpret_cast<const void *>(&k_interp_rc<T, NPT>);
     case SV_FUSED3: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, false>) : nullptr;
     case SV_FUSED3_P: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, true>) : nullptr;
+    case SV_FUSED3_PN: return NPT == 5 ? reinterpret_cast<const void *>(&k_stream3<T, true, true>) : nullptr;
     default: return nullptr;
     }
 }
@@ -942,6 +950,7 @@ int stream_steps_per_tile(int variant, int rb)
     switch (variant) {
     case SV_FUSED3: return rb + 6;
     case SV_FUSED3_P: return rb + 1;
+    case SV_FUSED3_PN: return rb + 2;
     case SV_SWEEP2_RQ:
     case SV_SWEEP2_RQ_ZX:
     case SV_SWEEP2_R:

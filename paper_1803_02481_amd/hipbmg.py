@@ -209,7 +209,8 @@ class Hierarchy:
 
     KERNELS = ("relax", "relax_zero", "relax_restrict", "relax_restrict_zero", "interp_relax",
                "interp_relax_norm", "relax_norm", "relax2_restrict", "relax2_restrict_zero", "fused3",
-               "fused3_rebuild", "relax2_restrict_noq", "relax2_restrict_noq_zero", "interp_rc_relax")
+               "fused3_rebuild", "relax2_restrict_noq", "relax2_restrict_noq_zero", "interp_rc_relax",
+               "fused3_last")
 
     def profile_read(self, precision=0):
         """{kernel name: (total_ms, launches, bytes_per_launch)} for launched kernels."""

@@ -1,0 +1,67 @@
+"""GPU checks of streaming-pass variants that must not change the iteration:
+the up leg forming r/C from the rows it loads instead of reading a stored
+plane, and the last cycle of a capped solve run as the pipelined pass's
+first stage alone.  Each is compared bitwise with the path it replaces."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1803_02481_amd import hipbmg as HB
+from paper_1803_02481_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def run(planes, b, cycles, tol=1e-30, **prm):
+    h = HB.Hierarchy(g(planes), max_cycles=cycles, **prm)
+    u, info = h.solve(g(b), tol=tol, check=False)
+    torch.cuda.synchronize()
+    return u, info
+
+
+@pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny", [(257, 257), (385, 193)])
+def test_up_leg_r_over_c_formed_from_rows_is_bitwise_the_stored_one(nx, ny, precision, monkeypatch):
+    # the up leg's r/C from the loaded pre-relaxed iterate (no q plane) on every
+    # coarse level, against the stored q on every level: the same expressions
+    # on the same values
+    planes = O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=60))
+    b = inputs.load_uniform(nx, ny, seed=61)
+    res = {}
+    for name, lim in (("stored", "1000000000000"), ("formed", "0")):
+        monkeypatch.setenv("HIPBMG_RC_MIN", lim)
+        for rb in ("1", "5"):
+            monkeypatch.setenv("HIPBMG_RB", rb)
+            res[(name, rb)] = run(planes, b, 4, collapse_level=1, precision=precision)
+    for rb in ("1", "5"):
+        assert torch.equal(res[("stored", rb)][0], res[("formed", rb)][0]), rb
+        assert res[("stored", rb)][1].history() == res[("formed", rb)][1].history()
+    assert torch.equal(res[("formed", "1")][0], res[("formed", "5")][0])
+
+
+
+@pytest.mark.parametrize("n", [129, 257])
+def test_last_cycle_pass_is_bitwise_the_rebuild(n, monkeypatch):
+    planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=70))
+    b = inputs.load_uniform(n, n, seed=71)
+    out = {}
+    for name, flag in (("rebuild", "1"), ("last_pass", "0")):
+        monkeypatch.setenv("HIPBMG_NO_LAST_PASS", flag)
+        # mixed: every inner FP32 solve stops at its cycle cap
+        out[(name, "mixed")] = run(planes, b, 500, tol=1e-10, precision=HB.MIXED)
+        # FP64 capped before the tolerance
+        out[(name, "fp64")] = run(planes, b, 5, tol=1e-30)
+    for prec in ("mixed", "fp64"):
+        (u0, i0), (u1, i1) = out[("rebuild", prec)], out[("last_pass", prec)]
+        print("%s: %d cycles, relres %.3e" % (prec, i1.cycles, i1.relres))
+        assert i0.cycles == i1.cycles and i0.outer_steps == i1.outer_steps
+        assert torch.equal(u0, u1), prec
+        assert i0.history() == i1.history(), prec
+        assert i0.relres == i1.relres

@@ -115,22 +115,3 @@ def test_calibration_measures_stage_terms():
         print("%3d workgroups: %.3f us per barrier phase, %.1f GB/s" % (wg, a, bw))
         assert a > 0.0 or bw > 0.0
 
-
-@pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED], ids=["fp64", "mixed"])
-@pytest.mark.parametrize("nx,ny", [(257, 257), (385, 193)])
-def test_up_leg_r_over_c_formed_from_rows_is_bitwise_the_stored_one(nx, ny, precision, monkeypatch):
-    # the up leg's r/C from the loaded pre-relaxed iterate (no q plane) on every
-    # coarse level, against the stored q on every level: the same expressions
-    # on the same values
-    planes = O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=60))
-    b = inputs.load_uniform(nx, ny, seed=61)
-    res = {}
-    for name, lim in (("stored", "1000000000000"), ("formed", "0")):
-        monkeypatch.setenv("HIPBMG_RC_MIN", lim)
-        for rb in ("1", "5"):
-            monkeypatch.setenv("HIPBMG_RB", rb)
-            res[(name, rb)] = run(planes, b, 4, collapse_level=1, precision=precision)
-    for rb in ("1", "5"):
-        assert torch.equal(res[("stored", rb)][0], res[("formed", rb)][0]), rb
-        assert res[("stored", rb)][1].history() == res[("formed", rb)][1].history()
-    assert torch.equal(res[("formed", "1")][0], res[("formed", "5")][0])
