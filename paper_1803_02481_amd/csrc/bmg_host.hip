@@ -218,6 +218,16 @@ static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
     return HIPBMG_OK;
 }
 
+// grid barriers of the agglomeration stages and their give-up flag (zero)
+static hipbmg_status alloc_stage_barriers(hipbmg_hier *h, hipStream_t s)
+{
+    if (h->d_bar) return HIPBMG_OK;
+    hipbmg_status st = dalloc(h, &h->d_bar, 2 * CLUSTER_MAX_STAGES, s);
+    if (st == HIPBMG_OK) st = dalloc(h, &h->d_err, 1, s);
+    return st;
+}
+
+
 template <typename T>
 static hipbmg_status alloc_levels(hipbmg_hier *h, std::vector<LevelDev<T>> &lv,
                                   const std::vector<int> &sx, const std::vector<int> &sy,
@@ -655,8 +665,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     }
     h->lstar = prm.collapse_level >= 0 ? prm.collapse_level : best;
     // agglomeration stages: the redistribution search of section 4 over
-    // (level, workgroups), or one forced stage
-    {
+    // (level, workgroups), or one forced stage (cluster_wg = 0: neither)
+    if (prm.cluster_wg != 0) {
         const int word = prm.precision == HIPBMG_MIXED ? 4 : 8;
         const int res = prm.precision == HIPBMG_MIXED ? cluster_max_resident<float>(COLLAPSE_LDS_BUDGET)
                                                       : cluster_max_resident<double>(COLLAPSE_LDS_BUDGET);
@@ -714,9 +724,12 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         }
         h->path_us = model_path_us(ml, L, prm.nu1, prm.nu2, h->nc, word, h->mp, h->lstar, h->cl_nstage, h->cl_wg,
                                    h->cl_hi);
-        st = dalloc(h, &h->d_bar, 2 * CLUSTER_MAX_STAGES, s);
-        if (st == HIPBMG_OK) st = dalloc(h, &h->d_err, 1, s);
-        if (st != HIPBMG_OK) return bail(st);
+        if (h->cl_nstage > 0) {
+            st = alloc_stage_barriers(h, s);
+            if (st != HIPBMG_OK) return bail(st);
+        }
+    } else {
+        h->path_us = h->model_us[h->lstar];
     }
     if (h->lstar >= L - 1) h->fused3 = 0;   // the finest level itself is collapsed
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "setup failed: %s",
@@ -1612,6 +1625,7 @@ static hipError_t calibrate_precision(hipbmg_hier *h, const std::vector<LevelDev
     // the stage runs no level); the increments are the levels' costs on K
     // workgroups, fitted to phases x alpha_stage + bytes x beta_stage
     {
+        if (alloc_stage_barriers(h, s) != HIPBMG_OK) return hipErrorOutOfMemory;
         const int max_wg = std::min(256, cluster_max_resident<T>(COLLAPSE_LDS_BUDGET));
         for (int k = 0; k < MODEL_STAGE_SIZES && L >= 4; ++k) {
             const int K = 2 << k;
