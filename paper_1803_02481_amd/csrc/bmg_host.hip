@@ -112,7 +112,7 @@ struct hipbmg_hier {
     // device-side stopping: run flag, residual history, and a ring of
     // host-mapped slots through which the host sees each cycle's test
     int *d_flags = nullptr;               // [0] run, [1] stopping cycle, [2] reason
-    int h_flags[4] = {};
+    int *h_flags = nullptr;               // pinned mirror of d_flags
     double *d_hist = nullptr;             // relres after each cycle of the current solve
     double *ring_host = nullptr, *ring_dev = nullptr;   // RING x {relres, run, stop, k}
     hipEvent_t ring_ev[RING] = {};
@@ -145,6 +145,7 @@ struct hipbmg_hier {
             if (ring_ev[k]) (void)hipEventDestroy(ring_ev[k]);
         for (void *p : allocs) (void)hipFree(p);
         if (h_scal) (void)hipHostFree(h_scal);
+        if (h_flags) (void)hipHostFree(h_flags);
         if (ring_host) (void)hipHostFree(ring_host);
     }
 };
@@ -612,7 +613,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if (st != HIPBMG_OK) return bail(st);
     st = dalloc(h, &h->d_scal, 8, s);
     if (st != HIPBMG_OK) return bail(st);
-    if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess)
+    if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&h->h_flags, 4 * sizeof(int)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
     // device-side stopping: run flag, residual history, host-mapped test slots
     st = dalloc(h, &h->d_flags, 4, s);
@@ -1064,8 +1066,9 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             if (slot[1] == 0.0) stopped = true;
         }
     }
+    // the flags come back with the same synchronisation that ends the cycles
+    HIPCHK(hipMemcpyAsync(h->h_flags, h->d_flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipMemcpy(h->h_flags, h->d_flags, 4 * sizeof(int), hipMemcpyDeviceToHost));
     const int kdone = h->h_flags[0] ? k : h->h_flags[1];
     prof_collect(h, true, kdone);
     if (pipe && kdone > 0 && kdone != stored_last) {
