@@ -1,4 +1,5 @@
-"""ctypes wrapper around the FP64 CPU oracle (``bmg_oracle.c``).
+"""ctypes wrapper around the FP64 CPU oracles (``bmg_oracle.c`` in 2D,
+``bmg_oracle3d.c`` in 3D).
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg use this module; the GPU library never does.  It shares no
@@ -14,7 +15,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "bmg_oracle.c")
+_SRCS = [os.path.join(_HERE, "bmg_oracle.c"), os.path.join(_HERE, "bmg_oracle3d.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -23,10 +24,11 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 def build(force=False):
     """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(s) for s in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared"]
+                              + _SRCS + ["-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -59,6 +61,25 @@ def lib():
         L.oracle_grad_logD.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.oracle_fv5_aniso.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
                                        _D, _D, _D]
+        I = ctypes.c_int
+        IP = ctypes.POINTER(ctypes.c_int)
+        L.oracle3_fv7.argtypes = [I, I, I, _D, _D, _D, _D, _D]
+        L.oracle3_setup.restype = ctypes.c_void_p
+        L.oracle3_setup.argtypes = [I, I, I, I, _D, I, I, I, I, IP]
+        L.oracle3_free.argtypes = [ctypes.c_void_p]
+        L.oracle3_num_levels.argtypes = [ctypes.c_void_p]
+        L.oracle3_num_levels.restype = I
+        L.oracle3_level_size.argtypes = [ctypes.c_void_p, I, IP, IP, IP]
+        L.oracle3_get_stencil.argtypes = [ctypes.c_void_p, I, _D]
+        L.oracle3_get_interp.argtypes = [ctypes.c_void_p, I, _D]
+        L.oracle3_solve.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_double, I, _D]
+        L.oracle3_solve.restype = I
+        L.oracle3_smooth.argtypes = [ctypes.c_void_p, I, _D, _D, I]
+        L.oracle3_residual.argtypes = [ctypes.c_void_p, I, _D, _D, _D]
+        L.oracle3_restrict.argtypes = [ctypes.c_void_p, I, _D, _D]
+        L.oracle3_interp_correct.argtypes = [ctypes.c_void_p, I, _D, _D, _D, I]
+        L.oracle3_coarse_solve.argtypes = [ctypes.c_void_p, _D, _D]
+        L.oracle3_vcycle.argtypes = [ctypes.c_void_p, _D, _D]
     return _lib
 
 
@@ -184,4 +205,109 @@ class Hierarchy:
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.zeros_like(b)
         lib().oracle_coarse_solve(self._h, _p(b), _p(x))
+        return x
+
+
+# --------------------------------------------------------------------------
+# 3D
+# --------------------------------------------------------------------------
+
+def fv7(cellD):
+    """7-point finite-volume planes (C, W, S, B) [4][nz][ny][nx] from per-cell
+    diffusivity [(nz-1)][(ny-1)][(nx-1)]."""
+    cellD = np.ascontiguousarray(cellD, dtype=np.float64)
+    nz, ny, nx = cellD.shape[0] + 1, cellD.shape[1] + 1, cellD.shape[2] + 1
+    out = np.zeros((4, nz, ny, nx))
+    lib().oracle3_fv7(nx, ny, nz, _p(cellD), _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3]))
+    return out
+
+
+class Hierarchy3:
+    """3D oracle hierarchy built from the finest stencil planes.
+
+    planes: [4][nz][ny][nx] = {C, W, S, B} (7-point), or [14][nz][ny][nx] =
+    {C, then -A(p, p+d) for the 13 lower-half offsets d in linear order
+    (dz+1)*9+(dy+1)*3+(dx+1) = 0..12} (27-point).  Level 0 is the coarsest.
+    """
+
+    def __init__(self, planes, coarsest_n=3, nu1=2, nu2=1, rescorr=1):
+        planes = np.ascontiguousarray(planes, dtype=np.float64)
+        npt = {4: 7, 14: 27}[planes.shape[0]]
+        self.nz, self.ny, self.nx = planes.shape[1:]
+        st = ctypes.c_int(0)
+        self._h = lib().oracle3_setup(self.nx, self.ny, self.nz, npt, _p(planes), coarsest_n, nu1, nu2,
+                                      rescorr, ctypes.byref(st))
+        self.status = st.value
+        if not self._h:
+            raise ValueError("oracle3_setup rejected the arguments (status %d)" % st.value)
+        self.L = lib().oracle3_num_levels(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().oracle3_free(self._h)
+            self._h = None
+
+    def size(self, l):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lib().oracle3_level_size(self._h, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return c.value, b.value, a.value  # (nz, ny, nx)
+
+    def stencil(self, l):
+        """[nz][ny][nx][3][3][3] matrix entries A(p, p + d) at [.., dz+1, dy+1, dx+1]."""
+        nz, ny, nx = self.size(l)
+        out = np.zeros((nz, ny, nx, 27))
+        lib().oracle3_get_stencil(self._h, l, _p(out))
+        return out.reshape(nz, ny, nx, 3, 3, 3)
+
+    def interp(self, l):
+        """[nz][ny][nx][2][2][2] interpolation rows of level l, weight on coarse
+        vertex ((i>>1)+a, (j>>1)+b, (k>>1)+c) at [.., c, b, a]."""
+        nz, ny, nx = self.size(l)
+        out = np.zeros((nz, ny, nx, 8))
+        lib().oracle3_get_interp(self._h, l, _p(out))
+        return out.reshape(nz, ny, nx, 2, 2, 2)
+
+    def solve(self, b, u0=None, tol=1e-10, max_cycles=500):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64, order="C")
+        hist = np.zeros(max_cycles)
+        n = lib().oracle3_solve(self._h, _p(b), _p(u), tol, max_cycles, _p(hist))
+        return u, hist[:n]
+
+    def vcycle(self, b, u):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        u = np.array(u, dtype=np.float64, order="C")
+        lib().oracle3_vcycle(self._h, _p(b), _p(u))
+        return u
+
+    def smooth(self, l, b, x, sweeps=1):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x, dtype=np.float64, order="C")
+        lib().oracle3_smooth(self._h, l, _p(b), _p(x), sweeps)
+        return x
+
+    def residual(self, l, b, x):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        r = np.zeros_like(b)
+        lib().oracle3_residual(self._h, l, _p(b), _p(x), _p(r))
+        return r
+
+    def restrict(self, l, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        bc = np.zeros(self.size(l - 1))
+        lib().oracle3_restrict(self._h, l, _p(r), _p(bc))
+        return bc
+
+    def interp_correct(self, l, x, r, xc, rescorr=1):
+        x = np.array(x, dtype=np.float64, order="C")
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        xc = np.ascontiguousarray(xc, dtype=np.float64)
+        lib().oracle3_interp_correct(self._h, l, _p(x), _p(r), _p(xc), rescorr)
+        return x
+
+    def coarse_solve(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b)
+        lib().oracle3_coarse_solve(self._h, _p(b), _p(x))
         return x

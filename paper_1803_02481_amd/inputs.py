@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the 2D diffusion problems the solver is run on.
+"""Seeded synthetic inputs for the 2D and 3D diffusion problems the solver is run on.
 
 This module holds no arithmetic of the method: it only draws coefficient fields
 and right-hand sides from numpy's PCG64 generator (``default_rng(seed)``),
@@ -7,6 +7,7 @@ take their inputs from here.
 
 Grids are vertex grids of nx x ny points including the boundary ring; cell
 fields have (ny-1) x (nx-1) entries, cell (i, j) = [x_i, x_i+1] x [y_j, y_j+1].
+In 3D the arrays are [nz][ny][nx] (vertices) and [nz-1][ny-1][nx-1] (cells).
 """
 import numpy as np
 
@@ -85,3 +86,31 @@ def load_uniform(nx, ny, seed=2):
 def batch_sizes(nprob=256, choices=(129, 257, 513, 1025), seed=5):
     rng = np.random.default_rng(seed)
     return [int(choices[k]) for k in rng.integers(0, len(choices), size=nprob)]
+
+
+def cells3_log10_blocks(nx, ny, nz, block=8, lo=-2.0, hi=2.0, seed=11):
+    """3D piecewise-constant D on block^3 cell tiles, log10 D ~ U[lo, hi]."""
+    rng = np.random.default_rng(seed)
+    bz, by, bx = -(-(nz - 1) // block), -(-(ny - 1) // block), -(-(nx - 1) // block)
+    e = rng.uniform(lo, hi, size=(bz, by, bx))
+    D = 10.0 ** np.repeat(np.repeat(np.repeat(e, block, axis=0), block, axis=1), block, axis=2)
+    return np.ascontiguousarray(D[: nz - 1, : ny - 1, : nx - 1])
+
+
+def cells3_lognormal(nx, ny, nz, sigma=1.0, seed=12):
+    """3D per-cell i.i.d. D = exp(sigma * Z), Z ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(sigma * rng.standard_normal((nz - 1, ny - 1, nx - 1)))
+
+
+def load3_uniform(nx, ny, nz, seed=13):
+    """3D load b = h^2 f (the 7-point scheme's connections leave out the
+    common factor h of the dual-face area over the edge length), f ~ U[-1, 1]
+    i.i.d. at interior vertices, h the mean spacing; boundary entries zero."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+    f[0], f[-1] = 0.0, 0.0
+    f[:, 0], f[:, -1] = 0.0, 0.0
+    f[:, :, 0], f[:, :, -1] = 0.0, 0.0
+    h = (1.0 / (nx - 1) + 1.0 / (ny - 1) + 1.0 / (nz - 1)) / 3.0
+    return f * (h * h)
