@@ -50,6 +50,9 @@ static hipbmg_status fail(hipbmg_status st, const char *fmt, ...)
 
 extern "C" const char *hipbmg_last_error(void) { return g_err.c_str(); }
 
+// the message of the calling thread's last failure, for the other entry-point files
+void hbmg::set_last_error(const char *msg) { g_err = msg; }
+
 extern "C" void hipbmg_default_params(hipbmg_params *p)
 {
     if (!p) return;

@@ -17,6 +17,9 @@
 
 namespace hbmg {
 
+// Set the message hipbmg_last_error() returns on the calling thread.
+void set_last_error(const char *msg);
+
 // Weight plane indices (fine vertex of coarse cell (I,J) -> coarse corner).
 enum { WXL = 0, WXR = 1, WYB = 2, WYT = 3, WCSW = 4, WCSE = 5, WCNW = 6, WCNE = 7 };
 

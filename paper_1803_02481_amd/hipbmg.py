@@ -79,6 +79,22 @@ _SIGS = {
                                   ctypes.POINTER(Info)]),
     "hipbmg_destroy_batched": (_I, [_VP]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
+    # 3D path (include/hipbmg3d.h)
+    "hipbmg3d_fv7_from_cells": (_I, [_I, _I, _I, _VP, _VP, _VP]),
+    "hipbmg3d_setup": (_I, [_I, _I, _I, _I, _VP, ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
+    "hipbmg3d_solve": (_I, [_VP, _VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(Info)]),
+    "hipbmg3d_destroy": (_I, [_VP]),
+    "hipbmg3d_num_levels": (_I, [_VP, ctypes.POINTER(_I)]),
+    "hipbmg3d_level_size": (_I, [_VP, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "hipbmg3d_get_stencil": (_I, [_VP, _I, _VP, _VP]),
+    "hipbmg3d_get_interp": (_I, [_VP, _I, _VP, _VP]),
+    "hipbmg3d_op_smooth": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
+    "hipbmg3d_op_residual": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
+    "hipbmg3d_op_restrict": (_I, [_VP, _I, _VP, _VP, _VP]),
+    "hipbmg3d_op_interp_correct": (_I, [_VP, _I, _VP, _VP, _VP, _I, _VP]),
+    "hipbmg3d_op_coarse_solve": (_I, [_VP, _VP, _VP, _VP]),
+    "hipbmg3d_profile": (_I, [_VP, _I]),
+    "hipbmg3d_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
 }
 
 
@@ -395,3 +411,116 @@ class SolveFVBatched(torch.autograd.Function):
         g_theta = torch.stack([grad_logD(th[k], u[k], lam[k]) for k in range(nb)])
         ctx.hier.close()
         return g_theta, lam, None, None
+
+
+# --------------------------------------------------------------------------
+# 3D (include/hipbmg3d.h)
+# --------------------------------------------------------------------------
+KERNELS3 = ("relax_colour", "residual", "restrict", "interp", "coarse_levels")
+
+
+def fv7_from_cells(cells):
+    """7-point finite-volume planes {C, W, S, B} [4][nz][ny][nx] from per-cell D
+    [(nz-1)][(ny-1)][(nx-1)] (a CUDA float64 tensor)."""
+    nz, ny, nx = (int(d) + 1 for d in cells.shape)
+    out = torch.empty((4, nz, ny, nx), dtype=torch.float64, device=cells.device)
+    _check(lib().hipbmg3d_fv7_from_cells(nx, ny, nz, _ptr(cells), _ptr(out), _stream()))
+    return out
+
+
+class Hierarchy3:
+    """3D multigrid hierarchy on the GPU (hipbmg3d_setup / hipbmg3d_solve).
+
+    planes: [4][nz][ny][nx] {C, W, S, B} (7-point) or [14][nz][ny][nx] (27-point:
+    C, then -A(p, p+d) for the lower-half offsets d, linear index 0..12)."""
+
+    def __init__(self, planes, **params):
+        if planes.dim() != 4 or planes.shape[0] not in (4, 14):
+            raise ValueError("planes must be [4 or 14][nz][ny][nx]")
+        self.npt = 7 if planes.shape[0] == 4 else 27
+        self.nz, self.ny, self.nx = (int(d) for d in planes.shape[1:])
+        self.params = default_params(**params)
+        self.device = planes.device
+        h = ctypes.c_void_p()
+        _check(lib().hipbmg3d_setup(self.nx, self.ny, self.nz, self.npt, _ptr(planes), ctypes.byref(self.params),
+                                    _stream(), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int()
+        _check(lib().hipbmg3d_num_levels(self._h, ctypes.byref(n)))
+        self.L = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hipbmg3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self, l):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().hipbmg3d_level_size(self._h, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return c.value, b.value, a.value   # (nz, ny, nx)
+
+    def _field(self, l):
+        return torch.zeros(self.size(l), dtype=torch.float64, device=self.device)
+
+    def stencil(self, l):
+        """[27][nz][ny][nx]: out[(dz+1)*9+(dy+1)*3+(dx+1)] = A(p, p+d)."""
+        out = torch.empty((27,) + self.size(l), dtype=torch.float64, device=self.device)
+        _check(lib().hipbmg3d_get_stencil(self._h, l, _ptr(out), _stream()))
+        return out
+
+    def interp(self, l):
+        """[8][nz][ny][nx]: weight of fine vertex (i,j,k) on ((i>>1)+a, (j>>1)+b, (k>>1)+c) at [4c+2b+a]."""
+        out = torch.empty((8,) + self.size(l), dtype=torch.float64, device=self.device)
+        _check(lib().hipbmg3d_get_interp(self._h, l, _ptr(out), _stream()))
+        return out
+
+    def solve(self, b, u0=None, tol=1e-10, check=True):
+        u = torch.zeros_like(b) if u0 is None else u0.clone()
+        info = Info()
+        st = lib().hipbmg3d_solve(self._h, _ptr(b), _ptr(u), float(tol), _stream(), ctypes.byref(info))
+        if st != OK and (check or st not in (ENOCONV,)):
+            _check(st)
+        return u, info
+
+    def smooth(self, l, b, x, sweeps=1):
+        x = x.clone()
+        _check(lib().hipbmg3d_op_smooth(self._h, l, _ptr(b), _ptr(x), sweeps, _stream()))
+        return x
+
+    def residual(self, l, b, x):
+        r = self._field(l)
+        _check(lib().hipbmg3d_op_residual(self._h, l, _ptr(b), _ptr(x), _ptr(r), _stream()))
+        return r
+
+    def restrict(self, l, r):
+        bc = self._field(l - 1)
+        _check(lib().hipbmg3d_op_restrict(self._h, l, _ptr(r), _ptr(bc), _stream()))
+        return bc
+
+    def interp_correct(self, l, x, r, xc, rescorr=1):
+        x = x.clone()
+        _check(lib().hipbmg3d_op_interp_correct(self._h, l, _ptr(x), _ptr(r), _ptr(xc), rescorr, _stream()))
+        return x
+
+    def coarse_solve(self, b):
+        x = self._field(0)
+        _check(lib().hipbmg3d_op_coarse_solve(self._h, _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def profile(self, enable=True):
+        _check(lib().hipbmg3d_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (ms, launches)} accumulated since profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNELS3):
+            ms, n = ctypes.c_double(), ctypes.c_longlong()
+            _check(lib().hipbmg3d_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out

@@ -1,5 +1,6 @@
 """CPU checks of the C boundary: the library is built, loads, and exports every
-entry point declared in include/hipbmg.h (no device calls)."""
+entry point declared in include/hipbmg.h and include/hipbmg3d.h (no device
+calls)."""
 import ctypes
 import os
 import re
@@ -7,20 +8,23 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hipbmg.h")
+HEADERS = [os.path.join(ROOT, "include", "hipbmg.h"), os.path.join(ROOT, "include", "hipbmg3d.h")]
 LIB = os.path.join(ROOT, "paper_1803_02481_amd", "libhipbmg.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hipbmg_[A-Za-z0-9_]+)\s*\(", text)))
+    names = set()
+    for hdr in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+        names |= set(re.findall(r"\b(hipbmg(?:3d)?_[A-Za-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("hipbmg_setup", "hipbmg_solve", "hipbmg_destroy", "hipbmg_fv5_from_cells",
-                 "hipbmg_grad_logD", "hipbmg_last_error", "hipbmg_default_params"):
+                 "hipbmg_grad_logD", "hipbmg_last_error", "hipbmg_default_params",
+                 "hipbmg3d_setup", "hipbmg3d_solve", "hipbmg3d_destroy", "hipbmg3d_fv7_from_cells"):
         assert must in names
 
 
@@ -51,6 +55,21 @@ def test_default_params_and_errors_without_device():
     assert lib.hipbmg_setup(65, 65, 5, None, None, None, ctypes.byref(h)) == hipbmg.EINVAL
     assert lib.hipbmg_solve(None, None, None, 1e-10, None, None) == hipbmg.EINVAL
     assert lib.hipbmg_destroy(None) == hipbmg.OK
+    # the 3D entry points validate before any device call as well
+    p3 = ctypes.byref(p)
+    assert lib.hipbmg3d_setup(33, 33, 32, 7, ctypes.c_void_p(8), p3, None, ctypes.byref(h)) == hipbmg.EINVAL
+    assert b"odd" in lib.hipbmg_last_error()
+    assert lib.hipbmg3d_setup(33, 33, 33, 9, ctypes.c_void_p(8), p3, None, ctypes.byref(h)) == hipbmg.EINVAL
+    pm = hipbmg.default_params(precision=hipbmg.MIXED)
+    assert lib.hipbmg3d_setup(33, 33, 33, 7, ctypes.c_void_p(8), ctypes.byref(pm), None,
+                              ctypes.byref(h)) == hipbmg.EINVAL
+    assert b"FP64" in lib.hipbmg_last_error()
+    pc = hipbmg.default_params(coarsest_n=33)
+    assert lib.hipbmg3d_setup(33, 33, 33, 7, ctypes.c_void_p(8), ctypes.byref(pc), None,
+                              ctypes.byref(h)) == hipbmg.EINVAL
+    assert b"unknowns" in lib.hipbmg_last_error()
+    assert lib.hipbmg3d_solve(None, None, None, 1e-10, None, None) == hipbmg.EINVAL
+    assert lib.hipbmg3d_destroy(None) == hipbmg.OK
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):
