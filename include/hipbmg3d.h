@@ -38,7 +38,9 @@
  *     whose linear index (dz+1)*9 + (dy+1)*3 + (dx+1) is 0..12; the entry for
  *     -d is the one stored at p-d (symmetry).
  *   - Only FP64 is provided in 3D (params->precision must be HIPBMG_FP64);
- *     collapse_level, cluster_wg, cluster_top and use_graph are ignored.
+ *     collapse_level, cluster_wg and cluster_top are ignored.  With use_graph
+ *     (the default) each V-cycle and its residual norm are replayed from a
+ *     hipGraph captured on the first solve on the caller's stream.
  *   - Inside a handle every field is held in an octant layout: eight
  *     sub-grids by index parity, so that each colour of the relaxation and
  *     each kind of interpolated vertex is one contiguous array.  The calls

@@ -443,19 +443,31 @@ __device__ __forceinline__ long long nbr(const Oct &g, long long t)
     return on * g.oct + t + sz * g.plane + sy * g.px + sx;
 }
 
-// sum_q A(p,q) x_q over the whole stencil of vertex t of octant O
-template <int NPT, int O>
+template <bool NT>
+__device__ __forceinline__ double ldc(const double *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+// sum_q A(p,q) x_q over the whole stencil of vertex t of octant O (NT: the
+// 7-point coefficients as nontemporal loads)
+template <int NPT, int O, bool NT = false>
 __device__ __forceinline__ double apply_at(const Oct &g, const double *st, const double *x, long long t)
 {
     const long long F = g.field;
     const long long v = O * g.oct + t;
     if (NPT == 7) {
+        // in a relaxation the coefficients stream through once per sweep
+        // (nontemporal); the iterate's octants are read again by the
+        // neighbouring colours
         const double *C = st, *W = st + F, *S = st + 2 * F, *B = st + 3 * F;
         const long long xw = nbr<O, -1, 0, 0>(g, t), xe = nbr<O, 1, 0, 0>(g, t);
         const long long ys = nbr<O, 0, -1, 0>(g, t), yn = nbr<O, 0, 1, 0>(g, t);
         const long long zb = nbr<O, 0, 0, -1>(g, t), zt = nbr<O, 0, 0, 1>(g, t);
-        return C[v] * x[v] - W[v] * x[xw] - W[xe] * x[xe] - S[v] * x[ys] - S[yn] * x[yn] - B[v] * x[zb] -
-               B[zt] * x[zt];
+        const double cv = ldc<NT>(C + v), wv = ldc<NT>(W + v), we = ldc<NT>(W + xe), sv = ldc<NT>(S + v),
+                     sn = ldc<NT>(S + yn), bv = ldc<NT>(B + v), bt = ldc<NT>(B + zt);
+        return cv * x[v] - wv * x[xw] - we * x[xe] - sv * x[ys] - sn * x[yn] - bv * x[zb] - bt * x[zt];
     } else {
         double s = st[v] * x[v];
 #define HB3_PAIR(o, dx, dy, dz)                                                                      \
@@ -485,17 +497,49 @@ __device__ __forceinline__ bool thread_vertex(const Oct &g, long long t, int &i,
     return a < g.mx && inner(g, i, j, k);
 }
 
-// one colour of the relaxation: x_p += (b_p - (A x)_p) / A_pp on octant O
+// x_p += (b_p - (A x)_p) / A_pp at vertex t of octant O
+template <int NPT, int O>
+__device__ __forceinline__ void gs_point(const LArgs &a, long long t)
+{
+    int i, j, k;
+    if (!thread_vertex<O>(a.g, t, i, j, k)) return;
+    const long long v = O * a.g.oct + t;
+    const double s = apply_at<NPT, O, true>(a.g, a.st, a.x, t);
+    a.x[v] += (a.b[v] - s) / a.st[v];
+}
+
+// one colour of the relaxation on octant O
 template <int NPT, int O>
 __global__ __launch_bounds__(256) void k3_gs(LArgs a)
 {
     const long long t = blockIdx.x * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
-    int i, j, k;
-    if (!thread_vertex<O>(a.g, t, i, j, k)) return;
-    const long long v = O * a.g.oct + t;
-    const double s = apply_at<NPT, O>(a.g, a.st, a.x, t);
-    a.x[v] += (a.b[v] - s) / a.st[v];
+    gs_point<NPT, O>(a, t);
+}
+
+// 7-point operators: a colour couples only to the three colours that differ
+// from it in one index parity, so colours 1, 2, 4 do not couple to each other,
+// nor do 3, 5, 6.  Running {0}, {1,2,4}, {3,5,6}, {7} as four launches updates
+// every vertex from the same values as the colour order 0..7 (bitwise the
+// same sweep), and one thread's three vertices share their neighbours' loads.
+template <int G>
+__global__ __launch_bounds__(256) void k3_gs7g(LArgs a)
+{
+    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    if (t >= a.g.oct) return;
+    if (G == 0) {
+        gs_point<7, 0>(a, t);
+    } else if (G == 1) {
+        gs_point<7, 1>(a, t);
+        gs_point<7, 2>(a, t);
+        gs_point<7, 4>(a, t);
+    } else if (G == 2) {
+        gs_point<7, 3>(a, t);
+        gs_point<7, 5>(a, t);
+        gs_point<7, 6>(a, t);
+    } else {
+        gs_point<7, 7>(a, t);
+    }
 }
 
 // residual r = b - A x (STORE) and/or block sums of r^2 (NORM); blockIdx.y = octant
@@ -513,13 +557,15 @@ __device__ __forceinline__ double resid_at(const LArgs &a, long long t)
     return NORM ? r * r : 0.0;
 }
 
+// blocks interleave the octants (octant = block mod 8), so that the eight
+// octants of one region run together and share their neighbours in L2
 template <int NPT, bool STORE, bool NORM>
 __global__ __launch_bounds__(256) void k3_resid(LArgs a)
 {
-    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    const long long t = (blockIdx.x >> 3) * 256LL + threadIdx.x;
     double sq = 0.0;
     if (t < a.g.oct) {
-        switch (blockIdx.y) {
+        switch (blockIdx.x & 7) {
         case 0: sq = resid_at<NPT, 0, STORE, NORM>(a, t); break;
         case 1: sq = resid_at<NPT, 1, STORE, NORM>(a, t); break;
         case 2: sq = resid_at<NPT, 2, STORE, NORM>(a, t); break;
@@ -535,7 +581,7 @@ __global__ __launch_bounds__(256) void k3_resid(LArgs a)
         __shared__ double ws[4];
         if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sq;
         __syncthreads();
-        if (threadIdx.x == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
     }
 }
 
@@ -558,27 +604,37 @@ __global__ __launch_bounds__(256) void k3_sumsq(Oct g, const double *f, double *
     if (threadIdx.x == 0) partials[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// one block: out[0] = sum of n partials
-__global__ __launch_bounds__(256) void k3_reduce(const double *partials, long long n, double *out)
+// zero a field (a kernel, not a memset node, so that it can sit in a captured graph)
+__global__ __launch_bounds__(256) void k3_fill0(double *p, long long n)
+{
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) p[t] = 0.0;
+}
+
+// block b: out[b] = sum of partials [b*chunk, min(n, (b+1)*chunk))
+__global__ __launch_bounds__(256) void k3_reduce(const double *partials, long long n, long long chunk, double *out)
 {
     double s = 0.0;
-    for (long long t = threadIdx.x; t < n; t += 256) s += partials[t];
+    const long long lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (long long t = lo + threadIdx.x; t < hi; t += 256) s += partials[t];
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     __shared__ double ws[4];
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = ws[0] + ws[1] + ws[2] + ws[3];
+    if (threadIdx.x == 0) out[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 // b_c = P^T r: each coarse vertex gathers its 27 fine support vertices
 __global__ __launch_bounds__(256) void k3_restrict(LArgs a)
 {
     const Oct g = a.g, c = a.c;
-    const long long t = blockIdx.x * 256LL + threadIdx.x;
-    if (t >= c.field) return;
-    const int oc = (int)(t / c.oct);
+    // blocks interleave the coarse octants: neighbouring coarse vertices,
+    // which share fine support vertices, run together
+    const int oc = blockIdx.x & 7;
+    const long long ts = (blockIdx.x >> 3) * 256LL + threadIdx.x;
+    if (ts >= c.oct) return;
+    const long long t = oc * c.oct + ts;
     int ca, cb, cc;
-    sub_coords(c, t % c.oct, ca, cb, cc);
+    sub_coords(c, ts, ca, cb, cc);
     const int I = 2 * ca + (oc & 1), J = 2 * cb + ((oc >> 1) & 1), K = 2 * cc + (oc >> 2);
     if (ca >= c.mx || !inner(c, I, J, K)) {
         a.bc[t] = 0.0;
@@ -710,6 +766,9 @@ struct hipbmg3d_hier {
     double *h_sum = nullptr;   // pinned
     double *d_nat = nullptr;   // plain-layout staging of the op_* entry points
     std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;        // one V-cycle and the residual norm, captured
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;         // the stream the graph is captured on (the caller's may be the null stream)
     int prof = 0;
     std::vector<hipEvent_t> evpool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
@@ -738,6 +797,9 @@ void free3(hipbmg3d_hier *h)
     h->allocs.clear();
     if (h->h_sum) (void)hipHostFree(h->h_sum);
     for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
@@ -836,11 +898,35 @@ hipbmg_status relax(hipbmg3d_hier *h, int l, int sweeps, hipStream_t s)
 {
     const Lev3 &f = h->lv[l];
     const LArgs a = largs(f, nullptr);
-    for (int it = 0; it < sweeps; ++it)
+    const dim3 grid(nblk(f.g.oct)), block(256);
+    for (int it = 0; it < sweeps; ++it) {
+        if (f.npt == 7) {
+            for (int gq = 0; gq < 4; ++gq) {
+                Mark mk(h, l == h->L - 1 ? 0 : 4, s);
+                if (gq == 0) hipLaunchKernelGGL(k3_gs7g<0>, grid, block, 0, s, a);
+                else if (gq == 1) hipLaunchKernelGGL(k3_gs7g<1>, grid, block, 0, s, a);
+                else if (gq == 2) hipLaunchKernelGGL(k3_gs7g<2>, grid, block, 0, s, a);
+                else hipLaunchKernelGGL(k3_gs7g<3>, grid, block, 0, s, a);
+                HIP3(hipGetLastError());
+            }
+            continue;
+        }
         for (int o = 0; o < 8; ++o) {
             Mark mk(h, l == h->L - 1 ? 0 : 4, s);
             HIP3(launch_gs_colour(f.npt, o, a, s));
         }
+    }
+    return HIPBMG_OK;
+}
+
+// d_sum[0] = sum of n partials, in two stages of fixed shape (deterministic)
+hipbmg_status reduce_sum(hipbmg3d_hier *h, const double *partials, long long n, hipStream_t s)
+{
+    const long long nb = std::min<long long>(256, (n + 2047) / 2048);
+    const long long chunk = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k3_reduce, dim3((unsigned)nb), dim3(256), 0, s, partials, n, chunk, h->d_sum + 8);
+    hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(256), 0, s, (const double *)(h->d_sum + 8), nb, nb, h->d_sum);
+    HIP3(hipGetLastError());
     return HIPBMG_OK;
 }
 
@@ -850,7 +936,7 @@ hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream
     const Lev3 &f = h->lv[l];
     LArgs a = largs(f, nullptr);
     a.partials = h->d_part;
-    const dim3 grid(nblk(f.g.oct), 8), block(256);
+    const dim3 grid(8 * nblk(f.g.oct)), block(256);
     Mark mk(h, l == h->L - 1 ? 1 : 4, s);
     if (f.npt == 7) {
         if (store && !norm) hipLaunchKernelGGL((k3_resid<7, true, false>), grid, block, 0, s, a);
@@ -862,11 +948,7 @@ hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream
         else hipLaunchKernelGGL((k3_resid<27, true, true>), grid, block, 0, s, a);
     }
     HIP3(hipGetLastError());
-    if (norm) {
-        hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(256), 0, s, (const double *)h->d_part,
-                           (long long)grid.x * 8, h->d_sum);
-        HIP3(hipGetLastError());
-    }
+    if (norm) ST3(reduce_sum(h, h->d_part, (long long)grid.x, s));
     return HIPBMG_OK;
 }
 
@@ -874,7 +956,7 @@ hipbmg_status restrict_to(hipbmg3d_hier *h, int l, hipStream_t s)
 {
     const LArgs a = largs(h->lv[l], &h->lv[l - 1]);
     Mark mk(h, l == h->L - 1 ? 2 : 4, s);
-    hipLaunchKernelGGL(k3_restrict, dim3(nblk(a.c.field)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k3_restrict, dim3(8 * nblk(a.c.oct)), dim3(256), 0, s, a);
     HIP3(hipGetLastError());
     return HIPBMG_OK;
 }
@@ -909,10 +991,42 @@ hipbmg_status vcycle(hipbmg3d_hier *h, int l, hipStream_t s)
     ST3(relax(h, l, h->prm.nu1, s));
     ST3(residual(h, l, true, false, s));
     ST3(restrict_to(h, l, s));
-    HIP3(hipMemsetAsync(h->lv[l - 1].x, 0, (size_t)h->lv[l - 1].g.field * sizeof(double), s));
+    {
+        const long long n = h->lv[l - 1].g.field;
+        hipLaunchKernelGGL(k3_fill0, dim3((unsigned)std::min<long long>(nblk(n), 2048)), dim3(256), 0, s,
+                           h->lv[l - 1].x, n);
+        HIP3(hipGetLastError());
+    }
     ST3(vcycle(h, l - 1, s));
     ST3(interp_from(h, l, h->prm.residual_correction, s));
     ST3(relax(h, l, h->prm.nu2, s));
+    return HIPBMG_OK;
+}
+
+// one cycle and the finest residual norm (into d_sum); replayed from a
+// captured graph unless use_graph is 0 or kernel timing is on
+hipbmg_status cycle_and_norm(hipbmg3d_hier *h, hipStream_t s)
+{
+    if (!h->prm.use_graph || h->prof) {
+        ST3(vcycle(h, h->L - 1, s));
+        return residual(h, h->L - 1, false, true, s);
+    }
+    if (!h->exec) {
+        if (!h->cap) HIP3(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        hipStream_t c = h->cap;
+        HIP3(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        hipbmg_status st = vcycle(h, h->L - 1, c);
+        if (st == HIPBMG_OK) st = residual(h, h->L - 1, false, true, c);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c, &g);
+        if (st != HIPBMG_OK || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != HIPBMG_OK ? st : fail3(HIPBMG_EHIP, "graph capture failed: %s", hipGetErrorString(e2));
+        }
+        h->graph = g;
+        HIP3(hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0));
+    }
+    HIP3(hipGraphLaunch(h->exec, s));
     return HIPBMG_OK;
 }
 
@@ -1097,7 +1211,7 @@ extern "C" hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const d
     if ((st = dalloc3(h, &h->d_nat, nnat)) != HIPBMG_OK) return bail(st);
     h->npart = 8 * (long long)nblk(top.g.oct) + 8;
     if ((st = dalloc3(h, &h->d_part, h->npart)) != HIPBMG_OK) return bail(st);
-    if ((st = dalloc3(h, &h->d_sum, 8)) != HIPBMG_OK) return bail(st);
+    if ((st = dalloc3(h, &h->d_sum, 8 + 256)) != HIPBMG_OK) return bail(st);
     if (hipHostMalloc((void **)&h->h_sum, 8 * sizeof(double), 0) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail3(HIPBMG_ENOMEM, "pinned allocation failed"));
@@ -1182,9 +1296,8 @@ extern "C" hipbmg_status hipbmg3d_solve(hipbmg3d_handle h, const double *b, doub
     ST3(to_oct(f.g, b, f.b, 1, s));
     ST3(to_oct(f.g, u, f.x, 1, s));
     hipLaunchKernelGGL(k3_sumsq, dim3(nblk(f.g.field)), dim3(256), 0, s, f.g, (const double *)f.b, h->d_part);
-    hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(256), 0, s, (const double *)h->d_part, (long long)nblk(f.g.field),
-                       h->d_sum);
     HIP3(hipGetLastError());
+    ST3(reduce_sum(h, h->d_part, (long long)nblk(f.g.field), s));
     double bb = 0.0;
     ST3(read_sum(h, s, &bb));
     const double bn = std::sqrt(bb);
@@ -1202,8 +1315,7 @@ extern "C" hipbmg_status hipbmg3d_solve(hipbmg3d_handle h, const double *b, doub
     } else {
         rc = HIPBMG_ENOCONV;
         while (cycles < h->prm.max_cycles) {
-            ST3(vcycle(h, h->L - 1, s));
-            ST3(residual(h, h->L - 1, false, true, s));
+            ST3(cycle_and_norm(h, s));
             double rr = 0.0;
             ST3(read_sum(h, s, &rr));
             rel = std::sqrt(rr) / bn;
@@ -1301,7 +1413,9 @@ extern "C" hipbmg_status hipbmg3d_op_coarse_solve(hipbmg3d_handle h, const doubl
     hipStream_t s = (hipStream_t)stream;
     Lev3 &c = h->lv[0];
     ST3(to_oct(c.g, b, c.b, 1, s));
-    HIP3(hipMemsetAsync(c.x, 0, (size_t)c.g.field * sizeof(double), s));
+    hipLaunchKernelGGL(k3_fill0, dim3((unsigned)std::min<long long>(nblk(c.g.field), 2048)), dim3(256), 0, s, c.x,
+                       c.g.field);
+    HIP3(hipGetLastError());
     ST3(coarse_solve(h, s));
     ST3(from_oct(c.g, c.x, x, s));
     HIP3(hipStreamSynchronize(s));

@@ -216,3 +216,19 @@ def test_full_size_257_sampled_against_oracle_windows_and_true_residual():
     assert info.relres <= 1e-10 and abs(rel - info.relres) <= 1e-3 * info.relres
     # contrast 1e4 between 8^3-cell blocks: tens of cycles (78 for the 2D analogue at 4097^2)
     assert info.cycles <= 80
+
+
+def test_graph_replay_is_bitwise_the_eager_cycle():
+    # the captured cycle replays on later solves (with eager work between
+    # them) and gives bitwise the eager launches' iterates and histories
+    D, b = problem((33, 17, 17), 54, "lognormal")
+    planes = g(O.fv7(D))
+    eager = HB.Hierarchy3(planes, use_graph=0)
+    u_e, i_e = eager.solve(g(b))
+    graph = HB.Hierarchy3(planes, use_graph=1)
+    for rep in range(3):
+        u_g, i_g = graph.solve(g(b))
+        assert torch.equal(u_g, u_e), rep
+        assert i_g.history() == i_e.history(), rep
+        graph.smooth(graph.L - 1, g(b), g(np.zeros((33, 17, 17))), 1)
+        torch.cuda.synchronize()
