@@ -167,6 +167,27 @@ def oracle_workloads(args, n, extra, O, np, inputs):
         res["adjoint"] = {"value": 1.0 / el, "unit": "gradients/s", "cores": 1,
                           "sample": "one %dx%d gradient: setup, FP64 forward and adjoint solves, cell kernel "
                                     "(%.2f s)" % (m, m, el)}
+    # 3D: two V-cycles of the 3D oracle at 129^3 (its 257^3 setup alone takes
+    # minutes), scaled by vertex count to 257^3 and by the cycles of the GPU
+    # solve
+    if "next_3d" in extra:
+        m = 129
+        oh = O.Hierarchy3(O.fv7(inputs.cells3_log10_blocks(m, m, m, block=8, seed=51)))
+        bm = inputs.load3_uniform(m, m, m, seed=53)
+        um = np.zeros_like(bm)
+        k = 2
+        t0 = time.perf_counter()
+        for _ in range(k):
+            um = oh.vcycle(bm, um)
+        tc = (time.perf_counter() - t0) / k
+        n3 = extra["next_3d"]["n"]
+        scale = (n3 / m) ** 3
+        cyc = extra["next_3d"]["cycles"]
+        res["next_3d"] = {"value": 1.0 / (tc * scale * cyc), "unit": "solves/s", "cores": 1,
+                          "sample": "%d FP64 V(2,1)-cycles of the 3D oracle at %d^3 (%.3f s/cycle), scaled by "
+                                    "vertex count to %d^3 and by the %d cycles of the GPU solve"
+                                    % (k, m, tc, n3, cyc)}
+        del oh
     return res
 
 
@@ -187,6 +208,8 @@ def main():
     ap.add_argument("--adjoint-batch", type=int, default=64, help="problems in the adjoint workload")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip timing each forced collapse level against the model")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D workload")
+    ap.add_argument("--n3", type=int, default=257, help="vertices per side of the 3D workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -439,6 +462,56 @@ def main():
         log("bench: adjoint %.1f gradients/s (%.1f ms per batch of %d)"
             % (args.steps * nb / el_a, 1e3 * el_a / args.steps, nb))
         del th0, ba, u_obs, gth
+
+    if not args.no_3d:
+        # 3D: n3^3 vertices, D constant on 8^3-cell blocks with log10 D ~ U[-2,2]
+        # (seed 51), f ~ U[-1,1] (seed 53), 7-point finite volumes, V(2,1)
+        # with eight-colour GS and 27-point Galerkin levels to rel. residual 1e-10
+        m3 = args.n3
+        log("bench: 3D workload %d^3" % m3)
+        D3 = torch.from_numpy(inputs.cells3_log10_blocks(m3, m3, m3, block=8, seed=51)).to(dev)
+        b3 = torch.from_numpy(inputs.load3_uniform(m3, m3, m3, seed=53)).to(dev)
+        p3 = HB.fv7_from_cells(D3)
+        del D3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h3 = HB.Hierarchy3(p3)
+        torch.cuda.synchronize()
+        t_setup3 = time.perf_counter() - t0
+        u3, i3 = h3.solve(b3, tol=TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u3, i3 = h3.solve(b3, tol=TOL)
+        torch.cuda.synchronize()
+        el3 = (time.perf_counter() - t0) / args.steps
+        # the finest relaxation sweep (four launches: colour groups {0}, {1,2,4},
+        # {3,5,6}, {7}) timed with HIP events on the solve's stream
+        h3.profile(True)
+        u3, i3 = h3.solve(b3, tol=TOL)
+        torch.cuda.synchronize()
+        pr3 = h3.profile_read()
+        h3.profile(False)
+        ms_r, n_r = pr3["relax_colour"]
+        sweep_s = 4 * ms_r / n_r / 1e3
+        bytes_sweep = 56.0 * m3 ** 3   # x read+written, b, C, W, S, B per vertex
+        ach3 = bytes_sweep / sweep_s / 1e9
+        extra["next_3d"] = {
+            "workload": "%d^3 vertex 3D diffusion, D on 8^3-cell blocks log10 D~U[-2,2] (seed 51), f~U[-1,1] "
+                        "(seed 53), 7-point FV, V(2,1), eight-colour GS, 27-point Galerkin levels, to rel. "
+                        "residual 1e-10, FP64" % m3,
+            "n": m3, "value": 1.0 / el3, "unit": "solves/s", "ms_per_solve": 1e3 * el3,
+            "cycles": i3.cycles, "ms_per_cycle": 1e3 * el3 / i3.cycles, "relres": i3.relres,
+            "levels": i3.levels, "setup_ms": 1e3 * t_setup3,
+            "kernel_ms_per_cycle": {k: v[0] / i3.cycles for k, v in pr3.items()},
+            "roofline": {"bound": "hbm", "kernel": "finest relaxation sweep (k3_gs7g<0..3>)",
+                         "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
+                         "traffic": None, "algorithmic_bytes_per_sweep": bytes_sweep,
+                         "avg_sweep_us": sweep_s * 1e6},
+        }
+        log("bench: 3D %.2f solves/s (%d cycles, %.3f ms/cycle), finest sweep %.1f us = %.0f GB/s algorithmic"
+            % (1.0 / el3, i3.cycles, 1e3 * el3 / i3.cycles, sweep_s * 1e6, ach3))
+        del h3, p3, b3, u3
 
     cpu = None
     if not args.no_cpu:
