@@ -38,7 +38,12 @@
  *     whose linear index (dz+1)*9 + (dy+1)*3 + (dx+1) is 0..12; the entry for
  *     -d is the one stored at p-d (symmetry).
  *   - Only FP64 is provided in 3D (params->precision must be HIPBMG_FP64);
- *     collapse_level, cluster_wg and cluster_top are ignored.  With use_graph
+ *     cluster_wg and cluster_top are ignored.  collapse_level works as in 2D:
+ *     levels 0..l* run inside one persistent workgroup (the one-GPU form of
+ *     the paper's coarse-grid redistribution, sections 2.2 and 4), l* forced
+ *     (0 .. min(L-1, 7)) or, with -1, the argmin of the section 3 model with 3D
+ *     counts on the calibrated machine parameters.  The iteration does not
+ *     depend on l*.  With use_graph
  *     (the default) each V-cycle and its residual norm are replayed from a
  *     hipGraph captured on the first solve on the caller's stream.
  *   - Inside a handle every field is held in an octant layout: eight
@@ -79,7 +84,8 @@ hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const double *plan
  * vertices or params->max_cycles.  b, u: [nz][ny][nx]; u is the initial guess
  * on entry and the iterate on return (boundary entries set to 0).  The
  * residual norm is read back after every cycle.  info (may be NULL) gets
- * cycles, relres, relres_hist and levels.  HIPBMG_ENOCONV if tol was not
+ * cycles, relres, relres_hist, levels, collapse_level and model_us (the
+ * model's time of one cycle for each l*).  HIPBMG_ENOCONV if tol was not
  * reached, HIPBMG_ENAN on a non-finite residual. */
 hipbmg_status hipbmg3d_solve(hipbmg3d_handle h, const double *b, double *u, double tol, void *stream,
                              hipbmg_info *info);

@@ -17,6 +17,7 @@
 // keeps its weights in 2, 4 or 8 octant-sized slots (26 in all).
 #include "hipbmg3d.h"
 #include "bmg_internal.h"
+#include "bmg_model.h"
 
 #include <algorithm>
 #include <chrono>
@@ -688,29 +689,204 @@ __global__ __launch_bounds__(256) void k3_interp(LArgs a)
     }
 }
 
-// coarsest solve, one workgroup: L y = b, L^T x = y with the host-computed
-// Cholesky factor (row-major n x n lower triangle), column-oriented updates
-__global__ __launch_bounds__(256) void k3_coarse(const double *Lf, const long long *idx, int n, const double *b,
-                                                 double *x)
+// ---------------------------------------------------------------------------
+// collapsed levels: levels 0..top in one persistent workgroup (the one-GPU
+// form of the paper's coarse-grid redistribution).  Every phase does the
+// arithmetic of the grid-wide kernels in the same expression order, so the
+// iteration does not depend on the collapse level.
+// ---------------------------------------------------------------------------
+constexpr int MAXC3 = 8;
+constexpr int CWG3 = 1024;
+
+struct CLev {
+    Oct g;
+    int npt;
+    const double *st;
+    const double *w;
+    double *x, *b, *r;
+};
+
+struct CArgs {
+    CLev lv[MAXC3];
+    int top;
+    const double *chol;
+    const long long *cidx;
+    int nc;
+    int nu1, nu2, rescorr;
+};
+
+__device__ __forceinline__ long long nbr_rt(const Oct &g, int o, long long t, int dx, int dy, int dz)
 {
-    extern __shared__ double y[];
-    for (int r = threadIdx.x; r < n; r += 256) y[r] = b[idx[r]];
+    const int ox = (o & 1) + dx, oy = ((o >> 1) & 1) + dy, oz = (o >> 2) + dz;
+    const int on = (ox & 1) | ((oy & 1) << 1) | ((oz & 1) << 2);
+    return on * g.oct + t + (long long)(oz >> 1) * g.plane + (long long)(oy >> 1) * g.px + (ox >> 1);
+}
+
+// apply_at with the octant at run time (same expressions, same order)
+__device__ double apply_rt(const CLev &L, int o, long long t)
+{
+    const Oct &g = L.g;
+    const long long F = g.field;
+    const long long v = o * g.oct + t;
+    const double *st = L.st, *x = L.x;
+    if (L.npt == 7) {
+        const double *C = st, *W = st + F, *S = st + 2 * F, *B = st + 3 * F;
+        const long long xw = nbr_rt(g, o, t, -1, 0, 0), xe = nbr_rt(g, o, t, 1, 0, 0);
+        const long long ys = nbr_rt(g, o, t, 0, -1, 0), yn = nbr_rt(g, o, t, 0, 1, 0);
+        const long long zb = nbr_rt(g, o, t, 0, 0, -1), zt = nbr_rt(g, o, t, 0, 0, 1);
+        const double cv = C[v], wv = W[v], we = W[xe], sv = S[v], sn = S[yn], bv = B[v], bt = B[zt];
+        return cv * x[v] - wv * x[xw] - we * x[xe] - sv * x[ys] - sn * x[yn] - bv * x[zb] - bt * x[zt];
+    }
+    double s = st[v] * x[v];
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+        const long long qm = nbr_rt(g, o, t, dx, dy, dz), qp = nbr_rt(g, o, t, -dx, -dy, -dz);
+        s -= st[(1 + q) * F + v] * x[qm];
+        s -= st[(1 + q) * F + qp] * x[qp];
+    }
+    return s;
+}
+
+// collapsed levels are small (fields < 2^31 entries): 32-bit index arithmetic
+__device__ __forceinline__ void sub_coords32(const Oct &g, int t, int &a, int &b, int &c)
+{
+    a = t % g.px;
+    const int r = t / g.px;
+    b = r % g.my;
+    c = r / g.my;
+}
+
+__device__ __forceinline__ bool vertex_rt(const Oct &g, int o, long long t, int &i, int &j, int &k)
+{
+    int a, b, c;
+    sub_coords32(g, (int)t, a, b, c);
+    i = 2 * a + (o & 1);
+    j = 2 * b + ((o >> 1) & 1);
+    k = 2 * c + (o >> 2);
+    return a < g.mx && inner(g, i, j, k);
+}
+
+__device__ void wg_relax(const CLev &L, int sweeps)
+{
+    for (int it = 0; it < sweeps; ++it)
+        for (int o = 0; o < 8; ++o) {
+            for (int t = threadIdx.x; t < (int)L.g.oct; t += CWG3) {
+                int i, j, k;
+                if (!vertex_rt(L.g, o, t, i, j, k)) continue;
+                const long long v = o * L.g.oct + t;
+                const double s = apply_rt(L, o, t);
+                L.x[v] += (L.b[v] - s) / L.st[v];
+            }
+            __syncthreads();
+        }
+}
+
+__device__ void wg_residual(const CLev &L)
+{
+    const int oct = (int)L.g.oct;
+    for (int u = threadIdx.x; u < (int)L.g.field; u += CWG3) {
+        const int o = u / oct;
+        const int t = u - o * oct;
+        int i, j, k;
+        if (!vertex_rt(L.g, o, t, i, j, k)) {
+            L.r[u] = 0.0;
+            continue;
+        }
+        L.r[u] = L.b[u] - apply_rt(L, o, t);
+    }
+    __syncthreads();
+}
+
+__device__ void wg_restrict(const CLev &F, const CLev &C)
+{
+    const Oct &g = F.g, &c = C.g;
+    const int coct = (int)c.oct;
+    for (int u = threadIdx.x; u < (int)c.field; u += CWG3) {
+        const int oc = u / coct;
+        int ca, cb, cc;
+        sub_coords32(c, u - oc * coct, ca, cb, cc);
+        const int I = 2 * ca + (oc & 1), J = 2 * cb + ((oc >> 1) & 1), K = 2 * cc + (oc >> 2);
+        if (ca >= c.mx || !inner(c, I, J, K)) {
+            C.b[u] = 0.0;
+            continue;
+        }
+        double s = 0.0;
+        for (int ez = -1; ez <= 1; ++ez)
+            for (int ey = -1; ey <= 1; ++ey)
+                for (int ex = -1; ex <= 1; ++ex) {
+                    const int pi = 2 * I + ex, pj = 2 * J + ey, pk = 2 * K + ez;
+                    const int mI = (ex == -1 ? 1 : 0) | (ey == -1 ? 2 : 0) | (ez == -1 ? 4 : 0);
+                    s += weight_on(g, F.w, pi, pj, pk, mI) * F.r[vid(g, pi, pj, pk)];
+                }
+        C.b[u] = s;
+    }
+    // the coarse iterate starts at zero
+    for (long long u = threadIdx.x; u < c.field; u += CWG3) C.x[u] = 0.0;
+    __syncthreads();
+}
+
+__device__ void wg_interp(const CLev &F, const CLev &C, int rescorr)
+{
+    const Oct &g = F.g, &c = C.g;
+    const int oct = (int)g.oct;
+    for (int u = threadIdx.x; u < (int)g.field; u += CWG3) {
+        const int o = u / oct;
+        const int t = u - o * oct;
+        int i, j, k;
+        if (!vertex_rt(g, o, t, i, j, k)) continue;
+        double s = 0.0;
+        for (int m = 0; m < 8; ++m) {
+            if (m & ~o) continue;
+            const double w = o == 0 ? 1.0 : F.w[(wbase(o) + wrank(o, m)) * g.oct + t];
+            s += w * C.x[vid(c, (i >> 1) + (m & 1), (j >> 1) + ((m >> 1) & 1), (k >> 1) + (m >> 2))];
+        }
+        double xv = F.x[u] + s;
+        if (o != 0 && rescorr) xv += F.r[u] / F.st[u];
+        F.x[u] = xv;
+    }
+    __syncthreads();
+}
+
+__device__ void wg_coarse(const CArgs &a, double *y)
+{
+    const int n = a.nc;
+    const double *Lf = a.chol;
+    for (int r = threadIdx.x; r < n; r += CWG3) y[r] = a.lv[0].b[a.cidx[r]];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
         const double yk = y[k] / Lf[(long long)k * n + k];
         __syncthreads();
         if (threadIdx.x == 0) y[k] = yk;
-        for (int r = k + 1 + threadIdx.x; r < n; r += 256) y[r] -= Lf[(long long)r * n + k] * yk;
+        for (int r = k + 1 + threadIdx.x; r < n; r += CWG3) y[r] -= Lf[(long long)r * n + k] * yk;
         __syncthreads();
     }
     for (int k = n - 1; k >= 0; --k) {
         const double yk = y[k] / Lf[(long long)k * n + k];
         __syncthreads();
         if (threadIdx.x == 0) y[k] = yk;
-        for (int r = threadIdx.x; r < k; r += 256) y[r] -= Lf[(long long)k * n + r] * yk;
+        for (int r = threadIdx.x; r < k; r += CWG3) y[r] -= Lf[(long long)k * n + r] * yk;
         __syncthreads();
     }
-    for (int r = threadIdx.x; r < n; r += 256) x[idx[r]] = y[r];
+    for (int r = threadIdx.x; r < n; r += CWG3) a.lv[0].x[a.cidx[r]] = y[r];
+    __syncthreads();
+}
+
+// levels 0..top: down (relax, residual, restrict), the coarse solve, up
+// (interpolate, relax).  The caller has set b and x of level top.
+__global__ __launch_bounds__(CWG3) void k3_collapse(CArgs a)
+{
+    extern __shared__ double y[];
+    for (int l = a.top; l >= 1; --l) {
+        wg_relax(a.lv[l], a.nu1);
+        wg_residual(a.lv[l]);
+        wg_restrict(a.lv[l], a.lv[l - 1]);
+    }
+    wg_coarse(a, y);
+    for (int l = 1; l <= a.top; ++l) {
+        wg_interp(a.lv[l], a.lv[l - 1], a.rescorr);
+        wg_relax(a.lv[l], a.nu2);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -755,6 +931,8 @@ constexpr int NPROF3 = 5;
 
 struct hipbmg3d_hier {
     int L = 0;
+    int lstar = 0;                      // levels 0..lstar run in one workgroup
+    double model_us[HIPBMG_MAX_LEVELS] = {0};
     Lev3 lv[HIPBMG_MAX_LEVELS];
     hipbmg_params prm;
     int nc = 0;
@@ -974,12 +1152,23 @@ hipbmg_status interp_from(hipbmg3d_hier *h, int l, int rescorr, hipStream_t s)
     return HIPBMG_OK;
 }
 
-hipbmg_status coarse_solve(hipbmg3d_hier *h, hipStream_t s)
+// levels 0..top in one workgroup (top = 0: the coarse solve alone)
+hipbmg_status collapse(hipbmg3d_hier *h, int top, hipStream_t s)
 {
-    const Lev3 &c = h->lv[0];
+    CArgs a{};
+    for (int l = 0; l <= top; ++l) {
+        const Lev3 &v = h->lv[l];
+        a.lv[l] = CLev{v.g, v.npt, v.st, v.w, v.x, v.b, v.r};
+    }
+    a.top = top;
+    a.chol = h->d_chol;
+    a.cidx = h->d_cidx;
+    a.nc = h->nc;
+    a.nu1 = h->prm.nu1;
+    a.nu2 = h->prm.nu2;
+    a.rescorr = h->prm.residual_correction;
     Mark mk(h, 4, s);
-    hipLaunchKernelGGL(k3_coarse, dim3(1), dim3(256), (size_t)std::max(h->nc, 1) * sizeof(double), s,
-                       (const double *)h->d_chol, (const long long *)h->d_cidx, h->nc, (const double *)c.b, c.x);
+    hipLaunchKernelGGL(k3_collapse, dim3(1), dim3(CWG3), (size_t)std::max(h->nc, 1) * sizeof(double), s, a);
     HIP3(hipGetLastError());
     return HIPBMG_OK;
 }
@@ -987,7 +1176,7 @@ hipbmg_status coarse_solve(hipbmg3d_hier *h, hipStream_t s)
 // Algorithm 1 on level l: x_l and b_l are the level's own fields
 hipbmg_status vcycle(hipbmg3d_hier *h, int l, hipStream_t s)
 {
-    if (l == 0) return coarse_solve(h, s);
+    if (l <= h->lstar) return collapse(h, l, s);
     ST3(relax(h, l, h->prm.nu1, s));
     ST3(residual(h, l, true, false, s));
     ST3(restrict_to(h, l, s));
@@ -1135,6 +1324,75 @@ hipbmg_status factor_coarsest(hipbmg3d_hier *h, hipStream_t s)
 
 bool odd_ok(int n) { return n >= 3 && (n & 1); }
 
+// mean time (ms) of `reps` repetitions of f on stream s, after one warm-up
+template <typename Fn>
+hipbmg_status time_ms(hipStream_t s, int reps, Fn f, double *ms)
+{
+    hipEvent_t e0, e1;
+    ST3(f());
+    HIP3(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail3(HIPBMG_EHIP, "hipEventCreate failed");
+    }
+    hipbmg_status st = HIPBMG_OK;
+    if (hipEventRecord(e0, s) != hipSuccess) st = fail3(HIPBMG_EHIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == HIPBMG_OK; ++r) st = f();
+    float t = 0.f;
+    if (st == HIPBMG_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        st = fail3(HIPBMG_EHIP, "event timing failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return st;
+}
+
+// The model's choice of l*.  For the levels up to 9^3-ish (l <= 3) both of a
+// level's terms are measured: its cost inside the workgroup as the growth of
+// the collapse launch from top = l-1 to top = l, and its grid-wide cost as one
+// eager visit of level l on top of the collapse of levels 0..l-1 minus that
+// collapse.  Larger levels take the model's formulas.  The levels hold zeros
+// while this runs, which the solve overwrites.
+hipbmg_status choose_collapse(hipbmg3d_hier *h, const hbmg::ModelLevel3 *ml, int lcap, hipStream_t s)
+{
+    const int L = h->L;
+    double t_us[HIPBMG_MAX_LEVELS];
+    hbmg::model3_choose(ml, L, h->prm.nu1, h->prm.nu2, h->nc, hbmg::model_params(), lcap, t_us);
+    const int m = std::min(3, lcap);
+    double tc[4] = {0}, tw[4] = {0}, tg[4] = {0};
+    for (int top = 0; top <= m; ++top)
+        ST3(time_ms(s, 5, [&]() { return collapse(h, top, s); }, &tc[top]));
+    for (int l = 1; l <= m; ++l) {
+        double t = 0.0;
+        h->lstar = l - 1;
+        const hipbmg_status st = time_ms(s, 5, [&]() { return vcycle(h, l, s); }, &t);
+        h->lstar = 0;
+        ST3(st);
+        tw[l] = 1e3 * (tc[l] - tc[l - 1]);
+        tg[l] = 1e3 * t - 1e3 * tc[l - 1];
+    }
+    int best = 0;
+    for (int ls = 0; ls <= lcap; ++ls) {
+        const hbmg::ModelParams &mp = hbmg::model_params();
+        double t = 1e3 * tc[0];
+        if (ls <= m) {
+            for (int l = 1; l < L; ++l) {
+                if (l <= m) t += l <= ls ? tw[l] : tg[l];
+                else t += hbmg::model3_grid_level_us(ml[l], h->prm.nu1, h->prm.nu2, mp);
+            }
+        } else {
+            // the model's path with its base and its small-level terms replaced by the measured ones
+            t += t_us[ls] - hbmg::model_base_us(h->nc, 8, mp);
+            for (int l = 1; l <= m; ++l) t += tw[l] - hbmg::model3_wg_level_us(ml[l], h->prm.nu1, h->prm.nu2, mp);
+        }
+        h->model_us[ls] = t;
+        if (t < h->model_us[best]) best = ls;
+    }
+    h->lstar = best;
+    return HIPBMG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1232,6 +1490,26 @@ extern "C" hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const d
         if (hipGetLastError() != hipSuccess) return bail(fail3(HIPBMG_EHIP, "setup kernel launch failed"));
     }
     if ((st = factor_coarsest(h, s)) != HIPBMG_OK) return bail(st);
+    // the collapse level: forced, or the model's argmin (section 3's model
+    // with 3D counts).  Its terms for the small levels are measured here on
+    // the hierarchy's own launches; larger levels use the process-wide
+    // calibrated machine parameters.
+    {
+        int lcap = std::min(L - 1, MAXC3 - 1);
+        while (lcap > 0 && h->lv[lcap].g.field >= (1LL << 31)) --lcap;   // 32-bit indices in the workgroup
+        hbmg::ModelLevel3 ml[HIPBMG_MAX_LEVELS];
+        for (int l = 0; l < L; ++l)
+            ml[l] = hbmg::ModelLevel3{h->lv[l].g.nx, h->lv[l].g.ny, h->lv[l].g.nz, h->lv[l].npt};
+        if (prm.collapse_level >= 0) {
+            if (prm.collapse_level > lcap)
+                return bail(fail3(HIPBMG_EINVAL, "collapse_level %d out of range (at most %d)", prm.collapse_level,
+                                  lcap));
+            hbmg::model3_choose(ml, L, prm.nu1, prm.nu2, h->nc, hbmg::model_params(), lcap, h->model_us);
+            h->lstar = prm.collapse_level;
+        } else if ((st = choose_collapse(h, ml, lcap, s)) != HIPBMG_OK) {
+            return bail(st);
+        }
+    }
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail3(HIPBMG_EHIP, "setup failed on the device"));
     (void)t0;
     *out = h;
@@ -1304,7 +1582,8 @@ extern "C" hipbmg_status hipbmg3d_solve(hipbmg3d_handle h, const double *b, doub
     if (info) {
         std::memset(info, 0, sizeof *info);
         info->levels = h->L;
-        info->collapse_level = 0;
+        info->collapse_level = h->lstar;
+        for (int l = 0; l < h->L && l < HIPBMG_MAX_LEVELS; ++l) info->model_us[l] = h->model_us[l];
     }
     hipbmg_status rc = HIPBMG_OK;
     int cycles = 0;
@@ -1416,7 +1695,7 @@ extern "C" hipbmg_status hipbmg3d_op_coarse_solve(hipbmg3d_handle h, const doubl
     hipLaunchKernelGGL(k3_fill0, dim3((unsigned)std::min<long long>(nblk(c.g.field), 2048)), dim3(256), 0, s, c.x,
                        c.g.field);
     HIP3(hipGetLastError());
-    ST3(coarse_solve(h, s));
+    ST3(collapse(h, 0, s));
     ST3(from_oct(c.g, c.x, x, s));
     HIP3(hipStreamSynchronize(s));
     h->marks.clear();

@@ -358,4 +358,70 @@ double model_path_us(const ModelLevel *lv, int L, int nu1, int nu2, int nc, int 
     return t + p.alpha_launch_us;
 }
 
+// ---------------------------------------------------------------------------
+// 3D levels
+// ---------------------------------------------------------------------------
+namespace {
+
+// loaded FP64 words per vertex of one relaxation or residual (stencil entries,
+// the iterate at every stencil point, b, one store)
+double words3_sweep(int npt) { return npt == 7 ? 16.0 : 56.0; }
+
+struct Kernels3 {
+    int n;             // launches
+    double bytes[4];   // relaxation launch, residual, restriction + zeroing, interpolation
+    int nrelax;
+};
+
+Kernels3 kernels3(const ModelLevel3 &lv, int nu1, int nu2)
+{
+    const double nv = (double)lv.nx * lv.ny * lv.nz;
+    Kernels3 k;
+    const int per = lv.npt == 7 ? 4 : 8;
+    k.nrelax = (nu1 + nu2) * per;
+    k.n = k.nrelax + 4;
+    k.bytes[0] = nv * words3_sweep(lv.npt) * 8.0 / per;
+    k.bytes[1] = nv * words3_sweep(lv.npt) * 8.0;
+    k.bytes[2] = nv * (54.0 / 8.0 + 1.0 / 8.0) * 8.0;   // 27 (r, weight) pairs per coarse vertex; zeroing
+    k.bytes[3] = nv * 8.25 * 8.0;                       // x in and out, r, C, 3.25 weights, x_c
+    return k;
+}
+
+}  // namespace
+
+double model3_grid_level_us(const ModelLevel3 &lv, int nu1, int nu2, const ModelParams &p)
+{
+    const Kernels3 k = kernels3(lv, nu1, nu2);
+    // the level's working set: stencil planes, x, b, r and the weights onto it
+    const double ws = (double)lv.nx * lv.ny * lv.nz * ((lv.npt == 7 ? 4.0 : 14.0) + 3.0 + 3.25) * 8.0;
+    const double beta = ws > p.cache_bytes ? p.beta_hbm_us_per_B : p.beta_cache_us_per_B;
+    const double t0 = p.t0_dn_us[0];
+    // the zeroing launch moves little; count it as its fixed cost
+    return k.nrelax * (t0 + k.bytes[0] * beta) + (t0 + k.bytes[1] * beta) + (2.0 * t0 + k.bytes[2] * beta) +
+           (t0 + k.bytes[3] * beta);
+}
+
+double model3_wg_level_us(const ModelLevel3 &lv, int nu1, int nu2, const ModelParams &p)
+{
+    const Kernels3 k = kernels3(lv, nu1, nu2);
+    const int phases = (nu1 + nu2) * 8 + 4;
+    const double bytes = (nu1 + nu2) * 8 * (k.bytes[1] / 8.0) + k.bytes[1] + k.bytes[2] + k.bytes[3];
+    return phases * p.alpha_bar_us[0][1] + bytes * p.beta_wg_us_per_B[0][1];
+}
+
+int model3_choose(const ModelLevel3 *lv, int L, int nu1, int nu2, int nc, const ModelParams &p, int lcap,
+                  double *t_us)
+{
+    int best = 0;
+    const int top = L - 1 < lcap ? L - 1 : lcap;
+    for (int ls = 0; ls <= top; ++ls) {
+        double t = model_base_us(nc, 8, p);
+        for (int l = 1; l < L; ++l)
+            t += l > ls ? model3_grid_level_us(lv[l], nu1, nu2, p) : model3_wg_level_us(lv[l], nu1, nu2, p);
+        t_us[ls] = t;
+        if (t < t_us[best]) best = ls;
+    }
+    return best;
+}
+
 }  // namespace hbmg

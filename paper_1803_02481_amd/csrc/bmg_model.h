@@ -132,4 +132,21 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
                            const ModelParams &p);
 double model_wg_level_us(const ModelLevel &lv, int nu1, int nu2, int word, const ModelParams &p);
 
+// The same model for 3D hierarchies (section 3's terms with 3D counts).  A
+// grid-wide level launches one kernel per colour and relaxation (four per
+// relaxation on a 7-point level, whose colours fall into four uncoupled
+// groups), the residual, the restriction, the zeroing of the coarse iterate
+// and the interpolation; each kernel costs its fixed cost t0 plus its loaded
+// bytes at the level's bandwidth (cache or HBM by working set).  A collapsed
+// level costs one barrier phase per kernel plus its bytes at the one-workgroup
+// bandwidth from global memory.  The collapse launch adds model_base_us.
+struct ModelLevel3 {
+    int nx, ny, nz, npt;
+};
+double model3_grid_level_us(const ModelLevel3 &lv, int nu1, int nu2, const ModelParams &p);
+double model3_wg_level_us(const ModelLevel3 &lv, int nu1, int nu2, const ModelParams &p);
+// t_us[l*] for l* in [0, min(L-1, lcap)]; returns the argmin
+int model3_choose(const ModelLevel3 *lv, int L, int nu1, int nu2, int nc, const ModelParams &p, int lcap,
+                  double *t_us);
+
 }  // namespace hbmg

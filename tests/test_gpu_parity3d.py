@@ -232,3 +232,29 @@ def test_graph_replay_is_bitwise_the_eager_cycle():
         assert i_g.history() == i_e.history(), rep
         graph.smooth(graph.L - 1, g(b), g(np.zeros((33, 17, 17))), 1)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape,kind", [((33, 33, 33), "lognormal"), ((17, 33, 65), "blocks")])
+def test_collapse_level_leaves_the_iteration_bitwise_unchanged(shape, kind):
+    # levels 0..l* in one workgroup do the grid-wide kernels' arithmetic in
+    # the same order: iterate and history are identical for every l*
+    D, b = problem(shape, 55, kind)
+    planes = g(O.fv7(D))
+    ref = None
+    L = HB.Hierarchy3(planes).L
+    for ls in range(L):
+        h = HB.Hierarchy3(planes, collapse_level=ls)
+        u, info = h.solve(g(b))
+        assert info.collapse_level == ls
+        if ref is None:
+            ref = (u, info.history())
+        else:
+            assert torch.equal(u, ref[0]), ls
+            assert info.history() == ref[1], ls
+    with pytest.raises(HB.HipBMGError) as e:
+        HB.Hierarchy3(planes, collapse_level=L)
+    assert e.value.status == HB.EINVAL
+    # the model's choice is one of them and reports its predictions
+    u, info = HB.Hierarchy3(planes).solve(g(b))
+    assert 0 <= info.collapse_level < L and torch.equal(u, ref[0])
+    assert all(info.model_us[l] > 0 for l in range(L))
