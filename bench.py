@@ -49,6 +49,23 @@ def measured_traffic(kernel):
     return t.get("hbm_bytes_per_launch")
 
 
+def measured_traffic3d():
+    """HBM bytes of one 3D finest relaxation sweep from the committed counter
+    summary, if it was taken on the current 3D source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic3d.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    with open(os.path.join(ROOT, "paper_1803_02481_amd", "csrc", "bmg3d.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if t.get("source_sha") != sha:
+        return None
+    return t.get("sweep_hbm_bytes")
+
+
 def time_solves(hier, b, steps, warmup, torch):
     u = torch.zeros_like(b)
     info = None
@@ -496,17 +513,31 @@ def main():
         sweep_s = 4 * ms_r / n_r / 1e3
         bytes_sweep = 56.0 * m3 ** 3   # x read+written, b, C, W, S, B per vertex
         ach3 = bytes_sweep / sweep_s / 1e9
+        # each forced collapse level l* (levels 0..l* in one workgroup) against
+        # the model's prediction; the largest levels are left out (seconds per solve)
+        sweep3 = []
+        for ls in range(min(5, i3.levels)):
+            hs = HB.Hierarchy3(p3, collapse_level=ls)
+            hs.solve(b3, tol=TOL)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, isw = hs.solve(b3, tol=TOL)
+            torch.cuda.synchronize()
+            sweep3.append({"collapse_level": ls, "measured_us_per_cycle": 1e6 * (time.perf_counter() - t0) / isw.cycles,
+                           "model_us_per_cycle": i3.model_us[ls]})
+            del hs
         extra["next_3d"] = {
             "workload": "%d^3 vertex 3D diffusion, D on 8^3-cell blocks log10 D~U[-2,2] (seed 51), f~U[-1,1] "
                         "(seed 53), 7-point FV, V(2,1), eight-colour GS, 27-point Galerkin levels, to rel. "
                         "residual 1e-10, FP64" % m3,
             "n": m3, "value": 1.0 / el3, "unit": "solves/s", "ms_per_solve": 1e3 * el3,
             "cycles": i3.cycles, "ms_per_cycle": 1e3 * el3 / i3.cycles, "relres": i3.relres,
-            "levels": i3.levels, "setup_ms": 1e3 * t_setup3,
+            "levels": i3.levels, "setup_ms": 1e3 * t_setup3, "collapse_level": i3.collapse_level,
+            "collapse_sweep": sweep3,
             "kernel_ms_per_cycle": {k: v[0] / i3.cycles for k, v in pr3.items()},
             "roofline": {"bound": "hbm", "kernel": "finest relaxation sweep (k3_gs7g<0..3>)",
                          "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
-                         "traffic": None, "algorithmic_bytes_per_sweep": bytes_sweep,
+                         "traffic": measured_traffic3d(), "algorithmic_bytes_per_sweep": bytes_sweep,
                          "avg_sweep_us": sweep_s * 1e6},
         }
         log("bench: 3D %.2f solves/s (%d cycles, %.3f ms/cycle), finest sweep %.1f us = %.0f GB/s algorithmic"

@@ -93,6 +93,17 @@ __host__ __device__ inline int wrank(int o, int m)
 
 constexpr int NWSLOT = 26;
 
+// Logical block of hardware block b in a grid of nb blocks (nb a multiple of
+// 8).  Workgroups are dealt to the eight XCDs round-robin (b mod 8), each with
+// its own L2; giving every XCD a contiguous range of logical blocks keeps the
+// rows and planes that neighbouring blocks re-read in one L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
+
 // sub-grid coordinates of thread t of an octant
 __device__ inline void sub_coords(const Oct &g, long long t, int &a, int &b, int &c)
 {
@@ -513,7 +524,7 @@ __device__ __forceinline__ void gs_point(const LArgs &a, long long t)
 template <int NPT, int O>
 __global__ __launch_bounds__(256) void k3_gs(LArgs a)
 {
-    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    const long long t = xcd_block(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
     gs_point<NPT, O>(a, t);
 }
@@ -526,7 +537,7 @@ __global__ __launch_bounds__(256) void k3_gs(LArgs a)
 template <int G>
 __global__ __launch_bounds__(256) void k3_gs7g(LArgs a)
 {
-    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    const long long t = xcd_block(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
     if (G == 0) {
         gs_point<7, 0>(a, t);
@@ -563,10 +574,11 @@ __device__ __forceinline__ double resid_at(const LArgs &a, long long t)
 template <int NPT, bool STORE, bool NORM>
 __global__ __launch_bounds__(256) void k3_resid(LArgs a)
 {
-    const long long t = (blockIdx.x >> 3) * 256LL + threadIdx.x;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long t = (lb >> 3) * 256LL + threadIdx.x;
     double sq = 0.0;
     if (t < a.g.oct) {
-        switch (blockIdx.x & 7) {
+        switch (lb & 7) {
         case 0: sq = resid_at<NPT, 0, STORE, NORM>(a, t); break;
         case 1: sq = resid_at<NPT, 1, STORE, NORM>(a, t); break;
         case 2: sq = resid_at<NPT, 2, STORE, NORM>(a, t); break;
@@ -630,8 +642,9 @@ __global__ __launch_bounds__(256) void k3_restrict(LArgs a)
     const Oct g = a.g, c = a.c;
     // blocks interleave the coarse octants: neighbouring coarse vertices,
     // which share fine support vertices, run together
-    const int oc = blockIdx.x & 7;
-    const long long ts = (blockIdx.x >> 3) * 256LL + threadIdx.x;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int oc = lb & 7;
+    const long long ts = (lb >> 3) * 256LL + threadIdx.x;
     if (ts >= c.oct) return;
     const long long t = oc * c.oct + ts;
     int ca, cb, cc;
@@ -675,7 +688,7 @@ __device__ __forceinline__ void interp_at(const LArgs &a, long long t)
 template <int NPT>
 __global__ __launch_bounds__(256) void k3_interp(LArgs a)
 {
-    const long long t = blockIdx.x * 256LL + threadIdx.x;
+    const long long t = xcd_block(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
     switch (blockIdx.y) {
     case 0: interp_at<NPT, 0>(a, t); break;
@@ -1043,7 +1056,7 @@ LArgs largs(const Lev3 &f, const Lev3 *c)
 
 hipError_t launch_gs_colour(int npt, int o, const LArgs &a, hipStream_t s)
 {
-    const dim3 grid(nblk(a.g.oct)), block(256);
+    const dim3 grid(round8(nblk(a.g.oct))), block(256);
 #define HB3_GS(N, O) hipLaunchKernelGGL((k3_gs<N, O>), grid, block, 0, s, a)
     if (npt == 7) {
         switch (o) {
@@ -1076,7 +1089,7 @@ hipbmg_status relax(hipbmg3d_hier *h, int l, int sweeps, hipStream_t s)
 {
     const Lev3 &f = h->lv[l];
     const LArgs a = largs(f, nullptr);
-    const dim3 grid(nblk(f.g.oct)), block(256);
+    const dim3 grid(round8(nblk(f.g.oct))), block(256);
     for (int it = 0; it < sweeps; ++it) {
         if (f.npt == 7) {
             for (int gq = 0; gq < 4; ++gq) {
@@ -1114,7 +1127,7 @@ hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream
     const Lev3 &f = h->lv[l];
     LArgs a = largs(f, nullptr);
     a.partials = h->d_part;
-    const dim3 grid(8 * nblk(f.g.oct)), block(256);
+    const dim3 grid(8 * nblk(f.g.oct)), block(256);   // a multiple of 8, octants interleaved
     Mark mk(h, l == h->L - 1 ? 1 : 4, s);
     if (f.npt == 7) {
         if (store && !norm) hipLaunchKernelGGL((k3_resid<7, true, false>), grid, block, 0, s, a);
@@ -1144,7 +1157,7 @@ hipbmg_status interp_from(hipbmg3d_hier *h, int l, int rescorr, hipStream_t s)
     const Lev3 &f = h->lv[l];
     LArgs a = largs(f, &h->lv[l - 1]);
     a.rescorr = rescorr;
-    const dim3 grid(nblk(f.g.oct), 8), block(256);
+    const dim3 grid(round8(nblk(f.g.oct)), 8), block(256);
     Mark mk(h, l == h->L - 1 ? 3 : 4, s);
     if (f.npt == 7) hipLaunchKernelGGL((k3_interp<7>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k3_interp<27>), grid, block, 0, s, a);
