@@ -481,12 +481,12 @@ __device__ __forceinline__ double apply_at(const Oct &g, const double *st, const
                      sn = ldc<NT>(S + yn), bv = ldc<NT>(B + v), bt = ldc<NT>(B + zt);
         return cv * x[v] - wv * x[xw] - we * x[xe] - sv * x[ys] - sn * x[yn] - bv * x[zb] - bt * x[zt];
     } else {
-        double s = st[v] * x[v];
+        double s = ldc<NT>(st + v) * x[v];
 #define HB3_PAIR(o, dx, dy, dz)                                                                      \
     {                                                                                                \
         const long long qm = nbr<O, dx, dy, dz>(g, t), qp = nbr<O, -(dx), -(dy), -(dz)>(g, t);      \
-        s -= st[(1 + o) * F + v] * x[qm];                                                            \
-        s -= st[(1 + o) * F + qp] * x[qp];                                                           \
+        s -= ldc<NT>(st + (1 + o) * F + v) * x[qm];                                                  \
+        s -= ldc<NT>(st + (1 + o) * F + qp) * x[qp];                                                 \
     }
         HB3_PAIR(0, -1, -1, -1) HB3_PAIR(1, 0, -1, -1) HB3_PAIR(2, 1, -1, -1)
         HB3_PAIR(3, -1, 0, -1) HB3_PAIR(4, 0, 0, -1) HB3_PAIR(5, 1, 0, -1)
