@@ -302,6 +302,31 @@ hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double 
 hipbmg_status hipbmg_calibrate(void *stream, double *out_host);
 
 /* Message for the calling thread's most recent failure ("" if none). */
+/* The paper's distributed V-cycle model in its own form (section 3), host
+ * only, no device calls.  D = 2 or 3 dimensions, L levels (0 coarsest),
+ * N_host [L][D] global grid points per level, P_host [L][D] processor grid
+ * per level (local sizes ceil(N/P)), ns stencil points, ncolors smoother
+ * colours, V(nu1,nu2), redundant = 1 if the coarse solution is not scattered
+ * back, alpha (s), beta (s/B), gamma (s/flop).  terms_host [L][6] (may be
+ * NULL): per level smoothing, residual, restriction, interpolation (the 2D
+ * and 3D interpolation cost equations), agglomeration (gather of level l-1's
+ * right-hand side, and scatter, when P shrinks from level l to l-1), and at
+ * level 0 the coarse solve (agglomeration onto one processor plus the
+ * Cholesky substitutions, (prod N^0)^2 gamma).  total_host: their sum,
+ * T_V-cycle. */
+hipbmg_status hipbmg_paper_model(int D, int L, const int *N_host, const int *P_host, int ns, int ncolors,
+                                 int nu1, int nu2, int redundant, double alpha, double beta, double gamma,
+                                 double *terms_host, double *total_host);
+
+/* The coarse processor grids the paper's redistribution search runs over
+ * (section 4, coarse processor grid enumeration): for a global coarse grid
+ * N_host [D] on processor grid P_host [D], start from 1 x ... x 1 and double
+ * one dimension at a time, the one whose agglomerated local size
+ * ceil(N_d / p_d) is largest among those still below P_d, stopping before P.
+ * grids_host [max][D]; *count_host = number written.  Host only. */
+hipbmg_status hipbmg_paper_enumerate(int D, const int *N_host, const int *P_host, int max, int *grids_host,
+                                     int *count_host);
+
 const char *hipbmg_last_error(void);
 
 #ifdef __cplusplus

@@ -1410,6 +1410,61 @@ extern "C" hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cel
     return HIPBMG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// the paper's distributed model (host only)
+// ---------------------------------------------------------------------------
+extern "C" hipbmg_status hipbmg_paper_model(int D, int L, const int *N_host, const int *P_host, int ns, int ncolors,
+                                            int nu1, int nu2, int redundant, double alpha, double beta, double gamma,
+                                            double *terms_host, double *total_host)
+{
+    if (!N_host || !P_host || !total_host) return fail(HIPBMG_EINVAL, "null argument");
+    if ((D != 2 && D != 3) || L < 1 || L > HIPBMG_MAX_LEVELS || ns < 1 || ncolors < 1 || nu1 < 0 || nu2 < 0)
+        return fail(HIPBMG_EINVAL, "bad model arguments");
+    for (int i = 0; i < L * D; ++i)
+        if (N_host[i] < 1 || P_host[i] < 1) return fail(HIPBMG_EINVAL, "sizes and processor counts must be >= 1");
+    const PaperMachine m{alpha, beta, gamma};
+    double total = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const int *N = N_host + l * D, *P = P_host + l * D;
+        int n[3], nc[3];
+        for (int d = 0; d < D; ++d) n[d] = (N[d] + P[d] - 1) / P[d];
+        double t[6] = {0, 0, 0, 0, 0, 0};
+        if (l == 0) {
+            // agglomeration of the coarsest grid onto one processor, then the
+            // Cholesky substitutions (the factor is computed at setup)
+            int one[3] = {1, 1, 1};
+            double nn = 1.0;
+            for (int d = 0; d < D; ++d) nn *= N[d];
+            t[5] = paper_agglomerate(D, N, P, one, redundant, m) + nn * nn * m.gamma;
+        } else {
+            const int *Nc = N_host + (l - 1) * D, *Pc = P_host + (l - 1) * D;
+            for (int d = 0; d < D; ++d) nc[d] = (Nc[d] + Pc[d] - 1) / Pc[d];
+            t[0] = paper_smooth(D, n, ns, ncolors, nu1, nu2, m);
+            t[1] = paper_residual(D, n, ns, m);
+            t[2] = paper_restrict(D, n, ns, m);
+            t[3] = paper_interp(D, n, nc, m);
+            // the coarse right-hand side is gathered when level l-1 runs on fewer processors
+            t[4] = paper_agglomerate(D, Nc, P, Pc, redundant, m);
+        }
+        for (int k = 0; k < 6; ++k) total += t[k];
+        if (terms_host)
+            for (int k = 0; k < 6; ++k) terms_host[l * 6 + k] = t[k];
+    }
+    *total_host = total;
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_paper_enumerate(int D, const int *N_host, const int *P_host, int max,
+                                                int *grids_host, int *count_host)
+{
+    if (!N_host || !P_host || !grids_host || !count_host) return fail(HIPBMG_EINVAL, "null argument");
+    if (D < 1 || D > 3 || max < 0) return fail(HIPBMG_EINVAL, "bad arguments");
+    for (int d = 0; d < D; ++d)
+        if (N_host[d] < 1 || P_host[d] < 1) return fail(HIPBMG_EINVAL, "sizes and processor counts must be >= 1");
+    *count_host = paper_enumerate(D, N_host, P_host, max, grids_host);
+    return HIPBMG_OK;
+}
+
 extern "C" hipbmg_status hipbmg_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx,
                                           double hy, double *coeffs_out, void *stream)
 {

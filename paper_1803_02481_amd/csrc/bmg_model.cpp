@@ -424,4 +424,92 @@ int model3_choose(const ModelLevel3 *lv, int L, int nu1, int nu2, int nc, const 
     return best;
 }
 
+// ---------------------------------------------------------------------------
+// the paper's distributed model (section 3) and grid enumeration (section 4)
+// ---------------------------------------------------------------------------
+namespace {
+double prod(int D, const int *n)
+{
+    double p = 1.0;
+    for (int d = 0; d < D; ++d) p *= n[d];
+    return p;
+}
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+}  // namespace
+
+// 2 D messages of alpha and, per dimension, two faces of n_d doubles
+double paper_exchange(int D, const int *n, const PaperMachine &m)
+{
+    double faces = 0.0;
+    for (int d = 0; d < D; ++d) faces += n[d];
+    return 2.0 * D * m.alpha + 2.0 * faces * 8.0 * m.beta;
+}
+
+// 2 ns flops per point and relaxation; one exchange per colour and relaxation
+double paper_smooth(int D, const int *n, int ns, int ncolors, int nu1, int nu2, const PaperMachine &m)
+{
+    return 2.0 * ns * prod(D, n) * (nu1 + nu2) * m.gamma + ncolors * (nu1 + nu2) * paper_exchange(D, n, m);
+}
+
+double paper_residual(int D, const int *n, int ns, const PaperMachine &m)
+{
+    return 2.0 * ns * prod(D, n) * m.gamma + paper_exchange(D, n, m);
+}
+
+// restriction needs no halo
+double paper_restrict(int D, const int *n, int ns, const PaperMachine &m)
+{
+    return 2.0 * ns * prod(D, n) * m.gamma;
+}
+
+// injection at every fine point, then per coarse point the edge, face and
+// cell formulas (5 and 9 flops in 2D), and the boundary lines and planes of
+// the coarse block; one exchange
+double paper_interp(int D, const int *n, const int *nc, const PaperMachine &m)
+{
+    double flops;
+    if (D == 2) {
+        flops = prod(2, n) + 20.0 * prod(2, nc) + 6.0 * ((double)nc[0] + nc[1]);
+    } else {
+        flops = prod(3, n) + 60.0 * prod(3, nc) + 15.0 * (double)nc[0] * nc[2] + 6.0 * (double)nc[1] * nc[2] +
+                (double)nc[2];
+    }
+    return flops * m.gamma + paper_exchange(D, n, m);
+}
+
+// a processor block of the finer grid sends its pieces to one coarse
+// processor: a binomial gather of log2 p_block messages and the block's data
+double paper_agglomerate(int D, const int *N, const int *pf, const int *pc, int redundant, const PaperMachine &m)
+{
+    bool shrinks = false;
+    for (int d = 0; d < D; ++d) shrinks = shrinks || pf[d] > pc[d];
+    if (!shrinks) return 0.0;
+    double pblock = 1.0, nblock = 1.0;
+    for (int d = 0; d < D; ++d) {
+        pblock *= ceil_div(pf[d], pc[d]);
+        nblock *= ceil_div(N[d], pc[d]);
+    }
+    const double gather = std::ceil(std::log2(pblock)) * m.alpha + nblock * (pblock - 1.0) / pblock * 8.0 * m.beta;
+    return gather + (redundant ? 0.0 : gather);
+}
+
+int paper_enumerate(int D, const int *N, const int *P, int max, int *grids)
+{
+    int p[4] = {1, 1, 1, 1};
+    int count = 0;
+    for (;;) {
+        bool full = true;
+        for (int d = 0; d < D; ++d) full = full && p[d] >= P[d];
+        if (full || count >= max) break;
+        for (int d = 0; d < D; ++d) grids[count * D + d] = p[d];
+        ++count;
+        // refine the dimension with the largest agglomerated local size that can still grow
+        int best = -1;
+        for (int d = 0; d < D; ++d)
+            if (p[d] < P[d] && (best < 0 || ceil_div(N[d], p[d]) > ceil_div(N[best], p[best]))) best = d;
+        p[best] = std::min(2 * p[best], P[best]);
+    }
+    return count;
+}
+
 }  // namespace hbmg

@@ -149,4 +149,31 @@ double model3_wg_level_us(const ModelLevel3 &lv, int nu1, int nu2, const ModelPa
 int model3_choose(const ModelLevel3 *lv, int L, int nu1, int nu2, int nc, const ModelParams &p, int lcap,
                   double *t_us);
 
+// ---------------------------------------------------------------------------
+// The paper's distributed model in its own form (section 3) and its processor
+// grid enumeration (section 4): what the redistribution search runs over when
+// the levels are spread over processors (here: GPUs), written out from the
+// equations.  Levels are numbered as in the paper, 0 coarsest.
+// ---------------------------------------------------------------------------
+struct PaperMachine {
+    double alpha, beta, gamma;   // seconds, seconds per byte, seconds per flop
+};
+// halo exchange of width 1 in D dimensions over the local sizes n[0..D-1]
+double paper_exchange(int D, const int *n, const PaperMachine &m);
+double paper_smooth(int D, const int *n, int ns, int ncolors, int nu1, int nu2, const PaperMachine &m);
+double paper_residual(int D, const int *n, int ns, const PaperMachine &m);
+double paper_restrict(int D, const int *n, int ns, const PaperMachine &m);
+// interpolation and correction from the coarse local sizes nc to the fine
+// local sizes n (D = 2 or 3: the two interpolation cost equations)
+double paper_interp(int D, const int *n, const int *nc, const PaperMachine &m);
+// gather of the right-hand side (and scatter of the solution unless
+// redundant) when the processor grid shrinks from pf to pc with the coarse
+// global sizes N (0 if it does not shrink)
+double paper_agglomerate(int D, const int *N, const int *pf, const int *pc, int redundant, const PaperMachine &m);
+// Coarse processor grids for a global coarse grid N on processor grid P:
+// start from 1 x ... x 1 and double, one dimension at a time, the dimension
+// whose agglomerated local size ceil(N_d / p_d) is largest among those below
+// P_d, stopping before P itself.  Returns the count (at most max).
+int paper_enumerate(int D, const int *N, const int *P, int max, int *grids);
+
 }  // namespace hbmg

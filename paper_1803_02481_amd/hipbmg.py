@@ -79,6 +79,11 @@ _SIGS = {
                                   ctypes.POINTER(Info)]),
     "hipbmg_destroy_batched": (_I, [_VP]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
+    "hipbmg_paper_model": (_I, [_I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, _I, _I, _I, _I,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_paper_enumerate": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, ctypes.POINTER(_I),
+                                    ctypes.POINTER(_I)]),
     # 3D path (include/hipbmg3d.h)
     "hipbmg3d_fv7_from_cells": (_I, [_I, _I, _I, _VP, _VP, _VP]),
     "hipbmg3d_setup": (_I, [_I, _I, _I, _I, _VP, ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
@@ -524,3 +529,34 @@ class Hierarchy3:
             _check(lib().hipbmg3d_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
             out[name] = (ms.value, n.value)
         return out
+
+
+# --------------------------------------------------------------------------
+# the paper's distributed model (host only)
+# --------------------------------------------------------------------------
+PAPER_TERMS = ("smooth", "residual", "restrict", "interp", "agglomerate", "cgsolve")
+
+
+def paper_model(N, P, ns, ncolors=4, nu1=2, nu2=1, redundant=0, alpha=0.65e-6, beta=5.65e-9, gamma=0.44e-9):
+    """T_V-cycle of the paper's model (section 3).  N, P: per level (0 coarsest)
+    global grid points and processor grid, each a list of D-tuples.  Returns
+    (total seconds, [per-level dict of the six terms])."""
+    L, D = len(N), len(N[0])
+    Na = (ctypes.c_int * (L * D))(*[int(v) for row in N for v in row])
+    Pa = (ctypes.c_int * (L * D))(*[int(v) for row in P for v in row])
+    terms = (ctypes.c_double * (L * 6))()
+    total = ctypes.c_double()
+    _check(lib().hipbmg_paper_model(D, L, Na, Pa, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma, terms,
+                                    ctypes.byref(total)))
+    return total.value, [dict(zip(PAPER_TERMS, terms[6 * l: 6 * l + 6])) for l in range(L)]
+
+
+def paper_enumerate(N, P, max_grids=64):
+    """Coarse processor grids of section 4's enumeration, [(p_0, .., p_{D-1}), ...]."""
+    D = len(N)
+    Na = (ctypes.c_int * D)(*[int(v) for v in N])
+    Pa = (ctypes.c_int * D)(*[int(v) for v in P])
+    g = (ctypes.c_int * (max_grids * D))()
+    cnt = ctypes.c_int()
+    _check(lib().hipbmg_paper_enumerate(D, Na, Pa, max_grids, g, ctypes.byref(cnt)))
+    return [tuple(g[k * D:(k + 1) * D]) for k in range(cnt.value)]

@@ -1,0 +1,129 @@
+"""CPU pins of the paper's own distributed model (section 3) and processor
+grid enumeration (section 4), through the library's host-only C entry points:
+the enumeration table the paper prints, the size of the brute-force search
+space it derives (T(h) = 2^h = n_p), and the printed cost equations, the 3D
+interpolation cost among them, term by term."""
+import math
+import os
+
+import pytest
+
+from paper_1803_02481_amd import hipbmg as HB
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1803_02481_amd",
+                   "libhipbmg.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhipbmg.so not built")
+
+
+def read_table(name):
+    meta, rows = {}, []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line.startswith("# ") and len(line.split()) >= 3 and line.split()[1].isidentifier() and \
+                all(t.replace(".", "").replace("e-", "").isdigit() for t in line.split()[2:]):
+            meta[line.split()[1]] = [int(t) for t in line.split()[2:]]
+        elif line and not line.startswith("#"):
+            rows.append(line.split())
+    return meta, rows
+
+
+def test_enumeration_reproduces_the_papers_table():
+    meta, rows = read_table("paper_enumeration_table.txt")
+    N, P = meta["global_coarse"], meta["processor_grid"]
+    grids = HB.paper_enumerate(N, P)
+    want = [(int(r[0]), int(r[1])) for r in rows]
+    assert grids == want
+    for (px, py), r in zip(grids, rows):
+        assert (math.ceil(N[0] / px), math.ceil(N[1] / py)) == (int(r[2]), int(r[3]))
+    # at most ceil(log2 n_p) grids
+    assert len(grids) <= math.ceil(math.log2(P[0] * P[1]))
+
+
+@pytest.mark.parametrize("N,P", [((1136, 71), (16, 8)), ((36352, 2272), (64, 32)), ((513, 257, 129), (8, 4, 4))])
+def test_brute_force_search_space_has_n_p_paths(N, P):
+    # from the top grid every coarser enumerated grid may come next or the
+    # search may stop: T(h) = sum_{k<h} T(k) + 1 paths over h grids, = 2^h,
+    # and with a refinement factor of 2 the enumeration has h = log2(n_p)
+    grids = HB.paper_enumerate(N, P)
+    h = len(grids)
+
+    def paths(k):   # paths starting below the k-th coarsest grid
+        return 1 + sum(paths(j) for j in range(k))
+
+    assert paths(h) == 2 ** h == math.prod(P)
+
+
+def machine():
+    _, rows = read_table("paper_machine_parameters.txt")
+    return {k: float(v) for k, v in rows}
+
+
+def one_level(D, n, nc, ns=9, ncolors=4, nu1=2, nu2=1, **m):
+    # level 1 with local sizes n over a coarsest level 0 with local sizes nc,
+    # both on one processor per dimension
+    N = [tuple(nc), tuple(n)]
+    P = [(1,) * D, (1,) * D]
+    total, terms = HB.paper_model(N, P, ns, ncolors, nu1, nu2, **m)
+    return terms[1], terms[0]
+
+
+def test_interpolation_cost_equations_2d_and_3d():
+    # flop counts with gamma = 1 and no communication
+    t, _ = one_level(2, (568, 71), (284, 36), alpha=0.0, beta=0.0, gamma=1.0)
+    assert t["interp"] == 568 * 71 + 20 * 284 * 36 + 6 * (284 + 36)
+    t, _ = one_level(3, (65, 33, 17), (33, 17, 9), alpha=0.0, beta=0.0, gamma=1.0)
+    assert t["interp"] == 65 * 33 * 17 + 60 * 33 * 17 * 9 + 15 * 33 * 9 + 6 * 17 * 9 + 9
+
+
+def test_component_equations_with_the_blue_waters_parameters():
+    m = machine()
+    n, nc = (568, 71), (284, 36)
+    t, t0 = one_level(2, n, nc, **m)
+    exch = 2 * 2 * m["alpha"] + 2 * (568 + 71) * 8 * m["beta"]
+    work = 2 * 9 * 568 * 71 * m["gamma"]
+    assert t["restrict"] == pytest.approx(work, rel=1e-15)
+    assert t["residual"] == pytest.approx(work + exch, rel=1e-15)
+    assert t["smooth"] == pytest.approx(3 * work + 4 * 3 * exch, rel=1e-15)
+    assert t["interp"] == pytest.approx((568 * 71 + 20 * 284 * 36 + 6 * 320) * m["gamma"] + exch, rel=1e-15)
+    assert t["agglomerate"] == 0.0
+    # the coarse solve on one processor: (prod N^0)^2 gamma
+    assert t0["cgsolve"] == pytest.approx((284 * 36) ** 2 * m["gamma"], rel=1e-15)
+    # 3D: three dimensions of halo
+    t3, _ = one_level(3, (64, 32, 16), (32, 16, 8), ns=27, ncolors=8, **m)
+    exch3 = 2 * 3 * m["alpha"] + 2 * (64 + 32 + 16) * 8 * m["beta"]
+    assert t3["residual"] - t3["restrict"] == pytest.approx(exch3, rel=1e-12)
+    assert t3["smooth"] == pytest.approx(3 * t3["restrict"] + 8 * 3 * exch3, rel=1e-12)
+
+
+def test_agglomeration_is_a_binomial_gather_and_optional_scatter():
+    m = dict(alpha=1.0, beta=0.0, gamma=0.0)
+    # 64 x 32 -> 64 x 16: blocks of 2 processors, one message each way
+    N = [(100, 50), (200, 100)]
+    P = [(64, 16), (64, 32)]
+    _, terms = HB.paper_model(N, P, 9, **m)
+    assert terms[1]["agglomerate"] == 2.0                 # gather + scatter
+    _, terms = HB.paper_model(N, P, 9, redundant=1, **m)
+    assert terms[1]["agglomerate"] == 1.0                 # gather only
+    # 64 x 32 -> 4 x 1: blocks of 16 x 32 = 512 processors, ceil(log2 512) = 9 messages
+    P = [(4, 1), (64, 32)]
+    _, terms = HB.paper_model(N, P, 9, redundant=1, **m)
+    assert terms[1]["agglomerate"] == 9.0
+    # the data term: the block's coarse local problem times (p_block - 1)/p_block doubles
+    mb = dict(alpha=0.0, beta=1.0, gamma=0.0)
+    _, terms = HB.paper_model(N, P, 9, redundant=1, **mb)
+    assert terms[1]["agglomerate"] == pytest.approx(math.ceil(100 / 4) * math.ceil(50 / 1) * 511 / 512 * 8)
+    # no shrink, no cost
+    P = [(64, 32), (64, 32)]
+    _, terms = HB.paper_model(N, P, 9, **m)
+    assert terms[1]["agglomerate"] == 0.0
+
+
+def test_host_entry_points_validate():
+    import ctypes
+    lib = HB.lib()
+    one = (ctypes.c_int * 2)(1, 1)
+    tot = ctypes.c_double()
+    assert lib.hipbmg_paper_model(4, 1, one, one, 9, 4, 2, 1, 0, 1.0, 1.0, 1.0, None, ctypes.byref(tot)) == HB.EINVAL
+    zero = (ctypes.c_int * 2)(0, 1)
+    assert lib.hipbmg_paper_model(2, 1, zero, one, 9, 4, 2, 1, 0, 1.0, 1.0, 1.0, None, ctypes.byref(tot)) == HB.EINVAL
