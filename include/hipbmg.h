@@ -327,6 +327,30 @@ hipbmg_status hipbmg_paper_model(int D, int L, const int *N_host, const int *P_h
 hipbmg_status hipbmg_paper_enumerate(int D, const int *N_host, const int *P_host, int max, int *grids_host,
                                      int *count_host);
 
+/* The redistribution search of section 4 over that model.  A state is a
+ * global grid and a processor grid.  Levels coarsen (N -> ceil(N/2)) while
+ * every local side ceil(N_d/p_d) exceeds `limit` (the coarsening limit) and
+ * every global side exceeds `coarsest`; at the limit the solve agglomerates
+ * onto one of the enumerated coarser processor grids; on 1 x ... x 1 the
+ * levels continue to `coarsest` and end in the Cholesky solve. */
+typedef struct {
+    int D, limit, coarsest, ns, ncolors, nu1, nu2, redundant;
+    double alpha, beta, gamma;
+} hipbmg_paper_setup;
+
+/* Cheapest redistribution path from fine global grid N_host [D] on processor
+ * grid P_host [D]: path_host [max_path][D] the grids after the first, ending
+ * with 1 x ... x 1, *len_host their number, *t_host the model time of one
+ * V-cycle along it (seconds).  Host only. */
+hipbmg_status hipbmg_paper_search(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
+                                  int max_path, int *path_host, int *len_host, double *t_host);
+
+/* Model time of one V-cycle along the given sequence of processor grids
+ * (path_host [len][D], the grids after the first); infinite if the sequence
+ * ends before 1 x ... x 1. */
+hipbmg_status hipbmg_paper_path_cost(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
+                                     const int *path_host, int len, double *t_host);
+
 const char *hipbmg_last_error(void);
 
 #ifdef __cplusplus

@@ -1465,6 +1465,48 @@ extern "C" hipbmg_status hipbmg_paper_enumerate(int D, const int *N_host, const 
     return HIPBMG_OK;
 }
 
+static hipbmg_status paper_setup_check(const hipbmg_paper_setup *st, const int *N, const int *P, PaperSetup *out)
+{
+    if (!st || !N || !P) return fail(HIPBMG_EINVAL, "null argument");
+    if ((st->D != 2 && st->D != 3) || st->limit < 1 || st->coarsest < 1 || st->ns < 1 || st->ncolors < 1 ||
+        st->nu1 < 0 || st->nu2 < 0)
+        return fail(HIPBMG_EINVAL, "bad model setup");
+    for (int d = 0; d < st->D; ++d)
+        if (N[d] < 1 || P[d] < 1) return fail(HIPBMG_EINVAL, "sizes and processor counts must be >= 1");
+    *out = PaperSetup{st->D,  st->limit, st->coarsest,  st->ns, st->ncolors,
+                      st->nu1, st->nu2,  st->redundant, PaperMachine{st->alpha, st->beta, st->gamma}};
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_paper_search(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
+                                             int max_path, int *path_host, int *len_host, double *t_host)
+{
+    PaperSetup ps;
+    const hipbmg_status st = paper_setup_check(setup, N_host, P_host, &ps);
+    if (st != HIPBMG_OK) return st;
+    if (!path_host || !len_host || !t_host || max_path < 1) return fail(HIPBMG_EINVAL, "null argument");
+    std::vector<std::vector<int>> path;
+    *t_host = paper_search(ps, N_host, P_host, &path);
+    if ((int)path.size() > max_path) return fail(HIPBMG_EINVAL, "path longer than max_path");
+    for (size_t k = 0; k < path.size(); ++k)
+        for (int d = 0; d < ps.D; ++d) path_host[k * ps.D + d] = path[k][d];
+    *len_host = (int)path.size();
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_paper_path_cost(const hipbmg_paper_setup *setup, const int *N_host,
+                                                const int *P_host, const int *path_host, int len, double *t_host)
+{
+    PaperSetup ps;
+    const hipbmg_status st = paper_setup_check(setup, N_host, P_host, &ps);
+    if (st != HIPBMG_OK) return st;
+    if ((!path_host && len > 0) || len < 0 || !t_host) return fail(HIPBMG_EINVAL, "null argument");
+    std::vector<std::vector<int>> seq(len);
+    for (int k = 0; k < len; ++k) seq[k].assign(path_host + k * ps.D, path_host + (k + 1) * ps.D);
+    *t_host = paper_path_cost(ps, N_host, P_host, seq);
+    return HIPBMG_OK;
+}
+
 extern "C" hipbmg_status hipbmg_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx,
                                           double hy, double *coeffs_out, void *stream)
 {

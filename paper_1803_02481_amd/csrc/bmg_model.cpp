@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <map>
 #include <queue>
 #include <vector>
 
@@ -510,6 +511,129 @@ int paper_enumerate(int D, const int *N, const int *P, int max, int *grids)
         p[best] = std::min(2 * p[best], P[best]);
     }
     return count;
+}
+
+namespace {
+
+using Grid = std::vector<int>;
+
+// one level on p from global N to its coarsening Nn (the coarse level on the same grid)
+double paper_level(const PaperSetup &s, const Grid &N, const Grid &Nn, const Grid &p)
+{
+    int n[3], nc[3];
+    for (int d = 0; d < s.D; ++d) {
+        n[d] = ceil_div(N[d], p[d]);
+        nc[d] = ceil_div(Nn[d], p[d]);
+    }
+    return paper_smooth(s.D, n, s.ns, s.ncolors, s.nu1, s.nu2, s.m) + paper_residual(s.D, n, s.ns, s.m) +
+           paper_restrict(s.D, n, s.ns, s.m) + paper_interp(s.D, n, nc, s.m);
+}
+
+bool at_one(const Grid &p)
+{
+    for (int v : p)
+        if (v != 1) return false;
+    return true;
+}
+
+// true while the level on p may coarsen once more
+bool coarsens(const PaperSetup &s, const Grid &N, const Grid &p, bool anywhere)
+{
+    for (int d = 0; d < s.D; ++d) {
+        if (N[d] <= s.coarsest) return false;
+        if (!anywhere && ceil_div(N[d], p[d]) <= s.limit) return false;
+    }
+    return true;
+}
+
+Grid halve(const Grid &N)
+{
+    Grid r(N.size());
+    for (size_t d = 0; d < N.size(); ++d) r[d] = ceil_div(N[d], 2);
+    return r;
+}
+
+// the levels on 1 x ... x 1 down to the coarsest and the Cholesky solve
+double paper_tail(const PaperSetup &s, Grid N)
+{
+    const Grid one(s.D, 1);
+    double t = 0.0;
+    while (coarsens(s, N, one, true)) {
+        const Grid Nn = halve(N);
+        t += paper_level(s, N, Nn, one);
+        N = Nn;
+    }
+    double nn = 1.0;
+    for (int v : N) nn *= v;
+    return t + nn * nn * s.m.gamma;
+}
+
+double paper_agg(const PaperSetup &s, const Grid &N, const Grid &pf, const Grid &pc)
+{
+    return paper_agglomerate(s.D, N.data(), pf.data(), pc.data(), s.redundant, s.m);
+}
+
+struct Searcher {
+    const PaperSetup &s;
+    std::map<std::pair<Grid, Grid>, std::pair<double, std::vector<Grid>>> memo;
+    // cheapest continuation from (N, p)
+    std::pair<double, std::vector<Grid>> go(Grid N, const Grid &p)
+    {
+        if (at_one(p)) return {paper_tail(s, N), {}};
+        double run = 0.0;
+        while (coarsens(s, N, p, false)) {
+            const Grid Nn = halve(N);
+            run += paper_level(s, N, Nn, p);
+            N = Nn;
+        }
+        const auto key = std::make_pair(N, p);
+        auto it = memo.find(key);
+        if (it == memo.end()) {
+            int grids[64 * 3];
+            const int cnt = paper_enumerate(s.D, N.data(), p.data(), 64, grids);
+            std::pair<double, std::vector<Grid>> best{std::numeric_limits<double>::infinity(), {}};
+            for (int k = 0; k < cnt; ++k) {
+                const Grid q(grids + k * s.D, grids + (k + 1) * s.D);
+                auto sub = go(N, q);
+                const double t = paper_agg(s, N, p, q) + sub.first;
+                if (t < best.first) {
+                    best.first = t;
+                    best.second.assign(1, q);
+                    best.second.insert(best.second.end(), sub.second.begin(), sub.second.end());
+                }
+            }
+            it = memo.emplace(key, best).first;
+        }
+        return {run + it->second.first, it->second.second};
+    }
+};
+
+}  // namespace
+
+double paper_search(const PaperSetup &s, const int *N, const int *P, std::vector<std::vector<int>> *path)
+{
+    Searcher se{s, {}};
+    auto r = se.go(Grid(N, N + s.D), Grid(P, P + s.D));
+    if (path) *path = r.second;
+    return r.first;
+}
+
+double paper_path_cost(const PaperSetup &s, const int *N0, const int *P, const std::vector<std::vector<int>> &seq)
+{
+    Grid N(N0, N0 + s.D), p(P, P + s.D);
+    double t = 0.0;
+    size_t k = 0;
+    for (;;) {
+        if (at_one(p)) return t + paper_tail(s, N);
+        while (coarsens(s, N, p, false)) {
+            const Grid Nn = halve(N);
+            t += paper_level(s, N, Nn, p);
+            N = Nn;
+        }
+        if (k >= seq.size()) return std::numeric_limits<double>::infinity();
+        t += paper_agg(s, N, p, seq[k]);
+        p = seq[k++];
+    }
 }
 
 }  // namespace hbmg

@@ -5,6 +5,8 @@
 
 #include "hipbmg.h"
 
+#include <vector>
+
 namespace hbmg {
 
 // One streaming kernel as the model sees it: the row-pair steps one wave
@@ -175,5 +177,20 @@ double paper_agglomerate(int D, const int *N, const int *pf, const int *pc, int 
 // whose agglomerated local size ceil(N_d / p_d) is largest among those below
 // P_d, stopping before P itself.  Returns the count (at most max).
 int paper_enumerate(int D, const int *N, const int *P, int max, int *grids);
+
+// The redistribution search of section 4 over the paper's model.  A state is
+// (global grid N, processor grid p).  A level on p coarsens N to ceil(N/2)
+// while every local side ceil(N_d/p_d) exceeds `limit` (the coarsening
+// limit) and N exceeds `coarsest`; at the limit the solve agglomerates onto
+// one of the enumerated coarser grids of (N, p).  On 1 x ... x 1 the levels
+// continue down to `coarsest` and end in the Cholesky solve.  The search
+// returns the cheapest path (the grids after the first, up to 1 x ... x 1)
+// and its model time; path_cost prices a given sequence of grids.
+struct PaperSetup {
+    int D, limit, coarsest, ns, ncolors, nu1, nu2, redundant;
+    PaperMachine m;
+};
+double paper_search(const PaperSetup &s, const int *N, const int *P, std::vector<std::vector<int>> *path);
+double paper_path_cost(const PaperSetup &s, const int *N, const int *P, const std::vector<std::vector<int>> &seq);
 
 }  // namespace hbmg

@@ -84,6 +84,10 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_double)]),
     "hipbmg_paper_enumerate": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, ctypes.POINTER(_I),
                                     ctypes.POINTER(_I)]),
+    "hipbmg_paper_search": (_I, [ctypes.c_void_p, ctypes.POINTER(_I), ctypes.POINTER(_I), _I,
+                                 ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_paper_path_cost": (_I, [ctypes.c_void_p, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                    ctypes.POINTER(_I), _I, ctypes.POINTER(ctypes.c_double)]),
     # 3D path (include/hipbmg3d.h)
     "hipbmg3d_fv7_from_cells": (_I, [_I, _I, _I, _VP, _VP, _VP]),
     "hipbmg3d_setup": (_I, [_I, _I, _I, _I, _VP, ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)]),
@@ -560,3 +564,42 @@ def paper_enumerate(N, P, max_grids=64):
     cnt = ctypes.c_int()
     _check(lib().hipbmg_paper_enumerate(D, Na, Pa, max_grids, g, ctypes.byref(cnt)))
     return [tuple(g[k * D:(k + 1) * D]) for k in range(cnt.value)]
+
+
+class PaperSetup(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int), ("limit", ctypes.c_int), ("coarsest", ctypes.c_int), ("ns", ctypes.c_int),
+                ("ncolors", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("redundant", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+def _paper_setup(D, limit, coarsest, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma):
+    return PaperSetup(D, limit, coarsest, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma)
+
+
+def paper_search(N, P, limit=9, coarsest=3, ns=9, ncolors=4, nu1=2, nu2=1, redundant=0, alpha=0.65e-6,
+                 beta=5.65e-9, gamma=0.44e-9):
+    """Cheapest redistribution path of section 4's search over the paper's
+    model: (model seconds per V-cycle, [processor grids after the first])."""
+    D = len(N)
+    st = _paper_setup(D, limit, coarsest, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma)
+    Na = (ctypes.c_int * D)(*N)
+    Pa = (ctypes.c_int * D)(*P)
+    path = (ctypes.c_int * (64 * D))()
+    ln = ctypes.c_int()
+    t = ctypes.c_double()
+    _check(lib().hipbmg_paper_search(ctypes.byref(st), Na, Pa, 64, path, ctypes.byref(ln), ctypes.byref(t)))
+    return t.value, [tuple(path[k * D:(k + 1) * D]) for k in range(ln.value)]
+
+
+def paper_path_cost(N, P, seq, limit=9, coarsest=3, ns=9, ncolors=4, nu1=2, nu2=1, redundant=0, alpha=0.65e-6,
+                    beta=5.65e-9, gamma=0.44e-9):
+    """Model seconds per V-cycle along the given processor grids (after the first)."""
+    D = len(N)
+    st = _paper_setup(D, limit, coarsest, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma)
+    Na = (ctypes.c_int * D)(*N)
+    Pa = (ctypes.c_int * D)(*P)
+    flat = [v for g in seq for v in g]
+    path = (ctypes.c_int * max(1, len(flat)))(*flat)
+    t = ctypes.c_double()
+    _check(lib().hipbmg_paper_path_cost(ctypes.byref(st), Na, Pa, path, len(seq), ctypes.byref(t)))
+    return t.value

@@ -78,7 +78,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     from paper_1803_02481_amd import hipbmg
     src = tmp_path / "layout.c"
     lines = ['#include <stdio.h>', '#include "hipbmg.h"', "int main(void) {"]
-    for cname, py in (("hipbmg_params", hipbmg.Params), ("hipbmg_info", hipbmg.Info)):
+    for cname, py in (("hipbmg_params", hipbmg.Params), ("hipbmg_info", hipbmg.Info),
+                      ("hipbmg_paper_setup", hipbmg.PaperSetup)):
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
         for f, _ in py._fields_:
             lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
@@ -90,7 +91,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
                    check=True)
     out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
                                                   text=True).stdout.splitlines())
-    for cname, py in (("hipbmg_params", hipbmg.Params), ("hipbmg_info", hipbmg.Info)):
+    for cname, py in (("hipbmg_params", hipbmg.Params), ("hipbmg_info", hipbmg.Info),
+                      ("hipbmg_paper_setup", hipbmg.PaperSetup)):
         assert int(out[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)

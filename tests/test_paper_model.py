@@ -127,3 +127,40 @@ def test_host_entry_points_validate():
     assert lib.hipbmg_paper_model(4, 1, one, one, 9, 4, 2, 1, 0, 1.0, 1.0, 1.0, None, ctypes.byref(tot)) == HB.EINVAL
     zero = (ctypes.c_int * 2)(0, 1)
     assert lib.hipbmg_paper_model(2, 1, zero, one, 9, 4, 2, 1, 0, 1.0, 1.0, 1.0, None, ctypes.byref(tot)) == HB.EINVAL
+
+
+def read_paths():
+    meta, rows = read_table("paper_redistribution_paths.txt")
+    paths = {}
+    for r in rows:
+        v = [int(t) for t in r]
+        paths[v[0]] = [tuple(v[1 + 2 * k: 3 + 2 * k]) for k in range((len(v) - 1) // 2)]
+    return meta, paths
+
+
+@pytest.mark.parametrize("limit", [8, 9, 12, 17])
+def test_search_selects_the_papers_path_for_its_weak_scaling_problem(limit):
+    # the search over the paper's model, with the Blue Waters parameters, a
+    # 9-point operator, four colours and V(2,1), picks the paper's path 1; the
+    # coarsening limit (a local side of 9 ends local coarsening in the
+    # enumeration example) is not printed, and the choice holds for 8..17
+    meta, paths = read_paths()
+    P, n = meta["processor_grid"], meta["local_problem"]
+    N = (P[0] * n[0], P[1] * n[1])
+    t, path = HB.paper_search(N, P, limit=limit, **machine())
+    assert path == paths[1]
+    # the path is the cheapest of the table's paths
+    for k, seq in paths.items():
+        assert HB.paper_path_cost(N, P, seq, limit=limit, **machine()) >= t * (1 - 1e-12), k
+
+
+def test_model_predicts_the_papers_speedup_over_all_to_one():
+    meta, paths = read_paths()
+    P, n = meta["processor_grid"], meta["local_problem"]
+    N = (P[0] * n[0], P[1] * n[1])
+    t0 = HB.paper_path_cost(N, P, paths[0], **machine())
+    t1 = HB.paper_path_cost(N, P, paths[1], **machine())
+    want = meta["speedup_path1_over_path0"][0]
+    assert 0.85 * want <= t0 / t1 <= 1.15 * want, t0 / t1
+    # a sequence that stops short of one processor has no coarse solve
+    assert HB.paper_path_cost(N, P, paths[1][:-1], **machine()) == math.inf
