@@ -136,6 +136,25 @@ def test_solve_history_matches_the_oracle(shape, kind, prm):
     assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
 
 
+def test_solve_from_a_27_point_finest_operator_matches_the_oracle():
+    # a 27-point finest operator (the oracle's first Galerkin level of a finer
+    # block medium) on a non-cubic grid: the whole solve cycle by cycle
+    fine = O.Hierarchy3(O.fv7(inputs.cells3_log10_blocks(33, 17, 33, block=4, seed=56)))
+    st = fine.stencil(fine.L - 2)
+    shape = st.shape[:3]
+    flat = st.reshape(shape + (27,))
+    planes = np.concatenate([flat[None, ..., 13]] + [-flat[None, ..., o] for o in range(13)])
+    b = inputs.load3_uniform(shape[2], shape[1], shape[0], seed=57)
+    ora = O.Hierarchy3(planes)
+    _, hist = ora.solve(b, tol=1e-10)
+    gpu = HB.Hierarchy3(g(planes))
+    u, info = gpu.solve(g(b), tol=1e-10)
+    h = np.array(info.history())
+    assert info.cycles == len(hist) and np.abs(h - hist).max() <= 1e-9 * hist.max()
+    r = ora.residual(ora.L - 1, b, c(u))
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+
+
 def test_edge_cases():
     # a 3^3 grid: one unknown, one level, the Cholesky solve alone
     D, b = problem((3, 3, 3), 46, "lognormal")
