@@ -1054,32 +1054,20 @@ LArgs largs(const Lev3 &f, const Lev3 *c)
     return a;
 }
 
-hipError_t launch_gs_colour(int npt, int o, const LArgs &a, hipStream_t s)
+// one colour of a 27-point level (7-point levels run the colour groups)
+hipError_t launch_gs_colour27(int o, const LArgs &a, hipStream_t s)
 {
     const dim3 grid(round8(nblk(a.g.oct))), block(256);
-#define HB3_GS(N, O) hipLaunchKernelGGL((k3_gs<N, O>), grid, block, 0, s, a)
-    if (npt == 7) {
-        switch (o) {
-        case 0: HB3_GS(7, 0); break;
-        case 1: HB3_GS(7, 1); break;
-        case 2: HB3_GS(7, 2); break;
-        case 3: HB3_GS(7, 3); break;
-        case 4: HB3_GS(7, 4); break;
-        case 5: HB3_GS(7, 5); break;
-        case 6: HB3_GS(7, 6); break;
-        default: HB3_GS(7, 7); break;
-        }
-    } else {
-        switch (o) {
-        case 0: HB3_GS(27, 0); break;
-        case 1: HB3_GS(27, 1); break;
-        case 2: HB3_GS(27, 2); break;
-        case 3: HB3_GS(27, 3); break;
-        case 4: HB3_GS(27, 4); break;
-        case 5: HB3_GS(27, 5); break;
-        case 6: HB3_GS(27, 6); break;
-        default: HB3_GS(27, 7); break;
-        }
+#define HB3_GS(O) hipLaunchKernelGGL((k3_gs<27, O>), grid, block, 0, s, a)
+    switch (o) {
+    case 0: HB3_GS(0); break;
+    case 1: HB3_GS(1); break;
+    case 2: HB3_GS(2); break;
+    case 3: HB3_GS(3); break;
+    case 4: HB3_GS(4); break;
+    case 5: HB3_GS(5); break;
+    case 6: HB3_GS(6); break;
+    default: HB3_GS(7); break;
     }
 #undef HB3_GS
     return hipGetLastError();
@@ -1104,7 +1092,7 @@ hipbmg_status relax(hipbmg3d_hier *h, int l, int sweeps, hipStream_t s)
         }
         for (int o = 0; o < 8; ++o) {
             Mark mk(h, l == h->L - 1 ? 0 : 4, s);
-            HIP3(launch_gs_colour(f.npt, o, a, s));
+            HIP3(launch_gs_colour27(o, a, s));
         }
     }
     return HIPBMG_OK;
@@ -1121,22 +1109,22 @@ hipbmg_status reduce_sum(hipbmg3d_hier *h, const double *partials, long long n, 
     return HIPBMG_OK;
 }
 
-// residual of level l: store r and/or the squared norm's block sums
+// residual of level l: store r (store), or only the squared norm's block
+// sums and their sum in d_sum[0] (norm)
 hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream_t s)
 {
+    if (store == norm) return fail3(HIPBMG_EINVAL, "residual: store or norm, not both");
     const Lev3 &f = h->lv[l];
     LArgs a = largs(f, nullptr);
     a.partials = h->d_part;
     const dim3 grid(8 * nblk(f.g.oct)), block(256);   // a multiple of 8, octants interleaved
     Mark mk(h, l == h->L - 1 ? 1 : 4, s);
     if (f.npt == 7) {
-        if (store && !norm) hipLaunchKernelGGL((k3_resid<7, true, false>), grid, block, 0, s, a);
-        else if (!store && norm) hipLaunchKernelGGL((k3_resid<7, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k3_resid<7, true, true>), grid, block, 0, s, a);
+        if (store) hipLaunchKernelGGL((k3_resid<7, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k3_resid<7, false, true>), grid, block, 0, s, a);
     } else {
-        if (store && !norm) hipLaunchKernelGGL((k3_resid<27, true, false>), grid, block, 0, s, a);
-        else if (!store && norm) hipLaunchKernelGGL((k3_resid<27, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k3_resid<27, true, true>), grid, block, 0, s, a);
+        if (store) hipLaunchKernelGGL((k3_resid<27, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k3_resid<27, false, true>), grid, block, 0, s, a);
     }
     HIP3(hipGetLastError());
     if (norm) ST3(reduce_sum(h, h->d_part, (long long)grid.x, s));
