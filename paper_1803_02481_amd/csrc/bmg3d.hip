@@ -443,6 +443,7 @@ struct LArgs {
     double *bc;
     double *partials;
     int rescorr;
+    double *xcz;       // restriction: the coarse iterate, cleared alongside
 };
 
 // index of the neighbour at (DX,DY,DZ) of thread t of octant O
@@ -650,6 +651,8 @@ __global__ __launch_bounds__(256) void k3_restrict(LArgs a)
     int ca, cb, cc;
     sub_coords(c, ts, ca, cb, cc);
     const int I = 2 * ca + (oc & 1), J = 2 * cb + ((oc >> 1) & 1), K = 2 * cc + (oc >> 2);
+    // the coarse level's iterate starts at zero (every entry, boundary included)
+    a.xcz[t] = 0.0;
     if (ca >= c.mx || !inner(c, I, J, K)) {
         a.bc[t] = 0.0;
         return;
@@ -1131,9 +1134,11 @@ hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream
     return HIPBMG_OK;
 }
 
+// b_{l-1} = P^T r_l, and x_{l-1} = 0
 hipbmg_status restrict_to(hipbmg3d_hier *h, int l, hipStream_t s)
 {
-    const LArgs a = largs(h->lv[l], &h->lv[l - 1]);
+    LArgs a = largs(h->lv[l], &h->lv[l - 1]);
+    a.xcz = h->lv[l - 1].x;
     Mark mk(h, l == h->L - 1 ? 2 : 4, s);
     hipLaunchKernelGGL(k3_restrict, dim3(8 * nblk(a.c.oct)), dim3(256), 0, s, a);
     HIP3(hipGetLastError());
@@ -1181,12 +1186,6 @@ hipbmg_status vcycle(hipbmg3d_hier *h, int l, hipStream_t s)
     ST3(relax(h, l, h->prm.nu1, s));
     ST3(residual(h, l, true, false, s));
     ST3(restrict_to(h, l, s));
-    {
-        const long long n = h->lv[l - 1].g.field;
-        hipLaunchKernelGGL(k3_fill0, dim3((unsigned)std::min<long long>(nblk(n), 2048)), dim3(256), 0, s,
-                           h->lv[l - 1].x, n);
-        HIP3(hipGetLastError());
-    }
     ST3(vcycle(h, l - 1, s));
     ST3(interp_from(h, l, h->prm.residual_correction, s));
     ST3(relax(h, l, h->prm.nu2, s));
