@@ -277,3 +277,32 @@ def test_collapse_level_leaves_the_iteration_bitwise_unchanged(shape, kind):
     u, info = HB.Hierarchy3(planes).solve(g(b))
     assert 0 <= info.collapse_level < L and torch.equal(u, ref[0])
     assert all(info.model_us[l] > 0 for l in range(L))
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_shapes_and_parameters_match_the_oracle(case):
+    # seeded random odd sizes (3..41 per side, coarsening stopping wherever a
+    # side turns even), media, V(nu1,nu2), r/C, coarsest size and collapse level
+    rng = np.random.default_rng(600 + case)
+    nx, ny, nz = (int(2 * rng.integers(1, 21) + 1) for _ in range(3))
+    kind = ["blocks", "lognormal", "const"][case % 3]
+    D, b = problem((nz, ny, nx), 610 + case, kind)
+    prm = {"nu1": int(rng.integers(1, 4)), "nu2": int(rng.integers(1, 3)),
+           "residual_correction": int(rng.integers(0, 2)), "coarsest_n": int(rng.choice([3, 5]))}
+    planes = O.fv7(D)
+    ora = O.Hierarchy3(planes, coarsest_n=prm["coarsest_n"], nu1=prm["nu1"], nu2=prm["nu2"],
+                       rescorr=prm["residual_correction"])
+    nunk = np.prod([s - 2 for s in ora.size(0)])
+    if nunk > 4096:
+        pytest.skip("coarsest level beyond the direct solver's limit")
+    _, hist = ora.solve(b, tol=1e-10, max_cycles=200)
+    gpu_L = HB.Hierarchy3(g(planes), **prm).L
+    prm["collapse_level"] = int(rng.integers(0, min(gpu_L, 8)))
+    gpu = HB.Hierarchy3(g(planes), max_cycles=200, **prm)
+    u, info = gpu.solve(g(b), tol=1e-10, check=False)
+    h = np.array(info.history())
+    print((nz, ny, nx), kind, prm, info.cycles, len(hist))
+    assert info.cycles == len(hist)
+    # relative residuals near the rounding level (a direct solve on one
+    # level) differ by rounding alone: an absolute floor of 1e-14
+    assert np.abs(h - hist).max() <= 1e-9 * hist.max() + 1e-14
