@@ -72,18 +72,19 @@ __global__ __launch_bounds__(1024) void k_wg_stream(double2 *__restrict__ g, lon
         }
 }
 
+// best of `reps` timed repetitions after one warm-up; ok turns false if any
+// HIP call fails (the launches included)
 template <typename F>
-static float time_ms(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, F &&launch)
+static float time_ms(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, bool &ok, F &&launch)
 {
     launch();   // warm-up
     float best = 1e30f;
-    for (int r = 0; r < reps; ++r) {
-        hipEventRecord(e0, s);
-        launch();
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+    for (int r = 0; r < reps && ok; ++r) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        ok = ok && hipEventRecord(e0, s) == hipSuccess;
+        launch();
+        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         best = std::min(best, ms);
     }
     return best;
@@ -97,32 +98,36 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
 {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HIPBMG_EHIP;
+    if (hipEventCreate(&e0) != hipSuccess) return HIPBMG_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HIPBMG_EHIP;
+    }
     ModelParams p = model_params();
     hipbmg_status st = HIPBMG_OK;
+    bool ok = true;   // every timing's HIP calls succeeded
     const long long nbig = 1LL << 24;      // doubles per array: 134 MB, far beyond the caches
     const long long nsmall = 1LL << 20;    // 8 MB per array: cache resident
     double *buf = nullptr, *small = nullptr;
     const size_t bytes = 6 * nbig * sizeof(double);
     if (hipMalloc(&buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         return HIPBMG_ENOMEM;
     }
     if (hipMalloc(&small, 4 * 1024 * 1024) != hipSuccess) {
         (void)hipGetLastError();
-        hipFree(buf);
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipFree(buf);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         return HIPBMG_ENOMEM;
     }
-    hipMemsetAsync(buf, 0, bytes, s);
-    hipMemsetAsync(small, 0, 4 * 1024 * 1024, s);
+    ok = hipMemsetAsync(buf, 0, bytes, s) == hipSuccess && hipMemsetAsync(small, 0, 4 * 1024 * 1024, s) == hipSuccess;
     {
         // dependent launch gap
         const int n = 200;
-        float ms = time_ms(s, e0, e1, 3, [&] {
+        float ms = time_ms(s, e0, e1, 3, ok, [&] {
             for (int k = 0; k < n; ++k) hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, k);
         });
         p.alpha_launch_us = 1e3 * ms / n;
@@ -134,11 +139,11 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
             hipLaunchKernelGGL(k_stream_mix, dim3(grid), dim3(256), 0, s, a, a + nd2, a + 2 * nd2,
                                a + 3 * nd2, a + 4 * nd2, reinterpret_cast<double2 *>(buf) + 5 * nd2, n2, reps);
         };
-        ms = time_ms(s, e0, e1, 5, [&] { mix(nbig / 2, 8192, 1); });
+        ms = time_ms(s, e0, e1, 5, ok, [&] { mix(nbig / 2, 8192, 1); });
         const double hbm_gbps = 6.0 * nbig * 8.0 / (ms * 1e-3) / 1e9;
         // cache-resident: six 8 MB arrays (48 MB, inside the last-level
         // cache), twenty passes in one launch so the launch gap does not count
-        ms = time_ms(s, e0, e1, 5, [&] { mix(nsmall / 2, 2048, 20); });
+        ms = time_ms(s, e0, e1, 5, ok, [&] { mix(nsmall / 2, 2048, 20); });
         const double cache_gbps = 20.0 * 6.0 * nsmall * 8.0 / (ms * 1e-3) / 1e9;
         p.beta_hbm_us_per_B = 1.0 / (hbm_gbps * 1e3);
         p.beta_cache_us_per_B = 1.0 / (cache_gbps * 1e3);
@@ -150,7 +155,7 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
             const size_t plane = (size_t)ny * pitch;
             double *lv = nullptr;
             if (hipMalloc(&lv, 9 * plane * sizeof(double)) == hipSuccess) {
-                hipMemsetAsync(lv, 0, 9 * plane * sizeof(double), s);
+                ok = ok && hipMemsetAsync(lv, 0, 9 * plane * sizeof(double), s) == hipSuccess;
                 StreamArgs<double> a{};
                 a.nx = nx;
                 a.ny = ny;
@@ -166,10 +171,10 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
                 a.rb = 64;
                 int g;
                 stream_geometry(nx, ny, 5, SV_SWEEP, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
-                ms = time_ms(s, e0, e1, 5, [&] { launch_stream<double>(5, SV_SWEEP, a, g, s); });
+                ms = time_ms(s, e0, e1, 5, ok, [&] { (void)launch_stream<double>(5, SV_SWEEP, a, g, s); });
                 sweep_step_us = std::max(0.05, (1e3 * ms - p.alpha_launch_us) / (a.rb + 1));
-                hipStreamSynchronize(s);
-                hipFree(lv);
+                ok = ok && hipStreamSynchronize(s) == hipSuccess;
+                (void)hipFree(lv);
             } else {
                 (void)hipGetLastError();
             }
@@ -178,24 +183,24 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
         // barriers in one workgroup
         const int iters = 2000;
         double *out = small + 1024 * 64;
-        ms = time_ms(s, e0, e1, 3, [&] {
+        ms = time_ms(s, e0, e1, 3, ok, [&] {
             hipLaunchKernelGGL((k_barrier<false>), dim3(1), dim3(1024), 0, s, small, iters, out);
         });
         const double bar_glb_us = 1e3 * ms / (2.0 * iters);
-        ms = time_ms(s, e0, e1, 3, [&] {
+        ms = time_ms(s, e0, e1, 3, ok, [&] {
             hipLaunchKernelGGL((k_barrier<true>), dim3(1), dim3(1024), 0, s, small, iters, out);
         });
         const double bar_lds_us = 1e3 * ms / (2.0 * iters);
 
         // one workgroup on L2-resident data
         const long long n2 = (1LL << 18) / 2;   // 2 MB
-        ms = time_ms(s, e0, e1, 3, [&] {
+        ms = time_ms(s, e0, e1, 3, ok, [&] {
             hipLaunchKernelGGL(k_wg_stream, dim3(1), dim3(1024), 0, s, reinterpret_cast<double2 *>(small), n2, 4);
         });
         const double wg_gbps = 4.0 * 2.0 * n2 * 16.0 / (ms * 1e-3) / 1e9;
-        if (hipStreamSynchronize(s) != hipSuccess) st = HIPBMG_EHIP;
-        hipFree(buf);
-        hipFree(small);
+        if (!ok || hipStreamSynchronize(s) != hipSuccess) st = HIPBMG_EHIP;
+        (void)hipFree(buf);
+        (void)hipFree(small);
         buf = small = nullptr;
         // the step latencies and collapsed-level terms from the solver's own kernels
         if (st == HIPBMG_OK) st = calibrate_on_kernels(stream, p);
@@ -233,9 +238,9 @@ extern "C" hipbmg_status hipbmg_calibrate(void *stream, double *out_host)
                 }
         }
     }
-    if (buf) hipFree(buf);
-    if (small) hipFree(small);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+    if (small) (void)hipFree(small);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return st;
 }

@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = denom ? sqrt(sh[0]) / denom[0] : sqrt(sh[0]);
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(256) void k_finalize_batched(const double *__restri
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(256) void k_count_active(const int *__restrict__ ac
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0) count[0] = sh[0];

@@ -55,7 +55,7 @@ __global__ void k_demote_weights(const double *__restrict__ wd, size_t pd, int p
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y;
-    if (I >= cnx) return;
+    if (I >= cnx || J >= cny) return;
     for (int k = 0; k < 8; ++k)
         wf[k * pf + (size_t)J * pitchf + I] = (float)wd[k * pd + (size_t)J * pitchd + I];
 }

@@ -369,7 +369,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<T> &a, const int ti
     const int nsteps = (ny - 1) / 2;            // steps j = 2, 4, ..., ny-1
     const int s0 = blk * a.rb;
     const int s1 = min(s0 + a.rb, nsteps);
-    const int jfirst = 2 + 2 * s0, jlast = 2 + 2 * (s1 - 1);
+    const int jfirst = 2 + 2 * s0;
     constexpr int PRO = F::RES ? 2 : 1;         // prologue steps
 
     const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
