@@ -345,6 +345,16 @@ typedef struct {
 hipbmg_status hipbmg_paper_search(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
                                   int max_path, int *path_host, int *len_host, double *t_host);
 
+/* The same search by A* (section 4, f(s) = g(s) + h(s)): g is the model time
+ * down to state s, h the remaining levels priced on s's processor grid plus
+ * the Cholesky solve.  A grid only shrinks along a path and no level is
+ * cheaper on fewer processors, so h never overestimates and the path found
+ * is a cheapest one (its time equals hipbmg_paper_search's up to summation
+ * order; among equally cheap paths either may be returned).  Outputs as
+ * there, plus *expanded_host = states taken off the open list.  Host only. */
+hipbmg_status hipbmg_paper_astar(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
+                                 int max_path, int *path_host, int *len_host, double *t_host, int *expanded_host);
+
 /* Model time of one V-cycle along the given sequence of processor grids
  * (path_host [len][D], the grids after the first); infinite if the sequence
  * ends before 1 x ... x 1. */

@@ -1494,6 +1494,24 @@ extern "C" hipbmg_status hipbmg_paper_search(const hipbmg_paper_setup *setup, co
     return HIPBMG_OK;
 }
 
+extern "C" hipbmg_status hipbmg_paper_astar(const hipbmg_paper_setup *setup, const int *N_host, const int *P_host,
+                                            int max_path, int *path_host, int *len_host, double *t_host,
+                                            int *expanded_host)
+{
+    PaperSetup ps;
+    const hipbmg_status st = paper_setup_check(setup, N_host, P_host, &ps);
+    if (st != HIPBMG_OK) return st;
+    if (!path_host || !len_host || !t_host || !expanded_host || max_path < 1)
+        return fail(HIPBMG_EINVAL, "null argument");
+    std::vector<std::vector<int>> path;
+    *t_host = paper_astar(ps, N_host, P_host, &path, expanded_host);
+    if ((int)path.size() > max_path) return fail(HIPBMG_EINVAL, "path longer than max_path");
+    for (size_t k = 0; k < path.size(); ++k)
+        for (int d = 0; d < ps.D; ++d) path_host[k * ps.D + d] = path[k][d];
+    *len_host = (int)path.size();
+    return HIPBMG_OK;
+}
+
 extern "C" hipbmg_status hipbmg_paper_path_cost(const hipbmg_paper_setup *setup, const int *N_host,
                                                 const int *P_host, const int *path_host, int len, double *t_host)
 {

@@ -636,4 +636,89 @@ double paper_path_cost(const PaperSetup &s, const int *N0, const int *P, const s
     }
 }
 
+// remaining levels from N priced on p down to the coarsest, plus the coarse solve
+static double paper_h(const PaperSetup &s, Grid N, const Grid &p)
+{
+    double t = 0.0;
+    while (coarsens(s, N, p, true)) {
+        const Grid Nn = halve(N);
+        t += paper_level(s, N, Nn, p);
+        N = Nn;
+    }
+    double nn = 1.0;
+    for (int v : N) nn *= v;
+    return t + nn * nn * s.m.gamma;
+}
+
+double paper_astar(const PaperSetup &s, const int *N0, const int *P, std::vector<std::vector<int>> *path,
+                   int *expanded)
+{
+    struct Node {
+        double f, g;
+        Grid N, p;
+        int parent;
+        bool goal;
+    };
+    std::vector<Node> nodes;
+    auto cmp = [&](int a, int b) { return nodes[a].f > nodes[b].f; };
+    std::priority_queue<int, std::vector<int>, decltype(cmp)> open(cmp);
+    // the start: coarsen on P to its limit
+    Grid N(N0, N0 + s.D), p(P, P + s.D);
+    double g0 = 0.0;
+    if (at_one(p)) {
+        if (path) path->clear();
+        if (expanded) *expanded = 1;
+        return paper_tail(s, N);
+    }
+    while (coarsens(s, N, p, false)) {
+        const Grid Nn = halve(N);
+        g0 += paper_level(s, N, Nn, p);
+        N = Nn;
+    }
+    nodes.push_back({g0 + paper_h(s, N, p), g0, N, p, -1, false});
+    open.push(0);
+    int exp = 0;
+    std::map<std::pair<Grid, Grid>, double> best_g;
+    while (!open.empty()) {
+        const int id = open.top();
+        open.pop();
+        if (nodes[id].goal) {
+            if (path) {
+                path->clear();
+                for (int k = id; nodes[k].parent >= 0; k = nodes[k].parent) path->insert(path->begin(), nodes[k].p);
+            }
+            if (expanded) *expanded = exp;
+            return nodes[id].g;
+        }
+        const auto key = std::make_pair(nodes[id].N, nodes[id].p);
+        auto it = best_g.find(key);
+        if (it != best_g.end() && it->second <= nodes[id].g) continue;
+        best_g[key] = nodes[id].g;
+        ++exp;
+        const Grid Nc = nodes[id].N, pc = nodes[id].p;
+        const double gc = nodes[id].g;
+        int grids[64 * 3];
+        const int cnt = paper_enumerate(s.D, Nc.data(), pc.data(), 64, grids);
+        for (int k = 0; k < cnt; ++k) {
+            const Grid q(grids + k * s.D, grids + (k + 1) * s.D);
+            double g = gc + paper_agg(s, Nc, pc, q);
+            if (at_one(q)) {
+                g += paper_tail(s, Nc);
+                nodes.push_back({g, g, Nc, q, id, true});
+            } else {
+                Grid Nq = Nc;
+                while (coarsens(s, Nq, q, false)) {
+                    const Grid Nn = halve(Nq);
+                    g += paper_level(s, Nq, Nn, q);
+                    Nq = Nn;
+                }
+                nodes.push_back({g + paper_h(s, Nq, q), g, Nq, q, id, false});
+            }
+            open.push((int)nodes.size() - 1);
+        }
+    }
+    if (expanded) *expanded = exp;
+    return std::numeric_limits<double>::infinity();
+}
+
 }  // namespace hbmg

@@ -191,6 +191,12 @@ struct PaperSetup {
     PaperMachine m;
 };
 double paper_search(const PaperSetup &s, const int *N, const int *P, std::vector<std::vector<int>> *path);
+// The same search by A* (section 4): f = g + h with h the remaining levels
+// priced on the current processor grid plus the coarse solve (a grid only
+// shrinks along a path and a level costs no less on fewer processors, so h
+// never overestimates).  *expanded = states taken off the open list.
+double paper_astar(const PaperSetup &s, const int *N, const int *P, std::vector<std::vector<int>> *path,
+                   int *expanded);
 double paper_path_cost(const PaperSetup &s, const int *N, const int *P, const std::vector<std::vector<int>> &seq);
 
 }  // namespace hbmg

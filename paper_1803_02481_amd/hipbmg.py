@@ -86,6 +86,9 @@ _SIGS = {
                                     ctypes.POINTER(_I)]),
     "hipbmg_paper_search": (_I, [ctypes.c_void_p, ctypes.POINTER(_I), ctypes.POINTER(_I), _I,
                                  ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
+    "hipbmg_paper_astar": (_I, [ctypes.c_void_p, ctypes.POINTER(_I), ctypes.POINTER(_I), _I,
+                                ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(_I)]),
     "hipbmg_paper_path_cost": (_I, [ctypes.c_void_p, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                     ctypes.POINTER(_I), _I, ctypes.POINTER(ctypes.c_double)]),
     # 3D path (include/hipbmg3d.h)
@@ -589,6 +592,23 @@ def paper_search(N, P, limit=9, coarsest=3, ns=9, ncolors=4, nu1=2, nu2=1, redun
     t = ctypes.c_double()
     _check(lib().hipbmg_paper_search(ctypes.byref(st), Na, Pa, 64, path, ctypes.byref(ln), ctypes.byref(t)))
     return t.value, [tuple(path[k * D:(k + 1) * D]) for k in range(ln.value)]
+
+
+def paper_astar(N, P, limit=9, coarsest=3, ns=9, ncolors=4, nu1=2, nu2=1, redundant=0, alpha=0.65e-6,
+                beta=5.65e-9, gamma=0.44e-9):
+    """The same search by A*: (model seconds per V-cycle, [processor grids
+    after the first], states expanded)."""
+    D = len(N)
+    st = _paper_setup(D, limit, coarsest, ns, ncolors, nu1, nu2, redundant, alpha, beta, gamma)
+    Na = (ctypes.c_int * D)(*N)
+    Pa = (ctypes.c_int * D)(*P)
+    path = (ctypes.c_int * (64 * D))()
+    ln = ctypes.c_int()
+    t = ctypes.c_double()
+    ex = ctypes.c_int()
+    _check(lib().hipbmg_paper_astar(ctypes.byref(st), Na, Pa, 64, path, ctypes.byref(ln), ctypes.byref(t),
+                                    ctypes.byref(ex)))
+    return t.value, [tuple(path[k * D:(k + 1) * D]) for k in range(ln.value)], ex.value
 
 
 def paper_path_cost(N, P, seq, limit=9, coarsest=3, ns=9, ncolors=4, nu1=2, nu2=1, redundant=0, alpha=0.65e-6,

@@ -164,3 +164,71 @@ def test_model_predicts_the_papers_speedup_over_all_to_one():
     assert 0.85 * want <= t0 / t1 <= 1.15 * want, t0 / t1
     # a sequence that stops short of one processor has no coarse solve
     assert HB.paper_path_cost(N, P, paths[1][:-1], **machine()) == math.inf
+
+
+def every_path(N, P, limit, coarsest):
+    # all redistribution paths, written out: coarsen on P while every local
+    # side exceeds the limit, then continue on any enumerated coarser grid
+    # (section 4's directed graph, walked exhaustively)
+    N = list(N)
+    while all(n > coarsest for n in N) and all(-(-n // p) > limit for n, p in zip(N, P)):
+        N = [-(-n // 2) for n in N]
+    if all(p == 1 for p in P):
+        return [[]]
+    out = []
+    for q in HB.paper_enumerate(tuple(N), tuple(P)):
+        out += [[q] + rest for rest in every_path(N, q, limit, coarsest)]
+    return out
+
+
+@pytest.mark.parametrize("P", [(2, 1), (2, 2), (4, 2), (4, 4), (8, 4), (16, 8), (4, 2, 2), (8, 4, 4)])
+@pytest.mark.parametrize("redundant", [0, 1])
+def test_searches_find_the_brute_force_optimum(P, redundant):
+    # the paper's weak-scaling local problem (568 x 71, and 3D boxes of
+    # 64 x 32 x 16 per processor).  A path visits or skips each of the h =
+    # log2(n_p) enumerated grids (the 2^h of the paper's count) but must end
+    # on one processor, so the brute force walks 2^(h-1) = n_p / 2 paths
+    n = (568, 71) if len(P) == 2 else (64, 32, 16)
+    N = tuple(a * b for a, b in zip(n, P))
+    m = dict(limit=9, redundant=redundant, **machine())
+    paths = every_path(N, P, 9, 3)
+    assert len(paths) == math.prod(P) // 2
+    costs = [HB.paper_path_cost(N, P, seq, **m) for seq in paths]
+    best = min(costs)
+    t_exh, p_exh = HB.paper_search(N, P, **m)
+    t_ast, p_ast, expanded = HB.paper_astar(N, P, **m)
+    assert t_exh == pytest.approx(best, rel=1e-13)
+    assert t_ast == pytest.approx(best, rel=1e-13)
+    assert p_exh in paths and p_ast in paths
+    assert HB.paper_path_cost(N, P, p_ast, **m) == pytest.approx(best, rel=1e-13)
+    assert 1 <= expanded <= math.prod(P)
+
+
+@pytest.mark.parametrize("limit", [8, 9, 12, 17])
+def test_astar_avoids_the_brute_force_complexity(limit):
+    # weak scaling with the local problem 568 x 71 on 2:1 processor grids up
+    # to 32768 processors: the optimum equals the exhaustive search's, and the
+    # states A* expands grow like log2(n_p), far below the n_p paths
+    for k in range(1, 16):
+        P = (2 ** ((k + 1) // 2), 2 ** (k // 2))
+        N = (568 * P[0], 71 * P[1])
+        t_exh, _ = HB.paper_search(N, P, limit=limit, **machine())
+        t_ast, path, expanded = HB.paper_astar(N, P, limit=limit, **machine())
+        assert t_ast == pytest.approx(t_exh, rel=1e-13)
+        assert path[-1] == (1, 1)
+        assert len(path) <= expanded <= 2 * k + 2, (P, expanded)
+
+
+def test_astar_selects_the_papers_path():
+    meta, paths = read_paths()
+    P, n = meta["processor_grid"], meta["local_problem"]
+    N = (P[0] * n[0], P[1] * n[1])
+    t, path, _ = HB.paper_astar(N, P, **machine())
+    # path 1 or a path of the same model time: splitting one gather 16 -> 1
+    # into 16 -> 2 -> 1 costs the same (3 + 1 latencies, 7/16 + 1/2 of the
+    # block's words), so the search may return either
+    assert path[:5] == paths[1][:5] and path[-1] == (1, 1)
+    assert t == pytest.approx(HB.paper_path_cost(N, P, paths[1], **machine()), rel=1e-13)
+    for k, seq in paths.items():
+        if k != 1:
+            assert HB.paper_path_cost(N, P, seq, **machine()) > t * (1 + 1e-9), k
