@@ -521,9 +521,12 @@ __device__ __forceinline__ void gs_point(const LArgs &a, long long t)
     a.x[v] += (a.b[v] - s) / a.st[v];
 }
 
-// one colour of the relaxation on octant O
+// one colour of the relaxation on octant O.  On the coarse levels a launch
+// holds a wave or less per SIMD; a four-wave occupancy target leaves the
+// registers to issue every load of a 27-point row before the first use (at
+// the default target they go out in three or four dependent batches)
 template <int NPT, int O>
-__global__ __launch_bounds__(256) void k3_gs(LArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k3_gs(LArgs a)
 {
     const long long t = xcd_block(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
@@ -658,8 +661,13 @@ __global__ __launch_bounds__(256) void k3_restrict(LArgs a)
         return;
     }
     double s = 0.0;
+    // unrolled, the fine octant of every support vertex is a constant and the
+    // 54 loads can go out together
+#pragma unroll
     for (int ez = -1; ez <= 1; ++ez)
+#pragma unroll
         for (int ey = -1; ey <= 1; ++ey)
+#pragma unroll
             for (int ex = -1; ex <= 1; ++ex) {
                 const int pi = 2 * I + ex, pj = 2 * J + ey, pk = 2 * K + ez;
                 const int mI = (ex == -1 ? 1 : 0) | (ey == -1 ? 2 : 0) | (ez == -1 ? 4 : 0);
@@ -712,7 +720,7 @@ __global__ __launch_bounds__(256) void k3_interp(LArgs a)
 // iteration does not depend on the collapse level.
 // ---------------------------------------------------------------------------
 constexpr int MAXC3 = 8;
-constexpr int CWG3 = 1024;
+constexpr int CWG3 = 512;
 
 struct CLev {
     Oct g;
@@ -731,25 +739,28 @@ struct CArgs {
     int nu1, nu2, rescorr;
 };
 
-__device__ __forceinline__ long long nbr_rt(const Oct &g, int o, long long t, int dx, int dy, int dz)
+// collapsed levels are small (the host caps l* so that every plane offset of a
+// collapsed level fits in 32 bits): 32-bit index arithmetic throughout, which
+// keeps the runtime-octant stencil within the workgroup's register budget
+__device__ __forceinline__ int nbr_rt(const Oct &g, int o, int t, int dx, int dy, int dz)
 {
     const int ox = (o & 1) + dx, oy = ((o >> 1) & 1) + dy, oz = (o >> 2) + dz;
     const int on = (ox & 1) | ((oy & 1) << 1) | ((oz & 1) << 2);
-    return on * g.oct + t + (long long)(oz >> 1) * g.plane + (long long)(oy >> 1) * g.px + (ox >> 1);
+    return on * (int)g.oct + t + (oz >> 1) * (int)g.plane + (oy >> 1) * g.px + (ox >> 1);
 }
 
 // apply_at with the octant at run time (same expressions, same order)
-__device__ double apply_rt(const CLev &L, int o, long long t)
+__device__ __forceinline__ double apply_rt(const CLev &L, int o, int t)
 {
     const Oct &g = L.g;
-    const long long F = g.field;
-    const long long v = o * g.oct + t;
+    const int F = (int)g.field;
+    const int v = o * (int)g.oct + t;
     const double *st = L.st, *x = L.x;
     if (L.npt == 7) {
         const double *C = st, *W = st + F, *S = st + 2 * F, *B = st + 3 * F;
-        const long long xw = nbr_rt(g, o, t, -1, 0, 0), xe = nbr_rt(g, o, t, 1, 0, 0);
-        const long long ys = nbr_rt(g, o, t, 0, -1, 0), yn = nbr_rt(g, o, t, 0, 1, 0);
-        const long long zb = nbr_rt(g, o, t, 0, 0, -1), zt = nbr_rt(g, o, t, 0, 0, 1);
+        const int xw = nbr_rt(g, o, t, -1, 0, 0), xe = nbr_rt(g, o, t, 1, 0, 0);
+        const int ys = nbr_rt(g, o, t, 0, -1, 0), yn = nbr_rt(g, o, t, 0, 1, 0);
+        const int zb = nbr_rt(g, o, t, 0, 0, -1), zt = nbr_rt(g, o, t, 0, 0, 1);
         const double cv = C[v], wv = W[v], we = W[xe], sv = S[v], sn = S[yn], bv = B[v], bt = B[zt];
         return cv * x[v] - wv * x[xw] - we * x[xe] - sv * x[ys] - sn * x[yn] - bv * x[zb] - bt * x[zt];
     }
@@ -757,7 +768,7 @@ __device__ double apply_rt(const CLev &L, int o, long long t)
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
         const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-        const long long qm = nbr_rt(g, o, t, dx, dy, dz), qp = nbr_rt(g, o, t, -dx, -dy, -dz);
+        const int qm = nbr_rt(g, o, t, dx, dy, dz), qp = nbr_rt(g, o, t, -dx, -dy, -dz);
         s -= st[(1 + q) * F + v] * x[qm];
         s -= st[(1 + q) * F + qp] * x[qp];
     }
@@ -773,24 +784,24 @@ __device__ __forceinline__ void sub_coords32(const Oct &g, int t, int &a, int &b
     c = r / g.my;
 }
 
-__device__ __forceinline__ bool vertex_rt(const Oct &g, int o, long long t, int &i, int &j, int &k)
+__device__ __forceinline__ bool vertex_rt(const Oct &g, int o, int t, int &i, int &j, int &k)
 {
     int a, b, c;
-    sub_coords32(g, (int)t, a, b, c);
+    sub_coords32(g, t, a, b, c);
     i = 2 * a + (o & 1);
     j = 2 * b + ((o >> 1) & 1);
     k = 2 * c + (o >> 2);
     return a < g.mx && inner(g, i, j, k);
 }
 
-__device__ void wg_relax(const CLev &L, int sweeps)
+__device__ __forceinline__ void wg_relax(const CLev &L, int sweeps)
 {
     for (int it = 0; it < sweeps; ++it)
         for (int o = 0; o < 8; ++o) {
             for (int t = threadIdx.x; t < (int)L.g.oct; t += CWG3) {
                 int i, j, k;
                 if (!vertex_rt(L.g, o, t, i, j, k)) continue;
-                const long long v = o * L.g.oct + t;
+                const int v = o * (int)L.g.oct + t;
                 const double s = apply_rt(L, o, t);
                 L.x[v] += (L.b[v] - s) / L.st[v];
             }
@@ -798,7 +809,7 @@ __device__ void wg_relax(const CLev &L, int sweeps)
         }
 }
 
-__device__ void wg_residual(const CLev &L)
+__device__ __forceinline__ void wg_residual(const CLev &L)
 {
     const int oct = (int)L.g.oct;
     for (int u = threadIdx.x; u < (int)L.g.field; u += CWG3) {
@@ -814,7 +825,7 @@ __device__ void wg_residual(const CLev &L)
     __syncthreads();
 }
 
-__device__ void wg_restrict(const CLev &F, const CLev &C)
+__device__ __forceinline__ void wg_restrict(const CLev &F, const CLev &C)
 {
     const Oct &g = F.g, &c = C.g;
     const int coct = (int)c.oct;
@@ -842,7 +853,7 @@ __device__ void wg_restrict(const CLev &F, const CLev &C)
     __syncthreads();
 }
 
-__device__ void wg_interp(const CLev &F, const CLev &C, int rescorr)
+__device__ __forceinline__ void wg_interp(const CLev &F, const CLev &C, int rescorr)
 {
     const Oct &g = F.g, &c = C.g;
     const int oct = (int)g.oct;
@@ -889,19 +900,27 @@ __device__ void wg_coarse(const CArgs &a, double *y)
 }
 
 // levels 0..top: down (relax, residual, restrict), the coarse solve, up
-// (interpolate, relax).  The caller has set b and x of level top.
-__global__ __launch_bounds__(CWG3) void k3_collapse(CArgs a)
+// (interpolate, relax).  The caller has set b and x of level top.  On the
+// small levels only a wave or two per SIMD has work, so nothing hides memory
+// latency: two waves per SIMD leave the registers to issue all 54 loads of a
+// 27-point row before the first use (at the default occupancy target the
+// compiler keeps two in flight, and a row costs 27 trips to L2).
+__global__ __launch_bounds__(CWG3) __attribute__((amdgpu_waves_per_eu(2, 2))) void k3_collapse(CArgs a)
 {
     extern __shared__ double y[];
+    // levels as values (not references into the argument block), so that
+    // their fields stay in scalar registers across the phase loops
     for (int l = a.top; l >= 1; --l) {
-        wg_relax(a.lv[l], a.nu1);
-        wg_residual(a.lv[l]);
-        wg_restrict(a.lv[l], a.lv[l - 1]);
+        const CLev F = a.lv[l], C = a.lv[l - 1];
+        wg_relax(F, a.nu1);
+        wg_residual(F);
+        wg_restrict(F, C);
     }
     wg_coarse(a, y);
     for (int l = 1; l <= a.top; ++l) {
-        wg_interp(a.lv[l], a.lv[l - 1], a.rescorr);
-        wg_relax(a.lv[l], a.nu2);
+        const CLev F = a.lv[l], C = a.lv[l - 1];
+        wg_interp(F, C, a.rescorr);
+        wg_relax(F, a.nu2);
     }
 }
 
@@ -1496,7 +1515,8 @@ extern "C" hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const d
     // calibrated machine parameters.
     {
         int lcap = std::min(L - 1, MAXC3 - 1);
-        while (lcap > 0 && h->lv[lcap].g.field >= (1LL << 31)) --lcap;   // 32-bit indices in the workgroup
+        // 32-bit indices in the workgroup: every plane offset of a collapsed level
+        while (lcap > 0 && (long long)(h->lv[lcap].npt == 7 ? 4 : 14) * h->lv[lcap].g.field >= (1LL << 31)) --lcap;
         hbmg::ModelLevel3 ml[HIPBMG_MAX_LEVELS];
         for (int l = 0; l < L; ++l)
             ml[l] = hbmg::ModelLevel3{h->lv[l].g.nx, h->lv[l].g.ny, h->lv[l].g.nz, h->lv[l].npt};
