@@ -115,6 +115,25 @@ typedef struct {
 /* Fill *p with the defaults above. */
 void hipbmg_default_params(hipbmg_params *p);
 
+/* Device memory of the handles (the 2D, batched and 3D hierarchies: level
+ * planes, weights, factors, launch tables) comes from this allocator, for
+ * callers that pool device memory themselves (PyTorch's caching allocator,
+ * for one).  alloc_fn(bytes, ctx) returns a device pointer on the current
+ * device, 256-byte aligned, or NULL on failure (the call then fails with
+ * HIPBMG_ENOMEM; a misaligned block is handed back and the call fails).
+ * free_fn(ptr, ctx) releases it.  Both NULL restores hipMalloc/hipFree;
+ * exactly one NULL is HIPBMG_EINVAL.  The setting is process-wide and applies
+ * to allocations made after the call; each block is returned to the
+ * allocator that made it, whenever its handle is destroyed.  Before handing
+ * such blocks back the library waits for the device, so memory the allocator
+ * gives out again is no longer in use by the library's streams.  The
+ * callbacks may be called from any library call that builds or destroys a
+ * handle (the solves allocate nothing).  The one-time machine calibration
+ * keeps its scratch on hipMalloc.  Host only; thread-safe. */
+typedef void *(*hipbmg_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hipbmg_free_fn)(void *ptr, void *ctx);
+hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx);
+
 /* Build the multigrid hierarchy for the operator given by `coeffs`
  * ([3][ny][nx] if npt == 5, [5][ny][nx] if npt == 9; see the plane convention
  * above).  On the GPU: operator-induced interpolation weights and the Galerkin

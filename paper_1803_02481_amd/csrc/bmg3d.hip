@@ -994,7 +994,7 @@ namespace {
 hipbmg_status dalloc3(hipbmg3d_hier *h, double **p, long long n)
 {
     void *q = nullptr;
-    if (hipMalloc(&q, (size_t)n * sizeof(double)) != hipSuccess) {
+    if (hbmg::dev_malloc(&q, (size_t)n * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         return fail3(HIPBMG_ENOMEM, "device allocation of %lld doubles failed", n);
     }
@@ -1006,8 +1006,7 @@ hipbmg_status dalloc3(hipbmg3d_hier *h, double **p, long long n)
 
 void free3(hipbmg3d_hier *h)
 {
-    for (void *p : h->allocs) (void)hipFree(p);
-    h->allocs.clear();
+    hbmg::dev_free_all(h->allocs);
     if (h->h_sum) (void)hipHostFree(h->h_sum);
     for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
     if (h->exec) (void)hipGraphExecDestroy(h->exec);

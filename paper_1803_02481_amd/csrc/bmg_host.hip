@@ -14,7 +14,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace hbmg;
@@ -52,6 +54,88 @@ extern "C" const char *hipbmg_last_error(void) { return g_err.c_str(); }
 
 // the message of the calling thread's last failure, for the other entry-point files
 void hbmg::set_last_error(const char *msg) { g_err = msg; }
+
+// ---------------------------------------------------------------------------
+// handle memory: the caller's allocator, or hipMalloc
+// ---------------------------------------------------------------------------
+namespace {
+struct BlockOwner {
+    hipbmg_free_fn fn;
+    void *ctx;
+};
+std::mutex g_alloc_mu;
+hipbmg_alloc_fn g_alloc_fn = nullptr;
+hipbmg_free_fn g_free_fn = nullptr;
+void *g_alloc_ctx = nullptr;
+std::unordered_map<void *, BlockOwner> g_blocks;   // blocks made by a registered allocator
+}  // namespace
+
+hipError_t hbmg::dev_malloc(void **p, size_t bytes)
+{
+    hipbmg_alloc_fn fa;
+    hipbmg_free_fn ff;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        fa = g_alloc_fn;
+        ff = g_free_fn;
+        ctx = g_alloc_ctx;
+    }
+    if (!fa) return hipMalloc(p, bytes);
+    void *q = fa(bytes, ctx);
+    if (!q) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {   // the kernels assume 256-byte aligned planes
+        ff(q, ctx);
+        *p = nullptr;
+        return hipErrorInvalidValue;
+    }
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        g_blocks[q] = BlockOwner{ff, ctx};
+    }
+    *p = q;
+    return hipSuccess;
+}
+
+void hbmg::dev_free_all(std::vector<void *> &v)
+{
+    std::vector<BlockOwner> own(v.size(), BlockOwner{nullptr, nullptr});
+    bool any = false;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        for (size_t k = 0; k < v.size(); ++k) {
+            auto it = g_blocks.find(v[k]);
+            if (it != g_blocks.end()) {
+                own[k] = it->second;
+                g_blocks.erase(it);
+                any = true;
+            }
+        }
+    }
+    if (any) (void)hipDeviceSynchronize();
+    for (size_t k = 0; k < v.size(); ++k) {
+        if (!v[k]) continue;
+        if (own[k].fn) own[k].fn(v[k], own[k].ctx);
+        else (void)hipFree(v[k]);
+    }
+    v.clear();
+}
+
+extern "C" hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx)
+{
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
+        hbmg::set_last_error("hipbmg_set_allocator: give both functions, or neither");
+        return HIPBMG_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc_fn = alloc_fn;
+    g_free_fn = free_fn;
+    g_alloc_ctx = alloc_fn ? ctx : nullptr;
+    return HIPBMG_OK;
+}
 
 extern "C" void hipbmg_default_params(hipbmg_params *p)
 {
@@ -146,7 +230,7 @@ struct hipbmg_hier {
         }
         for (int k = 0; k < RING; ++k)
             if (ring_ev[k]) (void)hipEventDestroy(ring_ev[k]);
-        for (void *p : allocs) (void)hipFree(p);
+        dev_free_all(allocs);
         if (h_scal) (void)hipHostFree(h_scal);
         if (h_flags) (void)hipHostFree(h_flags);
         if (ring_host) (void)hipHostFree(ring_host);
@@ -212,9 +296,9 @@ template <typename T>
 static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
 {
     void *q = nullptr;
-    if (hipMalloc(&q, n * sizeof(T) + 256) != hipSuccess) {
+    if (dev_malloc(&q, n * sizeof(T) + 256) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(HIPBMG_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
     }
     h->allocs.push_back(q);
     HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 256, s));
@@ -526,8 +610,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
                              hipGetErrorString(hipGetLastError())));
     }
-    if (hipMalloc(&h->d_lv, L * sizeof(LevelDev<double>)) != hipSuccess)
-        return bail(fail(HIPBMG_ENOMEM, "hipMalloc failed"));
+    if (dev_malloc((void **)&h->d_lv, L * sizeof(LevelDev<double>)) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
     h->allocs.push_back(h->d_lv);
     if (hipMemcpyAsync(h->d_lv, h->lv.data(), L * sizeof(LevelDev<double>), hipMemcpyHostToDevice, s) !=
         hipSuccess)
@@ -544,8 +628,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             if (launch_demote_level(h->lv[l], h->lv32[l], cnx, cny, s) != hipSuccess)
                 return bail(fail(HIPBMG_EHIP, "demote launch failed"));
         }
-        if (hipMalloc(&h->d_lv32, L * sizeof(LevelDev<float>)) != hipSuccess)
-            return bail(fail(HIPBMG_ENOMEM, "hipMalloc failed"));
+        if (dev_malloc((void **)&h->d_lv32, L * sizeof(LevelDev<float>)) != hipSuccess)
+            return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
         h->allocs.push_back(h->d_lv32);
         if (hipMemcpyAsync(h->d_lv32, h->lv32.data(), L * sizeof(LevelDev<float>),
                            hipMemcpyHostToDevice, s) != hipSuccess)
@@ -1924,7 +2008,7 @@ static void drop_plan(BPlan &p)
 {
     if (p.exec) (void)hipGraphExecDestroy(p.exec);
     if (p.graph) (void)hipGraphDestroy(p.graph);
-    for (void *q : p.allocs) (void)hipFree(q);
+    dev_free_all(p.allocs);
     p = BPlan{};
 }
 
@@ -1961,8 +2045,8 @@ struct hipbmg_batch {
         for (auto &p : plan64) drop_plan(p);
         for (auto &q : plan32)
             for (auto &p : q) drop_plan(p);
-        for (void *p : seg_allocs) (void)hipFree(p);
-        for (void *p : allocs) (void)hipFree(p);
+        dev_free_all(seg_allocs);
+        dev_free_all(allocs);
         if (h_relres) (void)hipHostFree(h_relres);
         if (h_active) (void)hipHostFree(h_active);
         if (h_count) (void)hipHostFree(h_count);
@@ -1974,9 +2058,9 @@ template <typename T>
 static hipbmg_status balloc_to(std::vector<void *> &owner, T **p, size_t n, hipStream_t s)
 {
     void *q = nullptr;
-    if (hipMalloc(&q, n * sizeof(T) + 64) != hipSuccess) {
+    if (dev_malloc(&q, n * sizeof(T) + 64) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(HIPBMG_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
     }
     owner.push_back(q);
     HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 64, s));
@@ -2251,8 +2335,7 @@ static hipbmg_status build_plans(hipbmg_batch *B, hipStream_t s)
     for (auto &p : B->plan64) drop_plan(p);
     for (auto &q : B->plan32)
         for (auto &p : q) drop_plan(p);
-    for (void *q : B->seg_allocs) (void)hipFree(q);
-    B->seg_allocs.clear();
+    dev_free_all(B->seg_allocs);
     B->d_partials = nullptr;
     B->d_poff = B->d_pcnt = nullptr;
     B->n_partials = 0;

@@ -14,11 +14,20 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace hbmg {
 
 // Set the message hipbmg_last_error() returns on the calling thread.
 void set_last_error(const char *msg);
+
+// Device memory owned by a handle: from the allocator registered with
+// hipbmg_set_allocator, else hipMalloc.  dev_free_all returns every block of
+// v to whichever allocator made it (waiting for the device first when a
+// registered allocator is involved, since such memory may be handed out again
+// at once) and clears v.
+hipError_t dev_malloc(void **p, size_t bytes);
+void dev_free_all(std::vector<void *> &v);
 
 // Weight plane indices (fine vertex of coarse cell (I,J) -> coarse corner).
 enum { WXL = 0, WXR = 1, WYB = 2, WYT = 3, WCSW = 4, WCSE = 5, WCNW = 6, WCNE = 7 };

@@ -78,6 +78,7 @@ _SIGS = {
     "hipbmg_solve_batched": (_I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_double, _VP,
                                   ctypes.POINTER(Info)]),
     "hipbmg_destroy_batched": (_I, [_VP]),
+    "hipbmg_set_allocator": (_I, [_VP, _VP, _VP]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
     "hipbmg_paper_model": (_I, [_I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, _I, _I, _I, _I,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -109,6 +110,11 @@ _SIGS = {
     "hipbmg3d_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
 }
 
+# hipbmg_alloc_fn / hipbmg_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None   # the registered callbacks, kept alive while registered
+
 
 def lib():
     """Load libhipbmg.so (raises if it is not built)."""
@@ -123,6 +129,49 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_allocator(alloc=None, free=None):
+    """Register Python callables as the library's device allocator for handle
+    memory: alloc(nbytes) -> device address (int, 256-byte aligned; 0 or an
+    exception on failure), free(address).  No arguments restores hipMalloc.
+    Blocks are returned to the allocator that made them when their handle is
+    closed, so keep the callables valid until then."""
+    global _allocator
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(lib().hipbmg_set_allocator(None, None, None))
+        return
+
+    def _a(nbytes, ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:
+            return None
+
+    def _f(ptr, ctx):
+        try:
+            free(int(ptr))
+        except Exception:
+            pass
+
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib().hipbmg_set_allocator(ctypes.cast(cbs[0], ctypes.c_void_p), ctypes.cast(cbs[1], ctypes.c_void_p),
+                                      None))
+    # earlier callbacks may still own blocks of open handles: keep them all alive
+    _allocator = (cbs, _allocator)
+
+
+def use_torch_allocator(device=None):
+    """Take handle memory from PyTorch's caching allocator (on `device`, by
+    default the current one), so that it is pooled with the caller's tensors."""
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=dev)
+
+    set_allocator(alloc, torch.cuda.caching_allocator_delete)
 
 
 def _check(status):

@@ -96,3 +96,17 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert int(out[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
+
+
+def test_set_allocator_validates_its_arguments():
+    import ctypes
+    from paper_1803_02481_amd import hipbmg as HB
+    L = HB.lib()
+    fa = HB.ALLOC_FN(lambda n, ctx: 0)
+    ff = HB.FREE_FN(lambda p, ctx: None)
+    assert L.hipbmg_set_allocator(ctypes.cast(fa, ctypes.c_void_p), None, None) == HB.EINVAL
+    assert L.hipbmg_set_allocator(None, ctypes.cast(ff, ctypes.c_void_p), None) == HB.EINVAL
+    assert L.hipbmg_set_allocator(ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p), None) == HB.OK
+    assert L.hipbmg_set_allocator(None, None, None) == HB.OK
+    with pytest.raises(ValueError):
+        HB.set_allocator(lambda n: 0)

@@ -1,0 +1,157 @@
+"""The handle allocator hook (hipbmg_set_allocator), through the C ABI: handle
+memory taken from a caller's allocator (here PyTorch's caching allocator,
+wrapped to count) gives bitwise the same solves as memory from hipMalloc,
+every block goes back to the allocator that made it when its handle is
+destroyed, and a failing allocator makes setup fail cleanly."""
+import pytest
+import torch
+
+from paper_1803_02481_amd import hipbmg as HB
+from paper_1803_02481_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def g(a):
+    return torch.from_numpy(a).to(DEV)
+
+
+class Pool:
+    """Counting wrapper around torch's caching allocator; optionally fails the
+    k-th request or returns misaligned blocks."""
+
+    def __init__(self, fail_at=None, misalign=False):
+        self.live, self.n_alloc, self.n_free = {}, 0, 0
+        self.fail_at, self.misalign = fail_at, misalign
+
+    def alloc(self, nbytes):
+        self.n_alloc += 1
+        if self.fail_at is not None and self.n_alloc == self.fail_at:
+            return 0
+        p = torch.cuda.caching_allocator_alloc(nbytes + (8 if self.misalign else 0), device=0)
+        q = p + 8 if self.misalign else p
+        self.live[q] = p
+        return q
+
+    def free(self, q):
+        p = self.live.pop(q)   # KeyError: a block this pool never made
+        self.n_free += 1
+        torch.cuda.caching_allocator_delete(p)
+
+
+def problems():
+    c2 = HB.fv5_from_cells(g(inputs.cells_log10_blocks(65, 65, block=8, seed=21)))
+    b2 = g(inputs.load_uniform(65, 65, seed=22))
+    c3 = HB.fv7_from_cells(g(inputs.cells3_log10_blocks(17, 17, 17, block=4, seed=23)))
+    b3 = g(inputs.load3_uniform(17, 17, 17, seed=24))
+    cb = [HB.fv5_from_cells(g(inputs.cells_lognormal(n, n, sigma=1.0, seed=31 + k)))
+          for k, n in enumerate((33, 65, 129))]
+    bb = [g(inputs.load_uniform(n, n, seed=41 + k)) for k, n in enumerate((33, 65, 129))]
+    return c2, b2, c3, b3, cb, bb
+
+
+def run_all(p):
+    c2, b2, c3, b3, cb, bb = p
+    out = []
+    for prec in (0, 1):
+        h = HB.Hierarchy(c2, precision=prec)
+        out.append(h.solve(b2, tol=1e-10))
+        h.close()
+    h3 = HB.Hierarchy3(c3)
+    out.append(h3.solve(b3, tol=1e-10))
+    h3.close()
+    hb = HB.BatchHierarchy(cb)
+    us, infos = hb.solve(bb, tol=1e-10)
+    hb.close()
+    out += list(zip(us, infos))
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.fixture(autouse=True, scope="module")
+def calibrated():
+    # the process-wide machine calibration runs inside the first setup and
+    # builds a hierarchy of its own: let it happen on hipMalloc, before any
+    # test allocator is registered
+    c2, b2, c3, b3, _, _ = problems()
+    HB.Hierarchy(c2).close()
+    HB.Hierarchy3(c3).close()
+    torch.cuda.synchronize()
+    yield
+
+
+def same(a, b):
+    for (ua, ia), (ub, ib) in zip(a, b):
+        assert ia.cycles == ib.cycles
+        assert torch.equal(ua, ub)
+
+
+def test_solves_from_a_registered_allocator_match_hipmalloc():
+    p = problems()
+    ref = run_all(p)
+    pool = Pool()
+    HB.set_allocator(pool.alloc, pool.free)
+    try:
+        got = run_all(p)
+    finally:
+        HB.set_allocator()
+    same(ref, got)
+    assert pool.n_alloc > 0
+    assert pool.n_free == pool.n_alloc and not pool.live
+    # back on hipMalloc: the pool sees nothing more
+    again = run_all(p)
+    same(ref, again)
+    assert pool.n_alloc == pool.n_free
+
+
+def test_blocks_return_to_their_own_allocator_after_a_switch():
+    c2, b2, c3, b3, _, _ = problems()
+    pool = Pool()
+    HB.set_allocator(pool.alloc, pool.free)
+    try:
+        h = HB.Hierarchy(c2)
+        h3 = HB.Hierarchy3(c3)
+    finally:
+        HB.set_allocator()
+    n = pool.n_alloc
+    assert n > 0 and len(pool.live) == n
+    # a handle built on hipMalloc in between, and solves on the pooled ones
+    h_plain = HB.Hierarchy(c2)
+    u1, _ = h.solve(b2, tol=1e-10)
+    u2, _ = h_plain.solve(b2, tol=1e-10)
+    assert torch.equal(u1, u2)
+    h3.solve(b3, tol=1e-10)
+    h.close()
+    h3.close()
+    h_plain.close()
+    assert pool.n_alloc == n and not pool.live
+
+
+@pytest.mark.parametrize("fail_at", [1, 3, 6])
+def test_a_failing_allocator_fails_setup_without_leaks(fail_at):
+    c2, _, c3, _, _, _ = problems()
+    for make in (lambda: HB.Hierarchy(c2), lambda: HB.Hierarchy3(c3)):
+        pool = Pool(fail_at=fail_at)
+        HB.set_allocator(pool.alloc, pool.free)
+        try:
+            with pytest.raises(HB.HipBMGError) as e:
+                make()
+        finally:
+            HB.set_allocator()
+        assert e.value.status == HB.ENOMEM
+        assert not pool.live, "blocks left behind after a failed setup"
+
+
+def test_misaligned_blocks_are_refused():
+    c2, _, _, _, _, _ = problems()
+    pool = Pool(misalign=True)
+    HB.set_allocator(pool.alloc, pool.free)
+    try:
+        with pytest.raises(HB.HipBMGError) as e:
+            HB.Hierarchy(c2)
+    finally:
+        HB.set_allocator()
+    assert e.value.status == HB.ENOMEM
+    assert pool.n_alloc >= 1 and not pool.live
