@@ -397,6 +397,27 @@ def main():
         log("bench: paper workload %.2f ms per 10 cycles, relres %.2e, rate %.3f"
             % (1e3 * el_p, hist[-1], extra["paper_workload"]["rate_per_cycle"]))
         del hp, cp, bp, up
+        # the paper's redistribution search in its own form (section 4), weak
+        # scaling of its search-time figure: local 568 x 71 on 2:1 processor
+        # grids, the paper's machine parameters; host only
+        scal = []
+        for k in range(1, 16):
+            P = (2 ** ((k + 1) // 2), 2 ** (k // 2))
+            N = (568 * P[0], 71 * P[1])
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                t_ex, _ = HB.paper_search(N, P)
+            t_exh = (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                t_as, path, expanded = HB.paper_astar(N, P)
+            t_ast = (time.perf_counter() - t0) / reps
+            scal.append({"n_p": P[0] * P[1], "processor_grid": list(P), "brute_force_paths": P[0] * P[1] // 2,
+                         "astar_expanded": expanded, "path_length": len(path),
+                         "astar_us": 1e6 * t_ast, "exhaustive_us": 1e6 * t_exh,
+                         "model_s_per_cycle": t_as, "same_optimum": abs(t_as - t_ex) <= 1e-12 * t_ex})
+        extra["paper_search_scaling"] = scal
 
     if not args.no_batch:
         # many independent problems of different sizes in one batched solve:
