@@ -5,8 +5,10 @@ library ``libhipbmg.so`` built in-tree for gfx950.  torch supplies device
 memory (tensor data pointers) and the current stream.  Loading fails loudly if
 the library is missing; there is no fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -114,6 +116,18 @@ _SIGS = {
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _allocator = None   # the registered callbacks, kept alive while registered
+_open_handles = weakref.WeakSet()
+_atexit_registered = False
+
+
+def _close_open_handles():
+    # handles whose memory came from a Python allocator call back into Python
+    # when they are destroyed: do it at exit, before the interpreter tears down
+    for h in list(_open_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -137,7 +151,7 @@ def set_allocator(alloc=None, free=None):
     exception on failure), free(address).  No arguments restores hipMalloc.
     Blocks are returned to the allocator that made them when their handle is
     closed, so keep the callables valid until then."""
-    global _allocator
+    global _allocator, _atexit_registered
     if (alloc is None) != (free is None):
         raise ValueError("give both alloc and free, or neither")
     if alloc is None:
@@ -156,6 +170,9 @@ def set_allocator(alloc=None, free=None):
         except Exception:
             pass
 
+    if not _atexit_registered:
+        atexit.register(_close_open_handles)
+        _atexit_registered = True
     cbs = (ALLOC_FN(_a), FREE_FN(_f))
     _check(lib().hipbmg_set_allocator(ctypes.cast(cbs[0], ctypes.c_void_p), ctypes.cast(cbs[1], ctypes.c_void_p),
                                       None))
@@ -215,6 +232,7 @@ class Hierarchy:
         _check(lib().hipbmg_setup(self.nx, self.ny, self.npt, _ptr(coeffs), ctypes.byref(self.params),
                                   _stream(), ctypes.byref(h)))
         self._h = h
+        _open_handles.add(self)
         self.L = self._levels()
 
     def _levels(self):
@@ -340,6 +358,7 @@ class BatchHierarchy:
         _check(lib().hipbmg_setup_batched(n, nx, ny, npt, ptrs, ctypes.byref(self.params), _stream(),
                                           ctypes.byref(h)))
         self._h = h
+        _open_handles.add(self)
         self.n = n
 
     def close(self):
@@ -506,6 +525,7 @@ class Hierarchy3:
         _check(lib().hipbmg3d_setup(self.nx, self.ny, self.nz, self.npt, _ptr(planes), ctypes.byref(self.params),
                                     _stream(), ctypes.byref(h)))
         self._h = h
+        _open_handles.add(self)
         n = ctypes.c_int()
         _check(lib().hipbmg3d_num_levels(self._h, ctypes.byref(n)))
         self.L = n.value

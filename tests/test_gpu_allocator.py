@@ -3,6 +3,10 @@ memory taken from a caller's allocator (here PyTorch's caching allocator,
 wrapped to count) gives bitwise the same solves as memory from hipMalloc,
 every block goes back to the allocator that made it when its handle is
 destroyed, and a failing allocator makes setup fail cleanly."""
+import os
+import subprocess
+import sys
+
 import pytest
 import torch
 
@@ -155,3 +159,21 @@ def test_misaligned_blocks_are_refused():
         HB.set_allocator()
     assert e.value.status == HB.ENOMEM
     assert pool.n_alloc >= 1 and not pool.live
+
+
+def test_handles_left_open_at_exit_are_closed_cleanly():
+    # a program that takes handle memory from torch's allocator and leaves its
+    # handles open: they are closed at exit, while the callbacks still work
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import torch\n"
+        "from paper_1803_02481_amd import hipbmg as HB, inputs\n"
+        "HB.use_torch_allocator()\n"
+        "c = HB.fv5_from_cells(torch.from_numpy(inputs.cells_log10_blocks(33, 33, block=8, seed=1)).to('cuda:0'))\n"
+        "h = HB.Hierarchy(c)\n"
+        "d = torch.from_numpy(inputs.cells3_log10_blocks(9, 9, 9, block=4, seed=2)).to('cuda:0')\n"
+        "h3 = HB.Hierarchy3(HB.fv7_from_cells(d))\n"
+        "print('built', len(HB._open_handles), flush=True)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "built 2" in r.stdout
