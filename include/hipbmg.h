@@ -317,7 +317,10 @@ hipbmg_status hipbmg_model_levels(hipbmg_handle h, double *grid_us_host, double 
  *   [57..63] 0.
  * Every timing of the solver's kernels is taken cold (after a 512 MB write
  * has evicted the caches), as the kernels run inside a solve.
- * Allocates about 1 GB of device memory for the duration of the call. */
+ * Allocates about 1 GB of device memory for the duration of the call (with
+ * hipMalloc; its internal hierarchy takes the registered allocator, if any).
+ * The parameters are process-wide and replaced at the end of the call: do not
+ * run it while another thread builds a hierarchy. */
 hipbmg_status hipbmg_calibrate(void *stream, double *out_host);
 
 /* Message for the calling thread's most recent failure ("" if none). */

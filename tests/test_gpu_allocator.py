@@ -76,9 +76,9 @@ def run_all(p):
 
 @pytest.fixture(autouse=True, scope="module")
 def calibrated():
-    # the process-wide machine calibration runs inside the first setup and
-    # builds a hierarchy of its own: let it happen on hipMalloc, before any
-    # test allocator is registered
+    # warm-up on hipMalloc: the first hierarchies of each kind in the process
+    # are built before any test allocator is registered, so the counts below
+    # see only the tests' own handles
     c2, b2, c3, b3, _, _ = problems()
     HB.Hierarchy(c2).close()
     HB.Hierarchy3(c3).close()
