@@ -232,3 +232,23 @@ def test_astar_selects_the_papers_path():
     for k, seq in paths.items():
         if k != 1:
             assert HB.paper_path_cost(N, P, seq, **machine()) > t * (1 + 1e-9), k
+
+
+def test_astar_equals_the_exhaustive_search_on_random_setups():
+    # 2D and 3D, processor grids that are not powers of two (the enumeration
+    # clips at P), random machine parameters, limits and coarsest sizes
+    import random
+    rng = random.Random(7)
+    for _ in range(300):
+        D = rng.choice((2, 3))
+        P = tuple(rng.randint(1, 40 if D == 2 else 12) for _ in range(D))
+        if all(p == 1 for p in P):
+            continue
+        N = tuple(p * rng.randint(3, 700 if D == 2 else 80) for p in P)
+        m = dict(limit=rng.choice((5, 9, 17, 33)), coarsest=rng.choice((3, 5)), redundant=rng.randint(0, 1),
+                 alpha=rng.uniform(1e-7, 1e-5), beta=rng.uniform(1e-10, 1e-8), gamma=rng.uniform(1e-11, 1e-9))
+        t_e, _ = HB.paper_search(N, P, **m)
+        t_a, path, expanded = HB.paper_astar(N, P, **m)
+        assert t_a == pytest.approx(t_e, rel=1e-12), (N, P, m)
+        assert HB.paper_path_cost(N, P, path, **m) == pytest.approx(t_a, rel=1e-12)
+        assert expanded >= 1
