@@ -2,8 +2,10 @@
 
 Argument marshalling only: every step of setup and solve runs in the HIP
 library ``libhipbmg.so`` built in-tree for gfx950.  torch supplies device
-memory (tensor data pointers) and the current stream.  Loading fails loudly if
-the library is missing; there is no fallback.
+memory (tensor data pointers, and through hipbmg_set_allocator the handles'
+own memory from its caching allocator, registered when the library is
+loaded) and the current stream.  Loading fails loudly if the library is
+missing; there is no fallback.
 """
 import atexit
 import ctypes
@@ -142,6 +144,10 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        # handle memory from torch's caching allocator: hierarchies rebuilt
+        # every step (the adjoint's setups) then reuse pooled blocks instead
+        # of paying hipMalloc and a synchronising hipFree per block
+        use_torch_allocator()
     return _lib
 
 
@@ -180,13 +186,14 @@ def set_allocator(alloc=None, free=None):
     _allocator = (cbs, _allocator)
 
 
-def use_torch_allocator(device=None):
-    """Take handle memory from PyTorch's caching allocator (on `device`, by
-    default the current one), so that it is pooled with the caller's tensors."""
-    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+def use_torch_allocator():
+    """Take handle memory from PyTorch's caching allocator, on the device that
+    is current when the library allocates, so that it is pooled with the
+    caller's tensors.  This is the binding's default; set_allocator() with no
+    arguments returns to hipMalloc."""
 
     def alloc(nbytes):
-        return torch.cuda.caching_allocator_alloc(nbytes, device=dev)
+        return torch.cuda.caching_allocator_alloc(nbytes, device=torch.cuda.current_device())
 
     set_allocator(alloc, torch.cuda.caching_allocator_delete)
 

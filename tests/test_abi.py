@@ -110,3 +110,4 @@ def test_set_allocator_validates_its_arguments():
     assert L.hipbmg_set_allocator(None, None, None) == HB.OK
     with pytest.raises(ValueError):
         HB.set_allocator(lambda n: 0)
+    HB.use_torch_allocator()   # the binding's default

@@ -76,9 +76,9 @@ def run_all(p):
 
 @pytest.fixture(autouse=True, scope="module")
 def calibrated():
-    # warm-up on hipMalloc: the first hierarchies of each kind in the process
-    # are built before any test allocator is registered, so the counts below
-    # see only the tests' own handles
+    # warm-up: the first hierarchies of each kind in the process are built
+    # before any test allocator is registered, so the counts below see only
+    # the tests' own handles
     c2, b2, c3, b3, _, _ = problems()
     HB.Hierarchy(c2).close()
     HB.Hierarchy3(c3).close()
@@ -94,17 +94,21 @@ def same(a, b):
 
 def test_solves_from_a_registered_allocator_match_hipmalloc():
     p = problems()
-    ref = run_all(p)
+    HB.set_allocator()
+    try:
+        ref = run_all(p)   # hipMalloc
+    finally:
+        HB.use_torch_allocator()
     pool = Pool()
     HB.set_allocator(pool.alloc, pool.free)
     try:
         got = run_all(p)
     finally:
-        HB.set_allocator()
+        HB.use_torch_allocator()
     same(ref, got)
     assert pool.n_alloc > 0
     assert pool.n_free == pool.n_alloc and not pool.live
-    # back on hipMalloc: the pool sees nothing more
+    # back on the binding's default (torch's caching allocator): the pool sees nothing more
     again = run_all(p)
     same(ref, again)
     assert pool.n_alloc == pool.n_free
@@ -118,10 +122,10 @@ def test_blocks_return_to_their_own_allocator_after_a_switch():
         h = HB.Hierarchy(c2)
         h3 = HB.Hierarchy3(c3)
     finally:
-        HB.set_allocator()
+        HB.use_torch_allocator()
     n = pool.n_alloc
     assert n > 0 and len(pool.live) == n
-    # a handle built on hipMalloc in between, and solves on the pooled ones
+    # a handle built on the default allocator in between, and solves on the pooled ones
     h_plain = HB.Hierarchy(c2)
     u1, _ = h.solve(b2, tol=1e-10)
     u2, _ = h_plain.solve(b2, tol=1e-10)
@@ -143,7 +147,7 @@ def test_a_failing_allocator_fails_setup_without_leaks(fail_at):
             with pytest.raises(HB.HipBMGError) as e:
                 make()
         finally:
-            HB.set_allocator()
+            HB.use_torch_allocator()
         assert e.value.status == HB.ENOMEM
         assert not pool.live, "blocks left behind after a failed setup"
 
@@ -156,7 +160,7 @@ def test_misaligned_blocks_are_refused():
         with pytest.raises(HB.HipBMGError) as e:
             HB.Hierarchy(c2)
     finally:
-        HB.set_allocator()
+        HB.use_torch_allocator()
     assert e.value.status == HB.ENOMEM
     assert pool.n_alloc >= 1 and not pool.live
 
@@ -168,7 +172,7 @@ def test_handles_left_open_at_exit_are_closed_cleanly():
     code = (
         "import torch\n"
         "from paper_1803_02481_amd import hipbmg as HB, inputs\n"
-        "HB.use_torch_allocator()\n"
+        "HB.lib()\n"
         "c = HB.fv5_from_cells(torch.from_numpy(inputs.cells_log10_blocks(33, 33, block=8, seed=1)).to('cuda:0'))\n"
         "h = HB.Hierarchy(c)\n"
         "d = torch.from_numpy(inputs.cells3_log10_blocks(9, 9, 9, block=4, seed=2)).to('cuda:0')\n"
