@@ -248,26 +248,37 @@ __global__ void k_rap(StView A, WView P, double *__restrict__ Cc, double *__rest
     const int cnx = P.cnx, cny = P.cny;
     auto cin = [&](int a, int b) { return a >= 1 && a <= cnx - 2 && b >= 1 && b <= cny - 2; };
     double out[5] = {0, 0, 0, 0, 0};
+    // fully unrolled (the summation order is the loops' order): every array
+    // index is a constant, so the stencil and weights stay in registers
     if (cin(I, J)) {
         const int dirs[5][2] = {{0, 0}, {-1, 0}, {0, -1}, {-1, -1}, {1, -1}};
         double pi[3][3];
+        #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
+            #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) pi[dy + 1][dx + 1] = P.col(I, J, dx, dy);
+        #pragma unroll
         for (int d = 0; d < 5; ++d) {
             const int ex = dirs[d][0], ey = dirs[d][1];
             const int KI = I + ex, KJ = J + ey;
             if (!cin(KI, KJ)) continue;
             double pj[3][3];
+            #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
+                #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) pj[dy + 1][dx + 1] = P.col(KI, KJ, dx, dy);
             double acc = 0.0;
+            #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
+                #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const double wp = pi[dy + 1][dx + 1];
                     const int pi_ = 2 * I + dx, pj_ = 2 * J + dy;
                     if (wp == 0.0 || !A.inner(pi_, pj_)) continue;
                     double inner = 0.0;
+                    #pragma unroll
                     for (int sy = -1; sy <= 1; ++sy)
+                        #pragma unroll
                         for (int sx = -1; sx <= 1; ++sx) {
                             // q = p + s, offset from 2K
                             const int ox = dx + sx - 2 * ex, oy = dy + sy - 2 * ey;
