@@ -131,6 +131,68 @@ def test_interp_one_dimensional_coefficient_is_flux_weighted():
             assert P[j, i, 0, 1] == pytest.approx(wE, rel=1e-14)
 
 
+def _layered_expected_weight(cond, i, j, a, b, axis, nc_x, nc_y):
+    """Closed-form interpolation weight of fine vertex (i, j) on coarse corner
+    ((i>>1)+a, (j>>1)+b) for a medium layered along `axis` (0: D = D(x),
+    1: D = D(y)).  cond[k] is the level's 1D conductance between vertex k and
+    k+1 along that axis.  Along the layered axis an odd index takes the 1D
+    flux weight cond_W / (cond_W + cond_E); along the other axis an odd index
+    takes the linear 1/2; an even index is injected.  Coarse boundary vertices
+    carry no weight."""
+    I, J = (i >> 1) + a, (j >> 1) + b
+    if not (1 <= I <= nc_x - 2 and 1 <= J <= nc_y - 2):
+        return 0.0
+    k, c, m = (i, a, j) if axis == 0 else (j, b, i)
+    if k & 1:
+        w = (cond[k - 1], cond[k])[c] / (cond[k - 1] + cond[k])
+    else:
+        w = 1.0 if c == 0 else 0.0
+    if m & 1:
+        w *= 0.5
+    elif (b if axis == 0 else a) == 1:
+        w = 0.0
+    return w
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_interp_layered_media_every_row_kind_on_every_level(axis):
+    # Section 2, operator-induced interpolation from continuity of the normal
+    # flux.  For D = D(x) the 5-point operator is K_x (x) I + diag(m) (x) K_y,
+    # every collapse reduces to the 1D flux balance along x, and the result is
+    # a tensor product: x-line vertices take the 1D flux weight, y-line vertices
+    # 1/2 and 1/2, cell centres 1/2 times the flux weight.  The Galerkin
+    # product keeps this form, with the 1D conductances of the next level
+    # those of two fine edges in series.  D = D(y) is the same with the axes
+    # exchanged.  A cell-centre row that took a mirrored neighbour, a y-line
+    # collapse over the wrong direction or a lost boundary zero fails here.
+    n = 65
+    rng = np.random.default_rng(17 + axis)
+    layer = 10.0 ** rng.uniform(-2, 2, size=n - 1)
+    D = np.tile(layer, (n - 1, 1)) if axis == 0 else np.tile(layer[:, None], (1, n - 1))
+    hier = O.Hierarchy(O.fv5(D))
+    cond = layer.copy()       # finest level: the edge between k and k+1 cuts cell k
+    checked = 0
+    for l in range(hier.L - 1, 0, -1):
+        P = hier.interp(l)
+        ny, nx = P.shape[:2]
+        ncy, ncx = hier.size(l - 1)
+        # the collapse denominators cancel the cross-direction connections,
+        # which on the Galerkin levels of a 1e4-contrast medium exceed the flux
+        # terms by orders of magnitude (measured over seeds: <= 4.4e-16 on the
+        # finest level, <= 1.1e-12 below); a wrong neighbour or direction
+        # errs by O(0.1)
+        tol = 2e-15 if l == hier.L - 1 else 5e-12
+        for j in range(1, ny - 1):
+            for i in range(1, nx - 1):
+                for b in (0, 1):
+                    for a in (0, 1):
+                        w = _layered_expected_weight(cond, i, j, a, b, axis, ncx, ncy)
+                        assert abs(P[j, i, b, a] - w) <= tol, (l, i, j, a, b, P[j, i], w)
+                        checked += 1
+        cond = 1.0 / (1.0 / cond[0::2] + 1.0 / cond[1::2])
+    assert checked > 15000
+
+
 def test_interp_reproduces_constants_away_from_the_boundary():
     planes, _ = rand_planes(65, seed=11)
     hier = O.Hierarchy(planes)
