@@ -31,7 +31,9 @@
  * the tests pin them by closed forms (bilinear for D=1, flux-weighted for
  * coefficients that vary in one direction only) rather than by BoxMG itself.
  *
- * Floating point: double throughout, built with -ffp-contract=off.
+ * Floating point: double throughout, built with -ffp-contract=off, except the
+ * FP32 edge-form section at the end, which emulates the inner solver of mixed
+ * precision with float arithmetic on a once-demoted copy of every level.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -46,6 +48,11 @@ typedef struct {
                    corners ((i>>1)+a, (j>>1)+b) of level l-1, index 2*b+a.
                    Unused on the coarsest level.                              */
     double *x, *b, *r;
+    /* FP32 edge form (mixed precision), built by oracle32_demote:
+     * A32[..][k] for k != 4 is the connection -A(p, p+d) rounded to float,
+     * A32[..][4] the excess A(p,p) - (sum of the connections) computed in
+     * double and rounded to float; P32 is P rounded to float. */
+    float *A32, *P32, *x32, *b32, *r32;
 } olevel;
 
 typedef struct {
@@ -369,6 +376,11 @@ void oracle_free(void *hv)
         free(h->lev[l].x);
         free(h->lev[l].b);
         free(h->lev[l].r);
+        free(h->lev[l].A32);
+        free(h->lev[l].P32);
+        free(h->lev[l].x32);
+        free(h->lev[l].b32);
+        free(h->lev[l].r32);
     }
     free(h->cidx);
     free(h->chol);
@@ -627,4 +639,282 @@ void oracle_grad_logD(int nx, int ny, const double *cellD, const double *u, cons
             }
             g[(size_t)cj * (nx - 1) + ci] = -0.5 * cellD[(size_t)cj * (nx - 1) + ci] * s;
         }
+}
+
+/* ---------------------------------------------------------------------------
+ * FP32 edge form: the inner solver of mixed-precision iterative refinement.
+ *
+ * Setup stays FP64; every level is demoted once.  Rounding the matrix entries
+ * of a pure-diffusion row to float would break its zero row sum by about one
+ * float ulp of the diagonal, which makes the FP32 operator a much worse model
+ * of the FP64 one as the grid grows.  The edge form keeps the connections
+ * c_pq = -A(p,q) (rounded to float) and the excess E_p = A(p,p) - sum_q c_pq
+ * (formed in double, then rounded), and applies the operator as
+ *     (A x)_p = sum_q c_pq (x_p - x_q) + E_p x_p ,
+ * whose diagonal is sum_q c_pq + E_p.  A row whose FP64 sum is zero keeps an
+ * excess of FP64 rounding size, so constants stay in the near null space.
+ * All arithmetic of the relaxation, residual, restriction and interpolation is
+ * float; residual norms are accumulated in double; the coarsest level is
+ * solved with the FP64 Cholesky factor (its right-hand side widened to double,
+ * the solution rounded to float).
+ * ------------------------------------------------------------------------- */
+void oracle32_demote(void *hv)
+{
+    ohier *h = hv;
+    for (int l = 0; l < h->L; ++l) {
+        olevel *lv = &h->lev[l];
+        size_t n = (size_t)lv->nx * lv->ny;
+        if (!lv->A32) {
+            lv->A32 = calloc(n * 9, sizeof(float));
+            lv->P32 = calloc(n * 4, sizeof(float));
+            lv->x32 = calloc(n, sizeof(float));
+            lv->b32 = calloc(n, sizeof(float));
+            lv->r32 = calloc(n, sizeof(float));
+        }
+        for (int j = 1; j <= lv->ny - 2; ++j)
+            for (int i = 1; i <= lv->nx - 2; ++i) {
+                float *e = &lv->A32[((size_t)j * lv->nx + i) * 9];
+                double conn_sum = 0.0;
+                for (int k = 0; k < 9; ++k) {
+                    if (k == 4) continue;
+                    double c = -lv->A[((size_t)j * lv->nx + i) * 9 + k];
+                    e[k] = (float)c;
+                    conn_sum += c;
+                }
+                e[4] = (float)(*Aent(lv, i, j, 0, 0) - conn_sum);
+            }
+        for (size_t k = 0; k < n * 4; ++k) lv->P32[k] = (float)lv->P[k];
+    }
+}
+
+void oracle32_get_level(void *hv, int l, float *A32, float *P32)
+{
+    ohier *h = hv;
+    const olevel *lv = &h->lev[l];
+    size_t n = (size_t)lv->nx * lv->ny;
+    memcpy(A32, lv->A32, n * 9 * sizeof(float));
+    if (P32) memcpy(P32, lv->P32, n * 4 * sizeof(float));
+}
+
+/* (A x)_p in edge form, and the diagonal sum_q c_pq + E_p */
+static float apply_row32(const olevel *lv, const float *x, int i, int j, float *diag)
+{
+    const float *e = &lv->A32[((size_t)j * lv->nx + i) * 9];
+    float xp = x[(size_t)j * lv->nx + i];
+    float s = 0.0f, d = 0.0f;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            int k = (dy + 1) * 3 + (dx + 1);
+            if (k == 4) continue;
+            float xq = x[(size_t)(j + dy) * lv->nx + (i + dx)];
+            s += e[k] * (xp - xq);
+            d += e[k];
+        }
+    s += e[4] * xp;
+    *diag = d + e[4];
+    return s;
+}
+
+static float diag32(const olevel *lv, int i, int j)
+{
+    const float *e = &lv->A32[((size_t)j * lv->nx + i) * 9];
+    float d = 0.0f;
+    for (int k = 0; k < 9; ++k)
+        if (k != 4) d += e[k];
+    return d + e[4];
+}
+
+static void gs_sweep32(const olevel *lv, float *x, const float *b)
+{
+    for (int colour = 0; colour < 4; ++colour)
+        for (int j = 1; j <= lv->ny - 2; ++j)
+            for (int i = 1; i <= lv->nx - 2; ++i) {
+                if ((i % 2) + 2 * (j % 2) != colour) continue;
+                size_t p = (size_t)j * lv->nx + i;
+                float d;
+                float r = b[p] - apply_row32(lv, x, i, j, &d);
+                x[p] += r / d;
+            }
+}
+
+static void residual32(const olevel *lv, const float *x, const float *b, float *r)
+{
+    memset(r, 0, (size_t)lv->nx * lv->ny * sizeof(float));
+    for (int j = 1; j <= lv->ny - 2; ++j)
+        for (int i = 1; i <= lv->nx - 2; ++i) {
+            size_t p = (size_t)j * lv->nx + i;
+            float d;
+            r[p] = b[p] - apply_row32(lv, x, i, j, &d);
+        }
+}
+
+static void restrict32(const olevel *f, const float *r, const olevel *c, float *bc)
+{
+    memset(bc, 0, (size_t)c->nx * c->ny * sizeof(float));
+    for (int j = 1; j <= f->ny - 2; ++j)
+        for (int i = 1; i <= f->nx - 2; ++i) {
+            const float *pr = &f->P32[((size_t)j * f->nx + i) * 4];
+            for (int k = 0; k < 4; ++k)
+                if (pr[k] != 0.0f)
+                    bc[(size_t)((j >> 1) + (k >> 1)) * c->nx + (i >> 1) + (k & 1)] +=
+                        pr[k] * r[(size_t)j * f->nx + i];
+        }
+}
+
+/* x += P x_c, plus r / diag at vertices that are not coarse points */
+static void interp_correct32(const olevel *f, float *x, const float *r, const olevel *c, const float *xc,
+                             int rescorr)
+{
+    for (int j = 1; j <= f->ny - 2; ++j)
+        for (int i = 1; i <= f->nx - 2; ++i) {
+            const float *pr = &f->P32[((size_t)j * f->nx + i) * 4];
+            float s = 0.0f;
+            for (int k = 0; k < 4; ++k)
+                s += pr[k] * xc[(size_t)((j >> 1) + (k >> 1)) * c->nx + (i >> 1) + (k & 1)];
+            size_t p = (size_t)j * f->nx + i;
+            x[p] += s;
+            if (rescorr && !(i % 2 == 0 && j % 2 == 0)) x[p] += r[p] / diag32(f, i, j);
+        }
+}
+
+static void coarse_solve32(const ohier *h, float *x, const float *b)
+{
+    const olevel *c = &h->lev[0];
+    size_t n = (size_t)c->nx * c->ny;
+    double *bd = calloc(n, sizeof(double)), *xd = calloc(n, sizeof(double));
+    for (size_t k = 0; k < n; ++k) bd[k] = (double)b[k];
+    coarse_solve(h, xd, bd);
+    for (size_t k = 0; k < n; ++k) x[k] = (float)xd[k];
+    free(bd);
+    free(xd);
+}
+
+static void vcycle32(ohier *h, int l, float *x, const float *b)
+{
+    olevel *f = &h->lev[l];
+    if (l == 0) {
+        coarse_solve32(h, x, b);
+        return;
+    }
+    olevel *c = &h->lev[l - 1];
+    for (int k = 0; k < h->nu1; ++k) gs_sweep32(f, x, b);
+    residual32(f, x, b, f->r32);
+    restrict32(f, f->r32, c, c->b32);
+    memset(c->x32, 0, (size_t)c->nx * c->ny * sizeof(float));
+    vcycle32(h, l - 1, c->x32, c->b32);
+    interp_correct32(f, x, f->r32, c, c->x32, h->rescorr);
+    for (int k = 0; k < h->nu2; ++k) gs_sweep32(f, x, b);
+}
+
+static double norm32_interior(const olevel *lv, const float *v)
+{
+    double s = 0.0;
+    for (int j = 1; j <= lv->ny - 2; ++j)
+        for (int i = 1; i <= lv->nx - 2; ++i) {
+            double a = (double)v[(size_t)j * lv->nx + i];
+            s += a * a;
+        }
+    return sqrt(s);
+}
+
+void oracle32_smooth(void *hv, int l, const float *b, float *x, int sweeps)
+{
+    ohier *h = hv;
+    for (int k = 0; k < sweeps; ++k) gs_sweep32(&h->lev[l], x, b);
+}
+
+void oracle32_residual(void *hv, int l, const float *b, const float *x, float *r)
+{
+    ohier *h = hv;
+    residual32(&h->lev[l], x, b, r);
+}
+
+void oracle32_restrict(void *hv, int l, const float *r, float *bc)
+{
+    ohier *h = hv;
+    restrict32(&h->lev[l], r, &h->lev[l - 1], bc);
+}
+
+void oracle32_interp_correct(void *hv, int l, float *x, const float *r, const float *xc, int rescorr)
+{
+    ohier *h = hv;
+    interp_correct32(&h->lev[l], x, r, &h->lev[l - 1], xc, rescorr);
+}
+
+void oracle32_vcycle(void *hv, const float *b, float *x)
+{
+    ohier *h = hv;
+    vcycle32(h, h->L - 1, x, b);
+}
+
+/* The inner solve of one refinement step: V-cycles on A e = r from e = 0,
+ * each followed by the inner relative residual ||r - A e|| / rnorm (rnorm the
+ * FP64 norm of the outer residual), until it is <= inner_tol or `cycles`
+ * cycles have run.  Returns the number of cycles; hist[k] is the inner
+ * relative residual after cycle k+1. */
+int oracle32_inner(void *hv, const float *r, float *e, int cycles, double rnorm, double inner_tol, double *hist)
+{
+    ohier *h = hv;
+    olevel *f = &h->lev[h->L - 1];
+    size_t n = (size_t)f->nx * f->ny;
+    float *rr = calloc(n, sizeof(float));
+    memset(e, 0, n * sizeof(float));
+    int k = 0;
+    while (k < cycles) {
+        vcycle32(h, h->L - 1, e, r);
+        residual32(f, e, r, rr);
+        double rel = norm32_interior(f, rr) / rnorm;
+        if (hist) hist[k] = rel;
+        ++k;
+        if (rel <= inner_tol) break;
+    }
+    free(rr);
+    return k;
+}
+
+/* Mixed precision: FP64 iterative refinement around FP32 inner solves.  Each
+ * step forms the outer residual r = b - A u in FP64 and its relative norm
+ * (hist[step]); it stops when that is <= tol or when the cycle budget is
+ * spent, else demotes r to float, runs an inner solve of at most
+ * min(inner_max, max_cycles - cycles done) cycles to inner_tol and adds the
+ * widened correction to u.  Returns the FP32 cycles run; *steps is the number
+ * of inner solves. */
+int oracle_solve_mixed(void *hv, const double *bin, double *u, double tol, int max_cycles, int inner_max,
+                       double inner_tol, double *hist, int *steps)
+{
+    ohier *h = hv;
+    olevel *f = &h->lev[h->L - 1];
+    size_t n = (size_t)f->nx * f->ny;
+    double *b = calloc(n, sizeof(double)), *r = calloc(n, sizeof(double));
+    float *r32 = calloc(n, sizeof(float)), *e32 = calloc(n, sizeof(float));
+    for (int j = 1; j <= f->ny - 2; ++j)
+        for (int i = 1; i <= f->nx - 2; ++i) b[(size_t)j * f->nx + i] = bin[(size_t)j * f->nx + i];
+    for (int j = 0; j < f->ny; ++j)
+        for (int i = 0; i < f->nx; ++i)
+            if (!interior(f, i, j)) u[(size_t)j * f->nx + i] = 0.0;
+    double bn = norm_interior(f, b);
+    int cycles = 0, st = 0;
+    if (bn == 0.0) {
+        memset(u, 0, n * sizeof(double));
+    } else {
+        for (;;) {
+            residual(f, u, b, r);
+            double rn = norm_interior(f, r);
+            double rel = rn / bn;
+            if (hist) hist[st] = rel;
+            if (rel <= tol || cycles >= max_cycles) break;
+            for (size_t k = 0; k < n; ++k) r32[k] = (float)r[k];
+            int cap = inner_max < max_cycles - cycles ? inner_max : max_cycles - cycles;
+            cycles += oracle32_inner(h, r32, e32, cap, rn, inner_tol, NULL);
+            for (int j = 1; j <= f->ny - 2; ++j)
+                for (int i = 1; i <= f->nx - 2; ++i) u[(size_t)j * f->nx + i] += (double)e32[(size_t)j * f->nx + i];
+            ++st;
+        }
+    }
+    if (steps) *steps = st;
+    free(b);
+    free(r);
+    free(r32);
+    free(e32);
+    return cycles;
 }

@@ -61,6 +61,19 @@ def lib():
         L.oracle_grad_logD.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.oracle_fv5_aniso.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
                                        _D, _D, _D]
+        F = ctypes.POINTER(ctypes.c_float)
+        L.oracle32_demote.argtypes = [ctypes.c_void_p]
+        L.oracle32_get_level.argtypes = [ctypes.c_void_p, ctypes.c_int, F, F]
+        L.oracle32_smooth.argtypes = [ctypes.c_void_p, ctypes.c_int, F, F, ctypes.c_int]
+        L.oracle32_residual.argtypes = [ctypes.c_void_p, ctypes.c_int, F, F, F]
+        L.oracle32_restrict.argtypes = [ctypes.c_void_p, ctypes.c_int, F, F]
+        L.oracle32_interp_correct.argtypes = [ctypes.c_void_p, ctypes.c_int, F, F, F, ctypes.c_int]
+        L.oracle32_vcycle.argtypes = [ctypes.c_void_p, F, F]
+        L.oracle32_inner.argtypes = [ctypes.c_void_p, F, F, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
+        L.oracle32_inner.restype = ctypes.c_int
+        L.oracle_solve_mixed.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_solve_mixed.restype = ctypes.c_int
         I = ctypes.c_int
         IP = ctypes.POINTER(ctypes.c_int)
         L.oracle3_fv7.argtypes = [I, I, I, _D, _D, _D, _D, _D]
@@ -86,6 +99,11 @@ def lib():
 def _p(a):
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_D)
+
+
+def _f(a):
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
 def fv5(cellD):
@@ -206,6 +224,84 @@ class Hierarchy:
         x = np.zeros_like(b)
         lib().oracle_coarse_solve(self._h, _p(b), _p(x))
         return x
+
+    # ---- FP32 edge form (inner solver of mixed precision) ----------------
+    def demote(self):
+        """Build the FP32 edge-form copy of every level (once per hierarchy)."""
+        if not getattr(self, "_has32", False):
+            lib().oracle32_demote(self._h)
+            self._has32 = True
+
+    def level32(self, l):
+        """FP32 edge form of level l: ([ny][nx][3][3] with the connections
+        -A(p, p+d) off the centre and the excess at the centre, [ny][nx][2][2]
+        interpolation rows), both float32."""
+        self.demote()
+        ny, nx = self.size(l)
+        A = np.zeros((ny, nx, 9), np.float32)
+        P = np.zeros((ny, nx, 4), np.float32)
+        lib().oracle32_get_level(self._h, l, _f(A), _f(P))
+        return A.reshape(ny, nx, 3, 3), P.reshape(ny, nx, 2, 2)
+
+    def smooth32(self, l, b, x, sweeps=1):
+        self.demote()
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        x = np.array(x, dtype=np.float32, order="C")
+        lib().oracle32_smooth(self._h, l, _f(b), _f(x), sweeps)
+        return x
+
+    def residual32(self, l, b, x):
+        self.demote()
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        r = np.zeros_like(b)
+        lib().oracle32_residual(self._h, l, _f(b), _f(x), _f(r))
+        return r
+
+    def restrict32(self, l, r):
+        self.demote()
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        bc = np.zeros(self.size(l - 1), np.float32)
+        lib().oracle32_restrict(self._h, l, _f(r), _f(bc))
+        return bc
+
+    def interp_correct32(self, l, x, r, xc, rescorr=1):
+        self.demote()
+        x = np.array(x, dtype=np.float32, order="C")
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        xc = np.ascontiguousarray(xc, dtype=np.float32)
+        lib().oracle32_interp_correct(self._h, l, _f(x), _f(r), _f(xc), rescorr)
+        return x
+
+    def vcycle32(self, b, x):
+        self.demote()
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        x = np.array(x, dtype=np.float32, order="C")
+        lib().oracle32_vcycle(self._h, _f(b), _f(x))
+        return x
+
+    def inner32(self, r, cycles, rnorm, inner_tol=0.0):
+        """One refinement step's inner solve of A e = r from e = 0: returns
+        (e, inner relative residual after each cycle)."""
+        self.demote()
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        e = np.zeros_like(r)
+        hist = np.zeros(max(cycles, 1))
+        k = lib().oracle32_inner(self._h, _f(r), _f(e), cycles, float(rnorm), float(inner_tol), _p(hist))
+        return e, hist[:k]
+
+    def solve_mixed(self, b, u0=None, tol=1e-10, max_cycles=500, inner_max=12, inner_tol=1e-5):
+        """FP64 iterative refinement around FP32 inner solves: returns
+        (u, outer relative residual before each step and at the end, FP32
+        cycles run, inner solves)."""
+        self.demote()
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64, order="C")
+        hist = np.zeros(max_cycles + 2)
+        steps = ctypes.c_int(0)
+        cyc = lib().oracle_solve_mixed(self._h, _p(b), _p(u), tol, max_cycles, inner_max, inner_tol, _p(hist),
+                                       ctypes.byref(steps))
+        return u, hist[:steps.value + 1], cyc, steps.value
 
 
 # --------------------------------------------------------------------------
