@@ -37,9 +37,14 @@
  *   - Every call returns a hipbmg_status and never throws; hipbmg_last_error()
  *     gives a message for the calling thread's last failure.
  *   - The caller owns every array it passes.  A handle owns all device memory
- *     of its hierarchy (allocated with hipMalloc at setup, freed by
- *     hipbmg_destroy).  A handle serves one stream at a time; calls on one
- *     handle must not overlap.
+ *     of its hierarchy.  Setup takes it from the allocator registered with
+ *     hipbmg_set_allocator, or from hipMalloc if none is registered; solves
+ *     allocate nothing.  hipbmg_destroy returns every block to the allocator
+ *     that made it.  When any block came from a registered allocator, destroy
+ *     first synchronises the whole device (hipDeviceSynchronize), because
+ *     such an allocator may hand the block out again at once; it therefore
+ *     waits for work on every stream, not only the caller's.  A handle serves
+ *     one stream at a time; calls on one handle must not overlap.
  */
 #ifndef HIPBMG_H
 #define HIPBMG_H
@@ -200,6 +205,40 @@ hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b,
 hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
                                       const double *q, const double *xc, int rescorr,
                                       double *sumsq_host, void *stream);
+
+/* The FP32 levels of a mixed-precision handle (precision HIPBMG_MIXED; any
+ * other handle gives HIPBMG_EINVAL).  Mixed precision keeps setup in FP64 and
+ * demotes every level once to an edge form: the connections W, S, SW, SE
+ * rounded to float, and in place of C the excess E = C - (sum of the eight
+ * connections of the vertex, including those that couple to boundary
+ * vertices), formed in FP64 and rounded.  The FP32 kernels apply
+ *   (A x)_p = sum_q conn_pq (x_p - x_q) + E_p x_p,  diagonal sum_q conn_pq + E_p,
+ * so rows of pure diffusion keep a zero row sum after rounding.  The inner
+ * FP32 V-cycles of iterative refinement run on these levels; the coarsest
+ * level is solved with the FP64 Cholesky factor.
+ *   get_level32: level l's planes {E, W, S, SW, SE} into stencil_out
+ *     ([5][ny][nx], float, device) and, if interp_out is not NULL (l >= 1),
+ *     the FP32 weights into interp_out ([8][cny][cnx], plane order as in
+ *     hipbmg_get_interp).
+ *   op32_smooth, op32_smooth_restrict, op32_interp_smooth: the FP32 forms of
+ *     the three single operations above, on float arrays; q holds r / diag.
+ *   op32_inner: the inner solve of one refinement step: up to `cycles` FP32
+ *     V-cycles (Algorithm 1, the finest level's passes as in a solve) on
+ *     A e = r from e = 0, each followed by the test
+ *     ||r - A e||_2 / rnorm <= inner_tol (norm accumulated in FP64 over
+ *     interior vertices; inner_tol 0 runs every cycle).  r: [ny][nx] float
+ *     (the demoted outer residual), e: [ny][nx] float output, rnorm > 0 the
+ *     FP64 norm of the outer residual.  hist_host (NULL or [cycles]) receives
+ *     the inner relative residual after each cycle run, cycles_host (NULL or
+ *     one int) their number. */
+hipbmg_status hipbmg_get_level32(hipbmg_handle h, int l, float *stencil_out, float *interp_out, void *stream);
+hipbmg_status hipbmg_op32_smooth(hipbmg_handle h, int l, const float *b, float *x, int sweeps, void *stream);
+hipbmg_status hipbmg_op32_smooth_restrict(hipbmg_handle h, int l, const float *b, float *x, int sweeps,
+                                          float *q, float *bc, void *stream);
+hipbmg_status hipbmg_op32_interp_smooth(hipbmg_handle h, int l, const float *b, float *x, const float *q,
+                                        const float *xc, int rescorr, double *sumsq_host, void *stream);
+hipbmg_status hipbmg_op32_inner(hipbmg_handle h, const float *r, float *e, int cycles, double rnorm,
+                                double inner_tol, double *hist_host, int *cycles_host, void *stream);
 
 /* Batched solves of many independent problems of different sizes (each with
  * its own hierarchy, built as by hipbmg_setup, and its own collapse level).

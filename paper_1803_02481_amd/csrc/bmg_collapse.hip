@@ -767,7 +767,8 @@ __global__ __launch_bounds__(256) void k_finalize_batched(const double *__restri
                                                           const int *__restrict__ cnt,
                                                           const double *__restrict__ denom,
                                                           double *__restrict__ out,
-                                                          int *__restrict__ active, double tol)
+                                                          int *__restrict__ active, double tol,
+                                                          const double *__restrict__ tol_dev)
 {
     __shared__ double sh[256];
     const int p = blockIdx.x;
@@ -784,16 +785,17 @@ __global__ __launch_bounds__(256) void k_finalize_batched(const double *__restri
     if (threadIdx.x == 0) {
         const double v = denom ? sqrt(sh[0]) / denom[p] : sqrt(sh[0]);
         out[p] = v;
-        if (active && (!(v > tol) || !isfinite(v))) active[p] = 0;
+        const double t = tol_dev ? tol_dev[0] : tol;
+        if (active && (!(v > t) || !isfinite(v))) active[p] = 0;
     }
 }
 
 hipError_t launch_finalize_batched(const double *partials, const int *off, const int *cnt,
-                                   const double *denom, double *out, int *active, double tol, int nprob,
-                                   hipStream_t s)
+                                   const double *denom, double *out, int *active, double tol,
+                                   const double *tol_dev, int nprob, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize_batched, dim3(nprob), dim3(256), 0, s, partials, off, cnt, denom, out,
-                       active, tol);
+                       active, tol, tol_dev);
     return hipGetLastError();
 }
 

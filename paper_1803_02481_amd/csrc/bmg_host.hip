@@ -1377,33 +1377,51 @@ extern "C" hipbmg_status hipbmg_get_interp(hipbmg_handle h, int l, double *out, 
     return HIPBMG_OK;
 }
 
-static hipbmg_status to_pitched(double *dst, int pitch, const double *src, int nx, int ny, hipStream_t s)
+template <typename T>
+static hipbmg_status to_pitched(T *dst, int pitch, const T *src, int nx, int ny, hipStream_t s)
 {
-    HIPCHK(hipMemcpy2DAsync(dst, pitch * sizeof(double), src, nx * sizeof(double), nx * sizeof(double),
-                            ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(dst, pitch * sizeof(T), src, nx * sizeof(T), nx * sizeof(T), ny,
+                            hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_zero_ring(dst, nx, ny, pitch, s));
     return HIPBMG_OK;
 }
 
-static hipbmg_status from_pitched(double *dst, const double *src, int pitch, int nx, int ny, hipStream_t s)
+template <typename T>
+static hipbmg_status from_pitched(T *dst, const T *src, int pitch, int nx, int ny, hipStream_t s)
 {
-    HIPCHK(hipMemcpy2DAsync(dst, nx * sizeof(double), src, pitch * sizeof(double), nx * sizeof(double),
-                            ny, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(dst, nx * sizeof(T), src, pitch * sizeof(T), nx * sizeof(T), ny,
+                            hipMemcpyDeviceToDevice, s));
     return HIPBMG_OK;
 }
 
-extern "C" hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *b, double *x,
-                                          int sweeps, void *stream)
+// The levels a single operation of precision T runs on: the FP64 hierarchy,
+// or the FP32 edge-form copy that a mixed-precision handle holds.
+static hipbmg_status op_levels(hipbmg_hier *h, const std::vector<LevelDev<double>> **lv)
+{
+    *lv = &h->lv;
+    return HIPBMG_OK;
+}
+
+static hipbmg_status op_levels(hipbmg_hier *h, const std::vector<LevelDev<float>> **lv)
+{
+    if (h->lv32.empty()) return fail(HIPBMG_EINVAL, "FP32 operations need a mixed-precision handle");
+    *lv = &h->lv32;
+    return HIPBMG_OK;
+}
+
+template <typename T>
+static hipbmg_status op_smooth(hipbmg_hier *h, int l, const T *b, T *x, int sweeps, hipStream_t s)
 {
     if (!h || !b || !x) return fail(HIPBMG_EINVAL, "null argument");
     if (l < 0 || l >= h->L || sweeps < 0) return fail(HIPBMG_EINVAL, "bad level or sweeps");
-    hipStream_t s = (hipStream_t)stream;
-    const LevelDev<double> &A = h->lv[l];
+    const std::vector<LevelDev<T>> *lv = nullptr;
+    STCHK(op_levels(h, &lv));
+    const LevelDev<T> &A = (*lv)[l];
     STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
     STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
     int xb = 0;
     for (int k = 0; k < sweeps; ++k) {
-        StreamArgs<double> a = base_args(A, h->rb[l]);
+        StreamArgs<T> a = base_args(A, h->rb[l]);
         a.x_in = A.x[xb];
         a.x_out = A.x[1 - xb];
         HIPCHK(run_stream(A, SV_SWEEP, a, s));
@@ -1414,19 +1432,21 @@ extern "C" hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *
     return HIPBMG_OK;
 }
 
-extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
-                                                   int sweeps, double *q, double *bc, void *stream)
+template <typename T>
+static hipbmg_status op_smooth_restrict(hipbmg_hier *h, int l, const T *b, T *x, int sweeps, T *q, T *bc,
+                                        hipStream_t s)
 {
     if (!h || !b || !x || !q || !bc) return fail(HIPBMG_EINVAL, "null argument");
     if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
     if (sweeps != 1 && sweeps != 2) return fail(HIPBMG_EINVAL, "sweeps must be 1 or 2");
-    hipStream_t s = (hipStream_t)stream;
-    const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
+    const std::vector<LevelDev<T>> *lv = nullptr;
+    STCHK(op_levels(h, &lv));
+    const LevelDev<T> &A = (*lv)[l], &C = (*lv)[l - 1];
     STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
     STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
-    HIPCHK(hipMemsetAsync(A.q, 0, A.plane * sizeof(double), s));
-    HIPCHK(hipMemsetAsync(C.b, 0, C.plane * sizeof(double), s));
-    StreamArgs<double> a = base_args(A, h->rb[l]);
+    HIPCHK(hipMemsetAsync(A.q, 0, A.plane * sizeof(T), s));
+    HIPCHK(hipMemsetAsync(C.b, 0, C.plane * sizeof(T), s));
+    StreamArgs<T> a = base_args(A, h->rb[l]);
     a.x_in = A.x[0];
     a.x_out = A.x[1];
     a.q_out = A.q;
@@ -1444,19 +1464,20 @@ extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const
     return HIPBMG_OK;
 }
 
-extern "C" hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
-                                                 const double *q, const double *xc, int rescorr,
-                                                 double *sumsq_host, void *stream)
+template <typename T>
+static hipbmg_status op_interp_smooth(hipbmg_hier *h, int l, const T *b, T *x, const T *q, const T *xc,
+                                      int rescorr, double *sumsq_host, hipStream_t s)
 {
     if (!h || !b || !x || !q || !xc) return fail(HIPBMG_EINVAL, "null argument");
     if (l < 1 || l >= h->L) return fail(HIPBMG_EINVAL, "level must be in [1, L)");
-    hipStream_t s = (hipStream_t)stream;
-    const LevelDev<double> &A = h->lv[l], &C = h->lv[l - 1];
+    const std::vector<LevelDev<T>> *lv = nullptr;
+    STCHK(op_levels(h, &lv));
+    const LevelDev<T> &A = (*lv)[l], &C = (*lv)[l - 1];
     STCHK(to_pitched(A.b, A.pitch, b, A.nx, A.ny, s));
     STCHK(to_pitched(A.x[0], A.pitch, x, A.nx, A.ny, s));
     STCHK(to_pitched(A.q, A.pitch, q, A.nx, A.ny, s));
     STCHK(to_pitched(C.x[1], C.pitch, xc, C.nx, C.ny, s));
-    StreamArgs<double> a = base_args(A, h->rb_up[l]);
+    StreamArgs<T> a = base_args(A, h->rb_up[l]);
     a.x_in = A.x[0];
     a.x_out = A.x[1];
     a.xc = C.x[1];
@@ -1477,6 +1498,97 @@ extern "C" hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const d
     }
     STCHK(from_pitched(x, A.x[1], A.pitch, A.nx, A.ny, s));
     HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_op_smooth(hipbmg_handle h, int l, const double *b, double *x,
+                                          int sweeps, void *stream)
+{
+    return op_smooth<double>(h, l, b, x, sweeps, (hipStream_t)stream);
+}
+
+extern "C" hipbmg_status hipbmg_op_smooth_restrict(hipbmg_handle h, int l, const double *b, double *x,
+                                                   int sweeps, double *q, double *bc, void *stream)
+{
+    return op_smooth_restrict<double>(h, l, b, x, sweeps, q, bc, (hipStream_t)stream);
+}
+
+extern "C" hipbmg_status hipbmg_op_interp_smooth(hipbmg_handle h, int l, const double *b, double *x,
+                                                 const double *q, const double *xc, int rescorr,
+                                                 double *sumsq_host, void *stream)
+{
+    return op_interp_smooth<double>(h, l, b, x, q, xc, rescorr, sumsq_host, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 edge-form levels of a mixed-precision handle
+// ---------------------------------------------------------------------------
+extern "C" hipbmg_status hipbmg_get_level32(hipbmg_handle h, int l, float *stencil_out, float *interp_out,
+                                            void *stream)
+{
+    if (!h || !stencil_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (l < 0 || l >= h->L) return fail(HIPBMG_EINVAL, "level out of range");
+    if (interp_out && l < 1) return fail(HIPBMG_EINVAL, "level 0 has no interpolation weights");
+    const std::vector<LevelDev<float>> *lv = nullptr;
+    STCHK(op_levels(h, &lv));
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<float> &A = (*lv)[l];
+    for (int k = 0; k < 5; ++k)
+        HIPCHK(hipMemcpy2DAsync(stencil_out + (size_t)k * A.nx * A.ny, A.nx * sizeof(float), A.C + k * A.plane,
+                                A.pitch * sizeof(float), A.nx * sizeof(float), A.ny, hipMemcpyDeviceToDevice, s));
+    if (interp_out) {
+        const LevelDev<float> &C = (*lv)[l - 1];
+        for (int k = 0; k < 8; ++k)
+            HIPCHK(hipMemcpy2DAsync(interp_out + (size_t)k * C.nx * C.ny, C.nx * sizeof(float),
+                                    A.wt + k * A.cplane, A.cpitch * sizeof(float), C.nx * sizeof(float), C.ny,
+                                    hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_op32_smooth(hipbmg_handle h, int l, const float *b, float *x, int sweeps,
+                                            void *stream)
+{
+    return op_smooth<float>(h, l, b, x, sweeps, (hipStream_t)stream);
+}
+
+extern "C" hipbmg_status hipbmg_op32_smooth_restrict(hipbmg_handle h, int l, const float *b, float *x,
+                                                     int sweeps, float *q, float *bc, void *stream)
+{
+    return op_smooth_restrict<float>(h, l, b, x, sweeps, q, bc, (hipStream_t)stream);
+}
+
+extern "C" hipbmg_status hipbmg_op32_interp_smooth(hipbmg_handle h, int l, const float *b, float *x,
+                                                   const float *q, const float *xc, int rescorr,
+                                                   double *sumsq_host, void *stream)
+{
+    return op_interp_smooth<float>(h, l, b, x, q, xc, rescorr, sumsq_host, (hipStream_t)stream);
+}
+
+extern "C" hipbmg_status hipbmg_op32_inner(hipbmg_handle h, const float *r, float *e, int cycles, double rnorm,
+                                           double inner_tol, double *hist_host, int *cycles_host, void *stream)
+{
+    if (!h || !r || !e) return fail(HIPBMG_EINVAL, "null argument");
+    if (cycles < 1 || cycles > HIPBMG_MAX_HIST) return fail(HIPBMG_EINVAL, "cycles must be in [1, %d]", HIPBMG_MAX_HIST);
+    if (!(rnorm > 0.0) || !std::isfinite(rnorm)) return fail(HIPBMG_EINVAL, "rnorm must be finite and > 0");
+    if (!(inner_tol >= 0.0)) return fail(HIPBMG_EINVAL, "inner_tol must be >= 0");
+    const std::vector<LevelDev<float>> *lv = nullptr;
+    STCHK(op_levels(h, &lv));
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDev<float> &F = (*lv)[h->L - 1];
+    STCHK(to_pitched(F.b, F.pitch, r, F.nx, F.ny, s));
+    h->h_scal[2] = rnorm;
+    HIPCHK(hipMemcpyAsync(h->d_scal + 2, h->h_scal + 2, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const float *res = nullptr;
+    int done = 0;
+    STCHK(run_cycles<float>(h, h->lv32, h->d_lv32, true, cycles, inner_tol, h->d_scal + 2, s, &res, &done));
+    if (hist_host && done > 0)
+        HIPCHK(hipMemcpyAsync(hist_host, h->d_hist, done * sizeof(double), hipMemcpyDeviceToHost, s));
+    STCHK(from_pitched(e, res, F.pitch, F.nx, F.ny, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (cycles_host) *cycles_host = done;
     return HIPBMG_OK;
 }
 
@@ -2031,6 +2143,7 @@ struct hipbmg_batch {
     std::vector<int> h_pcnt;
     double *h_relres = nullptr;
     int *h_active = nullptr, *h_count = nullptr;
+    double *d_tol = nullptr, *h_tol = nullptr;   // [0] the solve's tolerance, [1] the inner FP32 tolerance
     int max_nx = 0, max_ny = 0, fine_npt = 5;
     BPlan plan64[2], plan32[2][2];
     int rb_cap = 0;                           // row blocks of the batched launches (0: per-level rule)
@@ -2050,6 +2163,7 @@ struct hipbmg_batch {
         if (h_relres) (void)hipHostFree(h_relres);
         if (h_active) (void)hipHostFree(h_active);
         if (h_count) (void)hipHostFree(h_count);
+        if (h_tol) (void)hipHostFree(h_tol);
         for (hipbmg_hier *h : hs) delete h;
     }
 };
@@ -2286,12 +2400,16 @@ static hipError_t run_plan_launches(hipbmg_batch *B, BPlan &plan, const int *act
 // retirement; replayed from a captured graph when use_graph is set
 template <typename T>
 static hipbmg_status batch_cycle(hipbmg_batch *B, BPlan &plan, int *active, const double *denom, double *out,
-                                 double tol, hipStream_t s)
+                                 const double *tol_dev, hipStream_t s)
 {
+    // the tolerance is read from device memory when the test runs: a replayed
+    // graph then applies the tolerance of the current solve, not the one of
+    // the solve that captured it
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = run_plan_launches<T>(B, plan, active, s);
         if (e != hipSuccess) return e;
-        e = launch_finalize_batched(B->d_partials, B->d_poff, B->d_pcnt, denom, out, active, tol, B->n, s);
+        e = launch_finalize_batched(B->d_partials, B->d_poff, B->d_pcnt, denom, out, active, 0.0, tol_dev, B->n,
+                                    s);
         if (e != hipSuccess) return e;
         return launch_count_active(active, B->n, B->d_count, s);
     };
@@ -2380,12 +2498,17 @@ static double time_plan_us(hipbmg_batch *B, BPlan &plan, hipStream_t s, hipEvent
 // single-problem rule.
 static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
 {
+    // shared by every thread that sets up batches: guarded; the key holds
+    // every parameter that shapes the plans
+    static std::mutex cache_mu;
     static std::map<std::string, int> cache;
     std::vector<std::pair<int, int>> sz;
     for (hipbmg_hier *h : B->hs) sz.push_back({h->nx, h->ny});
     std::sort(sz.begin(), sz.end());
     std::string key = std::to_string(B->fine_npt) + "/" + std::to_string(B->prm.precision) + "/" +
-                      std::to_string(B->prm.nu1) + "," + std::to_string(B->prm.nu2) + ":";
+                      std::to_string(B->prm.nu1) + "," + std::to_string(B->prm.nu2) + "/c" +
+                      std::to_string(B->prm.coarsest_n) + "/l" + std::to_string(B->prm.collapse_level) + "/r" +
+                      std::to_string(B->prm.residual_correction) + ":";
     for (auto &q : sz) key += std::to_string(q.first) + "x" + std::to_string(q.second) + ";";
     bool tune = true;
     if (const char *e = std::getenv("HIPBMG_BATCH_TUNE")) tune = std::atoi(e) != 0;
@@ -2393,11 +2516,13 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
         B->rb_cap = 0;
         return build_plans(B, s);
     }
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-        B->rb_cap = it->second;
-        return build_plans(B, s);
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) B->rb_cap = it->second;
+        else B->rb_cap = -1;
     }
+    if (B->rb_cap >= 0) return build_plans(B, s);
     std::vector<int> ones(B->n, 1);
     HIPCHK(hipMemcpyAsync(B->d_active, ones.data(), B->n * sizeof(int), hipMemcpyHostToDevice, s));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2431,7 +2556,10 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
     (void)hipEventDestroy(e1);
     if (st != HIPBMG_OK) return st;
     HIPCHK(hipMemsetAsync(B->d_active, 0, B->n * sizeof(int), s));
-    cache[key] = best;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        cache[key] = best;
+    }
     B->rb_cap = best;
     return build_plans(B, s);
 }
@@ -2477,6 +2605,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     chk(balloc(B, &B->d_active, nprob, s));
     chk(balloc(B, &B->d_active2, nprob, s));
     chk(balloc(B, &B->d_count, 1, s));
+    chk(balloc(B, &B->d_tol, 2, s));
     chk(balloc(B, &B->d_relres, nprob, s));
     chk(balloc(B, &B->d_bnorm, nprob, s));
     chk(balloc(B, &B->d_rnorm, nprob, s));
@@ -2527,7 +2656,8 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     if (st != HIPBMG_OK) return bail(st);
     if (hipHostMalloc(&B->h_relres, nprob * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&B->h_active, nprob * sizeof(int)) != hipSuccess ||
-        hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess)
+        hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess ||
+        hipHostMalloc(&B->h_tol, 2 * sizeof(double)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
     st = tune_batch(B, s);
     if (st != HIPBMG_OK) return bail(st);
@@ -2553,7 +2683,8 @@ extern "C" hipbmg_status hipbmg_destroy_batched(hipbmg_batch_handle B)
 static hipbmg_status batch_bnorm(hipbmg_batch *B, hipStream_t s)
 {
     HIPCHK(launch_sumsq_batched(B->d_bptr, B->d_dims, B->n, B->d_bpart, 64, s));
-    HIPCHK(launch_finalize_batched(B->d_bpart, B->d_boff, B->d_bcnt, nullptr, B->d_bnorm, nullptr, 0.0, B->n, s));
+    HIPCHK(launch_finalize_batched(B->d_bpart, B->d_boff, B->d_bcnt, nullptr, B->d_bnorm, nullptr, 0.0, nullptr,
+                                   B->n, s));
     return HIPBMG_OK;
 }
 
@@ -2601,12 +2732,16 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         if (!std::isfinite(bnorm[p])) ++nbad;
     }
     HIPCHK(hipMemcpyAsync(B->d_active, act.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    // the tolerances the (possibly graph-replayed) convergence tests read
+    B->h_tol[0] = tol;
+    B->h_tol[1] = B->prm.inner_tol;
+    HIPCHK(hipMemcpyAsync(B->d_tol, B->h_tol, 2 * sizeof(double), hipMemcpyHostToDevice, s));
     hipbmg_status result = HIPBMG_OK;
     int cur = 0;
     if (B->prm.precision != HIPBMG_MIXED) {
         for (int c = 0; c < B->prm.max_cycles; ++c) {
             BPlan &plan = B->plan64[cur];
-            STCHK(batch_cycle<double>(B, plan, B->d_active, B->d_bnorm, B->d_relres, tol, s));
+            STCHK(batch_cycle<double>(B, plan, B->d_active, B->d_bnorm, B->d_relres, B->d_tol, s));
             STCHK(batch_read(B, B->d_relres, B->d_active, s));
             for (int p = 0; p < n; ++p)
                 if (act[p]) {
@@ -2631,9 +2766,9 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             HIPCHK(launch_ir_residual_batched(B->d_fine64, B->d_fine32, B->d_active, B->d_rpart, B->d_roff,
                                               B->fine_npt, B->max_nx, B->max_ny, n, s));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, nullptr, B->d_rnorm, B->d_active,
-                                           -1.0, n, s));
+                                           -1.0, nullptr, n, s));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, B->d_bnorm, B->d_relres, B->d_active,
-                                           tol, n, s));
+                                           tol, nullptr, n, s));
             HIPCHK(launch_count_active(B->d_active, n, B->d_count, s));
             STCHK(batch_read(B, B->d_relres, B->d_active, s));
             for (int p = 0; p < n; ++p)
@@ -2649,7 +2784,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             int icur = 0;
             for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
                 BPlan &plan = k == 0 ? B->plan32[1][0] : B->plan32[0][icur];
-                STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->prm.inner_tol, s));
+                STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_tol + 1, s));
                 icur = plan.end_cur;
                 ++total;
                 HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -5,6 +5,7 @@
 namespace hbmg {
 
 hipError_t launch_zero_ring(double *v, int nx, int ny, int pitch, hipStream_t s);
+hipError_t launch_zero_ring(float *v, int nx, int ny, int pitch, hipStream_t s);
 // FP64 level -> FP32 edge-form level (and its interpolation weights)
 hipError_t launch_demote_level(const LevelDev<double> &d, const LevelDev<float> &f, int cnx,
                                int cny, hipStream_t s);

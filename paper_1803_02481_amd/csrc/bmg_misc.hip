@@ -5,23 +5,31 @@
 
 namespace hbmg {
 
-__global__ void k_zero_ring(double *__restrict__ v, int nx, int ny, int pitch)
+template <typename T>
+__global__ void k_zero_ring(T *__restrict__ v, int nx, int ny, int pitch)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nx) {
-        v[k] = 0.0;
-        v[(size_t)(ny - 1) * pitch + k] = 0.0;
+        v[k] = T(0);
+        v[(size_t)(ny - 1) * pitch + k] = T(0);
     }
     if (k < ny) {
-        v[(size_t)k * pitch] = 0.0;
-        v[(size_t)k * pitch + nx - 1] = 0.0;
+        v[(size_t)k * pitch] = T(0);
+        v[(size_t)k * pitch + nx - 1] = T(0);
     }
 }
 
 hipError_t launch_zero_ring(double *v, int nx, int ny, int pitch, hipStream_t s)
 {
     const int n = nx > ny ? nx : ny;
-    hipLaunchKernelGGL(k_zero_ring, dim3((n + 255) / 256), dim3(256), 0, s, v, nx, ny, pitch);
+    hipLaunchKernelGGL(k_zero_ring<double>, dim3((n + 255) / 256), dim3(256), 0, s, v, nx, ny, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ring(float *v, int nx, int ny, int pitch, hipStream_t s)
+{
+    const int n = nx > ny ? nx : ny;
+    hipLaunchKernelGGL(k_zero_ring<float>, dim3((n + 255) / 256), dim3(256), 0, s, v, nx, ny, pitch);
     return hipGetLastError();
 }
 

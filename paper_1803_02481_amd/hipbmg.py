@@ -67,6 +67,12 @@ _SIGS = {
     "hipbmg_op_smooth": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
     "hipbmg_op_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _I, _VP, _VP, _VP]),
     "hipbmg_op_interp_smooth": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(ctypes.c_double), _VP]),
+    "hipbmg_get_level32": (_I, [_VP, _I, _VP, _VP, _VP]),
+    "hipbmg_op32_smooth": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
+    "hipbmg_op32_smooth_restrict": (_I, [_VP, _I, _VP, _VP, _I, _VP, _VP, _VP]),
+    "hipbmg_op32_interp_smooth": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(ctypes.c_double), _VP]),
+    "hipbmg_op32_inner": (_I, [_VP, _VP, _VP, _I, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(_I), _VP]),
     "hipbmg_fv5_from_cells": (_I, [_I, _I, _VP, _I, _VP, _VP]),
     "hipbmg_fv5_aniso": (_I, [_I, _I, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
     "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
@@ -203,11 +209,17 @@ def _check(status):
         raise HipBMGError(status, lib().hipbmg_last_error().decode())
 
 
-def _ptr(t, dtype=torch.float64):
+def _ptr(t, dtype=torch.float64, shape=None, name="array"):
+    """Device pointer of a contiguous CUDA tensor, checked against the dtype and
+    shape the library will read or write through it (the C interface takes
+    bare pointers and sizes, so a mismatch here would be an out-of-bounds
+    access there)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a CUDA tensor")
+        raise TypeError("%s: expected a CUDA tensor" % name)
     if t.dtype != dtype or not t.is_contiguous():
-        raise TypeError("expected a contiguous %s tensor" % dtype)
+        raise TypeError("%s: expected a contiguous %s tensor" % (name, dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s: expected shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -236,7 +248,7 @@ class Hierarchy:
         self.params = default_params(**params)
         self.device = coeffs.device
         h = ctypes.c_void_p()
-        _check(lib().hipbmg_setup(self.nx, self.ny, self.npt, _ptr(coeffs), ctypes.byref(self.params),
+        _check(lib().hipbmg_setup(self.nx, self.ny, self.npt, _ptr(coeffs, name="coeffs"), ctypes.byref(self.params),
                                   _stream(), ctypes.byref(h)))
         self._h = h
         _open_handles.add(self)
@@ -268,8 +280,10 @@ class Hierarchy:
         """Returns (u, info).  u is updated in place if given."""
         if u is None:
             u = torch.zeros_like(b)
+        shp = (self.ny, self.nx)
         info = Info()
-        st = lib().hipbmg_solve(self._h, _ptr(b), _ptr(u), tol, _stream(), ctypes.byref(info))
+        st = lib().hipbmg_solve(self._h, _ptr(b, shape=shp, name="b"), _ptr(u, shape=shp, name="u"), tol, _stream(),
+                                ctypes.byref(info))
         if check and st != OK:
             _check(st)
         info.status = st
@@ -325,9 +339,21 @@ class Hierarchy:
                 out[name] = (ms.value, n.value, by.value)
         return out
 
+    def _fields(self, l, dtype, **arrays):
+        """Pointers of level-l fields (coarse=True entries: level l-1), shapes checked."""
+        if not 0 <= l < self.L:
+            raise ValueError("level %d out of range [0, %d)" % (l, self.L))
+        out = []
+        for name, (t, coarse) in arrays.items():
+            if coarse and l < 1:
+                raise ValueError("level 0 has no coarser level")
+            out.append(_ptr(t, dtype, self.size(l - 1 if coarse else l), name))
+        return out
+
     def op_smooth(self, l, b, x, sweeps=1):
         x = x.clone()
-        _check(lib().hipbmg_op_smooth(self._h, l, _ptr(b), _ptr(x), sweeps, _stream()))
+        pb, px = self._fields(l, torch.float64, b=(b, False), x=(x, False))
+        _check(lib().hipbmg_op_smooth(self._h, l, pb, px, sweeps, _stream()))
         return x
 
     def op_smooth_restrict(self, l, b, x, sweeps=1):
@@ -335,16 +361,67 @@ class Hierarchy:
         q = torch.zeros_like(x)
         cny, cnx = self.size(l - 1)
         bc = torch.zeros((cny, cnx), dtype=torch.float64, device=x.device)
-        _check(lib().hipbmg_op_smooth_restrict(self._h, l, _ptr(b), _ptr(x), sweeps, _ptr(q), _ptr(bc),
-                                               _stream()))
+        pb, px, pq, pc = self._fields(l, torch.float64, b=(b, False), x=(x, False), q=(q, False), bc=(bc, True))
+        _check(lib().hipbmg_op_smooth_restrict(self._h, l, pb, px, sweeps, pq, pc, _stream()))
         return x, q, bc
 
     def op_interp_smooth(self, l, b, x, q, xc, rescorr=1, want_norm=False):
         x = x.clone()
         ss = ctypes.c_double(0.0)
-        _check(lib().hipbmg_op_interp_smooth(self._h, l, _ptr(b), _ptr(x), _ptr(q), _ptr(xc), rescorr,
+        pb, px, pq, pc = self._fields(l, torch.float64, b=(b, False), x=(x, False), q=(q, False), xc=(xc, True))
+        _check(lib().hipbmg_op_interp_smooth(self._h, l, pb, px, pq, pc, rescorr,
                                              ctypes.byref(ss) if want_norm else None, _stream()))
         return (x, ss.value) if want_norm else x
+
+    # ---- FP32 edge-form levels (mixed-precision handles) -----------------
+    def level32(self, l):
+        """(planes [5][ny][nx] = {E, W, S, SW, SE}, weights [8][cny][cnx] or None
+        on level 0), float32."""
+        if not 0 <= l < self.L:
+            raise ValueError("level %d out of range [0, %d)" % (l, self.L))
+        ny, nx = self.size(l)
+        st = torch.zeros((5, ny, nx), dtype=torch.float32, device=self.device)
+        wt = None
+        if l >= 1:
+            cny, cnx = self.size(l - 1)
+            wt = torch.zeros((8, cny, cnx), dtype=torch.float32, device=self.device)
+        _check(lib().hipbmg_get_level32(self._h, l, _ptr(st, torch.float32),
+                                        _ptr(wt, torch.float32) if wt is not None else None, _stream()))
+        return st, wt
+
+    def op32_smooth(self, l, b, x, sweeps=1):
+        x = x.clone()
+        pb, px = self._fields(l, torch.float32, b=(b, False), x=(x, False))
+        _check(lib().hipbmg_op32_smooth(self._h, l, pb, px, sweeps, _stream()))
+        return x
+
+    def op32_smooth_restrict(self, l, b, x, sweeps=1):
+        x = x.clone()
+        q = torch.zeros_like(x)
+        cny, cnx = self.size(l - 1)
+        bc = torch.zeros((cny, cnx), dtype=torch.float32, device=x.device)
+        pb, px, pq, pc = self._fields(l, torch.float32, b=(b, False), x=(x, False), q=(q, False), bc=(bc, True))
+        _check(lib().hipbmg_op32_smooth_restrict(self._h, l, pb, px, sweeps, pq, pc, _stream()))
+        return x, q, bc
+
+    def op32_interp_smooth(self, l, b, x, q, xc, rescorr=1, want_norm=False):
+        x = x.clone()
+        ss = ctypes.c_double(0.0)
+        pb, px, pq, pc = self._fields(l, torch.float32, b=(b, False), x=(x, False), q=(q, False), xc=(xc, True))
+        _check(lib().hipbmg_op32_interp_smooth(self._h, l, pb, px, pq, pc, rescorr,
+                                               ctypes.byref(ss) if want_norm else None, _stream()))
+        return (x, ss.value) if want_norm else x
+
+    def op32_inner(self, r, cycles, rnorm, inner_tol=0.0):
+        """The inner FP32 solve of one refinement step, A e = r from e = 0:
+        (e, inner relative residual after each cycle)."""
+        e = torch.zeros_like(r)
+        pr, pe = self._fields(self.L - 1, torch.float32, r=(r, False), e=(e, False))
+        hist = (ctypes.c_double * max(1, int(cycles)))()
+        done = ctypes.c_int(0)
+        _check(lib().hipbmg_op32_inner(self._h, pr, pe, int(cycles), float(rnorm), float(inner_tol), hist,
+                                       ctypes.byref(done), _stream()))
+        return e, list(hist)[: done.value]
 
 
 class BatchHierarchy:
@@ -355,11 +432,16 @@ class BatchHierarchy:
         n = len(coeffs_list)
         if n == 0:
             raise ValueError("empty batch")
+        for k, c in enumerate(coeffs_list):
+            if c.dim() != 3 or c.shape[0] not in (3, 5):
+                raise ValueError("coeffs_list[%d] must be [3 or 5][ny][nx]" % k)
+            if c.shape[0] != coeffs_list[0].shape[0]:
+                raise ValueError("every problem of a batch needs the same stencil (plane count)")
         npt = 5 if coeffs_list[0].shape[0] == 3 else 9
         self.shapes = [(int(c.shape[1]), int(c.shape[2])) for c in coeffs_list]
         nx = (_I * n)(*[s[1] for s in self.shapes])
         ny = (_I * n)(*[s[0] for s in self.shapes])
-        ptrs = (_VP * n)(*[_ptr(c).value for c in coeffs_list])
+        ptrs = (_VP * n)(*[_ptr(c, name="coeffs_list[%d]" % k).value for k, c in enumerate(coeffs_list)])
         self.params = default_params(**params)
         h = ctypes.c_void_p()
         _check(lib().hipbmg_setup_batched(n, nx, ny, npt, ptrs, ctypes.byref(self.params), _stream(),
@@ -383,8 +465,11 @@ class BatchHierarchy:
         if u_list is None:
             u_list = [torch.zeros_like(b) for b in b_list]
         n = self.n
-        bp = (_VP * n)(*[_ptr(b).value for b in b_list])
-        up = (_VP * n)(*[_ptr(u).value for u in u_list])
+        if len(b_list) != n or len(u_list) != n:
+            raise ValueError("the batch has %d problems: got %d right-hand sides, %d iterates"
+                             % (n, len(b_list), len(u_list)))
+        bp = (_VP * n)(*[_ptr(b, shape=self.shapes[k], name="b_list[%d]" % k).value for k, b in enumerate(b_list)])
+        up = (_VP * n)(*[_ptr(u, shape=self.shapes[k], name="u_list[%d]" % k).value for k, u in enumerate(u_list)])
         infos = (Info * n)()
         st = lib().hipbmg_solve_batched(self._h, bp, up, tol, _stream(), infos)
         if check and st != OK:
@@ -415,6 +500,8 @@ CALIBRATION_KEYS = ("alpha_launch_us", "hbm_GBps", "cache_GBps",
 
 def fv5_from_cells(cell, is_log=False):
     """5-point finite-volume planes {C, W, S} ([3][ny][nx]) from per-cell D or ln D."""
+    if cell.dim() != 2:
+        raise ValueError("cell must be [ny-1][nx-1]")
     ny, nx = cell.shape[0] + 1, cell.shape[1] + 1
     out = torch.empty((3, ny, nx), dtype=torch.float64, device=cell.device)
     _check(lib().hipbmg_fv5_from_cells(nx, ny, _ptr(cell), 1 if is_log else 0, _ptr(out), _stream()))
@@ -424,6 +511,8 @@ def fv5_from_cells(cell, is_log=False):
 def fv5_aniso(dx_cell, dy_cell, hx, hy):
     """5-point finite-volume planes {C, W, S} for D = diag(Dx, Dy) per cell on a
     grid of spacings hx, hy (the stretched grids of section 5)."""
+    if dx_cell.dim() != 2:
+        raise ValueError("dx_cell must be [ny-1][nx-1]")
     ny, nx = dx_cell.shape[0] + 1, dx_cell.shape[1] + 1
     if tuple(dy_cell.shape) != tuple(dx_cell.shape):
         raise ValueError("dx_cell and dy_cell must have the same shape")
@@ -434,9 +523,14 @@ def fv5_aniso(dx_cell, dy_cell, hx, hy):
 
 
 def grad_logD(theta, u, lam):
+    """dL/dtheta per cell ([ny-1][nx-1]) from the solution u and the adjoint lam ([ny][nx])."""
+    if u.dim() != 2:
+        raise ValueError("u must be [ny][nx]")
     ny, nx = u.shape
     g = torch.empty_like(theta)
-    _check(lib().hipbmg_grad_logD(nx, ny, _ptr(theta), _ptr(u), _ptr(lam), _ptr(g), _stream()))
+    _check(lib().hipbmg_grad_logD(nx, ny, _ptr(theta, shape=(ny - 1, nx - 1), name="theta"),
+                                  _ptr(u, name="u"), _ptr(lam, shape=(ny, nx), name="lam"),
+                                  _ptr(g, shape=(ny - 1, nx - 1), name="grad"), _stream()))
     return g
 
 
@@ -448,6 +542,8 @@ class SolveFV(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, b, tol=1e-10, params=None):
+        if theta.dim() != 2 or tuple(b.shape) != (theta.shape[0] + 1, theta.shape[1] + 1):
+            raise ValueError("theta must be [ny-1][nx-1] and b [ny][nx]")
         coeffs = fv5_from_cells(theta.detach().contiguous(), is_log=True)
         hier = Hierarchy(coeffs, **(params or {}))
         u, info = hier.solve(b.detach().contiguous(), tol=tol)
@@ -474,6 +570,8 @@ class SolveFVBatched(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, b, tol=1e-10, params=None):
+        if theta.dim() != 3 or tuple(b.shape) != (theta.shape[0], theta.shape[1] + 1, theta.shape[2] + 1):
+            raise ValueError("theta must be [B][ny-1][nx-1] and b [B][ny][nx]")
         th = theta.detach().contiguous()
         bb = b.detach().contiguous()
         nb = th.shape[0]
@@ -509,6 +607,8 @@ KERNELS3 = ("relax_colour", "residual", "restrict", "interp", "coarse_levels")
 def fv7_from_cells(cells):
     """7-point finite-volume planes {C, W, S, B} [4][nz][ny][nx] from per-cell D
     [(nz-1)][(ny-1)][(nx-1)] (a CUDA float64 tensor)."""
+    if cells.dim() != 3:
+        raise ValueError("cells must be [nz-1][ny-1][nx-1]")
     nz, ny, nx = (int(d) + 1 for d in cells.shape)
     out = torch.empty((4, nz, ny, nx), dtype=torch.float64, device=cells.device)
     _check(lib().hipbmg3d_fv7_from_cells(nx, ny, nz, _ptr(cells), _ptr(out), _stream()))
@@ -570,35 +670,43 @@ class Hierarchy3:
 
     def solve(self, b, u0=None, tol=1e-10, check=True):
         u = torch.zeros_like(b) if u0 is None else u0.clone()
+        shp = (self.nz, self.ny, self.nx)
         info = Info()
-        st = lib().hipbmg3d_solve(self._h, _ptr(b), _ptr(u), float(tol), _stream(), ctypes.byref(info))
+        st = lib().hipbmg3d_solve(self._h, _ptr(b, shape=shp, name="b"), _ptr(u, shape=shp, name="u0"), float(tol),
+                                  _stream(), ctypes.byref(info))
         if st != OK and (check or st not in (ENOCONV,)):
             _check(st)
         return u, info
 
+    def _lv(self, l, t, name, coarse=False):
+        if not 0 <= l < self.L or (coarse and l < 1):
+            raise ValueError("level %d out of range" % l)
+        return _ptr(t, shape=self.size(l - 1 if coarse else l), name=name)
+
     def smooth(self, l, b, x, sweeps=1):
         x = x.clone()
-        _check(lib().hipbmg3d_op_smooth(self._h, l, _ptr(b), _ptr(x), sweeps, _stream()))
+        _check(lib().hipbmg3d_op_smooth(self._h, l, self._lv(l, b, "b"), self._lv(l, x, "x"), sweeps, _stream()))
         return x
 
     def residual(self, l, b, x):
         r = self._field(l)
-        _check(lib().hipbmg3d_op_residual(self._h, l, _ptr(b), _ptr(x), _ptr(r), _stream()))
+        _check(lib().hipbmg3d_op_residual(self._h, l, self._lv(l, b, "b"), self._lv(l, x, "x"), _ptr(r), _stream()))
         return r
 
     def restrict(self, l, r):
         bc = self._field(l - 1)
-        _check(lib().hipbmg3d_op_restrict(self._h, l, _ptr(r), _ptr(bc), _stream()))
+        _check(lib().hipbmg3d_op_restrict(self._h, l, self._lv(l, r, "r"), _ptr(bc), _stream()))
         return bc
 
     def interp_correct(self, l, x, r, xc, rescorr=1):
         x = x.clone()
-        _check(lib().hipbmg3d_op_interp_correct(self._h, l, _ptr(x), _ptr(r), _ptr(xc), rescorr, _stream()))
+        _check(lib().hipbmg3d_op_interp_correct(self._h, l, self._lv(l, x, "x"), self._lv(l, r, "r"),
+                                                self._lv(l, xc, "xc", coarse=True), rescorr, _stream()))
         return x
 
     def coarse_solve(self, b):
         x = self._field(0)
-        _check(lib().hipbmg3d_op_coarse_solve(self._h, _ptr(b), _ptr(x), _stream()))
+        _check(lib().hipbmg3d_op_coarse_solve(self._h, self._lv(0, b, "b"), _ptr(x), _stream()))
         return x
 
     def profile(self, enable=True):

@@ -78,3 +78,22 @@ def from_interior(x, ny, nx):
     out = np.zeros((ny, nx))
     out[1:-1, 1:-1] = x.reshape(ny - 2, nx - 2)
     return out
+
+
+def residual_from_planes(planes, b, u):
+    """b - A u over interior vertices (zero on the boundary ring), vectorised,
+    with A the operator of the planes {C, W, S[, SW, SE]} (matrix entries
+    C, -W(p), -W(p+e), -S(p), -S(p+n), ...) and u = 0 on the boundary."""
+    u = np.array(u, dtype=np.float64)
+    u[0, :] = u[-1, :] = 0.0
+    u[:, 0] = u[:, -1] = 0.0
+    C, W, S = planes[0], planes[1], planes[2]
+    I = (slice(1, -1), slice(1, -1))
+    Au = (C[I] * u[I] - W[I] * u[1:-1, :-2] - W[1:-1, 2:] * u[1:-1, 2:]
+          - S[I] * u[:-2, 1:-1] - S[2:, 1:-1] * u[2:, 1:-1])
+    if planes.shape[0] == 5:
+        SW, SE = planes[3], planes[4]
+        Au -= SW[I] * u[:-2, :-2] + SW[2:, 2:] * u[2:, 2:] + SE[I] * u[:-2, 2:] + SE[2:, :-2] * u[2:, :-2]
+    r = np.zeros_like(u)
+    r[I] = b[I] - Au
+    return r

@@ -1,0 +1,316 @@
+"""GPU parity of the FP32 edge-form path of mixed precision against the
+oracle's FP32 mode, element by element, through the C interface.
+
+Each operation is checked on the GPU's own FP64 operator of a level: the
+oracle demotes that operator itself (connections rounded to float, excess
+formed in FP64), so the comparison isolates the demotion and the float
+kernels.  Both sides compute the same float expressions in different orders
+of association, so results agree to a few units of float rounding of the
+quantities involved; the bounds below are stated per check (measured values
+in the comments).  Whole refinement runs are compared on their step and cycle
+counts and on the FP64 residual the method fixes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1803_02481_amd import hipbmg as HB
+from paper_1803_02481_amd import inputs
+from tests import helpers as H
+from tests.test_gpu_parity import c, g, gpu_prows, planes_of_level, rand_cells, rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+U32 = 2.0 ** -24
+
+
+def g32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def ring0(a):
+    a[0] = a[-1] = 0
+    a[:, 0] = a[:, -1] = 0
+    return a
+
+
+def rand32(rng, shape):
+    return ring0(rng.standard_normal(shape).astype(np.float32))
+
+
+def mixed(planes, **kw):
+    return HB.Hierarchy(g(planes), precision=HB.MIXED, **kw)
+
+
+def step_oracle(hier, l):
+    """Oracle hierarchy whose finest level is the GPU's FP64 operator of level
+    l, or None for a level with an even side (the coarsest level of a grid
+    whose coarsening stopped there; the oracle takes odd sizes only)."""
+    ny, nx = hier.size(l)
+    if nx % 2 == 0 or ny % 2 == 0:
+        return None
+    st = O.Hierarchy(planes_of_level(hier, l))
+    st.demote()
+    return st
+
+
+CASES = [(65, 65, 1), (129, 97, 2), (257, 257, 3), (225, 161, 4)]
+
+
+# --------------------------------------------------------------------------
+# the demoted levels
+# --------------------------------------------------------------------------
+def _conn_from_gpu(pl):
+    """Connections c_pq [ny][nx][3][3] (centre 0) from GPU planes {E,W,S,SW,SE},
+    towards every neighbour including boundary vertices."""
+    E, W, S, SW, SE = (p.astype(np.float64) for p in pl)
+    ny, nx = E.shape
+    cn = np.zeros((ny, nx, 3, 3))
+    cn[:, 1:, 1, 0] = W[:, 1:]
+    cn[:, :-1, 1, 2] = W[:, 1:]
+    cn[1:, :, 0, 1] = S[1:, :]
+    cn[:-1, :, 2, 1] = S[1:, :]
+    cn[1:, 1:, 0, 0] = SW[1:, 1:]
+    cn[:-1, :-1, 2, 2] = SW[1:, 1:]
+    cn[1:, :-1, 0, 2] = SE[1:, :-1]
+    cn[:-1, 1:, 2, 0] = SE[1:, :-1]
+    return cn
+
+
+@pytest.mark.parametrize("nx,ny,seed", CASES)
+def test_demoted_levels_match_oracle(nx, ny, seed):
+    planes = O.fv5(rand_cells(nx, ny, seed))
+    hier = mixed(planes)
+    worst_e = 0.0
+    for l in range(hier.L - 1, -1, -1):
+        st = step_oracle(hier, l)
+        if st is None:
+            continue
+        A32, P32 = st.level32(st.L - 1)
+        A32 = A32.astype(np.float64)
+        pl, wt = hier.level32(l)
+        cn = _conn_from_gpu(c(pl))
+        ny_, nx_ = cn.shape[:2]
+        inner = np.zeros((ny_, nx_), bool)
+        inner[1:-1, 1:-1] = True
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                nb = np.zeros_like(inner)
+                nb[1:-1, 1:-1] = inner[1 + dy:ny_ - 1 + dy, 1 + dx:nx_ - 1 + dx]
+                both = inner & nb
+                # a connection between interior vertices is the same FP64
+                # value rounded once on each side: bitwise
+                assert np.array_equal(cn[:, :, dy + 1, dx + 1][both], A32[:, :, dy + 1, dx + 1][both]), (l, dx, dy)
+        # the excess: the GPU keeps the connections towards boundary vertices
+        # and leaves them out of E; the oracle drops them and E holds them.
+        # The same matrix diagonal either way, up to the FP64 rounding of the
+        # two sums and one float rounding of each side
+        bsum = np.zeros((ny_, nx_))
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                nb = np.zeros_like(inner)
+                nb[1:-1, 1:-1] = inner[1 + dy:ny_ - 1 + dy, 1 + dx:nx_ - 1 + dx]
+                bsum += np.where(inner & ~nb, cn[:, :, dy + 1, dx + 1], 0.0)
+        Eg = c(pl[0]).astype(np.float64) + bsum
+        Eo = A32[:, :, 1, 1]
+        C64 = c(hier.stencil(l))[0]
+        tol = 2 * U32 * (np.abs(Eo) + bsum) + 1e-14 * np.abs(C64)
+        d = np.abs(Eg - Eo)[inner]
+        assert np.all(d <= tol[inner]), (l, float(d.max()))
+        worst_e = max(worst_e, float((d / np.maximum(np.abs(C64[inner]), 1e-300)).max()))
+        if l >= 1:
+            # FP32 weights: the oracle's interpolation of the same operator
+            # (FP64, to 1e-13) rounded once: within one float rounding
+            Pg = gpu_prows(c(wt).astype(np.float64), (ny_, nx_))
+            Po = P32.astype(np.float64)
+            assert np.all(np.abs(Pg - Po) <= 2 * U32 * np.abs(Po) + 1e-13), l
+    print("demoted levels: worst excess difference %.2e C" % worst_e)
+
+
+# --------------------------------------------------------------------------
+# single FP32 operations
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,seed", CASES)
+def test_fp32_relaxation_matches_oracle(nx, ny, seed):
+    planes = O.fv5(rand_cells(nx, ny, seed))
+    hier = mixed(planes)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for l in sorted({hier.L - 1, hier.L - 2, hier.L - 3, 1}):
+        st = step_oracle(hier, l)
+        if st is None:
+            continue
+        lo = st.L - 1
+        shp = hier.size(l)
+        b, x = rand32(rng, shp), rand32(rng, shp)
+        for sweeps in (1, 2):
+            ref = st.smooth32(lo, b, x, sweeps)
+            got = c(hier.op32_smooth(l, g32(b), g32(x), sweeps))
+            e = rel(got, ref)
+            worst = max(worst, e)
+            # a few dozen float roundings per vertex and colour, carried by
+            # the later colours with weights summing to at most one
+            # (measured <= 6.3e-7)
+            assert e <= 6e-6, (l, sweeps, e)
+    print("fp32 relaxation: worst %.2e" % worst)
+
+
+def _q_of(st, r):
+    """r / diag at vertices that are not coarse points, float, from the
+    oracle's demoted level (diag = sum of connections + excess)."""
+    A32, _ = st.level32(st.L - 1)
+    d = A32.sum(axis=(2, 3), dtype=np.float32)
+    q = np.zeros_like(r)
+    fo = np.ones_like(r, bool)
+    fo[::2, ::2] = False
+    fo[0] = fo[-1] = False
+    fo[:, 0] = fo[:, -1] = False
+    q[fo] = r[fo] / d[fo]
+    return q
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+@pytest.mark.parametrize("nx,ny,seed", CASES[:3])
+def test_fp32_fused_down_pass_matches_oracle(nx, ny, seed, sweeps):
+    planes = O.fv5(rand_cells(nx, ny, seed))
+    hier = mixed(planes)
+    rng = np.random.default_rng(100 + seed)
+    worst = [0.0, 0.0, 0.0]
+    for l in (hier.L - 1, hier.L - 2, hier.L - 3):
+        st = step_oracle(hier, l)
+        if st is None:
+            continue
+        lo = st.L - 1
+        shp = hier.size(l)
+        b, x = rand32(rng, shp), rand32(rng, shp)
+        xs = st.smooth32(lo, b, x, sweeps)
+        r = st.residual32(lo, b, xs)
+        bc = st.restrict32(lo, r)
+        q = _q_of(st, r)
+        gx, gq, gbc = (c(t) for t in hier.op32_smooth_restrict(l, g32(b), g32(x), sweeps))
+        ex, eq, eb = rel(gx, xs), rel(gq, q), rel(gbc, bc)
+        worst = [max(a, b_) for a, b_ in zip(worst, (ex, eq, eb))]
+        # measured: x <= 3.3e-7, q <= 4.6e-6, bc <= 7.1e-7
+        assert ex <= 4e-6, (l, ex)
+        # the residual cancels the relaxed iterate's terms: its error is that
+        # of x times the operator's norm over the residual's size
+        assert eq <= 5e-5, (l, eq)
+        assert eb <= 7e-6, (l, eb)
+    print("fp32 down pass (sweeps %d): x %.2e q %.2e bc %.2e" % (sweeps, *worst))
+
+
+@pytest.mark.parametrize("rescorr", [1, 0])
+@pytest.mark.parametrize("nx,ny,seed", CASES[:3])
+def test_fp32_fused_up_pass_matches_oracle(nx, ny, seed, rescorr):
+    planes = O.fv5(rand_cells(nx, ny, seed))
+    hier = mixed(planes)
+    rng = np.random.default_rng(200 + seed)
+    worst = 0.0
+    for l in (hier.L - 1, hier.L - 2):
+        st = step_oracle(hier, l)
+        if st is None:
+            continue
+        lo = st.L - 1
+        shp = hier.size(l)
+        b, x, r = rand32(rng, shp), rand32(rng, shp), rand32(rng, shp)
+        xc = rand32(rng, hier.size(l - 1))
+        q = _q_of(st, r)
+        ref = st.interp_correct32(lo, x, r, xc, rescorr)
+        ref = st.smooth32(lo, b, ref, 1)
+        rres = st.residual32(lo, b, ref)
+        got, ss = hier.op32_interp_smooth(l, g32(b), g32(x), g32(q), g32(xc), rescorr, want_norm=True)
+        e = rel(c(got), ref)
+        worst = max(worst, e)
+        assert e <= 2e-6, (l, e)      # measured <= 1.8e-7
+        want = float((rres.astype(np.float64) ** 2).sum())
+        assert ss == pytest.approx(want, rel=1e-4)
+    print("fp32 up pass: worst %.2e" % worst)
+
+
+# --------------------------------------------------------------------------
+# inner FP32 solves and whole refinement runs
+# --------------------------------------------------------------------------
+INNER_CASES = [(129, 129, 5, 1), (257, 193, 5, 2), (161, 225, 5, 3), (129, 129, 9, 4)]
+
+
+def _planes(nx, ny, npt, seed):
+    from tests.test_gpu_parity import make_planes
+    return make_planes(nx, ny, npt, seed)
+
+
+@pytest.mark.parametrize("nx,ny,npt,seed", INNER_CASES)
+def test_fp32_inner_solve_matches_oracle(nx, ny, npt, seed):
+    planes = _planes(nx, ny, npt, seed)
+    hier = mixed(planes)
+    ora = O.Hierarchy(planes)
+    rng = np.random.default_rng(300 + seed)
+    r = rand32(rng, (ny, nx))
+    rn = float(np.linalg.norm(r.astype(np.float64)[1:-1, 1:-1]))
+    worst = 0.0
+    for cycles in (1, 3):
+        e_ref, h_ref = ora.inner32(r, cycles, rn)
+        e_gpu, h_gpu = hier.op32_inner(g32(r), cycles, rn)
+        err = rel(c(e_gpu), e_ref)
+        worst = max(worst, err)
+        # one V-cycle is a stable linear map of r: float rounding of a few
+        # dozen operations per vertex and level, carried through the levels
+        # (measured <= 1.6e-7)
+        assert err <= 2e-6, (cycles, err)
+        assert len(h_gpu) == len(h_ref) == cycles
+        assert np.allclose(h_gpu, h_ref, rtol=1e-3, atol=0), (h_gpu, list(h_ref))
+    # run to the inner tolerance: the same number of cycles
+    e_ref, h_ref = ora.inner32(r, 12, rn, 1e-5)
+    e_gpu, h_gpu = hier.op32_inner(g32(r), 12, rn, 1e-5)
+    assert len(h_gpu) == len(h_ref), (h_gpu, list(h_ref))
+    print("fp32 inner solve: worst %.2e, inner history %s" % (worst, ["%.3e" % v for v in h_gpu]))
+
+
+@pytest.mark.parametrize("kind,n,seed", [("blocks", 257, 1), ("checkerboard", 257, 3), ("lognormal", 193, 7)])
+def test_mixed_solve_matches_oracle_refinement(kind, n, seed):
+    if kind == "blocks":
+        D = inputs.cells_log10_blocks(n, n, 16, seed=seed)
+    elif kind == "checkerboard":
+        D = inputs.cells_two_phase_blocks(n, n, 16, seed=seed)
+    else:
+        D = inputs.cells_lognormal(n, n, 1.0, seed=seed)
+    planes = O.fv5(D)
+    b = inputs.load_uniform(n, n, seed=seed + 1)
+    ora = O.Hierarchy(planes)
+    u_ref, h_ref, cyc_ref, steps_ref = ora.solve_mixed(b, tol=1e-10)
+    hier = mixed(planes)
+    u, info = hier.solve(g(b), tol=1e-10)
+    # the outer residual before each step and after the last
+    hist = np.array(info.relres_hist[: info.outer_steps + 1])
+    # the same refinement: as many steps and FP32 cycles as the oracle's
+    assert info.outer_steps == steps_ref and info.cycles == cyc_ref, \
+        (info.outer_steps, steps_ref, info.cycles, cyc_ref)
+    # outer residuals before each step: a step cuts the residual by ~1e-5 to
+    # ~1e-6, down to what FP32 rounding of the inner solve leaves, so the
+    # float rounding differences of the two inner solves (~1e-7 of the
+    # correction) reach a few per cent of the new residual (measured <= 2.2%)
+    assert np.all(np.abs(hist - h_ref) <= 0.1 * h_ref), (list(hist), list(h_ref))
+    A = H.matrix_from_planes(planes)
+    bi = H.to_interior(b)
+    rr = np.linalg.norm(bi - A @ H.to_interior(c(u))) / np.linalg.norm(bi)
+    assert rr <= 1.2e-10, rr
+    print("mixed %s: steps %d cycles %d, outer history gpu %s oracle %s"
+          % (kind, steps_ref, cyc_ref, ["%.3e" % v for v in hist], ["%.3e" % v for v in h_ref]))
+
+
+def test_fp32_entry_points_need_a_mixed_handle():
+    planes = O.fv5(rand_cells(33, 33, 0))
+    hier = HB.Hierarchy(g(planes))
+    x = torch.zeros((33, 33), dtype=torch.float32, device=DEV)
+    with pytest.raises(HB.HipBMGError) as ei:
+        hier.op32_smooth(hier.L - 1, x, x)
+    assert ei.value.status == HB.EINVAL
+    with pytest.raises(HB.HipBMGError):
+        hier.level32(0)
+    with pytest.raises(HB.HipBMGError):
+        hier.op32_inner(x, 1, 1.0)

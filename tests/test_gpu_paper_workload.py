@@ -98,9 +98,12 @@ def test_paper_workload_full_size_ten_cycles():
         u = ora.vcycle(b, u)
         ref.append(relres(ora, b, u))
     print("oracle first cycles %s" % ref, flush=True)
-    assert np.all(np.abs(hist[:2] - np.array(ref)) <= 1e-8 * np.array(ref))
     u2, _ = HB.Hierarchy(HB.fv5_aniso(g(Dx), g(Dy), hx, hy), max_cycles=2).solve(g(b), tol=1e-30, check=False)
-    assert rel(c(u2), u) <= 1e-9
+    print("first cycles max rel difference %.3e, iterate after 2 cycles %.3e"
+          % (float((np.abs(hist[:2] - np.array(ref)) / np.array(ref)).max()), rel(c(u2), u)), flush=True)
+    # measured 3.0e-16 and 5.9e-14
+    assert np.all(np.abs(hist[:2] - np.array(ref)) <= 1e-14 * np.array(ref))
+    assert rel(c(u2), u) <= 5e-13
     assert relres(ora, b, c(u10)) == pytest.approx(hist[-1], rel=1e-3)
     # the isotropic-problem convergence the compensation is meant to give
     assert (hist[-1] / hist[0]) ** (1.0 / 9) <= 0.1

@@ -283,7 +283,10 @@ def test_solve_matches_oracle(name, nx, ny, cells, seed):
     # the residual is far above the rounding floor
     assert info.cycles == len(h_ref), (info.cycles, len(h_ref))
     early = h_ref > 1e-6
-    assert np.all(np.abs(hist[early] - h_ref[early]) <= 1e-8 * h_ref[early]), (list(hist[:5]), list(h_ref[:5]))
+    print("%s: history max rel difference %.3e" % (name, float((np.abs(hist[early] - h_ref[early]) / h_ref[early]).max())))
+    # rounding differences grow relative to the shrinking residual over the
+    # cycles (measured <= 4.2e-10 while relres > 1e-6)
+    assert np.all(np.abs(hist[early] - h_ref[early]) <= 5e-9 * h_ref[early]), (list(hist[:5]), list(h_ref[:5]))
     # the answer satisfies the stopping test, checked independently on the host;
     # evaluating ||b - A u|| at the 1e-10 level carries a rounding floor of
     # ~eps * ||A|| ||u|| / ||b|| (up to ~1e-11 here), hence the 20% margin
@@ -319,7 +322,9 @@ def test_collapse_level_does_not_change_the_iteration(n):
         # kernels: relative agreement plus an absolute rounding floor
         early = ref > 1e-6
         d = np.abs(h[early] - ref[early])
-        assert np.all(d <= 1e-9 * ref[early] + 1e-13), float(d.max())
+        print("collapse invariance: max rel difference %.3e" % float((d / ref[early]).max()))
+        # measured <= 1.3e-9 over levels and sizes
+        assert np.all(d <= 1e-8 * ref[early]), float((d / ref[early]).max())
 
 
 def test_model_choice_is_reported_and_valid():
@@ -611,7 +616,7 @@ def test_full_size_cycles_match_oracle(full_size_case):
     v = ora.vcycle(b, np.zeros_like(b))
     d = rel(c(u1), v)
     print("one V-cycle: max rel difference %.3e" % d, flush=True)
-    assert d <= 1e-9, d
+    assert d <= 1e-10, d      # measured 1.4e-11
     hist_ref = []
     u = np.zeros_like(b)
     for _ in range(3):
@@ -620,8 +625,11 @@ def test_full_size_cycles_match_oracle(full_size_case):
     u3, i3 = HB.Hierarchy(g(planes), max_cycles=3).solve(g(b), tol=1e-30, check=False)
     h3 = np.array(i3.history())
     print("first cycles: gpu %s oracle %s" % (list(h3), hist_ref), flush=True)
-    assert np.all(np.abs(h3 - np.array(hist_ref)) <= 1e-8 * np.array(hist_ref))
-    assert rel(c(u3), u) <= 1e-9
+    print("first cycles max rel difference %.3e, iterate after 3 cycles %.3e"
+          % (float((np.abs(h3 - np.array(hist_ref)) / np.array(hist_ref)).max()), rel(c(u3), u)), flush=True)
+    # measured 4.2e-12 and 5.9e-12
+    assert np.all(np.abs(h3 - np.array(hist_ref)) <= 5e-11 * np.array(hist_ref))
+    assert rel(c(u3), u) <= 5e-11
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -691,7 +699,7 @@ def test_adjoint_full_size_matches_oracle_gradient_and_central_differences():
     grad = c(th.grad)
     e = rel(grad, go)
     print("gradient vs oracle: max rel difference %.3e" % e, flush=True)
-    assert e <= 1e-6, e
+    assert e <= 1e-8, e       # measured 1.1e-9
     # central differences, h = 1e-6, on 32 random cells.  Each loss comes from
     # a solve started at the unperturbed solution and run to the rounding
     # floor; the loss's evaluation noise is measured by evaluating it at theta
@@ -731,7 +739,10 @@ def test_adjoint_full_size_matches_oracle_gradient_and_central_differences():
     assert resolved >= 16, resolved
 
 
-def test_batched_adjoint_equals_single_problem_adjoint():
+def test_batched_adjoint_equals_single_problem_adjoint(monkeypatch):
+    # the batch runs the unpipelined cycle with no agglomeration stages; the
+    # single-problem reference runs the same, so gradients are bitwise equal
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "1")
     n, nb = 129, 3
     theta = np.stack([inputs.theta_box5(n, n, seed=3100 + k) for k in range(nb)])
     b = np.stack([inputs.load_uniform(n, n, seed=5100 + k) for k in range(nb)])
@@ -743,11 +754,11 @@ def test_batched_adjoint_equals_single_problem_adjoint():
     gb = c(th.grad)
     for k in range(nb):
         t1 = g(theta[k]).requires_grad_(True)
-        u1 = HB.SolveFV.apply(t1, g(b[k]), 1e-10)
+        u1 = HB.SolveFV.apply(t1, g(b[k]), 1e-10, {"cluster_wg": 0})
         (0.5 * ((u1 - g(u_obs[k])) ** 2).sum()).backward()
         d = rel(gb[k], c(t1.grad))
         print("problem %d: batched vs single gradient %.3e" % (k, d), flush=True)
-        assert d <= 1e-6, d
+        assert torch.equal(th.grad[k], t1.grad), d
 
 
 @pytest.mark.parametrize("pipelined", ["0", "1"])

@@ -6,9 +6,10 @@ oracle window reproduces plus the true residual of the answer.
 
 Tolerances: the GPU sums the same terms in other orders (27-point stencils,
 Galerkin triple sums), so single operations agree to a few ulps of their
-magnitudes (1e-13 relative); relative residual histories agree to 1e-9
-relative over a solve (errors grow with the condition of the coarse
-operators but stay far below the 1e-10 stopping test's resolution).
+magnitudes (1e-13 relative); relative residual histories agree to 5e-14 of
+their largest entry over a solve (measured <= 5.7e-15: errors grow with the
+condition of the coarse operators but stay far below the 1e-10 stopping
+test's resolution).
 """
 import numpy as np
 import pytest
@@ -128,7 +129,10 @@ def test_solve_history_matches_the_oracle(shape, kind, prm):
     h = np.array(info.history())
     print("%s %s: %d cycles (oracle %d), relres %.3e" % (shape, kind, info.cycles, len(hist), info.relres))
     assert info.cycles == len(hist)
-    assert np.abs(h - hist).max() <= 1e-9 * hist.max()
+    print("history: max difference %.3e of the largest, %.3e relative" % (np.abs(h - hist).max() / hist.max(),
+                                                                         (np.abs(h - hist) / hist).max()))
+    # measured <= 2.3e-15 of the largest and <= 2.8e-7 relative per cycle
+    assert np.abs(h - hist).max() <= 5e-14 * hist.max()
     assert np.all(np.abs(h - hist) <= 1e-6 * hist)
     assert info.relres <= 1e-10
     # the answer's residual under the oracle's operator
@@ -150,7 +154,8 @@ def test_solve_from_a_27_point_finest_operator_matches_the_oracle():
     gpu = HB.Hierarchy3(g(planes))
     u, info = gpu.solve(g(b), tol=1e-10)
     h = np.array(info.history())
-    assert info.cycles == len(hist) and np.abs(h - hist).max() <= 1e-9 * hist.max()
+    print("27-point history: max difference %.3e of the largest" % (np.abs(h - hist).max() / hist.max()))
+    assert info.cycles == len(hist) and np.abs(h - hist).max() <= 5e-14 * hist.max()   # measured 1.6e-15
     r = ora.residual(ora.L - 1, b, c(u))
     assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
 
@@ -305,4 +310,5 @@ def test_random_shapes_and_parameters_match_the_oracle(case):
     assert info.cycles == len(hist)
     # relative residuals near the rounding level (a direct solve on one
     # level) differ by rounding alone: an absolute floor of 1e-14
-    assert np.abs(h - hist).max() <= 1e-9 * hist.max() + 1e-14
+    print("random case history: max difference %.3e of the largest" % (np.abs(h - hist).max() / hist.max()))
+    assert np.abs(h - hist).max() <= 5e-14 * hist.max() + 1e-14     # measured <= 5.7e-15
