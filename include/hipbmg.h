@@ -240,6 +240,20 @@ hipbmg_status hipbmg_op32_interp_smooth(hipbmg_handle h, int l, const float *b, 
 hipbmg_status hipbmg_op32_inner(hipbmg_handle h, const float *r, float *e, int cycles, double rnorm,
                                 double inner_tol, double *hist_host, int *cycles_host, void *stream);
 
+/* The quantity of the convergence test (relative residual, the stopping
+ * criterion of every solve) for any operator and iterate:
+ * out_host[0] = ||b - A u||_2 and out_host[1] = ||b||_2, both over interior
+ * vertices, with A given by coeffs ([3 or 5][ny][nx] planes, npt 5 or 9, the
+ * plane format above) and b, u [ny][nx] (device).  Entries of u on the
+ * boundary ring are read as 0.  Any nx, ny >= 3.  The sums of squares are
+ * reduced in a fixed order, so equal inputs give equal bits.  Per-workgroup
+ * partial sums go to scratch device memory taken for the call from the
+ * registered allocator (or hipMalloc) and returned before the call returns.
+ * Synchronises the stream.  EINVAL on a null pointer or bad sizes, ENOMEM if
+ * the scratch cannot be had, EHIP on a launch or copy failure. */
+hipbmg_status hipbmg_residual_norm(int nx, int ny, int npt, const double *coeffs, const double *b,
+                                   const double *u, double *out_host, void *stream);
+
 /* Batched solves of many independent problems of different sizes (each with
  * its own hierarchy, built as by hipbmg_setup, and its own collapse level).
  * One launch runs the same V-cycle stage (Algorithm 1) of all problems; the

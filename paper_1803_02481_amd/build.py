@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libhipbmg.so")
 OBJ = os.path.join(ROOT, "_build")
 
 HIP_SOURCES = ["bmg_stream.hip", "bmg_setup.hip", "bmg_collapse.hip", "bmg_misc.hip",
-               "bmg_host.hip", "bmg_calib.hip", "bmg3d.hip"]
+               "bmg_host.hip", "bmg_calib.hip", "bmg3d.hip", "bmg_resnorm.hip"]
 CXX_SOURCES = ["bmg_model.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INC,

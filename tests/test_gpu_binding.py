@@ -107,3 +107,23 @@ def test_batched_solves_apply_each_call_tolerance(precision, use_graph):
     assert all(a <= b for a, b in zip(cycles[1e-6], cycles[1e-10])), cycles
     if precision == HB.FP64:
         assert all(a < b for a, b in zip(cycles[1e-6], cycles[1e-10])), cycles
+
+
+@pytest.mark.parametrize("npt,nx,ny", [(5, 65, 65), (5, 257, 193), (9, 129, 97), (5, 3, 3), (9, 1025, 35)])
+def test_residual_norm_matches_host_residual(npt, nx, ny):
+    from tests import helpers as H
+    from tests.test_gpu_parity import make_planes
+    planes = make_planes(nx, ny, npt, seed=nx + ny) if nx > 3 else O.fv5(rand_cells(nx, ny, 1))
+    rng = np.random.default_rng(nx * ny)
+    b = rng.standard_normal((ny, nx))
+    u = rng.standard_normal((ny, nx))
+    rn, bn = HB.residual_norm(g(planes), g(b), g(u))
+    # the boundary ring of u is read as zero, of b ignored
+    r = H.residual_from_planes(planes, b, u)
+    want_r = float(np.linalg.norm(r))
+    want_b = float(np.linalg.norm(b[1:-1, 1:-1]))
+    assert rn == pytest.approx(want_r, rel=1e-13) and bn == pytest.approx(want_b, rel=1e-13), (rn, want_r, bn, want_b)
+    # the same bits on a second call
+    assert HB.residual_norm(g(planes), g(b), g(u)) == (rn, bn)
+    with pytest.raises(ValueError):
+        HB.residual_norm(g(planes), g(b[:-1]), g(u))
