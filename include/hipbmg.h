@@ -254,6 +254,18 @@ hipbmg_status hipbmg_op32_inner(hipbmg_handle h, const float *r, float *e, int c
 hipbmg_status hipbmg_residual_norm(int nx, int ny, int npt, const double *coeffs, const double *b,
                                    const double *u, double *out_host, void *stream);
 
+/* hipbmg_residual_norm for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results (bitwise), but the partial sums live in
+ * a fixed 512 KiB array of each device's global memory that the library holds
+ * until the process ends.  No hipMalloc, hipFree or other allocating call is
+ * made.  Grids whose partials exceed the array (more than 32767 workgroups of
+ * 256 columns x 64 rows; every grid up to 16385 x 16385 fits) give EINVAL
+ * before any device work.  All calls on one device share its array: calls that
+ * overlap on one device race and must be serialised by the caller. */
+hipbmg_status hipbmg_residual_norm_noalloc(int nx, int ny, int npt, const double *coeffs, const double *b,
+                                           const double *u, double *out_host, void *stream);
+
 /* Batched solves of many independent problems of different sizes (each with
  * its own hierarchy, built as by hipbmg_setup, and its own collapse level).
  * One launch runs the same V-cycle stage (Algorithm 1) of all problems; the

@@ -10,9 +10,19 @@
 #include "bmg_internal.h"
 
 #include <cmath>
+#include <cstdio>
+#include <mutex>
 #include <vector>
 
 namespace hbmg {
+
+// Scratch of the allocation-free entry point: a fixed array in each device's
+// global memory, held until the process ends.  65536 doubles (512 KiB) hold the
+// partials of 32767 workgroups, enough for every grid up to 16385 x 16385.
+// Every call on a device uses that device's array, so calls that overlap on
+// one device race.
+constexpr size_t RN_SCRATCH_DOUBLES = 65536;
+static __device__ __align__(256) double scratch[RN_SCRATCH_DOUBLES];
 
 constexpr int RN_THREADS = 256;
 constexpr int RN_ROWS = 64;
@@ -108,24 +118,24 @@ static size_t resnorm_scratch_doubles(int nx, int ny)
     return 2 * (size_t)g.x * g.y + 2;
 }
 
-// Both kernels on `scratch` (resnorm_scratch_doubles(nx, ny) doubles of device
+// Both kernels on `work` (resnorm_scratch_doubles(nx, ny) doubles of device
 // memory), the two norms copied to out_host.
 static hipbmg_status resnorm_run(int nx, int ny, int npt, const double *coeffs, const double *b, const double *u,
-                                 double *scratch, double *out_host, hipStream_t s)
+                                 double *work, double *out_host, hipStream_t s)
 {
     const size_t plane = (size_t)nx * ny;
     const double *C = coeffs, *W = coeffs + plane, *S = coeffs + 2 * plane;
     const double *SW = npt == 9 ? coeffs + 3 * plane : nullptr, *SE = npt == 9 ? coeffs + 4 * plane : nullptr;
     const dim3 g = resnorm_grid(nx, ny);
     const int nblk = (int)(g.x * g.y);
-    double *out = scratch + 2 * (size_t)nblk;
+    double *out = work + 2 * (size_t)nblk;
     if (npt == 9)
-        hipLaunchKernelGGL(k_resnorm_partials<9>, g, dim3(RN_THREADS), 0, s, nx, ny, C, W, S, SW, SE, b, u, scratch);
+        hipLaunchKernelGGL(k_resnorm_partials<9>, g, dim3(RN_THREADS), 0, s, nx, ny, C, W, S, SW, SE, b, u, work);
     else
-        hipLaunchKernelGGL(k_resnorm_partials<5>, g, dim3(RN_THREADS), 0, s, nx, ny, C, W, S, SW, SE, b, u, scratch);
+        hipLaunchKernelGGL(k_resnorm_partials<5>, g, dim3(RN_THREADS), 0, s, nx, ny, C, W, S, SW, SE, b, u, work);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(RN_THREADS), 0, s, scratch, nblk, out);
+        hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(RN_THREADS), 0, s, work, nblk, out);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(out_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -161,13 +171,62 @@ extern "C" hipbmg_status hipbmg_residual_norm(int nx, int ny, int npt, const dou
     hipbmg_status st = resnorm_check(nx, ny, npt, coeffs, b, u, out_host);
     if (st != HIPBMG_OK) return st;
     std::vector<void *> owned;
-    void *scratch = nullptr;
-    if (dev_malloc(&scratch, resnorm_scratch_doubles(nx, ny) * sizeof(double)) != hipSuccess || !scratch) {
+    void *work = nullptr;
+    if (dev_malloc(&work, resnorm_scratch_doubles(nx, ny) * sizeof(double)) != hipSuccess || !work) {
         set_last_error("scratch allocation failed");
         return HIPBMG_ENOMEM;
     }
-    owned.push_back(scratch);
-    st = resnorm_run(nx, ny, npt, coeffs, b, u, (double *)scratch, out_host, (hipStream_t)stream);
+    owned.push_back(work);
+    st = resnorm_run(nx, ny, npt, coeffs, b, u, (double *)work, out_host, (hipStream_t)stream);
     dev_free_all(owned);
     return st;
+}
+
+// Device address of this device's scratch array.  In host code `scratch` is
+// only a stand-in for the device symbol: its address is asked from the runtime
+// once per device, with that device current, and kept.
+static hipbmg_status scratch_of_device(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_last_error("no usable current device");
+        return HIPBMG_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_last_error(e != hipSuccess ? hipGetErrorString(e) : "scratch symbol has no address");
+            return HIPBMG_EHIP;
+        }
+        ptr[dev] = (double *)p;
+    }
+    *out = ptr[dev];
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_residual_norm_noalloc(int nx, int ny, int npt, const double *coeffs,
+                                                      const double *b, const double *u, double *out_host,
+                                                      void *stream)
+{
+    hipbmg_status st = resnorm_check(nx, ny, npt, coeffs, b, u, out_host);
+    if (st != HIPBMG_OK) return st;
+    const size_t need = resnorm_scratch_doubles(nx, ny);
+    if (need > RN_SCRATCH_DOUBLES) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "a %d x %d grid needs %zu doubles of scratch; the allocation-free limit is %zu",
+                      nx, ny, need, RN_SCRATCH_DOUBLES);
+        set_last_error(msg);
+        return HIPBMG_EINVAL;
+    }
+    double *sp = nullptr;
+    st = scratch_of_device(&sp);
+    if (st != HIPBMG_OK) return st;
+    // every partial and both results are written before they are read: nothing
+    // left by an earlier call needs clearing
+    return resnorm_run(nx, ny, npt, coeffs, b, u, sp, out_host, (hipStream_t)stream);
 }

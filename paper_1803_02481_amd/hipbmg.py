@@ -75,6 +75,7 @@ _SIGS = {
                                ctypes.POINTER(_I), _VP]),
     "hipbmg_fv5_from_cells": (_I, [_I, _I, _VP, _I, _VP, _VP]),
     "hipbmg_residual_norm": (_I, [_I, _I, _I, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "hipbmg_residual_norm_noalloc": (_I, [_I, _I, _I, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "hipbmg_fv5_aniso": (_I, [_I, _I, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
     "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
     "hipbmg_profile": (_I, [_VP, _I]),
@@ -499,16 +500,17 @@ CALIBRATION_KEYS = ("alpha_launch_us", "hbm_GBps", "cache_GBps",
     for k in range(8))
 
 
-def residual_norm(coeffs, b, u):
+def residual_norm(coeffs, b, u, noalloc=False):
     """(||b - A u||_2, ||b||_2) over interior vertices for the operator of the
-    stencil planes coeffs ([3 or 5][ny][nx])."""
+    stencil planes coeffs ([3 or 5][ny][nx]).  noalloc: the entry point that
+    allocates no device memory (hipbmg_residual_norm_noalloc)."""
     if coeffs.dim() != 3 or coeffs.shape[0] not in (3, 5):
         raise ValueError("coeffs must be [3 or 5][ny][nx]")
     ny, nx = int(coeffs.shape[1]), int(coeffs.shape[2])
     out = (ctypes.c_double * 2)()
-    _check(lib().hipbmg_residual_norm(nx, ny, 5 if coeffs.shape[0] == 3 else 9, _ptr(coeffs, name="coeffs"),
-                                      _ptr(b, shape=(ny, nx), name="b"), _ptr(u, shape=(ny, nx), name="u"), out,
-                                      _stream()))
+    fn = lib().hipbmg_residual_norm_noalloc if noalloc else lib().hipbmg_residual_norm
+    _check(fn(nx, ny, 5 if coeffs.shape[0] == 3 else 9, _ptr(coeffs, name="coeffs"),
+              _ptr(b, shape=(ny, nx), name="b"), _ptr(u, shape=(ny, nx), name="u"), out, _stream()))
     return out[0], out[1]
 
 
