@@ -104,10 +104,42 @@ def per_cycle(HB, torch, coeffs, b, reps=3, **prm):
     return sorted(diffs)[len(diffs) // 2], model
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, logical CPUs, the CPUs this
+    process may use, and OMP_NUM_THREADS."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_threads():
+    """Threads for the all-core oracle runs: OMP_NUM_THREADS if set (the share
+    of the host this process is given), else every CPU it may use."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) >= 1:
+        return int(env)
+    return host_info()["usable_cpus"] or 1
+
+
 def oracle_workloads(args, n, extra, O, np, inputs):
-    """The single-threaded FP64 oracle timed on bounded samples of the other
-    workloads (the oracle has no FP32 path: every entry is its FP64 solve)."""
+    """The FP64 oracle, on all the host cores this process is given, timed on
+    bounded samples of the other workloads (its FP32 mode emulates the inner
+    solver for checking; every entry here is an FP64 solve)."""
     res = {}
+    nth = oracle_threads()
+    O.set_threads(nth)
     # 65^2, D = 1: the whole solve
     m = 65
     oh = O.Hierarchy(O.fv5(inputs.cells_constant(m, m)))
@@ -115,7 +147,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
     t0 = time.perf_counter()
     _, hist = oh.solve(bm, tol=TOL)
     el = time.perf_counter() - t0
-    res["constant_65"] = {"value": 1.0 / el, "unit": "solves/s", "cores": 1,
+    res["constant_65"] = {"value": 1.0 / el, "unit": "solves/s", "cores": nth,
                           "sample": "whole FP64 solve, %d cycles" % (len(hist))}
     # two-phase checkerboard at n^2: a few cycles, scaled by the GPU solve's
     # FP64 cycle count
@@ -129,7 +161,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
         for _ in range(k):
             uc = oh.vcycle(bc, uc)
         tc = (time.perf_counter() - t0) / k
-        res["checkerboard_%d" % n] = {"value": 1.0 / (tc * cb["cycles"]), "unit": "solves/s", "cores": 1,
+        res["checkerboard_%d" % n] = {"value": 1.0 / (tc * cb["cycles"]), "unit": "solves/s", "cores": nth,
                                       "sample": "%d FP64 cycles (%.2f s/cycle), scaled by the %d cycles of the "
                                                 "GPU FP64 solve" % (k, tc, cb["cycles"])}
         del oh
@@ -146,7 +178,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
         for _ in range(k):
             up = oh.vcycle(bp, up)
         tc = (time.perf_counter() - t0) / k
-        res["paper_workload"] = {"value": 1e3 * 10 * tc, "unit": "ms per 10 cycles", "cores": 1,
+        res["paper_workload"] = {"value": 1e3 * 10 * tc, "unit": "ms per 10 cycles", "cores": nth,
                                  "sample": "%d FP64 cycles (%.2f s/cycle), scaled to 10" % (k, tc)}
         del oh
     # batched: the first 8 problems solved whole, scaled to the batch by vertex count
@@ -164,7 +196,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
             pts += mi * mi
             del oh
         t_batch = t_s * extra["batched"]["points"] / pts
-        res["batched"] = {"value": len(sizes) / t_batch, "unit": "problems/s", "cores": 1,
+        res["batched"] = {"value": len(sizes) / t_batch, "unit": "problems/s", "cores": nth,
                           "sample": "FP64 solves of problems 0-%d (sizes %s, %.2f s), scaled to the batch's "
                                     "%d vertices" % (len(sample) - 1, [sizes[i] for i in sample], t_s,
                                                      extra["batched"]["points"])}
@@ -181,7 +213,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
         lam, _ = oh.solve(uo - u_obs, tol=TOL)
         O.grad_logD(D, uo, lam)
         el = time.perf_counter() - t0
-        res["adjoint"] = {"value": 1.0 / el, "unit": "gradients/s", "cores": 1,
+        res["adjoint"] = {"value": 1.0 / el, "unit": "gradients/s", "cores": nth,
                           "sample": "one %dx%d gradient: setup, FP64 forward and adjoint solves, cell kernel "
                                     "(%.2f s)" % (m, m, el)}
     # 3D: two V-cycles of the 3D oracle at 129^3 (its 257^3 setup alone takes
@@ -200,7 +232,7 @@ def oracle_workloads(args, n, extra, O, np, inputs):
         n3 = extra["next_3d"]["n"]
         scale = (n3 / m) ** 3
         cyc = extra["next_3d"]["cycles"]
-        res["next_3d"] = {"value": 1.0 / (tc * scale * cyc), "unit": "solves/s", "cores": 1,
+        res["next_3d"] = {"value": 1.0 / (tc * scale * cyc), "unit": "solves/s", "cores": nth,
                           "sample": "%d FP64 V(2,1)-cycles of the 3D oracle at %d^3 (%.3f s/cycle), scaled by "
                                     "vertex count to %d^3 and by the %d cycles of the GPU solve"
                                     % (k, m, tc, n3, cyc)}
@@ -568,19 +600,29 @@ def main():
     cpu = None
     if not args.no_cpu:
         from oracle import oracle as O
-        log("bench: CPU oracle baseline (%d cycles)" % args.cpu_cycles)
+        nth = oracle_threads()
+        log("bench: CPU oracle baseline (%d cycles on %d threads, %d on one)" % (args.cpu_cycles, nth, 2))
         planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, -2.0, 2.0, seed=1))
         bh = inputs.load_uniform(n, n, seed=2)
         oh = O.Hierarchy(planes)
-        uh = np.zeros_like(bh)
-        t0 = time.perf_counter()
-        for _ in range(args.cpu_cycles):
-            uh = oh.vcycle(bh, uh)
-        t_cycle = (time.perf_counter() - t0) / args.cpu_cycles
-        cpu = {"value": 1.0 / (t_cycle * cycles), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": "%d FP64 V(2,1)-cycles of the single-threaded oracle on the same %dx%d problem "
-                         "(%.2f s/cycle), scaled by the %d cycles the solve takes"
-                         % (args.cpu_cycles, n, n, t_cycle, cycles)}
+
+        def oracle_cycle_s(threads, k):
+            O.set_threads(threads)
+            uh = np.zeros_like(bh)
+            t0 = time.perf_counter()
+            for _ in range(k):
+                uh = oh.vcycle(bh, uh)
+            return (time.perf_counter() - t0) / k
+
+        t_cycle = oracle_cycle_s(nth, args.cpu_cycles)
+        t_cycle1 = oracle_cycle_s(1, 2)
+        O.set_threads(nth)
+        cpu = {"value": 1.0 / (t_cycle * cycles), "unit": "solves/s", "cores": nth, "kind": "oracle",
+               "sample": "%d FP64 V(2,1)-cycles of the oracle on %d threads on the same %dx%d problem "
+                         "(%.3f s/cycle), scaled by the %d cycles the solve takes; the same oracle on one "
+                         "thread: 2 cycles, %.3f s/cycle" % (args.cpu_cycles, nth, n, n, t_cycle, cycles, t_cycle1),
+               "single_thread_value": 1.0 / (t_cycle1 * cycles),
+               "host": host_info()}
 
     if not args.no_cpu:
         extra["cpu_oracle_workloads"] = oracle_workloads(args, n, extra, O, np, inputs)

@@ -31,11 +31,17 @@
  * the tests pin them by closed forms (bilinear for D=1, flux-weighted for
  * coefficients that vary in one direction only) rather than by BoxMG itself.
  *
+ * Threads: the loops over rows of one colour, of the residual and of the
+ * interpolation run in parallel (OpenMP).  Their points are independent (no
+ * two points of one colour couple), so the results are bitwise those of one
+ * thread; restriction (a scatter), norms and setup stay sequential.
+ *
  * Floating point: double throughout, built with -ffp-contract=off, except the
  * FP32 edge-form section at the end, which emulates the inner solver of mixed
  * precision with float arithmetic on a once-demoted copy of every level.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -389,6 +395,15 @@ void oracle_free(void *hv)
 
 int oracle_num_levels(void *hv) { return ((ohier *)hv)->L; }
 
+/* Threads of the parallel loops from now on (n >= 1); returns the previous
+ * count.  Results do not depend on it. */
+int oracle_set_threads(int n)
+{
+    int prev = omp_get_max_threads();
+    if (n >= 1) omp_set_num_threads(n);
+    return prev;
+}
+
 void oracle_level_size(void *hv, int l, int *nx, int *ny)
 {
     ohier *h = hv;
@@ -425,6 +440,7 @@ static double apply_row(const olevel *lv, const double *x, int i, int j)
 static void gs_sweep(const olevel *lv, double *x, const double *b)
 {
     for (int colour = 0; colour < 4; ++colour)
+#pragma omp parallel for schedule(static)
         for (int j = 1; j <= lv->ny - 2; ++j)
             for (int i = 1; i <= lv->nx - 2; ++i) {
                 if ((i % 2) + 2 * (j % 2) != colour) continue;
@@ -437,6 +453,7 @@ static void gs_sweep(const olevel *lv, double *x, const double *b)
 static void residual(const olevel *lv, const double *x, const double *b, double *r)
 {
     memset(r, 0, (size_t)lv->nx * lv->ny * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int j = 1; j <= lv->ny - 2; ++j)
         for (int i = 1; i <= lv->nx - 2; ++i) {
             size_t p = (size_t)j * lv->nx + i;
@@ -462,6 +479,7 @@ static void restrict_pt(const olevel *f, const double *r, const olevel *c, doubl
 static void interp_correct(const olevel *f, double *x, const double *r, const olevel *c,
                            const double *xc, int rescorr)
 {
+#pragma omp parallel for schedule(static)
     for (int j = 1; j <= f->ny - 2; ++j)
         for (int i = 1; i <= f->nx - 2; ++i) {
             const double *pr = &f->P[((size_t)j * f->nx + i) * 4];
@@ -727,6 +745,7 @@ static float diag32(const olevel *lv, int i, int j)
 static void gs_sweep32(const olevel *lv, float *x, const float *b)
 {
     for (int colour = 0; colour < 4; ++colour)
+#pragma omp parallel for schedule(static)
         for (int j = 1; j <= lv->ny - 2; ++j)
             for (int i = 1; i <= lv->nx - 2; ++i) {
                 if ((i % 2) + 2 * (j % 2) != colour) continue;
@@ -740,6 +759,7 @@ static void gs_sweep32(const olevel *lv, float *x, const float *b)
 static void residual32(const olevel *lv, const float *x, const float *b, float *r)
 {
     memset(r, 0, (size_t)lv->nx * lv->ny * sizeof(float));
+#pragma omp parallel for schedule(static)
     for (int j = 1; j <= lv->ny - 2; ++j)
         for (int i = 1; i <= lv->nx - 2; ++i) {
             size_t p = (size_t)j * lv->nx + i;
@@ -765,6 +785,7 @@ static void restrict32(const olevel *f, const float *r, const olevel *c, float *
 static void interp_correct32(const olevel *f, float *x, const float *r, const olevel *c, const float *xc,
                              int rescorr)
 {
+#pragma omp parallel for schedule(static)
     for (int j = 1; j <= f->ny - 2; ++j)
         for (int i = 1; i <= f->nx - 2; ++i) {
             const float *pr = &f->P32[((size_t)j * f->nx + i) * 4];

@@ -37,6 +37,11 @@
  * a Kronecker-product coarse operator for D=1, products of one-dimensional
  * flux weights for coefficients that vary along x only).
  *
+ * Threads: the loops over planes of one colour, of the residual and of the
+ * interpolation run in parallel (OpenMP); their points are independent, so
+ * the results are bitwise those of one thread.  Restriction (a scatter),
+ * norms and setup stay sequential.
+ *
  * Floating point: double throughout, built with -ffp-contract=off.
  */
 #include <math.h>
@@ -464,6 +469,7 @@ static double apply3(const olev3 *lv, const double *x, int i, int j, int k)
 static void gs3(const olev3 *lv, double *x, const double *b)
 {
     for (int colour = 0; colour < 8; ++colour)
+#pragma omp parallel for schedule(static)
         for (int k = 1; k <= lv->nz - 2; ++k)
             for (int j = 1; j <= lv->ny - 2; ++j)
                 for (int i = 1; i <= lv->nx - 2; ++i) {
@@ -477,6 +483,7 @@ static void gs3(const olev3 *lv, double *x, const double *b)
 static void residual3(const olev3 *lv, const double *x, const double *b, double *r)
 {
     memset(r, 0, (size_t)lv->nx * lv->ny * lv->nz * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int k = 1; k <= lv->nz - 2; ++k)
         for (int j = 1; j <= lv->ny - 2; ++j)
             for (int i = 1; i <= lv->nx - 2; ++i) {
@@ -503,6 +510,7 @@ static void restrict3(const olev3 *f, const double *r, const olev3 *c, double *b
 /* x += P x_c, plus r/C at vertices that are not coarse points */
 static void interp3(const olev3 *f, double *x, const double *r, const olev3 *c, const double *xc, int rescorr)
 {
+#pragma omp parallel for schedule(static)
     for (int k = 1; k <= f->nz - 2; ++k)
         for (int j = 1; j <= f->ny - 2; ++j)
             for (int i = 1; i <= f->nx - 2; ++i) {

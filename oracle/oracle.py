@@ -23,11 +23,12 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force=False):
-    """Compile the oracle with gcc (plain IEEE double, no FMA contraction)."""
+    """Compile the oracle with gcc (plain IEEE double, no FMA contraction,
+    OpenMP for the loops whose points are independent)."""
     newest = max(os.path.getmtime(s) for s in _SRCS)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared"]
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
                               + _SRCS + ["-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -58,6 +59,8 @@ def lib():
         L.oracle_coarse_solve.argtypes = [ctypes.c_void_p, _D, _D]
         L.oracle_vcycle.argtypes = [ctypes.c_void_p, _D, _D]
         L.oracle_fv5.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_grad_logD.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.oracle_fv5_aniso.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
                                        _D, _D, _D]
@@ -94,6 +97,12 @@ def lib():
         L.oracle3_coarse_solve.argtypes = [ctypes.c_void_p, _D, _D]
         L.oracle3_vcycle.argtypes = [ctypes.c_void_p, _D, _D]
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (results do not depend on it);
+    returns the previous count."""
+    return lib().oracle_set_threads(int(n))
 
 
 def _p(a):

@@ -15,7 +15,7 @@ import argparse
 import os
 import sys
 
-sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 
 # rocprofv3 kernel names of the finest-level (5-point FP64) streaming kernels
@@ -63,7 +63,7 @@ def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
             if v:
                 per[k] = sum(v) / len(v) * 1024.0 * scale
         out[name] = {"scale": scale, "bytes_per_launch": per}
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    root = os.path.dirname(os.path.abspath(__file__))
     src = os.path.join(root, "paper_1803_02481_amd", "csrc", "bmg_stream.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     npts = n * n
@@ -71,10 +71,10 @@ def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
              "Commands (GPU box, `$R` = repository root):", "", "```",
              "cd /tmp && export TMPDIR=/tmp PYTHONPATH=$R",
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_FETCH_SIZE -o run -- "
-             "python3 $R/paper_1803_02481_amd/perf_probe.py",
+             "python3 $R/perf_probe.py",
              "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_WRITE_SIZE -o run -- "
-             "python3 $R/paper_1803_02481_amd/perf_probe.py",
-             "python3 $R/paper_1803_02481_amd/perf_probe.py --summarize $R/gpurun_out/pmc_FETCH_SIZE "
+             "python3 $R/perf_probe.py",
+             "python3 $R/perf_probe.py --summarize $R/gpurun_out/pmc_FETCH_SIZE "
              "$R/gpurun_out/pmc_WRITE_SIZE --kernel %s" % kernel, "```", "",
              "Scale factors from a 1 GiB `__amd_rocclr_copyBuffer` (bytes the copy moves / counter bytes): "
              "FETCH %.3f, WRITE %.3f." % (out["FETCH_SIZE"]["scale"], out["WRITE_SIZE"]["scale"]), "",

@@ -16,7 +16,7 @@ import os
 import re
 import sys
 
-sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 # finest-level kernels of the 3D path and their algorithmic bytes per vertex
 # of the whole grid (FP64, 7-point): a colour group reads x, b, C, W, S, B and
@@ -39,7 +39,7 @@ SWEEP = ("gs7g<0>", "gs7g<1>", "gs7g<2>", "gs7g<3>")
 
 def source_sha():
     import hashlib
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    root = os.path.dirname(os.path.abspath(__file__))
     with open(os.path.join(root, "paper_1803_02481_amd", "csrc", "bmg3d.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -71,17 +71,17 @@ def summarize(fetch_dir, write_dir, n=257, copy_bytes=1 << 30):
             v = [float(r["Counter_Value"]) for r in sel if int(r["Grid_Size"]) == gmax]
             per[k] = sum(v) / len(v) * 1024.0 * scale
         out[name] = {"scale": scale, "bytes_per_launch": per}
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    root = os.path.dirname(os.path.abspath(__file__))
     sha = source_sha()
     npts = n ** 3
     lines = ["# HBM traffic of the 3D finest-level kernels, FP64, 257^3 random blocks", "",
              "Commands (GPU box, `$R` = repository root):", "", "```",
              "cd /tmp && export TMPDIR=/tmp PYTHONPATH=$R",
              "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc3_FETCH_SIZE -o run -- "
-             "python3 $R/paper_1803_02481_amd/perf_probe3.py",
+             "python3 $R/perf_probe3.py",
              "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc3_WRITE_SIZE -o run -- "
-             "python3 $R/paper_1803_02481_amd/perf_probe3.py",
-             "python3 $R/paper_1803_02481_amd/perf_probe3.py --summarize $R/gpurun_out/pmc3_FETCH_SIZE "
+             "python3 $R/perf_probe3.py",
+             "python3 $R/perf_probe3.py --summarize $R/gpurun_out/pmc3_FETCH_SIZE "
              "$R/gpurun_out/pmc3_WRITE_SIZE", "```", "",
              "Scale factors from a 1 GiB `__amd_rocclr_copyBuffer` (bytes the copy moves / counter bytes): "
              "FETCH %.3f, WRITE %.3f." % (out["FETCH_SIZE"]["scale"], out["WRITE_SIZE"]["scale"]), "",
