@@ -705,9 +705,17 @@ void oracle32_demote(void *hv)
     }
 }
 
-void oracle32_get_level(void *hv, int l, float *A32, float *P32)
+/* every FP32 entry point works on the demoted levels: built on first use */
+static ohier *with32(void *hv)
 {
     ohier *h = hv;
+    if (!h->lev[0].A32) oracle32_demote(h);
+    return h;
+}
+
+void oracle32_get_level(void *hv, int l, float *A32, float *P32)
+{
+    ohier *h = with32(hv);
     const olevel *lv = &h->lev[l];
     size_t n = (size_t)lv->nx * lv->ny;
     memcpy(A32, lv->A32, n * 9 * sizeof(float));
@@ -840,31 +848,31 @@ static double norm32_interior(const olevel *lv, const float *v)
 
 void oracle32_smooth(void *hv, int l, const float *b, float *x, int sweeps)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     for (int k = 0; k < sweeps; ++k) gs_sweep32(&h->lev[l], x, b);
 }
 
 void oracle32_residual(void *hv, int l, const float *b, const float *x, float *r)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     residual32(&h->lev[l], x, b, r);
 }
 
 void oracle32_restrict(void *hv, int l, const float *r, float *bc)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     restrict32(&h->lev[l], r, &h->lev[l - 1], bc);
 }
 
 void oracle32_interp_correct(void *hv, int l, float *x, const float *r, const float *xc, int rescorr)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     interp_correct32(&h->lev[l], x, r, &h->lev[l - 1], xc, rescorr);
 }
 
 void oracle32_vcycle(void *hv, const float *b, float *x)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     vcycle32(h, h->L - 1, x, b);
 }
 
@@ -875,7 +883,7 @@ void oracle32_vcycle(void *hv, const float *b, float *x)
  * relative residual after cycle k+1. */
 int oracle32_inner(void *hv, const float *r, float *e, int cycles, double rnorm, double inner_tol, double *hist)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     olevel *f = &h->lev[h->L - 1];
     size_t n = (size_t)f->nx * f->ny;
     float *rr = calloc(n, sizeof(float));
@@ -903,7 +911,7 @@ int oracle32_inner(void *hv, const float *r, float *e, int cycles, double rnorm,
 int oracle_solve_mixed(void *hv, const double *bin, double *u, double tol, int max_cycles, int inner_max,
                        double inner_tol, double *hist, int *steps)
 {
-    ohier *h = hv;
+    ohier *h = with32(hv);
     olevel *f = &h->lev[h->L - 1];
     size_t n = (size_t)f->nx * f->ny;
     double *b = calloc(n, sizeof(double)), *r = calloc(n, sizeof(double));
