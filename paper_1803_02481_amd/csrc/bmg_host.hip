@@ -194,6 +194,7 @@ struct hipbmg_hier {
     int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
     int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
     int rb3 = 0;                // row-block steps of the pipelined finest kernel
+    int zexc[2] = {0, 0};       // the pipelined pass forms the finest diagonal ([0] FP64, [1] FP32)
     double *x3_64 = nullptr;    // third iterate buffer of the pipelined finest level
     float *x3_32 = nullptr;
     // device-side stopping: run flag, residual history, and a ring of
@@ -731,6 +732,25 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             st = dalloc(h, &h->x3_64, F.plane, s);
             if (st == HIPBMG_OK && prm.precision == HIPBMG_MIXED) st = dalloc(h, &h->x3_32, F.plane, s);
             if (st != HIPBMG_OK) return bail(st);
+            // a finest operator whose diagonal is exactly the sum of its
+            // connections (pure diffusion, as finite volumes build it) need
+            // not be loaded by the pipelined pass (HIPBMG_NO_ZEXC=1: always load)
+            int noz = 0;
+            if (const char *e = std::getenv("HIPBMG_NO_ZEXC")) noz = std::atoi(e);
+            if (!noz) {
+                int *d_ok = nullptr;
+                st = dalloc(h, &d_ok, 2, s);
+                if (st != HIPBMG_OK) return bail(st);
+                int ok[2] = {0, 0};
+                if (launch_zero_excess_check(F, d_ok, s) != hipSuccess ||
+                    (prm.precision == HIPBMG_MIXED && launch_zero_excess_check(h->lv32[L - 1], d_ok + 1, s) != hipSuccess) ||
+                    hipMemcpyAsync(ok, d_ok, (prm.precision == HIPBMG_MIXED ? 2 : 1) * sizeof(int),
+                                   hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return bail(fail(HIPBMG_EHIP, "zero-excess check failed"));
+                h->zexc[0] = ok[0];
+                h->zexc[1] = ok[1];
+            }
         }
     }
     // collapse level from the performance model (sections 3 and 4)
@@ -1112,6 +1132,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             hipError_t e = enqueue_vcycle<T>(h, lv, d_lv, 0, false, &cc, &dummy, s, true, act);
             if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
             StreamArgs<T> a = base_args(F, h->rb3);
+            a.zexc = h->zexc[PrecIdx<T>::v];
             a.x_in = xb[i];
             a.x_out = xb[(i + 1) % 3];
             a.x_out2 = xb[(i + 2) % 3];
@@ -1166,6 +1187,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
         const LevelDev<T> &Cl = lv[L - 2];
         const int ik = in_i[kdone];
         StreamArgs<T> a = base_args(F, h->rb3);
+        a.zexc = h->zexc[PrecIdx<T>::v];
         a.x_in = xb[ik];
         a.x_out = xb[(ik + 1) % 3];
         a.xc = in_xc[kdone];
@@ -1797,6 +1819,9 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         if (variant == SV_FUSED3_P || variant == SV_FUSED3_PN || variant == SV_INTERP_RC) per += 0.25 * w + 2.0 * w;
         if (variant == SV_SWEEP2_R_ZX) per -= w;
         if (variant == SV_SWEEP2_R || variant == SV_SWEEP2_R_ZX) per += 2.0 * w + 0.25 * w;
+        // a pipelined pass over a zero-excess operator forms C instead of loading it
+        if ((variant == SV_FUSED3 || variant == SV_FUSED3_P || variant == SV_FUSED3_PN) && h->zexc[precision])
+            per -= w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;

@@ -65,6 +65,10 @@ struct StreamArgs {
     // the solve's run flag (null: always run); a launch whose flag reads 0
     // returns at once (the convergence test of an earlier cycle was met)
     const int *active;
+    // SV_FUSED3*: the level's diagonal is the sum of its four connections
+    // (FP64, checked bitwise at setup) or its FP32 excess is zero: the pass
+    // forms the diagonal itself instead of loading the C plane
+    int zexc;
 };
 
 enum StreamVariant {
@@ -105,6 +109,12 @@ hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid,
 template <typename T>
 hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
                                  int nmap, const int *active, hipStream_t s);
+
+// 1 if every interior vertex of a 5-point level has C exactly equal to
+// ((W_p + W_e) + S_p) + S_n (FP64), or an FP32 edge-form excess of exactly 0;
+// the result goes to *flag (device int, written by the check)
+hipError_t launch_zero_excess_check(const LevelDev<double> &A, int *flag, hipStream_t s);
+hipError_t launch_zero_excess_check(const LevelDev<float> &A, int *flag, hipStream_t s);
 
 // Setup kernels.
 hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,

@@ -508,7 +508,11 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 // PONLY && PNORM: stage P alone with its norm and the iterate stored, for a
 // cycle known to be the last (two prologue steps, as the norm's residual
 // reads the row below a block's first final row).
-template <typename T, bool PONLY, bool PNORM = false>
+// ZC: the C plane is not loaded.  FP64 levels form C_p = ((W_p + W_e) + S_p) + S_n
+// from the connections of the row and the row above (the setup checked that
+// this is bitwise the stored C at every interior vertex); FP32 edge-form
+// levels have a zero excess.  The results are bitwise those of loading C.
+template <typename T, bool PONLY, bool PNORM = false, bool ZC = false>
 __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int NPT = 5;
@@ -535,7 +539,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
             const size_t off = (size_t)j * pitch + e;
             ld2(a.x_in + off, r.x0, r.x1);
             ld2(a.b + off, r.b0, r.b1);
-            ld2(a.C + off, r.C0, r.C1);
+            if (!ZC) ld2(a.C + off, r.C0, r.C1);
             ld2(a.W + off, r.W0, r.W1);
             ld2(a.S + off, r.S0, r.S1);
         }
@@ -558,6 +562,15 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
                 r.w0 = wt[WXL * cp + co];
                 r.w1 = wt[WXR * cp + co];
             }
+        }
+    };
+    // ZC: the diagonal of row r once the row above it (ab) is loaded; every
+    // lane calls (the east connection of the odd column is the next lane's W)
+    auto complete_C = [&](Row<T> &r, const Row<T> &ab) {
+        if (ZC && !IsEdge<T>::value) {
+            const T we = fromR(r.W0);
+            r.C0 = r.W0 + r.W1 + r.S0 + ab.S0;
+            r.C1 = r.W1 + we + r.S1 + ab.S1;
         }
     };
     // x += P x_c (+ r/C at fine-only vertices) on a loaded row; coarse column t
@@ -606,16 +619,22 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         load_raw(Rn, jp0);
         load_raw(N1, jp0 + 1);
         load_raw(N2, jp0 + 2);
+        complete_C(Ra, Rm1);
+        complete_C(Rm1, Rn);
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
     for (int jp = jp0; jp <= jpend; jp += 2) {
-        const Row<T> R1 = N1, R2 = N2;
+        Row<T> R1 = N1;
+        const Row<T> R2 = N2;
         if (jp + 2 <= jpend) {
             // the next step's rows: in flight while this step computes
             load_raw(N1, jp + 3);
             load_raw(N2, jp + 4);
         }
+        // diagonals of rows jp and jp+1, whose rows above are now loaded
+        complete_C(Rn, R1);
+        complete_C(R1, R2);
         const T q1_even_row = rc_odd(Rm1, Rn, R1);
         const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
         P.r0 = Rn;
@@ -661,13 +680,51 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     }
 }
 
-template <typename T, bool PONLY, bool PNORM = false>
+template <typename T, bool PONLY, bool PNORM = false, bool ZC = false>
 __global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile_fn();
     if (tile >= a.ntiles) return;
-    stream3_tile<T, PONLY, PNORM>(a, tile);
+    stream3_tile<T, PONLY, PNORM, ZC>(a, tile);
+}
+
+// Zero-excess check of a 5-point level (see launch_zero_excess_check): one
+// thread per vertex; any interior mismatch clears *flag (set to 1 beforehand)
+template <typename T>
+__global__ void k_zero_excess(LevelDev<T> A, int *flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < 1 || i > A.nx - 2 || j < 1 || j > A.ny - 2) return;
+    const size_t p = (size_t)j * A.pitch + i, P = A.pitch;
+    bool ok;
+    if (IsEdge<T>::value)
+        ok = A.C[p] == T(0);
+    else
+        ok = A.C[p] == A.W[p] + A.W[p + 1] + A.S[p] + A.S[p + P];
+    if (!ok) atomicAnd(flag, 0);
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+template <typename T>
+static hipError_t zero_excess_check(const LevelDev<T> &A, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, flag, A.npt == 5 ? 1 : 0);
+    if (A.npt == 5)
+        hipLaunchKernelGGL(k_zero_excess<T>, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_excess_check(const LevelDev<double> &A, int *flag, hipStream_t s)
+{
+    return zero_excess_check(A, flag, s);
+}
+
+hipError_t launch_zero_excess_check(const LevelDev<float> &A, int *flag, hipStream_t s)
+{
+    return zero_excess_check(A, flag, s);
 }
 
 // XCD-aware tile order: WG i runs on XCD i mod 8, so consecutive tiles (the
@@ -889,15 +946,18 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_INTERP_RC: hipLaunchKernelGGL((k_interp_rc<T, NPT>), g, b, 0, s, a); break;
     case SV_FUSED3:
         if (NPT != 5) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stream3<T, false>), g, b, 0, s, a);
+        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, false, false, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_stream3<T, false>), g, b, 0, s, a);
         break;
     case SV_FUSED3_P:
         if (NPT != 5) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stream3<T, true>), g, b, 0, s, a);
+        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, true, false, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_stream3<T, true>), g, b, 0, s, a);
         break;
     case SV_FUSED3_PN:
         if (NPT != 5) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stream3<T, true, true>), g, b, 0, s, a);
+        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, true, true, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_stream3<T, true, true>), g, b, 0, s, a);
         break;
     default: return hipErrorInvalidValue;
     }

@@ -1,7 +1,8 @@
 """GPU checks of streaming-pass variants that must not change the iteration:
 the up leg forming r/C from the rows it loads instead of reading a stored
-plane, and the last cycle of a capped solve run as the pipelined pass's
-first stage alone.  Each is compared bitwise with the path it replaces."""
+plane, the last cycle of a capped solve run as the pipelined pass's first
+stage alone, and the pipelined pass forming a zero-excess operator's diagonal
+instead of loading it.  Each is compared bitwise with the path it replaces."""
 import numpy as np
 import pytest
 import torch
@@ -9,6 +10,7 @@ import torch
 from oracle import oracle as O
 from paper_1803_02481_amd import hipbmg as HB
 from paper_1803_02481_amd import inputs
+from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +19,10 @@ DEV = "cuda:0"
 
 def g(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def c(t):
+    return t.detach().cpu().numpy()
 
 
 def run(planes, b, cycles, tol=1e-30, **prm):
@@ -65,3 +71,42 @@ def test_last_cycle_pass_is_bitwise_the_rebuild(n, monkeypatch):
         assert torch.equal(u0, u1), prec
         assert i0.history() == i1.history(), prec
         assert i0.relres == i1.relres
+
+
+@pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED])
+@pytest.mark.parametrize("nx,ny,gpu_fv", [(257, 257, False), (225, 161, True), (129, 385, False)])
+def test_zero_excess_pass_is_bitwise_the_loading_pass(nx, ny, gpu_fv, precision, monkeypatch):
+    # a finite-volume operator's diagonal is the sum of its connections: the
+    # pipelined pass forms it instead of loading it, with the same bits
+    cells = inputs.cells_log10_blocks(nx, ny, 8, seed=nx + ny)
+    planes = HB.fv5_from_cells(g(cells)) if gpu_fv else g(O.fv5(cells))
+    b = g(inputs.load_uniform(nx, ny, seed=7))
+    res = {}
+    for noz in ("1", "0"):
+        monkeypatch.setenv("HIPBMG_NO_ZEXC", noz)
+        h = HB.Hierarchy(planes, precision=precision)
+        h.profile(True)
+        u, info = h.solve(b, tol=1e-10)
+        per = h.profile_read(precision)["fused3"][2]
+        res[noz] = (u, info.history(), info.cycles, per)
+    assert torch.equal(res["0"][0], res["1"][0])
+    assert res["0"][1:3] == res["1"][1:3]
+    w = 8 if precision == HB.FP64 else 4
+    assert res["1"][3] - res["0"][3] == w * nx * ny     # one plane fewer per launch
+
+
+def test_operator_with_a_reaction_term_keeps_loading_the_diagonal(monkeypatch):
+    # C = sum of connections + h^2 c (a reaction term): not a zero excess
+    n = 129
+    planes = O.fv5(inputs.cells_log10_blocks(n, n, 8, seed=3))
+    planes[0, 1:-1, 1:-1] += 1e-3
+    b = g(inputs.load_uniform(n, n, seed=4))
+    monkeypatch.setenv("HIPBMG_NO_ZEXC", "0")
+    h = HB.Hierarchy(g(planes))
+    h.profile(True)
+    u, info = h.solve(b, tol=1e-10)
+    per = h.profile_read(0)["fused3"][2]
+    assert per == 68 * n * n
+    A = H.matrix_from_planes(planes)
+    bi = H.to_interior(c(b))
+    assert np.linalg.norm(bi - A @ H.to_interior(c(u))) <= 1.2e-10 * np.linalg.norm(bi)
