@@ -195,6 +195,7 @@ struct hipbmg_hier {
     int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
     int rb3 = 0;                // row-block steps of the pipelined finest kernel
     int zexc[2] = {0, 0};       // the pipelined pass forms the finest diagonal ([0] FP64, [1] FP32)
+    int wform = 0;              // the FP64 pipelined pass forms the interpolation weights
     double *x3_64 = nullptr;    // third iterate buffer of the pipelined finest level
     float *x3_32 = nullptr;
     // device-side stopping: run flag, residual history, and a ring of
@@ -751,6 +752,15 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
                 h->zexc[0] = ok[0];
                 h->zexc[1] = ok[1];
             }
+            // HIPBMG_WFORM=1: the FP64 pass forms the finest level's
+            // interpolation weights from the rows it loads instead of reading
+            // the stored ones (bitwise the same; 16 B per vertex fewer, but on
+            // gfx950 the pass is no faster: its eight extra divisions per lane
+            // and step land on a wave that already stalls on dependent
+            // arithmetic at one wave per SIMD)
+            int wf = 0;
+            if (const char *e = std::getenv("HIPBMG_WFORM")) wf = std::atoi(e);
+            h->wform = wf ? 1 : 0;
         }
     }
     // collapse level from the performance model (sections 3 and 4)
@@ -1133,6 +1143,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
             if (e != hipSuccess) return fail(HIPBMG_EHIP, "V-cycle launch failed: %s", hipGetErrorString(e));
             StreamArgs<T> a = base_args(F, h->rb3);
             a.zexc = h->zexc[PrecIdx<T>::v];
+            a.wform = PrecIdx<T>::v == 0 ? h->wform : 0;
             a.x_in = xb[i];
             a.x_out = xb[(i + 1) % 3];
             a.x_out2 = xb[(i + 2) % 3];
@@ -1188,6 +1199,7 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
         const int ik = in_i[kdone];
         StreamArgs<T> a = base_args(F, h->rb3);
         a.zexc = h->zexc[PrecIdx<T>::v];
+        a.wform = PrecIdx<T>::v == 0 ? h->wform : 0;
         a.x_in = xb[ik];
         a.x_out = xb[(ik + 1) % 3];
         a.xc = in_xc[kdone];
@@ -1820,8 +1832,10 @@ extern "C" hipbmg_status hipbmg_profile_read(hipbmg_handle h, int precision, int
         if (variant == SV_SWEEP2_R_ZX) per -= w;
         if (variant == SV_SWEEP2_R || variant == SV_SWEEP2_R_ZX) per += 2.0 * w + 0.25 * w;
         // a pipelined pass over a zero-excess operator forms C instead of loading it
-        if ((variant == SV_FUSED3 || variant == SV_FUSED3_P || variant == SV_FUSED3_PN) && h->zexc[precision])
-            per -= w;
+        const bool f3 = variant == SV_FUSED3 || variant == SV_FUSED3_P || variant == SV_FUSED3_PN;
+        if (f3 && h->zexc[precision]) per -= w;
+        // and forms the weights (FP64): the 8 weight planes at quarter size are not read
+        if (f3 && precision == 0 && h->wform) per -= 2.0 * w;
         *bytes_per_launch_host = per * n;
     }
     return HIPBMG_OK;

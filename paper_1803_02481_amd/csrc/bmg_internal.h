@@ -69,6 +69,9 @@ struct StreamArgs {
     // (FP64, checked bitwise at setup) or its FP32 excess is zero: the pass
     // forms the diagonal itself instead of loading the C plane
     int zexc;
+    // SV_FUSED3* on an FP64 level: the pass forms the interpolation weights
+    // from the rows it loads instead of reading the stored ones (bitwise equal)
+    int wform;
 };
 
 enum StreamVariant {

@@ -3,6 +3,7 @@
 // One thread per output vertex (or cell); these run once per hierarchy and are
 // not part of the solve-phase time the paper reports.
 #include "bmg_internal.h"
+#include "bmg_weights.h"
 
 namespace hbmg {
 
@@ -129,21 +130,15 @@ struct StView {
 // weights of the x-line vertex (i odd, j even) on its west and east coarse vertices
 __device__ void xline_w(const StView &A, int i, int j, double &ww, double &we)
 {
-    double den = A.c(i, j) - A.s(i, j + 1) - A.s(i, j);
-    double aw = A.w(i, j) + A.se(i - 1, j + 1) + A.sw(i, j);
-    double ae = A.w(i + 1, j) + A.sw(i + 1, j + 1) + A.se(i, j);
-    ww = aw / den;
-    we = ae / den;
+    xline_weights(A.c(i, j), A.s(i, j + 1), A.s(i, j), A.w(i, j), A.se(i - 1, j + 1), A.sw(i, j), A.w(i + 1, j),
+                  A.sw(i + 1, j + 1), A.se(i, j), ww, we);
 }
 
 // weights of the y-line vertex (i even, j odd) on its south and north coarse vertices
 __device__ void yline_w(const StView &A, int i, int j, double &ws, double &wn)
 {
-    double den = A.c(i, j) - A.w(i + 1, j) - A.w(i, j);
-    double as = A.s(i, j) + A.se(i, j) + A.sw(i, j);
-    double an = A.s(i, j + 1) + A.sw(i + 1, j + 1) + A.se(i - 1, j + 1);
-    ws = as / den;
-    wn = an / den;
+    yline_weights(A.c(i, j), A.w(i + 1, j), A.w(i, j), A.s(i, j), A.se(i, j), A.sw(i, j), A.s(i, j + 1),
+                  A.sw(i + 1, j + 1), A.se(i - 1, j + 1), ws, wn);
 }
 
 __global__ void k_interp_weights(StView A, int cnx, int cny, double *__restrict__ wt, int cpitch,
@@ -175,10 +170,10 @@ __global__ void k_interp_weights(StView A, int cnx, int cny, double *__restrict_
         double cw = A.w(i, j), ce = A.w(i + 1, j), cs = A.s(i, j), cn = A.s(i, j + 1);
         double csw = A.sw(i, j), cne = A.sw(i + 1, j + 1), cse = A.se(i, j), cnw = A.se(i - 1, j + 1);
         double d = A.c(i, j);
-        w[WCSW] = (csw + cs * sl + cw * wb) / d;
-        w[WCSE] = (cse + cs * sr + ce * eb) / d;
-        w[WCNW] = (cnw + cn * nl + cw * wtp) / d;
-        w[WCNE] = (cne + cn * nr + ce * etp) / d;
+        w[WCSW] = centre_weight(csw, cs, sl, cw, wb, d);
+        w[WCSE] = centre_weight(cse, cs, sr, ce, eb, d);
+        w[WCNW] = centre_weight(cnw, cn, nl, cw, wtp, d);
+        w[WCNE] = centre_weight(cne, cn, nr, ce, etp, d);
     }
     // no weight on boundary coarse vertices
     if (!cin(I, J)) w[WXL] = w[WYB] = w[WCSW] = 0.0;

@@ -30,6 +30,7 @@
 // The tile index is remapped so that the 8 XCDs (WG i runs on XCD i mod 8)
 // each get a contiguous band of strips and share halo rows in their own L2.
 #include "bmg_internal.h"
+#include "bmg_weights.h"
 
 namespace hbmg {
 
@@ -512,7 +513,14 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 // from the connections of the row and the row above (the setup checked that
 // this is bitwise the stored C at every interior vertex); FP32 edge-form
 // levels have a zero excess.  The results are bitwise those of loading C.
-template <typename T, bool PONLY, bool PNORM = false, bool ZC = false>
+// WF (FP64): the interpolation weights are not loaded either.  P forms them
+// from the connections of the rows it loads, with the expressions the setup
+// used to store them (bmg_weights.h), so they are bitwise the stored ones: an
+// x-line vertex from its own row and the S of the row above, a y-line vertex
+// and a cell centre from their row, the row above and the x-line weights of
+// the rows below and above.  The S plane of each row is therefore loaded one
+// step ahead of the rest of the row.
+template <typename T, bool PONLY, bool PNORM = false, bool ZC = false, bool WF = false>
 __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int NPT = 5;
@@ -531,8 +539,9 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
 
     // issue the loads of row j (no use of the loaded values: they stay in
-    // flight while the previous rows are being computed)
-    auto load_raw = [&](Row<T> &r, int j) {
+    // flight while the previous rows are being computed); with_s = false
+    // leaves the S plane out (WF: loaded a step earlier)
+    auto load_raw = [&](Row<T> &r, int j, bool with_s = true) {
         const bool rv = colv && j >= 0 && j < ny;
         r = Row<T>{};
         if (rv) {
@@ -541,7 +550,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
             ld2(a.b + off, r.b0, r.b1);
             if (!ZC) ld2(a.C + off, r.C0, r.C1);
             ld2(a.W + off, r.W0, r.W1);
-            ld2(a.S + off, r.S0, r.S1);
+            if (with_s) ld2(a.S + off, r.S0, r.S1);
         }
         const bool rin = j >= 1 && j <= ny - 2;
         if (cv && rin) {
@@ -552,25 +561,81 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
             r.ca = a.xc[co];
             if (j & 1) {
                 r.cu = a.xc[co + a.cpitch];
+                if (WF) return;
                 r.w0 = wt[WYB * cp + co];
                 r.w1 = wt[WYT * cp + co];
                 r.w2 = wt[WCSW * cp + co];
                 r.w3 = wt[WCSE * cp + co];
                 r.w4 = wt[WCNW * cp + co];
                 r.w5 = wt[WCNE * cp + co];
-            } else {
+            } else if (!WF) {
                 r.w0 = wt[WXL * cp + co];
                 r.w1 = wt[WXR * cp + co];
             }
         }
     };
-    // ZC: the diagonal of row r once the row above it (ab) is loaded; every
-    // lane calls (the east connection of the odd column is the next lane's W)
-    auto complete_C = [&](Row<T> &r, const Row<T> &ab) {
+    // the S plane of row j alone (WF)
+    auto load_s = [&](T &s0v, T &s1v, int j) {
+        s0v = s1v = T(0);
+        if (colv && j >= 0 && j < ny) ld2(a.S + (size_t)j * pitch + e, s0v, s1v);
+    };
+    // ZC: the diagonal of row r once the S of the row above it (sn0, sn1) is
+    // loaded; every lane calls (the east connection of the odd column is the
+    // next lane's W)
+    auto complete_Cs = [&](Row<T> &r, T sn0, T sn1) {
         if (ZC && !IsEdge<T>::value) {
             const T we = fromR(r.W0);
-            r.C0 = r.W0 + r.W1 + r.S0 + ab.S0;
-            r.C1 = r.W1 + we + r.S1 + ab.S1;
+            r.C0 = r.W0 + r.W1 + r.S0 + sn0;
+            r.C1 = r.W1 + we + r.S1 + sn1;
+        }
+    };
+    auto complete_C = [&](Row<T> &r, const Row<T> &ab) { complete_Cs(r, ab.S0, ab.S1); };
+    // WF: weights of the x-line vertex (o, j) of even row r, sn1 the S at
+    // (o, j+1).  w0, w1 are the stored form (zero on boundary coarse vertices
+    // and for a vertex that is not interior); w2, w3 keep the weights before
+    // the coarse-boundary zeroing, which the cell centres above and below use.
+    // Every lane calls.
+    auto inner_v = [&](int i, int j) { return i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2; };
+    auto cin = [&](int I, int J) { return I >= 1 && I <= a.cnx - 2 && J >= 1 && J <= a.cny - 2; };
+    auto xline_row = [&](Row<T> &r, int j, T sn1) {
+        if constexpr (WF) {
+            const T we = fromR(r.W0);
+            double ww_, we_;
+            xline_weights(r.C1, sn1, r.S1, r.W1, 0.0, 0.0, we, 0.0, 0.0, ww_, we_);
+            const bool in = inner_v(o, j);
+            const int J = j >> 1;
+            r.w2 = in ? ww_ : 0.0;
+            r.w3 = in ? we_ : 0.0;
+            r.w0 = in && cin(t, J) ? ww_ : 0.0;
+            r.w1 = in && cin(t + 1, J) ? we_ : 0.0;
+        }
+    };
+    // WF: weights of the y-line vertex (e, j) and the cell centre (o, j) of
+    // odd row r; bl and ab are the even rows below and above (their x-line
+    // weights formed), ab also gives the north connections.  Every lane calls.
+    auto odd_row_weights = [&](Row<T> &r, int j, const Row<T> &bl, const Row<T> &ab) {
+        if constexpr (WF) {
+            double ys, yn;
+            yline_weights(r.C0, r.W1, r.W0, r.S0, 0.0, 0.0, ab.S0, 0.0, 0.0, ys, yn);
+            const bool iny = inner_v(e, j);
+            ys = iny ? ys : 0.0;
+            yn = iny ? yn : 0.0;
+            // the y-line vertex east of the centre is the next lane's
+            const T eb = fromR(T(ys)), etp = fromR(T(yn));
+            const T ce = fromR(r.W0);
+            const T d = r.C1, cs = r.S1, cn = ab.S1, cw = r.W1;
+            const double wcsw = centre_weight(0.0, cs, bl.w2, cw, ys, d);
+            const double wcse = centre_weight(0.0, cs, bl.w3, ce, eb, d);
+            const double wcnw = centre_weight(0.0, cn, ab.w2, cw, yn, d);
+            const double wcne = centre_weight(0.0, cn, ab.w3, ce, etp, d);
+            const bool inc = inner_v(o, j);
+            const int J = j >> 1;
+            r.w0 = iny && cin(t, J) ? ys : 0.0;
+            r.w1 = iny && cin(t, J + 1) ? yn : 0.0;
+            r.w2 = inc && cin(t, J) ? wcsw : 0.0;
+            r.w3 = inc && cin(t + 1, J) ? wcse : 0.0;
+            r.w4 = inc && cin(t, J + 1) ? wcnw : 0.0;
+            r.w5 = inc && cin(t + 1, J + 1) ? wcne : 0.0;
         }
     };
     // x += P x_c (+ r/C at fine-only vertices) on a loaded row; coarse column t
@@ -612,6 +677,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     Stage<T> P{}, A{}, B{};
     Row<T> Rm1, Rn;                // raw rows jp-1 and jp
     Row<T> N1, N2;                 // raw rows jp+1 and jp+2, loaded one step ahead
+    T sa0 = T(0), sa1 = T(0);      // WF: S of row jp+3, loaded one step ahead of its row
     {
         Row<T> Ra;
         load_raw(Ra, jp0 - 2);
@@ -619,22 +685,45 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         load_raw(Rn, jp0);
         load_raw(N1, jp0 + 1);
         load_raw(N2, jp0 + 2);
+        if (WF) load_s(sa0, sa1, jp0 + 3);
         complete_C(Ra, Rm1);
         complete_C(Rm1, Rn);
+        if (WF) {
+            complete_C(Rn, N1);
+            xline_row(Ra, jp0 - 2, Rm1.S1);
+            xline_row(Rn, jp0, N1.S1);
+            odd_row_weights(Rm1, jp0 - 1, Ra, Rn);
+        }
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
     for (int jp = jp0; jp <= jpend; jp += 2) {
         Row<T> R1 = N1;
-        const Row<T> R2 = N2;
+        Row<T> R2 = N2;
+        const T s3a = sa0, s3b = sa1;  // WF: S of row jp+3
         if (jp + 2 <= jpend) {
             // the next step's rows: in flight while this step computes
-            load_raw(N1, jp + 3);
+            load_raw(N1, jp + 3, !WF);
             load_raw(N2, jp + 4);
+            if (WF) {
+                N1.S0 = s3a;
+                N1.S1 = s3b;
+                load_s(sa0, sa1, jp + 5);
+            }
         }
-        // diagonals of rows jp and jp+1, whose rows above are now loaded
-        complete_C(Rn, R1);
-        complete_C(R1, R2);
+        if (WF) {
+            // diagonals of rows jp+1 and jp+2 (row jp's is formed), then the
+            // weights of the x-line vertices of row jp+2 and of the y-line
+            // vertices and cell centres of row jp+1
+            complete_C(R1, R2);
+            complete_Cs(R2, s3a, s3b);
+            xline_row(R2, jp + 2, s3b);
+            odd_row_weights(R1, jp + 1, Rn, R2);
+        } else {
+            // diagonals of rows jp and jp+1, whose rows above are now loaded
+            complete_C(Rn, R1);
+            complete_C(R1, R2);
+        }
         const T q1_even_row = rc_odd(Rm1, Rn, R1);
         const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
         P.r0 = Rn;
@@ -680,13 +769,13 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     }
 }
 
-template <typename T, bool PONLY, bool PNORM = false, bool ZC = false>
+template <typename T, bool PONLY, bool PNORM = false, bool ZC = false, bool WF = false>
 __global__ __launch_bounds__(64) void k_stream3(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile_fn();
     if (tile >= a.ntiles) return;
-    stream3_tile<T, PONLY, PNORM, ZC>(a, tile);
+    stream3_tile<T, PONLY, PNORM, ZC, WF && !IsEdge<T>::value>(a, tile);
 }
 
 // Zero-excess check of a 5-point level (see launch_zero_excess_check): one
@@ -927,6 +1016,28 @@ void stream_geometry(int nx, int ny, int npt, int variant, int rb, int *nstrips,
     *grid = (*ntiles + 7) / 8 * 8;
 }
 
+// the pipelined finest kernel: variant x zero-excess x formed weights
+template <typename T, bool PONLY, bool PNORM>
+static void launch_f3(const StreamArgs<T> &a, dim3 g, dim3 b, hipStream_t s)
+{
+    const int k = (a.zexc ? 1 : 0) + (a.wform ? 2 : 0);
+    switch (k) {
+    case 0: hipLaunchKernelGGL((k_stream3<T, PONLY, PNORM, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_stream3<T, PONLY, PNORM, true, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_stream3<T, PONLY, PNORM, false, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_stream3<T, PONLY, PNORM, true, true>), g, b, 0, s, a); break;
+    }
+}
+
+template <typename T>
+static hipError_t launch_fused3(int variant, const StreamArgs<T> &a, dim3 g, dim3 b, hipStream_t s)
+{
+    if (variant == SV_FUSED3) launch_f3<T, false, false>(a, g, b, s);
+    else if (variant == SV_FUSED3_P) launch_f3<T, true, false>(a, g, b, s);
+    else launch_f3<T, true, true>(a, g, b, s);
+    return hipGetLastError();
+}
+
 template <typename T, int NPT>
 static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStream_t s)
 {
@@ -945,20 +1056,10 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_SWEEP2_R_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true, false>), g, b, 0, s, a); break;
     case SV_INTERP_RC: hipLaunchKernelGGL((k_interp_rc<T, NPT>), g, b, 0, s, a); break;
     case SV_FUSED3:
-        if (NPT != 5) return hipErrorInvalidValue;
-        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, false, false, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_stream3<T, false>), g, b, 0, s, a);
-        break;
     case SV_FUSED3_P:
-        if (NPT != 5) return hipErrorInvalidValue;
-        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, true, false, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_stream3<T, true>), g, b, 0, s, a);
-        break;
     case SV_FUSED3_PN:
         if (NPT != 5) return hipErrorInvalidValue;
-        if (a.zexc) hipLaunchKernelGGL((k_stream3<T, true, true, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_stream3<T, true, true>), g, b, 0, s, a);
-        break;
+        return launch_fused3<T>(variant, a, g, b, s);
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

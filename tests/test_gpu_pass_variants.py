@@ -74,7 +74,7 @@ def test_last_cycle_pass_is_bitwise_the_rebuild(n, monkeypatch):
 
 
 @pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED])
-@pytest.mark.parametrize("nx,ny,gpu_fv", [(257, 257, False), (225, 161, True), (129, 385, False)])
+@pytest.mark.parametrize("nx,ny,gpu_fv", [(257, 257, False), (225, 161, True), (129, 385, False), (65, 129, False)])
 def test_zero_excess_pass_is_bitwise_the_loading_pass(nx, ny, gpu_fv, precision, monkeypatch):
     # a finite-volume operator's diagonal is the sum of its connections: the
     # pipelined pass forms it instead of loading it, with the same bits
@@ -110,3 +110,29 @@ def test_operator_with_a_reaction_term_keeps_loading_the_diagonal(monkeypatch):
     A = H.matrix_from_planes(planes)
     bi = H.to_interior(c(b))
     assert np.linalg.norm(bi - A @ H.to_interior(c(u))) <= 1.2e-10 * np.linalg.norm(bi)
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(257, 257, 1), (225, 161, 2), (129, 385, 3), (65, 129, 4), (513, 97, 5)])
+def test_formed_weights_pass_is_bitwise_the_loading_pass(nx, ny, seed, monkeypatch):
+    # the FP64 pipelined pass forms the finest level's interpolation weights
+    # from the rows it loads with the setup's own expressions: the same bits
+    # as reading the stored weights, with and without the formed diagonal,
+    # through whole solves and through capped solves that end on the
+    # pipelined pass's last-cycle and rebuild variants
+    planes = g(O.fv5(inputs.cells_log10_blocks(nx, ny, 4, seed=seed)))
+    b = g(inputs.load_uniform(nx, ny, seed=seed + 10))
+    for noz in ("0", "1"):
+        monkeypatch.setenv("HIPBMG_NO_ZEXC", noz)
+        for cap in (None, 3):
+            res = {}
+            for nowf in ("1", "0"):
+                monkeypatch.setenv("HIPBMG_WFORM", "0" if nowf == "1" else "1")
+                prm = {} if cap is None else {"max_cycles": cap}
+                h = HB.Hierarchy(planes, **prm)
+                h.profile(True)
+                u, info = h.solve(b, tol=1e-10 if cap is None else 1e-30, check=cap is None)
+                per = h.profile_read(0)["fused3" if cap is None else "fused3_last"][2]
+                res[nowf] = (u, info.history(), info.cycles, per)
+            assert torch.equal(res["0"][0], res["1"][0]), (noz, cap)
+            assert res["0"][1:3] == res["1"][1:3], (noz, cap)
+            assert res["1"][3] - res["0"][3] == 16 * nx * ny     # the weight planes are not read
