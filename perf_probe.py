@@ -24,17 +24,19 @@ FINEST = {
     "relax_restrict": "void hbmg::k_stream<double, 5, 2>(hbmg::StreamArgs<double>)",
     "interp_relax_norm": "void hbmg::k_stream<double, 5, 5>(hbmg::StreamArgs<double>)",
     "relax2_restrict": "void hbmg::k_stream2<double, 5, false, true>(hbmg::StreamArgs<double>)",
-    "fused3": "void hbmg::k_stream3<double, false, false>(hbmg::StreamArgs<double>)",
-    "fused3_last": "void hbmg::k_stream3<double, true, true>(hbmg::StreamArgs<double>)",
+    # the pipelined pass over a zero-excess operator (diagonal formed, not loaded)
+    "fused3": "void hbmg::k_stream3<double, false, false, true, false>(hbmg::StreamArgs<double>)",
+    "fused3_last": "void hbmg::k_stream3<double, true, true, true, false>(hbmg::StreamArgs<double>)",
 }
 # algorithmic bytes per vertex (FP64, 5-point): relaxation reads x, b, C, W, S
 # and writes x; fused variants add q, the 8 weights at quarter resolution, and
 # the coarse right-hand side or coarse x; the pipelined finest pass reads what
 # the interpolating relaxation reads except r/C (formed from the loaded rows),
 # writes the next cycle's iterate and the coarse rhs; its first stage alone
-# (the last cycle of a capped run) writes the iterate instead
+# (the last cycle of a capped run) writes the iterate instead; both form the
+# diagonal of the finite-volume operator instead of reading the C plane
 ALGO_B_PER_VERTEX = {"relax": 48.0, "relax_restrict": 74.0, "interp_relax_norm": 74.0,
-                     "relax2_restrict": 74.0, "fused3": 68.0, "fused3_last": 66.0}
+                     "relax2_restrict": 74.0, "fused3": 60.0, "fused3_last": 58.0}
 
 
 def summarize(fetch_dir, write_dir, kernel, n=4097, copy_bytes=1 << 30):
