@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--n", type=int, default=4097)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles timed for the baseline")
+    ap.add_argument("--cpu-solve-max-s", type=float, default=40.0,
+                    help="time the oracle's whole solve when the timed cycles say it takes at most this long")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--collapse-level", type=int, default=-1)
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own workload")
@@ -359,6 +361,21 @@ def main():
                 log("bench: stage of %d workgroups on levels %d..%d above l*=%d: measured %.1f us/cycle, model %.1f"
                     % (wg, top, ls0 + 1, ls0, 1e6 * per, pus))
         extra["stage_sweep"] = ssweep
+        # coarsest grid size: coarsening stops at the first level with a side
+        # <= coarsest_n, solved with its dense Cholesky factor (section 3's
+        # coarse-solve term grows as the square of its unknowns); cycles to the
+        # tolerance and time per solve for each size
+        csweep = []
+        for cn in (3, 5, 9, 17, 33):
+            hc = HB.Hierarchy(coeffs, coarsest_n=cn)
+            el_c, _, info_c = time_solves(hc, b, 3, 1, torch)
+            csweep.append({"coarsest_n": cn, "levels": info_c.levels, "cycles": info_c.cycles,
+                           "ms_per_solve": 1e3 * el_c / 3, "us_per_cycle": 1e6 * el_c / 3 / info_c.cycles,
+                           "collapse_level": info_c.collapse_level, "relres": info_c.relres})
+            log("bench: coarsest_n %d: %d levels, %d cycles, %.2f ms/solve" % (cn, info_c.levels, info_c.cycles,
+                                                                             1e3 * el_c / 3))
+            hc.close()
+        extra["coarsest_sweep"] = csweep
         best = min(sweep, key=lambda r: r["measured_us_per_cycle"])
         chosen = [r for r in sweep if r["collapse_level"] == info.collapse_level]
         if chosen:
@@ -477,6 +494,21 @@ def main():
         torch.cuda.synchronize()
         el_b = time.perf_counter() - t0
         npts = sum(m * m for m in sizes)
+        # the tile shape the autotuner chose: strips per workgroup, the cap on
+        # row-pair steps per tile, and each size's row blocks, finest level first
+        shape = {}
+        for m in sorted(set(sizes)):
+            p = sizes.index(m)
+            rbs, lvl = [], 0
+            while True:
+                try:
+                    w, cap, rb = bh.tile_shape(p, lvl)
+                except HB.HipBMGError:
+                    break
+                rbs.append(rb)
+                lvl += 1
+            shape[str(m)] = rbs[::-1]
+        w, cap, _ = bh.tile_shape(0, 0)
         extra["batched"] = {
             "workload": "%d problems, n from {129,257,513,1025} (seed 5), lognormal D sigma=1, "
                         "FP32 V(2,1) inside FP64 refinement to rel. residual 1e-10" % args.batch,
@@ -487,6 +519,8 @@ def main():
             "max_relres": max(i.relres for i in infos_b),
             "fp32_cycles_max": max(i.cycles for i in infos_b),
             "refinement_steps_max": max(i.outer_steps for i in infos_b),
+            "tile_shape": {"strips_per_workgroup": w, "row_block_cap": cap,
+                           "row_blocks_by_size_finest_first": shape},
         }
         log("bench: batched %.1f problems/s (%.2f ms per batch)" % (args.steps * args.batch / el_b,
                                                                    1e3 * el_b / args.steps))
@@ -623,6 +657,27 @@ def main():
                          "thread: 2 cycles, %.3f s/cycle" % (args.cpu_cycles, nth, n, n, t_cycle, cycles, t_cycle1),
                "single_thread_value": 1.0 / (t_cycle1 * cycles),
                "host": host_info()}
+        if t_cycle * cycles <= args.cpu_solve_max_s:
+            # the whole oracle solve fits the time bound: time it instead of
+            # scaling a few cycles, and state the GPU solutions' error against it
+            log("bench: CPU oracle, whole FP64 solve on %d threads (~%.0f s)" % (nth, t_cycle * cycles))
+            t0 = time.perf_counter()
+            u_or, h_or = oh.solve(bh, tol=TOL)
+            t_solve = time.perf_counter() - t0
+            cpu["value"] = 1.0 / t_solve
+            cpu["sample"] = ("the whole FP64 solve of the oracle on %d threads on the same %dx%d problem (%d cycles, "
+                             "%.1f s, relres %.2e); the same oracle on one thread: 2 cycles, %.3f s/cycle, scaled "
+                             "by the cycle count" % (nth, n, n, len(h_or), t_solve, h_or[-1], t_cycle1))
+
+            def err_vs_oracle(u):
+                uh = u.cpu().numpy()
+                return {"max_abs_rel": float(np.abs(uh - u_or).max() / np.abs(u_or).max()),
+                        "l2_rel": float(np.linalg.norm(uh - u_or) / np.linalg.norm(u_or))}
+            cpu["error_vs_oracle_solution"] = {"fp64": err_vs_oracle(u64)}
+            if not args.no_mixed:
+                cpu["error_vs_oracle_solution"]["mixed"] = err_vs_oracle(um)
+            log("bench: error against the oracle's solution %s" % json.dumps(cpu["error_vs_oracle_solution"]))
+            del u_or
 
     if not args.no_cpu:
         extra["cpu_oracle_workloads"] = oracle_workloads(args, n, extra, O, np, inputs)
@@ -641,8 +696,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded random-block diffusivity, uniform random load)",
         "config": {"workload": "%dx%d vertex 2D diffusion, D on 16x16-cell blocks log10 D~U[-2,2], "
-                               "V(2,1) to rel. residual 1e-10, FP64" % (n, n),
-                   "n": n, "cycles": cycles, "levels": info.levels,
+                               "V(2,1) to rel. residual 1e-10, Galerkin coarsening to a %dx%d direct solve, FP64"
+                               % (n, n, hier.params.coarsest_n, hier.params.coarsest_n),
+                   "n": n, "cycles": cycles, "levels": info.levels, "coarsest_n": hier.params.coarsest_n,
                    "collapse_level": info.collapse_level, "setup_ms": info0.setup_ms,
                    "relres": info.relres,
                    "row_blocks": {"down": list(info.rb_down)[: info.levels],

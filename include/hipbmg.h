@@ -286,6 +286,15 @@ hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle h, const double *const *b
                                    double *const *u_host, double tol, void *stream,
                                    hipbmg_info *infos_host);
 hipbmg_status hipbmg_destroy_batched(hipbmg_batch_handle h);
+/* The tile shape the batch's autotuner chose at setup (row-block length of a
+ * tile, as for a single problem, and the number of neighbouring strips, one
+ * wave each, that share a workgroup): strips_per_group (1, 2 or 4), rb_cap
+ * (the cap on row-pair steps per tile, 0 for the single-problem rule) and rb,
+ * the row-pair steps per tile that level `level` (0 = coarsest) of problem
+ * `problem` uses (0 for a level inside the collapse).  Any output may be
+ * NULL.  EINVAL for a NULL handle or an index out of range. */
+hipbmg_status hipbmg_batch_tile_shape(hipbmg_batch_handle h, int problem, int level, int *strips_per_group,
+                                      int *rb_cap, int *rb);
 
 /* Vertex-centred 5-point finite-volume stencil of -div(D grad u) (section 5):
  * the face between vertices p and q takes the mean of the two cells it cuts,

@@ -492,6 +492,7 @@ static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
         ml[l].pipelined = fine && h->fused3 ? 1 : 0;
         if (ml[l].pipelined) describe(SV_FUSED3, h->rb3, ml[l].pipe);
         else ml[l].pipe = ModelKernel{0, 0, 1.0};
+        ml[l].zexc = ml[l].pipelined && h->zexc[fp32 ? 1 : 0] ? 1 : 0;
         const int cnx = l ? h->lv[l - 1].nx : 0, cny = l ? h->lv[l - 1].ny : 0;
         const size_t bytes = fp32 ? collapse_lds_bytes<float>(A.nx, A.ny, cnx, cny)
                                   : collapse_lds_bytes<double>(A.nx, A.ny, cnx, cny);
@@ -2140,6 +2141,7 @@ hipbmg_status hbmg::calibrate_on_kernels(void *stream, ModelParams &p)
 struct BLaunch {
     int kind;            // 0 streaming stage, 1 collapse
     int npt, variant;
+    int wpg;             // streaming stage: strips (waves) per workgroup
     void *d_args;        // StreamArgs<T>[nprob] or CollapseArgs<T>[nprob]
     int2 *d_map;
     int nmap;
@@ -2186,6 +2188,7 @@ struct hipbmg_batch {
     int max_nx = 0, max_ny = 0, fine_npt = 5;
     BPlan plan64[2], plan32[2][2];
     int rb_cap = 0;                           // row blocks of the batched launches (0: per-level rule)
+    int wpg = 1;                              // strips (one wave each) per workgroup of the batched launches
     std::vector<void *> seg_allocs;           // norm segment tables (rebuilt with the plans)
     hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -2387,6 +2390,7 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
         bl.kind = 0;
         bl.npt = recs[0].npt;
         bl.variant = recs[0].variant;
+        bl.wpg = B->wpg;
         StreamArgs<T> *da = nullptr;
         int2 *dm = nullptr;
         STCHK(balloc_to(plan.allocs, &da, n, s));
@@ -2426,7 +2430,7 @@ static hipError_t run_plan_launches(hipbmg_batch *B, BPlan &plan, const int *act
     for (BLaunch &bl : plan.launches) {
         if (bl.kind == 0)
             e = launch_stream_batched<T>(bl.npt, bl.variant, static_cast<const StreamArgs<T> *>(bl.d_args),
-                                         bl.d_map, bl.nmap, active, s);
+                                         bl.d_map, bl.nmap, active, bl.wpg, s);
         else
             e = launch_collapse_batched<T>(static_cast<const CollapseArgs<T> *>(bl.d_args), B->n,
                                            bl.lds_bytes, active, s);
@@ -2526,21 +2530,23 @@ static double time_plan_us(hipbmg_batch *B, BPlan &plan, hipStream_t s, hipEvent
     return best;
 }
 
-// Autotuner of the batched tile shape.  A tile is one wave's strip of column
-// pairs times a block of rb row-pair steps; in a batched launch the tiles of
-// every problem share the device, so the best rb is not the single-problem
-// one.  Each candidate cap on rb (and the single-problem rule) is built into
-// plans and one steady-state V-cycle of the batch is timed (every problem
-// active, on the zero data of a fresh hierarchy); the fastest is kept.  The
-// choice is remembered per batch signature (sizes, stencil, precision,
-// cycle) for the life of the process.  HIPBMG_BATCH_TUNE=0 keeps the
-// single-problem rule.
+// Autotuner of the batched tile shape.  A workgroup's tile is W neighbouring
+// strips of column pairs (one wave each, 54-62 owned pairs per strip by the
+// kernel's halo) times a block of rb row-pair steps; in a batched launch the
+// tiles of every problem share the device, so the best shape is not the
+// single-problem one.  Each candidate (W in {1, 2, 4}) x (cap on rb in
+// {1, ..., 64}, or the single-problem rule) is built into plans and one
+// steady-state V-cycle of the batch is timed (every problem active, on the
+// zero data of a fresh hierarchy); the fastest is kept.  The choice is
+// remembered per batch signature (sizes, stencil, precision, cycle) for the
+// life of the process.  HIPBMG_BATCH_TUNE=0 keeps one strip per workgroup
+// and the single-problem rule; HIPBMG_BATCH_WPG=1, 2 or 4 fixes W.
 static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
 {
     // shared by every thread that sets up batches: guarded; the key holds
     // every parameter that shapes the plans
     static std::mutex cache_mu;
-    static std::map<std::string, int> cache;
+    static std::map<std::string, std::pair<int, int>> cache;
     std::vector<std::pair<int, int>> sz;
     for (hipbmg_hier *h : B->hs) sz.push_back({h->nx, h->ny});
     std::sort(sz.begin(), sz.end());
@@ -2551,15 +2557,26 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
     for (auto &q : sz) key += std::to_string(q.first) + "x" + std::to_string(q.second) + ";";
     bool tune = true;
     if (const char *e = std::getenv("HIPBMG_BATCH_TUNE")) tune = std::atoi(e) != 0;
+    int wfix = 0;
+    if (const char *e = std::getenv("HIPBMG_BATCH_WPG")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) wfix = v;
+    }
+    key += "w" + std::to_string(wfix);
     if (!tune) {
         B->rb_cap = 0;
+        B->wpg = wfix ? wfix : 1;
         return build_plans(B, s);
     }
     {
         std::lock_guard<std::mutex> lk(cache_mu);
         auto it = cache.find(key);
-        if (it != cache.end()) B->rb_cap = it->second;
-        else B->rb_cap = -1;
+        if (it != cache.end()) {
+            B->rb_cap = it->second.first;
+            B->wpg = it->second.second;
+        } else {
+            B->rb_cap = -1;
+        }
     }
     if (B->rb_cap >= 0) return build_plans(B, s);
     std::vector<int> ones(B->n, 1);
@@ -2571,25 +2588,32 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
         return fail(HIPBMG_EHIP, "event creation failed");
     }
     const bool mixed = B->prm.precision == HIPBMG_MIXED;
-    int best = 0;
+    int best = 0, best_w = 1;
     double tbest = 1e30;
     hipbmg_status st = HIPBMG_OK;
-    for (int cap : {0, 1, 2, 4, 8, 16, 32, 64}) {
-        B->rb_cap = cap;
-        if ((st = build_plans(B, s)) != HIPBMG_OK) break;
-        double us;
-        if (mixed) {
-            const int c1 = B->plan32[1][0].end_cur;
-            us = time_plan_us<float>(B, B->plan32[0][c1], s, e0, e1);
-        } else {
-            us = time_plan_us<double>(B, B->plan64[0], s, e0, e1);
+    for (int w : {1, 2, 4}) {
+        if (wfix && w != wfix) continue;
+        B->wpg = w;
+        for (int cap : {0, 1, 2, 4, 8, 16, 32, 64}) {
+            B->rb_cap = cap;
+            if ((st = build_plans(B, s)) != HIPBMG_OK) break;
+            double us;
+            if (mixed) {
+                const int c1 = B->plan32[1][0].end_cur;
+                us = time_plan_us<float>(B, B->plan32[0][c1], s, e0, e1);
+            } else {
+                us = time_plan_us<double>(B, B->plan64[0], s, e0, e1);
+            }
+            if (std::getenv("HIPBMG_VERBOSE"))
+                std::fprintf(stderr, "hipbmg: batch of %d, %d strips per workgroup, row-block cap %d: %.1f us per cycle\n",
+                             B->n, w, cap, us);
+            if (us < tbest) {
+                tbest = us;
+                best = cap;
+                best_w = w;
+            }
         }
-        if (std::getenv("HIPBMG_VERBOSE"))
-            std::fprintf(stderr, "hipbmg: batch of %d, row-block cap %d: %.1f us per cycle\n", B->n, cap, us);
-        if (us < tbest) {
-            tbest = us;
-            best = cap;
-        }
+        if (st != HIPBMG_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2597,9 +2621,10 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
     HIPCHK(hipMemsetAsync(B->d_active, 0, B->n * sizeof(int), s));
     {
         std::lock_guard<std::mutex> lk(cache_mu);
-        cache[key] = best;
+        cache[key] = {best, best_w};
     }
     B->rb_cap = best;
+    B->wpg = best_w;
     return build_plans(B, s);
 }
 
@@ -2706,6 +2731,19 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess)
         return bail(fail(HIPBMG_EHIP, "stream creation failed"));
     *out = B;
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_batch_tile_shape(hipbmg_batch_handle B, int problem, int level,
+                                                 int *strips_per_group, int *rb_cap, int *rb)
+{
+    if (!B) return fail(HIPBMG_EINVAL, "handle is NULL");
+    if (problem < 0 || problem >= B->n) return fail(HIPBMG_EINVAL, "problem %d out of range [0, %d)", problem, B->n);
+    const hipbmg_hier *h = B->hs[problem];
+    if (level < 0 || level >= h->L) return fail(HIPBMG_EINVAL, "level %d out of range [0, %d)", level, h->L);
+    if (strips_per_group) *strips_per_group = B->wpg;
+    if (rb_cap) *rb_cap = B->rb_cap;
+    if (rb) *rb = level > h->lstar ? batch_rb<double>(B, h->lv[level]) : 0;
     return HIPBMG_OK;
 }
 

@@ -108,10 +108,11 @@ int stream_resident(int npt, int variant, int fp32);
 int stream_steps_per_tile(int variant, int rb);
 template <typename T>
 hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid, hipStream_t s);
-// one launch over many problems: map[w] = (problem, tile), args[problem]
+// one launch over many problems: map[w] = (problem, tile) of wave w,
+// args[problem]; wpg waves (strips) per workgroup, 1, 2 or 4
 template <typename T>
 hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
-                                 int nmap, const int *active, hipStream_t s);
+                                 int nmap, const int *active, int wpg, hipStream_t s);
 
 // 1 if every interior vertex of a 5-point level has C exactly equal to
 // ((W_p + W_e) + S_p) + S_n (FP64), or an FP32 edge-form excess of exactly 0;

@@ -78,8 +78,9 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
     if (finest && lv.pipelined) {
         // one pass per cycle: interpolate + relax + norm of this cycle, two
         // relaxations + residual + restriction of the next (68 B per vertex in
-        // FP64); its waves do the work of a down and an up step per row pair
-        const double bytes = n * w * (s + 3.0 + 0.25 + 2.0 + 0.25);
+        // FP64, 60 B when the diagonal is formed instead of loaded); its waves
+        // do the work of a down and an up step per row pair
+        const double bytes = n * w * (s + 3.0 + 0.25 + 2.0 + 0.25 - (lv.zexc ? 1.0 : 0.0));
         return kernel_us(lv.pipe, p.step_dn_us[q] + p.step_up_us[q], p.t0_dn_us[q], bytes, bdn, p);
     }
     double t = 0.0;

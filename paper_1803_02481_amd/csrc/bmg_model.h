@@ -33,6 +33,9 @@ struct ModelLevel {
     int dn_cold, up_cold;
     // the up leg forms r/C from the rows it loads (no q plane written or read)
     int rc;
+    // the pipelined pass forms the diagonal from the connections (zero-excess
+    // operator) instead of loading it
+    int zexc;
 };
 
 // Machine parameters.  Paper -> GPU correspondence:

@@ -300,7 +300,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<T> &a, const int ti
 
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;   // lane in the wave; a workgroup may hold several strips
     const int t = strip * OWN + lane - HL;   // column pair index
     const int e = 2 * t, o = 2 * t + 1;
     const int nx = a.nx, ny = a.ny, pitch = a.pitch;
@@ -433,7 +433,7 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
 
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;   // lane in the wave; a workgroup may hold several strips
     const int t = strip * OWN + lane - HL;
     const int e = 2 * t, o = 2 * t + 1;
     const int nx = a.nx, ny = a.ny, pitch = a.pitch;
@@ -527,7 +527,7 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
     constexpr int HL = 5, HR = 5, OWN = 64 - HL - HR;
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;   // lane in the wave; a workgroup may hold several strips
     const int t = strip * OWN + lane - HL;
     const int e = 2 * t, o = 2 * t + 1;
     const int nx = a.nx, ny = a.ny, pitch = a.pitch;
@@ -856,7 +856,7 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
     constexpr int HL = 1 + halo_left(NPT, 0), HR = 1 + halo_right(NPT, 0), OWN = 64 - HL - HR;
     const int strip = tile % a.nstrips;
     const int blk = tile / a.nstrips;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;   // lane in the wave; a workgroup may hold several strips
     const int t = strip * OWN + lane - HL;
     const int e = 2 * t, o = 2 * t + 1;
     const int nx = a.nx, ny = a.ny, pitch = a.pitch;
@@ -973,15 +973,17 @@ __global__ __launch_bounds__(64) void k_interp_rc(StreamArgs<T> a)
 }
 
 // Batched form: one launch covers the same stage of many problems.  map[w] =
-// (problem, tile) of workgroup w; problems whose flag in `active` is 0 are
-// skipped (converged).
-template <typename T, int NPT, int V>
-__global__ __launch_bounds__(64) void k_stream_batched(const StreamArgs<T> *__restrict__ args,
-                                                       const int2 *__restrict__ map, int nmap,
-                                                       const int *__restrict__ active)
+// (problem, tile) of wave w; a workgroup holds W waves, so W consecutive
+// entries (neighbouring strips of one row block) share a CU.  Problems whose
+// flag in `active` is 0 are skipped (converged).
+template <typename T, int NPT, int V, int W>
+__global__ __launch_bounds__(64 * W) void k_stream_batched(const StreamArgs<T> *__restrict__ args,
+                                                           const int2 *__restrict__ map, int nmap,
+                                                           const int *__restrict__ active)
 {
-    if ((int)blockIdx.x >= nmap) return;
-    const int2 m = map[blockIdx.x];
+    const int w = (int)blockIdx.x * W + (int)(threadIdx.x >> 6);
+    if (w >= nmap) return;
+    const int2 m = map[w];
     if (!active[m.x]) return;
     const StreamArgs<T> a = args[m.x];
     if (V == SV_SWEEP2_RQ)
@@ -1132,14 +1134,14 @@ hipError_t launch_stream(int npt, int variant, const StreamArgs<T> &a, int grid,
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NPT>
+template <typename T, int NPT, int W>
 static hipError_t launch_vb(int variant, const StreamArgs<T> *args, const int2 *map, int nmap,
                             const int *active, hipStream_t s)
 {
-    dim3 g(nmap), b(64);
+    dim3 g((nmap + W - 1) / W), b(64 * W);
     switch (variant) {
-#define HB_CASE(V)                                                                                 \
-    case V: hipLaunchKernelGGL((k_stream_batched<T, NPT, V>), g, b, 0, s, args, map, nmap, active); break;
+#define HB_CASE(V)                                                                                    \
+    case V: hipLaunchKernelGGL((k_stream_batched<T, NPT, V, W>), g, b, 0, s, args, map, nmap, active); break;
     HB_CASE(SV_SWEEP)
     HB_CASE(SV_SWEEP_ZX)
     HB_CASE(SV_SWEEP_RQ)
@@ -1157,17 +1159,25 @@ static hipError_t launch_vb(int variant, const StreamArgs<T> *args, const int2 *
 
 template <typename T>
 hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
-                                 int nmap, const int *active, hipStream_t s)
+                                 int nmap, const int *active, int wpg, hipStream_t s)
 {
     if (nmap <= 0) return hipSuccess;
-    if (npt == 5) return launch_vb<T, 5>(variant, args, map, nmap, active, s);
-    if (npt == 9) return launch_vb<T, 9>(variant, args, map, nmap, active, s);
+#define HB_W(W)                                                                          \
+    if (wpg == W) {                                                                      \
+        if (npt == 5) return launch_vb<T, 5, W>(variant, args, map, nmap, active, s);    \
+        if (npt == 9) return launch_vb<T, 9, W>(variant, args, map, nmap, active, s);    \
+        return hipErrorInvalidValue;                                                     \
+    }
+    HB_W(1)
+    HB_W(2)
+    HB_W(4)
+#undef HB_W
     return hipErrorInvalidValue;
 }
 template hipError_t launch_stream_batched<double>(int, int, const StreamArgs<double> *, const int2 *,
-                                                  int, const int *, hipStream_t);
+                                                  int, const int *, int, hipStream_t);
 template hipError_t launch_stream_batched<float>(int, int, const StreamArgs<float> *, const int2 *, int,
-                                                 const int *, hipStream_t);
+                                                 const int *, int, hipStream_t);
 
 template hipError_t launch_stream<double>(int, int, const StreamArgs<double> &, int, hipStream_t);
 template hipError_t launch_stream<float>(int, int, const StreamArgs<float> &, int, hipStream_t);

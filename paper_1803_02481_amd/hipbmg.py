@@ -90,6 +90,7 @@ _SIGS = {
     "hipbmg_solve_batched": (_I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_double, _VP,
                                   ctypes.POINTER(Info)]),
     "hipbmg_destroy_batched": (_I, [_VP]),
+    "hipbmg_batch_tile_shape": (_I, [_VP, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "hipbmg_set_allocator": (_I, [_VP, _VP, _VP]),
     "hipbmg_last_error": (ctypes.c_char_p, []),
     "hipbmg_paper_model": (_I, [_I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I, _I, _I, _I, _I,
@@ -451,6 +452,14 @@ class BatchHierarchy:
         self._h = h
         _open_handles.add(self)
         self.n = n
+
+    def tile_shape(self, problem, level):
+        """(strips per workgroup, row-block cap, row-pair steps per tile of
+        this level) chosen by the autotuner (hipbmg_batch_tile_shape)."""
+        w, cap, rb = _I(), _I(), _I()
+        _check(lib().hipbmg_batch_tile_shape(self._h, int(problem), int(level), ctypes.byref(w), ctypes.byref(cap),
+                                             ctypes.byref(rb)))
+        return w.value, cap.value, rb.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -299,6 +299,31 @@ def test_solve_matches_oracle(name, nx, ny, cells, seed):
     assert np.linalg.norm(A @ du) <= 2.5e-10 * np.linalg.norm(H.to_interior(b))
 
 
+@pytest.mark.parametrize("nx,ny,coarsest", [(257, 257, 5), (257, 257, 17), (257, 257, 33), (193, 97, 9)])
+def test_larger_coarsest_grid_matches_oracle(nx, ny, coarsest):
+    # coarsening stops at the first level with a side <= coarsest_n; that level
+    # is solved with the dense Cholesky factor (section 3, coarse-grid solve)
+    planes = O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=21))
+    b = inputs.load_uniform(nx, ny, seed=22)
+    ora = O.Hierarchy(planes, coarsest_n=coarsest)
+    u_ref, h_ref = ora.solve(b, tol=1e-10)
+    hier = HB.Hierarchy(g(planes), coarsest_n=coarsest)
+    assert hier.L == ora.L, (hier.L, ora.L)
+    cny, cnx = hier.size(0)
+    assert (cny, cnx) == ora.size(0)
+    assert min(cnx, cny) <= coarsest or cnx % 2 == 0 or cny % 2 == 0
+    u, info = hier.solve(g(b), tol=1e-10)
+    hist = np.array(info.history())
+    assert info.cycles == len(h_ref), (info.cycles, len(h_ref))
+    early = h_ref > 1e-6
+    d = np.abs(hist[early] - h_ref[early]) / h_ref[early]
+    print("coarsest %d (%dx%d): %d cycles, history max rel difference %.3e" % (coarsest, cnx, cny, info.cycles,
+                                                                              float(d.max())))
+    assert np.all(d <= 5e-9), float(d.max())
+    rr = oracle_relres(planes, b, c(u))
+    assert rr <= 1.2e-10, rr
+
+
 @pytest.mark.parametrize("n", [65, 257])
 def test_collapse_level_does_not_change_the_iteration(n):
     planes = O.fv5(inputs.cells_log10_blocks(n, n, 16, seed=11))
@@ -501,6 +526,65 @@ def test_batched_fp64_equals_single_problem_solves(use_graph, monkeypatch):
         assert torch.equal(us[k], u1), k
         rr = oracle_relres(planes[k], bs[k], c(us[k]))
         assert rr <= 1.2e-10, (k, rr)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_tile_shape_does_not_change_the_iterate(precision, monkeypatch):
+    # strips per workgroup and row-block length change only which wave
+    # computes which vertices: every shape gives the same bits.  The collapse
+    # level is fixed: the model's choice of it depends on the row blocks
+    monkeypatch.setenv("HIPBMG_NO_FUSE3", "1")
+    sizes = [(129, 129), (65, 65), (257, 129), (97, 97), (33, 65)]
+    planes, bs = batch_case(sizes, seed0=70)
+    prec = HB.FP64 if precision == "fp64" else HB.MIXED
+    ref = None
+    for wpg in ("1", "2", "4"):
+        for rb in ("1", "3", "64"):
+            monkeypatch.setenv("HIPBMG_BATCH_WPG", wpg)
+            monkeypatch.setenv("HIPBMG_RB", rb)
+            bh = HB.BatchHierarchy([g(p) for p in planes], precision=prec, use_graph=1, collapse_level=1)
+            w, _, _ = bh.tile_shape(0, bh_levels_top(bh, 0))
+            assert w == int(wpg)
+            us, infos = bh.solve([g(b) for b in bs], tol=1e-10)
+            cyc = [i.cycles for i in infos]
+            if ref is None:
+                ref = (us, cyc)
+                for k in range(len(sizes)):
+                    assert oracle_relres(planes[k], bs[k], c(us[k])) <= 1.2e-10, k
+            else:
+                assert cyc == ref[1], (wpg, rb, cyc, ref[1])
+                for k in range(len(sizes)):
+                    assert torch.equal(us[k], ref[0][k]), (wpg, rb, k)
+            bh.close()
+
+
+def bh_levels_top(bh, problem):
+    # the finest level of a problem: the highest level index tile_shape accepts
+    l = 0
+    while True:
+        try:
+            bh.tile_shape(problem, l + 1)
+        except HB.HipBMGError:
+            return l
+        l += 1
+
+
+def test_batched_autotuner_reports_its_shape(monkeypatch):
+    monkeypatch.delenv("HIPBMG_BATCH_WPG", raising=False)
+    monkeypatch.delenv("HIPBMG_RB", raising=False)
+    sizes = [(129, 129), (257, 257), (65, 65)]
+    planes, _ = batch_case(sizes, seed0=90)
+    bh = HB.BatchHierarchy([g(p) for p in planes], precision=HB.MIXED)
+    for k, (nx, ny) in enumerate(sizes):
+        top = bh_levels_top(bh, k)
+        w, cap, rb = bh.tile_shape(k, top)
+        print("problem %d (%dx%d): %d strips per workgroup, cap %d, finest rb %d" % (k, nx, ny, w, cap, rb))
+        assert w in (1, 2, 4) and cap in (0, 1, 2, 4, 8, 16, 32, 64)
+        assert 1 <= rb <= (ny - 1) // 2
+        if cap > 0:
+            assert rb == min(cap, (ny - 1) // 2)
+    with pytest.raises(HB.HipBMGError):
+        bh.tile_shape(len(sizes), 0)
 
 
 def test_batched_mixed_precision_reaches_fp64_residual(monkeypatch):

@@ -6,6 +6,9 @@ at their full sizes, in the launch configuration the benchmark times.
   mixed precision with the V-cycle replayed from a captured graph.  Every
   problem's relative residual is recomputed on the host from the oracle's
   finite-volume operator.
+- Checkerboard: the 4097^2 two-phase checkerboard (64-cell blocks, D in
+  {1, 1e-3}, seed 3; load seed 4) solved to 1e-10 in FP64 and in mixed
+  precision, each solution compared with the oracle's FP64 solution.
 - Adjoint: the 64-problem batch of 1025^2 grids (theta = box5(N(0,1)),
   seeds 3000+k; loads seeds 5000+k).  Problem 0's observation u_obs comes from
   an oracle solve with theta from seed 4000; its gradient from the batched
@@ -84,3 +87,32 @@ def test_benchmarked_adjoint_batch_gradient_matches_oracle():
     # gradient carries about that relative error (the single-problem check at
     # this size measures 1.1e-9)
     assert e <= 1e-8, e
+
+
+def test_checkerboard_solutions_against_the_oracle_fp64_solution():
+    # the mixed-precision workload's operator at full size: both GPU solutions
+    # meet the tolerance by the oracle's residual, and their error against the
+    # oracle's own FP64 solution is stated
+    n = 4097
+    planes = O.fv5(inputs.cells_two_phase_blocks(n, n, 64, (1.0, 1e-3), seed=3))
+    b = inputs.load_uniform(n, n, seed=4)
+    ora = O.Hierarchy(planes)
+    u_ref, h_ref = ora.solve(b, tol=1e-10)
+    print("oracle: %d cycles, relres %.3e" % (len(h_ref), h_ref[-1]), flush=True)
+    scale = np.abs(u_ref).max()
+    for prec in (HB.FP64, HB.MIXED):
+        hier = HB.Hierarchy(g(planes), precision=prec)
+        u, info = hier.solve(g(b), tol=1e-10)
+        u = c(u)
+        r = ora.residual(ora.L - 1, b, u)
+        rr = float(np.linalg.norm(r[1:-1, 1:-1]) / np.linalg.norm(b[1:-1, 1:-1]))
+        err = float(np.abs(u - u_ref).max() / scale)
+        print("%s: %d cycles, oracle relres %.3e, max |u - u_oracle| / max |u_oracle| = %.3e"
+              % ("fp64" if prec == HB.FP64 else "mixed", info.cycles, rr, err), flush=True)
+        assert rr <= 1.2e-10, rr
+        # two iterates whose residuals are both below 1e-10 differ by at most
+        # the operator's inverse applied to 2e-10 ||b||: on this operator the
+        # slow modes amplify that to ~1e-8 of the solution (measured FP64
+        # 8.4e-12, mixed 2.0e-8); the bound leaves a factor of 50
+        assert err <= 1e-6, err
+        hier.close()
