@@ -190,6 +190,9 @@ struct hipbmg_hier {
     std::vector<int> rb;        // row-block steps per level, pre-relaxation (down) kernels
     std::vector<int> rb_up;     // row-block steps per level, interpolation (up) kernels
     std::vector<char> rc_level; // level forms r/C in its up leg (no q plane)
+    // waves per tile of the level's tile kernels, 0 for the streaming kernels:
+    // the down leg, and the up leg of the FP64 [0] and FP32 [1] levels
+    std::vector<char> tile_dn, tile_up[2];
     int no_lds = 0;             // HIPBMG_NO_LDS=1: keep collapsed levels in global memory
     int no_fuse2 = 0;           // HIPBMG_NO_FUSE2=1: run the two pre-relaxations as two passes
     int fused3 = 0;             // finest post-relaxation fused with the next cycle's pre-relaxations
@@ -433,6 +436,32 @@ static int variant_down(const hipbmg_params &prm, bool fine, bool rc = false)
 }
 static int variant_up(bool fine, bool rc = false) { return fine ? SV_INTERP_NORM : (rc ? SV_INTERP_RC : SV_INTERP); }
 
+// Small coarse levels run the tile kernels instead of the streaming ones:
+// 9-point levels of a V(2,1) cycle with the two pre-relaxations fused, up to
+// a vertex count per leg and precision where they measured faster on gfx950
+// (4097^2 blocks): every down leg up to 513^2 (HIPBMG_TILE_MAX), the up legs
+// of FP32 levels up to 257^2 (HIPBMG_TILE_UP_MAX); FP64 up legs stay
+// streaming (HIPBMG_TILE_UP_MAX64, default 0).  8-wave tiles where a level
+// still gets 64 of them, 4-wave tiles otherwise (HIPBMG_TILE_NW forces one).
+static long long tile_limit(const char *env, long long dflt)
+{
+    if (const char *e = std::getenv(env)) return std::atoll(e);
+    return dflt;
+}
+
+static int tile_waves(const hipbmg_hier *h, int nx, int ny, int npt, bool fine, bool rc, long long lim)
+{
+    if (fine || rc || npt != 9 || h->prm.nu1 != 2 || h->prm.nu2 != 1 || h->no_fuse2 || (long long)nx * ny > lim)
+        return 0;
+    if (const char *e = std::getenv("HIPBMG_TILE_NW")) {
+        const int v = std::atoi(e);
+        if (v == 4 || v == 8) return v;
+    }
+    int nst, nbl, nt;
+    tile_geometry(nx, ny, npt, 8, 1, &nst, &nbl, &nt);
+    return nt >= 64 ? 8 : 4;
+}
+
 // Levels whose up leg forms r/C from the rows it loads instead of reading the
 // q plane the down leg would store (16 bytes per vertex less): coarse levels
 // of at least HIPBMG_RC_MIN vertices (default 2^20, where the two legs are
@@ -647,6 +676,9 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     h->rb.resize(L);
     h->rb_up.resize(L);
     h->rc_level.assign(L, 0);
+    h->tile_dn.assign(L, 0);
+    h->tile_up[0].assign(L, 0);
+    h->tile_up[1].assign(L, 0);
     size_t np = 4096;
     {
         bool fixed = false;
@@ -656,6 +688,10 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             const int lnpt = h->lv[l].npt;
             const bool fine = l == L - 1;
             h->rc_level[l] = rc_on_the_fly(h, sx[l], sy[l], fine) ? 1 : 0;
+            const bool rcl = h->rc_level[l] != 0;
+            h->tile_dn[l] = (char)tile_waves(h, sx[l], sy[l], lnpt, fine, rcl, tile_limit("HIPBMG_TILE_MAX", 513LL * 513));
+            h->tile_up[0][l] = (char)tile_waves(h, sx[l], sy[l], lnpt, fine, rcl, tile_limit("HIPBMG_TILE_UP_MAX64", 0));
+            h->tile_up[1][l] = (char)tile_waves(h, sx[l], sy[l], lnpt, fine, rcl, tile_limit("HIPBMG_TILE_UP_MAX", 257LL * 257));
             const int vdn = variant_down(prm, fine, h->rc_level[l]), vup = variant_up(fine, h->rc_level[l]);
             const int rdn = fixed ? 0 : stream_resident(lnpt, vdn, fp32);
             const int rup = fixed ? 0 : stream_resident(lnpt, vup, fp32);
@@ -1011,7 +1047,16 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             }
             const int pk = prof_begin(h, v, PrecIdx<T>::v, l, 0, fine, s);
             a.active = active;
-            if ((e = run_stream(A, v, a, s)) != hipSuccess) return e;
+            if (v == SV_SWEEP2_RQ_ZX && h->tile_dn[l]) {
+                const int nw = h->tile_dn[l];
+                int nbl;
+                a.rb = tile_steps(nw, 1);
+                tile_geometry(A.nx, A.ny, A.npt, nw, 1, &a.nstrips, &nbl, &a.ntiles);
+                a.nblocks = nbl;
+                if ((e = launch_tile<T>(1, nw, a, s)) != hipSuccess) return e;
+            } else if ((e = run_stream(A, v, a, s)) != hipSuccess) {
+                return e;
+            }
             prof_end(h, pk, s);
             xb = 1 - xb;
         }
@@ -1066,7 +1111,16 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             int nt = 0;
             const int pk = prof_begin(h, v, PrecIdx<T>::v, l, 1, fine, s);
             a.active = active;
-            if ((e = run_stream(A, v, a, s, &nt)) != hipSuccess) return e;
+            if (v == SV_INTERP && h->tile_up[PrecIdx<T>::v][l]) {
+                const int nw = h->tile_up[PrecIdx<T>::v][l];
+                int nbl;
+                a.rb = tile_steps(nw, 0);
+                tile_geometry(A.nx, A.ny, A.npt, nw, 0, &a.nstrips, &nbl, &a.ntiles);
+                a.nblocks = nbl;
+                if ((e = launch_tile<T>(0, nw, a, s)) != hipSuccess) return e;
+            } else if ((e = run_stream(A, v, a, s, &nt)) != hipSuccess) {
+                return e;
+            }
             prof_end(h, pk, s);
             if (fine && last) *nparts = nt;
             xb = 1 - xb;

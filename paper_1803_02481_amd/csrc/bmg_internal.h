@@ -114,6 +114,16 @@ template <typename T>
 hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
                                  int nmap, const int *active, int wpg, hipStream_t s);
 
+// Tile kernels of the small 9-point coarse levels (V(2,1)): a workgroup of nw
+// waves (4 or 8) owns a strip by tile_steps(nw, down) row-pair steps.  down:
+// two relaxations from zero, residual, r/C and restriction (the work of
+// SV_SWEEP2_RQ_ZX); up: interpolate and correct, one relaxation (SV_INTERP).
+// a.nstrips / a.ntiles come from tile_geometry; one workgroup per tile.
+int tile_steps(int nw, int down);
+void tile_geometry(int nx, int ny, int npt, int nw, int down, int *nstrips, int *nblocks, int *ntiles);
+template <typename T>
+hipError_t launch_tile(int down, int nw, const StreamArgs<T> &a, hipStream_t s);
+
 // 1 if every interior vertex of a 5-point level has C exactly equal to
 // ((W_p + W_e) + S_p) + S_n (FP64), or an FP32 edge-form excess of exactly 0;
 // the result goes to *flag (device int, written by the check)

@@ -1182,4 +1182,365 @@ template hipError_t launch_stream_batched<float>(int, int, const StreamArgs<floa
 template hipError_t launch_stream<double>(int, int, const StreamArgs<double> &, int, hipStream_t);
 template hipError_t launch_stream<float>(int, int, const StreamArgs<float> &, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Tile kernels for the small coarse levels (9-point, V(2,1)).  On levels too
+// small to fill the device a streaming wave's time is its chain of row-pair
+// steps (one memory round trip and four dependent colour updates each, plus
+// the prologue steps).  Here a workgroup of NW waves loads a whole tile at
+// once: the strip's 64 lanes of column pairs by NW * 4 rows, four consecutive
+// rows per wave.  A relaxation is then two phases, because on a 9-point
+// stencil the even rows (colours 0 and 1) depend only on the odd rows and the
+// odd rows (colours 2 and 3) only on the even rows: every wave relaxes its
+// even rows, the waves swap the rows at their edges through LDS and meet at
+// a barrier, then the odd rows.  Each point is updated by the same
+// expressions (res_even / res_odd, interpolation, restriction) from the same
+// values as in the colour-by-colour sweep, so the results are bitwise those
+// of the streaming kernels.  Rows at the tile's edges see missing
+// neighbours and are recomputed by the neighbouring tiles: a down tile owning
+// row-pair steps [s0, s1) loads rows 2 s0 - 6 .. 2 s1 + 3, an up tile rows
+// 2 s0 - 2 .. 2 s1 + 1; columns have the streaming kernels' halo lanes.
+// ---------------------------------------------------------------------------
+constexpr int TILE_RPW = 4;   // rows per wave
+
+int tile_steps(int nw, int down) { return down ? (nw * TILE_RPW - 10) / 2 : (nw * TILE_RPW - 4) / 2; }
+
+int tile_owned_pairs(int npt, int down)
+{
+    return down ? stream_owned_pairs(npt, SV_SWEEP2_RQ_ZX) : stream_owned_pairs(npt, SV_INTERP);
+}
+
+void tile_geometry(int nx, int ny, int npt, int nw, int down, int *nstrips, int *nblocks, int *ntiles)
+{
+    const int own = tile_owned_pairs(npt, down), r = tile_steps(nw, down);
+    *nstrips = ((nx + 1) / 2 + own - 1) / own;
+    *nblocks = ((ny - 1) / 2 + r - 1) / r;
+    *ntiles = *nstrips * *nblocks;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_relax_row(const Row<T> &bl, Row<T> &cu, const Row<T> &ab, int j,
+                                               const LaneCtx &L)
+{
+    const bool rj = j >= 1 && j <= L.ny - 2;
+    T d;
+    T r = res_even<T, 9>(bl, cu, ab, d);
+    if (rj && L.ie) cu.x0 += r / d;
+    r = res_odd<T, 9>(bl, cu, ab, d);
+    if (rj && L.io) cu.x1 += r / d;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_load_row(Row<T> &r, int j, bool with_x, const LaneCtx &L, bool colv,
+                                              const StreamArgs<T> &a)
+{
+    r = Row<T>{};
+    if (colv && j >= 0 && j < L.ny) {
+        const size_t off = (size_t)j * L.pitch + L.e;
+        if (with_x) ld2(a.x_in + off, r.x0, r.x1);
+        ld2(a.b + off, r.b0, r.b1);
+        ld2(a.C + off, r.C0, r.C1);
+        ld2(a.W + off, r.W0, r.W1);
+        ld2(a.S + off, r.S0, r.S1);
+        ld2(a.SW + off, r.SW0, r.SW1);
+        ld2(a.SE + off, r.SE0, r.SE1);
+    }
+}
+
+// the connections of row j that the row below reads (S, SW, SE)
+template <typename T>
+__device__ __forceinline__ void tile_load_above(Row<T> &r, int j, const LaneCtx &L, bool colv,
+                                                const StreamArgs<T> &a)
+{
+    r = Row<T>{};
+    if (colv && j >= 0 && j < L.ny) {
+        const size_t off = (size_t)j * L.pitch + L.e;
+        ld2(a.S + off, r.S0, r.S1);
+        ld2(a.SW + off, r.SW0, r.SW1);
+        ld2(a.SE + off, r.SE0, r.SE1);
+    }
+}
+
+// Two relaxations from x = 0, residual, r/C and restriction onto the coarse
+// right-hand side (the down leg of a coarse level; stream2_tile's work).
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tile_down(StreamArgs<T> a)
+{
+    constexpr int NPT = 9;
+    constexpr int HA = 1 + (NPT == 9);
+    constexpr int HL = HA + halo_left(NPT, 1);
+    constexpr int HR = HA + halo_right(NPT, 0);
+    constexpr int OWN = 64 - HL - HR;
+    constexpr int R = (NW * TILE_RPW - 10) / 2;
+    __shared__ T xs[2][NW][64][2];   // x of each wave's first [0] and last [1] row
+    __shared__ T rs[NW][64][2];      // residual of each wave's last row
+    if (a.active && *a.active == 0) return;
+    const int tile = blockIdx.x;
+    if (tile >= a.ntiles) return;
+    const int strip = tile % a.nstrips, blk = tile / a.nstrips;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = strip * OWN + lane - HL;
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = t >= 0 && t < a.cnx;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+    const int nsteps = (ny - 1) / 2;
+    const int s0 = blk * R, s1 = min(s0 + R, nsteps);
+    const int jw0 = 2 * s0 - 6 + TILE_RPW * w;
+
+    Row<T> rw[TILE_RPW], up;
+#pragma unroll
+    for (int k = 0; k < TILE_RPW; ++k) tile_load_row(rw[k], jw0 + k, false, L, colv, a);
+    tile_load_above(up, jw0 + TILE_RPW, L, colv, a);
+    if (w == NW - 1) up = Row<T>{};   // the row above the tile is not loaded
+    // the restriction weights of coarse rows jw0/2 - 1 .. jw0/2 + 1, loaded
+    // with the rows so that their latency overlaps the relaxations
+    T wxl[2], wxr[2], wyb[2], wcsw[2], wcse[2], wyt[2], wcnw[2], wcne[2];
+    {
+        const long long cp = a.cplane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jc = (jw0 >> 1) + h;
+            wxl[h] = wxr[h] = wyb[h] = wcsw[h] = wcse[h] = wyt[h] = wcnw[h] = wcne[h] = T(0);
+            if (cv && jc >= 0 && jc <= a.cny - 1) {
+                const size_t co = (size_t)jc * a.cpitch + t;
+                wxl[h] = a.wt[WXL * cp + co];
+                wxr[h] = a.wt[WXR * cp + co];
+                wyb[h] = a.wt[WYB * cp + co];
+                wcsw[h] = a.wt[WCSW * cp + co];
+                wcse[h] = a.wt[WCSE * cp + co];
+            }
+            if (cv && jc - 1 >= 0 && jc - 1 <= a.cny - 1) {
+                const size_t co = (size_t)(jc - 1) * a.cpitch + t;
+                wyt[h] = a.wt[WYT * cp + co];
+                wcnw[h] = a.wt[WCNW * cp + co];
+                wcne[h] = a.wt[WCNE * cp + co];
+            }
+        }
+    }
+    auto below = [&](bool zero) {
+        Row<T> r{};
+        if (w > 0 && !zero) {
+            r.x0 = xs[1][w - 1][lane][0];
+            r.x1 = xs[1][w - 1][lane][1];
+        }
+        return r;
+    };
+    auto above = [&]() {
+        Row<T> r = up;
+        if (w < NW - 1) {
+            r.x0 = xs[0][w + 1][lane][0];
+            r.x1 = xs[0][w + 1][lane][1];
+        }
+        return r;
+    };
+#pragma unroll
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        {   // even rows: colours 0 and 1 (the first sweep starts from x = 0)
+            const Row<T> b0 = below(sweep == 0);
+            tile_relax_row(b0, rw[0], rw[1], jw0, L);
+            tile_relax_row(rw[1], rw[2], rw[3], jw0 + 2, L);
+            xs[0][w][lane][0] = rw[0].x0;
+            xs[0][w][lane][1] = rw[0].x1;
+        }
+        __syncthreads();
+        {   // odd rows: colours 2 and 3
+            tile_relax_row(rw[0], rw[1], rw[2], jw0 + 1, L);
+            const Row<T> a3 = above();
+            tile_relax_row(rw[2], rw[3], a3, jw0 + 3, L);
+            xs[1][w][lane][0] = rw[3].x0;
+            xs[1][w][lane][1] = rw[3].x1;
+        }
+        __syncthreads();
+    }
+    // residuals of the final rows, zero outside the interior
+    T res_e[TILE_RPW], res_o[TILE_RPW], dg_e[TILE_RPW], dg_o[TILE_RPW];
+    {
+        const Row<T> b0 = below(false), a3 = above();
+#pragma unroll
+        for (int k = 0; k < TILE_RPW; ++k) {
+            const Row<T> &bl = k == 0 ? b0 : rw[k - 1];
+            const Row<T> &ab = k == TILE_RPW - 1 ? a3 : rw[k + 1];
+            res_e[k] = res_even<T, NPT>(bl, rw[k], ab, dg_e[k]);
+            res_o[k] = res_odd<T, NPT>(bl, rw[k], ab, dg_o[k]);
+            const int j = jw0 + k;
+            const bool rr = j >= 1 && j <= ny - 2;
+            if (!(rr && ie)) res_e[k] = T(0);
+            if (!(rr && io)) res_o[k] = T(0);
+        }
+    }
+    rs[w][lane][0] = res_e[TILE_RPW - 1];
+    rs[w][lane][1] = res_o[TILE_RPW - 1];
+    // the iterate and r/C of the rows this tile owns
+    if (own) {
+#pragma unroll
+        for (int k = 0; k < TILE_RPW; ++k) {
+            const int j = jw0 + k;
+            if (j >= 2 * s0 + 1 && j <= 2 * s1 && j >= 1 && j <= ny - 2)
+                st2(a.x_out + (size_t)j * pitch + e, rw[k].x0, rw[k].x1);
+            if (j >= 2 * s0 && j <= 2 * s1 - 1 && j >= 1 && j <= ny - 2) {
+                if ((k & 1) == 0) {
+                    if (io) a.q_out[(size_t)j * pitch + o] = res_o[k] / dg_o[k];
+                } else {
+                    st2(a.q_out + (size_t)j * pitch + e, ie ? res_e[k] / dg_e[k] : T(0),
+                        io ? res_o[k] / dg_o[k] : T(0));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // restriction onto coarse rows jw0/2 and jw0/2 + 1: fine rows 2jc-1, 2jc, 2jc+1
+    T r3e = w > 0 ? rs[w - 1][lane][0] : T(0), r3o = w > 0 ? rs[w - 1][lane][1] : T(0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int jc = (jw0 >> 1) + h;
+        const int k = 2 * h;                       // row 2jc is rw[k], 2jc+1 is rw[k+1]
+        const T xl = wxl[h], xr = wxr[h], yb = wyb[h], csw = wcsw[h], cse = wcse[h];
+        const T ytp = wyt[h], cnwp = wcnw[h], cnep = wcne[h];
+        const T ae = res_e[k], ao = res_o[k], be = res_e[k + 1], bo = res_o[k + 1];
+        T lxr = fromL(xr), lcse = fromL(cse), lcnep = fromL(cnep);
+        T lao = fromL(ao), lbo = fromL(bo), lr3o = fromL(r3o);
+        T bcv = ae + xl * ao + lxr * lao + yb * be + ytp * r3e + csw * bo + lcse * lbo + cnwp * r3o +
+                lcnep * lr3o;
+        if (own && jc >= s0 && jc < s1 && jc >= 1 && jc <= a.cny - 2 && t >= 1 && t <= a.cnx - 2)
+            a.bc[(size_t)jc * a.cpitch + t] = bcv;
+        r3e = be;
+        r3o = bo;
+    }
+}
+
+// Interpolate and correct (x += P x_c + r/C), then one relaxation (the up
+// leg of a coarse level with one post-relaxation; stream_tile's SV_INTERP).
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tile_up(StreamArgs<T> a)
+{
+    constexpr int NPT = 9;
+    constexpr int HL = halo_left(NPT, 0);
+    constexpr int HR = halo_right(NPT, 1);
+    constexpr int OWN = 64 - HL - HR;
+    constexpr int R = (NW * TILE_RPW - 4) / 2;
+    __shared__ T xs[2][NW][64][2];
+    if (a.active && *a.active == 0) return;
+    const int tile = blockIdx.x;
+    if (tile >= a.ntiles) return;
+    const int strip = tile % a.nstrips, blk = tile / a.nstrips;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = strip * OWN + lane - HL;
+    const int e = 2 * t, o = 2 * t + 1;
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const bool colv = t >= 0 && e < nx;
+    const bool own = lane >= HL && lane < 64 - HR && colv;
+    const bool ie = e >= 1 && e <= nx - 2;
+    const bool io = o >= 1 && o <= nx - 2;
+    const bool cv = t >= 0 && t < a.cnx;
+    const LaneCtx L{t, e, o, pitch, ny, own, ie, io, cv};
+    const int nsteps = (ny - 1) / 2;
+    const int s0 = blk * R, s1 = min(s0 + R, nsteps);
+    const int jw0 = 2 * s0 - 2 + TILE_RPW * w;
+
+    Row<T> rw[TILE_RPW], up;
+#pragma unroll
+    for (int k = 0; k < TILE_RPW; ++k) {
+        Row<T> &r = rw[k];
+        const int j = jw0 + k;
+        tile_load_row(r, j, true, L, colv, a);
+        // the interpolation's inputs, as the streaming up leg loads them
+        const bool rin = j >= 1 && j <= ny - 2;
+        if (cv && rin) {
+            const int jc = j >> 1;
+            const size_t co = (size_t)jc * a.cpitch + t;
+            const T *wt = a.wt;
+            const long long cp = a.cplane;
+            r.ca = a.xc[co];
+            if (j & 1) {
+                r.cu = a.xc[co + a.cpitch];
+                r.w0 = wt[WYB * cp + co];
+                r.w1 = wt[WYT * cp + co];
+                r.w2 = wt[WCSW * cp + co];
+                r.w3 = wt[WCSE * cp + co];
+                r.w4 = wt[WCNW * cp + co];
+                r.w5 = wt[WCNE * cp + co];
+            } else {
+                r.w0 = wt[WXL * cp + co];
+                r.w1 = wt[WXR * cp + co];
+            }
+            if (a.rescorr) ld2(a.q_in + (size_t)j * pitch + e, r.q0, r.q1);
+        }
+    }
+    tile_load_above(up, jw0 + TILE_RPW, L, colv, a);
+    if (w == NW - 1) up = Row<T>{};
+    // x += P x_c (+ r/C at fine-only vertices)
+#pragma unroll
+    for (int k = 0; k < TILE_RPW; ++k) {
+        Row<T> &r = rw[k];
+        const int j = jw0 + k;
+        const bool rin = j >= 1 && j <= ny - 2;
+        if ((j & 1) == 0) {
+            const T xb = fromR(r.ca);
+            if (rin && ie) r.x0 += r.ca;
+            if (rin && io) r.x1 += r.w0 * r.ca + r.w1 * xb + r.q1;
+        } else {
+            const T xb = fromR(r.ca), xd = fromR(r.cu);
+            if (rin && ie) r.x0 += r.w0 * r.ca + r.w1 * r.cu + r.q0;
+            if (rin && io) r.x1 += r.w2 * r.ca + r.w3 * xb + r.w4 * r.cu + r.w5 * xd + r.q1;
+        }
+    }
+    xs[0][w][lane][0] = rw[0].x0;
+    xs[0][w][lane][1] = rw[0].x1;
+    xs[1][w][lane][0] = rw[TILE_RPW - 1].x0;
+    xs[1][w][lane][1] = rw[TILE_RPW - 1].x1;
+    __syncthreads();
+    {   // even rows
+        Row<T> b0{};
+        if (w > 0) {
+            b0.x0 = xs[1][w - 1][lane][0];
+            b0.x1 = xs[1][w - 1][lane][1];
+        }
+        tile_relax_row(b0, rw[0], rw[1], jw0, L);
+        tile_relax_row(rw[1], rw[2], rw[3], jw0 + 2, L);
+        // first rows are read again only in the odd phase
+        xs[0][w][lane][0] = rw[0].x0;
+        xs[0][w][lane][1] = rw[0].x1;
+    }
+    __syncthreads();
+    {   // odd rows
+        tile_relax_row(rw[0], rw[1], rw[2], jw0 + 1, L);
+        Row<T> a3 = up;
+        if (w < NW - 1) {
+            a3.x0 = xs[0][w + 1][lane][0];
+            a3.x1 = xs[0][w + 1][lane][1];
+        }
+        tile_relax_row(rw[2], rw[3], a3, jw0 + 3, L);
+    }
+    if (own) {
+#pragma unroll
+        for (int k = 0; k < TILE_RPW; ++k) {
+            const int j = jw0 + k;
+            if (j >= 2 * s0 + 1 && j <= 2 * s1 && j >= 1 && j <= ny - 2)
+                st2(a.x_out + (size_t)j * pitch + e, rw[k].x0, rw[k].x1);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_tile(int down, int nw, const StreamArgs<T> &a, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    if (nw == 8) {
+        if (down) hipLaunchKernelGGL((k_tile_down<T, 8>), dim3(a.ntiles), dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_up<T, 8>), dim3(a.ntiles), dim3(512), 0, s, a);
+    } else if (nw == 4) {
+        if (down) hipLaunchKernelGGL((k_tile_down<T, 4>), dim3(a.ntiles), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_up<T, 4>), dim3(a.ntiles), dim3(256), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_tile<double>(int, int, const StreamArgs<double> &, hipStream_t);
+template hipError_t launch_tile<float>(int, int, const StreamArgs<float> &, hipStream_t);
+
 }  // namespace hbmg

@@ -1,8 +1,9 @@
 """GPU checks of streaming-pass variants that must not change the iteration:
 the up leg forming r/C from the rows it loads instead of reading a stored
 plane, the last cycle of a capped solve run as the pipelined pass's first
-stage alone, and the pipelined pass forming a zero-excess operator's diagonal
-instead of loading it.  Each is compared bitwise with the path it replaces."""
+stage alone, the pipelined pass forming a zero-excess operator's diagonal
+instead of loading it, and the tile kernels of the small coarse levels.  Each
+is compared bitwise with the path it replaces."""
 import numpy as np
 import pytest
 import torch
@@ -136,3 +137,43 @@ def test_formed_weights_pass_is_bitwise_the_loading_pass(nx, ny, seed, monkeypat
             assert torch.equal(res["0"][0], res["1"][0]), (noz, cap)
             assert res["0"][1:3] == res["1"][1:3], (noz, cap)
             assert res["1"][3] - res["0"][3] == 16 * nx * ny     # the weight planes are not read
+
+
+@pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("nw", ["4", "8"])
+@pytest.mark.parametrize("nx,ny,cells", [(257, 257, "blocks"), (257, 225, "lognormal"), (193, 97, "blocks"),
+                                         (449, 129, "checker")])
+def test_tile_kernels_are_bitwise_the_streaming_kernels(nx, ny, cells, nw, precision, monkeypatch):
+    # every coarse 9-point level on the tile kernels (whole tiles relaxed in
+    # two row phases per sweep) against every level on the streaming kernels:
+    # the same expressions on the same values, so the same bits; the collapse
+    # level is fixed, as the model prices the two kinds differently
+    if cells == "blocks":
+        D = inputs.cells_log10_blocks(nx, ny, 16, seed=61)
+    elif cells == "lognormal":
+        D = inputs.cells_lognormal(nx, ny, 1.0, seed=62)
+    else:
+        D = inputs.cells_two_phase_blocks(nx, ny, 16, seed=63)
+    planes = O.fv5(D)
+    b = inputs.load_uniform(nx, ny, seed=64)
+    for pipelined in ("0", "1"):
+        monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
+        limits = ("HIPBMG_TILE_MAX", "HIPBMG_TILE_UP_MAX", "HIPBMG_TILE_UP_MAX64")
+        for k in limits:
+            monkeypatch.setenv(k, "0")
+        u0, i0 = run(planes, b, 6, precision=precision, collapse_level=1)
+        for k in limits:
+            monkeypatch.setenv(k, str(1 << 40))
+        monkeypatch.setenv("HIPBMG_TILE_NW", nw)
+        u1, i1 = run(planes, b, 6, precision=precision, collapse_level=1)
+        monkeypatch.delenv("HIPBMG_TILE_NW")
+        for k in limits:
+            monkeypatch.delenv(k)
+        assert i1.cycles == i0.cycles
+        assert list(i1.history()) == list(i0.history())
+        assert torch.equal(u1, u0), float((u1 - u0).abs().max())
+    # and a whole solve to the tolerance, with the default choice of levels,
+    # meets it by the host's residual
+    u, info = run(planes, b, 500, tol=1e-10, precision=precision)
+    r = H.residual_from_planes(planes, b, c(u))
+    assert np.linalg.norm(r) <= 1.2e-10 * np.linalg.norm(b[1:-1, 1:-1])
