@@ -2193,9 +2193,10 @@ hipbmg_status hbmg::calibrate_on_kernels(void *stream, ModelParams &p)
 // every later launch.  A cycle is captured once as a hipGraph and replayed.
 // ---------------------------------------------------------------------------
 struct BLaunch {
-    int kind;            // 0 streaming stage, 1 collapse
+    int kind;            // 0 streaming stage, 1 collapse, 2 pipelined finest pass
     int npt, variant;
     int wpg;             // streaming stage: strips (waves) per workgroup
+    int zc;              // pipelined pass: every problem forms its diagonal
     void *d_args;        // StreamArgs<T>[nprob] or CollapseArgs<T>[nprob]
     int2 *d_map;
     int nmap;
@@ -2243,6 +2244,17 @@ struct hipbmg_batch {
     BPlan plan64[2], plan32[2][2];
     int rb_cap = 0;                           // row blocks of the batched launches (0: per-level rule)
     int wpg = 1;                              // strips (one wave each) per workgroup of the batched launches
+    // pipelined finest level: every problem's finest post-relaxation and the
+    // next cycle's pre-relaxations run as one pass (as for a single problem)
+    bool pipe = false;
+    int zc[2] = {0, 0};                       // every problem's pass forms its diagonal (FP64, FP32)
+    BPlan pipe64[4], pipe32[4];               // [0..2] a cycle with iterate rotation i, [3] the first cycle
+    std::vector<int> cc64, cc32;              // coarse buffer holding each problem's coarse correction
+    StreamArgs<double> *d_rb64 = nullptr, *h_rb64 = nullptr;   // rebuild of the stopping cycles' iterates
+    StreamArgs<float> *d_rb32 = nullptr, *h_rb32 = nullptr;
+    int *d_rbact = nullptr, *h_rbact = nullptr;
+    float **d_eptr = nullptr, **h_eptr = nullptr;              // each problem's FP32 correction
+    int *h_act2 = nullptr;
     std::vector<void *> seg_allocs;           // norm segment tables (rebuilt with the plans)
     hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -2254,8 +2266,15 @@ struct hipbmg_batch {
         for (auto &p : plan64) drop_plan(p);
         for (auto &q : plan32)
             for (auto &p : q) drop_plan(p);
+        for (auto &p : pipe64) drop_plan(p);
+        for (auto &p : pipe32) drop_plan(p);
         dev_free_all(seg_allocs);
         dev_free_all(allocs);
+        if (h_rb64) (void)hipHostFree(h_rb64);
+        if (h_rb32) (void)hipHostFree(h_rb32);
+        if (h_rbact) (void)hipHostFree(h_rbact);
+        if (h_eptr) (void)hipHostFree(h_eptr);
+        if (h_act2) (void)hipHostFree(h_act2);
         if (h_relres) (void)hipHostFree(h_relres);
         if (h_active) (void)hipHostFree(h_active);
         if (h_count) (void)hipHostFree(h_count);
@@ -2313,9 +2332,13 @@ static int batch_rb(const hipbmg_batch *B, const LevelDev<T> &A)
 }
 
 // Record the launches of one V-cycle of every problem (same order as
-// enqueue_vcycle) and group them into batched stages.
+// enqueue_vcycle) and group them into batched stages.  pipe_i >= 0: the
+// finest level pipelined, its pass reading iterate buffer pipe_i of
+// {x[0], x[1], x3} and writing the next two; pipe_first adds the finest
+// pre-relaxations of the first cycle (from x[0], or from zero) before it.
 template <typename T>
-static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan &plan, hipStream_t s)
+static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan &plan, hipStream_t s,
+                                int pipe_i = -1, bool pipe_first = false)
 {
     const int n = B->n;
     const int nu1 = B->prm.nu1, nu2 = B->prm.nu2, rc = B->prm.residual_correction;
@@ -2338,6 +2361,10 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             const int d = L - 1 - l;
             const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
             const bool fine = l == L - 1;
+            if (fine && pipe_i >= 0 && !pipe_first) {
+                xb_after[l] = 0;   // the previous cycle's pass did these pre-relaxations
+                continue;
+            }
             int xb = fine ? cur : 0;
             const bool zero = !fine || zero_start;
             const int nk = (nu1 >= 2 && !h->no_fuse2) ? nu1 - 1 : nu1;
@@ -2376,6 +2403,33 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             const int d = L - 1 - l;
             const LevelDev<T> &A = lv[l], &Cl = lv[l - 1];
             const bool fine = l == L - 1;
+            if (fine && pipe_i >= 0) {
+                // this cycle's interpolation, relaxation and norm, and the
+                // next cycle's pre-relaxations and restriction, in one pass
+                T *x3[3] = {A.x[0], A.x[1], x3_of<T>(h)};
+                StreamArgs<T> a = base_args(A, batch_rb(B, A));
+                a.x_in = x3[pipe_i];
+                a.x_out = x3[(pipe_i + 1) % 3];
+                a.x_out2 = x3[(pipe_i + 2) % 3];
+                a.xc = Cl.x[xres[l - 1]];
+                a.wt = A.wt;
+                a.rescorr = rc;
+                a.bc = Cl.b;
+                a.cnx = Cl.nx;
+                a.cny = Cl.ny;
+                a.cpitch = Cl.pitch;
+                a.cplane = (long long)Cl.plane;
+                a.zexc = B->zc[PrecIdx<T>::v];
+                int g;
+                stream_geometry(A.nx, A.ny, A.npt, SV_FUSED3, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+                pc = a.ntiles;
+                if ((int)up.size() <= d) up.resize(d + 1);
+                if (up[d].empty()) up[d].resize(1);
+                up[d][0].push_back({p, A.npt, SV_FUSED3, a});
+                (PrecIdx<T>::v ? B->cc32 : B->cc64)[p] = xres[l - 1];
+                xres[l] = (pipe_i + 2) % 3;
+                continue;
+            }
             int xb = xb_after[l];
             for (int k = 1; k <= nu2; ++k) {
                 const bool first = k == 1, last = k == nu2;
@@ -2441,10 +2495,11 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
             for (int tl = 0; tl < r.a.ntiles; ++tl) map.push_back(make_int2(r.p, tl));
         }
         BLaunch bl{};
-        bl.kind = 0;
+        bl.kind = recs[0].variant == SV_FUSED3 ? 2 : 0;
         bl.npt = recs[0].npt;
         bl.variant = recs[0].variant;
         bl.wpg = B->wpg;
+        bl.zc = B->zc[PrecIdx<T>::v];
         StreamArgs<T> *da = nullptr;
         int2 *dm = nullptr;
         STCHK(balloc_to(plan.allocs, &da, n, s));
@@ -2485,6 +2540,9 @@ static hipError_t run_plan_launches(hipbmg_batch *B, BPlan &plan, const int *act
         if (bl.kind == 0)
             e = launch_stream_batched<T>(bl.npt, bl.variant, static_cast<const StreamArgs<T> *>(bl.d_args),
                                          bl.d_map, bl.nmap, active, bl.wpg, s);
+        else if (bl.kind == 2)
+            e = launch_stream3_batched<T>(bl.variant, bl.zc, static_cast<const StreamArgs<T> *>(bl.d_args),
+                                          bl.d_map, bl.nmap, active, bl.wpg, s);
         else
             e = launch_collapse_batched<T>(static_cast<const CollapseArgs<T> *>(bl.d_args), B->n,
                                            bl.lds_bytes, active, s);
@@ -2550,11 +2608,26 @@ static hipbmg_status build_plans(hipbmg_batch *B, hipStream_t s)
     for (auto &p : B->plan64) drop_plan(p);
     for (auto &q : B->plan32)
         for (auto &p : q) drop_plan(p);
+    for (auto &p : B->pipe64) drop_plan(p);
+    for (auto &p : B->pipe32) drop_plan(p);
     dev_free_all(B->seg_allocs);
     B->d_partials = nullptr;
     B->d_poff = B->d_pcnt = nullptr;
     B->n_partials = 0;
     B->h_pcnt.clear();
+    if (B->pipe) {
+        // the first cycle (pre-relaxations from x[0] or zero, then the pass
+        // on buffer 1) and the three buffer rotations of the later cycles
+        hipbmg_status st = HIPBMG_OK;
+        if (B->prm.precision == HIPBMG_MIXED) {
+            st = build_plan<float>(B, 0, true, B->pipe32[3], s, 1, true);
+            for (int i = 0; i < 3 && st == HIPBMG_OK; ++i) st = build_plan<float>(B, 0, false, B->pipe32[i], s, i);
+        } else {
+            st = build_plan<double>(B, 0, false, B->pipe64[3], s, 1, true);
+            for (int i = 0; i < 3 && st == HIPBMG_OK; ++i) st = build_plan<double>(B, 0, false, B->pipe64[i], s, i);
+        }
+        return st;
+    }
     hipbmg_status st = build_plan<double>(B, 0, false, B->plan64[0], s);
     if (st == HIPBMG_OK && B->plan64[0].end_cur != 0) st = build_plan<double>(B, 1, false, B->plan64[1], s);
     if (st == HIPBMG_OK && B->prm.precision == HIPBMG_MIXED) {
@@ -2616,7 +2689,7 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
         const int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4) wfix = v;
     }
-    key += "w" + std::to_string(wfix);
+    key += "w" + std::to_string(wfix) + "p" + std::to_string(B->pipe ? 1 : 0);
     if (!tune) {
         B->rb_cap = 0;
         B->wpg = wfix ? wfix : 1;
@@ -2652,7 +2725,10 @@ static hipbmg_status tune_batch(hipbmg_batch *B, hipStream_t s)
             B->rb_cap = cap;
             if ((st = build_plans(B, s)) != HIPBMG_OK) break;
             double us;
-            if (mixed) {
+            if (B->pipe) {
+                us = mixed ? time_plan_us<float>(B, B->pipe32[0], s, e0, e1)
+                           : time_plan_us<double>(B, B->pipe64[0], s, e0, e1);
+            } else if (mixed) {
                 const int c1 = B->plan32[1][0].end_cur;
                 us = time_plan_us<float>(B, B->plan32[0][c1], s, e0, e1);
             } else {
@@ -2777,6 +2853,39 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess ||
         hipHostMalloc(&B->h_tol, 2 * sizeof(double)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+    // the finest level pipelined across cycles when every problem's is (as
+    // hipbmg_setup decided it: 5-point, V(2,1), not collapsed); its pass forms
+    // the diagonal when every problem's operator allows it.
+    // HIPBMG_BATCH_PIPE=0 keeps one pass per leg.
+    {
+        bool pipe = true;
+        if (const char *e = std::getenv("HIPBMG_BATCH_PIPE")) pipe = std::atoi(e) != 0;
+        B->zc[0] = B->zc[1] = 1;
+        for (hipbmg_hier *h : B->hs) {
+            pipe = pipe && h->fused3 && h->lstar < h->L - 1;
+            B->zc[0] = B->zc[0] && h->zexc[0];
+            B->zc[1] = B->zc[1] && h->zexc[1];
+        }
+        B->pipe = pipe;
+        B->cc64.assign(nprob, 0);
+        B->cc32.assign(nprob, 0);
+        if (pipe) {
+            if (prm.precision == HIPBMG_MIXED) {
+                chk(balloc(B, &B->d_rb32, nprob, s));
+                chk(balloc(B, &B->d_eptr, nprob, s));
+            } else {
+                chk(balloc(B, &B->d_rb64, nprob, s));
+            }
+            chk(balloc(B, &B->d_rbact, nprob, s));
+            if (st != HIPBMG_OK) return bail(st);
+            if (hipHostMalloc(&B->h_rb64, nprob * sizeof(StreamArgs<double>)) != hipSuccess ||
+                hipHostMalloc(&B->h_rb32, nprob * sizeof(StreamArgs<float>)) != hipSuccess ||
+                hipHostMalloc(&B->h_rbact, nprob * sizeof(int)) != hipSuccess ||
+                hipHostMalloc(&B->h_eptr, nprob * sizeof(float *)) != hipSuccess ||
+                hipHostMalloc(&B->h_act2, nprob * sizeof(int)) != hipSuccess)
+                return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+        }
+    }
     st = tune_batch(B, s);
     if (st != HIPBMG_OK) return bail(st);
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(HIPBMG_EHIP, "batch setup failed"));
@@ -2819,6 +2928,54 @@ static hipbmg_status batch_bnorm(hipbmg_batch *B, hipStream_t s)
     return HIPBMG_OK;
 }
 
+// The pipelined pass does not store the iterate after its own cycle.  After
+// the cycles, every problem's iterate after its stopping cycle kstop[p] (0:
+// none) is rebuilt by the pass's interpolation and relaxation stage alone from
+// that cycle's inputs, which the later launches (skipped once the problem
+// retired) left untouched; cycle k ran the pass on buffer (1 + 2 (k - 1)) mod 3
+// of {x[0], x[1], x3}.  out[p] receives the buffer holding the iterate.
+template <typename T>
+static hipbmg_status batch_rebuild(hipbmg_batch *B, const BPlan &plan, const std::vector<int> &kstop,
+                                   StreamArgs<T> *h_args, StreamArgs<T> *d_args, std::vector<T *> &out,
+                                   hipStream_t s)
+{
+    const BLaunch &fl = plan.launches.back();   // the pass's stage: every problem's tiles
+    if (fl.kind != 2) return fail(HIPBMG_EINVAL, "batched plan: no pipelined pass to rebuild from");
+    const int rc = B->prm.residual_correction;
+    bool any = false;
+    for (int p = 0; p < B->n; ++p) {
+        hipbmg_hier *h = B->hs[p];
+        const std::vector<LevelDev<T>> &lv = levels_of<T>(h);
+        const LevelDev<T> &F = lv[h->L - 1], &Cl = lv[h->L - 2];
+        T *x3[3] = {F.x[0], F.x[1], x3_of<T>(h)};
+        h_args[p] = StreamArgs<T>{};
+        B->h_rbact[p] = kstop[p] > 0;
+        out[p] = x3[0];
+        if (kstop[p] <= 0) continue;
+        any = true;
+        const int i = (1 + 2 * (kstop[p] - 1)) % 3;
+        StreamArgs<T> a = base_args(F, batch_rb(B, F));
+        a.x_in = x3[i];
+        a.x_out = x3[(i + 1) % 3];
+        a.xc = Cl.x[(PrecIdx<T>::v ? B->cc32 : B->cc64)[p]];
+        a.wt = F.wt;
+        a.rescorr = rc;
+        a.cnx = Cl.nx;
+        a.cny = Cl.ny;
+        a.cpitch = Cl.pitch;
+        a.cplane = (long long)Cl.plane;
+        int g;
+        stream_geometry(F.nx, F.ny, F.npt, SV_FUSED3, a.rb, &a.nstrips, &a.nblocks, &a.ntiles, &g);
+        h_args[p] = a;
+        out[p] = x3[(i + 1) % 3];
+    }
+    if (!any) return HIPBMG_OK;
+    HIPCHK(hipMemcpyAsync(d_args, h_args, B->n * sizeof(StreamArgs<T>), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->d_rbact, B->h_rbact, B->n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_stream3_batched<T>(SV_FUSED3_P, fl.zc, d_args, fl.d_map, fl.nmap, B->d_rbact, fl.wpg, s));
+    return HIPBMG_OK;
+}
+
 extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const double *const *b, double *const *u,
                                               double tol, void *stream, hipbmg_info *infos)
 {
@@ -2845,7 +3002,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             memset(&infos[p], 0, sizeof(hipbmg_info));
             fill_info_common(h, &infos[p]);
             for (int l = 0; l < h->L; ++l) infos[p].rb_down[l] = infos[p].rb_up[l] = batch_rb(B, h->lv[l]);
-            infos[p].rb_pipelined = 0;
+            infos[p].rb_pipelined = B->pipe ? batch_rb(B, F) : 0;
         }
     }
     const int maxn = std::max(B->max_nx, B->max_ny);
@@ -2869,7 +3026,27 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
     HIPCHK(hipMemcpyAsync(B->d_tol, B->h_tol, 2 * sizeof(double), hipMemcpyHostToDevice, s));
     hipbmg_status result = HIPBMG_OK;
     int cur = 0;
-    if (B->prm.precision != HIPBMG_MIXED) {
+    std::vector<double *> res64(n, nullptr);
+    if (B->prm.precision != HIPBMG_MIXED && B->pipe) {
+        std::vector<int> kstop(n, 0);
+        int i = 1;
+        for (int c = 0; c < B->prm.max_cycles; ++c) {
+            BPlan &plan = c == 0 ? B->pipe64[3] : B->pipe64[i];
+            STCHK(batch_cycle<double>(B, plan, B->d_active, B->d_bnorm, B->d_relres, B->d_tol, s));
+            STCHK(batch_read(B, B->d_relres, B->d_active, s));
+            for (int p = 0; p < n; ++p)
+                if (act[p]) {
+                    rel[p] = B->h_relres[p];
+                    if (infos && cycles[p] < HIPBMG_MAX_HIST) infos[p].relres_hist[cycles[p]] = rel[p];
+                    kstop[p] = ++cycles[p];
+                    if (!B->h_active[p]) act[p] = 0;
+                }
+            i = plan.end_cur;
+            if (B->h_count[0] == 0) break;
+        }
+        STCHK(batch_rebuild<double>(B, B->pipe64[0], kstop, B->h_rb64, B->d_rb64, res64, s));
+        for (int p = 0; p < n; ++p) steps[p] = cycles[p];
+    } else if (B->prm.precision != HIPBMG_MIXED) {
         for (int c = 0; c < B->prm.max_cycles; ++c) {
             BPlan &plan = B->plan64[cur];
             STCHK(batch_cycle<double>(B, plan, B->d_active, B->d_bnorm, B->d_relres, B->d_tol, s));
@@ -2912,6 +3089,36 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             if (B->h_count[0] == 0 || total >= B->prm.max_cycles) break;
             // inner FP32 solves of A e = r for the active problems
             HIPCHK(hipMemcpyAsync(B->d_active2, B->d_active, n * sizeof(int), hipMemcpyDeviceToDevice, s));
+            if (B->pipe) {
+                // pipelined finest level: each problem's inner solve stops at
+                // its own cycle, whose iterate is rebuilt after the cycles
+                std::vector<int> in2(act), kin(n, 0);
+                int i = 1;
+                for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
+                    BPlan &plan = k == 0 ? B->pipe32[3] : B->pipe32[i];
+                    STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_tol + 1, s));
+                    i = plan.end_cur;
+                    ++total;
+                    HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipMemcpyAsync(B->h_act2, B->d_active2, n * sizeof(int), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    for (int p = 0; p < n; ++p) {
+                        if (act[p]) ++cycles[p];
+                        if (in2[p]) {
+                            ++kin[p];
+                            if (!B->h_act2[p]) in2[p] = 0;
+                        }
+                    }
+                    if (B->h_count[0] == 0) break;
+                }
+                std::vector<float *> e32(n, nullptr);
+                STCHK(batch_rebuild<float>(B, B->pipe32[0], kin, B->h_rb32, B->d_rb32, e32, s));
+                for (int p = 0; p < n; ++p) B->h_eptr[p] = e32[p];
+                HIPCHK(hipMemcpyAsync(B->d_eptr, B->h_eptr, n * sizeof(float *), hipMemcpyHostToDevice, s));
+                HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_eptr, B->d_active, B->max_nx,
+                                                B->max_ny, n, s));
+                continue;
+            }
             int icur = 0;
             for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
                 BPlan &plan = k == 0 ? B->plan32[1][0] : B->plan32[0][icur];
@@ -2925,7 +3132,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 if (B->h_count[0] == 0) break;
             }
             if (icur != 0) return fail(HIPBMG_EINVAL, "batched refinement expects the correction in buffer 0");
-            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_active, B->max_nx, B->max_ny, n, s));
+            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, nullptr, B->d_active, B->max_nx, B->max_ny, n,
+                                            s));
         }
         for (int p = 0; p < n; ++p) done_cur[p] = 0;
     }
@@ -2935,7 +3143,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         if (bnorm[p] == 0.0) {
             HIPCHK(hipMemsetAsync(u[p], 0, (size_t)F.nx * F.ny * sizeof(double), s));
         } else {
-            HIPCHK(hipMemcpy2DAsync(u[p], F.nx * sizeof(double), F.x[done_cur[p]], F.pitch * sizeof(double),
+            const double *src = res64[p] ? res64[p] : F.x[done_cur[p]];
+            HIPCHK(hipMemcpy2DAsync(u[p], F.nx * sizeof(double), src, F.pitch * sizeof(double),
                                     F.nx * sizeof(double), F.ny, hipMemcpyDeviceToDevice, s));
         }
         const bool ok = bnorm[p] == 0.0 || rel[p] <= tol;

@@ -114,6 +114,14 @@ template <typename T>
 hipError_t launch_stream_batched(int npt, int variant, const StreamArgs<T> *args, const int2 *map,
                                  int nmap, const int *active, int wpg, hipStream_t s);
 
+// the pipelined finest pass (SV_FUSED3, or SV_FUSED3_P for the rebuild of a
+// stopped cycle's iterate) over many problems: map[w] = (problem, tile) of
+// wave w, args[problem]; zc: every problem's pass forms its diagonal; active
+// may be null (every problem in the map runs)
+template <typename T>
+hipError_t launch_stream3_batched(int variant, int zc, const StreamArgs<T> *args, const int2 *map, int nmap,
+                                  const int *active, int wpg, hipStream_t s);
+
 // Tile kernels of the small 9-point coarse levels (V(2,1)): a workgroup of nw
 // waves (4 or 8) owns a strip by tile_steps(nw, down) row-pair steps.  down:
 // two relaxations from zero, residual, r/C and restriction (the work of

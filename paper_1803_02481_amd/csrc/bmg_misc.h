@@ -22,8 +22,10 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
                                       const int *active, double *partials, const int *poff, int npt,
                                       int max_nx, int max_ny, int nprob, hipStream_t s);
-hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const int *active,
-                                    int max_nx, int max_ny, int nprob, hipStream_t s);
+// u += e for every active problem; e from eptr[p] (device array of device
+// pointers with the FP32 level's pitch), or the FP32 finest x[0] if eptr is null
+hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
+                                    const int *active, int max_nx, int max_ny, int nprob, hipStream_t s);
 hipError_t launch_zero_ring_batched(double *const *v, const int4 *dims, int maxn, int nprob, hipStream_t s);
 
 }  // namespace hbmg

@@ -204,22 +204,23 @@ hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<
 }
 
 __global__ void k_ir_update_batched(const LevelDev<double> *__restrict__ d, const LevelDev<float> *__restrict__ f,
-                                    const int *__restrict__ active)
+                                    const float *const *__restrict__ eptr, const int *__restrict__ active)
 {
     const int p = blockIdx.z;
     if (!active[p]) return;
     const LevelDev<double> &D = d[p];
+    const float *e = eptr ? eptr[p] : f[p].x[0];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2)
-        D.x[0][(size_t)j * D.pitch + i] += (double)f[p].x[0][(size_t)j * f[p].pitch + i];
+        D.x[0][(size_t)j * D.pitch + i] += (double)e[(size_t)j * f[p].pitch + i];
 }
 
-hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const int *active,
-                                    int max_nx, int max_ny, int nprob, hipStream_t s)
+hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
+                                    const int *active, int max_nx, int max_ny, int nprob, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ir_update_batched, dim3((max_nx + 255) / 256, max_ny, nprob), dim3(256), 0, s, d, f,
-                       active);
+                       eptr, active);
     return hipGetLastError();
 }
 

@@ -1182,6 +1182,53 @@ template hipError_t launch_stream_batched<float>(int, int, const StreamArgs<floa
 template hipError_t launch_stream<double>(int, int, const StreamArgs<double> &, int, hipStream_t);
 template hipError_t launch_stream<float>(int, int, const StreamArgs<float> &, int, hipStream_t);
 
+// The pipelined finest pass over many problems: map[w] = (problem, tile) of
+// wave w as in k_stream_batched.  active may be null (the rebuild of every
+// stopped problem's iterate after the cycles).
+template <typename T, bool PONLY, bool ZC, int W>
+__global__ __launch_bounds__(64 * W) void k_stream3_batched(const StreamArgs<T> *__restrict__ args,
+                                                            const int2 *__restrict__ map, int nmap,
+                                                            const int *__restrict__ active)
+{
+    const int w = (int)blockIdx.x * W + (int)(threadIdx.x >> 6);
+    if (w >= nmap) return;
+    const int2 m = map[w];
+    if (active && !active[m.x]) return;
+    const StreamArgs<T> a = args[m.x];
+    stream3_tile<T, PONLY, false, ZC, false>(a, m.y);
+}
+
+template <typename T, bool PONLY, bool ZC>
+static hipError_t launch_s3b(const StreamArgs<T> *args, const int2 *map, int nmap, const int *active, int wpg,
+                             hipStream_t s)
+{
+    switch (wpg) {
+    case 1: hipLaunchKernelGGL((k_stream3_batched<T, PONLY, ZC, 1>), dim3(nmap), dim3(64), 0, s, args, map, nmap, active); break;
+    case 2: hipLaunchKernelGGL((k_stream3_batched<T, PONLY, ZC, 2>), dim3((nmap + 1) / 2), dim3(128), 0, s, args, map, nmap, active); break;
+    case 4: hipLaunchKernelGGL((k_stream3_batched<T, PONLY, ZC, 4>), dim3((nmap + 3) / 4), dim3(256), 0, s, args, map, nmap, active); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stream3_batched(int variant, int zc, const StreamArgs<T> *args, const int2 *map, int nmap,
+                                  const int *active, int wpg, hipStream_t s)
+{
+    if (nmap <= 0) return hipSuccess;
+    if (variant == SV_FUSED3)
+        return zc ? launch_s3b<T, false, true>(args, map, nmap, active, wpg, s)
+                  : launch_s3b<T, false, false>(args, map, nmap, active, wpg, s);
+    if (variant == SV_FUSED3_P)
+        return zc ? launch_s3b<T, true, true>(args, map, nmap, active, wpg, s)
+                  : launch_s3b<T, true, false>(args, map, nmap, active, wpg, s);
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_stream3_batched<double>(int, int, const StreamArgs<double> *, const int2 *, int,
+                                                   const int *, int, hipStream_t);
+template hipError_t launch_stream3_batched<float>(int, int, const StreamArgs<float> *, const int2 *, int,
+                                                  const int *, int, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Tile kernels for the small coarse levels (9-point, V(2,1)).  On levels too
 // small to fill the device a streaming wave's time is its chain of row-pair

@@ -603,6 +603,70 @@ def test_batched_mixed_precision_reaches_fp64_residual(monkeypatch):
         assert rel(c(us[k]), c(u1)) <= 1e-9, k
 
 
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batched_pipelined_fp64_equals_single_problem_solves(use_graph, monkeypatch):
+    # the batch runs every problem's finest level as the pipelined pass; each
+    # problem stops at its own cycle and its iterate is rebuilt afterwards from
+    # that cycle's inputs: the single pipelined solve's iterate, bit for bit
+    monkeypatch.delenv("HIPBMG_NO_FUSE3", raising=False)
+    monkeypatch.delenv("HIPBMG_BATCH_PIPE", raising=False)
+    # media of different difficulty, so that the problems stop at cycles of
+    # every residue mod 3 (every rotation of the pass's three buffers)
+    cases = [(129, 129, lambda nx, ny: inputs.cells_lognormal(nx, ny, 1.0, seed=111)),
+             (257, 257, lambda nx, ny: inputs.cells_log10_blocks(nx, ny, 16, seed=112)),
+             (97, 65, lambda nx, ny: inputs.cells_constant(nx, ny)),
+             (129, 257, lambda nx, ny: inputs.cells_log10_blocks(nx, ny, 8, seed=113)),
+             (193, 193, lambda nx, ny: inputs.cells_two_phase_blocks(nx, ny, 16, seed=114)),
+             (65, 65, lambda nx, ny: inputs.cells_lognormal(nx, ny, 2.0, seed=115)),
+             (161, 129, lambda nx, ny: inputs.cells_log10_blocks(nx, ny, 4, seed=116))]
+    sizes = [(nx, ny) for nx, ny, _ in cases]
+    planes = [O.fv5(f(nx, ny)) for nx, ny, f in cases]
+    bs = [inputs.load_uniform(nx, ny, seed=117 + k) for k, (nx, ny) in enumerate(sizes)]
+    bh = HB.BatchHierarchy([g(p) for p in planes], use_graph=use_graph)
+    us, infos = bh.solve([g(b) for b in bs], tol=1e-10)
+    cyc = set()
+    for k in range(len(sizes)):
+        assert infos[k].rb_pipelined > 0, k
+        single = HB.Hierarchy(g(planes[k]), cluster_wg=0)   # a batch uses no stages
+        u1, info1 = single.solve(g(bs[k]), tol=1e-10)
+        assert info1.rb_pipelined > 0
+        assert infos[k].cycles == info1.cycles, (k, infos[k].cycles, info1.cycles)
+        assert torch.equal(us[k], u1), (k, rel(c(us[k]), c(u1)))
+        assert oracle_relres(planes[k], bs[k], c(us[k])) <= 1.2e-10, k
+        cyc.add(info1.cycles)
+    print("stopping cycles", sorted(cyc))
+    assert len({k % 3 for k in cyc}) == 3, sorted(cyc)
+
+
+def test_batched_pipelined_mixed_matches_single_and_unpipelined(monkeypatch):
+    monkeypatch.delenv("HIPBMG_NO_FUSE3", raising=False)
+    sizes = [(129, 129), (65, 65), (257, 257), (97, 129), (193, 97)]
+    planes, bs = batch_case(sizes, seed0=120)
+    res = {}
+    for pipe in ("1", "0"):
+        monkeypatch.setenv("HIPBMG_BATCH_PIPE", pipe)
+        bh = HB.BatchHierarchy([g(p) for p in planes], precision=HB.MIXED)
+        res[pipe] = bh.solve([g(b) for b in bs], tol=1e-10)
+        assert all((i.rb_pipelined > 0) == (pipe == "1") for i in res[pipe][1])
+        bh.close()
+    monkeypatch.delenv("HIPBMG_BATCH_PIPE")
+    us, infos = res["1"]
+    for k in range(len(sizes)):
+        rr = oracle_relres(planes[k], bs[k], c(us[k]))
+        assert rr <= 1.2e-10, (k, rr)
+        single = HB.Hierarchy(g(planes[k]), precision=HB.MIXED, cluster_wg=0)
+        u1, info1 = single.solve(g(bs[k]), tol=1e-10)
+        # the same refinement as the single pipelined solve (the inner cycles
+        # stop at the same tests), so the same iterate
+        assert infos[k].outer_steps == info1.outer_steps, k
+        print("problem %d: batched vs single %.3e, vs unpipelined batch %.3e"
+              % (k, rel(c(us[k]), c(u1)), rel(c(us[k]), c(res["0"][0][k]))))
+        assert torch.equal(us[k], u1), (k, rel(c(us[k]), c(u1)))
+        # and the unpipelined batch reaches the same answer
+        assert infos[k].outer_steps == res["0"][1][k].outer_steps, k
+        assert rel(c(us[k]), c(res["0"][0][k])) <= 1e-9, k
+
+
 def test_batched_zero_rhs_and_retirement():
     sizes = [(65, 65), (33, 33), (65, 65)]
     planes, bs = batch_case(sizes, seed0=80)
