@@ -190,6 +190,10 @@ struct hipbmg_hier {
     std::vector<int> rb;        // row-block steps per level, pre-relaxation (down) kernels
     std::vector<int> rb_up;     // row-block steps per level, interpolation (up) kernels
     std::vector<char> rc_level; // level forms r/C in its up leg (no q plane)
+    // the level's two kernels form the diagonal of its deep vertices (FP64 [0],
+    // FP32 [1]; only levels with rc_level)
+    std::vector<char> zc9[2];
+    int zc9_form = 1;           // HIPBMG_ZC9_LOAD=1: keep the stored diagonal but load it (tests)
     // waves per tile of the level's tile kernels, 0 for the streaming kernels:
     // the down leg, and the up leg of the FP64 [0] and FP32 [1] levels
     std::vector<char> tile_dn, tile_up[2];
@@ -522,6 +526,7 @@ static void model_levels(const hipbmg_hier *h, int fp32, ModelLevel *ml)
         if (ml[l].pipelined) describe(SV_FUSED3, h->rb3, ml[l].pipe);
         else ml[l].pipe = ModelKernel{0, 0, 1.0};
         ml[l].zexc = ml[l].pipelined && h->zexc[fp32 ? 1 : 0] ? 1 : 0;
+        ml[l].zc9 = rc && h->zc9_form && h->zc9[fp32 ? 1 : 0][l] ? 1 : 0;
         const int cnx = l ? h->lv[l - 1].nx : 0, cny = l ? h->lv[l - 1].ny : 0;
         const size_t bytes = fp32 ? collapse_lds_bytes<float>(A.nx, A.ny, cnx, cny)
                                   : collapse_lds_bytes<double>(A.nx, A.ny, cnx, cny);
@@ -634,13 +639,38 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
                              ny, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return bail(fail(HIPBMG_EHIP, "copy of the stencil planes failed (device pointer?)"));
     }
-    // coarse operators: interpolation weights and Galerkin products
+    // coarse operators: interpolation weights and Galerkin products.  On the
+    // large coarse levels whose up leg forms r/C from its rows, a vertex at
+    // least two vertices from the boundary has a zero row sum in exact
+    // arithmetic (the Galerkin operator of a pure-diffusion operator); where
+    // the computed diagonal agrees with the ordered sum of the connections to
+    // 1e-12 at every such vertex, that sum is stored as the diagonal before
+    // the level's own weights and Galerkin product are formed, so every later
+    // step sees one operator, and the level's streaming kernels form it
+    // instead of loading it (HIPBMG_NO_ZC9=1: keep the computed diagonal)
+    h->zc9[0].assign(L, 0);
+    h->zc9[1].assign(L, 0);
+    int no_zc9 = 0;
+    if (const char *e = std::getenv("HIPBMG_NO_ZC9")) no_zc9 = std::atoi(e);
+    if (const char *e = std::getenv("HIPBMG_ZC9_LOAD")) h->zc9_form = std::atoi(e) ? 0 : 1;
+    int *d_zflag = nullptr;
+    st = dalloc(h, &d_zflag, 1, s);
+    if (st != HIPBMG_OK) return bail(st);
     for (int l = L - 1; l >= 1; --l) {
         const LevelDev<double> &f = h->lv[l], &c = h->lv[l - 1];
         if (launch_interp_weights(f, c.nx, c.ny, f.wt, f.cpitch, f.cplane, s) != hipSuccess ||
             launch_rap(f, c, s) != hipSuccess)
             return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
                              hipGetErrorString(hipGetLastError())));
+        if (!no_zc9 && c.npt == 9 && rc_on_the_fly(h, c.nx, c.ny, false)) {
+            int ok = 0;
+            if (launch_rowsum_diag(c, d_zflag, 0, s) != hipSuccess ||
+                hipMemcpyAsync(&ok, d_zflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess ||
+                (ok && launch_rowsum_diag(c, d_zflag, 1, s) != hipSuccess))
+                return bail(fail(HIPBMG_EHIP, "row-sum diagonal setup failed"));
+            h->zc9[0][l - 1] = (char)ok;
+        }
     }
     if (dev_malloc((void **)&h->d_lv, L * sizeof(LevelDev<double>)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
@@ -659,6 +689,16 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             int cnx = l ? sx[l - 1] : 0, cny = l ? sy[l - 1] : 0;
             if (launch_demote_level(h->lv[l], h->lv32[l], cnx, cny, s) != hipSuccess)
                 return bail(fail(HIPBMG_EHIP, "demote launch failed"));
+            if (h->zc9[0][l]) {
+                // the FP32 copy's excess at the deep vertices: zero if the
+                // stored diagonal is the demotion's own sum of the connections
+                int ok = 0;
+                if (launch_zero_excess9(h->lv32[l], d_zflag, s) != hipSuccess ||
+                    hipMemcpyAsync(&ok, d_zflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return bail(fail(HIPBMG_EHIP, "zero-excess check failed"));
+                h->zc9[1][l] = (char)ok;
+            }
         }
         if (dev_malloc((void **)&h->d_lv32, L * sizeof(LevelDev<float>)) != hipSuccess)
             return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
@@ -1036,6 +1076,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             StreamArgs<T> a = base_args(A, h->rb[l]);
             a.x_in = A.x[xb];
             a.x_out = A.x[1 - xb];
+            if (v == SV_SWEEP2_R_ZX) a.zexc = h->zc9_form && h->zc9[PrecIdx<T>::v][l];
             if (last) {
                 a.q_out = A.q;
                 a.bc = Cl.b;
@@ -1097,6 +1138,7 @@ static hipError_t enqueue_vcycle(hipbmg_hier *h, const std::vector<LevelDev<T>> 
             StreamArgs<T> a = base_args(A, h->rb_up[l]);
             a.x_in = A.x[xb];
             a.x_out = A.x[1 - xb];
+            if (v == SV_INTERP_RC) a.zexc = h->zc9_form && h->zc9[PrecIdx<T>::v][l];
             if (first) {
                 a.xc = Cl.x[xres[l - 1]];
                 a.wt = A.wt;

@@ -122,6 +122,15 @@ template <typename T>
 hipError_t launch_stream3_batched(int variant, int zc, const StreamArgs<T> *args, const int2 *map, int nmap,
                                   const int *active, int wpg, hipStream_t s);
 
+// ZC9 (9-point levels whose rows at least two vertices from the boundary have
+// zero row sums): set = 0 sets *flag (device int) to 1 if every such vertex's
+// diagonal is within 1e-12 of the ordered sum of its eight connections, else
+// 0; set = 1 stores that sum as their diagonal.  The FP32 check sets *flag to
+// 1 if the edge-form excess is exactly zero there.  The streaming kernels of
+// SV_SWEEP2_R_ZX and SV_INTERP_RC take a.zexc = 1 on such a level.
+hipError_t launch_rowsum_diag(const LevelDev<double> &A, int *flag, int set, hipStream_t s);
+hipError_t launch_zero_excess9(const LevelDev<float> &A, int *flag, hipStream_t s);
+
 // Tile kernels of the small 9-point coarse levels (V(2,1)): a workgroup of nw
 // waves (4 or 8) owns a strip by tile_steps(nw, down) row-pair steps.  down:
 // two relaxations from zero, residual, r/C and restriction (the work of

@@ -91,12 +91,14 @@ double model_grid_level_us(const ModelLevel &lv, bool finest, int nu1, int nu2, 
         double bytes = n * w * (s + 3.0);                    // one pass, however many sweeps it fuses
         if (k == 1 && !finest) bytes -= n * w;               // iterate starts at zero
         if (k == nk) bytes += n * w * ((lv.rc ? 0.0 : 1.0) + 2.0 + 0.25);   // q, weights, coarse rhs
+        if (k == nk && lv.rc && lv.zc9) bytes -= n * w;                      // diagonal formed
         t += kernel_us(lv.dn, p.step_dn_us[q], p.t0_dn_us[q], bytes, bdn, p);
     }
     // up: interpolation fused with the first post-relaxation
     for (int k = 1; k <= nu2; ++k) {
         double bytes = n * w * (s + 3.0);
         if (k == 1) bytes += n * w * (0.25 + 2.0 + (lv.rc ? 0.0 : 1.0));   // coarse x, weights, q
+        if (k == 1 && lv.rc && lv.zc9) bytes -= n * w;                      // diagonal formed
         t += kernel_us(lv.up, p.step_up_us[q], p.t0_up_us[q], bytes, bup, p);
     }
     return t;

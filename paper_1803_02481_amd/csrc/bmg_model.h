@@ -36,6 +36,8 @@ struct ModelLevel {
     // the pipelined pass forms the diagonal from the connections (zero-excess
     // operator) instead of loading it
     int zexc;
+    // the r/C level's two kernels form the diagonal of its deep vertices
+    int zc9;
 };
 
 // Machine parameters.  Paper -> GPU correspondence:

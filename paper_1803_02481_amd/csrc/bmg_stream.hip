@@ -152,6 +152,28 @@ __device__ __forceinline__ T res_odd(const Row<T> &bl, const Row<T> &cu, const R
     }
 }
 
+// ZC9: on a 9-point level whose rows at least two vertices from the boundary
+// have zero row sums, the setup stored there exactly the sum of the eight
+// connections, W_p + W_e + S_p + S_n + SW_p + SW_ne + SE_p + SE_nw in this
+// order, as the diagonal (FP64), and an FP32 edge-form copy has a zero excess
+// there.  The kernels then load C only at the rows and columns next to the
+// boundary and form the FP64 diagonal of the deep vertices from the row and
+// the row above it (ab: its S, SW, SE), bitwise the stored value.
+__device__ __forceinline__ bool deep9(int j, int e, int o, int nx, int ny)
+{
+    return j >= 2 && j <= ny - 3 && e >= 2 && o <= nx - 3;
+}
+
+template <typename T>
+__device__ __forceinline__ void complete_C9(Row<T> &r, const Row<T> &ab, bool deep)
+{
+    const T we = fromR(r.W0), cne = fromR(ab.SW0), cnw = fromL(ab.SE1);
+    if (deep && !IsEdge<T>::value) {
+        r.C0 = r.W0 + r.W1 + r.S0 + ab.S0 + r.SW0 + ab.SW1 + r.SE0 + cnw;
+        r.C1 = r.W1 + we + r.S1 + ab.S1 + r.SW1 + cne + r.SE1 + ab.SE0;
+    }
+}
+
 // The next row pair's loads are issued before the current step is computed,
 // so their latency overlaps the step's arithmetic.  It costs registers (FP64
 // two-sweep kernels drop to one wave per SIMD); measured on gfx950 it is
@@ -423,7 +445,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs<T> &a, const int ti
 // second colour-by-colour sweep.  A's results are correct on fewer lanes than
 // a loaded row, so the halo is the sum of both stages' halos, and each block
 // of rows starts with three A steps and two B steps of prologue.
-template <typename T, int NPT, bool ZX, bool STOREQ = true>
+template <typename T, int NPT, bool ZX, bool STOREQ = true, bool ZC9 = false>
 __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int HA = 1 + (NPT == 9);          // lanes of A's garbage margin per side
@@ -450,7 +472,7 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
             const size_t off = (size_t)j * pitch + e;
             if (!ZX) ld2(a.x_in + off, r.x0, r.x1);
             ld2(a.b + off, r.b0, r.b1);
-            ld2(a.C + off, r.C0, r.C1);
+            if (!ZC9 || !deep9(j, e, o, nx, ny)) ld2(a.C + off, r.C0, r.C1);
             ld2(a.W + off, r.W0, r.W1);
             ld2(a.S + off, r.S0, r.S1);
             if (NPT == 9) {
@@ -476,6 +498,11 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
         if (ja + 2 <= jlast + 2) {
             load_row(N0, ja + 2);
             load_row(N1, ja + 3);
+        }
+        if (ZC9) {
+            // diagonals of rows ja-1 and ja, whose rows above are loaded
+            complete_C9(A.rm1, A.r0, deep9(ja - 1, e, o, nx, ny));
+            complete_C9(A.r0, A.rp1, deep9(ja, e, o, nx, ny));
         }
         stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
         const int jb = ja - 2;
@@ -797,6 +824,48 @@ __global__ void k_zero_excess(LevelDev<T> A, int *flag)
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+// ZC9 setup of an FP64 9-point level.  set = 0: clear *flag if a vertex at
+// least two vertices from the boundary has a diagonal further than 1e-12 of
+// itself from the ordered sum of its connections (not a zero-row-sum row);
+// set = 1: store that sum as the diagonal there.
+__global__ void k_rowsum_diag(LevelDev<double> A, int *flag, int set)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < 2 || i > A.nx - 3 || j < 2 || j > A.ny - 3) return;
+    const size_t p = (size_t)j * A.pitch + i, P = A.pitch;
+    const double rs = A.W[p] + A.W[p + 1] + A.S[p] + A.S[p + P] + A.SW[p] + A.SW[p + P + 1] + A.SE[p] +
+                      A.SE[p + P - 1];
+    if (set) A.C[p] = rs;
+    else if (!(fabs(A.C[p] - rs) <= 1e-12 * fabs(A.C[p]))) atomicAnd(flag, 0);
+}
+
+// ZC9 check of an FP32 edge-form 9-point level: clear *flag unless every
+// vertex at least two vertices from the boundary has a zero excess
+__global__ void k_zero_excess9(LevelDev<float> A, int *flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < 2 || i > A.nx - 3 || j < 2 || j > A.ny - 3) return;
+    if (A.C[(size_t)j * A.pitch + i] != 0.0f) atomicAnd(flag, 0);
+}
+
+hipError_t launch_rowsum_diag(const LevelDev<double> &A, int *flag, int set, hipStream_t s)
+{
+    if (!set) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, flag, A.npt == 9 ? 1 : 0);
+    if (A.npt == 9)
+        hipLaunchKernelGGL(k_rowsum_diag, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A, flag, set);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_excess9(const LevelDev<float> &A, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, flag, A.npt == 9 ? 1 : 0);
+    if (A.npt == 9)
+        hipLaunchKernelGGL(k_zero_excess9, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A, flag);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t zero_excess_check(const LevelDev<T> &A, int *flag, hipStream_t s)
 {
@@ -833,13 +902,13 @@ __global__ __launch_bounds__(64) void k_stream(StreamArgs<T> a)
     stream_tile<T, NPT, V>(a, tile);
 }
 
-template <typename T, int NPT, bool ZX, bool STOREQ = true>
+template <typename T, int NPT, bool ZX, bool STOREQ = true, bool ZC9 = false>
 __global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile();
     if (tile >= a.ntiles) return;
-    stream2_tile<T, NPT, ZX, STOREQ>(a, tile);
+    stream2_tile<T, NPT, ZX, STOREQ, ZC9>(a, tile);
 }
 
 // The up leg's first pass with the r/C term formed from the loaded rows
@@ -850,7 +919,7 @@ __global__ __launch_bounds__(64) void k_stream2(StreamArgs<T> a)
 // x += P x_c + r/C and one relaxation.  Rows are loaded two rows ahead of the
 // relaxation, because the r/C of an odd row needs the raw row above it.  The
 // r/C costs one lane of exact columns on each side.
-template <typename T, int NPT>
+template <typename T, int NPT, bool ZC9 = false>
 __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int tile)
 {
     constexpr int HL = 1 + halo_left(NPT, 0), HR = 1 + halo_right(NPT, 0), OWN = 64 - HL - HR;
@@ -874,7 +943,7 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
             const size_t off = (size_t)j * pitch + e;
             ld2(a.x_in + off, r.x0, r.x1);
             ld2(a.b + off, r.b0, r.b1);
-            ld2(a.C + off, r.C0, r.C1);
+            if (!ZC9 || !deep9(j, e, o, nx, ny)) ld2(a.C + off, r.C0, r.C1);
             ld2(a.W + off, r.W0, r.W1);
             ld2(a.S + off, r.S0, r.S1);
             if (NPT == 9) {
@@ -941,14 +1010,23 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
         load_raw(Rn, jp0);
         load_raw(N1, jp0 + 1);
         load_raw(N2, jp0 + 2);
+        if (ZC9) {
+            complete_C9(Ra, Rm1, deep9(jp0 - 2, e, o, nx, ny));
+            complete_C9(Rm1, Rn, deep9(jp0 - 1, e, o, nx, ny));
+        }
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
     for (int jp = jp0; jp <= jlast; jp += 2) {
-        const Row<T> R1 = N1, R2 = N2;
+        Row<T> R1 = N1, R2 = N2;
         if (jp + 2 <= jlast) {
             load_raw(N1, jp + 3);
             load_raw(N2, jp + 4);
+        }
+        if (ZC9) {
+            // diagonals of rows jp and jp+1, whose rows above are loaded
+            complete_C9(Rn, R1, deep9(jp, e, o, nx, ny));
+            complete_C9(R1, R2, deep9(jp + 1, e, o, nx, ny));
         }
         const T q1_even_row = rc_odd(Rm1, Rn, R1);
         const T q0_odd_row = rc_even(Rn, R1, R2), q1_odd_row = rc_odd(Rn, R1, R2);
@@ -963,13 +1041,13 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
     }
 }
 
-template <typename T, int NPT>
+template <typename T, int NPT, bool ZC9 = false>
 __global__ __launch_bounds__(64) void k_interp_rc(StreamArgs<T> a)
 {
     if (a.active && *a.active == 0) return;
     const int tile = xcd_tile();
     if (tile >= a.ntiles) return;
-    interp_rc_tile<T, NPT>(a, tile);
+    interp_rc_tile<T, NPT, ZC9>(a, tile);
 }
 
 // Batched form: one launch covers the same stage of many problems.  map[w] =
@@ -1055,8 +1133,15 @@ static hipError_t launch_v(int variant, const StreamArgs<T> &a, int grid, hipStr
     case SV_SWEEP2_RQ: hipLaunchKernelGGL((k_stream2<T, NPT, false>), g, b, 0, s, a); break;
     case SV_SWEEP2_RQ_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true>), g, b, 0, s, a); break;
     case SV_SWEEP2_R: hipLaunchKernelGGL((k_stream2<T, NPT, false, false>), g, b, 0, s, a); break;
-    case SV_SWEEP2_R_ZX: hipLaunchKernelGGL((k_stream2<T, NPT, true, false>), g, b, 0, s, a); break;
-    case SV_INTERP_RC: hipLaunchKernelGGL((k_interp_rc<T, NPT>), g, b, 0, s, a); break;
+    case SV_SWEEP2_R_ZX:
+        // a.zexc on a 9-point level: the deep vertices' diagonal is formed (ZC9)
+        if (NPT == 9 && a.zexc) hipLaunchKernelGGL((k_stream2<T, NPT, true, false, NPT == 9>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_stream2<T, NPT, true, false>), g, b, 0, s, a);
+        break;
+    case SV_INTERP_RC:
+        if (NPT == 9 && a.zexc) hipLaunchKernelGGL((k_interp_rc<T, NPT, NPT == 9>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_interp_rc<T, NPT>), g, b, 0, s, a);
+        break;
     case SV_FUSED3:
     case SV_FUSED3_P:
     case SV_FUSED3_PN:

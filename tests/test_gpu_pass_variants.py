@@ -2,8 +2,9 @@
 the up leg forming r/C from the rows it loads instead of reading a stored
 plane, the last cycle of a capped solve run as the pipelined pass's first
 stage alone, the pipelined pass forming a zero-excess operator's diagonal
-instead of loading it, and the tile kernels of the small coarse levels.  Each
-is compared bitwise with the path it replaces."""
+instead of loading it, the tile kernels of the small coarse levels, and the
+large coarse levels forming the diagonal of their deep vertices.  Each is
+compared bitwise with the path it replaces."""
 import numpy as np
 import pytest
 import torch
@@ -174,6 +175,46 @@ def test_tile_kernels_are_bitwise_the_streaming_kernels(nx, ny, cells, nw, preci
         assert torch.equal(u1, u0), float((u1 - u0).abs().max())
     # and a whole solve to the tolerance, with the default choice of levels,
     # meets it by the host's residual
+    u, info = run(planes, b, 500, tol=1e-10, precision=precision)
+    r = H.residual_from_planes(planes, b, c(u))
+    assert np.linalg.norm(r) <= 1.2e-10 * np.linalg.norm(b[1:-1, 1:-1])
+
+
+@pytest.mark.parametrize("precision", [HB.FP64, HB.MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny", [(257, 257), (385, 193)])
+def test_coarse_deep_diagonal_formed_is_bitwise_the_loaded_one(nx, ny, precision, monkeypatch):
+    # every coarse level on the r/C kernels (HIPBMG_RC_MIN lowered); their
+    # deep vertices' diagonal is stored as the ordered sum of the connections
+    # at setup, and the kernels form it instead of loading it: the same bits
+    # as loading it from the same stored operator
+    planes = O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=71))
+    b = inputs.load_uniform(nx, ny, seed=72)
+    monkeypatch.setenv("HIPBMG_RC_MIN", "1000")
+    for pipelined in ("0", "1"):
+        monkeypatch.setenv("HIPBMG_NO_FUSE3", "0" if pipelined == "1" else "1")
+        monkeypatch.setenv("HIPBMG_ZC9_LOAD", "1")
+        u0, i0 = run(planes, b, 6, precision=precision, collapse_level=1)
+        monkeypatch.delenv("HIPBMG_ZC9_LOAD")
+        u1, i1 = run(planes, b, 6, precision=precision, collapse_level=1)
+        assert list(i1.history()) == list(i0.history())
+        assert torch.equal(u1, u0), float((u1 - u0).abs().max())
+    # the stored diagonal: the ordered sum of the eight connections at the
+    # deep vertices of every such level, within rounding of the oracle's
+    # Galerkin diagonal everywhere
+    h = HB.Hierarchy(g(planes), collapse_level=1)
+    ora = O.Hierarchy(planes)
+    for l in range(1, h.L - 1):
+        C, W, S, SW, SE = (c(t) for t in h.stencil(l))
+        ny_, nx_ = C.shape
+        if nx_ * ny_ < 1000:
+            continue
+        rs = (W[2:-2, 2:-2] + W[2:-2, 3:-1] + S[2:-2, 2:-2] + S[3:-1, 2:-2] + SW[2:-2, 2:-2] + SW[3:-1, 3:-1]
+              + SE[2:-2, 2:-2] + SE[3:-1, 1:-3])
+        assert np.array_equal(C[2:-2, 2:-2], rs), l
+        Co = ora.stencil(l)[:, :, 1, 1]
+        assert np.all(np.abs(C[1:-1, 1:-1] - Co[1:-1, 1:-1]) <= 1e-12 * np.abs(Co[1:-1, 1:-1])), l
+    # a whole solve meets the tolerance by the host's residual
+    monkeypatch.delenv("HIPBMG_NO_FUSE3")
     u, info = run(planes, b, 500, tol=1e-10, precision=precision)
     r = H.residual_from_planes(planes, b, c(u))
     assert np.linalg.norm(r) <= 1.2e-10 * np.linalg.norm(b[1:-1, 1:-1])
