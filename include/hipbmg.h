@@ -81,8 +81,10 @@ typedef struct {
     int residual_correction; /* 1: add r/C at fine-only vertices after interpolation (sec 3) */
     int max_cycles;          /* FP64: V-cycles; mixed: total inner cycles cap, default 500  */
     int precision;           /* hipbmg_precision, default HIPBMG_FP64                       */
-    int inner_max_cycles;    /* mixed: FP32 cycles per refinement step, default 12          */
-    double inner_tol;        /* mixed: inner relative residual target, default 1e-5         */
+    int inner_max_cycles;    /* mixed: FP32 cycles per refinement step, default 32          */
+    double inner_tol;        /* mixed: inner relative residual target, default 1e-4; a step */
+                             /* stops its inner solve already at tol / (2 relres) when that */
+                             /* is looser (what the outer tolerance still needs)            */
     int use_graph;           /* 1: replay the V-cycle as a captured hipGraph, default 1     */
     int cluster_wg;          /* agglomeration stages on several workgroups between the      */
                              /* grid-wide kernels and the collapsed workgroup (section 4):  */

@@ -903,13 +903,14 @@ int oracle32_inner(void *hv, const float *r, float *e, int cycles, double rnorm,
 
 /* Mixed precision: FP64 iterative refinement around FP32 inner solves.  Each
  * step forms the outer residual r = b - A u in FP64 and its relative norm
- * (hist[step]); it stops when that is <= tol or when the cycle budget is
+ * rel (hist[step]); it stops when that is <= tol or when the cycle budget is
  * spent, else demotes r to float, runs an inner solve of at most
- * min(inner_max, max_cycles - cycles done) cycles to inner_tol and adds the
- * widened correction to u.  Returns the FP32 cycles run; *steps is the number
+ * min(inner_max, max_cycles - cycles done) cycles to an inner relative
+ * residual of max(inner_tol, tol / (2 rel)) (inner_tol alone if !adapt) and
+ * adds the widened correction to u.  Returns the FP32 cycles run; *steps is the number
  * of inner solves. */
 int oracle_solve_mixed(void *hv, const double *bin, double *u, double tol, int max_cycles, int inner_max,
-                       double inner_tol, double *hist, int *steps)
+                       double inner_tol, int adapt, double *hist, int *steps)
 {
     ohier *h = with32(hv);
     olevel *f = &h->lev[h->L - 1];
@@ -934,7 +935,12 @@ int oracle_solve_mixed(void *hv, const double *bin, double *u, double tol, int m
             if (rel <= tol || cycles >= max_cycles) break;
             for (size_t k = 0; k < n; ++k) r32[k] = (float)r[k];
             int cap = inner_max < max_cycles - cycles ? inner_max : max_cycles - cycles;
-            cycles += oracle32_inner(h, r32, e32, cap, rn, inner_tol, NULL);
+            /* the inner solve stops at inner_tol, or (adapt) as soon as its
+             * residual is below half of what the outer tolerance still asks
+             * for (tol / rel), whichever comes first */
+            double itol = 0.5 * tol / rel;
+            if (!adapt || itol < inner_tol) itol = inner_tol;
+            cycles += oracle32_inner(h, r32, e32, cap, rn, itol, NULL);
             for (int j = 1; j <= f->ny - 2; ++j)
                 for (int i = 1; i <= f->nx - 2; ++i) u[(size_t)j * f->nx + i] += (double)e32[(size_t)j * f->nx + i];
             ++st;

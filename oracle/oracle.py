@@ -75,7 +75,7 @@ def lib():
         L.oracle32_inner.argtypes = [ctypes.c_void_p, F, F, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         L.oracle32_inner.restype = ctypes.c_int
         L.oracle_solve_mixed.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int)]
+                                         ctypes.c_double, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
         L.oracle_solve_mixed.restype = ctypes.c_int
         I = ctypes.c_int
         IP = ctypes.POINTER(ctypes.c_int)
@@ -299,17 +299,18 @@ class Hierarchy:
         k = lib().oracle32_inner(self._h, _f(r), _f(e), cycles, float(rnorm), float(inner_tol), _p(hist))
         return e, hist[:k]
 
-    def solve_mixed(self, b, u0=None, tol=1e-10, max_cycles=500, inner_max=12, inner_tol=1e-5):
+    def solve_mixed(self, b, u0=None, tol=1e-10, max_cycles=500, inner_max=32, inner_tol=1e-4, adapt=True):
         """FP64 iterative refinement around FP32 inner solves: returns
         (u, outer relative residual before each step and at the end, FP32
-        cycles run, inner solves)."""
+        cycles run, inner solves).  Each inner solve stops at inner_tol or,
+        with adapt, already at tol / (2 outer relres) when that is looser."""
         self.demote()
         b = np.ascontiguousarray(b, dtype=np.float64)
         u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64, order="C")
         hist = np.zeros(max_cycles + 2)
         steps = ctypes.c_int(0)
-        cyc = lib().oracle_solve_mixed(self._h, _p(b), _p(u), tol, max_cycles, inner_max, inner_tol, _p(hist),
-                                       ctypes.byref(steps))
+        cyc = lib().oracle_solve_mixed(self._h, _p(b), _p(u), tol, max_cycles, inner_max, inner_tol,
+                                       1 if adapt else 0, _p(hist), ctypes.byref(steps))
         return u, hist[:steps.value + 1], cyc, steps.value
 
 

@@ -768,7 +768,7 @@ __global__ __launch_bounds__(256) void k_finalize_batched(const double *__restri
                                                           const double *__restrict__ denom,
                                                           double *__restrict__ out,
                                                           int *__restrict__ active, double tol,
-                                                          const double *__restrict__ tol_dev)
+                                                          const double *__restrict__ tol_dev, int tol_stride)
 {
     __shared__ double sh[256];
     const int p = blockIdx.x;
@@ -785,17 +785,17 @@ __global__ __launch_bounds__(256) void k_finalize_batched(const double *__restri
     if (threadIdx.x == 0) {
         const double v = denom ? sqrt(sh[0]) / denom[p] : sqrt(sh[0]);
         out[p] = v;
-        const double t = tol_dev ? tol_dev[0] : tol;
+        const double t = tol_dev ? tol_dev[(size_t)tol_stride * p] : tol;
         if (active && (!(v > t) || !isfinite(v))) active[p] = 0;
     }
 }
 
 hipError_t launch_finalize_batched(const double *partials, const int *off, const int *cnt,
                                    const double *denom, double *out, int *active, double tol,
-                                   const double *tol_dev, int nprob, hipStream_t s)
+                                   const double *tol_dev, int nprob, hipStream_t s, int tol_stride)
 {
     hipLaunchKernelGGL(k_finalize_batched, dim3(nprob), dim3(256), 0, s, partials, off, cnt, denom, out,
-                       active, tol, tol_dev);
+                       active, tol, tol_dev, tol_stride);
     return hipGetLastError();
 }
 

@@ -147,8 +147,8 @@ extern "C" void hipbmg_default_params(hipbmg_params *p)
     p->residual_correction = 1;
     p->max_cycles = 500;
     p->precision = HIPBMG_FP64;
-    p->inner_max_cycles = 12;
-    p->inner_tol = 1e-5;
+    p->inner_max_cycles = 32;
+    p->inner_tol = 1e-4;
     p->use_graph = 1;
     p->cluster_wg = -1;
     p->cluster_top = -1;
@@ -194,6 +194,7 @@ struct hipbmg_hier {
     // FP32 [1]; only levels with rc_level)
     std::vector<char> zc9[2];
     int zc9_form = 1;           // HIPBMG_ZC9_LOAD=1: keep the stored diagonal but load it (tests)
+    int inner_adapt = 1;        // HIPBMG_INNER_ADAPT=0: every inner solve to inner_tol
     // waves per tile of the level's tile kernels, 0 for the streaming kernels:
     // the down leg, and the up leg of the FP64 [0] and FP32 [1] levels
     std::vector<char> tile_dn, tile_up[2];
@@ -653,6 +654,7 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     int no_zc9 = 0;
     if (const char *e = std::getenv("HIPBMG_NO_ZC9")) no_zc9 = std::atoi(e);
     if (const char *e = std::getenv("HIPBMG_ZC9_LOAD")) h->zc9_form = std::atoi(e) ? 0 : 1;
+    if (const char *e = std::getenv("HIPBMG_INNER_ADAPT")) h->inner_adapt = std::atoi(e);
     int *d_zflag = nullptr;
     st = dalloc(h, &d_zflag, 1, s);
     if (st != HIPBMG_OK) return bail(st);
@@ -1411,12 +1413,15 @@ static hipbmg_status solve_mixed(hipbmg_hier *h, double tol, hipStream_t s, hipb
         }
         if (cycles >= h->prm.max_cycles) break;
         ++steps;
-        // inner FP32 solve of A e = r from e = 0, relative to ||r|| (on the device)
+        // inner FP32 solve of A e = r from e = 0, relative to ||r|| (on the
+        // device), to inner_tol or to what the outer tolerance still needs
+        // (half of tol / relres), whichever is looser
         const int cap = std::min(h->prm.inner_max_cycles, h->prm.max_cycles - cycles);
         const float *e32 = nullptr;
         int done = 0;
-        STCHK(run_cycles<float>(h, h->lv32, h->d_lv32, true, cap, h->prm.inner_tol, h->d_scal + 2, s, &e32,
-                                &done));
+        double itol = h->prm.inner_tol;
+        if (h->inner_adapt) itol = std::max(itol, 0.5 * tol / rel);
+        STCHK(run_cycles<float>(h, h->lv32, h->d_lv32, true, cap, itol, h->d_scal + 2, s, &e32, &done));
         cycles += done;
         HIPCHK(launch_ir_update(F.x[0], F.pitch, e32, F32.pitch, F.nx, F.ny, s));
     }
@@ -2282,6 +2287,7 @@ struct hipbmg_batch {
     double *h_relres = nullptr;
     int *h_active = nullptr, *h_count = nullptr;
     double *d_tol = nullptr, *h_tol = nullptr;   // [0] the solve's tolerance, [1] the inner FP32 tolerance
+    double *d_itol = nullptr, *h_itol = nullptr; // each problem's inner FP32 tolerance of the current step
     int max_nx = 0, max_ny = 0, fine_npt = 5;
     BPlan plan64[2], plan32[2][2];
     int rb_cap = 0;                           // row blocks of the batched launches (0: per-level rule)
@@ -2321,6 +2327,7 @@ struct hipbmg_batch {
         if (h_active) (void)hipHostFree(h_active);
         if (h_count) (void)hipHostFree(h_count);
         if (h_tol) (void)hipHostFree(h_tol);
+        if (h_itol) (void)hipHostFree(h_itol);
         for (hipbmg_hier *h : hs) delete h;
     }
 };
@@ -2597,7 +2604,7 @@ static hipError_t run_plan_launches(hipbmg_batch *B, BPlan &plan, const int *act
 // retirement; replayed from a captured graph when use_graph is set
 template <typename T>
 static hipbmg_status batch_cycle(hipbmg_batch *B, BPlan &plan, int *active, const double *denom, double *out,
-                                 const double *tol_dev, hipStream_t s)
+                                 const double *tol_dev, hipStream_t s, int tol_stride = 0)
 {
     // the tolerance is read from device memory when the test runs: a replayed
     // graph then applies the tolerance of the current solve, not the one of
@@ -2606,7 +2613,7 @@ static hipbmg_status batch_cycle(hipbmg_batch *B, BPlan &plan, int *active, cons
         hipError_t e = run_plan_launches<T>(B, plan, active, s);
         if (e != hipSuccess) return e;
         e = launch_finalize_batched(B->d_partials, B->d_poff, B->d_pcnt, denom, out, active, 0.0, tol_dev, B->n,
-                                    s);
+                                    s, tol_stride);
         if (e != hipSuccess) return e;
         return launch_count_active(active, B->n, B->d_count, s);
     };
@@ -2842,6 +2849,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     chk(balloc(B, &B->d_active2, nprob, s));
     chk(balloc(B, &B->d_count, 1, s));
     chk(balloc(B, &B->d_tol, 2, s));
+    chk(balloc(B, &B->d_itol, nprob, s));
     chk(balloc(B, &B->d_relres, nprob, s));
     chk(balloc(B, &B->d_bnorm, nprob, s));
     chk(balloc(B, &B->d_rnorm, nprob, s));
@@ -2893,7 +2901,8 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     if (hipHostMalloc(&B->h_relres, nprob * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&B->h_active, nprob * sizeof(int)) != hipSuccess ||
         hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess ||
-        hipHostMalloc(&B->h_tol, 2 * sizeof(double)) != hipSuccess)
+        hipHostMalloc(&B->h_tol, 2 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&B->h_itol, nprob * sizeof(double)) != hipSuccess)
         return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
     // the finest level pipelined across cycles when every problem's is (as
     // hipbmg_setup decided it: 5-point, V(2,1), not collapsed); its pass forms
@@ -3129,7 +3138,14 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                     else ++steps[p];
                 }
             if (B->h_count[0] == 0 || total >= B->prm.max_cycles) break;
-            // inner FP32 solves of A e = r for the active problems
+            // inner FP32 solves of A e = r for the active problems, each to
+            // inner_tol or to what its outer tolerance still needs (half of
+            // tol / relres), whichever is looser
+            const bool adapt = B->hs[0]->inner_adapt != 0;
+            for (int p = 0; p < n; ++p)
+                B->h_itol[p] = adapt && act[p] && rel[p] > 0.0 ? std::max(B->prm.inner_tol, 0.5 * tol / rel[p])
+                                                               : B->prm.inner_tol;
+            HIPCHK(hipMemcpyAsync(B->d_itol, B->h_itol, n * sizeof(double), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(B->d_active2, B->d_active, n * sizeof(int), hipMemcpyDeviceToDevice, s));
             if (B->pipe) {
                 // pipelined finest level: each problem's inner solve stops at
@@ -3138,7 +3154,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 int i = 1;
                 for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
                     BPlan &plan = k == 0 ? B->pipe32[3] : B->pipe32[i];
-                    STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_tol + 1, s));
+                    STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_itol, s, 1));
                     i = plan.end_cur;
                     ++total;
                     HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -3164,7 +3180,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             int icur = 0;
             for (int k = 0; k < B->prm.inner_max_cycles && total < B->prm.max_cycles; ++k) {
                 BPlan &plan = k == 0 ? B->plan32[1][0] : B->plan32[0][icur];
-                STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_tol + 1, s));
+                STCHK(batch_cycle<float>(B, plan, B->d_active2, B->d_rnorm, B->d_irel, B->d_itol, s, 1));
                 icur = plan.end_cur;
                 ++total;
                 HIPCHK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, s));

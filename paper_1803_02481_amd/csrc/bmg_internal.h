@@ -220,11 +220,12 @@ hipError_t launch_sumsq_batched(const double *const *v, const int4 *dims, int np
                                 int nparts, hipStream_t s);
 // out[p] = sqrt(sum of problem p's partials) (/ denom[p]); an active problem
 // whose value is <= the tolerance (or not finite) is retired.  The tolerance
-// is tol_dev[0] when tol_dev is not null (read when the kernel runs, so a
-// captured graph sees the value written before each replay), else tol.
+// is tol_dev[tol_stride * p] when tol_dev is not null (read when the kernel
+// runs, so a captured graph sees the values written before each replay; one
+// for all problems with stride 0, one per problem with stride 1), else tol.
 hipError_t launch_finalize_batched(const double *partials, const int *off, const int *cnt,
                                    const double *denom, double *out, int *active, double tol,
-                                   const double *tol_dev, int nprob, hipStream_t s);
+                                   const double *tol_dev, int nprob, hipStream_t s, int tol_stride = 0);
 hipError_t launch_count_active(const int *active, int n, int *count, hipStream_t s);
 
 // Sum of squares of interior entries of a pitched field -> partials.

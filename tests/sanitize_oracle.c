@@ -37,7 +37,7 @@ void oracle32_interp_correct(void *h, int l, float *x, const float *r, const flo
 void oracle32_vcycle(void *h, const float *b, float *x);
 int oracle32_inner(void *h, const float *r, float *e, int cycles, double rnorm, double inner_tol, double *hist);
 int oracle_solve_mixed(void *h, const double *b, double *u, double tol, int max_cycles, int inner_max,
-                       double inner_tol, double *hist, int *steps);
+                       double inner_tol, int adapt, double *hist, int *steps);
 /* 3D oracle */
 void oracle3_fv7(int nx, int ny, int nz, const double *cellD, double *C, double *W, double *S, double *B);
 void *oracle3_setup(int nx, int ny, int nz, int npt, const double *planes, int coarsest_n, int nu1, int nu2,
@@ -129,7 +129,7 @@ static void exercise2(void *h, int nx, int ny)
     acc(u, n);
     int steps = 0;
     memset(u, 0, n * sizeof(double));
-    int cyc32 = oracle_solve_mixed(h, b, u, 1e-10, 200, 12, 1e-5, hist, &steps);
+    int cyc32 = oracle_solve_mixed(h, b, u, 1e-10, 200, 32, 1e-4, 1, hist, &steps);
     float *r32 = vec32(n), *e32 = calloc(n, sizeof(float));
     double ih[4];
     oracle32_inner(h, r32, e32, 4, 1.0, 0.0, ih);

@@ -272,7 +272,7 @@ def test_fp32_inner_solve_matches_oracle(nx, ny, npt, seed):
 
 
 @pytest.mark.parametrize("kind,n,seed", [("blocks", 257, 1), ("checkerboard", 257, 3), ("lognormal", 193, 7)])
-def test_mixed_solve_matches_oracle_refinement(kind, n, seed):
+def test_mixed_solve_matches_oracle_refinement(kind, n, seed, monkeypatch):
     if kind == "blocks":
         D = inputs.cells_log10_blocks(n, n, 16, seed=seed)
     elif kind == "checkerboard":
@@ -282,9 +282,13 @@ def test_mixed_solve_matches_oracle_refinement(kind, n, seed):
     planes = O.fv5(D)
     b = inputs.load_uniform(n, n, seed=seed + 1)
     ora = O.Hierarchy(planes)
-    u_ref, h_ref, cyc_ref, steps_ref = ora.solve_mixed(b, tol=1e-10)
-    hier = mixed(planes)
+    # the refinement with a fixed inner tolerance: the inner solves stop at
+    # 1e-4 or 12 cycles on both sides, so the two take the same steps
+    u_ref, h_ref, cyc_ref, steps_ref = ora.solve_mixed(b, tol=1e-10, inner_max=12, adapt=False)
+    monkeypatch.setenv("HIPBMG_INNER_ADAPT", "0")
+    hier = mixed(planes, inner_max_cycles=12)
     u, info = hier.solve(g(b), tol=1e-10)
+    monkeypatch.delenv("HIPBMG_INNER_ADAPT")
     # the outer residual before each step and after the last
     hist = np.array(info.relres_hist[: info.outer_steps + 1])
     # the same refinement: as many steps and FP32 cycles as the oracle's
@@ -301,6 +305,19 @@ def test_mixed_solve_matches_oracle_refinement(kind, n, seed):
     assert rr <= 1.2e-10, rr
     print("mixed %s: steps %d cycles %d, outer history gpu %s oracle %s"
           % (kind, steps_ref, cyc_ref, ["%.3e" % v for v in hist], ["%.3e" % v for v in h_ref]))
+    # the default refinement (32-cycle cap, inner solves stopped as soon as
+    # the outer tolerance is within reach): the stopping tolerance of a step
+    # depends on the outer residual, which FP32 rounding moves by a few per
+    # cent, so an inner solve may stop a cycle earlier or later than the
+    # oracle's; the steps agree within one, the cycles within one per step
+    u_ref, h_ref, cyc_ref, steps_ref = ora.solve_mixed(b, tol=1e-10)
+    u, info = mixed(planes).solve(g(b), tol=1e-10)
+    print("mixed %s, default refinement: gpu %d steps %d cycles, oracle %d steps %d cycles"
+          % (kind, info.outer_steps, info.cycles, steps_ref, cyc_ref))
+    assert abs(info.outer_steps - steps_ref) <= 1
+    assert abs(info.cycles - cyc_ref) <= max(info.outer_steps, steps_ref)
+    rr = np.linalg.norm(bi - A @ H.to_interior(c(u))) / np.linalg.norm(bi)
+    assert rr <= 1.2e-10, rr
 
 
 def test_fp32_entry_points_need_a_mixed_handle():

@@ -39,7 +39,10 @@ def run(planes, b, cycles, tol=1e-30, **prm):
 def test_up_leg_r_over_c_formed_from_rows_is_bitwise_the_stored_one(nx, ny, precision, monkeypatch):
     # the up leg's r/C from the loaded pre-relaxed iterate (no q plane) on every
     # coarse level, against the stored q on every level: the same expressions
-    # on the same values
+    # on the same values.  The computed diagonal is kept on every level (an r/C
+    # level would otherwise store its deep vertices' diagonal as the sum of its
+    # connections, a different operator at the rounding level)
+    monkeypatch.setenv("HIPBMG_NO_ZC9", "1")
     planes = O.fv5(inputs.cells_log10_blocks(nx, ny, 16, seed=60))
     b = inputs.load_uniform(nx, ny, seed=61)
     res = {}
@@ -62,8 +65,9 @@ def test_last_cycle_pass_is_bitwise_the_rebuild(n, monkeypatch):
     out = {}
     for name, flag in (("rebuild", "1"), ("last_pass", "0")):
         monkeypatch.setenv("HIPBMG_NO_LAST_PASS", flag)
-        # mixed: every inner FP32 solve stops at its cycle cap
-        out[(name, "mixed")] = run(planes, b, 500, tol=1e-10, precision=HB.MIXED)
+        # mixed: the inner FP32 solves stop at a cycle cap of 8 (all but
+        # possibly the last, which may reach its looser tolerance first)
+        out[(name, "mixed")] = run(planes, b, 500, tol=1e-10, precision=HB.MIXED, inner_max_cycles=8)
         # FP64 capped before the tolerance
         out[(name, "fp64")] = run(planes, b, 5, tol=1e-30)
     for prec in ("mixed", "fp64"):

@@ -219,10 +219,11 @@ def test_mixed_solve_reaches_the_fp64_answer(kind):
     bi = H.to_interior(b)
     rel = np.linalg.norm(bi - A @ H.to_interior(u)) / np.linalg.norm(bi)
     assert rel <= 1e-10 and hist[-1] <= 1e-10 and steps == len(hist) - 1
-    # each refinement step cuts the FP64 residual by at least 1e-2 (inner
-    # solves stop at 1e-5 relative; the FP32 operator is a close model of the
-    # FP64 one because of the edge form)
-    assert np.all(hist[1:] / hist[:-1] <= 1e-2), hist
+    # each refinement step cuts the FP64 residual by at least 1e-2 or reaches
+    # the tolerance (inner solves stop at 1e-4 relative, or at tol / (2 rel)
+    # when that is looser; the FP32 operator is a close model of the FP64 one
+    # because of the edge form)
+    assert np.all(hist[1:] <= np.maximum(1e-2 * hist[:-1], 1e-10)), hist
     # the answer is the direct solution to the conditioning of the residual
     ud = spla.spsolve(A.tocsc(), bi)
     assert np.abs(H.to_interior(u) - ud).max() <= 1e-6 * np.abs(ud).max()
