@@ -596,9 +596,11 @@ def main():
         torch.cuda.synchronize()
         pr3 = h3.profile_read()
         h3.profile(False)
-        ms_r, n_r = pr3["relax_colour"]
+        ms_r, n_r, b_r = pr3["relax_colour"]
         sweep_s = 4 * ms_r / n_r / 1e3
-        bytes_sweep = 56.0 * m3 ** 3   # x read+written, b, C, W, S, B per vertex
+        # x read+written, b, W, S, B per vertex, and C unless the diagonal is
+        # formed from the connections (the library counts what it moves)
+        bytes_sweep = 4 * b_r
         ach3 = bytes_sweep / sweep_s / 1e9
         # each forced collapse level l* (levels 0..l* in one workgroup) against
         # the model's prediction; the largest levels are left out (seconds per solve)

@@ -128,12 +128,19 @@ hipbmg_status hipbmg3d_op_coarse_solve(hipbmg3d_handle h, const double *b, doubl
 /* Kernel timing of the solve phase: with enable = 1 every later solve
  * brackets its finest-level relaxation, residual, restriction and
  * interpolation launches with HIP events and accumulates their durations;
- * profile_read returns (ms, launches) for kernel class k: 0 relaxation
- * colours of the finest level, 1 finest residual (with or without the norm),
- * 2 finest-to-next restriction, 3 next-to-finest interpolation, 4 everything
- * below the finest level. */
+ * profile_read returns, for kernel class k (0 relaxation colours of the
+ * finest level, 1 finest residual, with or without the norm, 2
+ * finest-to-next restriction, 3 next-to-finest interpolation, 4 everything
+ * below the finest level), the summed duration in ms, the number of launches
+ * and the mean algorithmic bytes of one launch (FP64 values read and written
+ * once each; 0 for class 4).  A 7-point finest level whose every interior
+ * diagonal is bitwise the sum of its six connections (finite volumes of pure
+ * diffusion, hipbmg3d_fv7_from_cells) has that sum formed in its relaxation
+ * and residual kernels instead of the C plane loaded, which shows as 8 bytes
+ * per vertex fewer in classes 0 and 1.  Any output pointer may be NULL. */
 hipbmg_status hipbmg3d_profile(hipbmg3d_handle h, int enable);
-hipbmg_status hipbmg3d_profile_read(hipbmg3d_handle h, int k, double *ms_host, long long *launches_host);
+hipbmg_status hipbmg3d_profile_read(hipbmg3d_handle h, int k, double *ms_host, long long *launches_host,
+                                    double *bytes_per_launch_host);
 
 #ifdef __cplusplus
 }

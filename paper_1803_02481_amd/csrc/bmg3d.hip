@@ -444,6 +444,7 @@ struct LArgs {
     double *partials;
     int rescorr;
     double *xcz;       // restriction: the coarse iterate, cleared alongside
+    int zc;            // 7-point level whose diagonal is the sum of its connections
 };
 
 // index of the neighbour at (DX,DY,DZ) of thread t of octant O
@@ -464,9 +465,12 @@ __device__ __forceinline__ double ldc(const double *p)
 }
 
 // sum_q A(p,q) x_q over the whole stencil of vertex t of octant O (NT: the
-// 7-point coefficients as nontemporal loads)
-template <int NPT, int O, bool NT = false>
-__device__ __forceinline__ double apply_at(const Oct &g, const double *st, const double *x, long long t)
+// 7-point coefficients as nontemporal loads; ZC: the 7-point diagonal formed
+// as W_p + W_e + S_p + S_n + B_p + B_t in this order instead of loaded, which
+// the setup checked is bitwise the stored one; diag receives the diagonal)
+template <int NPT, int O, bool NT = false, bool ZC = false>
+__device__ __forceinline__ double apply_at(const Oct &g, const double *st, const double *x, long long t,
+                                           double *diag = nullptr)
 {
     const long long F = g.field;
     const long long v = O * g.oct + t;
@@ -478,8 +482,10 @@ __device__ __forceinline__ double apply_at(const Oct &g, const double *st, const
         const long long xw = nbr<O, -1, 0, 0>(g, t), xe = nbr<O, 1, 0, 0>(g, t);
         const long long ys = nbr<O, 0, -1, 0>(g, t), yn = nbr<O, 0, 1, 0>(g, t);
         const long long zb = nbr<O, 0, 0, -1>(g, t), zt = nbr<O, 0, 0, 1>(g, t);
-        const double cv = ldc<NT>(C + v), wv = ldc<NT>(W + v), we = ldc<NT>(W + xe), sv = ldc<NT>(S + v),
-                     sn = ldc<NT>(S + yn), bv = ldc<NT>(B + v), bt = ldc<NT>(B + zt);
+        const double wv = ldc<NT>(W + v), we = ldc<NT>(W + xe), sv = ldc<NT>(S + v), sn = ldc<NT>(S + yn),
+                     bv = ldc<NT>(B + v), bt = ldc<NT>(B + zt);
+        const double cv = ZC ? wv + we + sv + sn + bv + bt : ldc<NT>(C + v);
+        if (diag) *diag = cv;
         return cv * x[v] - wv * x[xw] - we * x[xe] - sv * x[ys] - sn * x[yn] - bv * x[zb] - bt * x[zt];
     } else {
         double s = ldc<NT>(st + v) * x[v];
@@ -511,12 +517,18 @@ __device__ __forceinline__ bool thread_vertex(const Oct &g, long long t, int &i,
 }
 
 // x_p += (b_p - (A x)_p) / A_pp at vertex t of octant O
-template <int NPT, int O>
+template <int NPT, int O, bool ZC = false>
 __device__ __forceinline__ void gs_point(const LArgs &a, long long t)
 {
     int i, j, k;
     if (!thread_vertex<O>(a.g, t, i, j, k)) return;
     const long long v = O * a.g.oct + t;
+    if (ZC && NPT == 7) {
+        double d;
+        const double s = apply_at<NPT, O, true, true>(a.g, a.st, a.x, t, &d);
+        a.x[v] += (a.b[v] - s) / d;
+        return;
+    }
     const double s = apply_at<NPT, O, true>(a.g, a.st, a.x, t);
     a.x[v] += (a.b[v] - s) / a.st[v];
 }
@@ -538,28 +550,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // nor do 3, 5, 6.  Running {0}, {1,2,4}, {3,5,6}, {7} as four launches updates
 // every vertex from the same values as the colour order 0..7 (bitwise the
 // same sweep), and one thread's three vertices share their neighbours' loads.
-template <int G>
+template <int G, bool ZC = false>
 __global__ __launch_bounds__(256) void k3_gs7g(LArgs a)
 {
     const long long t = xcd_block(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (t >= a.g.oct) return;
     if (G == 0) {
-        gs_point<7, 0>(a, t);
+        gs_point<7, 0, ZC>(a, t);
     } else if (G == 1) {
-        gs_point<7, 1>(a, t);
-        gs_point<7, 2>(a, t);
-        gs_point<7, 4>(a, t);
+        gs_point<7, 1, ZC>(a, t);
+        gs_point<7, 2, ZC>(a, t);
+        gs_point<7, 4, ZC>(a, t);
     } else if (G == 2) {
-        gs_point<7, 3>(a, t);
-        gs_point<7, 5>(a, t);
-        gs_point<7, 6>(a, t);
+        gs_point<7, 3, ZC>(a, t);
+        gs_point<7, 5, ZC>(a, t);
+        gs_point<7, 6, ZC>(a, t);
     } else {
-        gs_point<7, 7>(a, t);
+        gs_point<7, 7, ZC>(a, t);
     }
 }
 
 // residual r = b - A x (STORE) and/or block sums of r^2 (NORM); blockIdx.y = octant
-template <int NPT, int O, bool STORE, bool NORM>
+template <int NPT, int O, bool STORE, bool NORM, bool ZC = false>
 __device__ __forceinline__ double resid_at(const LArgs &a, long long t)
 {
     int i, j, k;
@@ -568,14 +580,14 @@ __device__ __forceinline__ double resid_at(const LArgs &a, long long t)
         return 0.0;
     }
     const long long v = O * a.g.oct + t;
-    const double r = a.b[v] - apply_at<NPT, O>(a.g, a.st, a.x, t);
+    const double r = a.b[v] - apply_at<NPT, O, false, ZC>(a.g, a.st, a.x, t);
     if (STORE) a.r[v] = r;
     return NORM ? r * r : 0.0;
 }
 
 // blocks interleave the octants (octant = block mod 8), so that the eight
 // octants of one region run together and share their neighbours in L2
-template <int NPT, bool STORE, bool NORM>
+template <int NPT, bool STORE, bool NORM, bool ZC = false>
 __global__ __launch_bounds__(256) void k3_resid(LArgs a)
 {
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
@@ -583,14 +595,14 @@ __global__ __launch_bounds__(256) void k3_resid(LArgs a)
     double sq = 0.0;
     if (t < a.g.oct) {
         switch (lb & 7) {
-        case 0: sq = resid_at<NPT, 0, STORE, NORM>(a, t); break;
-        case 1: sq = resid_at<NPT, 1, STORE, NORM>(a, t); break;
-        case 2: sq = resid_at<NPT, 2, STORE, NORM>(a, t); break;
-        case 3: sq = resid_at<NPT, 3, STORE, NORM>(a, t); break;
-        case 4: sq = resid_at<NPT, 4, STORE, NORM>(a, t); break;
-        case 5: sq = resid_at<NPT, 5, STORE, NORM>(a, t); break;
-        case 6: sq = resid_at<NPT, 6, STORE, NORM>(a, t); break;
-        default: sq = resid_at<NPT, 7, STORE, NORM>(a, t); break;
+        case 0: sq = resid_at<NPT, 0, STORE, NORM, ZC>(a, t); break;
+        case 1: sq = resid_at<NPT, 1, STORE, NORM, ZC>(a, t); break;
+        case 2: sq = resid_at<NPT, 2, STORE, NORM, ZC>(a, t); break;
+        case 3: sq = resid_at<NPT, 3, STORE, NORM, ZC>(a, t); break;
+        case 4: sq = resid_at<NPT, 4, STORE, NORM, ZC>(a, t); break;
+        case 5: sq = resid_at<NPT, 5, STORE, NORM, ZC>(a, t); break;
+        case 6: sq = resid_at<NPT, 6, STORE, NORM, ZC>(a, t); break;
+        default: sq = resid_at<NPT, 7, STORE, NORM, ZC>(a, t); break;
         }
     }
     if (NORM) {
@@ -601,6 +613,41 @@ __global__ __launch_bounds__(256) void k3_resid(LArgs a)
         if (threadIdx.x == 0) a.partials[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
     }
 }
+
+// ZC check of a 7-point level: clears *flag unless every interior vertex's
+// diagonal is bitwise W_p + W_e + S_p + S_n + B_p + B_t (finite volumes of
+// pure diffusion build it so); blocks interleave the octants
+template <int O>
+__device__ __forceinline__ bool zexc7_at(const Oct &g, const double *st, long long t)
+{
+    int i, j, k;
+    if (!thread_vertex<O>(g, t, i, j, k)) return true;
+    const long long F = g.field, v = O * g.oct + t;
+    const double *C = st, *W = st + F, *S = st + 2 * F, *B = st + 3 * F;
+    const long long xe = nbr<O, 1, 0, 0>(g, t), yn = nbr<O, 0, 1, 0>(g, t), zt = nbr<O, 0, 0, 1>(g, t);
+    return C[v] == W[v] + W[xe] + S[v] + S[yn] + B[v] + B[zt];
+}
+
+__global__ __launch_bounds__(256) void k3_zero_excess7(Oct g, const double *st, int *flag)
+{
+    const unsigned lb = blockIdx.x;
+    const long long t = (lb >> 3) * 256LL + threadIdx.x;
+    if (t >= g.oct) return;
+    bool ok = true;
+    switch (lb & 7) {
+    case 0: ok = zexc7_at<0>(g, st, t); break;
+    case 1: ok = zexc7_at<1>(g, st, t); break;
+    case 2: ok = zexc7_at<2>(g, st, t); break;
+    case 3: ok = zexc7_at<3>(g, st, t); break;
+    case 4: ok = zexc7_at<4>(g, st, t); break;
+    case 5: ok = zexc7_at<5>(g, st, t); break;
+    case 6: ok = zexc7_at<6>(g, st, t); break;
+    default: ok = zexc7_at<7>(g, st, t); break;
+    }
+    if (!ok) atomicAnd(flag, 0);
+}
+
+__global__ void k3_set_int(int *p, int v) { *p = v; }
 
 // sum of squares of a field's interior entries (the norm of b), block sums
 __global__ __launch_bounds__(256) void k3_sumsq(Oct g, const double *f, double *partials)
@@ -955,6 +1002,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 struct Lev3 {
     Oct g;
     int npt = 27;
+    int zc = 0;             // 7-point: the diagonal is formed from the connections
     double *st = nullptr;   // npt == 7: 4 fields; 27: 14 fields
     double *w = nullptr;    // NWSLOT octant slots: weights onto the next coarser level
     double *x = nullptr, *b = nullptr, *r = nullptr;
@@ -984,9 +1032,15 @@ struct hipbmg3d_hier {
     hipStream_t cap = nullptr;         // the stream the graph is captured on (the caller's may be the null stream)
     int prof = 0;
     std::vector<hipEvent_t> evpool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    struct ProfMark {
+        int k;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
+    std::vector<ProfMark> marks;
     double prof_ms[NPROF3] = {0};
     long long prof_n[NPROF3] = {0};
+    double prof_b[NPROF3] = {0};   // algorithmic bytes of the launches timed
 };
 
 namespace {
@@ -1015,13 +1069,14 @@ void free3(hipbmg3d_hier *h)
     delete h;
 }
 
-// kernel-class timing: an event pair around launches of class k
+// kernel-class timing: an event pair around launches of class k, which
+// move `bytes` algorithmic bytes
 struct Mark {
     hipbmg3d_hier *h;
     int k;
     hipStream_t s;
     hipEvent_t e1 = nullptr;
-    Mark(hipbmg3d_hier *h_, int k_, hipStream_t s_) : h(h_), k(k_), s(s_)
+    Mark(hipbmg3d_hier *h_, int k_, hipStream_t s_, double bytes = 0.0) : h(h_), k(k_), s(s_)
     {
         if (!h->prof) return;
         const size_t need = 2 * (h->marks.size() + 1);
@@ -1037,7 +1092,7 @@ struct Mark {
         hipEvent_t e0 = h->evpool[2 * h->marks.size()];
         e1 = h->evpool[2 * h->marks.size() + 1];
         (void)hipEventRecord(e0, s);
-        h->marks.push_back({k, {e0, e1}});
+        h->marks.push_back({k, bytes, e0, e1});
     }
     ~Mark()
     {
@@ -1049,14 +1104,27 @@ hipbmg_status prof_collect(hipbmg3d_hier *h)
 {
     for (auto &m : h->marks) {
         float ms = 0.f;
-        HIP3(hipEventSynchronize(m.second.second));
-        HIP3(hipEventElapsedTime(&ms, m.second.first, m.second.second));
-        h->prof_ms[m.first] += ms;
-        h->prof_n[m.first] += 1;
+        HIP3(hipEventSynchronize(m.e1));
+        HIP3(hipEventElapsedTime(&ms, m.e0, m.e1));
+        h->prof_ms[m.k] += ms;
+        h->prof_n[m.k] += 1;
+        h->prof_b[m.k] += m.bytes;
     }
     h->marks.clear();
     return HIPBMG_OK;
 }
+
+// algorithmic bytes per vertex of level f's whole grid (FP64): one
+// relaxation sweep or residual reads x, b and the stencil's planes (7-point:
+// C, W, S, B, or W, S, B with the diagonal formed; 27-point: 14) and writes
+// x or r (the norm-only residual writes nothing)
+double sweep_bytes_per_vertex(const Lev3 &f)
+{
+    const double planes = f.npt == 7 ? (f.zc ? 3.0 : 4.0) : 14.0;
+    return 8.0 * (3.0 + planes);
+}
+
+double grid_vertices(const Lev3 &f) { return (double)f.g.nx * f.g.ny * f.g.nz; }
 
 LArgs largs(const Lev3 &f, const Lev3 *c)
 {
@@ -1067,6 +1135,7 @@ LArgs largs(const Lev3 &f, const Lev3 *c)
     a.x = f.x;
     a.r = f.r;
     a.w = f.w;
+    a.zc = f.zc;
     if (c) {
         a.c = c->g;
         a.xc = c->x;
@@ -1102,17 +1171,26 @@ hipbmg_status relax(hipbmg3d_hier *h, int l, int sweeps, hipStream_t s)
     for (int it = 0; it < sweeps; ++it) {
         if (f.npt == 7) {
             for (int gq = 0; gq < 4; ++gq) {
-                Mark mk(h, l == h->L - 1 ? 0 : 4, s);
-                if (gq == 0) hipLaunchKernelGGL(k3_gs7g<0>, grid, block, 0, s, a);
-                else if (gq == 1) hipLaunchKernelGGL(k3_gs7g<1>, grid, block, 0, s, a);
-                else if (gq == 2) hipLaunchKernelGGL(k3_gs7g<2>, grid, block, 0, s, a);
-                else hipLaunchKernelGGL(k3_gs7g<3>, grid, block, 0, s, a);
+                // colour groups {0}, {1,2,4}, {3,5,6}, {7}: 1/8, 3/8, 3/8, 1/8 of the vertices
+                Mark mk(h, l == h->L - 1 ? 0 : 4, s,
+                        sweep_bytes_per_vertex(f) * grid_vertices(f) * ((gq == 0 || gq == 3) ? 0.125 : 0.375));
+                if (f.zc) {
+                    if (gq == 0) hipLaunchKernelGGL((k3_gs7g<0, true>), grid, block, 0, s, a);
+                    else if (gq == 1) hipLaunchKernelGGL((k3_gs7g<1, true>), grid, block, 0, s, a);
+                    else if (gq == 2) hipLaunchKernelGGL((k3_gs7g<2, true>), grid, block, 0, s, a);
+                    else hipLaunchKernelGGL((k3_gs7g<3, true>), grid, block, 0, s, a);
+                } else {
+                    if (gq == 0) hipLaunchKernelGGL(k3_gs7g<0>, grid, block, 0, s, a);
+                    else if (gq == 1) hipLaunchKernelGGL(k3_gs7g<1>, grid, block, 0, s, a);
+                    else if (gq == 2) hipLaunchKernelGGL(k3_gs7g<2>, grid, block, 0, s, a);
+                    else hipLaunchKernelGGL(k3_gs7g<3>, grid, block, 0, s, a);
+                }
                 HIP3(hipGetLastError());
             }
             continue;
         }
         for (int o = 0; o < 8; ++o) {
-            Mark mk(h, l == h->L - 1 ? 0 : 4, s);
+            Mark mk(h, l == h->L - 1 ? 0 : 4, s, sweep_bytes_per_vertex(f) * grid_vertices(f) * 0.125);
             HIP3(launch_gs_colour27(o, a, s));
         }
     }
@@ -1139,8 +1217,11 @@ hipbmg_status residual(hipbmg3d_hier *h, int l, bool store, bool norm, hipStream
     LArgs a = largs(f, nullptr);
     a.partials = h->d_part;
     const dim3 grid(8 * nblk(f.g.oct)), block(256);   // a multiple of 8, octants interleaved
-    Mark mk(h, l == h->L - 1 ? 1 : 4, s);
-    if (f.npt == 7) {
+    Mark mk(h, l == h->L - 1 ? 1 : 4, s, (sweep_bytes_per_vertex(f) - (store ? 0.0 : 8.0)) * grid_vertices(f));
+    if (f.npt == 7 && f.zc) {
+        if (store) hipLaunchKernelGGL((k3_resid<7, true, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k3_resid<7, false, true, true>), grid, block, 0, s, a);
+    } else if (f.npt == 7) {
         if (store) hipLaunchKernelGGL((k3_resid<7, true, false>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k3_resid<7, false, true>), grid, block, 0, s, a);
     } else {
@@ -1157,7 +1238,9 @@ hipbmg_status restrict_to(hipbmg3d_hier *h, int l, hipStream_t s)
 {
     LArgs a = largs(h->lv[l], &h->lv[l - 1]);
     a.xcz = h->lv[l - 1].x;
-    Mark mk(h, l == h->L - 1 ? 2 : 4, s);
+    // reads r and the 26 weights per coarse cell (3.25 per fine vertex),
+    // writes the coarse right-hand side and the zero coarse iterate
+    Mark mk(h, l == h->L - 1 ? 2 : 4, s, 8.0 * (1.0 + 3.25 + 0.25) * grid_vertices(h->lv[l]));
     hipLaunchKernelGGL(k3_restrict, dim3(8 * nblk(a.c.oct)), dim3(256), 0, s, a);
     HIP3(hipGetLastError());
     return HIPBMG_OK;
@@ -1169,7 +1252,8 @@ hipbmg_status interp_from(hipbmg3d_hier *h, int l, int rescorr, hipStream_t s)
     LArgs a = largs(f, &h->lv[l - 1]);
     a.rescorr = rescorr;
     const dim3 grid(round8(nblk(f.g.oct)), 8), block(256);
-    Mark mk(h, l == h->L - 1 ? 3 : 4, s);
+    // reads and writes x, reads r, C, the weights and the coarse iterate
+    Mark mk(h, l == h->L - 1 ? 3 : 4, s, 8.0 * (2.0 + 1.0 + 1.0 + 3.25 + 0.125) * grid_vertices(f));
     if (f.npt == 7) hipLaunchKernelGGL((k3_interp<7>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k3_interp<27>), grid, block, 0, s, a);
     HIP3(hipGetLastError());
@@ -1496,6 +1580,28 @@ extern "C" hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const d
     const int nf = npt == 7 ? 4 : 14;
     for (int q = 0; q < nf; ++q)
         if ((st = to_oct(top.g, planes + q * nnat, top.st + q * top.g.field, 0, s)) != HIPBMG_OK) return bail(st);
+    // a 7-point finest operator whose diagonal is the sum of its six
+    // connections (finite volumes of pure diffusion): its relaxation and
+    // residual kernels form the diagonal instead of loading it
+    // (HIPBMG_NO_ZEXC=1: always load)
+    if (npt == 7) {
+        int noz = 0;
+        if (const char *e = std::getenv("HIPBMG_NO_ZEXC")) noz = std::atoi(e);
+        if (!noz) {
+            int ok = 0;
+            double *dflag = nullptr;   // one double of device memory holds the int flag
+            if ((st = dalloc3(h, &dflag, 1)) != HIPBMG_OK) return bail(st);
+            int *d_flag = reinterpret_cast<int *>(dflag);
+            hipLaunchKernelGGL(k3_set_int, dim3(1), dim3(1), 0, s, d_flag, 1);
+            hipLaunchKernelGGL(k3_zero_excess7, dim3(8 * nblk(top.g.oct)), dim3(256), 0, s, top.g,
+                               (const double *)top.st, d_flag);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(&ok, d_flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return bail(fail3(HIPBMG_EHIP, "zero-excess check failed"));
+            h->lv[L - 1].zc = ok;
+        }
+    }
     // interpolation and Galerkin products, finest to coarsest
     for (int l = L - 1; l >= 1; --l) {
         Lev3 &f = h->lv[l], &c = h->lv[l - 1];
@@ -1728,16 +1834,19 @@ extern "C" hipbmg_status hipbmg3d_profile(hipbmg3d_handle h, int enable)
     for (int k = 0; k < NPROF3; ++k) {
         h->prof_ms[k] = 0.0;
         h->prof_n[k] = 0;
+        h->prof_b[k] = 0.0;
     }
     h->marks.clear();
     return HIPBMG_OK;
 }
 
-extern "C" hipbmg_status hipbmg3d_profile_read(hipbmg3d_handle h, int k, double *ms_host, long long *launches_host)
+extern "C" hipbmg_status hipbmg3d_profile_read(hipbmg3d_handle h, int k, double *ms_host, long long *launches_host,
+                                               double *bytes_per_launch_host)
 {
-    if (!h || !ms_host || !launches_host) return fail3(HIPBMG_EINVAL, "null argument");
+    if (!h) return fail3(HIPBMG_EINVAL, "null argument");
     if (k < 0 || k >= NPROF3) return fail3(HIPBMG_EINVAL, "kernel class %d out of range", k);
-    *ms_host = h->prof_ms[k];
-    *launches_host = h->prof_n[k];
+    if (ms_host) *ms_host = h->prof_ms[k];
+    if (launches_host) *launches_host = h->prof_n[k];
+    if (bytes_per_launch_host) *bytes_per_launch_host = h->prof_n[k] ? h->prof_b[k] / (double)h->prof_n[k] : 0.0;
     return HIPBMG_OK;
 }

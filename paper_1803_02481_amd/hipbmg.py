@@ -120,7 +120,8 @@ _SIGS = {
     "hipbmg3d_op_interp_correct": (_I, [_VP, _I, _VP, _VP, _VP, _I, _VP]),
     "hipbmg3d_op_coarse_solve": (_I, [_VP, _VP, _VP, _VP]),
     "hipbmg3d_profile": (_I, [_VP, _I]),
-    "hipbmg3d_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "hipbmg3d_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(ctypes.c_double)]),
 }
 
 # hipbmg_alloc_fn / hipbmg_free_fn
@@ -738,12 +739,13 @@ class Hierarchy3:
         _check(lib().hipbmg3d_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        """{kernel class: (ms, launches)} accumulated since profile(True)."""
+        """{kernel class: (ms, launches, algorithmic bytes per launch)}
+        accumulated since profile(True)."""
         out = {}
         for k, name in enumerate(KERNELS3):
-            ms, n = ctypes.c_double(), ctypes.c_longlong()
-            _check(lib().hipbmg3d_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
-            out[name] = (ms.value, n.value)
+            ms, n, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+            _check(lib().hipbmg3d_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+            out[name] = (ms.value, n.value, by.value)
         return out
 
 
