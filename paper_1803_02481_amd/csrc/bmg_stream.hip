@@ -30,6 +30,8 @@
 // The tile index is remapped so that the 8 XCDs (WG i runs on XCD i mod 8)
 // each get a contiguous band of strips and share halo rows in their own L2.
 #include "bmg_internal.h"
+
+#include <type_traits>
 #include "bmg_weights.h"
 
 namespace hbmg {
@@ -724,11 +726,17 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
-    for (int jp = jp0; jp <= jpend; jp += 2) {
+    // one step; HASA, HASB: stages A and B active (false only in the first
+    // four steps), MORE: the next step's rows are loaded (false in the last).
+    // The first and last steps are separate copies of the step, so the steady
+    // loop runs every stage unconditionally and its windows rotate without the
+    // copies a conditional stage would need.
+    auto step = [&](const int jp, auto ha, auto hb, auto mo) {
+        constexpr bool HASA = decltype(ha)::value, HASB = decltype(hb)::value, MORE = decltype(mo)::value;
         Row<T> R1 = N1;
         Row<T> R2 = N2;
         const T s3a = sa0, s3b = sa1;  // WF: S of row jp+3
-        if (jp + 2 <= jpend) {
+        if (MORE) {
             // the next step's rows: in flight while this step computes
             load_raw(N1, jp + 3, !WF);
             load_raw(N2, jp + 4);
@@ -763,19 +771,19 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
         if (PONLY) {
             stage_step<T, NPT, true, PNORM, false, PNORM>(P, jp, modeP, L, a);
             stage_rotate(P);
-            continue;
+            return;
         }
         // the iterate after cycle k is not stored: only the stopping cycle's
         // is needed, and it is rebuilt from this pass's inputs afterwards
         stage_step<T, NPT, true, true, false, true, false, false>(P, jp, modeP, L, a);
         const int ja = jp - 2;
-        if (ja >= jfirst - 6) {
+        if constexpr (HASA) {
             if (ja == jfirst - 6) A.rm1 = P.rm3;   // P-final row ja-1
             A.r0 = P.rm2;
             A.rp1 = P.rm1;
             stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
             const int jb = ja - 2;
-            if (jb >= jfirst - 4) {
+            if constexpr (HASB) {
                 if (jb == jfirst - 4) B.rm1 = A.rm3;
                 B.r0 = A.rm2;
                 B.rp1 = A.rm1;
@@ -788,6 +796,22 @@ __device__ __forceinline__ void stream3_tile(const StreamArgs<T> &a, const int t
             stage_rotate(A);
         }
         stage_rotate(P);
+        };
+    using Y = std::true_type;
+    using N = std::false_type;
+    if (PONLY) {
+        int jp = jp0;
+        for (; jp < jpend; jp += 2) step(jp, N{}, N{}, Y{});
+        step(jp, N{}, N{}, N{});
+    } else {
+        // A joins at jp0 + 4, B at jp0 + 8 = jfirst, and jpend >= jfirst + 4
+        step(jp0, N{}, N{}, Y{});
+        step(jp0 + 2, N{}, N{}, Y{});
+        step(jp0 + 4, Y{}, N{}, Y{});
+        step(jp0 + 6, Y{}, N{}, Y{});
+        int jp = jp0 + 8;
+        for (; jp < jpend; jp += 2) step(jp, Y{}, Y{}, Y{});
+        step(jp, Y{}, Y{}, N{});
     }
     if (!PONLY || PNORM) {
         double acc = P.acc;
