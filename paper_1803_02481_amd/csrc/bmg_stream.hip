@@ -494,10 +494,15 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
     Row<T> N0, N1;                 // rows ja and ja+1, loaded one step ahead
     load_row(N0, jfirst - 6);
     load_row(N1, jfirst - 5);
-    for (int ja = jfirst - 6; ja <= jlast + 2; ja += 2) {
+    // one step; AM, BM: the stages' modes (BM < 0: B not yet active), MORE:
+    // the next step's rows are loaded.  The prologue steps and the last one
+    // are separate copies, so the steady loop has no conditional stage.
+    auto step = [&](const int ja, auto am, auto bm, auto mo) {
+        constexpr int AM = decltype(am)::value, BM = decltype(bm)::value;
+        constexpr bool MORE = decltype(mo)::value;
         A.r0 = N0;
         A.rp1 = N1;
-        if (ja + 2 <= jlast + 2) {
+        if (MORE) {
             load_row(N0, ja + 2);
             load_row(N1, ja + 3);
         }
@@ -506,18 +511,30 @@ __device__ __forceinline__ void stream2_tile(const StreamArgs<T> &a, const int t
             complete_C9(A.rm1, A.r0, deep9(ja - 1, e, o, nx, ny));
             complete_C9(A.r0, A.rp1, deep9(ja, e, o, nx, ny));
         }
-        stage_step<T, NPT, false, false, false, false>(A, ja, ja == jfirst - 6 ? 0 : 1, L, a);
+        stage_step<T, NPT, false, false, false, false>(A, ja, AM, L, a);
         const int jb = ja - 2;
-        if (jb >= jfirst - 4) {
-            if (jb == jfirst - 4) B.rm1 = A.rm3;   // A-final row jb-1
-            B.r0 = A.rm2;                           // A-final rows jb, jb+1 as B's old rows
+        if constexpr (BM >= 0) {
+            if (BM == 0) B.rm1 = A.rm3;   // A-final row jb-1 (first B step, jb = jfirst - 4)
+            B.r0 = A.rm2;                  // A-final rows jb, jb+1 as B's old rows
             B.rp1 = A.rm1;
-            const int mode = jb < jfirst - 2 ? 0 : (jb == jfirst - 2 ? 1 : 2);
-            stage_step<T, NPT, true, true, true, false, false, true, STOREQ>(B, jb, mode, L, a);
+            stage_step<T, NPT, true, true, true, false, false, true, STOREQ>(B, jb, BM, L, a);
             stage_rotate(B);
         }
         stage_rotate(A);
-    }
+    };
+    using M0 = std::integral_constant<int, 0>;
+    using M1 = std::integral_constant<int, 1>;
+    using M2 = std::integral_constant<int, 2>;
+    using Off = std::integral_constant<int, -1>;
+    // A starts at jfirst - 6 (mode 0, then 1); B at jb = jfirst - 4 (mode 0),
+    // jfirst - 2 (mode 1), then mode 2; the last step is ja = jlast + 2 >= jfirst + 2
+    step(jfirst - 6, M0{}, Off{}, std::true_type{});
+    step(jfirst - 4, M1{}, Off{}, std::true_type{});
+    step(jfirst - 2, M1{}, M0{}, std::true_type{});
+    step(jfirst, M1{}, M1{}, std::true_type{});
+    int ja = jfirst + 2;
+    for (; ja < jlast + 2; ja += 2) step(ja, M1{}, M2{}, std::true_type{});
+    step(ja, M1{}, M2{}, std::false_type{});
 }
 
 // The finest level's post-relaxation of cycle k and both pre-relaxations of
@@ -1041,9 +1058,13 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
         P.rm1 = Rm1;
         finish_row(P.rm1, jp0 - 1, rc_even(Ra, Rm1, Rn), rc_odd(Ra, Rm1, Rn));
     }
-    for (int jp = jp0; jp <= jlast; jp += 2) {
+    // one step (MODE: the stage's mode, MORE: the next rows are loaded); the
+    // prologue step and the last one are separate copies of it
+    auto step = [&](const int jp, auto md, auto mo) {
+        constexpr int MODE = decltype(md)::value;
+        constexpr bool MORE = decltype(mo)::value;
         Row<T> R1 = N1, R2 = N2;
-        if (jp + 2 <= jlast) {
+        if (MORE) {
             load_raw(N1, jp + 3);
             load_raw(N2, jp + 4);
         }
@@ -1060,9 +1081,14 @@ __device__ __forceinline__ void interp_rc_tile(const StreamArgs<T> &a, const int
         finish_row(P.rp1, jp + 1, q0_odd_row, q1_odd_row);
         Rm1 = R1;
         Rn = R2;
-        stage_step<T, NPT, true, false, false, false>(P, jp, jp == jp0 ? 0 : 2, L, a);
+        stage_step<T, NPT, true, false, false, false>(P, jp, MODE, L, a);
         stage_rotate(P);
-    }
+    };
+    // jp0 = jfirst - 2 < jlast
+    step(jp0, std::integral_constant<int, 0>{}, std::true_type{});
+    int jp = jfirst;
+    for (; jp < jlast; jp += 2) step(jp, std::integral_constant<int, 2>{}, std::true_type{});
+    step(jp, std::integral_constant<int, 2>{}, std::false_type{});
 }
 
 template <typename T, int NPT, bool ZC9 = false>
