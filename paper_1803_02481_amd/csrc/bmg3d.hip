@@ -1061,7 +1061,10 @@ hipbmg_status dalloc3(hipbmg3d_hier *h, double **p, long long n)
 void free3(hipbmg3d_hier *h)
 {
     hbmg::dev_free_all(h->allocs);
-    if (h->h_sum) (void)hipHostFree(h->h_sum);
+    if (h->h_sum) {
+        (void)hipDeviceSynchronize();
+        hbmg::pinned_small_free(h->h_sum);
+    }
     for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
@@ -1572,7 +1575,7 @@ extern "C" hipbmg_status hipbmg3d_setup(int nx, int ny, int nz, int npt, const d
     h->npart = 8 * (long long)nblk(top.g.oct) + 8;
     if ((st = dalloc3(h, &h->d_part, h->npart)) != HIPBMG_OK) return bail(st);
     if ((st = dalloc3(h, &h->d_sum, 8 + 256)) != HIPBMG_OK) return bail(st);
-    if (hipHostMalloc((void **)&h->h_sum, 8 * sizeof(double), 0) != hipSuccess) {
+    if (hbmg::pinned_small((void **)&h->h_sum, nullptr, 8 * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail3(HIPBMG_ENOMEM, "pinned allocation failed"));
     }

@@ -124,6 +124,53 @@ void hbmg::dev_free_all(std::vector<void *> &v)
     v.clear();
 }
 
+// Small pinned host buffers (a handle's scalars, flags and host-mapped test
+// slots) are 512-byte slots of slabs of mapped, coherent pinned memory that
+// stay allocated until the process ends: hipHostMalloc and above all
+// hipHostFree cost tens to hundreds of microseconds a call, which dominated
+// building and destroying the many small handles of a batch.
+namespace {
+constexpr size_t PIN_SLOT = 512, PIN_SLAB = 256 * PIN_SLOT;
+std::mutex g_pin_mu;
+std::vector<std::pair<char *, char *>> g_pin_slabs;   // host and device address of each slab
+std::vector<char *> g_pin_free;                       // free slots (host addresses)
+}  // namespace
+
+hipError_t hbmg::pinned_small(void **host, void **dev, size_t bytes)
+{
+    if (bytes > PIN_SLOT) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    if (g_pin_free.empty()) {
+        void *h = nullptr, *d = nullptr;
+        hipError_t e = hipHostMalloc(&h, PIN_SLAB, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e != hipSuccess) return e;
+        e = hipHostGetDevicePointer(&d, h, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(h);
+            return e;
+        }
+        g_pin_slabs.push_back({static_cast<char *>(h), static_cast<char *>(d)});
+        for (size_t k = PIN_SLAB / PIN_SLOT; k-- > 0;) g_pin_free.push_back(static_cast<char *>(h) + k * PIN_SLOT);
+    }
+    char *p = g_pin_free.back();
+    g_pin_free.pop_back();
+    std::memset(p, 0, PIN_SLOT);
+    *host = p;
+    if (dev) {
+        *dev = nullptr;
+        for (const auto &sl : g_pin_slabs)
+            if (p >= sl.first && p < sl.first + PIN_SLAB) *dev = sl.second + (p - sl.first);
+    }
+    return hipSuccess;
+}
+
+void hbmg::pinned_small_free(void *host)
+{
+    if (!host) return;
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_free.push_back(static_cast<char *>(host));
+}
+
 extern "C" hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx)
 {
     if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
@@ -241,9 +288,12 @@ struct hipbmg_hier {
         for (int k = 0; k < RING; ++k)
             if (ring_ev[k]) (void)hipEventDestroy(ring_ev[k]);
         dev_free_all(allocs);
-        if (h_scal) (void)hipHostFree(h_scal);
-        if (h_flags) (void)hipHostFree(h_flags);
-        if (ring_host) (void)hipHostFree(ring_host);
+        // the pinned slots go back to the pool for the next handle: nothing
+        // of this handle may still write them
+        if (h_scal || h_flags || ring_host) (void)hipDeviceSynchronize();
+        pinned_small_free(h_scal);
+        pinned_small_free(h_flags);
+        pinned_small_free(ring_host);
     }
 };
 
@@ -781,16 +831,15 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if (st != HIPBMG_OK) return bail(st);
     st = dalloc(h, &h->d_scal, 8, s);
     if (st != HIPBMG_OK) return bail(st);
-    if (hipHostMalloc(&h->h_scal, 8 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&h->h_flags, 4 * sizeof(int)) != hipSuccess)
-        return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+    if (pinned_small((void **)&h->h_scal, nullptr, 8 * sizeof(double)) != hipSuccess ||
+        pinned_small((void **)&h->h_flags, nullptr, 4 * sizeof(int)) != hipSuccess)
+        return bail(fail(HIPBMG_ENOMEM, "pinned host allocation failed"));
     // device-side stopping: run flag, residual history, host-mapped test slots
     st = dalloc(h, &h->d_flags, 4, s);
     if (st == HIPBMG_OK) st = dalloc(h, &h->d_hist, HIPBMG_MAX_HIST, s);
     if (st != HIPBMG_OK) return bail(st);
-    if (hipHostMalloc(&h->ring_host, RING * 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess ||
-        hipHostGetDevicePointer((void **)&h->ring_dev, h->ring_host, 0) != hipSuccess)
+    if (pinned_small((void **)&h->ring_host, (void **)&h->ring_dev, RING * 4 * sizeof(double)) != hipSuccess ||
+        !h->ring_dev)
         return bail(fail(HIPBMG_ENOMEM, "host-mapped allocation failed"));
     for (int k = 0; k < RING * 4; ++k) h->ring_host[k] = 0.0;
     for (int k = 0; k < RING; ++k)

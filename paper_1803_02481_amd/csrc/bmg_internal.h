@@ -28,6 +28,11 @@ void set_last_error(const char *msg);
 // at once) and clears v.
 hipError_t dev_malloc(void **p, size_t bytes);
 void dev_free_all(std::vector<void *> &v);
+// a zeroed pinned host buffer of at most 512 bytes, mapped (dev, if not null,
+// gets its device address) and coherent, from a pool kept for the process;
+// pinned_small_free returns it to the pool (null is accepted)
+hipError_t pinned_small(void **host, void **dev, size_t bytes);
+void pinned_small_free(void *host);
 
 // Weight plane indices (fine vertex of coarse cell (I,J) -> coarse corner).
 enum { WXL = 0, WXR = 1, WYB = 2, WYT = 3, WCSW = 4, WCSE = 5, WCNW = 6, WCNE = 7 };

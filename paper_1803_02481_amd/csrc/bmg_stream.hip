@@ -31,6 +31,8 @@
 // each get a contiguous band of strips and share halo rows in their own L2.
 #include "bmg_internal.h"
 
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include "bmg_weights.h"
 
@@ -1234,12 +1236,26 @@ int stream_resident(int npt, int variant, int fp32)
     else
         k = npt == 9 ? kernel_of<double, 9>(variant) : kernel_of<double, 5>(variant);
     int dev = 0, ncu = 0, per = 0;
-    if (!k || hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    if (!k || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    // the answer depends only on the kernel and the device: kept after the
+    // first query (a handle's setup asks for many levels and variants)
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> cache;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find({dev, k});
+        if (it != cache.end()) return it->second;
+    }
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 64, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
+    std::lock_guard<std::mutex> g(mu);
+    cache[{dev, k}] = ncu * per;
     return ncu * per;
 }
 
