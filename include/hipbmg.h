@@ -135,8 +135,10 @@ void hipbmg_default_params(hipbmg_params *p);
  * such blocks back the library waits for the device, so memory the allocator
  * gives out again is no longer in use by the library's streams.  The
  * callbacks may be called from any library call that builds or destroys a
- * handle (the solves allocate nothing).  The one-time machine calibration
- * keeps its scratch on hipMalloc.  Host only; thread-safe. */
+ * handle (the solves allocate nothing).  A 2D hierarchy asks for one block
+ * per array larger than 8 MiB and cuts its smaller arrays from 16 MiB blocks,
+ * so it makes a few calls, not one per array.  The one-time machine
+ * calibration keeps its scratch on hipMalloc.  Host only; thread-safe. */
 typedef void *(*hipbmg_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*hipbmg_free_fn)(void *ptr, void *ctx);
 hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx);

@@ -215,6 +215,8 @@ struct hipbmg_hier {
     LevelDev<double> *d_lv = nullptr;
     LevelDev<float> *d_lv32 = nullptr;
     std::vector<void *> allocs;
+    char *arena = nullptr;        // the unused part of the handle's current zeroed chunk
+    size_t arena_left = 0;
     double *d_chol = nullptr;
     int *d_cidx = nullptr;
     double *d_work = nullptr;
@@ -352,17 +354,41 @@ static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30, bo
 
 static int pitch_for(int nx) { return (nx + 63) / 64 * 64; }   // >= nx+1 for odd nx
 
+// A handle's device arrays, zeroed, 256-byte aligned and 256 bytes longer than
+// asked.  Arrays up to half a chunk are cut from 16 MiB chunks that are zeroed
+// once when taken, so a hierarchy makes a few allocator calls and fills, not
+// one of each per array (each costs microseconds on the host, and the binding's
+// allocator is a Python callback); larger arrays get a block of their own.
+constexpr size_t ARENA_CHUNK = size_t(16) << 20;
+
 template <typename T>
 static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
 {
+    const size_t bytes = (n * sizeof(T) + 256 + 255) / 256 * 256;
     void *q = nullptr;
-    if (dev_malloc(&q, n * sizeof(T) + 256) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
+    if (bytes > ARENA_CHUNK / 2) {
+        if (dev_malloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
+        }
+        h->allocs.push_back(q);
+        HIPCHK(hipMemsetAsync(q, 0, bytes, s));
+        *p = static_cast<T *>(q);
+        return HIPBMG_OK;
     }
-    h->allocs.push_back(q);
-    HIPCHK(hipMemsetAsync(q, 0, n * sizeof(T) + 256, s));
-    *p = static_cast<T *>(q);
+    if (bytes > h->arena_left) {
+        if (dev_malloc(&q, ARENA_CHUNK) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", ARENA_CHUNK);
+        }
+        h->allocs.push_back(q);
+        HIPCHK(hipMemsetAsync(q, 0, ARENA_CHUNK, s));
+        h->arena = static_cast<char *>(q);
+        h->arena_left = ARENA_CHUNK;
+    }
+    *p = reinterpret_cast<T *>(h->arena);
+    h->arena += bytes;
+    h->arena_left -= bytes;
     return HIPBMG_OK;
 }
 

@@ -137,10 +137,22 @@ def test_blocks_return_to_their_own_allocator_after_a_switch():
     assert pool.n_alloc == n and not pool.live
 
 
-@pytest.mark.parametrize("fail_at", [1, 3, 6])
-def test_a_failing_allocator_fails_setup_without_leaks(fail_at):
+@pytest.mark.parametrize("which", ["first", "middle", "last"])
+def test_a_failing_allocator_fails_setup_without_leaks(which):
+    # the setup's first, middle or last request fails (the number of requests
+    # is counted on a setup that succeeds: small arrays share zeroed chunks)
     c2, _, c3, _, _, _ = problems()
     for make in (lambda: HB.Hierarchy(c2), lambda: HB.Hierarchy3(c3)):
+        make().close()   # the process's one-time model calibration, if not done yet
+        count = Pool()
+        HB.set_allocator(count.alloc, count.free)
+        try:
+            make().close()
+        finally:
+            HB.use_torch_allocator()
+        n = count.n_alloc
+        assert n >= 1 and not count.live
+        fail_at = {"first": 1, "middle": (n + 1) // 2, "last": n}[which]
         pool = Pool(fail_at=fail_at)
         HB.set_allocator(pool.alloc, pool.free)
         try:
