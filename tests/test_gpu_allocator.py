@@ -193,3 +193,24 @@ def test_handles_left_open_at_exit_are_closed_cleanly():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "built 2" in r.stdout
+
+
+def test_many_handles_share_the_pinned_pool():
+    # every handle takes three 512-byte pinned slots (scalars, flags, the
+    # host-mapped test slots) from slabs of 256 slots kept for the process:
+    # 300 open handles need several slabs, and the slots of destroyed handles
+    # serve the next ones; every solve still reads its own convergence test
+    c2, b2, _, _, _, _ = problems()
+    hs = [HB.Hierarchy(c2) for _ in range(300)]
+    ref, info_ref = hs[0].solve(b2, tol=1e-10)
+    for k in (1, 150, 299):
+        u, info = hs[k].solve(b2, tol=1e-10)
+        assert torch.equal(u, ref) and info.cycles == info_ref.cycles and info.history() == info_ref.history()
+    for h in hs[::2]:
+        h.close()
+    more = [HB.Hierarchy(c2) for _ in range(150)]
+    for h in (more[0], more[-1], hs[1]):
+        u, info = h.solve(b2, tol=1e-10)
+        assert torch.equal(u, ref) and info.cycles == info_ref.cycles
+    for h in hs[1::2] + more:
+        h.close()
