@@ -709,7 +709,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
-                     "avg_launch_us": kavg_s * 1e6},
+                     "avg_launch_us": kavg_s * 1e6,
+                     # the relaxation's own access mix (five arrays read, one
+                     # written) streamed by a probe kernel in this run's model
+                     # calibration: the rate this kind of kernel can reach here
+                     "access_mix_GBps": calib["hbm_GBps"],
+                     "frac_of_access_mix": achieved / calib["hbm_GBps"] if calib["hbm_GBps"] > 0 else None},
         "kernels_fp64_finest": kernels,
         "model_calibration": calib,
         "redistribution_search": {"collapse_level": info.collapse_level, "stages": info.cluster_stages,
