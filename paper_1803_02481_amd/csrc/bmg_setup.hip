@@ -233,7 +233,7 @@ __device__ __forceinline__ double Aent(const StView &A, int i, int j, int sx, in
     return -A.se(i - 1, j + 1);
 }
 
-__global__ void k_rap(StView A, WView P, double *__restrict__ Cc, double *__restrict__ Wc,
+__global__ __launch_bounds__(128) void k_rap(StView A, WView P, double *__restrict__ Cc, double *__restrict__ Wc,
                       double *__restrict__ Sc, double *__restrict__ SWc, double *__restrict__ SEc,
                       int cpitch)
 {
@@ -247,21 +247,37 @@ __global__ void k_rap(StView A, WView P, double *__restrict__ Cc, double *__rest
     // index is a constant, so the stencil and weights stay in registers
     if (cin(I, J)) {
         const int dirs[5][2] = {{0, 0}, {-1, 0}, {0, -1}, {-1, -1}, {1, -1}};
-        double pi[3][3];
+        // every weight and matrix entry the sums can touch, loaded before any
+        // of the sums' data-dependent skips, so no load waits on another
+        // load's value (all in bounds for an interior coarse vertex: the fine
+        // points and their neighbours lie within 2I-2..2I+2, 2J-2..2J+2)
+        double pi[3][3], pw[5][3][3], a[3][3][3][3];
         #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
             #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) pi[dy + 1][dx + 1] = P.col(I, J, dx, dy);
         #pragma unroll
+        for (int d = 0; d < 5; ++d)
+            #pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+                #pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    pw[d][dy + 1][dx + 1] = P.col(I + dirs[d][0], J + dirs[d][1], dx, dy);
+        #pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+            #pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+                #pragma unroll
+                for (int sy = -1; sy <= 1; ++sy)
+                    #pragma unroll
+                    for (int sx = -1; sx <= 1; ++sx)
+                        a[dy + 1][dx + 1][sy + 1][sx + 1] = Aent(A, 2 * I + dx, 2 * J + dy, sx, sy);
+        #pragma unroll
         for (int d = 0; d < 5; ++d) {
             const int ex = dirs[d][0], ey = dirs[d][1];
             const int KI = I + ex, KJ = J + ey;
             if (!cin(KI, KJ)) continue;
-            double pj[3][3];
-            #pragma unroll
-            for (int dy = -1; dy <= 1; ++dy)
-                #pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) pj[dy + 1][dx + 1] = P.col(KI, KJ, dx, dy);
+            const double (&pj)[3][3] = pw[d];
             double acc = 0.0;
             #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
@@ -281,7 +297,7 @@ __global__ void k_rap(StView A, WView P, double *__restrict__ Cc, double *__rest
                             if (!A.inner(pi_ + sx, pj_ + sy)) continue;
                             const double wq = pj[oy + 1][ox + 1];
                             if (wq == 0.0) continue;
-                            inner += Aent(A, pi_, pj_, sx, sy) * wq;
+                            inner += a[dy + 1][dx + 1][sy + 1][sx + 1] * wq;
                         }
                     acc += wp * inner;
                 }
