@@ -40,11 +40,13 @@
  *     of its hierarchy.  Setup takes it from the allocator registered with
  *     hipbmg_set_allocator, or from hipMalloc if none is registered; solves
  *     allocate nothing.  hipbmg_destroy returns every block to the allocator
- *     that made it.  When any block came from a registered allocator, destroy
- *     first synchronises the whole device (hipDeviceSynchronize), because
- *     such an allocator may hand the block out again at once; it therefore
- *     waits for work on every stream, not only the caller's.  A handle serves
- *     one stream at a time; calls on one handle must not overlap.
+ *     that made it, and the handle's small pinned host buffers to a pool the
+ *     library keeps for the process.  Destroy first synchronises the whole
+ *     device (hipDeviceSynchronize), because a registered allocator may hand a
+ *     block out again at once and the next handle may take the pinned
+ *     buffers; it therefore waits for work on every stream, not only the
+ *     caller's.  A handle serves one stream at a time; calls on one handle
+ *     must not overlap.
  */
 #ifndef HIPBMG_H
 #define HIPBMG_H
@@ -136,9 +138,9 @@ void hipbmg_default_params(hipbmg_params *p);
  * gives out again is no longer in use by the library's streams.  The
  * callbacks may be called from any library call that builds or destroys a
  * handle (the solves allocate nothing).  A 2D hierarchy asks for one block
- * per array larger than 8 MiB and cuts its smaller arrays from 16 MiB blocks,
- * so it makes a few calls, not one per array.  The one-time machine
- * calibration keeps its scratch on hipMalloc.  Host only; thread-safe. */
+ * per array larger than 8 MiB and cuts its smaller arrays from blocks of 1, 2,
+ * 4, 8, then 16 MiB, so it makes a few calls, not one per array.  The one-time
+ * machine calibration keeps its scratch on hipMalloc.  Host only; thread-safe. */
 typedef void *(*hipbmg_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*hipbmg_free_fn)(void *ptr, void *ctx);
 hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx);

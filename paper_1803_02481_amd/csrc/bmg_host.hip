@@ -217,6 +217,7 @@ struct hipbmg_hier {
     std::vector<void *> allocs;
     char *arena = nullptr;        // the unused part of the handle's current zeroed chunk
     size_t arena_left = 0;
+    size_t arena_next = size_t(1) << 20;   // size of the next chunk (doubling to 16 MiB)
     double *d_chol = nullptr;
     int *d_cidx = nullptr;
     double *d_work = nullptr;
@@ -355,10 +356,11 @@ static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30, bo
 static int pitch_for(int nx) { return (nx + 63) / 64 * 64; }   // >= nx+1 for odd nx
 
 // A handle's device arrays, zeroed, 256-byte aligned and 256 bytes longer than
-// asked.  Arrays up to half a chunk are cut from 16 MiB chunks that are zeroed
-// once when taken, so a hierarchy makes a few allocator calls and fills, not
-// one of each per array (each costs microseconds on the host, and the binding's
-// allocator is a Python callback); larger arrays get a block of their own.
+// asked.  Arrays of at most 8 MiB are cut from chunks that are zeroed once when
+// taken (1 MiB, then doubling to 16 MiB, so a small hierarchy stays small), so
+// a hierarchy makes a few allocator calls and fills, not one of each per array
+// (each costs microseconds on the host, and the binding's allocator is a
+// Python callback); larger arrays get a block of their own.
 constexpr size_t ARENA_CHUNK = size_t(16) << 20;
 
 template <typename T>
@@ -377,14 +379,16 @@ static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
         return HIPBMG_OK;
     }
     if (bytes > h->arena_left) {
-        if (dev_malloc(&q, ARENA_CHUNK) != hipSuccess) {
+        const size_t chunk = std::max(h->arena_next, bytes);
+        if (dev_malloc(&q, chunk) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", ARENA_CHUNK);
+            return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", chunk);
         }
         h->allocs.push_back(q);
-        HIPCHK(hipMemsetAsync(q, 0, ARENA_CHUNK, s));
+        HIPCHK(hipMemsetAsync(q, 0, chunk, s));
         h->arena = static_cast<char *>(q);
-        h->arena_left = ARENA_CHUNK;
+        h->arena_left = chunk;
+        h->arena_next = std::min(2 * h->arena_next, ARENA_CHUNK);
     }
     *p = reinterpret_cast<T *>(h->arena);
     h->arena += bytes;
