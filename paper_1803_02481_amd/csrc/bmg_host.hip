@@ -6,6 +6,8 @@
 #include "bmg_misc.h"
 #include "bmg_model.h"
 
+#include <atomic>
+#include <thread>
 #include <algorithm>
 #include <map>
 #include <chrono>
@@ -2907,17 +2909,62 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         g_err = m;
         return st;
     };
-    for (int p = 0; p < nprob; ++p) {
-        hipbmg_handle h = nullptr;
-        hipbmg_status st = hipbmg_setup(nx[p], ny[p], npt, coeffs[p], &prm, stream, &h);
-        if (st != HIPBMG_OK) {
-            std::string m = g_err;
-            (void)fail(st, "problem %d: %s", p, m.c_str());
-            return bail(st);
+    // The problems' hierarchies are independent: the first is built on the
+    // caller's stream, the others on several host threads with a stream each
+    // (HIPBMG_SETUP_THREADS, default 8; 1 builds them in turn), so that one
+    // problem's kernels run while another's host steps and read-backs go on.
+    {
+        B->hs.assign(nprob, nullptr);
+        std::vector<hipbmg_status> sts(nprob, HIPBMG_OK);
+        std::vector<std::string> msgs(nprob);
+        auto build = [&](int p, hipStream_t sp) {
+            sts[p] = hipbmg_setup(nx[p], ny[p], npt, coeffs[p], &prm, sp, &B->hs[p]);
+            if (sts[p] != HIPBMG_OK) msgs[p] = g_err;   // the worker's own last error
+        };
+        build(0, s);
+        int nth = 8;
+        if (const char *e = std::getenv("HIPBMG_SETUP_THREADS")) nth = std::max(1, std::atoi(e));
+        nth = std::min(nth, nprob - 1);
+        if (sts[0] == HIPBMG_OK && nth >= 1) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return bail(fail(HIPBMG_EHIP, "hipGetDevice failed"));
+            std::atomic<int> next{1};
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nth; ++t)
+                pool.emplace_back([&, t] {
+                    (void)t;
+                    hipStream_t sp = nullptr;
+                    if (hipSetDevice(dev) != hipSuccess ||
+                        hipStreamCreateWithFlags(&sp, hipStreamNonBlocking) != hipSuccess) {
+                        (void)hipGetLastError();
+                        sp = nullptr;
+                    }
+                    for (int p; (p = next.fetch_add(1)) < nprob;) {
+                        if (!sp) {
+                            sts[p] = HIPBMG_EHIP;
+                            msgs[p] = "cannot create a setup stream";
+                            continue;
+                        }
+                        build(p, sp);
+                    }
+                    if (sp) {
+                        (void)hipStreamSynchronize(sp);
+                        (void)hipStreamDestroy(sp);
+                    }
+                });
+            for (std::thread &th : pool) th.join();
+        } else if (sts[0] == HIPBMG_OK) {
+            for (int p = 1; p < nprob; ++p) build(p, s);
         }
-        B->hs.push_back(h);
-        B->max_nx = std::max(B->max_nx, nx[p]);
-        B->max_ny = std::max(B->max_ny, ny[p]);
+        for (int p = 0; p < nprob; ++p)
+            if (sts[p] != HIPBMG_OK) {
+                (void)fail(sts[p], "problem %d: %s", p, msgs[p].c_str());
+                return bail(sts[p]);
+            }
+        for (int p = 0; p < nprob; ++p) {
+            B->max_nx = std::max(B->max_nx, nx[p]);
+            B->max_ny = std::max(B->max_ny, ny[p]);
+        }
     }
     B->fine_npt = npt;
     hipbmg_status st = HIPBMG_OK;
