@@ -137,7 +137,8 @@ void hipbmg_default_params(hipbmg_params *p);
  * such blocks back the library waits for the device, so memory the allocator
  * gives out again is no longer in use by the library's streams.  The
  * callbacks may be called from any library call that builds or destroys a
- * handle (the solves allocate nothing).  A 2D hierarchy asks for one block
+ * handle (the solves allocate nothing), and from the worker threads of
+ * hipbmg_setup_batched, so they must be thread-safe.  A 2D hierarchy asks for one block
  * per array larger than 8 MiB and cuts its smaller arrays from blocks of 1, 2,
  * 4, 8, then 16 MiB, so it makes a few calls, not one per array.  The one-time
  * machine calibration keeps its scratch on hipMalloc.  Host only; thread-safe. */
@@ -283,7 +284,12 @@ hipbmg_status hipbmg_residual_norm_noalloc(int nx, int ny, int npt, const double
  * [3 or 5][ny][nx] planes (npt 5 or 9 for every problem).  b, u: host arrays
  * of nprob device pointers to [ny][nx]; u holds the initial guesses on entry.
  * infos: NULL or a host array [nprob].  Returns HIPBMG_ENOCONV if any problem
- * did not reach tol (every u holds its last iterate). */
+ * did not reach tol (every u holds its last iterate).  hipbmg_setup_batched
+ * builds the first problem's hierarchy on `stream` and the others on up to 8
+ * host threads of its own, each with its own stream (HIPBMG_SETUP_THREADS
+ * sets the count; 1 builds them all on `stream`), and returns when all are
+ * built; a registered allocator's callbacks may therefore be called from
+ * those threads. */
 typedef struct hipbmg_batch *hipbmg_batch_handle;
 hipbmg_status hipbmg_setup_batched(int nprob, const int *nx_host, const int *ny_host, int npt,
                                    const double *const *coeffs_host, const hipbmg_params *params,
