@@ -173,6 +173,44 @@ void hbmg::pinned_small_free(void *host)
     g_pin_free.push_back(static_cast<char *>(host));
 }
 
+// Larger pinned host buffers (a batch's host tables) are blocks of a power of
+// two bytes (at least 4 KiB), kept on per-size free lists for the process.
+namespace {
+std::map<size_t, std::vector<void *>> g_pin_blocks;   // guarded by g_pin_mu
+}  // namespace
+
+hipError_t hbmg::pinned_block(void **host, size_t bytes, size_t *cap)
+{
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    *host = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_pin_mu);
+        std::vector<void *> &v = g_pin_blocks[c];
+        if (!v.empty()) {
+            *host = v.back();
+            v.pop_back();
+        }
+    }
+    if (!*host) {
+        const hipError_t e = hipHostMalloc(host, c);
+        if (e != hipSuccess) {
+            *host = nullptr;
+            return e;
+        }
+    }
+    std::memset(*host, 0, c);
+    *cap = c;
+    return hipSuccess;
+}
+
+void hbmg::pinned_block_free(void *host, size_t cap)
+{
+    if (!host) return;
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_blocks[cap].push_back(host);
+}
+
 extern "C" hipbmg_status hipbmg_set_allocator(hipbmg_alloc_fn alloc_fn, hipbmg_free_fn free_fn, void *ctx)
 {
     if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
@@ -2360,6 +2398,11 @@ struct hipbmg_batch {
     int *d_roff = nullptr, *d_rcnt = nullptr;
     double **d_bptr = nullptr, **d_xptr = nullptr;
     int4 *d_dims = nullptr;
+    // the caller's arrays of a solve ([0, n) b, [n, 2n) u, [2n, 3n) each
+    // problem's result plane) and the first row of each problem in the batch
+    const double **d_user = nullptr, **h_user = nullptr;
+    int *d_rowoff = nullptr;
+    int rows = 0;
     LevelDev<double> *d_fine64 = nullptr;
     LevelDev<float> *d_fine32 = nullptr;
     double *d_rpart = nullptr;   // refinement residual partials (segments d_roff / d_rcnt)
@@ -2384,6 +2427,8 @@ struct hipbmg_batch {
     int *d_rbact = nullptr, *h_rbact = nullptr;
     float **d_eptr = nullptr, **h_eptr = nullptr;              // each problem's FP32 correction
     int *h_act2 = nullptr;
+    void *h_block = nullptr;                  // pinned block holding every h_ table above
+    size_t h_block_cap = 0;
     std::vector<void *> seg_allocs;           // norm segment tables (rebuilt with the plans)
     hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -2399,17 +2444,8 @@ struct hipbmg_batch {
         for (auto &p : pipe32) drop_plan(p);
         dev_free_all(seg_allocs);
         dev_free_all(allocs);
-        if (h_rb64) (void)hipHostFree(h_rb64);
-        if (h_rb32) (void)hipHostFree(h_rb32);
-        if (h_rbact) (void)hipHostFree(h_rbact);
-        if (h_eptr) (void)hipHostFree(h_eptr);
-        if (h_act2) (void)hipHostFree(h_act2);
-        if (h_relres) (void)hipHostFree(h_relres);
-        if (h_active) (void)hipHostFree(h_active);
-        if (h_count) (void)hipHostFree(h_count);
-        if (h_tol) (void)hipHostFree(h_tol);
-        if (h_itol) (void)hipHostFree(h_itol);
-        for (hipbmg_hier *h : hs) delete h;
+        for (hipbmg_hier *h : hs) delete h;   // each waits for the device first
+        hbmg::pinned_block_free(h_block, h_block_cap);
     }
 };
 
@@ -2988,12 +3024,15 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     chk(balloc(B, &B->d_bptr, nprob, s));
     chk(balloc(B, &B->d_xptr, nprob, s));
     chk(balloc(B, &B->d_dims, nprob, s));
+    chk(balloc(B, &B->d_user, 3 * (size_t)nprob, s));
+    chk(balloc(B, &B->d_rowoff, (size_t)nprob + 1, s));
     chk(balloc(B, &B->d_fine64, nprob, s));
     if (prm.precision == HIPBMG_MIXED) chk(balloc(B, &B->d_fine32, nprob, s));
     if (st != HIPBMG_OK) return bail(st);
     std::vector<int> boff(nprob), bcnt(nprob, 64), roff(nprob), rcnt(nprob);
     std::vector<double *> bptr(nprob), xptr(nprob);
     std::vector<int4> dims(nprob);
+    std::vector<int> rowoff(nprob + 1, 0);
     std::vector<LevelDev<double>> f64(nprob);
     std::vector<LevelDev<float>> f32(nprob);
     size_t roffs = 0;
@@ -3003,6 +3042,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         bptr[p] = F.b;
         xptr[p] = F.x[0];
         dims[p] = make_int4(F.nx, F.ny, F.pitch, 0);
+        rowoff[p + 1] = rowoff[p] + F.ny;
         f64[p] = F;
         if (prm.precision == HIPBMG_MIXED) f32[p] = B->hs[p]->lv32[B->hs[p]->L - 1];
         roff[p] = (int)roffs;
@@ -3021,15 +3061,41 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     up(B->d_bptr, bptr.data(), nprob * sizeof(double *));
     up(B->d_xptr, xptr.data(), nprob * sizeof(double *));
     up(B->d_dims, dims.data(), nprob * sizeof(int4));
+    up(B->d_rowoff, rowoff.data(), (nprob + 1) * sizeof(int));
+    B->rows = rowoff[nprob];
     up(B->d_fine64, f64.data(), nprob * sizeof(LevelDev<double>));
     if (prm.precision == HIPBMG_MIXED) up(B->d_fine32, f32.data(), nprob * sizeof(LevelDev<float>));
     if (st != HIPBMG_OK) return bail(st);
-    if (hipHostMalloc(&B->h_relres, nprob * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&B->h_active, nprob * sizeof(int)) != hipSuccess ||
-        hipHostMalloc(&B->h_count, sizeof(int)) != hipSuccess ||
-        hipHostMalloc(&B->h_tol, 2 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&B->h_itol, nprob * sizeof(double)) != hipSuccess)
-        return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+    // the batch's pinned host tables, cut from one pooled block
+    {
+        size_t need = 0;
+        auto room = [&](size_t bytes) {
+            const size_t o = need;
+            need += (bytes + 63) & ~size_t(63);
+            return o;
+        };
+        const size_t n = (size_t)nprob;
+        const size_t o_relres = room(n * sizeof(double)), o_active = room(n * sizeof(int)),
+                     o_count = room(sizeof(int)), o_tol = room(2 * sizeof(double)),
+                     o_itol = room(n * sizeof(double)), o_user = room(3 * n * sizeof(double *)),
+                     o_rb64 = room(n * sizeof(StreamArgs<double>)), o_rb32 = room(n * sizeof(StreamArgs<float>)),
+                     o_rbact = room(n * sizeof(int)), o_eptr = room(n * sizeof(float *)),
+                     o_act2 = room(n * sizeof(int));
+        if (hbmg::pinned_block(&B->h_block, need, &B->h_block_cap) != hipSuccess)
+            return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
+        char *base = static_cast<char *>(B->h_block);
+        B->h_relres = reinterpret_cast<double *>(base + o_relres);
+        B->h_active = reinterpret_cast<int *>(base + o_active);
+        B->h_count = reinterpret_cast<int *>(base + o_count);
+        B->h_tol = reinterpret_cast<double *>(base + o_tol);
+        B->h_itol = reinterpret_cast<double *>(base + o_itol);
+        B->h_user = reinterpret_cast<const double **>(base + o_user);
+        B->h_rb64 = reinterpret_cast<StreamArgs<double> *>(base + o_rb64);
+        B->h_rb32 = reinterpret_cast<StreamArgs<float> *>(base + o_rb32);
+        B->h_rbact = reinterpret_cast<int *>(base + o_rbact);
+        B->h_eptr = reinterpret_cast<float **>(base + o_eptr);
+        B->h_act2 = reinterpret_cast<int *>(base + o_act2);
+    }
     // the finest level pipelined across cycles when every problem's is (as
     // hipbmg_setup decided it: 5-point, V(2,1), not collapsed); its pass forms
     // the diagonal when every problem's operator allows it.
@@ -3055,12 +3121,6 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
             }
             chk(balloc(B, &B->d_rbact, nprob, s));
             if (st != HIPBMG_OK) return bail(st);
-            if (hipHostMalloc(&B->h_rb64, nprob * sizeof(StreamArgs<double>)) != hipSuccess ||
-                hipHostMalloc(&B->h_rb32, nprob * sizeof(StreamArgs<float>)) != hipSuccess ||
-                hipHostMalloc(&B->h_rbact, nprob * sizeof(int)) != hipSuccess ||
-                hipHostMalloc(&B->h_eptr, nprob * sizeof(float *)) != hipSuccess ||
-                hipHostMalloc(&B->h_act2, nprob * sizeof(int)) != hipSuccess)
-                return bail(fail(HIPBMG_ENOMEM, "hipHostMalloc failed"));
         }
     }
     st = tune_batch(B, s);
@@ -3167,14 +3227,19 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
     HIPCHK(hipEventRecord(B->ev_in, s_user));
     HIPCHK(hipStreamWaitEvent(s, B->ev_in, 0));
     const int n = B->n;
+    for (int p = 0; p < n; ++p)
+        if (!b[p] || !u[p]) return fail(HIPBMG_EINVAL, "problem %d: null pointer", p);
+    // every problem's b and u into its finest level in one launch, the
+    // boundary ring cleared
+    for (int p = 0; p < n; ++p) {
+        B->h_user[p] = b[p];
+        B->h_user[n + p] = u[p];
+    }
+    HIPCHK(hipMemcpyAsync(B->d_user, B->h_user, 2 * n * sizeof(double *), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_stage_batched(B->d_user, B->d_bptr, B->d_xptr, B->d_dims, B->d_rowoff, n, B->rows, 0, s));
     for (int p = 0; p < n; ++p) {
         hipbmg_hier *h = B->hs[p];
         const LevelDev<double> &F = h->lv[h->L - 1];
-        if (!b[p] || !u[p]) return fail(HIPBMG_EINVAL, "problem %d: null pointer", p);
-        HIPCHK(hipMemcpy2DAsync(F.b, F.pitch * sizeof(double), b[p], F.nx * sizeof(double), F.nx * sizeof(double),
-                                F.ny, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpy2DAsync(F.x[0], F.pitch * sizeof(double), u[p], F.nx * sizeof(double),
-                                F.nx * sizeof(double), F.ny, hipMemcpyDeviceToDevice, s));
         if (infos) {
             memset(&infos[p], 0, sizeof(hipbmg_info));
             fill_info_common(h, &infos[p]);
@@ -3182,9 +3247,6 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
             infos[p].rb_pipelined = B->pipe ? batch_rb(B, F) : 0;
         }
     }
-    const int maxn = std::max(B->max_nx, B->max_ny);
-    HIPCHK(launch_zero_ring_batched(B->d_bptr, B->d_dims, maxn, n, s));
-    HIPCHK(launch_zero_ring_batched(B->d_xptr, B->d_dims, maxn, n, s));
     STCHK(batch_bnorm(B, s));
     HIPCHK(hipMemcpyAsync(B->h_relres, B->d_bnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -3321,16 +3383,15 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         }
         for (int p = 0; p < n; ++p) done_cur[p] = 0;
     }
+    // every problem's result (zero where b is) to its u in one launch
     for (int p = 0; p < n; ++p) {
         hipbmg_hier *h = B->hs[p];
         const LevelDev<double> &F = h->lv[h->L - 1];
-        if (bnorm[p] == 0.0) {
-            HIPCHK(hipMemsetAsync(u[p], 0, (size_t)F.nx * F.ny * sizeof(double), s));
-        } else {
-            const double *src = res64[p] ? res64[p] : F.x[done_cur[p]];
-            HIPCHK(hipMemcpy2DAsync(u[p], F.nx * sizeof(double), src, F.pitch * sizeof(double),
-                                    F.nx * sizeof(double), F.ny, hipMemcpyDeviceToDevice, s));
-        }
+        B->h_user[2 * n + p] = bnorm[p] == 0.0 ? nullptr : res64[p] ? res64[p] : F.x[done_cur[p]];
+    }
+    HIPCHK(hipMemcpyAsync(B->d_user + 2 * n, B->h_user + 2 * n, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_stage_batched(B->d_user, B->d_bptr, B->d_xptr, B->d_dims, B->d_rowoff, n, B->rows, 1, s));
+    for (int p = 0; p < n; ++p) {
         const bool ok = bnorm[p] == 0.0 || rel[p] <= tol;
         if (!std::isfinite(rel[p]) || !std::isfinite(bnorm[p])) result = HIPBMG_ENAN;
         else if (!ok && result == HIPBMG_OK) result = HIPBMG_ENOCONV;

@@ -33,6 +33,11 @@ void dev_free_all(std::vector<void *> &v);
 // pinned_small_free returns it to the pool (null is accepted)
 hipError_t pinned_small(void **host, void **dev, size_t bytes);
 void pinned_small_free(void *host);
+// a zeroed pinned host block of at least `bytes` (its size, a power of two of
+// at least 4 KiB, in *cap) from a per-size pool kept for the process;
+// pinned_block_free returns it (null is accepted)
+hipError_t pinned_block(void **host, size_t bytes, size_t *cap);
+void pinned_block_free(void *host, size_t cap);
 
 // Weight plane indices (fine vertex of coarse cell (I,J) -> coarse corner).
 enum { WXL = 0, WXR = 1, WYB = 2, WYT = 3, WCSW = 4, WCSE = 5, WCNW = 6, WCNE = 7 };

@@ -26,6 +26,13 @@ hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<
 // pointers with the FP32 level's pitch), or the FP32 finest x[0] if eptr is null
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
                                     const int *active, int max_nx, int max_ny, int nprob, hipStream_t s);
-hipError_t launch_zero_ring_batched(double *const *v, const int4 *dims, int maxn, int nprob, hipStream_t s);
+// the caller's arrays of a batch to and from the finest levels' padded planes,
+// one wave per row over all problems (rowoff[p]: the first row of problem p in
+// the batch, rowoff[nprob] the rows of all; dims[p] = (nx, ny, pitch)).
+// In (out == 0): user[p] -> bdst[p] and user[nprob + p] -> xdst[p], with 0 on
+// the boundary ring.  Out (out == 1): user[2 nprob + p] (padded; null gives
+// zeros) -> user[nprob + p], every vertex as it is.
+hipError_t launch_stage_batched(const double *const *user, double *const *bdst, double *const *xdst,
+                                const int4 *dims, const int *rowoff, int nprob, int rows, int out, hipStream_t s);
 
 }  // namespace hbmg

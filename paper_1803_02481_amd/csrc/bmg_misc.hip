@@ -1,7 +1,10 @@
 // bmg_misc.hip -- small element-wise kernels of the solve driver: boundary ring
-// clearing, FP32 demotion of a level into edge form, and the FP64 outer steps
-// of mixed-precision iterative refinement.
+// clearing, FP32 demotion of a level into edge form, the FP64 outer steps of
+// mixed-precision iterative refinement, and a batch's copies of the caller's
+// arrays to and from its finest levels.
 #include "bmg_misc.h"
+
+#include <algorithm>
 
 namespace hbmg {
 
@@ -224,25 +227,62 @@ hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<fl
     return hipGetLastError();
 }
 
-__global__ void k_zero_ring_batched(double *const *__restrict__ v, const int4 *__restrict__ dims)
+// one wave per row of the batch; the row's problem by bisection of the row
+// offsets (the same for all lanes of the wave)
+template <bool OUT>
+__global__ __launch_bounds__(256) void k_stage_batched(const double *const *__restrict__ user,
+                                                       double *const *__restrict__ bdst,
+                                                       double *const *__restrict__ xdst,
+                                                       const int4 *__restrict__ dims,
+                                                       const int *__restrict__ rowoff, int nprob, int rows)
 {
-    const int p = blockIdx.y;
-    const int4 dd = dims[p];
-    double *x = v[p];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < dd.x) {
-        x[k] = 0.0;
-        x[(size_t)(dd.y - 1) * dd.z + k] = 0.0;
-    }
-    if (k < dd.y) {
-        x[(size_t)k * dd.z] = 0.0;
-        x[(size_t)k * dd.z + dd.x - 1] = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int total = OUT ? rows : 2 * rows;
+    for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < total; r += waves) {
+        const int w = r >= rows;              // in: 0 the right-hand side, 1 the iterate
+        const int rr = r - w * rows;
+        int lo = 0, hi = nprob;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rowoff[mid] <= rr) lo = mid;
+            else hi = mid;
+        }
+        const int p = lo;
+        const int4 dd = dims[p];
+        const int j = rr - rowoff[p];
+        if (OUT) {
+            const double *src = user[2 * nprob + p];
+            double *dst = const_cast<double *>(user[nprob + p]) + (size_t)j * dd.x;
+            if (src) {
+                src += (size_t)j * dd.z;
+#pragma unroll 4
+                for (int i = lane; i < dd.x; i += 64) dst[i] = src[i];
+            } else {
+                for (int i = lane; i < dd.x; i += 64) dst[i] = 0.0;
+            }
+        } else {
+            const double *src = user[w * nprob + p] + (size_t)j * dd.x;
+            double *dst = (w ? xdst : bdst)[p] + (size_t)j * dd.z;
+            const bool edge = j == 0 || j == dd.y - 1;
+#pragma unroll 4
+            for (int i = lane; i < dd.x; i += 64)
+                dst[i] = edge || i == 0 || i == dd.x - 1 ? 0.0 : src[i];
+        }
     }
 }
 
-hipError_t launch_zero_ring_batched(double *const *v, const int4 *dims, int maxn, int nprob, hipStream_t s)
+hipError_t launch_stage_batched(const double *const *user, double *const *bdst, double *const *xdst,
+                                const int4 *dims, const int *rowoff, int nprob, int rows, int out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_ring_batched, dim3((maxn + 255) / 256, nprob), dim3(256), 0, s, v, dims);
+    const int total = out ? rows : 2 * rows;
+    const int blocks = std::max(1, std::min((total + 3) / 4, 4096));
+    if (out)
+        hipLaunchKernelGGL(k_stage_batched<true>, dim3(blocks), dim3(256), 0, s, user, bdst, xdst, dims, rowoff,
+                           nprob, rows);
+    else
+        hipLaunchKernelGGL(k_stage_batched<false>, dim3(blocks), dim3(256), 0, s, user, bdst, xdst, dims, rowoff,
+                           nprob, rows);
     return hipGetLastError();
 }
 

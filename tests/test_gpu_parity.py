@@ -558,6 +558,34 @@ def test_batched_tile_shape_does_not_change_the_iterate(precision, monkeypatch):
             bh.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_setup_threads_do_not_change_the_batch(precision, monkeypatch):
+    # a batch of more problems than setup threads, built on the worker
+    # threads (each taking several problems) and in turn on the caller's
+    # stream: every hierarchy is built by the same calls, so the tile shapes,
+    # cycle counts and iterates are the same bits
+    monkeypatch.delenv("HIPBMG_BATCH_WPG", raising=False)
+    monkeypatch.delenv("HIPBMG_RB", raising=False)
+    sizes = [(33 + 32 * (k % 4), 65 + 32 * ((k // 4) % 3)) for k in range(21)]
+    planes, bs = batch_case(sizes, seed0=130)
+    prec = HB.FP64 if precision == "fp64" else HB.MIXED
+    runs = []
+    for nth in ("1", "8", "3"):
+        monkeypatch.setenv("HIPBMG_SETUP_THREADS", nth)
+        bh = HB.BatchHierarchy([g(p) for p in planes], precision=prec, collapse_level=1)
+        shapes = [bh.tile_shape(k, bh_levels_top(bh, k)) for k in range(len(sizes))]
+        us, infos = bh.solve([g(b) for b in bs], tol=1e-10)
+        runs.append((shapes, [i.cycles for i in infos], us))
+        bh.close()
+    for k in (0, 7, 20):
+        assert oracle_relres(planes[k], bs[k], c(runs[0][2][k])) <= 1.2e-10, k
+    for shapes, cyc, us in runs[1:]:
+        assert shapes == runs[0][0]
+        assert cyc == runs[0][1]
+        for k in range(len(sizes)):
+            assert torch.equal(us[k], runs[0][2][k]), k
+
+
 def bh_levels_top(bh, problem):
     # the finest level of a problem: the highest level index tile_shape accepts
     l = 0
