@@ -396,19 +396,39 @@ static void prof_collect(hipbmg_hier *h, bool wait, int last_cycle = 1 << 30, bo
 static int pitch_for(int nx) { return (nx + 63) / 64 * 64; }   // >= nx+1 for odd nx
 
 // A handle's device arrays, zeroed, 256-byte aligned and 256 bytes longer than
-// asked.  Arrays of at most 8 MiB are cut from chunks that are zeroed once when
-// taken (1 MiB, then doubling to 16 MiB, so a small hierarchy stays small), so
-// a hierarchy makes a few allocator calls and fills, not one of each per array
-// (each costs microseconds on the host, and the binding's allocator is a
-// Python callback); larger arrays get a block of their own.
+// asked.  The setup reserves one zeroed block for every array it knows it will
+// cut (the levels, the pipelined pass's third iterate and some room for the
+// small ones) and cuts them from it in order, so a hierarchy makes one
+// allocator call and one fill for them, not one of each per array (each costs
+// microseconds of host time, serialised in the runtime when many hierarchies
+// are built at once, and the binding's allocator is a Python callback).  An
+// array that no longer fits is cut from a chunk zeroed once when taken (1 MiB,
+// doubling to 16 MiB) if it is at most 8 MiB, and gets a block of its own if
+// larger.
 constexpr size_t ARENA_CHUNK = size_t(16) << 20;
+
+static size_t dalloc_bytes(size_t n, size_t elem) { return (n * elem + 256 + 255) / 256 * 256; }
+
+static hipbmg_status arena_reserve(hipbmg_hier *h, size_t bytes, hipStream_t s)
+{
+    void *q = nullptr;
+    if (dev_malloc(&q, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    h->allocs.push_back(q);
+    HIPCHK(hipMemsetAsync(q, 0, bytes, s));
+    h->arena = static_cast<char *>(q);
+    h->arena_left = bytes;
+    return HIPBMG_OK;
+}
 
 template <typename T>
 static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
 {
-    const size_t bytes = (n * sizeof(T) + 256 + 255) / 256 * 256;
+    const size_t bytes = dalloc_bytes(n, sizeof(T));
     void *q = nullptr;
-    if (bytes > ARENA_CHUNK / 2) {
+    if (bytes > h->arena_left && bytes > ARENA_CHUNK / 2) {
         if (dev_malloc(&q, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return fail(HIPBMG_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
@@ -434,6 +454,18 @@ static hipbmg_status dalloc(hipbmg_hier *h, T **p, size_t n, hipStream_t s)
     h->arena += bytes;
     h->arena_left -= bytes;
     return HIPBMG_OK;
+}
+
+// bytes alloc_levels cuts for levels of these sizes
+template <typename T>
+static size_t levels_bytes(const std::vector<int> &sx, const std::vector<int> &sy)
+{
+    size_t t = 0;
+    for (size_t l = 0; l < sx.size(); ++l) {
+        t += dalloc_bytes((size_t)sy[l] * pitch_for(sx[l]) * 9, sizeof(T));
+        if (l >= 1) t += dalloc_bytes((size_t)sy[l - 1] * pitch_for(sx[l - 1]) * 8, sizeof(T));
+    }
+    return t;
 }
 
 // grid barriers of the agglomeration stages and their give-up flag (zero)
@@ -749,17 +781,22 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         delete h;
         return st;
     };
+    {
+        const bool mixed = prm.precision == HIPBMG_MIXED;
+        const size_t fplane = (size_t)ny * pitch_for(nx);
+        size_t need = levels_bytes<double>(sx, sy) + (mixed ? levels_bytes<float>(sx, sy) : 0) + (size_t(1) << 20);
+        if (npt == 5 && prm.nu1 == 2 && prm.nu2 == 1 && L >= 2)
+            need += dalloc_bytes(fplane, sizeof(double)) + (mixed ? dalloc_bytes(fplane, sizeof(float)) : 0);
+        const hipbmg_status rs = arena_reserve(h, need, s);
+        if (rs != HIPBMG_OK) return bail(rs);
+    }
     hipbmg_status st = alloc_levels(h, h->lv, sx, sy, s);
     if (st != HIPBMG_OK) return bail(st);
     // finest operator, as given
     LevelDev<double> &F = h->lv[L - 1];
     const int nplanes = npt == 5 ? 3 : 5;
-    for (int k = 0; k < nplanes; ++k) {
-        if (hipMemcpy2DAsync(F.C + k * F.plane, F.pitch * sizeof(double),
-                             coeffs + (size_t)k * nx * ny, nx * sizeof(double), nx * sizeof(double),
-                             ny, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return bail(fail(HIPBMG_EHIP, "copy of the stencil planes failed (device pointer?)"));
-    }
+    if (launch_planes_in(coeffs, nx, ny, nplanes, F.C, F.pitch, F.plane, s) != hipSuccess)
+        return bail(fail(HIPBMG_EHIP, "copy of the stencil planes failed"));
     // coarse operators: interpolation weights and Galerkin products.  On the
     // large coarse levels whose up leg forms r/C from its rows, a vertex at
     // least two vertices from the boundary has a zero row sum in exact
@@ -778,13 +815,34 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     int *d_zflag = nullptr;
     st = dalloc(h, &d_zflag, 1, s);
     if (st != HIPBMG_OK) return bail(st);
+    // the smallest levels (coarse grids of at most SETUP_TAIL_POINTS vertices,
+    // none of them forming its diagonal) in one launch (HIPBMG_SETUP_TAIL=0:
+    // two launches per level throughout)
+    auto zc9_here = [&](const LevelDev<double> &c) {
+        return !no_zc9 && c.npt == 9 && rc_on_the_fly(h, c.nx, c.ny, false);
+    };
+    int l_tail = 0;
+    {
+        int tail_on = 1;
+        if (const char *e = std::getenv("HIPBMG_SETUP_TAIL")) tail_on = std::atoi(e);
+        while (tail_on && l_tail + 1 <= L - 1 && l_tail + 1 <= SETUP_TAIL_MAX &&
+               (long long)h->lv[l_tail].nx * h->lv[l_tail].ny <= SETUP_TAIL_POINTS && !zc9_here(h->lv[l_tail]))
+            ++l_tail;
+        if (l_tail < 2) l_tail = 0;   // one level: no launch to save
+    }
     for (int l = L - 1; l >= 1; --l) {
         const LevelDev<double> &f = h->lv[l], &c = h->lv[l - 1];
+        if (l <= l_tail) {
+            if (launch_setup_tail(h->lv.data(), l_tail, s) != hipSuccess)
+                return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
+                                 hipGetErrorString(hipGetLastError())));
+            break;
+        }
         if (launch_interp_weights(f, c.nx, c.ny, f.wt, f.cpitch, f.cplane, s) != hipSuccess ||
             launch_rap(f, c, s) != hipSuccess)
             return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
                              hipGetErrorString(hipGetLastError())));
-        if (!no_zc9 && c.npt == 9 && rc_on_the_fly(h, c.nx, c.ny, false)) {
+        if (zc9_here(c)) {
             int ok = 0;
             if (launch_rowsum_diag(c, d_zflag, 0, s) != hipSuccess ||
                 hipMemcpyAsync(&ok, d_zflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||

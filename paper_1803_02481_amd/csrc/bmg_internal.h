@@ -167,6 +167,12 @@ hipError_t launch_grad_logD(int nx, int ny, const double *theta, const double *u
 hipError_t launch_interp_weights(const LevelDev<double> &f, int cnx, int cny, double *wt,
                                  int cpitch, size_t cplane, hipStream_t s);
 hipError_t launch_rap(const LevelDev<double> &f, const LevelDev<double> &c, hipStream_t s);
+// weights and Galerkin products of levels l_top .. 1 (each coarse level of at
+// most SETUP_TAIL_POINTS vertices, l_top <= SETUP_TAIL_MAX) in one launch of
+// one workgroup, the same values as launch_interp_weights and launch_rap
+// level by level
+constexpr int SETUP_TAIL_MAX = 6, SETUP_TAIL_POINTS = 512;
+hipError_t launch_setup_tail(const LevelDev<double> *lv, int l_top, hipStream_t s);
 
 // Collapsed coarse levels: one persistent workgroup runs levels top..0 of the
 // V-cycle.  The iterate of a collapsed level below `top` is x[1] and x[0] holds

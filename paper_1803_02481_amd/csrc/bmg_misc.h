@@ -26,6 +26,10 @@ hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<
 // pointers with the FP32 level's pitch), or the FP32 finest x[0] if eptr is null
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
                                     const int *active, int max_nx, int max_ny, int nprob, hipStream_t s);
+// planes [nplanes][ny][nx] (contiguous) into a level's padded planes
+// (dst + k * plane, rows of `pitch`); the padding is left as it is
+hipError_t launch_planes_in(const double *src, int nx, int ny, int nplanes, double *dst, int pitch, size_t plane,
+                            hipStream_t s);
 // the caller's arrays of a batch to and from the finest levels' padded planes,
 // one wave per row over all problems (rowoff[p]: the first row of problem p in
 // the batch, rowoff[nprob] the rows of all; dims[p] = (nx, ny, pitch)).

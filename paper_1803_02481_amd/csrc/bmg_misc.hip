@@ -227,6 +227,22 @@ hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<fl
     return hipGetLastError();
 }
 
+__global__ void k_planes_in(const double *__restrict__ src, int nx, int ny, double *__restrict__ dst, int pitch,
+                            size_t plane)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
+    if (i < nx) dst[k * plane + (size_t)j * pitch + i] = src[((size_t)k * ny + j) * nx + i];
+}
+
+hipError_t launch_planes_in(const double *src, int nx, int ny, int nplanes, double *dst, int pitch, size_t plane,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_planes_in, dim3((nx + 255) / 256, ny, nplanes), dim3(256), 0, s, src, nx, ny, dst, pitch,
+                       plane);
+    return hipGetLastError();
+}
+
 // one wave per row of the batch; the row's problem by bisection of the row
 // offsets (the same for all lanes of the wave)
 template <bool OUT>

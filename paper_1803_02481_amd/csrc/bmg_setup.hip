@@ -141,12 +141,10 @@ __device__ void yline_w(const StView &A, int i, int j, double &ws, double &wn)
                   A.sw(i + 1, j + 1), A.se(i - 1, j + 1), ws, wn);
 }
 
-__global__ void k_interp_weights(StView A, int cnx, int cny, double *__restrict__ wt, int cpitch,
-                                 size_t cplane)
+// the 8 weights stored at coarse vertex (I, J)
+__device__ __forceinline__ void interp_weights_at(const StView &A, int cnx, int cny, double *__restrict__ wt,
+                                                  int cpitch, size_t cplane, int I, int J)
 {
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    int J = blockIdx.y;
-    if (I >= cnx) return;
     auto cin = [&](int a, int b) { return a >= 1 && a <= cnx - 2 && b >= 1 && b <= cny - 2; };
     double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // x-line vertex (2I+1, 2J)
@@ -182,6 +180,15 @@ __global__ void k_interp_weights(StView A, int cnx, int cny, double *__restrict_
     if (!cin(I + 1, J + 1)) w[WCNE] = 0.0;
     size_t o = (size_t)J * cpitch + I;
     for (int k = 0; k < 8; ++k) wt[k * cplane + o] = w[k];
+}
+
+__global__ void k_interp_weights(StView A, int cnx, int cny, double *__restrict__ wt, int cpitch,
+                                 size_t cplane)
+{
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int J = blockIdx.y;
+    if (I >= cnx) return;
+    interp_weights_at(A, cnx, cny, wt, cpitch, cplane, I, J);
 }
 
 hipError_t launch_interp_weights(const LevelDev<double> &f, int cnx, int cny, double *wt,
@@ -233,13 +240,11 @@ __device__ __forceinline__ double Aent(const StView &A, int i, int j, int sx, in
     return -A.se(i - 1, j + 1);
 }
 
-__global__ __launch_bounds__(128) void k_rap(StView A, WView P, double *__restrict__ Cc, double *__restrict__ Wc,
-                      double *__restrict__ Sc, double *__restrict__ SWc, double *__restrict__ SEc,
-                      int cpitch)
+// the five stored entries of A_c at coarse vertex (I, J)
+__device__ __forceinline__ void rap_at(const StView &A, const WView &P, double *__restrict__ Cc,
+                                       double *__restrict__ Wc, double *__restrict__ Sc, double *__restrict__ SWc,
+                                       double *__restrict__ SEc, int cpitch, int I, int J)
 {
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    int J = blockIdx.y;
-    if (I >= P.cnx) return;
     const int cnx = P.cnx, cny = P.cny;
     auto cin = [&](int a, int b) { return a >= 1 && a <= cnx - 2 && b >= 1 && b <= cny - 2; };
     double out[5] = {0, 0, 0, 0, 0};
@@ -312,12 +317,75 @@ __global__ __launch_bounds__(128) void k_rap(StView A, WView P, double *__restri
     SEc[o] = out[4];
 }
 
+__global__ __launch_bounds__(128) void k_rap(StView A, WView P, double *__restrict__ Cc, double *__restrict__ Wc,
+                      double *__restrict__ Sc, double *__restrict__ SWc, double *__restrict__ SEc,
+                      int cpitch)
+{
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    int J = blockIdx.y;
+    if (I >= P.cnx) return;
+    rap_at(A, P, Cc, Wc, Sc, SWc, SEc, cpitch, I, J);
+}
+
 hipError_t launch_rap(const LevelDev<double> &f, const LevelDev<double> &c, hipStream_t s)
 {
     StView A{f.nx, f.ny, f.pitch, f.C, f.W, f.S, f.SW, f.SE, f.npt};
     WView P{f.wt, c.nx, c.ny, c.pitch, c.plane};   // weights onto f live at c's resolution
     dim3 b(128), g((c.nx + 127) / 128, c.ny);
     hipLaunchKernelGGL(k_rap, g, b, 0, s, A, P, c.C, c.W, c.S, c.SW, c.SE, c.pitch);
+    return hipGetLastError();
+}
+
+// The smallest levels' weights and Galerkin products, level after level, in
+// one workgroup: the same per-vertex functions as the two kernels above, with
+// a barrier between the steps (each step reads what the step before wrote),
+// instead of two short launches per level.
+struct TailLevel {
+    StView A;
+    WView P;
+    double *C, *W, *S, *SW, *SE;
+    int cpitch;
+};
+struct TailArgs {
+    int n;
+    TailLevel lv[SETUP_TAIL_MAX];
+};
+
+__global__ __launch_bounds__(256) void k_setup_tail(TailArgs a)
+{
+#pragma unroll
+    for (int k = 0; k < SETUP_TAIL_MAX; ++k) {
+        if (k >= a.n) break;
+        const TailLevel &t = a.lv[k];
+        const int cnx = t.P.cnx, npts = cnx * t.P.cny;
+        double *wt = const_cast<double *>(t.P.wt);
+        for (int v = threadIdx.x; v < npts; v += blockDim.x)
+            interp_weights_at(t.A, cnx, t.P.cny, wt, t.P.cpitch, t.P.cplane, v % cnx, v / cnx);
+        __syncthreads();
+        for (int v = threadIdx.x; v < npts; v += blockDim.x)
+            rap_at(t.A, t.P, t.C, t.W, t.S, t.SW, t.SE, t.cpitch, v % cnx, v / cnx);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_setup_tail(const LevelDev<double> *lv, int l_top, hipStream_t s)
+{
+    if (l_top < 1 || l_top > SETUP_TAIL_MAX) return hipErrorInvalidValue;
+    TailArgs a{};
+    a.n = l_top;
+    for (int k = 0; k < l_top; ++k) {
+        const LevelDev<double> &f = lv[l_top - k], &c = lv[l_top - k - 1];
+        if ((long long)c.nx * c.ny > SETUP_TAIL_POINTS) return hipErrorInvalidValue;
+        a.lv[k].A = StView{f.nx, f.ny, f.pitch, f.C, f.W, f.S, f.SW, f.SE, f.npt};
+        a.lv[k].P = WView{f.wt, c.nx, c.ny, c.pitch, c.plane};
+        a.lv[k].C = c.C;
+        a.lv[k].W = c.W;
+        a.lv[k].S = c.S;
+        a.lv[k].SW = c.SW;
+        a.lv[k].SE = c.SE;
+        a.lv[k].cpitch = c.pitch;
+    }
+    hipLaunchKernelGGL(k_setup_tail, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

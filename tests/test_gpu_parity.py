@@ -149,6 +149,23 @@ def test_setup_stencils_and_weights_match_oracle(nx, ny, npt, seed):
         assert drift <= 1e-13 * 4.0 ** depth, ("drift", l - 1, drift)
 
 
+@pytest.mark.parametrize("nx,ny,npt,seed", CASES + [(129, 33, 5, 7), (65, 257, 9, 8), (17, 17, 5, 9)])
+def test_setup_tail_launch_gives_the_same_levels(nx, ny, npt, seed, monkeypatch):
+    # the smallest levels' weights and Galerkin products in one workgroup
+    # launch against two launches per level: every level's stencil and weights
+    # byte for byte
+    planes = make_planes(nx, ny, npt, seed)
+    monkeypatch.setenv("HIPBMG_SETUP_TAIL", "0")
+    ref = HB.Hierarchy(g(planes))
+    monkeypatch.delenv("HIPBMG_SETUP_TAIL")
+    hier = HB.Hierarchy(g(planes))
+    assert hier.L == ref.L
+    for l in range(hier.L):
+        assert torch.equal(hier.stencil(l), ref.stencil(l)), ("stencil", l)
+        if l >= 1:
+            assert torch.equal(hier.interp(l), ref.interp(l)), ("weights", l)
+
+
 def test_setup_constant_D_closed_form_on_gpu():
     # interior Galerkin stencils of the D=1 Laplacian are dyadic (see the oracle pins)
     n = 257
