@@ -138,9 +138,10 @@ void hipbmg_default_params(hipbmg_params *p);
  * gives out again is no longer in use by the library's streams.  The
  * callbacks may be called from any library call that builds or destroys a
  * handle (the solves allocate nothing), and from the worker threads of
- * hipbmg_setup_batched, so they must be thread-safe.  A 2D hierarchy asks for one block
- * per array larger than 8 MiB and cuts its smaller arrays from blocks of 1, 2,
- * 4, 8, then 16 MiB, so it makes a few calls, not one per array.  The one-time
+ * hipbmg_setup_batched, so they must be thread-safe.  A 2D hierarchy asks for
+ * one block sized for all its levels (and a little more) at setup and cuts its
+ * arrays from it; only arrays that no longer fit ask for more (blocks of 1, 2,
+ * 4, 8, then 16 MiB, or one block per array larger than 8 MiB).  The one-time
  * machine calibration keeps its scratch on hipMalloc.  Host only; thread-safe. */
 typedef void *(*hipbmg_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*hipbmg_free_fn)(void *ptr, void *ctx);
