@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -2487,6 +2488,8 @@ struct hipbmg_batch {
     int *h_act2 = nullptr;
     void *h_block = nullptr;                  // pinned block holding every h_ table above
     size_t h_block_cap = 0;
+    char *tab_next = nullptr;                 // unused part of the current table chunk
+    size_t tab_left = 0;
     std::vector<void *> seg_allocs;           // norm segment tables (rebuilt with the plans)
     hipStream_t ws = nullptr;                 // own stream: graphs cannot be captured on the null stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -2521,10 +2524,23 @@ static hipbmg_status balloc_to(std::vector<void *> &owner, T **p, size_t n, hipS
     return HIPBMG_OK;
 }
 
+// the batch's own tables: up to 256 KiB cut from zeroed 1 MiB chunks, larger
+// ones a block each (zeroed, 64 bytes longer than asked)
 template <typename T>
 static hipbmg_status balloc(hipbmg_batch *B, T **p, size_t n, hipStream_t s)
 {
-    return balloc_to(B->allocs, p, n, s);
+    const size_t bytes = (n * sizeof(T) + 64 + 255) / 256 * 256;
+    if (bytes > (size_t(256) << 10)) return balloc_to(B->allocs, p, n, s);
+    if (bytes > B->tab_left) {
+        char *c = nullptr;
+        STCHK(balloc_to(B->allocs, &c, (size_t(1) << 20) - 64, s));
+        B->tab_next = c;
+        B->tab_left = size_t(1) << 20;
+    }
+    *p = reinterpret_cast<T *>(B->tab_next);
+    B->tab_next += bytes;
+    B->tab_left -= bytes;
+    return HIPBMG_OK;
 }
 
 template <typename T>
@@ -2707,7 +2723,18 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
         for (auto &kk : dd)
             for (Rec &r : kk) r.a.partials = parts + poff[r.p];
     for (int p = 0; p < n; ++p) cargs[p].partials = parts + poff[p];
-    // materialise the stages
+    // materialise the stages: every launch's tables are packed into one host
+    // buffer, uploaded to one device block of the plan (one allocation and one
+    // copy per plan, not two of each per launch)
+    const size_t first_launch = plan.launches.size();
+    std::vector<char> tab;
+    std::vector<std::pair<size_t, size_t>> offs;   // per launch: args, map (SIZE_MAX: none)
+    auto put = [&](const void *src, size_t bytes) {
+        const size_t o = (tab.size() + 255) / 256 * 256;
+        tab.resize(o + bytes);
+        std::memcpy(tab.data() + o, src, bytes);
+        return o;
+    };
     auto add_stage = [&](std::vector<Rec> &recs) -> hipbmg_status {
         if (recs.empty()) return HIPBMG_OK;
         std::vector<StreamArgs<T>> args(n);
@@ -2724,14 +2751,9 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
         bl.variant = recs[0].variant;
         bl.wpg = B->wpg;
         bl.zc = B->zc[PrecIdx<T>::v];
-        StreamArgs<T> *da = nullptr;
-        int2 *dm = nullptr;
-        STCHK(balloc_to(plan.allocs, &da, n, s));
-        STCHK(balloc_to(plan.allocs, &dm, map.size(), s));
-        HIPCHK(hipMemcpyAsync(da, args.data(), n * sizeof(StreamArgs<T>), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(dm, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-        bl.d_args = da;
-        bl.d_map = dm;
+        const size_t oa = put(args.data(), n * sizeof(StreamArgs<T>));
+        const size_t om = put(map.data(), map.size() * sizeof(int2));
+        offs.push_back({oa, om});
         bl.nmap = (int)map.size();
         plan.launches.push_back(bl);
         return HIPBMG_OK;
@@ -2741,15 +2763,20 @@ static hipbmg_status build_plan(hipbmg_batch *B, int cur, bool zero_start, BPlan
     {
         BLaunch bl{};
         bl.kind = 1;
-        CollapseArgs<T> *dc = nullptr;
-        STCHK(balloc_to(plan.allocs, &dc, n, s));
-        HIPCHK(hipMemcpyAsync(dc, cargs.data(), n * sizeof(CollapseArgs<T>), hipMemcpyHostToDevice, s));
-        bl.d_args = dc;
+        offs.push_back({put(cargs.data(), n * sizeof(CollapseArgs<T>)), SIZE_MAX});
         bl.lds_bytes = lds_max;
         plan.launches.push_back(bl);
     }
     for (int d = (int)up.size() - 1; d >= 0; --d)
         for (auto &kk : up[d]) STCHK(add_stage(kk));
+    char *dt = nullptr;
+    STCHK(balloc_to(plan.allocs, &dt, tab.size(), s));
+    HIPCHK(hipMemcpyAsync(dt, tab.data(), tab.size(), hipMemcpyHostToDevice, s));
+    for (size_t k = 0; k < offs.size(); ++k) {
+        BLaunch &bl = plan.launches[first_launch + k];
+        bl.d_args = dt + offs[k].first;
+        bl.d_map = offs[k].second == SIZE_MAX ? nullptr : reinterpret_cast<int2 *>(dt + offs[k].second);
+    }
     HIPCHK(hipStreamSynchronize(s));
     plan.end_cur = end_cur;
     plan.built = true;
