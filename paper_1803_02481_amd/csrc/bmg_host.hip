@@ -853,9 +853,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             h->zc9[0][l - 1] = (char)ok;
         }
     }
-    if (dev_malloc((void **)&h->d_lv, L * sizeof(LevelDev<double>)) != hipSuccess)
-        return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
-    h->allocs.push_back(h->d_lv);
+    st = dalloc(h, &h->d_lv, L, s);
+    if (st != HIPBMG_OK) return bail(st);
     if (hipMemcpyAsync(h->d_lv, h->lv.data(), L * sizeof(LevelDev<double>), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return bail(fail(HIPBMG_EHIP, "hipMemcpyAsync failed"));
@@ -881,9 +880,8 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
                 h->zc9[1][l] = (char)ok;
             }
         }
-        if (dev_malloc((void **)&h->d_lv32, L * sizeof(LevelDev<float>)) != hipSuccess)
-            return bail(fail(HIPBMG_ENOMEM, "device allocation failed"));
-        h->allocs.push_back(h->d_lv32);
+        st = dalloc(h, &h->d_lv32, L, s);
+        if (st != HIPBMG_OK) return bail(st);
         if (hipMemcpyAsync(h->d_lv32, h->lv32.data(), L * sizeof(LevelDev<float>),
                            hipMemcpyHostToDevice, s) != hipSuccess)
             return bail(fail(HIPBMG_EHIP, "hipMemcpyAsync failed"));
@@ -971,9 +969,6 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
         !h->ring_dev)
         return bail(fail(HIPBMG_ENOMEM, "host-mapped allocation failed"));
     for (int k = 0; k < RING * 4; ++k) h->ring_host[k] = 0.0;
-    for (int k = 0; k < RING; ++k)
-        if (hipEventCreateWithFlags(&h->ring_ev[k], hipEventDisableTiming) != hipSuccess)
-            return bail(fail(HIPBMG_EHIP, "event creation failed"));
     if (const char *e = std::getenv("HIPBMG_AHEAD")) {   // cycles enqueued ahead of the last test seen
         const int v = std::atoi(e);
         if (v >= 0 && v < RING) h->ahead = v;
@@ -1378,6 +1373,13 @@ static hipbmg_status run_cycles(hipbmg_hier *h, const std::vector<LevelDev<T>> &
     const int *act = h->d_flags;
     const bool pipe = h->fused3 != 0;
     T *xb[3] = {F.x[0], F.x[1], pipe ? x3_of<T>(h) : nullptr};
+    // the convergence-test events, made on the handle's first solve (the
+    // hierarchies of a batch never need them)
+    for (int k = 0; k < RING; ++k)
+        if (!h->ring_ev[k] && hipEventCreateWithFlags(&h->ring_ev[k], hipEventDisableTiming) != hipSuccess) {
+            h->ring_ev[k] = nullptr;
+            return fail(HIPBMG_EHIP, "event creation failed");
+        }
 
     std::vector<const T *> res_after((size_t)max_cycles + 1, F.x[0]);
     // pipelined: the inputs of each cycle's finest pass (iterate buffer,
