@@ -813,9 +813,11 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
     if (const char *e = std::getenv("HIPBMG_NO_ZC9")) no_zc9 = std::atoi(e);
     if (const char *e = std::getenv("HIPBMG_ZC9_LOAD")) h->zc9_form = std::atoi(e) ? 0 : 1;
     if (const char *e = std::getenv("HIPBMG_INNER_ADAPT")) h->inner_adapt = std::atoi(e);
-    int *d_zflag = nullptr;
+    int *d_zflag = nullptr, *d_zf9 = nullptr;
     st = dalloc(h, &d_zflag, 1, s);
+    if (st == HIPBMG_OK) st = dalloc(h, &d_zf9, L, s);
     if (st != HIPBMG_OK) return bail(st);
+    std::vector<char> zc9_ran(L, 0);
     // the smallest levels (coarse grids of at most SETUP_TAIL_POINTS vertices,
     // none of them forming its diagonal) in one launch (HIPBMG_SETUP_TAIL=0:
     // two launches per level throughout)
@@ -844,14 +846,21 @@ extern "C" hipbmg_status hipbmg_setup(int nx, int ny, int npt, const double *coe
             return bail(fail(HIPBMG_EHIP, "setup kernel launch failed: %s",
                              hipGetErrorString(hipGetLastError())));
         if (zc9_here(c)) {
-            int ok = 0;
-            if (launch_rowsum_diag(c, d_zflag, 0, s) != hipSuccess ||
-                hipMemcpyAsync(&ok, d_zflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess ||
-                (ok && launch_rowsum_diag(c, d_zflag, 1, s) != hipSuccess))
+            // the check, then the store where it passed, both on the device;
+            // the outcomes are read back together after the loop
+            if (launch_rowsum_diag(c, d_zf9 + (l - 1), 0, s) != hipSuccess ||
+                launch_rowsum_diag(c, d_zf9 + (l - 1), 1, s) != hipSuccess)
                 return bail(fail(HIPBMG_EHIP, "row-sum diagonal setup failed"));
-            h->zc9[0][l - 1] = (char)ok;
+            zc9_ran[l - 1] = 1;
         }
+    }
+    if (std::find(zc9_ran.begin(), zc9_ran.end(), 1) != zc9_ran.end()) {
+        std::vector<int> ok(L, 0);
+        if (hipMemcpyAsync(ok.data(), d_zf9, L * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(HIPBMG_EHIP, "row-sum diagonal setup failed"));
+        for (int m = 0; m < L; ++m)
+            if (zc9_ran[m]) h->zc9[0][m] = (char)(ok[m] != 0);
     }
     st = dalloc(h, &h->d_lv, L, s);
     if (st != HIPBMG_OK) return bail(st);

@@ -135,7 +135,8 @@ hipError_t launch_stream3_batched(int variant, int zc, const StreamArgs<T> *args
 // ZC9 (9-point levels whose rows at least two vertices from the boundary have
 // zero row sums): set = 0 sets *flag (device int) to 1 if every such vertex's
 // diagonal is within 1e-12 of the ordered sum of its eight connections, else
-// 0; set = 1 stores that sum as their diagonal.  The FP32 check sets *flag to
+// 0; set = 1 stores that sum as their diagonal if *flag is 1 (read on the
+// device, so no host round trip between the two).  The FP32 check sets *flag to
 // 1 if the edge-form excess is exactly zero there.  The streaming kernels of
 // SV_SWEEP2_R_ZX and SV_INTERP_RC take a.zexc = 1 on such a level.
 hipError_t launch_rowsum_diag(const LevelDev<double> &A, int *flag, int set, hipStream_t s);

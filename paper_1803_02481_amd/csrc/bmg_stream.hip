@@ -879,8 +879,9 @@ __global__ void k_rowsum_diag(LevelDev<double> A, int *flag, int set)
     const size_t p = (size_t)j * A.pitch + i, P = A.pitch;
     const double rs = A.W[p] + A.W[p + 1] + A.S[p] + A.S[p + P] + A.SW[p] + A.SW[p + P + 1] + A.SE[p] +
                       A.SE[p + P - 1];
-    if (set) A.C[p] = rs;
-    else if (!(fabs(A.C[p] - rs) <= 1e-12 * fabs(A.C[p]))) atomicAnd(flag, 0);
+    if (set) {
+        if (*flag) A.C[p] = rs;
+    } else if (!(fabs(A.C[p] - rs) <= 1e-12 * fabs(A.C[p]))) atomicAnd(flag, 0);
 }
 
 // ZC9 check of an FP32 edge-form 9-point level: clear *flag unless every
