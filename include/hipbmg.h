@@ -316,6 +316,13 @@ hipbmg_status hipbmg_batch_tile_shape(hipbmg_batch_handle h, int problem, int le
 hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cell, int is_log,
                                     double *coeffs_out, void *stream);
 
+/* hipbmg_fv5_from_cells for nprob problems of one size in one launch, the
+ * same values problem by problem: cell [nprob][ny-1][nx-1], coeffs_out
+ * [nprob][3][ny][nx] (device).  EINVAL for null pointers, nprob outside
+ * 1..65535 or nx, ny < 3. */
+hipbmg_status hipbmg_fv5_from_cells_batched(int nprob, int nx, int ny, const double *cell, int is_log,
+                                            double *coeffs_out, void *stream);
+
 /* The same stencil for a diagonal diffusion tensor D = diag(Dx, Dy) per cell
  * on a grid of spacings hx, hy (section 5: the stretched grids with
  * compensating anisotropy D = diag(1/r, r)).  The dual face of an x-edge has
@@ -333,6 +340,13 @@ hipbmg_status hipbmg_fv5_aniso(int nx, int ny, const double *dx_cell, const doub
  * theta: [ny-1][nx-1]; u, lam: [ny][nx]; grad_out: [ny-1][nx-1]. */
 hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, const double *u,
                                const double *lam, double *grad_out, void *stream);
+
+/* hipbmg_grad_logD for nprob problems of one size in one launch, the same
+ * values problem by problem: theta, grad_out [nprob][ny-1][nx-1]; u, lam
+ * [nprob][ny][nx] (device).  EINVAL for null pointers, nprob outside
+ * 1..65535 or nx, ny < 3. */
+hipbmg_status hipbmg_grad_logD_batched(int nprob, int nx, int ny, const double *theta, const double *u,
+                                       const double *lam, double *grad_out, void *stream);
 
 /* Live timing of the relaxation kernels, the per-component timers of the
  * paper's experiments (section 5) for one GPU.  While enabled, every solve

@@ -1931,6 +1931,18 @@ extern "C" hipbmg_status hipbmg_fv5_from_cells(int nx, int ny, const double *cel
     return HIPBMG_OK;
 }
 
+extern "C" hipbmg_status hipbmg_fv5_from_cells_batched(int nprob, int nx, int ny, const double *cell, int is_log,
+                                                       double *coeffs_out, void *stream)
+{
+    if (!cell || !coeffs_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (nprob < 1 || nprob > 65535) return fail(HIPBMG_EINVAL, "nprob must be in 1..65535");
+    if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
+    const size_t n = (size_t)nx * ny;
+    HIPCHK(launch_fv5(nx, ny, cell, is_log, coeffs_out, coeffs_out + n, coeffs_out + 2 * n, nx, (hipStream_t)stream,
+                      nprob, 3 * n));
+    return HIPBMG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // the paper's distributed model (host only)
 // ---------------------------------------------------------------------------
@@ -2066,6 +2078,16 @@ extern "C" hipbmg_status hipbmg_grad_logD(int nx, int ny, const double *theta, c
     if (!theta || !u || !lam || !grad_out) return fail(HIPBMG_EINVAL, "null argument");
     if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
     HIPCHK(launch_grad_logD(nx, ny, theta, u, lam, grad_out, (hipStream_t)stream));
+    return HIPBMG_OK;
+}
+
+extern "C" hipbmg_status hipbmg_grad_logD_batched(int nprob, int nx, int ny, const double *theta, const double *u,
+                                                  const double *lam, double *grad_out, void *stream)
+{
+    if (!theta || !u || !lam || !grad_out) return fail(HIPBMG_EINVAL, "null argument");
+    if (nprob < 1 || nprob > 65535) return fail(HIPBMG_EINVAL, "nprob must be in 1..65535");
+    if (nx < 3 || ny < 3) return fail(HIPBMG_EINVAL, "grid too small");
+    HIPCHK(launch_grad_logD(nx, ny, theta, u, lam, grad_out, (hipStream_t)stream, nprob));
     return HIPBMG_OK;
 }
 

@@ -159,12 +159,14 @@ hipError_t launch_zero_excess_check(const LevelDev<double> &A, int *flag, hipStr
 hipError_t launch_zero_excess_check(const LevelDev<float> &A, int *flag, hipStream_t s);
 
 // Setup kernels.
+// nprob problems of one size (cells one after another; problem k's planes
+// k * ostride elements after the first's)
 hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,
-                      double *S, int pitch, hipStream_t s);
+                      double *S, int pitch, hipStream_t s, int nprob = 1, size_t ostride = 0);
 hipError_t launch_fv5_aniso(int nx, int ny, const double *dx_cell, const double *dy_cell, double hx, double hy,
                             double *C, double *W, double *S, int pitch, hipStream_t s);
 hipError_t launch_grad_logD(int nx, int ny, const double *theta, const double *u,
-                            const double *lam, double *g, hipStream_t s);
+                            const double *lam, double *g, hipStream_t s, int nprob = 1);
 hipError_t launch_interp_weights(const LevelDev<double> &f, int cnx, int cny, double *wt,
                                  int cpitch, size_t cplane, hipStream_t s);
 hipError_t launch_rap(const LevelDev<double> &f, const LevelDev<double> &c, hipStream_t s);

@@ -25,13 +25,20 @@ __device__ __forceinline__ double cell_at(const double *cell, int nx, int ny, in
 // of an x-edge has length hy across a distance hx, so it takes sx = hy/hx times
 // the mean Dx of the two cells it cuts; a y-edge takes sy = hx/hy times the
 // mean Dy.  The isotropic form passes the same cells twice and sx = sy = 1.
+// (blockIdx.z: problem of a batch, its cells cstride and its planes ostride
+// elements after the previous problem's)
 __global__ void k_fv5(int nx, int ny, const double *__restrict__ cx, const double *__restrict__ cy, int is_log,
                       double sx, double sy, double *__restrict__ C, double *__restrict__ W,
-                      double *__restrict__ S, int pitch)
+                      double *__restrict__ S, int pitch, size_t cstride, size_t ostride)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (i >= nx) return;
+    cx += blockIdx.z * cstride;
+    cy += blockIdx.z * cstride;
+    C += blockIdx.z * ostride;
+    W += blockIdx.z * ostride;
+    S += blockIdx.z * ostride;
     size_t p = (size_t)j * pitch + i;
     // W(i,j): edge (i-1,j)-(i,j), cells (i-1,j-1) and (i-1,j)
     double w = 0.0, s = 0.0;
@@ -52,10 +59,11 @@ __global__ void k_fv5(int nx, int ny, const double *__restrict__ cx, const doubl
 }
 
 hipError_t launch_fv5(int nx, int ny, const double *cell, int is_log, double *C, double *W,
-                      double *S, int pitch, hipStream_t s)
+                      double *S, int pitch, hipStream_t s, int nprob, size_t ostride)
 {
-    dim3 b(256), g((nx + 255) / 256, ny);
-    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, cell, cell, is_log, 1.0, 1.0, C, W, S, pitch);
+    dim3 b(256), g((nx + 255) / 256, ny, nprob);
+    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, cell, cell, is_log, 1.0, 1.0, C, W, S, pitch,
+                       (size_t)(nx - 1) * (ny - 1), ostride);
     return hipGetLastError();
 }
 
@@ -63,7 +71,7 @@ hipError_t launch_fv5_aniso(int nx, int ny, const double *dx_cell, const double 
                             double *C, double *W, double *S, int pitch, hipStream_t s)
 {
     dim3 b(256), g((nx + 255) / 256, ny);
-    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, dx_cell, dy_cell, 0, hy / hx, hx / hy, C, W, S, pitch);
+    hipLaunchKernelGGL(k_fv5, g, b, 0, s, nx, ny, dx_cell, dy_cell, 0, hy / hx, hx / hy, C, W, S, pitch, 0, 0);
     return hipGetLastError();
 }
 
@@ -79,6 +87,7 @@ __device__ __forceinline__ double vtx(const double *v, int nx, int ny, int i, in
     return v[(size_t)j * nx + i];
 }
 
+// (blockIdx.z: problem of a batch of one size, arrays stored one after another)
 __global__ void k_grad_logD(int nx, int ny, const double *__restrict__ theta,
                             const double *__restrict__ u, const double *__restrict__ lam,
                             double *__restrict__ g)
@@ -86,6 +95,11 @@ __global__ void k_grad_logD(int nx, int ny, const double *__restrict__ theta,
     int ci = blockIdx.x * blockDim.x + threadIdx.x;
     int cj = blockIdx.y;
     if (ci >= nx - 1) return;
+    const size_t vs = (size_t)blockIdx.z * nx * ny, cs = (size_t)blockIdx.z * (nx - 1) * (ny - 1);
+    theta += cs;
+    g += cs;
+    u += vs;
+    lam += vs;
     double u00 = vtx(u, nx, ny, ci, cj), u10 = vtx(u, nx, ny, ci + 1, cj);
     double u01 = vtx(u, nx, ny, ci, cj + 1), u11 = vtx(u, nx, ny, ci + 1, cj + 1);
     double l00 = vtx(lam, nx, ny, ci, cj), l10 = vtx(lam, nx, ny, ci + 1, cj);
@@ -97,9 +111,9 @@ __global__ void k_grad_logD(int nx, int ny, const double *__restrict__ theta,
 }
 
 hipError_t launch_grad_logD(int nx, int ny, const double *theta, const double *u,
-                            const double *lam, double *g, hipStream_t s)
+                            const double *lam, double *g, hipStream_t s, int nprob)
 {
-    dim3 b(256), g2((nx - 1 + 255) / 256, ny - 1);
+    dim3 b(256), g2((nx - 1 + 255) / 256, ny - 1, nprob);
     hipLaunchKernelGGL(k_grad_logD, g2, b, 0, s, nx, ny, theta, u, lam, g);
     return hipGetLastError();
 }

@@ -78,6 +78,8 @@ _SIGS = {
     "hipbmg_residual_norm_noalloc": (_I, [_I, _I, _I, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "hipbmg_fv5_aniso": (_I, [_I, _I, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
     "hipbmg_grad_logD": (_I, [_I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "hipbmg_fv5_from_cells_batched": (_I, [_I, _I, _I, _VP, _I, _VP, _VP]),
+    "hipbmg_grad_logD_batched": (_I, [_I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "hipbmg_profile": (_I, [_VP, _I]),
     "hipbmg_profile_read": (_I, [_VP, _I, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
@@ -534,6 +536,18 @@ def fv5_from_cells(cell, is_log=False):
     return out
 
 
+def fv5_from_cells_batched(cells, is_log=False):
+    """fv5_from_cells for a batch of one size in one launch: cells [B][ny-1][nx-1]
+    -> planes [B][3][ny][nx]."""
+    if cells.dim() != 3 or cells.shape[0] < 1:
+        raise ValueError("cells must be [B][ny-1][nx-1]")
+    nb, ny, nx = cells.shape[0], cells.shape[1] + 1, cells.shape[2] + 1
+    out = torch.empty((nb, 3, ny, nx), dtype=torch.float64, device=cells.device)
+    _check(lib().hipbmg_fv5_from_cells_batched(nb, nx, ny, _ptr(cells, name="cells"), 1 if is_log else 0,
+                                               _ptr(out), _stream()))
+    return out
+
+
 def fv5_aniso(dx_cell, dy_cell, hx, hy):
     """5-point finite-volume planes {C, W, S} for D = diag(Dx, Dy) per cell on a
     grid of spacings hx, hy (the stretched grids of section 5)."""
@@ -557,6 +571,19 @@ def grad_logD(theta, u, lam):
     _check(lib().hipbmg_grad_logD(nx, ny, _ptr(theta, shape=(ny - 1, nx - 1), name="theta"),
                                   _ptr(u, name="u"), _ptr(lam, shape=(ny, nx), name="lam"),
                                   _ptr(g, shape=(ny - 1, nx - 1), name="grad"), _stream()))
+    return g
+
+
+def grad_logD_batched(theta, u, lam):
+    """grad_logD for a batch of one size in one launch: theta [B][ny-1][nx-1],
+    u and lam [B][ny][nx] -> [B][ny-1][nx-1]."""
+    if u.dim() != 3 or u.shape[0] < 1:
+        raise ValueError("u must be [B][ny][nx]")
+    nb, ny, nx = u.shape
+    g = torch.empty((nb, ny - 1, nx - 1), dtype=torch.float64, device=u.device)
+    _check(lib().hipbmg_grad_logD_batched(nb, nx, ny, _ptr(theta, shape=(nb, ny - 1, nx - 1), name="theta"),
+                                          _ptr(u, name="u"), _ptr(lam, shape=(nb, ny, nx), name="lam"),
+                                          _ptr(g), _stream()))
     return g
 
 
@@ -601,9 +628,10 @@ class SolveFVBatched(torch.autograd.Function):
         th = theta.detach().contiguous()
         bb = b.detach().contiguous()
         nb = th.shape[0]
-        coeffs = [fv5_from_cells(th[k], is_log=True) for k in range(nb)]
+        planes = fv5_from_cells_batched(th, is_log=True)
+        coeffs = [planes[k] for k in range(nb)]
         hier = BatchHierarchy(coeffs, **(params or {}))
-        del coeffs
+        del coeffs, planes
         u = torch.zeros_like(bb)
         hier.solve([bb[k] for k in range(nb)], [u[k] for k in range(nb)], tol=tol)
         ctx.hier = hier
@@ -619,7 +647,7 @@ class SolveFVBatched(torch.autograd.Function):
         lam = torch.zeros_like(gu)
         ctx.hier.solve([gu[k] for k in range(nb)], [lam[k] for k in range(nb)], tol=ctx.tol)
         th = theta.detach().contiguous()
-        g_theta = torch.stack([grad_logD(th[k], u[k], lam[k]) for k in range(nb)])
+        g_theta = grad_logD_batched(th, u.contiguous(), lam)
         ctx.hier.close()
         return g_theta, lam, None, None
 

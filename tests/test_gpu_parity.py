@@ -421,6 +421,30 @@ def test_grad_kernel_matches_oracle():
     assert e <= 1e-13, e
 
 
+def test_batched_fv5_and_grad_kernels_equal_single_problem_ones():
+    # one launch over the batch: problem by problem the single kernels' bits;
+    # problem 0 also against the oracle
+    nb, nx, ny = 5, 65, 33
+    rng = np.random.default_rng(15)
+    theta = g(rng.standard_normal((nb, ny - 1, nx - 1)))
+    u = g(rng.standard_normal((nb, ny, nx)))
+    lam = g(rng.standard_normal((nb, ny, nx)))
+    planes = HB.fv5_from_cells_batched(theta, is_log=True)
+    grads = HB.grad_logD_batched(theta, u, lam)
+    for k in range(nb):
+        assert torch.equal(planes[k], HB.fv5_from_cells(theta[k], is_log=True)), k
+        assert torch.equal(grads[k], HB.grad_logD(theta[k], u[k], lam[k])), k
+    assert rel(c(planes[0]), O.fv5(np.exp(c(theta[0])))) <= 4e-15
+    assert rel(c(grads[0]), O.grad_logD(np.exp(c(theta[0])), c(u[0]), c(lam[0]))) <= 1e-13
+    # argument errors come back as EINVAL before any launch
+    L = HB.lib()
+    z = HB._ptr(theta)
+    assert L.hipbmg_fv5_from_cells_batched(0, nx, ny, z, 1, z, None) == HB.EINVAL
+    assert L.hipbmg_fv5_from_cells_batched(nb, 2, ny, z, 1, z, None) == HB.EINVAL
+    assert L.hipbmg_grad_logD_batched(0, nx, ny, z, z, z, z, None) == HB.EINVAL
+    assert L.hipbmg_grad_logD_batched(nb, nx, ny, None, z, z, z, None) == HB.EINVAL
+
+
 def test_autograd_gradient_matches_oracle_and_fd():
     n = 33
     theta = inputs.theta_box5(n, n, seed=3000)
