@@ -3429,7 +3429,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         int total = 0;
         while (true) {
             HIPCHK(launch_ir_residual_batched(B->d_fine64, B->d_fine32, B->d_active, B->d_rpart, B->d_roff,
-                                              B->fine_npt, B->max_nx, B->max_ny, n, s));
+                                              B->fine_npt, B->max_nx, B->max_ny, n, s, B->zc[0]));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, nullptr, B->d_rnorm, B->d_active,
                                            -1.0, nullptr, n, s));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, B->d_bnorm, B->d_relres, B->d_active,

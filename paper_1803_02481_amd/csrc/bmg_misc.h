@@ -18,10 +18,12 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
 
 // batched forms (blockIdx.z = problem; inactive problems skipped).  The FP64
 // iterate is x[0] of the finest level, the FP32 correction x[0] of the FP32
-// finest level; partials of problem p start at poff[p]
+// finest level; partials of problem p start at poff[p].  zc: every problem's
+// 5-point diagonal is bitwise the ordered sum of its four connections (checked
+// at setup), so the residual forms it instead of loading it
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
                                       const int *active, double *partials, const int *poff, int npt,
-                                      int max_nx, int max_ny, int nprob, hipStream_t s);
+                                      int max_nx, int max_ny, int nprob, hipStream_t s, int zc = 0);
 // u += e for every active problem; e from eptr[p] (device array of device
 // pointers with the FP32 level's pitch), or the FP32 finest x[0] if eptr is null
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,

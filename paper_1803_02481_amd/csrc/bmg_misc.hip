@@ -155,7 +155,9 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
 // batched forms of the refinement steps: blockIdx.z = problem; problems whose
 // flag is 0 are skipped
 // ---------------------------------------------------------------------------
-template <int NPT>
+// ZC: every problem's 5-point diagonal is bitwise the ordered sum of its four
+// connections (checked at setup), formed instead of loaded
+template <int NPT, bool ZC>
 __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<double> *__restrict__ d,
                                                              const LevelDev<float> *__restrict__ f,
                                                              const int *__restrict__ active,
@@ -181,7 +183,8 @@ __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<doub
             if (NPT == 9)
                 s += D.SW[q] * u[q - P - 1] + D.SW[q + P + 1] * u[q + P + 1] + D.SE[q] * u[q - P + 1] +
                      D.SE[q + P - 1] * u[q + P - 1];
-            const double r = s - D.C[q] * u[q];
+            const double cq = ZC && NPT == 5 ? D.W[q] + D.W[q + 1] + D.S[q] + D.S[q + P] : D.C[q];
+            const double r = s - cq * u[q];
             acc = r * r;
             out = (float)r;
         }
@@ -196,13 +199,15 @@ __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<doub
 
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
                                       const int *active, double *partials, const int *poff, int npt,
-                                      int max_nx, int max_ny, int nprob, hipStream_t s)
+                                      int max_nx, int max_ny, int nprob, hipStream_t s, int zc)
 {
     dim3 g((max_nx + 255) / 256, max_ny, nprob);
     if (npt == 9)
-        hipLaunchKernelGGL(k_ir_residual_batched<9>, g, dim3(256), 0, s, d, f, active, partials, poff);
+        hipLaunchKernelGGL((k_ir_residual_batched<9, false>), g, dim3(256), 0, s, d, f, active, partials, poff);
+    else if (zc)
+        hipLaunchKernelGGL((k_ir_residual_batched<5, true>), g, dim3(256), 0, s, d, f, active, partials, poff);
     else
-        hipLaunchKernelGGL(k_ir_residual_batched<5>, g, dim3(256), 0, s, d, f, active, partials, poff);
+        hipLaunchKernelGGL((k_ir_residual_batched<5, false>), g, dim3(256), 0, s, d, f, active, partials, poff);
     return hipGetLastError();
 }
 
