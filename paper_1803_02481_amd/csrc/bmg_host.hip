@@ -2498,6 +2498,7 @@ struct hipbmg_batch {
     LevelDev<double> *d_fine64 = nullptr;
     LevelDev<float> *d_fine32 = nullptr;
     double *d_rpart = nullptr;   // refinement residual partials (segments d_roff / d_rcnt)
+    int n_rblocks = 0;           // workgroups of the refinement kernels (d_roff[n])
     int n_partials = 0;
     std::vector<int> h_pcnt;
     double *h_relres = nullptr;
@@ -3137,7 +3138,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     chk(balloc(B, &B->d_bpart, (size_t)nprob * 64, s));
     chk(balloc(B, &B->d_boff, nprob, s));
     chk(balloc(B, &B->d_bcnt, nprob, s));
-    chk(balloc(B, &B->d_roff, nprob, s));
+    chk(balloc(B, &B->d_roff, (size_t)nprob + 1, s));
     chk(balloc(B, &B->d_rcnt, nprob, s));
     chk(balloc(B, &B->d_bptr, nprob, s));
     chk(balloc(B, &B->d_xptr, nprob, s));
@@ -3147,7 +3148,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     chk(balloc(B, &B->d_fine64, nprob, s));
     if (prm.precision == HIPBMG_MIXED) chk(balloc(B, &B->d_fine32, nprob, s));
     if (st != HIPBMG_OK) return bail(st);
-    std::vector<int> boff(nprob), bcnt(nprob, 64), roff(nprob), rcnt(nprob);
+    std::vector<int> boff(nprob), bcnt(nprob, 64), roff(nprob + 1), rcnt(nprob);
     std::vector<double *> bptr(nprob), xptr(nprob);
     std::vector<int4> dims(nprob);
     std::vector<int> rowoff(nprob + 1, 0);
@@ -3167,6 +3168,8 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         rcnt[p] = ((F.nx + 255) / 256) * F.ny;
         roffs += rcnt[p];
     }
+    roff[nprob] = (int)roffs;
+    B->n_rblocks = (int)roffs;
     if (balloc(B, &B->d_rpart, roffs + 1, s) != HIPBMG_OK) return bail(HIPBMG_ENOMEM);
     auto up = [&](void *dst, const void *src, size_t bytes) {
         if (st == HIPBMG_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -3174,7 +3177,7 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
     };
     up(B->d_boff, boff.data(), nprob * sizeof(int));
     up(B->d_bcnt, bcnt.data(), nprob * sizeof(int));
-    up(B->d_roff, roff.data(), nprob * sizeof(int));
+    up(B->d_roff, roff.data(), (nprob + 1) * sizeof(int));
     up(B->d_rcnt, rcnt.data(), nprob * sizeof(int));
     up(B->d_bptr, bptr.data(), nprob * sizeof(double *));
     up(B->d_xptr, xptr.data(), nprob * sizeof(double *));
@@ -3429,7 +3432,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         int total = 0;
         while (true) {
             HIPCHK(launch_ir_residual_batched(B->d_fine64, B->d_fine32, B->d_active, B->d_rpart, B->d_roff,
-                                              B->fine_npt, B->max_nx, B->max_ny, n, s, B->zc[0]));
+                                              B->n_rblocks, B->fine_npt, n, s, B->zc[0]));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, nullptr, B->d_rnorm, B->d_active,
                                            -1.0, nullptr, n, s));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, B->d_bnorm, B->d_relres, B->d_active,
@@ -3479,8 +3482,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 STCHK(batch_rebuild<float>(B, B->pipe32[0], kin, B->h_rb32, B->d_rb32, e32, s));
                 for (int p = 0; p < n; ++p) B->h_eptr[p] = e32[p];
                 HIPCHK(hipMemcpyAsync(B->d_eptr, B->h_eptr, n * sizeof(float *), hipMemcpyHostToDevice, s));
-                HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_eptr, B->d_active, B->max_nx,
-                                                B->max_ny, n, s));
+                HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_eptr, B->d_active, B->d_roff,
+                                                B->n_rblocks, n, s));
                 continue;
             }
             int icur = 0;
@@ -3496,8 +3499,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 if (B->h_count[0] == 0) break;
             }
             if (icur != 0) return fail(HIPBMG_EINVAL, "batched refinement expects the correction in buffer 0");
-            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, nullptr, B->d_active, B->max_nx, B->max_ny, n,
-                                            s));
+            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, nullptr, B->d_active, B->d_roff,
+                                            B->n_rblocks, n, s));
         }
         for (int p = 0; p < n; ++p) done_cur[p] = 0;
     }

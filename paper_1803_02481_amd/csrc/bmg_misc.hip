@@ -152,26 +152,48 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
 }
 
 // ---------------------------------------------------------------------------
-// batched forms of the refinement steps: blockIdx.z = problem; problems whose
-// flag is 0 are skipped
+// batched forms of the refinement steps: one workgroup per 256 columns of a
+// row of a problem, numbered problem by problem (boff[p]: the first block of
+// problem p, boff[nprob] the blocks of all), so no workgroup falls outside its
+// problem; problems whose flag is 0 are skipped
 // ---------------------------------------------------------------------------
+struct BatchBlock {
+    int p, j, bx;
+};
+
+template <typename Nx>
+__device__ __forceinline__ BatchBlock find_block(const int *__restrict__ boff, int nprob, Nx nx_of)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const int nxb = (nx_of(lo) + 255) / 256, local = b - boff[lo];
+    const int j = local / nxb;
+    return {lo, j, local - j * nxb};
+}
+
 // ZC: every problem's 5-point diagonal is bitwise the ordered sum of its four
-// connections (checked at setup), formed instead of loaded
+// connections (checked at setup), formed instead of loaded.  Partial k of
+// problem p (k = row * blocks per row + block in the row) is partials[boff[p] + k].
 template <int NPT, bool ZC>
 __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<double> *__restrict__ d,
                                                              const LevelDev<float> *__restrict__ f,
                                                              const int *__restrict__ active,
                                                              double *__restrict__ partials,
-                                                             const int *__restrict__ poff)
+                                                             const int *__restrict__ boff, int nprob)
 {
     __shared__ double sh[4];
-    const int p = blockIdx.z;
+    const BatchBlock bb = find_block(boff, nprob, [&](int q) { return d[q].nx; });
+    const int p = bb.p;
     if (!active[p]) return;
     const LevelDev<double> &D = d[p];
     if (D.npt != NPT) return;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
-    if (j >= D.ny || (int)(blockIdx.x * 256) >= D.nx) return;   // whole block outside: uniform
+    const int i = bb.bx * 256 + threadIdx.x;
+    const int j = bb.j;
     const double *u = D.x[0];
     double acc = 0.0;
     if (i < D.nx) {
@@ -193,42 +215,47 @@ __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<doub
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0)
-        partials[poff[p] + blockIdx.y * ((D.nx + 255) / 256) + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
-                                      const int *active, double *partials, const int *poff, int npt,
-                                      int max_nx, int max_ny, int nprob, hipStream_t s, int zc)
+                                      const int *active, double *partials, const int *boff, int nblocks,
+                                      int npt, int nprob, hipStream_t s, int zc)
 {
-    dim3 g((max_nx + 255) / 256, max_ny, nprob);
+    dim3 g(nblocks);
     if (npt == 9)
-        hipLaunchKernelGGL((k_ir_residual_batched<9, false>), g, dim3(256), 0, s, d, f, active, partials, poff);
+        hipLaunchKernelGGL((k_ir_residual_batched<9, false>), g, dim3(256), 0, s, d, f, active, partials, boff,
+                           nprob);
     else if (zc)
-        hipLaunchKernelGGL((k_ir_residual_batched<5, true>), g, dim3(256), 0, s, d, f, active, partials, poff);
+        hipLaunchKernelGGL((k_ir_residual_batched<5, true>), g, dim3(256), 0, s, d, f, active, partials, boff,
+                           nprob);
     else
-        hipLaunchKernelGGL((k_ir_residual_batched<5, false>), g, dim3(256), 0, s, d, f, active, partials, poff);
+        hipLaunchKernelGGL((k_ir_residual_batched<5, false>), g, dim3(256), 0, s, d, f, active, partials, boff,
+                           nprob);
     return hipGetLastError();
 }
 
-__global__ void k_ir_update_batched(const LevelDev<double> *__restrict__ d, const LevelDev<float> *__restrict__ f,
-                                    const float *const *__restrict__ eptr, const int *__restrict__ active)
+__global__ __launch_bounds__(256) void k_ir_update_batched(const LevelDev<double> *__restrict__ d,
+                                                           const LevelDev<float> *__restrict__ f,
+                                                           const float *const *__restrict__ eptr,
+                                                           const int *__restrict__ active,
+                                                           const int *__restrict__ boff, int nprob)
 {
-    const int p = blockIdx.z;
+    const BatchBlock bb = find_block(boff, nprob, [&](int q) { return d[q].nx; });
+    const int p = bb.p;
     if (!active[p]) return;
     const LevelDev<double> &D = d[p];
     const float *e = eptr ? eptr[p] : f[p].x[0];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
+    const int i = bb.bx * 256 + threadIdx.x;
+    const int j = bb.j;
     if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2)
         D.x[0][(size_t)j * D.pitch + i] += (double)e[(size_t)j * f[p].pitch + i];
 }
 
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
-                                    const int *active, int max_nx, int max_ny, int nprob, hipStream_t s)
+                                    const int *active, const int *boff, int nblocks, int nprob, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ir_update_batched, dim3((max_nx + 255) / 256, max_ny, nprob), dim3(256), 0, s, d, f,
-                       eptr, active);
+    hipLaunchKernelGGL(k_ir_update_batched, dim3(nblocks), dim3(256), 0, s, d, f, eptr, active, boff, nprob);
     return hipGetLastError();
 }
 
