@@ -2498,7 +2498,6 @@ struct hipbmg_batch {
     LevelDev<double> *d_fine64 = nullptr;
     LevelDev<float> *d_fine32 = nullptr;
     double *d_rpart = nullptr;   // refinement residual partials (segments d_roff / d_rcnt)
-    int n_rblocks = 0;           // workgroups of the refinement kernels (d_roff[n])
     int n_partials = 0;
     std::vector<int> h_pcnt;
     double *h_relres = nullptr;
@@ -3169,7 +3168,6 @@ extern "C" hipbmg_status hipbmg_setup_batched(int nprob, const int *nx, const in
         roffs += rcnt[p];
     }
     roff[nprob] = (int)roffs;
-    B->n_rblocks = (int)roffs;
     if (balloc(B, &B->d_rpart, roffs + 1, s) != HIPBMG_OK) return bail(HIPBMG_ENOMEM);
     auto up = [&](void *dst, const void *src, size_t bytes) {
         if (st == HIPBMG_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -3432,7 +3430,7 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
         int total = 0;
         while (true) {
             HIPCHK(launch_ir_residual_batched(B->d_fine64, B->d_fine32, B->d_active, B->d_rpart, B->d_roff,
-                                              B->n_rblocks, B->fine_npt, n, s, B->zc[0]));
+                                              B->d_rowoff, B->rows, B->fine_npt, n, s, B->zc[0]));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, nullptr, B->d_rnorm, B->d_active,
                                            -1.0, nullptr, n, s));
             HIPCHK(launch_finalize_batched(B->d_rpart, B->d_roff, B->d_rcnt, B->d_bnorm, B->d_relres, B->d_active,
@@ -3482,8 +3480,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 STCHK(batch_rebuild<float>(B, B->pipe32[0], kin, B->h_rb32, B->d_rb32, e32, s));
                 for (int p = 0; p < n; ++p) B->h_eptr[p] = e32[p];
                 HIPCHK(hipMemcpyAsync(B->d_eptr, B->h_eptr, n * sizeof(float *), hipMemcpyHostToDevice, s));
-                HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_eptr, B->d_active, B->d_roff,
-                                                B->n_rblocks, n, s));
+                HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, B->d_eptr, B->d_active, B->d_rowoff,
+                                                B->rows, n, s));
                 continue;
             }
             int icur = 0;
@@ -3499,8 +3497,8 @@ extern "C" hipbmg_status hipbmg_solve_batched(hipbmg_batch_handle B, const doubl
                 if (B->h_count[0] == 0) break;
             }
             if (icur != 0) return fail(HIPBMG_EINVAL, "batched refinement expects the correction in buffer 0");
-            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, nullptr, B->d_active, B->d_roff,
-                                            B->n_rblocks, n, s));
+            HIPCHK(launch_ir_update_batched(B->d_fine64, B->d_fine32, nullptr, B->d_active, B->d_rowoff,
+                                            B->rows, n, s));
         }
         for (int p = 0; p < n; ++p) done_cur[p] = 0;
     }

@@ -16,21 +16,21 @@ hipError_t launch_ir_residual(const LevelDev<double> &d, const double *u, float 
 hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, int nx, int ny,
                             hipStream_t s);
 
-// batched forms: one workgroup per 256 columns of a row of a problem, the
-// nblocks workgroups numbered problem by problem (boff[p]: the first of
-// problem p, ((nx + 255) / 256) * ny of them; boff[nprob] = nblocks); inactive
-// problems skipped.  The FP64 iterate is x[0] of the finest level, the FP32
-// correction x[0] of the FP32 finest level; the residual writes one partial
-// per workgroup (partials[block]).  zc: every problem's 5-point diagonal is
-// bitwise the ordered sum of its four connections (checked at setup), so the
-// residual forms it instead of loading it
+// batched forms: one workgroup per row of a problem (rowoff[p]: the first row
+// of problem p, rowoff[nprob] = nrows); inactive problems skipped.  The FP64
+// iterate is x[0] of the finest level, the FP32 correction x[0] of the FP32
+// finest level.  The residual writes one partial per 256-column block of a
+// row: block bx of row j of problem p at partials[boff[p] + j * ((nx + 255) /
+// 256) + bx].  zc: every problem's 5-point diagonal is bitwise the ordered sum
+// of its four connections (checked at setup), so the residual forms it
+// instead of loading it
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
-                                      const int *active, double *partials, const int *boff, int nblocks,
-                                      int npt, int nprob, hipStream_t s, int zc = 0);
+                                      const int *active, double *partials, const int *boff, const int *rowoff,
+                                      int nrows, int npt, int nprob, hipStream_t s, int zc = 0);
 // u += e for every active problem; e from eptr[p] (device array of device
 // pointers with the FP32 level's pitch), or the FP32 finest x[0] if eptr is null
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
-                                    const int *active, const int *boff, int nblocks, int nprob, hipStream_t s);
+                                    const int *active, const int *rowoff, int nrows, int nprob, hipStream_t s);
 // planes [nplanes][ny][nx] (contiguous) into a level's padded planes
 // (dst + k * plane, rows of `pitch`); the padding is left as it is
 hipError_t launch_planes_in(const double *src, int nx, int ny, int nplanes, double *dst, int pitch, size_t plane,

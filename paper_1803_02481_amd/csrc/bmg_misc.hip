@@ -152,86 +152,84 @@ hipError_t launch_ir_update(double *u, int pitch, const float *e, int pitchf, in
 }
 
 // ---------------------------------------------------------------------------
-// batched forms of the refinement steps: one workgroup per 256 columns of a
-// row of a problem, numbered problem by problem (boff[p]: the first block of
-// problem p, boff[nprob] the blocks of all), so no workgroup falls outside its
-// problem; problems whose flag is 0 are skipped
+// batched forms of the refinement steps: one workgroup per row of a problem
+// (rowoff[p]: the first row of problem p, rowoff[nprob] the rows of all),
+// found by bisection, looping over the row's 256-column blocks; problems whose
+// flag is 0 are skipped
 // ---------------------------------------------------------------------------
-struct BatchBlock {
-    int p, j, bx;
-};
-
-template <typename Nx>
-__device__ __forceinline__ BatchBlock find_block(const int *__restrict__ boff, int nprob, Nx nx_of)
+__device__ __forceinline__ int2 find_row(const int *__restrict__ rowoff, int nprob)
 {
-    const int b = blockIdx.x;
+    const int r = blockIdx.x;
     int lo = 0, hi = nprob;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (boff[mid] <= b) lo = mid;
+        if (rowoff[mid] <= r) lo = mid;
         else hi = mid;
     }
-    const int nxb = (nx_of(lo) + 255) / 256, local = b - boff[lo];
-    const int j = local / nxb;
-    return {lo, j, local - j * nxb};
+    return make_int2(lo, r - rowoff[lo]);
 }
 
 // ZC: every problem's 5-point diagonal is bitwise the ordered sum of its four
-// connections (checked at setup), formed instead of loaded.  Partial k of
-// problem p (k = row * blocks per row + block in the row) is partials[boff[p] + k].
+// connections (checked at setup), formed instead of loaded.  Each 256-column
+// block of a row gives one partial: block bx of row j of problem p is
+// partials[boff[p] + j * blocks per row + bx].
 template <int NPT, bool ZC>
 __global__ __launch_bounds__(256) void k_ir_residual_batched(const LevelDev<double> *__restrict__ d,
                                                              const LevelDev<float> *__restrict__ f,
                                                              const int *__restrict__ active,
                                                              double *__restrict__ partials,
-                                                             const int *__restrict__ boff, int nprob)
+                                                             const int *__restrict__ boff,
+                                                             const int *__restrict__ rowoff, int nprob)
 {
-    __shared__ double sh[4];
-    const BatchBlock bb = find_block(boff, nprob, [&](int q) { return d[q].nx; });
-    const int p = bb.p;
+    __shared__ double sh[2][4];   // alternate blocks: one barrier per block
+    const int2 pr = find_row(rowoff, nprob);
+    const int p = pr.x, j = pr.y;
     if (!active[p]) return;
     const LevelDev<double> &D = d[p];
     if (D.npt != NPT) return;
-    const int i = bb.bx * 256 + threadIdx.x;
-    const int j = bb.j;
     const double *u = D.x[0];
-    double acc = 0.0;
-    if (i < D.nx) {
-        const size_t q = (size_t)j * D.pitch + i, P = D.pitch;
-        float out = 0.0f;
-        if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2) {
-            double s = D.b[q] + D.W[q] * u[q - 1] + D.W[q + 1] * u[q + 1] + D.S[q] * u[q - P] +
-                       D.S[q + P] * u[q + P];
-            if (NPT == 9)
-                s += D.SW[q] * u[q - P - 1] + D.SW[q + P + 1] * u[q + P + 1] + D.SE[q] * u[q - P + 1] +
-                     D.SE[q + P - 1] * u[q + P - 1];
-            const double cq = ZC && NPT == 5 ? D.W[q] + D.W[q + 1] + D.S[q] + D.S[q + P] : D.C[q];
-            const double r = s - cq * u[q];
-            acc = r * r;
-            out = (float)r;
+    const int nxb = (D.nx + 255) / 256;
+    for (int bx = 0; bx < nxb; ++bx) {
+        const int i = bx * 256 + threadIdx.x;
+        double acc = 0.0;
+        if (i < D.nx) {
+            const size_t q = (size_t)j * D.pitch + i, P = D.pitch;
+            float out = 0.0f;
+            if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2) {
+                double s = D.b[q] + D.W[q] * u[q - 1] + D.W[q + 1] * u[q + 1] + D.S[q] * u[q - P] +
+                           D.S[q + P] * u[q + P];
+                if (NPT == 9)
+                    s += D.SW[q] * u[q - P - 1] + D.SW[q + P + 1] * u[q + P + 1] + D.SE[q] * u[q - P + 1] +
+                         D.SE[q + P - 1] * u[q + P - 1];
+                const double cq = ZC && NPT == 5 ? D.W[q] + D.W[q + 1] + D.S[q] + D.S[q + P] : D.C[q];
+                const double r = s - cq * u[q];
+                acc = r * r;
+                out = (float)r;
+            }
+            f[p].b[(size_t)j * f[p].pitch + i] = out;
         }
-        f[p].b[(size_t)j * f[p].pitch + i] = out;
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        double *w = sh[bx & 1];
+        if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) partials[boff[p] + j * nxb + bx] = ((w[0] + w[1]) + w[2]) + w[3];
     }
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 hipError_t launch_ir_residual_batched(const LevelDev<double> *d, const LevelDev<float> *f,
-                                      const int *active, double *partials, const int *boff, int nblocks,
-                                      int npt, int nprob, hipStream_t s, int zc)
+                                      const int *active, double *partials, const int *boff, const int *rowoff,
+                                      int nrows, int npt, int nprob, hipStream_t s, int zc)
 {
-    dim3 g(nblocks);
+    dim3 g(nrows);
     if (npt == 9)
         hipLaunchKernelGGL((k_ir_residual_batched<9, false>), g, dim3(256), 0, s, d, f, active, partials, boff,
-                           nprob);
+                           rowoff, nprob);
     else if (zc)
         hipLaunchKernelGGL((k_ir_residual_batched<5, true>), g, dim3(256), 0, s, d, f, active, partials, boff,
-                           nprob);
+                           rowoff, nprob);
     else
         hipLaunchKernelGGL((k_ir_residual_batched<5, false>), g, dim3(256), 0, s, d, f, active, partials, boff,
-                           nprob);
+                           rowoff, nprob);
     return hipGetLastError();
 }
 
@@ -239,23 +237,22 @@ __global__ __launch_bounds__(256) void k_ir_update_batched(const LevelDev<double
                                                            const LevelDev<float> *__restrict__ f,
                                                            const float *const *__restrict__ eptr,
                                                            const int *__restrict__ active,
-                                                           const int *__restrict__ boff, int nprob)
+                                                           const int *__restrict__ rowoff, int nprob)
 {
-    const BatchBlock bb = find_block(boff, nprob, [&](int q) { return d[q].nx; });
-    const int p = bb.p;
+    const int2 pr = find_row(rowoff, nprob);
+    const int p = pr.x, j = pr.y;
     if (!active[p]) return;
     const LevelDev<double> &D = d[p];
-    const float *e = eptr ? eptr[p] : f[p].x[0];
-    const int i = bb.bx * 256 + threadIdx.x;
-    const int j = bb.j;
-    if (i >= 1 && i <= D.nx - 2 && j >= 1 && j <= D.ny - 2)
-        D.x[0][(size_t)j * D.pitch + i] += (double)e[(size_t)j * f[p].pitch + i];
+    if (j < 1 || j > D.ny - 2) return;
+    const float *e = (eptr ? eptr[p] : f[p].x[0]) + (size_t)j * f[p].pitch;
+    double *x = D.x[0] + (size_t)j * D.pitch;
+    for (int i = 1 + threadIdx.x; i <= D.nx - 2; i += 256) x[i] += (double)e[i];
 }
 
 hipError_t launch_ir_update_batched(const LevelDev<double> *d, const LevelDev<float> *f, const float *const *eptr,
-                                    const int *active, const int *boff, int nblocks, int nprob, hipStream_t s)
+                                    const int *active, const int *rowoff, int nrows, int nprob, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ir_update_batched, dim3(nblocks), dim3(256), 0, s, d, f, eptr, active, boff, nprob);
+    hipLaunchKernelGGL(k_ir_update_batched, dim3(nrows), dim3(256), 0, s, d, f, eptr, active, rowoff, nprob);
     return hipGetLastError();
 }
 
